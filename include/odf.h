@@ -1,0 +1,111 @@
+/*
+ * odf.h -- C ABI of libodf, order-statistics directional vector filters
+ * (BVDF, DDF) on AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. E. Celebi, "Real-time implementation of order-statistics based
+ * directional filters", arXiv:1009.0958.
+ *
+ * Every image is an RGB array in HWC order: pixel (b, r, c) channel k lives at
+ * element ((b*M + r)*N + c)*3 + k.  A window of w x w pixels (w = 3 or 5) is
+ * centred on each pixel; border windows repeat the nearest edge pixel
+ * (replicated border), so every window has n = w*w members.  Members are
+ * numbered u = 0..n-1 row-major inside the window; the centre is (n-1)/2.
+ *
+ * Conventions shared by every entry point:
+ *   - All data pointers are DEVICE pointers owned by the caller.  The library
+ *     neither frees nor retains them.  Outputs must not overlap inputs.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *     on it and return without waiting; they allocate nothing except where
+ *     stated (odf_batch_plan, odf_autotune).
+ *   - Arguments are validated on the host before anything is launched.  A
+ *     rejected call returns a negative odf_status, launches nothing and sets
+ *     the message returned by odf_last_error() (per thread).
+ *   - Sizes: B, M, N >= 1 and B*M*N < 2^31 pixels per call.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef ODF_H
+#define ODF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ODF_OK = 0,
+    ODF_EINVAL = -1,        /* bad argument (null pointer, size, range, aliasing) */
+    ODF_EUNSUPPORTED = -2,  /* valid request this build does not provide (e.g. w = 7) */
+    ODF_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    ODF_ENOMEM = -4         /* a library-side allocation failed */
+} odf_status;
+
+/* Filter family.  BVDF (Section II, eq. 2): member minimising the sum of
+ * angles to all window members.  DDF: member minimising
+ * Omega_u = A_u^(1-p) * D_u^p, A_u the angle sum of eq. (2) and D_u the sum of
+ * L2 distances of eq. (1); p = 1/2 orders members as the product of eq. (3),
+ * p = 0 is BVDF and p = 1 the vector median of eq. (1). */
+typedef enum { ODF_BVDF = 0, ODF_DDF = 1 } odf_kind;
+
+/* Angular pair term.  EXACT: the angle of eq. (2).  MINIMAX: Section 2.1
+ * (Method 1), the degree-q minimax polynomials of Table 1 with the
+ * substitution of eqs. (5)-(6) for cosines >= 1/2.  RGB: Section 2.2
+ * (Method 2), the L2 distance between chromaticities (eq. 7); DDF maps it
+ * through the line of eq. (10). */
+typedef enum { ODF_EXACT = 0, ODF_MINIMAX = 1, ODF_RGB = 2 } odf_dist;
+
+/* Library version, (major << 16) | minor. */
+int odf_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* odf_last_error(void);
+
+/*
+ * Forward filter, uint8 images (Section II; eqs. 1-3 with the pair term
+ * chosen by `dist`).
+ *   img   B x M x N x 3 uint8, read only.
+ *   out   B x M x N x 3 uint8: out(b,r,c) is an exact copy of the selected
+ *         window member.
+ *   idx   B x M x N uint8 or NULL: the selected member index u in 0..n-1.
+ *         Ties go to the lowest index.
+ *   window 3 or 5; kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only, ignored by
+ *         BVDF); dist ODF_EXACT / ODF_MINIMAX / ODF_RGB; q in {2, 3, 4} for
+ *         ODF_MINIMAX (ignored otherwise).
+ * Zero pixels take the direction (1,1,1) in the angle and chromaticity terms.
+ * Errors: ODF_EINVAL for null img/out, sizes < 1, out overlapping img, or a
+ * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5};
+ * ODF_EHIP if the launch fails.
+ */
+int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, float p,
+                  int dist, int q, uint8_t* out, uint8_t* idx, void* stream);
+
+/*
+ * Forward filter, float32 images: same contract as odf_filter_u8 with
+ * img/out as B x M x N x 3 float32.  ODF_MINIMAX and ODF_RGB need
+ * non-negative inputs (the cosine lies in [0, 1], Section 2.1; chromaticity
+ * sums are positive, eq. 7); ODF_EXACT accepts any finite input.
+ */
+int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, float p,
+                   int dist, int q, float* out, uint8_t* idx, void* stream);
+
+/*
+ * Aggregates of every window (test and inspection hook, not the fast path).
+ *   img    uint8 (is_u8 != 0) or float32 image as above.
+ *   A      B x M x N x n float32: A[.., u] = sum_v theta(x_u, x_v), the pair
+ *          term of `dist` (self pair included).
+ *   D      B x M x N x n float32 or NULL: sum_v |x_u - x_v|_2 (DDF only;
+ *          written as 0 for BVDF).
+ *   Omega  B x M x N x n float32 or NULL: the objective the argmin uses
+ *          (A for BVDF; A^(1-p) D^p for DDF).
+ * Errors as for odf_filter_u8.
+ */
+int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, int kind,
+                   float p, int dist, int q, float* A, float* D, float* Omega, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ODF_H */

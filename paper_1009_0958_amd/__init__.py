@@ -1,4 +1,6 @@
 """Order-statistics directional filters (BVDF, DDF) on AMD Instinct MI355X.
 
-Placeholder: the GPU binding is added with the C-ABI library.
+The compute path is the HIP library ``libodf.so`` (C ABI in include/odf.h);
+``paper_1009_0958_amd.odf`` is its Python binding and
+``paper_1009_0958_amd.synth`` the seeded synthetic-input generator.
 """

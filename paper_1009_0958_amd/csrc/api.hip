@@ -1,0 +1,136 @@
+// api.hip -- host side of libodf: argument validation, error reporting and
+// dispatch to the kernels.  Declarations and contracts: include/odf.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "odf.h"
+#include "odf_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(ODF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+// Table 1 (Section 2.1): minimax coefficients a_0..a_4, rows q = 2, 3, 4.
+const float kTab1Asin[3][5] = {
+    {1.829125e-03f, 1.371117f, 1.480266e-01f, 0.0f, 0.0f},
+    {-1.358425e-04f, 1.419488f, -3.090315e-02f, 1.666491e-01f, 0.0f},
+    {2.097797e-05f, 1.412840f, 1.429881e-02f, 6.704361e-02f, 6.909677e-02f},
+};
+const float kTab1Acos[3][5] = {
+    {1.569882f, -9.695260e-01f, -1.480266e-01f, 0.0f, 0.0f},
+    {1.570864f, -1.003730f, 3.090318e-02f, -2.356775e-01f, 0.0f},
+    {1.570786f, -9.990285e-01f, -1.429899e-02f, -9.481335e-02f, -1.381942e-01f},
+};
+
+int check_common(const void* img, int B, int M, int N, int window, int kind, float p, int dist,
+                 int q) {
+    if (!img) return fail(ODF_EINVAL, "img is NULL");
+    if (B < 1 || M < 1 || N < 1) return fail(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
+    if ((long long)B * M * N >= (1ll << 31))
+        return fail(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
+    if (window != 3 && window != 5)
+        return fail(ODF_EUNSUPPORTED, "window %d not supported (3 or 5)", window);
+    if (kind != ODF_BVDF && kind != ODF_DDF) return fail(ODF_EINVAL, "kind %d out of range", kind);
+    if (dist < ODF_EXACT || dist > ODF_RGB) return fail(ODF_EINVAL, "dist %d out of range", dist);
+    if (dist == ODF_MINIMAX && (q < 2 || q > 4))
+        return fail(ODF_EINVAL, "q %d out of range (2, 3 or 4)", q);
+    if (kind == ODF_DDF && !(p >= 0.0f && p <= 1.0f))
+        return fail(ODF_EINVAL, "p must lie in [0, 1] for DDF");
+    return ODF_OK;
+}
+
+odf::FwdParams make_params(const void* img, int B, int M, int N, float p, int dist, int q) {
+    odf::FwdParams prm{};
+    prm.img = img;
+    prm.B = B;
+    prm.M = M;
+    prm.N = N;
+    prm.p = p;
+    if (dist == ODF_MINIMAX) {
+        memcpy(prm.coef.asin_c, kTab1Asin[q - 2], sizeof prm.coef.asin_c);
+        memcpy(prm.coef.acos_c, kTab1Acos[q - 2], sizeof prm.coef.acos_c);
+    }
+    return prm;
+}
+
+int filter_any(const void* img, bool u8, int B, int M, int N, int window, int kind, float p,
+               int dist, int q, void* out, uint8_t* idx, void* stream) {
+    int rc = check_common(img, B, M, N, window, kind, p, dist, q);
+    if (rc) return rc;
+    if (!out) return fail(ODF_EINVAL, "out is NULL");
+    const size_t npix = (size_t)B * M * N;
+    const size_t esz = u8 ? 1 : 4;
+    if (overlaps(img, npix * 3 * esz, out, npix * 3 * esz))
+        return fail(ODF_EINVAL, "out overlaps img (the filter cannot run in place)");
+    if (idx && (overlaps(img, npix * 3 * esz, idx, npix) || overlaps(out, npix * 3 * esz, idx, npix)))
+        return fail(ODF_EINVAL, "idx overlaps img or out");
+    odf::FwdParams prm = make_params(img, B, M, N, kind == ODF_DDF ? p : 0.0f, dist, q);
+    prm.out = out;
+    prm.idx = idx;
+    hipError_t e = odf::launch_forward(window, kind, dist, u8, false, prm,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return ODF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int odf_version(void) { return (0 << 16) | 1; }
+
+const char* odf_last_error(void) { return g_err; }
+
+int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, float p, int dist,
+                  int q, uint8_t* out, uint8_t* idx, void* stream) {
+    return filter_any(img, true, B, M, N, window, kind, p, dist, q, out, idx, stream);
+}
+
+int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, float p, int dist,
+                   int q, float* out, uint8_t* idx, void* stream) {
+    return filter_any(img, false, B, M, N, window, kind, p, dist, q, out, idx, stream);
+}
+
+int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, int kind, float p,
+                   int dist, int q, float* A, float* D, float* Omega, void* stream) {
+    int rc = check_common(img, B, M, N, window, kind, p, dist, q);
+    if (rc) return rc;
+    if (!A) return fail(ODF_EINVAL, "A is NULL");
+    const size_t npix = (size_t)B * M * N;
+    const size_t nagg = npix * window * window * sizeof(float);
+    const size_t nimg = npix * 3 * (is_u8 ? 1 : 4);
+    if (overlaps(img, nimg, A, nagg) || overlaps(img, nimg, D, nagg) ||
+        overlaps(img, nimg, Omega, nagg) || overlaps(A, nagg, D, nagg) ||
+        overlaps(A, nagg, Omega, nagg) || overlaps(D, nagg, Omega, nagg))
+        return fail(ODF_EINVAL, "output arrays overlap each other or img");
+    odf::FwdParams prm = make_params(img, B, M, N, kind == ODF_DDF ? p : 0.0f, dist, q);
+    prm.dbg_A = A;
+    prm.dbg_D = D;
+    prm.dbg_O = Omega;
+    hipError_t e = odf::launch_forward(window, kind, dist, is_u8 != 0, true, prm,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "aggregate launch");
+    return ODF_OK;
+}
+
+}  // extern "C"

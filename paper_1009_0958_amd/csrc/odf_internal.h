@@ -1,0 +1,27 @@
+// odf_internal.h -- launch parameters shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pair_terms.h"
+
+namespace odf {
+
+struct FwdParams {
+    const void* img;      // B x M x N x 3, uint8 or float32
+    void* out;            // same type and shape as img (may be null in aggregate mode)
+    uint8_t* idx;         // B x M x N or null
+    float* dbg_A;         // aggregate mode: B x M x N x n (null otherwise)
+    float* dbg_D;
+    float* dbg_O;
+    int B, M, N;
+    float p;              // DDF weight
+    MinimaxCoef coef;     // Table 1 row for the chosen q
+};
+
+// Launch the forward filter on `stream`.  Returns hipSuccess or the launch error.
+hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates,
+                          const FwdParams& prm, hipStream_t stream);
+
+}  // namespace odf

@@ -1,0 +1,170 @@
+// pair_terms.h -- device-side pixel preparation and pair terms of the
+// directional filters (Section II and Sections 2.1-2.2 of Celebi,
+// arXiv:1009.0958), in binary32 on the VALU of gfx950.
+//
+// Each prepared pixel is two float4 values:
+//   dir = (d.x, d.y, d.z, aux1)   d: direction (the pixel, or (1,1,1) for 0)
+//   raw = (x.x, x.y, x.z, aux2)   x: the raw pixel
+//   EXACT:   aux1, aux2 unused
+//   MINIMAX: aux1 = |d|^2, aux2 = 1/|d|
+//   RGB:     aux1 = d.x + d.y + d.z, aux2 = 1/aux1
+//
+// Every pair term is symmetric bit for bit (term(a,b) == term(b,a)) and
+// returns for a pair of equal vectors exactly the value it returns for the
+// self pair, so equal colours in a window get bitwise-equal aggregates.
+// Cross-product and chromaticity numerators are differences of two rounded
+// products (no fused multiply-add), which keeps swapped arguments exact
+// negations; for uint8 inputs they are exact integers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "atan_poly.h"
+
+namespace odf {
+
+enum Kind { kBVDF = 0, kDDF = 1 };
+enum Dist { kExact = 0, kMinimax = 1, kRgb = 2 };
+
+// eq. (10): A ~= 1.436437 B + 0.027664
+constexpr float kEq10Alpha = 1.436437f;
+constexpr float kEq10Beta = 0.027664f;
+
+constexpr float kHalfPi = 1.57079632679489661923f;
+constexpr float kPi = 3.14159265358979323846f;
+
+// a*b - c*d with both products rounded separately.
+__device__ __forceinline__ float diff_of_products(float a, float b, float c, float d) {
+#pragma clang fp contract(off)
+    return a * b - c * d;
+}
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float sqrt_raw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Table 1 coefficients, zero-padded to degree 4 (Horner with leading zeros
+// reproduces the degree-q evaluation exactly).
+struct MinimaxCoef {
+    float asin_c[5];
+    float acos_c[5];
+};
+
+__device__ __forceinline__ float horner4(const float* c, float t) {
+    float acc = c[4];
+    acc = fmaf(acc, t, c[3]);
+    acc = fmaf(acc, t, c[2]);
+    acc = fmaf(acc, t, c[1]);
+    acc = fmaf(acc, t, c[0]);
+    return acc;
+}
+
+// Prepare one pixel.  For float inputs the direction is scaled by a power of
+// two (exact; angles and chromaticities are scale-free) so that its largest
+// magnitude lies in [1, 2), which keeps every product below in range.
+template <int DIST, bool U8>
+__device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, float4& dir,
+                                              float4& raw) {
+    float d0 = x0, d1 = x1, d2 = x2;
+    bool zero = (x0 == 0.0f) & (x1 == 0.0f) & (x2 == 0.0f);
+    if (!U8) {
+        float m = fmaxf(fabsf(x0), fmaxf(fabsf(x1), fabsf(x2)));
+        int e = zero ? 0 : ilogbf(m);
+        d0 = ldexpf(x0, -e);
+        d1 = ldexpf(x1, -e);
+        d2 = ldexpf(x2, -e);
+    }
+    if (zero) d0 = d1 = d2 = 1.0f;
+    float aux1 = 0.0f, aux2 = 0.0f;
+    if (DIST == kMinimax) {
+        aux1 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        aux2 = 1.0f / sqrtf(aux1);
+    } else if (DIST == kRgb) {
+        aux1 = (d0 + d1) + d2;
+        aux2 = 1.0f / aux1;
+    }
+    dir = make_float4(d0, d1, d2, aux1);
+    raw = make_float4(x0, x1, x2, aux2);
+}
+
+// Exact angle of eq. (2), evaluated as atan2(|a x b|, a.b):
+// with P = |a x b|^2 and Q = (a.b)^2, r = sqrt(min(P,Q)/max(P,Q)) =
+// min(P,Q) / sqrt(P Q) lies in [0, 1] and the angle is atan(r) or
+// pi/2 - atan(r); one reciprocal square root per pair.
+template <bool SIGNED>
+__device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
+    float dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
+    float c0 = diff_of_products(a.y, b.z, a.z, b.y);
+    float c1 = diff_of_products(a.z, b.x, a.x, b.z);
+    float c2 = diff_of_products(a.x, b.y, a.y, b.x);
+    float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+    float Q = dot * dot;
+    float m = fminf(P, Q);
+    float r = m * rsq(fmaxf(P * Q, 1.17549435e-38f));
+    float t = r * r;
+    float acc = kAtanPoly[ODF_ATAN_DEG];
+#pragma unroll
+    for (int k = ODF_ATAN_DEG - 1; k >= 0; --k) acc = fmaf(acc, t, kAtanPoly[k]);
+    float at = r * acc;
+    float th = (P > Q) ? (kHalfPi - at) : at;
+    if (SIGNED) th = (dot < 0.0f) ? (kPi - th) : th;
+    return th;
+}
+
+// Method 1 (Section 2.1): ACOS row of Table 1 in z for z < 1/2, ASIN row in
+// tau = sqrt(1 - z) for z >= 1/2 (eqs. 5-6), clamped at 0.  The branch is the
+// exact predicate 4 (a.b)^2 < |a|^2 |b|^2 (binary64 products of binary32
+// values are exact), and 1 - z = |a x b|^2 / (|a|^2 |b|^2 (1 + z)) avoids the
+// cancellation of 1 - z next to z = 1.
+__device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra, const float4& b,
+                                               const float4& rb, const MinimaxCoef& cf) {
+    float dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
+    float z = dot * (ra.w * rb.w);
+    bool acos_branch = (dot < 0.0f) ||
+                       (4.0 * (double)dot * (double)dot < (double)a.w * (double)b.w);
+    float c0 = diff_of_products(a.y, b.z, a.z, b.y);
+    float c1 = diff_of_products(a.z, b.x, a.x, b.z);
+    float c2 = diff_of_products(a.x, b.y, a.y, b.x);
+    float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+    float X = (a.w * b.w) * (1.0f + z);
+    float tau = P * rsq(fmaxf(P * X, 1.17549435e-38f));
+    float v = acos_branch ? horner4(cf.acos_c, z) : horner4(cf.asin_c, tau);
+    return fmaxf(v, 0.0f);
+}
+
+// Method 2 (Section 2.2, eq. 7): L2 distance of chromaticities
+// |a / sum a - b / sum b| = |a sum b - b sum a| / (sum a sum b).
+template <int KIND>
+__device__ __forceinline__ float chroma_term(const float4& a, const float4& ra, const float4& b,
+                                             const float4& rb) {
+    float n0 = diff_of_products(a.x, b.w, b.x, a.w);
+    float n1 = diff_of_products(a.y, b.w, b.y, a.w);
+    float n2 = diff_of_products(a.z, b.w, b.z, a.w);
+    float Nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+    float B = sqrt_raw(Nn) * (ra.w * rb.w);
+    if (KIND == kDDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
+    return B;
+}
+
+// Angular pair term of the chosen variant.
+template <int KIND, int DIST, bool U8>
+__device__ __forceinline__ float pair_term(const float4& a, const float4& ra, const float4& b,
+                                           const float4& rb, const MinimaxCoef& cf) {
+    if (DIST == kExact) return angle_exact<!U8>(a, b);
+    if (DIST == kMinimax) return angle_minimax(a, ra, b, rb, cf);
+    return chroma_term<KIND>(a, ra, b, rb);
+}
+
+// eq. (1) with the L2 norm (Section III), on raw values.
+__device__ __forceinline__ float l2_term(const float4& ra, const float4& rb) {
+    float e0 = ra.x - rb.x, e1 = ra.y - rb.y, e2 = ra.z - rb.z;
+    return sqrt_raw(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
+}
+
+// Total order on floats (no NaN) as unsigned keys.
+__device__ __forceinline__ uint32_t order_key(float v) {
+    uint32_t bits = __float_as_uint(v + 0.0f);  // -0 -> +0
+    return (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
+}
+
+}  // namespace odf

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/odf.h declares, and rejects bad arguments before any
+launch (return codes and messages)."""
+import ctypes
+
+import pytest
+
+from paper_1009_0958_amd import odf
+
+FAKE = ctypes.c_void_p(0x7F0000000000)  # never dereferenced: validation fails first
+FAKE2 = ctypes.c_void_p(0x7F0000100000)
+
+
+def test_exports_every_declared_function():
+    L = odf.lib()
+    names = odf.declared_functions()
+    assert "odf_filter_u8" in names and "odf_last_error" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert L.odf_version() >= 1
+
+
+def _u8(img, B, M, N, w, kind, p, dist, q, out, idx=None):
+    return odf.lib().odf_filter_u8(img, B, M, N, w, kind, p, dist, q, out, idx, None)
+
+
+@pytest.mark.parametrize("args,code,text", [
+    ((None, 1, 8, 8, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "img"),
+    ((FAKE, 1, 8, 8, 3, 0, 0.0, 0, 4, None), odf.EINVAL, "out"),
+    ((FAKE, 0, 8, 8, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
+    ((FAKE, 1, -1, 8, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
+    ((FAKE, 1, 8, 0, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
+    ((FAKE, 4096, 4096, 4096, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "2^31"),
+    ((FAKE, 1, 8, 8, 7, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 4, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 3, 2, 0.0, 0, 4, FAKE2), odf.EINVAL, "kind"),
+    ((FAKE, 1, 8, 8, 3, 0, 0.0, 3, 4, FAKE2), odf.EINVAL, "dist"),
+    ((FAKE, 1, 8, 8, 3, 0, 0.0, 1, 5, FAKE2), odf.EINVAL, "q"),
+    ((FAKE, 1, 8, 8, 3, 0, 0.0, 1, 1, FAKE2), odf.EINVAL, "q"),
+    ((FAKE, 1, 8, 8, 3, 1, 1.5, 0, 4, FAKE2), odf.EINVAL, "p"),
+    ((FAKE, 1, 8, 8, 3, 1, -0.1, 0, 4, FAKE2), odf.EINVAL, "p"),
+    ((FAKE, 1, 8, 8, 3, 1, float("nan"), 0, 4, FAKE2), odf.EINVAL, "p"),
+    ((FAKE, 1, 8, 8, 3, 0, 0.0, 0, 4, FAKE), odf.EINVAL, "overlaps"),
+    ((FAKE, 1, 8, 8, 3, 0, 0.0, 0, 4, ctypes.c_void_p(0x7F0000000000 + 100)), odf.EINVAL,
+     "overlaps"),
+])
+def test_filter_rejects(args, code, text):
+    rc = _u8(*args)
+    assert rc == code
+    assert text in odf.last_error()
+
+
+def test_idx_aliasing_rejected():
+    rc = _u8(FAKE, 1, 8, 8, 3, 0, 0.0, 0, 4, FAKE2, ctypes.c_void_p(0x7F0000100000 + 10))
+    assert rc == odf.EINVAL and "idx" in odf.last_error()
+
+
+def test_f32_and_aggregates_reject():
+    L = odf.lib()
+    assert L.odf_filter_f32(None, 1, 4, 4, 3, 0, 0.0, 0, 4, FAKE2, None, None) == odf.EINVAL
+    assert L.odf_aggregates(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, None, None, None, None) == odf.EINVAL
+    assert "A" in odf.last_error()
+    assert L.odf_aggregates(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, FAKE2, FAKE2, None, None) == odf.EINVAL
+    assert "overlap" in odf.last_error()
+
+
+def test_declared_names_match_binding():
+    # every declared function has a binding attribute configured or a plain C symbol
+    for name in odf.declared_functions():
+        assert callable(getattr(odf.lib(), name))

@@ -41,5 +41,18 @@ def build(verbose: bool = False, extra=None) -> str:
     return LIB
 
 
+def build_microbench(verbose: bool = False) -> str:
+    """Compile the VALU-rate / copy-bandwidth microbenchmark executable."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    src = os.path.join(HERE, "microbench", "valu_rates.hip")
+    exe = os.path.join(HERE, "microbench", "valu_rates")
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    cmd = [hipcc, *flags, src, "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True, extra=sys.argv[1:])

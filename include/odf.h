@@ -104,6 +104,51 @@ int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, 
 int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, int kind,
                    float p, int dist, int q, float* A, float* D, float* Omega, void* stream);
 
+/*
+ * Gradient of the hard filter (one-hot routing of the selection).
+ *   idx  B x M x N uint8 from odf_filter_* (read only).
+ *   dy   B x M x N x 3 float32 upstream gradient dL/dy.
+ *   dx   B x M x N x 3 float32 output: dx(q) = sum of dy(c) over the windows c
+ *        whose selected member is the pixel q (replicated border: a window
+ *        selecting an out-of-image position selects its clamped source).  Each
+ *        sum is formed in binary64 over c in raster order and rounded once.
+ * The forward selection is not touched.  Errors: ODF_EINVAL for null
+ * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for window.
+ */
+int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int N, int window,
+                          float* dx, void* stream);
+
+/*
+ * Softmin relaxation of the argmin (exact angle of eq. 2; kind/p as for the
+ * filter): per window c, pi_u = exp(-(Omega_u - min_v Omega_v) / tau) / Z and
+ * y(c) = sum_u pi_u x_u.  tau -> 0 tends to the hard selection where the
+ * minimum is unique.
+ *   x  B x M x N x 3 float32 (read only); y  B x M x N x 3 float32 output.
+ * Errors: as odf_filter_f32, plus ODF_EINVAL for tau <= 0 or not finite.
+ */
+int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,
+                        float tau, float* y, void* stream);
+
+/* Workspace bytes odf_softmin_bwd_f32 needs for this shape (0 if invalid). */
+size_t odf_softmin_bwd_workspace(int B, int M, int N, int window, int kind);
+
+/*
+ * Gradient of sum(dy * y) for the softmin relaxation, with respect to x:
+ * through the weights pi (and so through Omega, the angle aggregates A and the
+ * L2 aggregates D down to every pixel) and through the direct term pi_u.
+ * Conventions where the derivative does not exist: the angle gradient is 0
+ * for parallel pairs and zero pixels, the L2 gradient 0 for equal pixels,
+ * dOmega/dA (dD) 0 where A (D) is 0 under a fractional power.
+ *   dy         B x M x N x 3 float32 upstream gradient.
+ *   dx         B x M x N x 3 float32 output.
+ *   workspace  device scratch of at least odf_softmin_bwd_workspace() bytes,
+ *              owned by the caller; its contents on entry are ignored.
+ * Deterministic: the result does not depend on scheduling.
+ */
+int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, int window, int kind,
+                        float p, float tau, float* dx, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,129 @@
+// aggregates.h -- per-member window aggregates over a workgroup tile (shared
+// by the forward filter and the softmin kernels).
+//
+// One workgroup owns an extended tile of EXT_H x EXT_W pixels (the output
+// tile plus a halo of h = (w-1)/2 pixels) with one thread per extended
+// pixel.  For a member pixel p, its offset grid
+// G_p(dy, dx) = theta(p, p + (dy, dx)), dy, dx in [-2h, 2h], holds every pair
+// term a window containing p needs: the aggregate of p in window c is the sum
+// of G_p over the w x w box of W(c) (Section II, eqs. 2-3).  Each unordered
+// pixel pair is evaluated once: for each row group g = |dy| = 0..2h the
+// thread computes the pair terms of offsets (g, dx) of its own pixel,
+// publishes them in an LDS plane, and reads back the mirrored terms of row -g
+// from the pixels above.  Rows +g and -g are reduced at once into row sums of
+// w consecutive offsets; the window aggregates are the column sums of those
+// row sums.  The summation tree is the same in absolute pixel positions for
+// every member of a window (rows left to right, then rows top to bottom), so
+// equal colours get bitwise-equal aggregates and ties stay ties.
+#pragma once
+
+#include "pair_terms.h"
+
+namespace odf {
+
+template <int W, int EXT_W, int EXT_H>
+struct FwdGeom {
+    static constexpr int H = W / 2;
+    static constexpr int NW = W * W;
+    static constexpr int G = 4 * H + 1;  // offsets per axis of a member's grid
+    static constexpr int TW = EXT_W - 2 * H;
+    static constexpr int TH = EXT_H - 2 * H;
+    static constexpr int NT = EXT_W * EXT_H;
+};
+
+template <int W>
+__device__ __forceinline__ void row_sums(const float (&row)[4 * (W / 2) + 1], float (&out)[W]) {
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+        float acc = row[s];
+#pragma unroll
+        for (int k = 1; k < W; ++k) acc += row[s + k];
+        out[s] = acc;
+    }
+}
+
+// Aggregates of the own member p over every window containing it, for the
+// angular term (L2PASS = false) or the L2 term of eq. (1) (L2PASS = true).
+// agg[u] is the aggregate of p in the window c = p - offset(u).
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS>
+__device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_dir,
+                                                  const float4* __restrict__ s_raw,
+                                                  float* __restrict__ s_plane, int ey, int ex,
+                                                  int tid, const float4& mdir, const float4& mraw,
+                                                  const MinimaxCoef& cf, float (&agg)[W * W]) {
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    constexpr int H = Gm::H, G = Gm::G, NT = Gm::NT;
+
+    auto term = [&](int q) -> float {
+        if (L2PASS) return l2_term(mraw, s_raw[q]);
+        return pair_term<KIND, DIST, U8>(mdir, mraw, s_dir[q], s_raw[q], cf);
+    };
+    const float self =
+        L2PASS ? 0.0f : pair_term<KIND, DIST, U8>(mdir, mraw, mdir, mraw, cf);
+
+    float R[G][W];  // R[dy + 2h][s + 2h]: sum of G_p(dy, s .. s + w - 1)
+#pragma unroll
+    for (int g = 0; g <= 2 * H; ++g) {
+        float own[G], up[G];
+#pragma unroll
+        for (int dx = -2 * H; dx <= 2 * H; ++dx) {
+            own[dx + 2 * H] = 0.0f;
+            if (g == 0 && dx <= 0) continue;
+            const int py = ey + g, px = ex + dx;
+            if (py < EXT_H && px >= 0 && px < EXT_W) {
+                const float v = term(py * EXT_W + px);
+                own[dx + 2 * H] = v;
+                s_plane[(dx + 2 * H) * NT + tid] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int dx = -2 * H; dx <= 2 * H; ++dx) {
+            up[dx + 2 * H] = 0.0f;
+            if (g == 0 && dx >= 0) continue;
+            const int py = ey - g, px = ex + dx;
+            if (py >= 0 && px >= 0 && px < EXT_W)
+                up[dx + 2 * H] = s_plane[(2 * H - dx) * NT + py * EXT_W + px];
+        }
+        if (g == 0) {
+            float row[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) row[k] = k < 2 * H ? up[k] : (k == 2 * H ? self : own[k]);
+            row_sums<W>(row, R[2 * H]);
+        } else {
+            row_sums<W>(own, R[2 * H + g]);
+            row_sums<W>(up, R[2 * H - g]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int uy = -H; uy <= H; ++uy) {
+#pragma unroll
+        for (int ux = -H; ux <= H; ++ux) {
+            const int s = -H - ux + 2 * H;
+            float acc = R[-H - uy + 2 * H][s];
+#pragma unroll
+            for (int dy = -H - uy + 1; dy <= H - uy; ++dy) acc += R[dy + 2 * H][s];
+            agg[(uy + H) * W + (ux + H)] = acc;
+        }
+    }
+}
+
+// Objective of one member: BVDF (eq. 2) A; DDF A^(1-p) D^p (p = 1/2 orders as
+// the product of eq. 3).  objective_log is a monotone image used for
+// comparisons; objective_value is the objective itself.
+template <int KIND>
+__device__ __forceinline__ float objective_log(float A, float D, float p) {
+    if (KIND == kBVDF || p == 0.0f) return A;
+    if (p == 1.0f) return D;
+    return fmaf(1.0f - p, __builtin_amdgcn_logf(A), p * __builtin_amdgcn_logf(D));
+}
+
+template <int KIND>
+__device__ __forceinline__ float objective_value(float A, float D, float p) {
+    if (KIND == kBVDF || p == 0.0f) return A;
+    if (p == 1.0f) return D;
+    return exp2f(fmaf(1.0f - p, log2f(A), p * log2f(D)));
+}
+
+}  // namespace odf

@@ -133,4 +133,73 @@ int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, 
     return ODF_OK;
 }
 
+int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int N, int window,
+                          float* dx, void* stream) {
+    if (!idx || !dy || !dx) return fail(ODF_EINVAL, "idx, dy and dx must be non-NULL");
+    if (B < 1 || M < 1 || N < 1) return fail(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
+    if ((long long)B * M * N >= (1ll << 31)) return fail(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
+    if (window != 3 && window != 5)
+        return fail(ODF_EUNSUPPORTED, "window %d not supported (3 or 5)", window);
+    const size_t npix = (size_t)B * M * N;
+    if (overlaps(dx, npix * 12, dy, npix * 12) || overlaps(dx, npix * 12, idx, npix))
+        return fail(ODF_EINVAL, "dx overlaps dy or idx");
+    hipError_t e = odf::launch_backward_hard(window, idx, dy, dx, B, M, N,
+                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hard backward launch");
+    return ODF_OK;
+}
+
+static int check_soft(const float* x, int B, int M, int N, int window, int kind, float p, float tau) {
+    int rc = check_common(x, B, M, N, window, kind, p, ODF_EXACT, 4);
+    if (rc) return rc;
+    if (!(tau > 0.0f) || !(tau < 3.0e38f)) return fail(ODF_EINVAL, "tau must be positive and finite");
+    return ODF_OK;
+}
+
+int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,
+                        float tau, float* y, void* stream) {
+    int rc = check_soft(x, B, M, N, window, kind, p, tau);
+    if (rc) return rc;
+    if (!y) return fail(ODF_EINVAL, "y is NULL");
+    const size_t nb = (size_t)B * M * N * 12;
+    if (overlaps(x, nb, y, nb)) return fail(ODF_EINVAL, "y overlaps x");
+    odf::SoftParams prm{};
+    prm.x = x; prm.y = y; prm.B = B; prm.M = M; prm.N = N;
+    prm.p = kind == ODF_DDF ? p : 0.0f;
+    prm.inv_tau = 1.0f / tau;
+    hipError_t e = odf::launch_softmin(window, kind, false, prm, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "softmin forward launch");
+    return ODF_OK;
+}
+
+size_t odf_softmin_bwd_workspace(int B, int M, int N, int window, int kind) {
+    if (B < 1 || M < 1 || N < 1 || (window != 3 && window != 5) ||
+        (kind != ODF_BVDF && kind != ODF_DDF))
+        return 0;
+    return odf::softmin_workspace_bytes(window, kind, B, M, N);
+}
+
+int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, int window, int kind,
+                        float p, float tau, float* dx, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+    int rc = check_soft(x, B, M, N, window, kind, p, tau);
+    if (rc) return rc;
+    if (!dy || !dx || !workspace) return fail(ODF_EINVAL, "dy, dx and workspace must be non-NULL");
+    const size_t need = odf::softmin_workspace_bytes(window, kind, B, M, N);
+    if (workspace_bytes < need)
+        return fail(ODF_EINVAL, "workspace too small (%zu < %zu bytes)", workspace_bytes, need);
+    const size_t nb = (size_t)B * M * N * 12;
+    if (overlaps(dx, nb, x, nb) || overlaps(dx, nb, dy, nb) || overlaps(workspace, need, x, nb) ||
+        overlaps(workspace, need, dy, nb) || overlaps(workspace, need, dx, nb))
+        return fail(ODF_EINVAL, "dx / workspace overlap an input or each other");
+    odf::SoftParams prm{};
+    prm.x = x; prm.dy = dy; prm.dx = dx; prm.ws = static_cast<float*>(workspace);
+    prm.B = B; prm.M = M; prm.N = N;
+    prm.p = kind == ODF_DDF ? p : 0.0f;
+    prm.inv_tau = 1.0f / tau;
+    hipError_t e = odf::launch_softmin(window, kind, true, prm, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "softmin backward launch");
+    return ODF_OK;
+}
+
 }  // extern "C"

@@ -24,4 +24,20 @@ struct FwdParams {
 hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates,
                           const FwdParams& prm, hipStream_t stream);
 
+struct SoftParams {
+    const float* x;   // B x M x N x 3
+    const float* dy;  // backward: upstream gradient, B x M x N x 3
+    float* y;         // forward output
+    float* dx;        // backward output
+    float* ws;        // backward workspace (per-tile contributions)
+    int B, M, N;
+    float p;
+    float inv_tau;
+};
+
+hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy, float* dx, int B,
+                                int M, int N, hipStream_t stream);
+size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N);
+hipError_t launch_softmin(int window, int kind, bool bwd, const SoftParams& prm, hipStream_t s);
+
 }  // namespace odf

@@ -5,7 +5,7 @@
 // Each prepared pixel is two float4 values:
 //   dir = (d.x, d.y, d.z, aux1)   d: direction (the pixel, or (1,1,1) for 0)
 //   raw = (x.x, x.y, x.z, aux2)   x: the raw pixel
-//   EXACT:   aux1, aux2 unused
+//   EXACT:   aux1 unused, aux2 = |d| / |x| (a power of two; 0 for x = 0)
 //   MINIMAX: aux1 = |d|^2, aux2 = 1/|d|
 //   RGB:     aux1 = d.x + d.y + d.z, aux2 = 1/aux1
 //
@@ -66,17 +66,22 @@ template <int DIST, bool U8>
 __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, float4& dir,
                                               float4& raw) {
     float d0 = x0, d1 = x1, d2 = x2;
-    bool zero = (x0 == 0.0f) & (x1 == 0.0f) & (x2 == 0.0f);
+    const bool zero = (x0 == 0.0f) & (x1 == 0.0f) & (x2 == 0.0f);
+    int e = 0;
     if (!U8) {
-        float m = fmaxf(fabsf(x0), fmaxf(fabsf(x1), fabsf(x2)));
-        int e = zero ? 0 : ilogbf(m);
+        const float m = fmaxf(fabsf(x0), fmaxf(fabsf(x1), fabsf(x2)));
+        e = zero ? 0 : ilogbf(m);
         d0 = ldexpf(x0, -e);
         d1 = ldexpf(x1, -e);
         d2 = ldexpf(x2, -e);
     }
     if (zero) d0 = d1 = d2 = 1.0f;
     float aux1 = 0.0f, aux2 = 0.0f;
-    if (DIST == kMinimax) {
+    if (DIST == kExact) {
+        // d = 2^-e x: the derivative of the direction (0 for the zero pixel,
+        // whose direction is a constant), used by the angle gradient
+        aux2 = zero ? 0.0f : ldexpf(1.0f, -e);
+    } else if (DIST == kMinimax) {
         aux1 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
         aux2 = 1.0f / sqrtf(aux1);
     } else if (DIST == kRgb) {

@@ -1,0 +1,396 @@
+// softmin.hip -- temperature-tau softmin relaxation of the argmin and its
+// gradient (float32 images, exact angle of eq. 2, DDF objective
+// Omega = A^(1-p) D^p or BVDF Omega = A).
+//
+// Forward, per window c:  pi_u = exp(-(Omega_u - min Omega) / tau) / Z,
+//                         y(c) = sum_u pi_u x(c + u).
+// Backward (reverse mode of the same expression, written for the tile):
+//   direct term      dx(q) += pi_u(c) dy(c)                   (q = c + u)
+//   through Omega    g_u(c) = -pi_u (x_u - y(c)) . dy(c) / tau,
+//                    G^A_u(c) = g_u dOmega/dA_u, G^D_u(c) = g_u dOmega/dD_u
+//   through the pair terms: with A_u(c) = sum_v theta(x_{c+u}, x_{c+v}),
+//     dx(q) += sum_{r != q} S(q, r) grad_1 theta(q, r),
+//     S(q, r) = sum over windows c containing q and r of G_{u_q}(c) + G_{u_r}(c)
+//             = B_q(r - q) + B_r(q - r),
+//     B_p(d) = sum of G_u(p - u) over the members u of windows that contain
+//              both p and p + d (a box sum of the transposed window grid);
+//   the same for D with the L2 gradient.
+// Each workgroup handles the windows of its tile and produces gradient
+// contributions for every pixel of its extended tile; contributions of
+// replicated border positions are folded into their source pixel inside the
+// tile, written per tile to a workspace, and summed over the (at most four)
+// overlapping tiles by a second kernel in a fixed order, so the result does
+// not depend on scheduling.
+#include "aggregates.h"
+#include "odf_internal.h"
+
+namespace odf {
+
+// Extended tile of the softmin kernels (one thread per extended pixel).
+template <int W, int KIND>
+struct SoftTile {
+    static constexpr int EXT_W = 32;
+    static constexpr int EXT_H = 16;
+};
+constexpr int kSoftThreads = 512;
+
+__device__ __forceinline__ float key_value(uint32_t k) {
+    uint32_t bits = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(bits);
+}
+
+// dOmega/dA and dOmega/dD (0 where a fractional power meets a zero aggregate).
+template <int KIND>
+__device__ __forceinline__ void objective_grad(float A, float D, float Om, float p, float& dA,
+                                               float& dD) {
+    if (KIND == kBVDF || p == 0.0f) { dA = 1.0f; dD = 0.0f; return; }
+    if (p == 1.0f) { dA = 0.0f; dD = 1.0f; return; }
+    dA = A > 0.0f ? (1.0f - p) * Om / A : 0.0f;
+    dD = D > 0.0f ? p * Om / D : 0.0f;
+}
+
+// u*v - w*z to within a rounding of the exact value: the rounding error of
+// w*z is recovered with a fused multiply-add (Dekker's two-product).
+__device__ __forceinline__ float cross_term(float u, float v, float w, float z) {
+    const float p = w * z;
+    const float e = fmaf(w, z, -p);
+    return fmaf(u, v, -p) - e;
+}
+
+// grad_1 theta(a, b) = (a x c) / (|c| |a|^2), c = a x b, on the directions a, b
+// of the two pixels, times da/dx = `scale` for the raw first pixel.  c is
+// formed to full relative accuracy and a x c is well conditioned (c is
+// orthogonal to a), so nearly parallel pairs keep an accurate gradient
+// direction; equal directions give c = 0 exactly and a zero gradient.
+__device__ __forceinline__ float3 angle_grad(const float4& a, float inv_a2, float scale,
+                                             const float4& b) {
+    const float c0 = cross_term(a.y, b.z, a.z, b.y);
+    const float c1 = cross_term(a.z, b.x, a.x, b.z);
+    const float c2 = cross_term(a.x, b.y, a.y, b.x);
+    const float s2 = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+    const float k = s2 > 0.0f ? rsq(s2) * (inv_a2 * scale) : 0.0f;
+    const float k0 = fmaf(a.y, c2, -a.z * c1);
+    const float k1 = fmaf(a.z, c0, -a.x * c2);
+    const float k2 = fmaf(a.x, c1, -a.y * c0);
+    return make_float3(k0 * k, k1 * k, k2 * k);
+}
+
+// grad_1 |a - b| = (a - b) / |a - b|, 0 for a = b.
+__device__ __forceinline__ float3 l2_grad(const float4& a, const float4& b) {
+    float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z;
+    float l2 = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+    float il = l2 > 0.0f ? rsq(l2) : 0.0f;
+    return make_float3(e0 * il, e1 * il, e2 * il);
+}
+
+// Sum of gr[u] over members u = (uy, ux) of windows containing both p and p + d.
+template <int W>
+__device__ __forceinline__ float box_over_members(const float (&gr)[W * W], int dy, int dx) {
+    constexpr int H = W / 2;
+    float acc = 0.0f;
+#pragma unroll
+    for (int uy = -H; uy <= H; ++uy) {
+        if (uy + dy < -H || uy + dy > H) continue;
+#pragma unroll
+        for (int ux = -H; ux <= H; ++ux) {
+            if (ux + dx < -H || ux + dx > H) continue;
+            acc += gr[(uy + H) * W + (ux + H)];
+        }
+    }
+    return acc;
+}
+
+// Pair-term part of the gradient for one plane (angle, or L2 when L2PASS):
+// dx(q) += sum_{r != q} (B_q(r - q) + B_r(q - r)) grad_1 term(q, r), the B
+// of the neighbours exchanged through LDS planes one row group at a time.
+template <int W, int EXT_W, int EXT_H, bool L2PASS>
+__device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
+                                                const float4* __restrict__ s_dir,
+                                                const float4* __restrict__ s_raw,
+                                                float* __restrict__ s_plane, int ey, int ex,
+                                                int tid, const float4& mdir, const float4& mraw,
+                                                float inv_a2, float& gx0, float& gx1, float& gx2) {
+    constexpr int H = W / 2, G = 4 * H + 1, NT = EXT_W * EXT_H;
+    float* P_dn = s_plane;           // B_r((-g, -dx)), read by the pixel r - (g, dx)
+    float* P_up = s_plane + G * NT;  // B_r((g, -dx)),  read by the pixel r - (-g, dx)
+#pragma unroll
+    for (int g = 0; g <= 2 * H; ++g) {
+#pragma unroll
+        for (int dx = -2 * H; dx <= 2 * H; ++dx) {
+            if (g == 0 && dx == 0) continue;
+            P_dn[(dx + 2 * H) * NT + tid] = box_over_members<W>(gr, -g, -dx);
+            if (g > 0) P_up[(dx + 2 * H) * NT + tid] = box_over_members<W>(gr, g, -dx);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int sgn = 1; sgn >= -1; sgn -= 2) {
+            if (g == 0 && sgn < 0) continue;
+            const float* P = sgn > 0 ? P_dn : P_up;
+#pragma unroll
+            for (int dx = -2 * H; dx <= 2 * H; ++dx) {
+                if (g == 0 && dx == 0) continue;
+                const int ry = ey + sgn * g, rx = ex + dx;
+                if (ry < 0 || ry >= EXT_H || rx < 0 || rx >= EXT_W) continue;
+                const int r = ry * EXT_W + rx;
+                const float S = box_over_members<W>(gr, sgn * g, dx) + P[(dx + 2 * H) * NT + r];
+                if (S == 0.0f) continue;
+                const float3 gv = L2PASS ? l2_grad(mraw, s_raw[r])
+                                         : angle_grad(mdir, inv_a2, mraw.w, s_dir[r]);
+                gx0 = fmaf(S, gv.x, gx0);
+                gx1 = fmaf(S, gv.y, gx1);
+                gx2 = fmaf(S, gv.z, gx2);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int W, int KIND, bool BWD>
+__global__ void __launch_bounds__(kSoftThreads) softmin_kernel(SoftParams prm) {
+    constexpr int EXT_W = SoftTile<W, KIND>::EXT_W, EXT_H = SoftTile<W, KIND>::EXT_H;
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
+    constexpr int TT = TW * TH;
+    constexpr int NPLANE = BWD ? 2 * G : G;
+    static_assert(NT == kSoftThreads, "one thread per extended pixel");
+
+    __shared__ float4 s_dir[NT];
+    __shared__ float4 s_raw[NT];
+    __shared__ float s_plane[NPLANE * NT];
+    __shared__ uint32_t s_key[TT];
+    __shared__ float s_e[NW * TT];
+    __shared__ float s_win[BWD ? 8 * TT : 1];
+
+    const int tid = threadIdx.x;
+    const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
+    const int b = blockIdx.z;
+    const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+    const int M = prm.M, N = prm.N;
+    const float p = prm.p;
+    const float inv_tau = prm.inv_tau;
+
+    {
+        const int gy = min(max(ty0 - H + ey, 0), M - 1);
+        const int gx = min(max(tx0 - H + ex, 0), N - 1);
+        const float* s = prm.x + (((size_t)b * M + gy) * N + gx) * 3;
+        float4 d, r;
+        prepare_pixel<kExact, false>(s[0], s[1], s[2], d, r);
+        s_dir[tid] = d;
+        s_raw[tid] = r;
+    }
+    for (int i = tid; i < TT; i += NT) s_key[i] = 0xffffffffu;
+    __syncthreads();
+    const float4 mdir = s_dir[tid];
+    const float4 mraw = s_raw[tid];
+    const MinimaxCoef no_coef{};
+
+    float A[NW], D[NW], Om[NW];
+    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex,
+                                                                  tid, mdir, mraw, no_coef, A);
+    if (KIND == kDDF)
+        member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey,
+                                                                     ex, tid, mdir, mraw,
+                                                                     no_coef, D);
+    else
+#pragma unroll
+        for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+
+    auto window_of = [&](int u, int& c) -> bool {
+        const int cy = ey - u / W, cx = ex - u % W;
+        if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) return false;
+        if (ty0 + cy >= M || tx0 + cx >= N) return false;
+        c = cy * TW + cx;
+        return true;
+    };
+
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        Om[u] = objective_value<KIND>(A[u], D[u], p);
+        int c;
+        if (window_of(u, c)) atomicMin(&s_key[c], order_key(Om[u]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        int c;
+        if (window_of(u, c)) s_e[u * TT + c] = __expf((key_value(s_key[c]) - Om[u]) * inv_tau);
+    }
+    __syncthreads();
+
+    // per window: Z, y (and dy for the backward), members in index order
+    for (int i = tid; i < TT; i += NT) {
+        const int cy = i / TW, cx = i - (i / TW) * TW;
+        const int gy = ty0 + cy, gx = tx0 + cx;
+        if (gy >= M || gx >= N) continue;
+        float z = 0.0f;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) z += s_e[u * TT + i];
+        const float iz = 1.0f / z;
+        float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const float pi = s_e[u * TT + i] * iz;
+            const float4 r = s_raw[(cy + u / W) * EXT_W + cx + u % W];
+            y0 = fmaf(pi, r.x, y0);
+            y1 = fmaf(pi, r.y, y1);
+            y2 = fmaf(pi, r.z, y2);
+        }
+        const size_t pix = ((size_t)b * M + gy) * N + gx;
+        if (!BWD) {
+            prm.y[pix * 3 + 0] = y0;
+            prm.y[pix * 3 + 1] = y1;
+            prm.y[pix * 3 + 2] = y2;
+        } else {
+            float* w = s_win + 8 * i;
+            w[0] = iz; w[1] = y0; w[2] = y1; w[3] = y2;
+            w[4] = prm.dy[pix * 3 + 0];
+            w[5] = prm.dy[pix * 3 + 1];
+            w[6] = prm.dy[pix * 3 + 2];
+        }
+    }
+    if (!BWD) return;
+    __syncthreads();
+
+    // ---------------------------------------------------------------- backward
+    float gx0 = 0.0f, gx1 = 0.0f, gx2 = 0.0f;  // dL/dx of this extended position
+    // A[] <- G^A, D[] <- G^D (per member u of the window p - u)
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        int c;
+        float ga = 0.0f, gd = 0.0f;
+        if (window_of(u, c)) {
+            const float* w = s_win + 8 * c;
+            const float pi = s_e[u * TT + c] * w[0];
+            gx0 = fmaf(pi, w[4], gx0);
+            gx1 = fmaf(pi, w[5], gx1);
+            gx2 = fmaf(pi, w[6], gx2);
+            const float t = fmaf(mraw.x - w[1], w[4], fmaf(mraw.y - w[2], w[5], (mraw.z - w[3]) * w[6]));
+            const float gom = -pi * t * inv_tau;
+            float dA, dD;
+            objective_grad<KIND>(A[u], D[u], Om[u], p, dA, dD);
+            ga = gom * dA;
+            gd = gom * dD;
+        }
+        A[u] = ga;
+        D[u] = gd;
+    }
+    const float inv_a2 = 1.0f / fmaf(mdir.x, mdir.x, fmaf(mdir.y, mdir.y, mdir.z * mdir.z));
+    propagate_pairs<W, EXT_W, EXT_H, false>(A, s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw,
+                                            inv_a2, gx0, gx1, gx2);
+    if (KIND == kDDF)
+        propagate_pairs<W, EXT_W, EXT_H, true>(D, s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw,
+                                               inv_a2, gx0, gx1, gx2);
+
+    // fold replicated border positions into their source pixel, then write
+    // this tile's contribution for every in-image extended position
+    float* s_dx = s_plane;
+    s_dx[tid * 3 + 0] = gx0;
+    s_dx[tid * 3 + 1] = gx1;
+    s_dx[tid * 3 + 2] = gx2;
+    __syncthreads();
+    const int gy = ty0 - H + ey, gxp = tx0 - H + ex;
+    if (gy < 0 || gy >= M || gxp < 0 || gxp >= N) return;
+    int eylo = ey, eyhi = ey, exlo = ex, exhi = ex;
+    if (gy == 0) eylo = 0;                        // rows above the image clamp to row 0
+    if (gy == M - 1) eyhi = EXT_H - 1;            // rows below clamp to row M - 1
+    if (gxp == 0) exlo = 0;
+    if (gxp == N - 1) exhi = EXT_W - 1;
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+    for (int yy = eylo; yy <= eyhi; ++yy) {
+        const int gyy = min(max(ty0 - H + yy, 0), M - 1);
+        if (gyy != gy) continue;
+        for (int xx = exlo; xx <= exhi; ++xx) {
+            const int gxx = min(max(tx0 - H + xx, 0), N - 1);
+            if (gxx != gxp) continue;
+            const float* v = s_dx + (yy * EXT_W + xx) * 3;
+            f0 += v[0];
+            f1 += v[1];
+            f2 += v[2];
+        }
+    }
+    const size_t tile = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float* o = prm.ws + (tile * NT + tid) * 3;
+    o[0] = f0;
+    o[1] = f1;
+    o[2] = f2;
+}
+
+// dx(q) = sum of the tile contributions at q over the tiles whose extended
+// region contains q, in increasing tile order.
+template <int W, int KIND>
+__global__ void __launch_bounds__(256) softmin_combine(SoftParams prm, int tiles_x, int tiles_y) {
+    constexpr int EXT_W = SoftTile<W, KIND>::EXT_W, EXT_H = SoftTile<W, KIND>::EXT_H;
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    constexpr int H = Gm::H, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
+    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    if (gx >= prm.N || gy >= prm.M) return;
+    const int tylo = max(0, (gy - H - TH + 1 + TH * 4) / TH - 4);
+    const int tyhi = min(tiles_y - 1, (gy + H) / TH);
+    const int txlo = max(0, (gx - H - TW + 1 + TW * 4) / TW - 4);
+    const int txhi = min(tiles_x - 1, (gx + H) / TW);
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    for (int ty = tylo; ty <= tyhi; ++ty) {
+        const int ey = gy - (ty * TH - H);
+        if (ey < 0 || ey >= EXT_H) continue;
+        for (int tx = txlo; tx <= txhi; ++tx) {
+            const int ex = gx - (tx * TW - H);
+            if (ex < 0 || ex >= EXT_W) continue;
+            const size_t tile = ((size_t)b * tiles_y + ty) * tiles_x + tx;
+            const float* v = prm.ws + (tile * NT + ey * EXT_W + ex) * 3;
+            a0 += v[0];
+            a1 += v[1];
+            a2 += v[2];
+        }
+    }
+    float* o = prm.dx + (((size_t)b * prm.M + gy) * prm.N + gx) * 3;
+    o[0] = a0;
+    o[1] = a1;
+    o[2] = a2;
+}
+
+template <int W, int KIND>
+static void soft_grid(const SoftParams& prm, int& tx, int& ty, int& nt) {
+    using Gm = FwdGeom<W, SoftTile<W, KIND>::EXT_W, SoftTile<W, KIND>::EXT_H>;
+    tx = (prm.N + Gm::TW - 1) / Gm::TW;
+    ty = (prm.M + Gm::TH - 1) / Gm::TH;
+    nt = Gm::NT;
+}
+
+template <int W, int KIND>
+static hipError_t launch_soft_t(bool bwd, const SoftParams& prm, hipStream_t s) {
+    int tx, ty, nt;
+    soft_grid<W, KIND>(prm, tx, ty, nt);
+    dim3 grid(tx, ty, prm.B);
+    if (!bwd) {
+        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>), grid, dim3(nt), 0, s, prm);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((softmin_kernel<W, KIND, true>), grid, dim3(nt), 0, s, prm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((prm.N + 63) / 64, (prm.M + 3) / 4, prm.B);
+    hipLaunchKernelGGL((softmin_combine<W, KIND>), g2, dim3(256), 0, s, prm, tx, ty);
+    return hipGetLastError();
+}
+
+size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
+    SoftParams prm{};
+    prm.B = B; prm.M = M; prm.N = N;
+    int tx, ty, nt;
+    if (window == 3) {
+        if (kind == kBVDF) soft_grid<3, kBVDF>(prm, tx, ty, nt); else soft_grid<3, kDDF>(prm, tx, ty, nt);
+    } else {
+        if (kind == kBVDF) soft_grid<5, kBVDF>(prm, tx, ty, nt); else soft_grid<5, kDDF>(prm, tx, ty, nt);
+    }
+    return (size_t)B * tx * ty * nt * 3 * sizeof(float);
+}
+
+hipError_t launch_softmin(int window, int kind, bool bwd, const SoftParams& prm, hipStream_t s) {
+    if (window == 3)
+        return kind == kBVDF ? launch_soft_t<3, kBVDF>(bwd, prm, s) : launch_soft_t<3, kDDF>(bwd, prm, s);
+    return kind == kBVDF ? launch_soft_t<5, kBVDF>(bwd, prm, s) : launch_soft_t<5, kDDF>(bwd, prm, s);
+}
+
+}  // namespace odf

@@ -49,7 +49,13 @@ def lib():
         L.odf_filter_u8.argtypes = [P, I, I, I, I, I, F, I, I, P, P, P]
         L.odf_filter_f32.argtypes = [P, I, I, I, I, I, F, I, I, P, P, P]
         L.odf_aggregates.argtypes = [P, I, I, I, I, I, I, F, I, I, P, P, P, P]
-        for name in ("odf_filter_u8", "odf_filter_f32", "odf_aggregates"):
+        L.odf_backward_hard_f32.argtypes = [P, P, I, I, I, I, P, P]
+        L.odf_softmin_fwd_f32.argtypes = [P, I, I, I, I, I, F, F, P, P]
+        L.odf_softmin_bwd_workspace.argtypes = [I, I, I, I, I]
+        L.odf_softmin_bwd_workspace.restype = ctypes.c_size_t
+        L.odf_softmin_bwd_f32.argtypes = [P, P, I, I, I, I, I, F, F, P, P, ctypes.c_size_t, P]
+        for name in ("odf_filter_u8", "odf_filter_f32", "odf_aggregates", "odf_backward_hard_f32",
+                     "odf_softmin_fwd_f32", "odf_softmin_bwd_f32"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -138,3 +144,97 @@ def aggregates(img, window=3, kind=BVDF, p=0.5, dist=EXACT, q=4):
     if squeeze:
         A, D, O = A[0], D[0], O[0]
     return A, D, O
+
+
+# ------------------------------------------------------------------ gradients
+
+def backward_hard(idx, dy, window):
+    """Gradient of the hard filter: dy routed to the selected pixels (float32)."""
+    g, squeeze = _as_batch(dy)
+    _check_tensor(g, "dy")
+    _check_tensor(idx, "idx")
+    if g.dtype != torch.float32 or idx.dtype != torch.uint8:
+        raise ValueError("dy must be float32 and idx uint8")
+    B, M, N, _ = g.shape
+    if idx.numel() != B * M * N:
+        raise ValueError("idx must have B*M*N elements")
+    dx = torch.empty_like(g)
+    _check(lib().odf_backward_hard_f32(_ptr(idx), _ptr(g), B, M, N, window, _ptr(dx),
+                                       _stream(g.device)))
+    return dx[0] if squeeze else dx
+
+
+def softmin_forward(x, window=5, kind=DDF, p=0.25, tau=0.1):
+    """Softmin relaxation y = sum_u pi_u x_u (float32, exact angle)."""
+    xb, squeeze = _as_batch(x)
+    _check_tensor(xb, "x")
+    if xb.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    B, M, N, _ = xb.shape
+    y = torch.empty_like(xb)
+    _check(lib().odf_softmin_fwd_f32(_ptr(xb), B, M, N, window, _kind(kind), float(p), float(tau),
+                                     _ptr(y), _stream(xb.device)))
+    return y[0] if squeeze else y
+
+
+def softmin_backward(x, dy, window=5, kind=DDF, p=0.25, tau=0.1, workspace=None):
+    """Gradient of sum(dy * softmin_forward(x)) with respect to x."""
+    xb, squeeze = _as_batch(x)
+    g, _ = _as_batch(dy)
+    _check_tensor(xb, "x")
+    _check_tensor(g, "dy")
+    if xb.dtype != torch.float32 or g.dtype != torch.float32 or g.shape != xb.shape:
+        raise ValueError("x and dy must be float32 of the same shape")
+    B, M, N, _ = xb.shape
+    need = lib().odf_softmin_bwd_workspace(B, M, N, window, _kind(kind))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=xb.device)
+    dx = torch.empty_like(xb)
+    _check(lib().odf_softmin_bwd_f32(_ptr(xb), _ptr(g), B, M, N, window, _kind(kind), float(p),
+                                     float(tau), _ptr(dx), _ptr(workspace), workspace.numel(),
+                                     _stream(xb.device)))
+    return dx[0] if squeeze else dx
+
+
+class HardFilter(torch.autograd.Function):
+    """y = filter(x) with the one-hot backward of the selection."""
+
+    @staticmethod
+    def forward(ctx, x, window, kind, p, dist, q):
+        out, idx = filter(x.contiguous(), window, kind, p, dist, q)
+        ctx.save_for_backward(idx)
+        ctx.window = window
+        ctx.mark_non_differentiable(idx)
+        return out, idx
+
+    @staticmethod
+    def backward(ctx, gy, gidx):
+        (idx,) = ctx.saved_tensors
+        return backward_hard(idx, gy.contiguous(), ctx.window), None, None, None, None, None
+
+
+class SoftminFilter(torch.autograd.Function):
+    """y = softmin relaxation of the filter, differentiable through A and D."""
+
+    @staticmethod
+    def forward(ctx, x, window, kind, p, tau):
+        x = x.contiguous()
+        ctx.save_for_backward(x)
+        ctx.args = (window, kind, p, tau)
+        return softmin_forward(x, window, kind, p, tau)
+
+    @staticmethod
+    def backward(ctx, gy):
+        (x,) = ctx.saved_tensors
+        window, kind, p, tau = ctx.args
+        return softmin_backward(x, gy.contiguous(), window, kind, p, tau), None, None, None, None
+
+
+def hard_filter(x, window=5, kind=DDF, p=0.25, dist=EXACT, q=4):
+    """Differentiable hard filter on float32 images: returns (y, idx)."""
+    return HardFilter.apply(x, window, _kind(kind), float(p), _dist(dist), q)
+
+
+def softmin_filter(x, window=5, kind=DDF, p=0.25, tau=0.1):
+    """Differentiable softmin relaxation on float32 images."""
+    return SoftminFilter.apply(x, window, _kind(kind), float(p), float(tau))

@@ -1,0 +1,146 @@
+"""GPU parity of the gradients (hard one-hot backward, softmin forward and
+backward) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1009_0958_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1009_0958_amd import odf  # noqa: E402
+
+DEV = "cuda:0"
+BVDF, DDF = odf.BVDF, odf.DDF
+EPS32 = 2.0 ** -24
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+# ------------------------------------------------------------------ hard backward
+
+@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("shape", [(2, 37, 45), (1, 1, 1), (1, 3, 70), (3, 64, 64)])
+def test_backward_hard_matches_oracle_bitwise(window, shape):
+    print("case: hard bwd w=%d shape=%s" % (window, shape), flush=True)
+    B, M, N = shape
+    x = synth.float_batch(B, M, N, 0.1, key=window)
+    out, idx = odf.filter(_gpu(x), window, DDF, 0.25)
+    rng = np.random.default_rng(window)
+    dy = rng.standard_normal(x.shape).astype(np.float32)
+    dx = odf.backward_hard(idx, _gpu(dy), window).cpu().numpy()
+    ref = oracle.backward_hard(idx.cpu().numpy(), dy.astype(np.float64), window)
+    # binary64 raster-order sums rounded once on both sides
+    assert np.array_equal(dx, ref.astype(np.float32))
+    assert dx.sum(dtype=np.float64) == pytest.approx(dy.sum(dtype=np.float64), rel=1e-6, abs=1e-5)
+    ones = odf.backward_hard(idx, torch.ones_like(out), window).cpu().numpy()
+    assert np.all(ones == np.rint(ones)) and ones.sum() == B * M * N * 3
+
+
+def test_hard_filter_autograd():
+    x = _gpu(synth.float_batch(2, 40, 48, 0.15, key=2)).requires_grad_(True)
+    y, idx = odf.hard_filter(x, 5, DDF, 0.25)
+    w = torch.randn_like(y)
+    (y * w).sum().backward()
+    ref = oracle.backward_hard(idx.cpu().numpy(), w.cpu().numpy().astype(np.float64), 5)
+    assert np.array_equal(x.grad.cpu().numpy(), ref.astype(np.float32))
+
+
+# ------------------------------------------------------------------ softmin
+
+def _soft_tol(x, window, kind, p, tau, scale=64.0):
+    """binary32 error budget: the objective carries a few ulp of relative error
+    and enters exp(-Omega / tau); with max Omega <= n * (pi/2 + max|x| sqrt 3),
+    weights move by ~ scale * eps * max Omega / tau relative."""
+    n = window * window
+    om_max = n * (np.pi / 2 + np.abs(x).max() * np.sqrt(3))
+    return scale * EPS32 * om_max / tau
+
+
+@pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
+                                           (5, BVDF, 0.0), (5, DDF, 0.5)])
+@pytest.mark.parametrize("tau", [0.1, 0.01])
+def test_softmin_forward_matches_oracle(window, kind, p, tau):
+    print("case: softmin fwd w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
+    x = synth.float_batch(2, 41, 67, 0.1, key=window + kind)
+    y = odf.softmin_forward(_gpu(x), window, kind, p, tau).cpu().numpy()
+    ref = oracle.softmin_fwd(x, window, kind, p, tau)
+    err = np.abs(y - ref).max()
+    tol = _soft_tol(x, window, kind, p, tau) * np.abs(x).max()
+    print("max |y - ref| = %.3e (tol %.3e)" % (err, tol))
+    assert err <= tol
+
+
+@pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
+                                           (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0)])
+@pytest.mark.parametrize("tau", [0.1, 0.01])
+def test_softmin_backward_matches_oracle(window, kind, p, tau):
+    print("case: softmin bwd w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
+    x = synth.float_batch(2, 33, 45, 0.1, key=10 + window + kind)
+    rng = np.random.default_rng(window)
+    dy = rng.standard_normal(x.shape).astype(np.float32)
+    dx = odf.softmin_backward(_gpu(x), _gpu(dy), window, kind, p, tau).cpu().numpy()
+    ref = oracle.softmin_bwd(x, dy.astype(np.float64), window, kind, p, tau)
+    err = np.abs(dx - ref).max()
+    scale = np.abs(ref).max()
+    tol = _soft_tol(x, window, kind, p, tau) * scale
+    print("max |dx - ref| = %.3e, max |ref| = %.3e (tol %.3e)" % (err, scale, tol), flush=True)
+    assert err <= tol
+    # deterministic
+    dx2 = odf.softmin_backward(_gpu(x), _gpu(dy), window, kind, p, tau).cpu().numpy()
+    assert np.array_equal(dx, dx2)
+
+
+def test_softmin_autograd_and_edge_shapes():
+    for shape in ((1, 1, 1), (1, 2, 9), (1, 17, 1), (2, 13, 70)):
+        x = synth.float_batch(*shape, 0.2, key=3)
+        xt = _gpu(x).requires_grad_(True)
+        y = odf.softmin_filter(xt, 5, DDF, 0.25, 0.1)
+        w = torch.randn_like(y)
+        (y * w).sum().backward()
+        ref = oracle.softmin_bwd(x, w.cpu().numpy().astype(np.float64), 5, DDF, 0.25, 0.1)
+        tol = _soft_tol(x, 5, DDF, 0.25, 0.1) * max(np.abs(ref).max(), 1e-6)
+        assert np.abs(xt.grad.cpu().numpy() - ref).max() <= tol, shape
+        yr = oracle.softmin_fwd(x, 5, DDF, 0.25, 0.1)
+        assert np.abs(y.detach().cpu().numpy() - yr).max() <= _soft_tol(x, 5, DDF, 0.25, 0.1)
+
+
+def test_softmin_small_tau_is_hard_selection():
+    x = synth.float_batch(1, 40, 40, 0.1, key=8)
+    y = odf.softmin_forward(_gpu(x), 3, DDF, 0.25, 1e-6).cpu().numpy()
+    out, _, _, _, O = oracle.filter(x, 3, DDF, 0.25, aggregates=True)
+    srt = np.sort(O, -1)
+    clear = (srt[..., 1] - srt[..., 0]) > 1e-3 * srt[..., 1]
+    assert np.array_equal(y[clear], out.astype(np.float32)[clear])
+
+
+def test_full_size_batch_crops():
+    """16 x 512 x 512 float32, DDF 5x5 p = 0.25: the whole batch on the GPU;
+    8 seeded 40 x 40 crops checked by the oracle on pixels at least 2h = 4 from
+    the crop edge (their gradient only depends on pixels within 2h)."""
+    x = synth.float_batch(16, 512, 512, 0.1)
+    rng = np.random.default_rng(4)
+    dy = rng.standard_normal(x.shape).astype(np.float32)
+    xg, dyg = _gpu(x), _gpu(dy)
+    for tau in (0.1, 0.01):
+        y = odf.softmin_forward(xg, 5, DDF, 0.25, tau).cpu().numpy()
+        dx = odf.softmin_backward(xg, dyg, 5, DDF, 0.25, tau).cpu().numpy()
+        for k in range(8):
+            b = int(rng.integers(0, 16))
+            r0, c0 = (int(v) for v in rng.integers(0, 512 - 40, 2))
+            crop = x[b, r0:r0 + 40, c0:c0 + 40]
+            gcrop = dy[b, r0:r0 + 40, c0:c0 + 40]
+            ry = oracle.softmin_fwd(crop, 5, DDF, 0.25, tau)
+            rdx = oracle.softmin_bwd(crop, gcrop.astype(np.float64), 5, DDF, 0.25, tau)
+            inner = (slice(4, 36), slice(4, 36))
+            tol = _soft_tol(crop, 5, DDF, 0.25, tau)
+            ey = np.abs(y[b, r0:r0 + 40, c0:c0 + 40][inner] - ry[inner]).max()
+            ed = np.abs(dx[b, r0:r0 + 40, c0:c0 + 40][inner] - rdx[inner]).max()
+            sd = np.abs(rdx[inner]).max()
+            print("tau %g crop %d: y err %.2e, dx err %.2e of %.2e (tol %.2e)"
+                  % (tau, k, ey, ed, sd, tol * sd), flush=True)
+            assert ey <= tol
+            assert ed <= tol * sd

@@ -16,7 +16,7 @@
  *     neither frees nor retains them.  Outputs must not overlap inputs.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *     on it and return without waiting; they allocate nothing except where
- *     stated (odf_batch_plan, odf_autotune).
+ *     stated (odf_batch_plan, odf_autotune, odf_tune_load).
  *   - Arguments are validated on the host before anything is launched.  A
  *     rejected call returns a negative odf_status, launches nothing and sets
  *     the message returned by odf_last_error() (per thread).
@@ -148,6 +148,66 @@ size_t odf_softmin_bwd_workspace(int B, int M, int N, int window, int kind);
 int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, int window, int kind,
                         float p, float tau, float* dx, void* workspace, size_t workspace_bytes,
                         void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many uint8 images of different sizes, windows and variants in one launch.
+ * A job is one image with its own parameters (same meaning as the arguments
+ * of odf_filter_u8; idx may be NULL).  Results are bitwise equal to those of
+ * odf_filter_u8 on each image. */
+typedef struct {
+    const uint8_t* img; /* M x N x 3 uint8 */
+    uint8_t* out;       /* M x N x 3 uint8 */
+    uint8_t* idx;       /* M x N uint8 or NULL */
+    int M, N;
+    int window, kind, dist, q;
+    float p;
+} odf_job;
+
+typedef struct odf_plan odf_plan; /* opaque, owned by the library */
+
+/* Validate the jobs, cut them into tiles and upload the work lists (one per
+ * class of window, kind and pair term, larger tiles first).  Allocates device
+ * memory and synchronises; the job buffers must stay valid while the plan is
+ * launched.  On success *plan receives a plan to pass to odf_batch_launch and
+ * finally to odf_plan_destroy.  Errors: ODF_EINVAL / ODF_EUNSUPPORTED for a bad
+ * job (nothing is allocated), ODF_ENOMEM, ODF_EHIP. */
+int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream);
+
+/* Enqueue the plan on `stream`: a counter-reset kernel, then one persistent
+ * kernel per non-empty class whose workgroups take tiles from the work list
+ * with an atomic counter.  Allocates nothing and does not synchronise, so it
+ * may be captured in a hipGraph and replayed.  Launches of one plan must not
+ * overlap in time (they share the tile counters). */
+int odf_batch_launch(const odf_plan* plan, void* stream);
+
+/* Plan summary: job count, total pixels, tiles and persistent grid per class,
+ * class = ((window == 5) * 2 + kind) * 3 + dist (arrays of 12, each nullable). */
+int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles, int* grids);
+
+/* Free a plan (after its last launch has completed). */
+int odf_plan_destroy(odf_plan* plan);
+
+/* ---------------------------------------------------------------- tuning
+ * The forward kernels run one thread per pixel of an extended tile
+ * (output tile plus halo).  Tile shapes are numbered 0..3; odf_tile_config
+ * gives the extended width and height of one.  The process-wide table picks a
+ * shape per (window, kind, dist, input type); defaults are 32 x 32 (32 x 16
+ * for 5x5 DDF). */
+int odf_tile_config(int config, int* ext_w, int* ext_h);
+int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
+int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */
+
+/* Time every valid tile shape on a seeded random M x N image (reps launches
+ * each, HIP events on `stream`), set the fastest in the table, store the
+ * per-shape milliseconds in times_ms[4] (-1 for shapes not offered; nullable)
+ * and append one JSON line to cache_path (nullable).  Allocates and frees
+ * device memory and synchronises `stream`. */
+int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
+                 const char* cache_path, float* times_ms, void* stream);
+
+/* Apply the entries of a cache written by odf_autotune whose architecture
+ * matches the current device; returns the number applied or ODF_EINVAL. */
+int odf_tune_load(const char* cache_path);
 
 #ifdef __cplusplus
 }

@@ -8,16 +8,23 @@
 #include "odf_internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
 
-int fail(int code, const char* fmt, ...) {
+namespace odf {
+int set_error(int code, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
     return code;
 }
+}  // namespace odf
+
+namespace {
+
+using odf::set_error;
+#define fail set_error
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(ODF_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -59,6 +66,19 @@ int check_common(const void* img, int B, int M, int N, int window, int kind, flo
     return ODF_OK;
 }
 
+}  // namespace
+
+odf::MinimaxCoef odf::minimax_coef(int q) {
+    MinimaxCoef c{};
+    if (q >= 2 && q <= 4) {
+        memcpy(c.asin_c, kTab1Asin[q - 2], sizeof c.asin_c);
+        memcpy(c.acos_c, kTab1Acos[q - 2], sizeof c.acos_c);
+    }
+    return c;
+}
+
+namespace {
+
 odf::FwdParams make_params(const void* img, int B, int M, int N, float p, int dist, int q) {
     odf::FwdParams prm{};
     prm.img = img;
@@ -66,10 +86,7 @@ odf::FwdParams make_params(const void* img, int B, int M, int N, float p, int di
     prm.M = M;
     prm.N = N;
     prm.p = p;
-    if (dist == ODF_MINIMAX) {
-        memcpy(prm.coef.asin_c, kTab1Asin[q - 2], sizeof prm.coef.asin_c);
-        memcpy(prm.coef.acos_c, kTab1Acos[q - 2], sizeof prm.coef.acos_c);
-    }
+    if (dist == ODF_MINIMAX) prm.coef = odf::minimax_coef(q);
     return prm;
 }
 
@@ -87,7 +104,8 @@ int filter_any(const void* img, bool u8, int B, int M, int N, int window, int ki
     odf::FwdParams prm = make_params(img, B, M, N, kind == ODF_DDF ? p : 0.0f, dist, q);
     prm.out = out;
     prm.idx = idx;
-    hipError_t e = odf::launch_forward(window, kind, dist, u8, false, prm,
+    const int cfg = odf::tuned_config(window, kind, dist, u8);
+    hipError_t e = odf::launch_forward(window, kind, dist, u8, false, cfg, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return ODF_OK;
@@ -127,7 +145,7 @@ int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, 
     prm.dbg_A = A;
     prm.dbg_D = D;
     prm.dbg_O = Omega;
-    hipError_t e = odf::launch_forward(window, kind, dist, is_u8 != 0, true, prm,
+    hipError_t e = odf::launch_forward(window, kind, dist, is_u8 != 0, true, 0, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "aggregate launch");
     return ODF_OK;

@@ -1,0 +1,121 @@
+// fwd_tile.h -- one output tile of the forward filter (BVDF / DDF), shared
+// by the per-image kernels and the persistent batch kernels.
+//
+// Per workgroup tile (aggregates.h describes a2/a3):
+//   a1  load + prepare the pixel (direction, norms / chromaticity sums) -> LDS
+//   a2  pair terms, each unordered pixel pair once, via LDS row-group planes
+//   a3  canonical-order box sums -> aggregates of every (member, window)
+//   a4  objective (BVDF: A; DDF: A^(1-p) D^p compared as (1-p) log2 A + p log2 D)
+//       and argmin by a 64-bit LDS atomicMin of (ordered objective, member
+//       index): the smallest objective wins, ties go to the lowest index,
+//       independent of the order of the atomics; then the selected member is
+//       copied to the output.
+#pragma once
+
+#include "aggregates.h"
+#include "odf_internal.h"
+
+namespace odf {
+
+// LDS of one forward tile.
+template <int W, int EXT_W, int EXT_H, bool AGG>
+struct FwdShared {
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    float4 dir[Gm::NT];
+    float4 raw[Gm::NT];
+    float plane[Gm::G * Gm::NT];
+    unsigned long long key[AGG ? 1 : Gm::TH * Gm::TW];
+};
+
+// Filter one output tile whose top-left output pixel is (ty0, tx0) of image b.
+// Every thread of the workgroup must call it (it synchronises); tid is the
+// thread's index in the workgroup.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
+__device__ __forceinline__ void fwd_tile(FwdShared<W, EXT_W, EXT_H, AGG>& sh, const FwdParams& prm,
+                                         int b, int ty0, int tx0, int tid) {
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    constexpr int H = Gm::H, NW = Gm::NW, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
+    float4* s_dir = sh.dir;
+    float4* s_raw = sh.raw;
+    float* s_plane = sh.plane;
+    unsigned long long* s_key = sh.key;
+
+    const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
+    const int M = prm.M, N = prm.N;
+
+    // a1: own extended pixel, replicated border
+    {
+        const int gy = min(max(ty0 - H + ey, 0), M - 1);
+        const int gx = min(max(tx0 - H + ex, 0), N - 1);
+        const size_t pix = ((size_t)b * M + gy) * N + gx;
+        float x0, x1, x2;
+        if (U8) {
+            const uint8_t* s = static_cast<const uint8_t*>(prm.img) + pix * 3;
+            x0 = s[0]; x1 = s[1]; x2 = s[2];
+        } else {
+            const float* s = static_cast<const float*>(prm.img) + pix * 3;
+            x0 = s[0]; x1 = s[1]; x2 = s[2];
+        }
+        float4 d, r;
+        prepare_pixel<DIST, U8>(x0, x1, x2, d, r);
+        s_dir[tid] = d;
+        s_raw[tid] = r;
+    }
+    if (!AGG)
+        for (int i = tid; i < TH * TW; i += NT) s_key[i] = ~0ull;
+    __syncthreads();
+    const float4 mdir = s_dir[tid];
+    const float4 mraw = s_raw[tid];
+
+    // a2 + a3
+    float A[NW], D[NW];
+    member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex, tid,
+                                                             mdir, mraw, prm.coef, A);
+    if (KIND == kDDF)
+        member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey, ex,
+                                                                tid, mdir, mraw, prm.coef, D);
+    else
+#pragma unroll
+        for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+
+    // a4: objective of this member in every window of the tile containing it
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        const int cy = ey - u / W;  // window centre, tile-local
+        const int cx = ex - u % W;
+        if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+        if (ty0 + cy >= M || tx0 + cx >= N) continue;
+        if (AGG) {
+            const size_t o = (((size_t)b * M + ty0 + cy) * N + tx0 + cx) * NW + u;
+            prm.dbg_A[o] = A[u];
+            if (prm.dbg_D) prm.dbg_D[o] = D[u];
+            if (prm.dbg_O) prm.dbg_O[o] = objective_value<KIND>(A[u], D[u], prm.p);
+        } else {
+            const float om = objective_log<KIND>(A[u], D[u], prm.p);
+            const unsigned long long key = ((unsigned long long)order_key(om) << 32) | (unsigned)u;
+            atomicMin(&s_key[cy * TW + cx], key);
+        }
+    }
+    if (AGG) return;
+    __syncthreads();
+
+    // write the selected member of every window of the tile
+    for (int i = tid; i < TH * TW; i += NT) {
+        const int cy = i / TW, cx = i - (i / TW) * TW;
+        const int gy = ty0 + cy, gx = tx0 + cx;
+        if (gy >= M || gx >= N) continue;
+        const int u = min((int)(s_key[i] & 0xffu), NW - 1);
+        const float4 r = s_raw[(cy + u / W) * EXT_W + cx + u % W];
+        const size_t pix = ((size_t)b * M + gy) * N + gx;
+        if (U8) {
+            uint8_t* o = static_cast<uint8_t*>(prm.out) + pix * 3;
+            o[0] = (uint8_t)r.x; o[1] = (uint8_t)r.y; o[2] = (uint8_t)r.z;
+        } else {
+            float* o = static_cast<float*>(prm.out) + pix * 3;
+            o[0] = r.x; o[1] = r.y; o[2] = r.z;
+        }
+        if (prm.idx) prm.idx[pix] = (uint8_t)u;
+    }
+}
+
+}  // namespace odf

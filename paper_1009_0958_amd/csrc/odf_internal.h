@@ -20,9 +20,22 @@ struct FwdParams {
     MinimaxCoef coef;     // Table 1 row for the chosen q
 };
 
-// Launch the forward filter on `stream`.  Returns hipSuccess or the launch error.
-hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates,
+// Launch the forward filter on `stream` with extended-tile shape `cfg`.
+// Returns hipSuccess or the launch error.
+hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates, int cfg,
                           const FwdParams& prm, hipStream_t stream);
+bool tile_config_valid(int window, int kind, int cfg);
+int tile_config_default(int window, int kind);
+void tile_config_shape(int cfg, int* ext_w, int* ext_h);
+constexpr int kNumTileShapes = 4;
+int tuned_config(int window, int kind, int dist, bool u8);
+void set_tuned_config(int window, int kind, int dist, bool u8, int cfg);
+
+// Table 1 coefficients for degree q (zeros outside 2..4).
+MinimaxCoef minimax_coef(int q);
+
+// Record the message returned by odf_last_error() on this thread; returns code.
+int set_error(int code, const char* fmt, ...);
 
 struct SoftParams {
     const float* x;   // B x M x N x 3

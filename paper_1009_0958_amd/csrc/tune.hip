@@ -1,0 +1,202 @@
+// tune.hip -- tile-shape table of the forward filter and its autotuner.
+//
+// The table maps (window, kind, dist, input type) to one of the extended-tile
+// shapes of fwd.hip.  odf_autotune times every valid shape on a seeded
+// random image with HIP events, keeps the fastest and records the timings in
+// a small JSON cache keyed by the GPU architecture; odf_tune_load reads such a
+// cache back.  The table is process-wide; updates are atomic per entry.
+#include <atomic>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "odf.h"
+#include "odf_internal.h"
+
+namespace odf {
+
+namespace {
+
+// [window 3/5][kind][dist][u8]
+std::atomic<int> g_table[2][2][3][2];
+std::atomic<bool> g_table_init{false};
+
+void ensure_init() {
+    bool expect = false;
+    if (!g_table_init.load()) {
+        for (int w = 0; w < 2; ++w)
+            for (int k = 0; k < 2; ++k)
+                for (int d = 0; d < 3; ++d)
+                    for (int u = 0; u < 2; ++u)
+                        g_table[w][k][d][u].store(tile_config_default(w ? 5 : 3, k));
+        g_table_init.compare_exchange_strong(expect, true);
+    }
+}
+
+}  // namespace
+
+int tuned_config(int window, int kind, int dist, bool u8) {
+    ensure_init();
+    return g_table[window == 5][kind][dist][u8 ? 1 : 0].load();
+}
+
+void set_tuned_config(int window, int kind, int dist, bool u8, int cfg) {
+    ensure_init();
+    g_table[window == 5][kind][dist][u8 ? 1 : 0].store(cfg);
+}
+
+}  // namespace odf
+
+namespace {
+
+// splitmix64: seeded bytes for the tuning image
+uint64_t splitmix(uint64_t& s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+int odf_tile_config(int config, int* ext_w, int* ext_h) {
+    if (config < 0 || config >= odf::kNumTileShapes || !ext_w || !ext_h) return ODF_EINVAL;
+    odf::tile_config_shape(config, ext_w, ext_h);
+    return ODF_OK;
+}
+
+int odf_tune_get(int window, int kind, int dist, int is_u8) {
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || dist < 0 ||
+        dist > 2)
+        return ODF_EINVAL;
+    return odf::tuned_config(window, kind, dist, is_u8 != 0);
+}
+
+int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || dist < 0 ||
+        dist > 2 || !odf::tile_config_valid(window, kind, config))
+        return ODF_EINVAL;
+    odf::set_tuned_config(window, kind, dist, is_u8 != 0, config);
+    return ODF_OK;
+}
+
+int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
+                 const char* cache_path, float* times_ms, void* stream) {
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || dist < 0 ||
+        dist > 2 || M < 1 || N < 1 || reps < 1 || (long long)M * N >= (1ll << 28))
+        return odf::set_error(ODF_EINVAL, "autotune: arguments out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t npix = (size_t)M * N;
+    const size_t esz = is_u8 ? 1 : 4;
+    std::vector<uint8_t> h8(npix * 3);
+    std::vector<float> hf(is_u8 ? 0 : npix * 3);
+    uint64_t seed = 1009;
+    for (size_t i = 0; i < npix * 3; ++i) {
+        h8[i] = (uint8_t)(splitmix(seed) >> 56);
+        if (!is_u8) hf[i] = h8[i] / 255.0f;
+    }
+    void *img = nullptr, *out = nullptr;
+    uint8_t* idx = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = ODF_OK;
+    int best = -1;
+    float best_ms = 0.0f;
+    float ms_all[odf::kNumTileShapes];
+    if (hipMalloc(&img, npix * 3 * esz) != hipSuccess || hipMalloc(&out, npix * 3 * esz) != hipSuccess ||
+        hipMalloc(&idx, npix) != hipSuccess) {
+        rc = ODF_ENOMEM;
+        goto done;
+    }
+    if (hipMemcpy(img, is_u8 ? (const void*)h8.data() : (const void*)hf.data(), npix * 3 * esz,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = ODF_EHIP;
+        goto done;
+    }
+    for (int cfg = 0; cfg < odf::kNumTileShapes; ++cfg) {
+        ms_all[cfg] = -1.0f;
+        if (!odf::tile_config_valid(window, kind, cfg)) continue;
+        odf::FwdParams prm{};
+        prm.img = img; prm.out = out; prm.idx = idx;
+        prm.B = 1; prm.M = M; prm.N = N;
+        prm.p = kind == ODF_DDF ? 0.25f : 0.0f;
+        if (dist == ODF_MINIMAX) prm.coef = odf::minimax_coef(4);  // timing does not depend on q
+        for (int w = 0; w < 2; ++w)
+            if (odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s) != hipSuccess) {
+                rc = ODF_EHIP;
+                goto done;
+            }
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s);
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = ODF_EHIP;
+            goto done;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        ms_all[cfg] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = cfg;
+            best_ms = ms;
+        }
+    }
+    if (best >= 0) odf::set_tuned_config(window, kind, dist, is_u8 != 0, best);
+    if (times_ms)
+        for (int c = 0; c < odf::kNumTileShapes; ++c) times_ms[c] = ms_all[c];
+    if (cache_path && best >= 0) {
+        hipDeviceProp_t prop;
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipGetDeviceProperties(&prop, dev);
+        FILE* f = fopen(cache_path, "a");
+        if (!f) {
+            rc = odf::set_error(ODF_EINVAL, "cannot open %s", cache_path);
+            goto done;
+        }
+        fprintf(f,
+                "{\"arch\": \"%s\", \"window\": %d, \"kind\": %d, \"dist\": %d, \"u8\": %d, "
+                "\"config\": %d, \"M\": %d, \"N\": %d, \"ms\": [%.5f, %.5f, %.5f, %.5f]}\n",
+                prop.gcnArchName, window, kind, dist, is_u8 != 0, best, M, N, ms_all[0],
+                ms_all[1], ms_all[2], ms_all[3]);
+        fclose(f);
+    }
+done:
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(img);
+    hipFree(out);
+    hipFree(idx);
+    return best >= 0 || rc != ODF_OK ? rc : ODF_EHIP;
+}
+
+int odf_tune_load(const char* cache_path) {
+    if (!cache_path) return ODF_EINVAL;
+    FILE* f = fopen(cache_path, "r");
+    if (!f) return ODF_EINVAL;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    hipGetDevice(&dev);
+    const bool have_dev = hipGetDeviceProperties(&prop, dev) == hipSuccess;
+    char line[512];
+    int applied = 0;
+    while (fgets(line, sizeof line, f)) {
+        char arch[128] = "";
+        int w, k, d, u, c;
+        if (sscanf(line,
+                   "{\"arch\": \"%127[^\"]\", \"window\": %d, \"kind\": %d, \"dist\": %d, "
+                   "\"u8\": %d, \"config\": %d",
+                   arch, &w, &k, &d, &u, &c) != 6)
+            continue;  // malformed lines are ignored
+        if (have_dev && strcmp(arch, prop.gcnArchName) != 0) continue;
+        if (odf_tune_set(w, k, d, u, c) == ODF_OK) ++applied;
+    }
+    fclose(f);
+    return applied;
+}
+
+}  // extern "C"

@@ -82,6 +82,8 @@ def _ptr(t):
 
 
 def _stream(device):
+    if not torch.cuda.is_available():
+        return None
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
@@ -238,3 +240,136 @@ def hard_filter(x, window=5, kind=DDF, p=0.25, dist=EXACT, q=4):
 def softmin_filter(x, window=5, kind=DDF, p=0.25, tau=0.1):
     """Differentiable softmin relaxation on float32 images."""
     return SoftminFilter.apply(x, window, _kind(kind), float(p), float(tau))
+
+
+# ------------------------------------------------------------------ batches
+
+class _Job(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("idx", ctypes.c_void_p),
+                ("M", ctypes.c_int), ("N", ctypes.c_int), ("window", ctypes.c_int),
+                ("kind", ctypes.c_int), ("dist", ctypes.c_int), ("q", ctypes.c_int),
+                ("p", ctypes.c_float)]
+
+
+def _batch_lib():
+    L = lib()
+    if not hasattr(L, "_batch_ready"):
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.odf_batch_plan.argtypes = [P, I, ctypes.POINTER(ctypes.c_void_p), P]
+        L.odf_batch_launch.argtypes = [P, P]
+        L.odf_plan_info.argtypes = [P, P, P, P, P]
+        L.odf_plan_destroy.argtypes = [P]
+        L.odf_tile_config.argtypes = [I, P, P]
+        L.odf_tune_get.argtypes = [I, I, I, I]
+        L.odf_tune_set.argtypes = [I, I, I, I, I]
+        L.odf_autotune.argtypes = [I, I, I, I, I, I, I, ctypes.c_char_p, P, P]
+        L.odf_tune_load.argtypes = [ctypes.c_char_p]
+        for name in ("odf_batch_plan", "odf_batch_launch", "odf_plan_info", "odf_plan_destroy",
+                     "odf_tile_config", "odf_tune_get", "odf_tune_set", "odf_autotune",
+                     "odf_tune_load"):
+            getattr(L, name).restype = I
+        L._batch_ready = True
+    return L
+
+
+NUM_CLASSES = 12  # ((window == 5) * 2 + kind) * 3 + dist
+
+
+class BatchPlan:
+    """A planned batch of uint8 jobs; ``launch()`` enqueues it on the current
+    stream (graph-capturable), ``capture()`` records it in a CUDA/HIP graph.
+
+    jobs: iterable of dicts with keys img, out, idx (tensors; idx may be None),
+    window, kind, p, dist, q.
+    """
+
+    def __init__(self, jobs):
+        self._keep = []
+        arr = (_Job * len(jobs))()
+        for i, j in enumerate(jobs):
+            img, out, idx = j["img"], j["out"], j.get("idx")
+            for t, name in ((img, "img"), (out, "out")):
+                _check_tensor(t, name)
+                if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[-1] != 3:
+                    raise ValueError("batch %s must be an (M, N, 3) uint8 tensor" % name)
+            if out.shape != img.shape:
+                raise ValueError("out must have the shape of img")
+            if idx is not None:
+                _check_tensor(idx, "idx")
+                if idx.dtype != torch.uint8 or idx.numel() != img.shape[0] * img.shape[1]:
+                    raise ValueError("idx must be uint8 with M*N elements")
+            self._keep.extend([img, out, idx])
+            M, N, _ = img.shape
+            arr[i] = _Job(img.data_ptr(), out.data_ptr(), 0 if idx is None else idx.data_ptr(),
+                          M, N, int(j.get("window", 3)), _kind(j.get("kind", BVDF)),
+                          _dist(j.get("dist", EXACT)), int(j.get("q", 4)), float(j.get("p", 0.5)))
+        self._jobs = arr
+        self._plan = ctypes.c_void_p()
+        L = _batch_lib()
+        _check(L.odf_batch_plan(ctypes.cast(arr, ctypes.c_void_p), len(jobs),
+                                ctypes.byref(self._plan), _stream(torch.cuda.current_device())))
+
+    def launch(self):
+        _check(_batch_lib().odf_batch_launch(self._plan, _stream(torch.cuda.current_device())))
+
+    def capture(self):
+        """Record one launch in a graph (replay with ``graph.replay()``)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.launch()
+        return g
+
+    def info(self):
+        nj = ctypes.c_int()
+        npix = ctypes.c_longlong()
+        tiles = (ctypes.c_int * NUM_CLASSES)()
+        grids = (ctypes.c_int * NUM_CLASSES)()
+        _check(_batch_lib().odf_plan_info(self._plan, ctypes.byref(nj), ctypes.byref(npix),
+                                          ctypes.cast(tiles, ctypes.c_void_p),
+                                          ctypes.cast(grids, ctypes.c_void_p)))
+        return {"jobs": nj.value, "pixels": npix.value, "tiles": list(tiles), "grids": list(grids)}
+
+    def close(self):
+        if self._plan:
+            _batch_lib().odf_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ tuning
+
+def tile_config(config):
+    w, h = ctypes.c_int(), ctypes.c_int()
+    _check(_batch_lib().odf_tile_config(config, ctypes.byref(w), ctypes.byref(h)))
+    return w.value, h.value
+
+
+def tune_get(window, kind, dist, is_u8=True):
+    return _batch_lib().odf_tune_get(window, _kind(kind), _dist(dist), int(is_u8))
+
+
+def tune_set(window, kind, dist, is_u8, config):
+    _check(_batch_lib().odf_tune_set(window, _kind(kind), _dist(dist), int(is_u8), config))
+
+
+def autotune(window, kind, dist, is_u8=True, M=1024, N=1024, reps=10, cache_path=None):
+    """Time every tile shape, keep the fastest; returns (best, [ms per shape])."""
+    times = (ctypes.c_float * 4)()
+    path = None if cache_path is None else cache_path.encode()
+    _check(_batch_lib().odf_autotune(window, _kind(kind), _dist(dist), int(is_u8), M, N, reps,
+                                     path, ctypes.cast(times, ctypes.c_void_p),
+                                     _stream(torch.cuda.current_device())))
+    return tune_get(window, kind, dist, is_u8), list(times)
+
+
+def tune_load(cache_path):
+    """Apply a tuning cache; returns the number of entries applied."""
+    rc = _batch_lib().odf_tune_load(cache_path.encode())
+    if rc < 0:
+        raise ODFError(rc, "cannot read tuning cache %s" % cache_path)
+    return rc

@@ -75,15 +75,18 @@ def smooth_image(M: int, N: int, rng: np.random.Generator) -> np.ndarray:
     hi = field.reshape(-1, 3).max(axis=0)
     scale = (255.0 / np.maximum(hi - lo, 1e-6)).astype(np.float32)
     out = np.empty((M, N, 3), np.uint8)
-    for r0 in range(0, M, _CHUNK_ROWS):
-        r1 = min(M, r0 + _CHUNK_ROWS)
+    ec0 = np.array([e[0] for e in edges], np.float32)
+    er0 = np.array([e[1] for e in edges], np.float32)
+    esin = np.array([np.sin(e[2]) for e in edges], np.float32)
+    ecos = np.array([np.cos(e[2]) for e in edges], np.float32)
+    eoff = np.array([e[3] for e in edges], np.float32)  # (20, 3)
+    colterm = (cols.astype(np.float32)[:, None] - ec0[None, :]) * esin[None, :]  # (N, 20)
+    for r0 in range(0, M, _CHUNK_ROWS // 4):
+        r1 = min(M, r0 + _CHUNK_ROWS // 4)
         blk = (field[r0:r1] - lo) * scale
-        rr = np.arange(r0, r1, dtype=np.float32)[:, None]
-        cc = cols.astype(np.float32)[None, :]
-        for c0, e_r0, ang, off in edges:
-            side = (cc - np.float32(c0)) * np.float32(np.sin(ang)) - \
-                   (rr - np.float32(e_r0)) * np.float32(np.cos(ang)) > 0
-            blk += side[..., None] * off.astype(np.float32)
+        rowterm = (np.arange(r0, r1, dtype=np.float32)[:, None] - er0[None, :]) * ecos[None, :]
+        side = (colterm[None, :, :] - rowterm[:, None, :] > 0).astype(np.float32)  # (R, N, 20)
+        blk += side @ eoff
         np.clip(blk, 0, 255, out=blk)
         out[r0:r1] = np.rint(blk).astype(np.uint8)
     return out
@@ -107,9 +110,8 @@ def noise_eq8(x: np.ndarray, phi: float, rng: np.random.Generator,
               channel_probs=(0.25, 0.25, 0.25)) -> np.ndarray:
     """Impulsive noise of eq. (8): R, G, B alone or all three, after a per-pixel draw."""
     hit = rng.random(x.shape[:-1]) < phi
-    which = rng.choice(4, size=x.shape[:-1],
-                       p=[channel_probs[0], channel_probs[1], channel_probs[2],
-                          1.0 - sum(channel_probs)])
+    cum = np.cumsum([channel_probs[0], channel_probs[1], channel_probs[2]])
+    which = np.searchsorted(cum, rng.random(x.shape[:-1]), side="right")  # 0, 1, 2 or 3 (all)
     vals = rng.integers(0, 256, x.shape, dtype=np.uint8)
     chan = np.arange(3)
     replace = hit[..., None] & ((which[..., None] == chan) | (which[..., None] == 3))
@@ -160,10 +162,15 @@ def mixed_batch_specs(count: int = 256, key: int = 0, max_M: int = 1536, max_N: 
     return specs
 
 
-def mixed_batch_images(specs, key: int = 0):
-    """The uint8 images of ``mixed_batch_specs``."""
-    imgs = []
-    for s in specs:
+def mixed_batch_images(specs, key: int = 0, workers: int = 8):
+    """The uint8 images of ``mixed_batch_specs`` (generated in a thread pool;
+    each image has its own seeded generator, so the result does not depend on
+    the number of workers)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(s):
         rng = rng_for(3, key, 1000 + s["index"])
-        imgs.append(noise_eq8(smooth_image(s["M"], s["N"], rng), s["phi"], rng))
-    return imgs
+        return noise_eq8(smooth_image(s["M"], s["N"], rng), s["phi"], rng)
+
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(one, specs))

@@ -68,3 +68,45 @@ def test_declared_names_match_binding():
     # every declared function has a binding attribute configured or a plain C symbol
     for name in odf.declared_functions():
         assert callable(getattr(odf.lib(), name))
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("idx", ctypes.c_void_p),
+                ("M", ctypes.c_int), ("N", ctypes.c_int), ("window", ctypes.c_int),
+                ("kind", ctypes.c_int), ("dist", ctypes.c_int), ("q", ctypes.c_int),
+                ("p", ctypes.c_float)]
+
+
+@pytest.mark.parametrize("fields,code,text", [
+    (dict(img=None), odf.EINVAL, "img"),
+    (dict(M=0), odf.EINVAL, "size"),
+    (dict(window=7), odf.EUNSUPPORTED, "window"),
+    (dict(kind=3), odf.EINVAL, "kind"),
+    (dict(dist=5), odf.EINVAL, "dist"),
+    (dict(dist=1, q=9), odf.EINVAL, "q"),
+    (dict(kind=1, p=2.0), odf.EINVAL, "p"),
+    (dict(out=0x7F0000000000 + 10), odf.EINVAL, "overlap"),
+])
+def test_batch_plan_rejects(fields, code, text):
+    L = odf._batch_lib()
+    base = dict(img=0x7F0000000000, out=0x7F0000100000, idx=None, M=8, N=8, window=3, kind=0,
+                dist=0, q=4, p=0.5)
+    base.update(fields)
+    jobs = (_Job * 2)(_Job(**dict(base, img=0x7F0000200000, out=0x7F0000300000)), _Job(**base))
+    plan = ctypes.c_void_p()
+    rc = L.odf_batch_plan(ctypes.cast(jobs, ctypes.c_void_p), 2, ctypes.byref(plan), None)
+    assert rc == code and not plan.value
+    assert text in odf.last_error()
+
+
+def test_batch_and_tune_argument_errors():
+    L = odf._batch_lib()
+    plan = ctypes.c_void_p()
+    assert L.odf_batch_plan(None, 1, ctypes.byref(plan), None) == odf.EINVAL
+    assert L.odf_batch_launch(None, None) == odf.EINVAL
+    assert L.odf_plan_destroy(None) == odf.EINVAL
+    assert L.odf_tune_set(3, 0, 0, 1, 9) == odf.EINVAL
+    assert L.odf_tune_set(5, 1, 0, 1, 0) == odf.EINVAL  # 1024-thread shape not offered for 5x5 DDF
+    assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
+    assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
+    assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL

@@ -1,0 +1,113 @@
+"""GPU tests of the batched persistent launch, its graph capture and the
+tile-shape autotuner: results must be bitwise those of the per-image filter
+(and so of the oracle up to near-ties), whatever the tile shape or schedule."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1009_0958_amd import synth
+from parity import check_selection
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1009_0958_amd import odf  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _mixed_jobs(count, seed, max_side=160):
+    rng = np.random.default_rng(seed)
+    jobs, refs = [], []
+    for i in range(count):
+        M = int(rng.integers(1, max_side))
+        N = int(rng.integers(1, max_side))
+        img = synth.noise_eq8(synth.smooth_image(M, N, synth.rng_for(9, seed, i)),
+                              float(rng.uniform(0.05, 0.3)), rng)
+        job = dict(img=torch.from_numpy(img).to(DEV),
+                   out=torch.empty((M, N, 3), dtype=torch.uint8, device=DEV),
+                   idx=torch.empty((M, N), dtype=torch.uint8, device=DEV),
+                   window=int(rng.choice([3, 5])), kind=int(rng.integers(0, 2)),
+                   dist=int(rng.integers(0, 3)), q=int(rng.integers(2, 5)),
+                   p=float(rng.choice([0.0, 0.25, 0.5, 1.0])))
+        jobs.append(job)
+        refs.append(img)
+    return jobs, refs
+
+
+def _per_image(job):
+    return odf.filter(job["img"], job["window"], job["kind"], job["p"], job["dist"], job["q"])
+
+
+def test_batch_equals_per_image_and_oracle():
+    jobs, imgs = _mixed_jobs(40, 1)
+    plan = odf.BatchPlan(jobs)
+    info = plan.info()
+    print("plan:", info, flush=True)
+    assert info["jobs"] == 40 and sum(info["tiles"]) > 0
+    plan.launch()
+    torch.cuda.synchronize()
+    for j, img in zip(jobs, imgs):
+        out, idx = _per_image(j)
+        assert torch.equal(j["out"], out) and torch.equal(j["idx"], idx)
+        _, _, _, _, O = oracle.filter(img, j["window"], j["kind"], j["p"], j["dist"], j["q"],
+                                      aggregates=True)
+        check_selection(j["idx"].cpu().numpy(), O)
+    plan.close()
+
+
+def test_batch_graph_replays():
+    jobs, _ = _mixed_jobs(24, 2)
+    refs = [_per_image(j) for j in jobs]
+    plan = odf.BatchPlan(jobs)
+    g = plan.capture()
+    for rep in range(4):
+        for j in jobs:  # eager work between replays: clear the outputs
+            j["out"].zero_()
+            j["idx"].fill_(255)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for j, (o, i) in zip(jobs, refs):
+            assert torch.equal(j["out"], o) and torch.equal(j["idx"], i), rep
+    plan.close()
+
+
+def test_batch_without_idx_and_single_job():
+    img = torch.from_numpy(synth.image_corr(77, 91, 0.2, key=4)).to(DEV)
+    out = torch.empty_like(img)
+    plan = odf.BatchPlan([dict(img=img, out=out, idx=None, window=5, kind=odf.DDF, p=0.25,
+                               dist=odf.EXACT)])
+    plan.launch()
+    ref, _ = odf.filter(img, 5, odf.DDF, 0.25, odf.EXACT)
+    assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("window,kind", [(3, 0), (3, 1), (5, 0), (5, 1)])
+def test_tile_shapes_give_identical_results(window, kind):
+    img = torch.from_numpy(synth.image_corr(150, 170, 0.2, key=window + kind)).to(DEV)
+    default = odf.tune_get(window, kind, odf.EXACT, True)
+    ref = odf.filter(img, window, kind, 0.25, odf.EXACT)
+    tried = 0
+    for cfg in range(4):
+        try:
+            odf.tune_set(window, kind, odf.EXACT, True, cfg)
+        except odf.ODFError:
+            continue  # shape not offered for this class
+        tried += 1
+        o, i = odf.filter(img, window, kind, 0.25, odf.EXACT)
+        assert torch.equal(o, ref[0]) and torch.equal(i, ref[1]), cfg
+    odf.tune_set(window, kind, odf.EXACT, True, default)
+    assert tried >= 2
+
+
+def test_autotune_picks_a_valid_shape(tmp_path):
+    cache = str(tmp_path / "tune.jsonl")
+    best, times = odf.autotune(3, odf.DDF, odf.EXACT, True, 512, 512, 3, cache)
+    print("autotune 3x3 DDF:", best, times)
+    assert 0 <= best < 4 and times[best] > 0 and times[best] == min(t for t in times if t > 0)
+    best5, times5 = odf.autotune(5, odf.DDF, odf.EXACT, True, 256, 256, 2, cache)
+    assert times5[0] < 0 and times5[1] < 0  # 1024-thread shapes are not offered for 5x5 DDF
+    odf.tune_set(3, odf.DDF, odf.EXACT, True, 0)
+    assert odf.tune_load(cache) == 2
+    assert odf.tune_get(3, odf.DDF, odf.EXACT, True) == best

@@ -105,6 +105,12 @@ def main():
     x = torch.from_numpy(img_np).to(dev)
     variants = [(p, d) for p in (0.25, 0.5) for d in ("exact", "minimax", "rgb")]
     DIST = {"exact": odf.EXACT, "minimax": odf.MINIMAX, "rgb": odf.RGB}
+    # tile shapes for this image size, chosen by the library's autotuner (untimed)
+    tuned = {}
+    for d in ("exact", "minimax", "rgb"):
+        best, times = odf.autotune(3, odf.DDF, DIST[d], True, M, N, 10)
+        tuned["ddf3_%s" % d] = {"config": best, "ext_tile": odf.tile_config(best),
+                                "ms_per_shape": [round(t, 5) for t in times]}
     outs = {v: (torch.empty_like(x), torch.empty((M, N), dtype=torch.uint8, device=dev))
             for v in variants}
 
@@ -153,20 +159,14 @@ def main():
 
     forms = {}
     if not args.no_forms:
-        big = torch.from_numpy(synth.image_corr(4320, 7680, 0.15, key=5)).to(dev)
-        bo = torch.empty_like(big)
-        bi = torch.empty((4320, 7680), dtype=torch.uint8, device=dev)
-        npx = 4320 * 7680
-        for w, kind, p in ((3, "bvdf", 0.0), (5, "bvdf", 0.0), (5, "ddf", 0.25)):
-            for d in ("exact", "minimax", "rgb"):
-                kk = odf.BVDF if kind == "bvdf" else odf.DDF
-                ms = time_launches(torch, lambda: odf.filter(big, w, kk, p, DIST[d], 4, out=bo,
-                                                             idx=bi), 5, warm=1)
-                forms["%s%d_%s_7680x4320" % (kind, w, d)] = {
-                    "mpix_s": round(npx / (ms * 1e3), 1), "ms": round(ms, 3),
-                    "valu_frac": round(slots_per_pixel(w, kind, p, d) * npx / (ms * 1e-3)
-                                       / PEAK_SLOTS, 4)}
-        del big, bo, bi
+        for name, fn in (("large_frames", lambda: large_frame_forms(torch, odf, synth, dev, DIST)),
+                         ("batched", lambda: batched_form(torch, odf, synth, dev)),
+                         ("differentiable", lambda: differentiable_forms(torch, odf, synth, dev))):
+            try:
+                forms.update(fn())
+            except Exception as exc:  # keep the main line; report the failure
+                forms[name + "_error"] = repr(exc)[:300]
+            torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
@@ -181,11 +181,149 @@ def main():
                                "noise 0.20, p in {0.25, 0.5} x {exact, minimax q=4, rgb}",
                    "image": [M, N], "launches_per_step": len(variants), "parallelism": "none"},
         "wall_s": round(wall, 3),
-        "variants": per_variant, "roofline": roofline, "forms": forms, "cpu_baseline": cpu,
+        "tuned": tuned, "variants": per_variant, "roofline": roofline, "forms": forms,
+        "cpu_baseline": cpu,
         "paper_context": {"ddf3_exact_1024x1024_mpix_s": 0.0368,
                           "hardware": "Pentium D 2.66 GHz, C, gcc 3.4.4 (paper, Section II)"},
     }
     print(json.dumps(line), flush=True)
+
+
+def large_frame_forms(torch, odf, synth, dev, DIST):
+    """7680 x 4320 frame and 64 x 1920 x 1080 frames, correlated noise 0.15."""
+    forms = {}
+    for tag, shape, key in (("7680x4320", (1, 4320, 7680), 5), ("64x1920x1080", (64, 1080, 1920), 6)):
+        B, M, N = shape
+        imgs = np.stack([synth.image_corr(M, N, 0.15, key=key * 100 + b) for b in range(B)])
+        big = torch.from_numpy(imgs).to(dev)
+        del imgs
+        bo = torch.empty_like(big)
+        bi = torch.empty((B, M, N), dtype=torch.uint8, device=dev)
+        npx = B * M * N
+        for w, kind, p in ((3, "bvdf", 0.0), (5, "bvdf", 0.0), (5, "ddf", 0.25)):
+            if tag != "7680x4320" and w == 3:
+                continue
+            for d in ("exact", "minimax", "rgb"):
+                kk = odf.BVDF if kind == "bvdf" else odf.DDF
+                ms = time_launches(torch, lambda: odf.filter(big, w, kk, p, DIST[d], 4, out=bo,
+                                                             idx=bi), 5, warm=1)
+                forms["%s%d_%s_%s" % (kind, w, d, tag)] = {
+                    "mpix_s": round(npx / (ms * 1e3), 1), "ms": round(ms, 3),
+                    "valu_frac": round(slots_per_pixel(w, kind, p, d) * npx / (ms * 1e-3)
+                                       / PEAK_SLOTS, 4)}
+        del big, bo, bi
+    return forms
+
+
+def batched_form(torch, odf, synth, dev):
+    """256 uint8 images of mixed size (64..2048 x 64..1536), window, kind and
+    noise: one planned persistent launch captured in a graph, against a loop
+    of per-image launches of the same jobs."""
+    specs = synth.mixed_batch_specs(256)
+    imgs = synth.mixed_batch_images(specs, workers=16)
+    jobs = []
+    for s_, im in zip(specs, imgs):
+        t = torch.from_numpy(im).to(dev)
+        jobs.append(dict(img=t, out=torch.empty_like(t),
+                         idx=torch.empty(t.shape[:2], dtype=torch.uint8, device=dev),
+                         window=s_["window"], kind=s_["kind"], p=s_["p"], dist=odf.EXACT, q=4))
+    del imgs
+    npx = sum(int(j["img"].shape[0] * j["img"].shape[1]) for j in jobs)
+    plan = odf.BatchPlan(jobs)
+    graph = plan.capture()
+    ms_graph = time_launches(torch, graph.replay, 5, warm=2)
+    dplan = odf.BatchPlan(jobs, direct=True)
+    dgraph = dplan.capture()
+    ms_direct = time_launches(torch, dgraph.replay, 5, warm=2)
+    dplan.close()
+    loop_out = [(torch.empty_like(j["out"]), torch.empty_like(j["idx"])) for j in jobs]
+
+    def loop():
+        for j, (o, i) in zip(jobs, loop_out):
+            odf.filter(j["img"], j["window"], j["kind"], j["p"], odf.EXACT, 4, out=o, idx=i)
+
+    ms_loop = time_launches(torch, loop, 3, warm=1)
+    same = all(torch.equal(j["out"], o) and torch.equal(j["idx"], i)
+               for j, (o, i) in zip(jobs, loop_out))
+    info = plan.info()
+    plan.close()
+    return {"batched_256_mixed": {
+        "mpix": round(npx / 1e6, 2), "graph_ms": round(ms_graph, 3),
+        "graph_mpix_s": round(npx / (ms_graph * 1e3), 1),
+        "direct_graph_ms": round(ms_direct, 3), "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
+        "loop_ms": round(ms_loop, 3),
+        "loop_mpix_s": round(npx / (ms_loop * 1e3), 1),
+        "speedup_vs_loop": round(ms_loop / ms_graph, 3),
+        "bitwise_equal_to_loop": bool(same), "tiles_per_class": info["tiles"]}}
+
+
+def plain_softmin(torch, x, w, p, tau):
+    """Unfused PyTorch form of the DDF softmin relaxation (every window's n^2
+    pair terms materialised, autograd backward): the plain form the HIP kernels
+    are compared with."""
+    F = torch.nn.functional
+    B, M, N, _ = x.shape
+    h, n = w // 2, w * w
+    xp = F.pad(x.permute(0, 3, 1, 2), (h, h, h, h), mode="replicate")
+    win = xp.unfold(2, w, 1).unfold(3, w, 1).reshape(B, 3, M, N, n).permute(0, 2, 3, 4, 1)
+    zero = (win == 0).all(-1, keepdim=True)
+    d = torch.where(zero, torch.ones_like(win), win)
+    a, b = d.unsqueeze(-2), d.unsqueeze(-3)
+    dot = (a * b).sum(-1)
+    c0 = a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1]
+    c1 = a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2]
+    c2 = a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]
+    th = torch.atan2(torch.sqrt(c0 * c0 + c1 * c1 + c2 * c2 + 1e-30), dot)
+    A = th.sum(-1)
+    D = torch.sqrt(((win.unsqueeze(-2) - win.unsqueeze(-3)) ** 2).sum(-1) + 1e-30).sum(-1)
+    om = A.pow(1 - p) * D.pow(p)
+    pi = torch.softmax(-om / tau, dim=-1)
+    return (pi.unsqueeze(-1) * win).sum(-2)
+
+
+def differentiable_forms(torch, odf, synth, dev):
+    """16 x 512 x 512 float32, DDF 5x5 p = 0.25: hard fwd + one-hot bwd, and
+    softmin fwd + bwd at tau 0.01 and 0.1; a plain PyTorch softmin on 2 of the
+    images for comparison."""
+    forms = {}
+    x = torch.from_numpy(synth.float_batch(16, 512, 512, 0.1)).to(dev)
+    dy = torch.randn_like(x)
+    npx = 16 * 512 * 512
+    out = torch.empty_like(x)
+    idx = torch.empty(x.shape[:3], dtype=torch.uint8, device=dev)
+    ms_f = time_launches(torch, lambda: odf.filter(x, 5, odf.DDF, 0.25, odf.EXACT, 4, out=out,
+                                                   idx=idx), 10)
+    ms_b = time_launches(torch, lambda: odf.backward_hard(idx, dy, 5), 10)
+    forms["ddf5_f32_16x512x512_hard"] = {
+        "fwd_ms": round(ms_f, 3), "bwd_ms": round(ms_b, 3),
+        "fwd_bwd_mpix_s": round(npx / ((ms_f + ms_b) * 1e3), 1),
+        "bwd_hbm_GBps": round(npx * 25 / (ms_b * 1e-3) / 1e9, 1)}
+    ws = torch.empty(odf.lib().odf_softmin_bwd_workspace(16, 512, 512, 5, odf.DDF),
+                     dtype=torch.uint8, device=dev)
+    for tau in (0.01, 0.1):
+        ms_sf = time_launches(torch, lambda: odf.softmin_forward(x, 5, odf.DDF, 0.25, tau), 5)
+        ms_sb = time_launches(torch, lambda: odf.softmin_backward(x, dy, 5, odf.DDF, 0.25, tau,
+                                                                  workspace=ws), 5)
+        forms["ddf5_f32_16x512x512_softmin_tau%g" % tau] = {
+            "fwd_ms": round(ms_sf, 3), "bwd_ms": round(ms_sb, 3),
+            "fwd_bwd_mpix_s": round(npx / ((ms_sf + ms_sb) * 1e3), 1)}
+    # plain PyTorch on 2 images (its n^2 intermediates take several GB per image)
+    xs = x[:2].clone().requires_grad_(True)
+    g = dy[:2].contiguous()
+
+    def plain():
+        xs.grad = None
+        y = plain_softmin(torch, xs, 5, 0.25, 0.1)
+        y.backward(g)
+
+    ms_plain = time_launches(torch, plain, 2, warm=1)
+    ref = odf.softmin_backward(x[:2].contiguous(), g, 5, odf.DDF, 0.25, 0.1)
+    rel = ((xs.grad - ref).abs().max() / ref.abs().max()).item()
+    forms["ddf5_f32_2x512x512_softmin_tau0.1_plain_torch"] = {
+        "fwd_bwd_ms": round(ms_plain, 3),
+        "fwd_bwd_mpix_s": round(2 * 512 * 512 / (ms_plain * 1e3), 1),
+        "max_rel_diff_vs_hip": rel}
+    return forms
 
 
 def cpu_baseline(img_np, outs, variants, seconds):
@@ -195,13 +333,13 @@ def cpu_baseline(img_np, outs, variants, seconds):
     M, N = img_np.shape[:2]
     codes = {"exact": 0, "minimax": 1, "rgb": 2}
     rng = np.random.default_rng(1009)
-    # calibrate on 4000 pixels per variant, then size the work to ~seconds:
+    # calibrate on 200000 pixels per variant, then size the work to ~seconds:
     # a seeded pixel sample, or whole-image passes repeated when one pass is short
-    probe = rng.integers(0, M * N, 4000)
+    probe = rng.integers(0, M * N, 200000)
     t0 = time.perf_counter()
     for (p, d) in variants:
         oracle.filter_at(img_np, probe, 3, oracle.DDF, p, codes[d])
-    per_px = (time.perf_counter() - t0) / (4000 * len(variants))
+    per_px = (time.perf_counter() - t0) / (200000 * len(variants))
     want = seconds / (per_px * len(variants))
     k = int(min(M * N, max(4000, want)))
     reps = max(1, int(round(want / (M * N)))) if k == M * N else 1

@@ -173,6 +173,12 @@ typedef struct odf_plan odf_plan; /* opaque, owned by the library */
  * job (nothing is allocated), ODF_ENOMEM, ODF_EHIP. */
 int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream);
 
+/* odf_batch_plan with a launch form: ODF_BATCH_PERSISTENT (what odf_batch_plan
+ * uses) or ODF_BATCH_DIRECT, one workgroup per tile of the work list (no
+ * counter; the hardware dispatches the list in order).  Same results. */
+enum { ODF_BATCH_PERSISTENT = 0, ODF_BATCH_DIRECT = 1 };
+int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream);
+
 /* Enqueue the plan on `stream`: a counter-reset kernel, then one persistent
  * kernel per non-empty class whose workgroups take tiles from the work list
  * with an atomic counter.  Allocates nothing and does not synchronise, so it

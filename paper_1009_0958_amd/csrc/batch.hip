@@ -49,7 +49,7 @@ struct BatchClass {
 template <int W, int KIND>
 struct BatchShape {
     static constexpr int EXT_W = 32;
-    static constexpr int EXT_H = W == 5 ? 16 : 32;
+    static constexpr int EXT_H = (W == 5 && KIND == kDDF) ? 16 : 32;
 };
 
 template <int W, int KIND>
@@ -71,37 +71,56 @@ __device__ __forceinline__ T* uni(T* v) {
     return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
+// Filter tile t of a class work list (all fields are uniform over the
+// workgroup and are moved to scalar registers).
+template <int W, int KIND, int DIST>
+__device__ __forceinline__ void batch_tile(
+    FwdShared<W, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false>& sh,
+    const BatchClass& bc, int t) {
+    constexpr int EXT_W = BatchShape<W, KIND>::EXT_W, EXT_H = BatchShape<W, KIND>::EXT_H;
+    const BatchTile tile = bc.tiles[t];
+    const BatchJob& job = bc.jobs[uni(tile.job)];
+    FwdParams prm{};
+    prm.img = uni(job.img);
+    prm.out = uni(job.out);
+    prm.idx = uni(job.idx);
+    prm.B = 1;
+    prm.M = uni(job.M);
+    prm.N = uni(job.N);
+    prm.p = uni(job.p);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        prm.coef.asin_c[k] = uni(job.coef.asin_c[k]);
+        prm.coef.acos_c[k] = uni(job.coef.acos_c[k]);
+    }
+    // an opaque copy of the thread index keeps the tile's address arithmetic
+    // inside a persistent loop instead of hoisted and held in registers
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    fwd_tile<W, KIND, DIST, true, EXT_W, EXT_H, false>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0), tid);
+}
+
+// Persistent form: workgroups take tiles with an atomic counter until the
+// list is exhausted.
 template <int W, int KIND, int DIST>
 __global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_kernel(BatchClass bc) {
-    constexpr int EXT_W = BatchShape<W, KIND>::EXT_W, EXT_H = BatchShape<W, KIND>::EXT_H;
-    __shared__ FwdShared<W, EXT_W, EXT_H, false> sh;
+    __shared__ FwdShared<W, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
     __shared__ int s_tile;
     for (;;) {
         __syncthreads();  // the previous tile is finished with s_tile and sh
         if (threadIdx.x == 0) s_tile = atomicAdd(bc.counter, 1);
         __syncthreads();
-        // uniform across the workgroup: keeps the tile and job fields in scalar registers
         const int t = __builtin_amdgcn_readfirstlane(s_tile);
         if (t >= bc.ntiles) break;
-        // every field is the same for the whole workgroup: move them to scalar registers
-        const BatchTile tile = bc.tiles[t];
-        const BatchJob& job = bc.jobs[uni(tile.job)];
-        FwdParams prm{};
-        prm.img = uni(job.img);
-        prm.out = uni(job.out);
-        prm.idx = uni(job.idx);
-        prm.B = 1;
-        prm.M = uni(job.M);
-        prm.N = uni(job.N);
-        prm.p = uni(job.p);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            prm.coef.asin_c[k] = uni(job.coef.asin_c[k]);
-            prm.coef.acos_c[k] = uni(job.coef.acos_c[k]);
-        }
-        fwd_tile<W, KIND, DIST, true, EXT_W, EXT_H, false>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0),
-                                                           threadIdx.x);
+        batch_tile<W, KIND, DIST>(sh, bc, t);
     }
+}
+
+// Direct form: one workgroup per tile of the list, dispatched in list order.
+template <int W, int KIND, int DIST>
+__global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_direct_kernel(BatchClass bc) {
+    __shared__ FwdShared<W, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
+    batch_tile<W, KIND, DIST>(sh, bc, blockIdx.x);
 }
 
 __global__ void batch_reset(int* counters, int n) {
@@ -143,22 +162,31 @@ static const void* class_kernel(int cls) {
     }
 }
 
-template <int W, int KIND>
-static void launch_class_wk(int dist, int grid, int threads, const BatchClass& bc, hipStream_t s) {
-    if (dist == kExact)
-        hipLaunchKernelGGL((batch_kernel<W, KIND, kExact>), dim3(grid), dim3(threads), 0, s, bc);
-    else if (dist == kMinimax)
-        hipLaunchKernelGGL((batch_kernel<W, KIND, kMinimax>), dim3(grid), dim3(threads), 0, s, bc);
+template <int W, int KIND, int DIST>
+static void launch_class_wkd(bool direct, int grid, int threads, const BatchClass& bc,
+                             hipStream_t s) {
+    if (direct)
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, DIST>), dim3(bc.ntiles), dim3(threads), 0,
+                           s, bc);
     else
-        hipLaunchKernelGGL((batch_kernel<W, KIND, kRgb>), dim3(grid), dim3(threads), 0, s, bc);
+        hipLaunchKernelGGL((batch_kernel<W, KIND, DIST>), dim3(grid), dim3(threads), 0, s, bc);
 }
 
-static void launch_class(int cls, int grid, int threads, const BatchClass& bc, hipStream_t s) {
+template <int W, int KIND>
+static void launch_class_wk(int dist, bool direct, int grid, int threads, const BatchClass& bc,
+                            hipStream_t s) {
+    if (dist == kExact) launch_class_wkd<W, KIND, kExact>(direct, grid, threads, bc, s);
+    else if (dist == kMinimax) launch_class_wkd<W, KIND, kMinimax>(direct, grid, threads, bc, s);
+    else launch_class_wkd<W, KIND, kRgb>(direct, grid, threads, bc, s);
+}
+
+static void launch_class(int cls, bool direct, int grid, int threads, const BatchClass& bc,
+                         hipStream_t s) {
     switch (cls / 3) {
-    case 0: launch_class_wk<3, kBVDF>(cls % 3, grid, threads, bc, s); break;
-    case 1: launch_class_wk<3, kDDF>(cls % 3, grid, threads, bc, s); break;
-    case 2: launch_class_wk<5, kBVDF>(cls % 3, grid, threads, bc, s); break;
-    default: launch_class_wk<5, kDDF>(cls % 3, grid, threads, bc, s); break;
+    case 0: launch_class_wk<3, kBVDF>(cls % 3, direct, grid, threads, bc, s); break;
+    case 1: launch_class_wk<3, kDDF>(cls % 3, direct, grid, threads, bc, s); break;
+    case 2: launch_class_wk<5, kBVDF>(cls % 3, direct, grid, threads, bc, s); break;
+    default: launch_class_wk<5, kDDF>(cls % 3, direct, grid, threads, bc, s); break;
     }
 }
 
@@ -174,6 +202,7 @@ struct odf_plan {
     int grid[odf::kNumClasses] = {};
     int njobs = 0;
     long long npix = 0;
+    int flags = 0;
 };
 
 namespace {
@@ -194,7 +223,13 @@ void destroy(odf_plan* p) {
 extern "C" {
 
 int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream) {
+    return odf_batch_plan_ex(jobs, njobs, ODF_BATCH_PERSISTENT, plan, stream);
+}
+
+int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream) {
     (void)stream;
+    if (flags != ODF_BATCH_PERSISTENT && flags != ODF_BATCH_DIRECT)
+        return bfail(ODF_EINVAL, "flags must be ODF_BATCH_PERSISTENT or ODF_BATCH_DIRECT");
     if (!plan) return bfail(ODF_EINVAL, "plan is NULL");
     *plan = nullptr;
     if (!jobs || njobs < 1) return bfail(ODF_EINVAL, "jobs must be a non-empty array");
@@ -278,6 +313,7 @@ int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream
     }
     p->njobs = njobs;
     p->npix = npix;
+    p->flags = flags;
     *plan = p;
     return ODF_OK;
 }
@@ -293,7 +329,7 @@ int odf_batch_launch(const odf_plan* plan, void* stream) {
                            plan->ntiles[c]};
         int tw, th, thr;
         odf::class_geometry(c, tw, th, thr);
-        odf::launch_class(c, plan->grid[c], thr, bc, s);
+        odf::launch_class(c, plan->flags == ODF_BATCH_DIRECT, plan->grid[c], thr, bc, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(ODF_EHIP, hipGetErrorString(e));

@@ -256,6 +256,7 @@ def _batch_lib():
     if not hasattr(L, "_batch_ready"):
         P, I = ctypes.c_void_p, ctypes.c_int
         L.odf_batch_plan.argtypes = [P, I, ctypes.POINTER(ctypes.c_void_p), P]
+        L.odf_batch_plan_ex.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_void_p), P]
         L.odf_batch_launch.argtypes = [P, P]
         L.odf_plan_info.argtypes = [P, P, P, P, P]
         L.odf_plan_destroy.argtypes = [P]
@@ -264,7 +265,7 @@ def _batch_lib():
         L.odf_tune_set.argtypes = [I, I, I, I, I]
         L.odf_autotune.argtypes = [I, I, I, I, I, I, I, ctypes.c_char_p, P, P]
         L.odf_tune_load.argtypes = [ctypes.c_char_p]
-        for name in ("odf_batch_plan", "odf_batch_launch", "odf_plan_info", "odf_plan_destroy",
+        for name in ("odf_batch_plan", "odf_batch_plan_ex", "odf_batch_launch", "odf_plan_info", "odf_plan_destroy",
                      "odf_tile_config", "odf_tune_get", "odf_tune_set", "odf_autotune",
                      "odf_tune_load"):
             getattr(L, name).restype = I
@@ -280,10 +281,11 @@ class BatchPlan:
     stream (graph-capturable), ``capture()`` records it in a CUDA/HIP graph.
 
     jobs: iterable of dicts with keys img, out, idx (tensors; idx may be None),
-    window, kind, p, dist, q.
+    window, kind, p, dist, q.  direct=True: one workgroup per tile instead of
+    persistent workgroups with an atomic tile counter.
     """
 
-    def __init__(self, jobs):
+    def __init__(self, jobs, direct=False):
         self._keep = []
         arr = (_Job * len(jobs))()
         for i, j in enumerate(jobs):
@@ -306,8 +308,8 @@ class BatchPlan:
         self._jobs = arr
         self._plan = ctypes.c_void_p()
         L = _batch_lib()
-        _check(L.odf_batch_plan(ctypes.cast(arr, ctypes.c_void_p), len(jobs),
-                                ctypes.byref(self._plan), _stream(torch.cuda.current_device())))
+        _check(L.odf_batch_plan_ex(ctypes.cast(arr, ctypes.c_void_p), len(jobs), int(bool(direct)),
+                                   ctypes.byref(self._plan), _stream(torch.cuda.current_device())))
 
     def launch(self):
         _check(_batch_lib().odf_batch_launch(self._plan, _stream(torch.cuda.current_device())))

@@ -39,9 +39,10 @@ def _per_image(job):
     return odf.filter(job["img"], job["window"], job["kind"], job["p"], job["dist"], job["q"])
 
 
-def test_batch_equals_per_image_and_oracle():
+@pytest.mark.parametrize("direct", [False, True])
+def test_batch_equals_per_image_and_oracle(direct):
     jobs, imgs = _mixed_jobs(40, 1)
-    plan = odf.BatchPlan(jobs)
+    plan = odf.BatchPlan(jobs, direct=direct)
     info = plan.info()
     print("plan:", info, flush=True)
     assert info["jobs"] == 40 and sum(info["tiles"]) > 0
@@ -56,10 +57,11 @@ def test_batch_equals_per_image_and_oracle():
     plan.close()
 
 
-def test_batch_graph_replays():
+@pytest.mark.parametrize("direct", [False, True])
+def test_batch_graph_replays(direct):
     jobs, _ = _mixed_jobs(24, 2)
     refs = [_per_image(j) for j in jobs]
-    plan = odf.BatchPlan(jobs)
+    plan = odf.BatchPlan(jobs, direct=direct)
     g = plan.capture()
     for rep in range(4):
         for j in jobs:  # eager work between replays: clear the outputs

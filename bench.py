@@ -57,7 +57,11 @@ def slots_per_pixel(window, kind, p, dist):
         s += pairs
     if kind == "ddf":
         s += pairs * L2_SLOTS + box
-        if p not in (0.0, 1.0):
+        if p == 0.5:
+            s += n  # A*D orders like A^(1/2) D^(1/2)
+        elif p == 0.25:
+            s += 3 * n  # A^3 D orders like A^(3/4) D^(1/4)
+        elif p not in (0.0, 1.0):
             s += n * (2 * TRANS + 2)  # (1-p) log2 A + p log2 D per member
     return s
 

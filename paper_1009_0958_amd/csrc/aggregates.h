@@ -110,20 +110,50 @@ __device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_d
 }
 
 // Objective of one member: BVDF (eq. 2) A; DDF A^(1-p) D^p (p = 1/2 orders as
-// the product of eq. 3).  objective_log is a monotone image used for
-// comparisons; objective_value is the objective itself.
-template <int KIND>
-__device__ __forceinline__ float objective_log(float A, float D, float p) {
-    if (KIND == kBVDF || p == 0.0f) return A;
-    if (p == 1.0f) return D;
-    return fmaf(1.0f - p, __builtin_amdgcn_logf(A), p * __builtin_amdgcn_logf(D));
-}
-
+// the product of eq. 3).  objective_value is the objective itself;
+// ObjectiveKey gives, per launch, a monotone image of it used for comparisons:
+// A (BVDF, p = 0), D (p = 1), A*D (p = 1/2), A^3 D (p = 1/4) or
+// (1-p) log2 A + p log2 D.  The mode depends only on p, so it is uniform.
 template <int KIND>
 __device__ __forceinline__ float objective_value(float A, float D, float p) {
     if (KIND == kBVDF || p == 0.0f) return A;
     if (p == 1.0f) return D;
     return exp2f(fmaf(1.0f - p, log2f(A), p * log2f(D)));
+}
+
+enum ObjMode { kObjA = 0, kObjD = 1, kObjProd = 2, kObjQuarter = 3, kObjLog = 4 };
+
+template <int KIND>
+__device__ __forceinline__ int objective_mode(float p) {
+    if (KIND == kBVDF || p == 0.0f) return kObjA;
+    if (p == 1.0f) return kObjD;
+    if (p == 0.5f) return kObjProd;
+    if (p == 0.25f) return kObjQuarter;
+    return kObjLog;
+}
+
+// Order keys of the objective for all n members, one uniform branch.
+template <int NW>
+__device__ __forceinline__ void objective_keys(int mode, float p, const float (&A)[NW],
+                                               const float (&D)[NW], float (&om)[NW]) {
+    if (mode == kObjA) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) om[u] = A[u];
+    } else if (mode == kObjD) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) om[u] = D[u];
+    } else if (mode == kObjProd) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) om[u] = A[u] * D[u];
+    } else if (mode == kObjQuarter) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) om[u] = (A[u] * A[u]) * (A[u] * D[u]);
+    } else {
+        const float q = 1.0f - p;
+#pragma unroll
+        for (int u = 0; u < NW; ++u)
+            om[u] = fmaf(q, __builtin_amdgcn_logf(A[u]), p * __builtin_amdgcn_logf(D[u]));
+    }
 }
 
 }  // namespace odf

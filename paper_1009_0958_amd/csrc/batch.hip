@@ -43,13 +43,12 @@ struct BatchClass {
     int ntiles;
 };
 
-// Class shapes: 32 x 32 extended tiles for 3x3, 32 x 16 for 5x5 (the
-// persistent loop needs more registers than one tile; 5x5 would spill at
-// 1024 threads).
+// Class shapes: 32 x 32 extended tiles for 3x3; 32 x 16 for 5x5, whose
+// persistent loop needs more registers than a 1024-thread tile allows.
 template <int W, int KIND>
 struct BatchShape {
     static constexpr int EXT_W = 32;
-    static constexpr int EXT_H = (W == 5 && KIND == kDDF) ? 16 : 32;
+    static constexpr int EXT_H = W == 5 ? 16 : 32;
 };
 
 template <int W, int KIND>
@@ -75,7 +74,7 @@ __device__ __forceinline__ T* uni(T* v) {
 // workgroup and are moved to scalar registers).
 template <int W, int KIND, int DIST>
 __device__ __forceinline__ void batch_tile(
-    FwdShared<W, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false>& sh,
+    FwdSharedFor<W, KIND, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false>& sh,
     const BatchClass& bc, int t) {
     constexpr int EXT_W = BatchShape<W, KIND>::EXT_W, EXT_H = BatchShape<W, KIND>::EXT_H;
     const BatchTile tile = bc.tiles[t];
@@ -104,7 +103,7 @@ __device__ __forceinline__ void batch_tile(
 // list is exhausted.
 template <int W, int KIND, int DIST>
 __global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_kernel(BatchClass bc) {
-    __shared__ FwdShared<W, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
+    __shared__ FwdSharedFor<W, KIND, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
     __shared__ int s_tile;
     for (;;) {
         __syncthreads();  // the previous tile is finished with s_tile and sh
@@ -119,7 +118,7 @@ __global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_kernel(Batch
 // Direct form: one workgroup per tile of the list, dispatched in list order.
 template <int W, int KIND, int DIST>
 __global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_direct_kernel(BatchClass bc) {
-    __shared__ FwdShared<W, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
+    __shared__ FwdSharedFor<W, KIND, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
     batch_tile<W, KIND, DIST>(sh, bc, blockIdx.x);
 }
 

@@ -6,26 +6,29 @@ namespace odf {
 
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
 __global__ void __launch_bounds__(EXT_W* EXT_H) fwd_kernel(FwdParams prm) {
-    __shared__ FwdShared<W, EXT_W, EXT_H, AGG> sh;
+    __shared__ FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG> sh;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     fwd_tile<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>(sh, prm, blockIdx.z, blockIdx.y * Gm::TH,
                                                    blockIdx.x * Gm::TW, threadIdx.x);
 }
 
 // Extended-tile shapes (EXT_W x EXT_H, one thread per extended pixel) the
-// autotuner chooses from.  1024-thread shapes leave the 5x5 DDF path too few
-// registers (it keeps both aggregate sets live) and are not offered there.
+// autotuner chooses from.
 constexpr int kNumTileConfigs = 4;
 constexpr int kTileW[kNumTileConfigs] = {32, 64, 32, 64};
 constexpr int kTileH[kNumTileConfigs] = {32, 16, 16, 8};
 
 bool tile_config_valid(int window, int kind, int cfg) {
-    if (cfg < 0 || cfg >= kNumTileConfigs) return false;
-    if (window == 5 && kind == kDDF) return kTileW[cfg] * kTileH[cfg] <= 512;
-    return true;
+    (void)window;
+    (void)kind;
+    return cfg >= 0 && cfg < kNumTileConfigs;
 }
 
-int tile_config_default(int window, int kind) { return (window == 5 && kind == kDDF) ? 2 : 0; }
+int tile_config_default(int window, int kind) {
+    (void)window;
+    (void)kind;
+    return 0;
+}
 
 void tile_config_shape(int cfg, int* ext_w, int* ext_h) {
     *ext_w = kTileW[cfg];
@@ -43,21 +46,16 @@ static hipError_t launch_shape(const FwdParams& prm, hipStream_t stream) {
 
 template <int W, int KIND, int DIST, bool U8, bool AGG>
 static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
-    if (AGG) {  // inspection path: the default shape only
-        if (W == 5 && KIND == kDDF) return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-        return launch_shape<W, KIND, DIST, U8, AGG, 32, 32>(prm, stream);
-    }
-    switch (cfg) {
-    case 0:
-        if (W == 5 && KIND == kDDF) return hipErrorInvalidValue;
-        return launch_shape<W, KIND, DIST, U8, AGG, (W == 5 && KIND == kDDF) ? 32 : 32,
-                            (W == 5 && KIND == kDDF) ? 16 : 32>(prm, stream);
-    case 1:
-        if (W == 5 && KIND == kDDF) return hipErrorInvalidValue;
-        return launch_shape<W, KIND, DIST, U8, AGG, (W == 5 && KIND == kDDF) ? 32 : 64, 16>(prm,
-                                                                                        stream);
-    case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-    default: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+    if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
+        (void)cfg;
+        return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+    } else {
+        switch (cfg) {
+        case 0: return launch_shape<W, KIND, DIST, U8, AGG, 32, 32>(prm, stream);
+        case 1: return launch_shape<W, KIND, DIST, U8, AGG, 64, 16>(prm, stream);
+        case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+        default: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+        }
     }
 }
 

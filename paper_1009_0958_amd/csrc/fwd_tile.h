@@ -17,22 +17,33 @@
 
 namespace odf {
 
-// LDS of one forward tile.
-template <int W, int EXT_W, int EXT_H, bool AGG>
+// LDS of one forward tile.  STAGE: the 5x5 DDF path parks the angle part of
+// every (window, member) objective in LDS during the L2 pass instead of
+// keeping 25 aggregates live in registers, which lets it use 1024-thread tiles.
+template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     float4 dir[Gm::NT];
     float4 raw[Gm::NT];
     float plane[Gm::G * Gm::NT];
     unsigned long long key[AGG ? 1 : Gm::TH * Gm::TW];
+    float stage[STAGE ? Gm::NW * Gm::TH * Gm::TW : 1];
 };
+
+template <int W, int KIND, bool AGG>
+constexpr bool stage_angle_part() {
+    return W == 5 && KIND == kDDF && !AGG;
+}
+
+template <int W, int KIND, int EXT_W, int EXT_H, bool AGG>
+using FwdSharedFor = FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>()>;
 
 // Filter one output tile whose top-left output pixel is (ty0, tx0) of image b.
 // Every thread of the workgroup must call it (it synchronises); tid is the
 // thread's index in the workgroup.
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
-__device__ __forceinline__ void fwd_tile(FwdShared<W, EXT_W, EXT_H, AGG>& sh, const FwdParams& prm,
-                                         int b, int ty0, int tx0, int tid) {
+__device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG>& sh,
+                                         const FwdParams& prm, int b, int ty0, int tx0, int tid) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, NW = Gm::NW, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     float4* s_dir = sh.dir;
@@ -71,6 +82,38 @@ __device__ __forceinline__ void fwd_tile(FwdShared<W, EXT_W, EXT_H, AGG>& sh, co
     float A[NW], D[NW];
     member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex, tid,
                                                              mdir, mraw, prm.coef, A);
+    if constexpr (stage_angle_part<W, KIND, AGG>()) {
+        // angle part of each objective -> LDS, then the L2 pass, then the keys
+        const int mode = objective_mode<KIND>(prm.p);
+        const float p = prm.p;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int cy = ey - u / W, cx = ex - u % W;
+            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+            const float a = A[u];
+            float part = a;                                             // A, A*D
+            if (mode == kObjQuarter) part = (a * a) * a;                // A^3 D
+            else if (mode == kObjLog) part = (1.0f - p) * __builtin_amdgcn_logf(a);
+            sh.stage[u * (TH * TW) + cy * TW + cx] = part;
+        }
+        member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey, ex,
+                                                                tid, mdir, mraw, prm.coef, D);
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int cy = ey - u / W, cx = ex - u % W;
+            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+            if (ty0 + cy >= M || tx0 + cx >= N) continue;
+            const float part = sh.stage[u * (TH * TW) + cy * TW + cx];
+            float om;
+            if (mode == kObjA) om = part;
+            else if (mode == kObjD) om = D[u];
+            else if (mode == kObjLog) om = fmaf(p, __builtin_amdgcn_logf(D[u]), part);
+            else om = part * D[u];
+            const unsigned long long key =
+                ((unsigned long long)order_key(om) << 32) | (unsigned)u;
+            atomicMin(&s_key[cy * TW + cx], key);
+        }
+    } else {
     if (KIND == kDDF)
         member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey, ex,
                                                                 tid, mdir, mraw, prm.coef, D);
@@ -79,22 +122,32 @@ __device__ __forceinline__ void fwd_tile(FwdShared<W, EXT_W, EXT_H, AGG>& sh, co
         for (int u = 0; u < NW; ++u) D[u] = 0.0f;
 
     // a4: objective of this member in every window of the tile containing it
+    if (AGG) {
 #pragma unroll
-    for (int u = 0; u < NW; ++u) {
-        const int cy = ey - u / W;  // window centre, tile-local
-        const int cx = ex - u % W;
-        if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-        if (ty0 + cy >= M || tx0 + cx >= N) continue;
-        if (AGG) {
+        for (int u = 0; u < NW; ++u) {
+            const int cy = ey - u / W;  // window centre, tile-local
+            const int cx = ex - u % W;
+            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+            if (ty0 + cy >= M || tx0 + cx >= N) continue;
             const size_t o = (((size_t)b * M + ty0 + cy) * N + tx0 + cx) * NW + u;
             prm.dbg_A[o] = A[u];
             if (prm.dbg_D) prm.dbg_D[o] = D[u];
             if (prm.dbg_O) prm.dbg_O[o] = objective_value<KIND>(A[u], D[u], prm.p);
-        } else {
-            const float om = objective_log<KIND>(A[u], D[u], prm.p);
-            const unsigned long long key = ((unsigned long long)order_key(om) << 32) | (unsigned)u;
+        }
+    } else {
+        float om[NW];
+        objective_keys<NW>(objective_mode<KIND>(prm.p), prm.p, A, D, om);
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int cy = ey - u / W;  // window centre, tile-local
+            const int cx = ex - u % W;
+            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+            if (ty0 + cy >= M || tx0 + cx >= N) continue;
+            const unsigned long long key =
+                ((unsigned long long)order_key(om[u]) << 32) | (unsigned)u;
             atomicMin(&s_key[cy * TW + cx], key);
         }
+    }
     }
     if (AGG) return;
     __syncthreads();

@@ -106,7 +106,7 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_batch_launch(None, None) == odf.EINVAL
     assert L.odf_plan_destroy(None) == odf.EINVAL
     assert L.odf_tune_set(3, 0, 0, 1, 9) == odf.EINVAL
-    assert L.odf_tune_set(5, 1, 0, 1, 0) == odf.EINVAL  # 1024-thread shape not offered for 5x5 DDF
+    assert L.odf_tune_set(3, 0, 0, 1, -1) == odf.EINVAL
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL

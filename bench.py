@@ -3,7 +3,9 @@
 Default workload (one step): DDF 3x3 on one 1024 x 1024 uint8 RGB image
 (smooth synthetic field + 20 edges, correlated impulsive noise 0.20), for
 p in {0.25, 0.5} and each pair term {exact angle, minimax q=4, chromaticity}
--- six forward launches per step.  ``value`` is pixels filtered per second
+-- six forward filters per step, timed three ways (a loop of six launches; the
+six as one planned batch recorded in a graph, persistent or direct work
+list) and reported for the fastest.  ``value`` is pixels filtered per second
 over the whole step (Mpixels/s).
 
 Also reported on the same JSON line:
@@ -15,6 +17,7 @@ Also reported on the same JSON line:
     that sample (every mismatch checked to be a near-tie).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
+                       [--step-forms loop,persistent,direct] [--copy-probe-mib MiB]
 """
 import argparse
 import json
@@ -93,11 +96,20 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--step-forms", default="loop,persistent,direct",
+                    help="step forms to time (comma list of loop, persistent, direct)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one elementwise copy (float32 negation) of this many MiB, "
+                         "untimed: the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
               "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    forms_wanted = [f for f in args.step_forms.split(",") if f]
+    if not forms_wanted or any(f not in ("loop", "persistent", "direct") for f in forms_wanted):
+        ap.error("--step-forms takes a comma list of loop, persistent, direct")
 
     import torch
     from paper_1009_0958_amd import odf, synth
@@ -118,25 +130,56 @@ def main():
     outs = {v: (torch.empty_like(x), torch.empty((M, N), dtype=torch.uint8, device=dev))
             for v in variants}
 
-    def step():
+    def loop_step():
         for (p, d) in variants:
             o, i = outs[(p, d)]
             odf.filter(x, 3, odf.DDF, p, DIST[d], 4, out=o, idx=i)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    s, e = _events(torch)
-    t0 = time.perf_counter()
-    s.record()
-    for _ in range(args.steps):
-        step()
-    e.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = s.elapsed_time(e) / args.steps
+    # the six filters of a step as one planned batch launch, recorded in a
+    # graph (classes run concurrently on the plan's streams)
+    graphs = {}
+    for mode in [f for f in ("persistent", "direct") if f in forms_wanted]:
+        plan = odf.BatchPlan([dict(img=x, out=outs[(p, d)][0], idx=outs[(p, d)][1], window=3,
+                                   kind=odf.DDF, p=p, dist=DIST[d], q=4) for (p, d) in variants],
+                             direct=(mode == "direct"))
+        graphs[mode] = (plan, plan.capture())
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        s_, e_ = _events(torch)
+        t0_ = time.perf_counter()
+        s_.record()
+        for _ in range(args.steps):
+            fn()
+        e_.record()
+        torch.cuda.synchronize()
+        return s_.elapsed_time(e_) / args.steps, time.perf_counter() - t0_
+
+    step_forms = {"loop_of_launches": timed(loop_step)} if "loop" in forms_wanted else {}
+    for mode, (plan, g) in graphs.items():
+        step_forms["graph_batch_" + mode] = timed(g.replay)
+    best = min(step_forms, key=lambda k: step_forms[k][0])
+    ms_step, wall = step_forms[best]
     px_step = len(variants) * M * N
     value = px_step / (ms_step * 1e3)
+    # the step's outputs are the filter's: check every form's six outputs against
+    # plain launches
+    refs = {v: odf.filter(x, 3, odf.DDF, v[0], DIST[v[1]], 4) for v in variants}
+
+    def outputs_match():
+        return all(torch.equal(refs[v][0], outs[v][0]) and torch.equal(refs[v][1], outs[v][1])
+                   for v in variants)
+
+    step_ok = True
+    for fn in ([loop_step] if "loop" in forms_wanted else []) + [g.replay for (_, g) in graphs.values()]:
+        for o, i in outs.values():
+            o.zero_()
+            i.zero_()
+        fn()
+        torch.cuda.synchronize()
+        step_ok = step_ok and outputs_match()
 
     # per-variant kernel time (HIP events on the launch stream)
     per_variant = {}
@@ -148,6 +191,12 @@ def main():
         per_variant["ddf3_p%.2f_%s" % (p, d)] = {
             "ms": round(ms, 5), "mpix_s": round(M * N / (ms * 1e3), 1),
             "valu_frac": round(slots / (ms * 1e-3) / PEAK_SLOTS, 4)}
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
     dp, dd = float(dom.split("_")[1][1:]), dom.split("_")[2]
     dslots = slots_per_pixel(3, "ddf", dp, dd) * M * N
@@ -182,9 +231,13 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "DDF 3x3 forward, 1024x1024 uint8 RGB, correlated impulsive "
-                               "noise 0.20, p in {0.25, 0.5} x {exact, minimax q=4, rgb}",
+                               "noise 0.20, p in {0.25, 0.5} x {exact, minimax q=4, rgb}; "
+                               "timed as the fastest of: six launches, one batched graph "
+                               "(persistent or direct work list)",
                    "image": [M, N], "launches_per_step": len(variants), "parallelism": "none"},
         "wall_s": round(wall, 3),
+        "step_forms_ms": {k: round(v[0], 5) for k, v in step_forms.items()}, "step_form": best,
+        "step_outputs_match_plain_launch": step_ok,
         "tuned": tuned, "variants": per_variant, "roofline": roofline, "forms": forms,
         "cpu_baseline": cpu,
         "paper_context": {"ddf3_exact_1024x1024_mpix_s": 0.0368,
@@ -221,10 +274,17 @@ def large_frame_forms(torch, odf, synth, dev, DIST):
 
 def batched_form(torch, odf, synth, dev):
     """256 uint8 images of mixed size (64..2048 x 64..1536), window, kind and
-    noise: one planned persistent launch captured in a graph, against a loop
+    noise: one planned launch captured in a graph (direct form, whose tile
+    shapes come from the autotuned table, and persistent form), against a loop
     of per-image launches of the same jobs."""
     specs = synth.mixed_batch_specs(256)
     imgs = synth.mixed_batch_images(specs, workers=16)
+    # tile shapes of the four classes in the batch (untimed)
+    tuned = {}
+    for w in (3, 5):
+        for kind in (odf.BVDF, odf.DDF):
+            best, _ = odf.autotune(w, kind, odf.EXACT, True, 1024, 1024, 5)
+            tuned[f"w{w}_{'ddf' if kind else 'bvdf'}"] = odf.tile_config(best)
     jobs = []
     for s_, im in zip(specs, imgs):
         t = torch.from_numpy(im).to(dev)
@@ -233,13 +293,6 @@ def batched_form(torch, odf, synth, dev):
                          window=s_["window"], kind=s_["kind"], p=s_["p"], dist=odf.EXACT, q=4))
     del imgs
     npx = sum(int(j["img"].shape[0] * j["img"].shape[1]) for j in jobs)
-    plan = odf.BatchPlan(jobs)
-    graph = plan.capture()
-    ms_graph = time_launches(torch, graph.replay, 5, warm=2)
-    dplan = odf.BatchPlan(jobs, direct=True)
-    dgraph = dplan.capture()
-    ms_direct = time_launches(torch, dgraph.replay, 5, warm=2)
-    dplan.close()
     loop_out = [(torch.empty_like(j["out"]), torch.empty_like(j["idx"])) for j in jobs]
 
     def loop():
@@ -247,18 +300,32 @@ def batched_form(torch, odf, synth, dev):
             odf.filter(j["img"], j["window"], j["kind"], j["p"], odf.EXACT, 4, out=o, idx=i)
 
     ms_loop = time_launches(torch, loop, 3, warm=1)
-    same = all(torch.equal(j["out"], o) and torch.equal(j["idx"], i)
-               for j, (o, i) in zip(jobs, loop_out))
-    info = plan.info()
-    plan.close()
+
+    def same_as_loop():
+        return all(torch.equal(j["out"], o) and torch.equal(j["idx"], i)
+                   for j, (o, i) in zip(jobs, loop_out))
+
+    res = {}
+    for name, direct in (("direct", True), ("persistent", False)):
+        for j in jobs:
+            j["out"].zero_()
+            j["idx"].zero_()
+        plan = odf.BatchPlan(jobs, direct=direct)
+        graph = plan.capture()
+        ms = time_launches(torch, graph.replay, 5, warm=2)
+        res[name] = (ms, same_as_loop(), plan.info())
+        plan.close()
+    ms_direct, same_d, info = res["direct"]
+    ms_pers, same_p, _ = res["persistent"]
     return {"batched_256_mixed": {
-        "mpix": round(npx / 1e6, 2), "graph_ms": round(ms_graph, 3),
-        "graph_mpix_s": round(npx / (ms_graph * 1e3), 1),
+        "mpix": round(npx / 1e6, 2), "tile_shapes": tuned,
         "direct_graph_ms": round(ms_direct, 3), "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
+        "persistent_graph_ms": round(ms_pers, 3),
+        "persistent_graph_mpix_s": round(npx / (ms_pers * 1e3), 1),
         "loop_ms": round(ms_loop, 3),
         "loop_mpix_s": round(npx / (ms_loop * 1e3), 1),
-        "speedup_vs_loop": round(ms_loop / ms_graph, 3),
-        "bitwise_equal_to_loop": bool(same), "tiles_per_class": info["tiles"]}}
+        "speedup_direct_vs_loop": round(ms_loop / ms_direct, 3),
+        "bitwise_equal_to_loop": bool(same_d and same_p), "tiles_per_class": info["tiles"]}}
 
 
 def plain_softmin(torch, x, w, p, tau):

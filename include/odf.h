@@ -173,17 +173,22 @@ typedef struct odf_plan odf_plan; /* opaque, owned by the library */
  * job (nothing is allocated), ODF_ENOMEM, ODF_EHIP. */
 int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream);
 
-/* odf_batch_plan with a launch form: ODF_BATCH_PERSISTENT (what odf_batch_plan
- * uses) or ODF_BATCH_DIRECT, one workgroup per tile of the work list (no
- * counter; the hardware dispatches the list in order).  Same results. */
+/* odf_batch_plan with a launch form: ODF_BATCH_DIRECT (what odf_batch_plan
+ * uses: one workgroup per tile of the work list, dispatched by the hardware
+ * in list order, tile shape from the tuning table) or ODF_BATCH_PERSISTENT
+ * (persistent workgroups taking tiles with an atomic counter).  Same results;
+ * on MI355X the direct form is faster (the persistent loop costs registers). */
 enum { ODF_BATCH_PERSISTENT = 0, ODF_BATCH_DIRECT = 1 };
 int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream);
 
-/* Enqueue the plan on `stream`: a counter-reset kernel, then one persistent
- * kernel per non-empty class whose workgroups take tiles from the work list
- * with an atomic counter.  Allocates nothing and does not synchronise, so it
- * may be captured in a hipGraph and replayed.  Launches of one plan must not
- * overlap in time (they share the tile counters). */
+/* Enqueue the plan on `stream`: a counter-reset kernel, then one kernel per
+ * non-empty class over its work list (direct or persistent form).  Classes
+ * after the first run on the plan's own
+ * auxiliary streams, forked from and joined back to `stream` with events, so
+ * they overlap; everything is ordered after prior work on `stream` and before
+ * later work on it.  Allocates nothing and does not synchronise, so it may be
+ * captured in a hipGraph and replayed.  Launches of one plan must not overlap
+ * in time (they share the tile counters and streams). */
 int odf_batch_launch(const odf_plan* plan, void* stream);
 
 /* Plan summary: job count, total pixels, tiles and persistent grid per class,

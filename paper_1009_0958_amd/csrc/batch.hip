@@ -8,8 +8,10 @@
 // its own tile function (a single kernel branching over all of them would
 // carry the largest budget, and spill, everywhere).  Tiles are ordered by
 // decreasing size.  odf_batch_launch enqueues a counter
-// reset kernel and the class kernels on one stream; it allocates nothing and
-// never synchronises, so it can be captured in a hipGraph.  Every tile writes
+// reset kernel on the caller's stream, then the class kernels, forked onto
+// per-plan auxiliary streams (default priority) and joined back with events
+// so that classes run concurrently and their tails overlap; it allocates
+// nothing and never synchronises, so it can be captured in a hipGraph.  Every tile writes
 // only its own outputs with the same tile function as the per-image kernels,
 // so results do not depend on which workgroup takes which tile.
 #include <algorithm>
@@ -43,18 +45,17 @@ struct BatchClass {
     int ntiles;
 };
 
-// Class shapes: 32 x 32 extended tiles for 3x3; 32 x 16 for 5x5, whose
-// persistent loop needs more registers than a 1024-thread tile allows.
-template <int W, int KIND>
+// Extended-tile shapes of the batch kernels: 0 = 32 x 32, 1 = 32 x 16.  The
+// persistent form uses 32 x 32 for 3x3 and 32 x 16 for 5x5 (its loop needs
+// more registers than a 1024-thread 5x5 tile allows); the direct form takes
+// the shape the tuning table holds for the class (1024-thread entries map to
+// 32 x 32, 512-thread ones to 32 x 16).
+template <int SHAPE>
 struct BatchShape {
     static constexpr int EXT_W = 32;
-    static constexpr int EXT_H = W == 5 ? 16 : 32;
+    static constexpr int EXT_H = SHAPE == 0 ? 32 : 16;
+    static constexpr int THREADS = EXT_W * EXT_H;
 };
-
-template <int W, int KIND>
-constexpr int batch_threads() {
-    return BatchShape<W, KIND>::EXT_W * BatchShape<W, KIND>::EXT_H;
-}
 
 constexpr int kNumClasses = 12;  // (window 3/5) x (BVDF/DDF) x (exact/minimax/rgb)
 
@@ -72,11 +73,11 @@ __device__ __forceinline__ T* uni(T* v) {
 
 // Filter tile t of a class work list (all fields are uniform over the
 // workgroup and are moved to scalar registers).
-template <int W, int KIND, int DIST>
+template <int W, int KIND, int DIST, int SHAPE>
 __device__ __forceinline__ void batch_tile(
-    FwdSharedFor<W, KIND, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false>& sh,
+    FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false>& sh,
     const BatchClass& bc, int t) {
-    constexpr int EXT_W = BatchShape<W, KIND>::EXT_W, EXT_H = BatchShape<W, KIND>::EXT_H;
+    constexpr int EXT_W = BatchShape<SHAPE>::EXT_W, EXT_H = BatchShape<SHAPE>::EXT_H;
     const BatchTile tile = bc.tiles[t];
     const BatchJob& job = bc.jobs[uni(tile.job)];
     FwdParams prm{};
@@ -99,11 +100,18 @@ __device__ __forceinline__ void batch_tile(
     fwd_tile<W, KIND, DIST, true, EXT_W, EXT_H, false>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0), tid);
 }
 
+template <int W>
+constexpr int persistent_shape() {
+    return W == 5 ? 1 : 0;
+}
+
 // Persistent form: workgroups take tiles with an atomic counter until the
 // list is exhausted.
 template <int W, int KIND, int DIST>
-__global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_kernel(BatchClass bc) {
-    __shared__ FwdSharedFor<W, KIND, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
+__global__ void __launch_bounds__(BatchShape<persistent_shape<W>()>::THREADS)
+    batch_kernel(BatchClass bc) {
+    constexpr int SHAPE = persistent_shape<W>();
+    __shared__ FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
     __shared__ int s_tile;
     for (;;) {
         __syncthreads();  // the previous tile is finished with s_tile and sh
@@ -111,81 +119,75 @@ __global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_kernel(Batch
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_tile);
         if (t >= bc.ntiles) break;
-        batch_tile<W, KIND, DIST>(sh, bc, t);
+        batch_tile<W, KIND, DIST, SHAPE>(sh, bc, t);
     }
 }
 
 // Direct form: one workgroup per tile of the list, dispatched in list order.
-template <int W, int KIND, int DIST>
-__global__ void __launch_bounds__((batch_threads<W, KIND>())) batch_direct_kernel(BatchClass bc) {
-    __shared__ FwdSharedFor<W, KIND, BatchShape<W, KIND>::EXT_W, BatchShape<W, KIND>::EXT_H, false> sh;
-    batch_tile<W, KIND, DIST>(sh, bc, blockIdx.x);
+template <int W, int KIND, int DIST, int SHAPE>
+__global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS) batch_direct_kernel(BatchClass bc) {
+    __shared__ FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
+    batch_tile<W, KIND, DIST, SHAPE>(sh, bc, blockIdx.x);
 }
 
 __global__ void batch_reset(int* counters, int n) {
     if (threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
-template <int W, int KIND>
-static void class_geometry(int& tw, int& th, int& threads) {
-    using S = BatchShape<W, KIND>;
-    using Gm = FwdGeom<W, S::EXT_W, S::EXT_H>;
-    tw = Gm::TW;
-    th = Gm::TH;
-    threads = Gm::NT;
-}
-
 // class = ((window == 5) * 2 + kind) * 3 + dist
-static void class_geometry(int cls, int& tw, int& th, int& threads) {
-    switch (cls / 3) {
-    case 0: class_geometry<3, kBVDF>(tw, th, threads); break;
-    case 1: class_geometry<3, kDDF>(tw, th, threads); break;
-    case 2: class_geometry<5, kBVDF>(tw, th, threads); break;
-    default: class_geometry<5, kDDF>(tw, th, threads); break;
-    }
+static int class_window(int cls) { return cls / 6 ? 5 : 3; }
+
+static void class_geometry(int cls, int shape, int& tw, int& th, int& threads) {
+    const int h = class_window(cls) / 2;
+    tw = BatchShape<0>::EXT_W - 2 * h;
+    th = (shape == 0 ? BatchShape<0>::EXT_H : BatchShape<1>::EXT_H) - 2 * h;
+    threads = shape == 0 ? BatchShape<0>::THREADS : BatchShape<1>::THREADS;
 }
 
 template <int W, int KIND>
-static const void* class_kernel_wk(int dist) {
+static const void* persistent_kernel_wk(int dist) {
     if (dist == kExact) return reinterpret_cast<const void*>(&batch_kernel<W, KIND, kExact>);
     if (dist == kMinimax) return reinterpret_cast<const void*>(&batch_kernel<W, KIND, kMinimax>);
     return reinterpret_cast<const void*>(&batch_kernel<W, KIND, kRgb>);
 }
 
-static const void* class_kernel(int cls) {
+static const void* persistent_kernel(int cls) {
     switch (cls / 3) {
-    case 0: return class_kernel_wk<3, kBVDF>(cls % 3);
-    case 1: return class_kernel_wk<3, kDDF>(cls % 3);
-    case 2: return class_kernel_wk<5, kBVDF>(cls % 3);
-    default: return class_kernel_wk<5, kDDF>(cls % 3);
+    case 0: return persistent_kernel_wk<3, kBVDF>(cls % 3);
+    case 1: return persistent_kernel_wk<3, kDDF>(cls % 3);
+    case 2: return persistent_kernel_wk<5, kBVDF>(cls % 3);
+    default: return persistent_kernel_wk<5, kDDF>(cls % 3);
     }
 }
 
 template <int W, int KIND, int DIST>
-static void launch_class_wkd(bool direct, int grid, int threads, const BatchClass& bc,
+static void launch_class_wkd(bool direct, int shape, int grid, int threads, const BatchClass& bc,
                              hipStream_t s) {
-    if (direct)
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, DIST>), dim3(bc.ntiles), dim3(threads), 0,
-                           s, bc);
-    else
+    if (!direct)
         hipLaunchKernelGGL((batch_kernel<W, KIND, DIST>), dim3(grid), dim3(threads), 0, s, bc);
+    else if (shape == 0)
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, DIST, 0>), dim3(bc.ntiles), dim3(threads),
+                           0, s, bc);
+    else
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, DIST, 1>), dim3(bc.ntiles), dim3(threads),
+                           0, s, bc);
 }
 
 template <int W, int KIND>
-static void launch_class_wk(int dist, bool direct, int grid, int threads, const BatchClass& bc,
-                            hipStream_t s) {
-    if (dist == kExact) launch_class_wkd<W, KIND, kExact>(direct, grid, threads, bc, s);
-    else if (dist == kMinimax) launch_class_wkd<W, KIND, kMinimax>(direct, grid, threads, bc, s);
-    else launch_class_wkd<W, KIND, kRgb>(direct, grid, threads, bc, s);
+static void launch_class_wk(int dist, bool direct, int shape, int grid, int threads,
+                            const BatchClass& bc, hipStream_t s) {
+    if (dist == kExact) launch_class_wkd<W, KIND, kExact>(direct, shape, grid, threads, bc, s);
+    else if (dist == kMinimax) launch_class_wkd<W, KIND, kMinimax>(direct, shape, grid, threads, bc, s);
+    else launch_class_wkd<W, KIND, kRgb>(direct, shape, grid, threads, bc, s);
 }
 
-static void launch_class(int cls, bool direct, int grid, int threads, const BatchClass& bc,
-                         hipStream_t s) {
+static void launch_class(int cls, bool direct, int shape, int grid, int threads,
+                         const BatchClass& bc, hipStream_t s) {
     switch (cls / 3) {
-    case 0: launch_class_wk<3, kBVDF>(cls % 3, direct, grid, threads, bc, s); break;
-    case 1: launch_class_wk<3, kDDF>(cls % 3, direct, grid, threads, bc, s); break;
-    case 2: launch_class_wk<5, kBVDF>(cls % 3, direct, grid, threads, bc, s); break;
-    default: launch_class_wk<5, kDDF>(cls % 3, direct, grid, threads, bc, s); break;
+    case 0: launch_class_wk<3, kBVDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
+    case 1: launch_class_wk<3, kDDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
+    case 2: launch_class_wk<5, kBVDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
+    default: launch_class_wk<5, kDDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
     }
 }
 
@@ -199,9 +201,13 @@ struct odf_plan {
     int ntiles[odf::kNumClasses] = {};
     int offset[odf::kNumClasses] = {};
     int grid[odf::kNumClasses] = {};
+    int shape[odf::kNumClasses] = {};
     int njobs = 0;
     long long npix = 0;
     int flags = 0;
+    hipStream_t aux[odf::kNumClasses] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[odf::kNumClasses] = {};
 };
 
 namespace {
@@ -209,11 +215,27 @@ namespace {
 int bfail(int code, const char* msg) { return odf::set_error(code, "%s", msg); }
 
 
+// Tile shape of a class: fixed for the persistent form, from the tuning
+// table for the direct form.
+int shape_of(int cls, int flags) {
+    const int w = odf::class_window(cls);
+    if (flags != ODF_BATCH_DIRECT) return w == 5 ? 1 : 0;
+    const int cfg = odf::tuned_config(w, (cls / 3) % 2, cls % 3, true);
+    int ew, eh;
+    odf::tile_config_shape(cfg, &ew, &eh);
+    return ew * eh >= 1024 ? 0 : 1;
+}
+
 void destroy(odf_plan* p) {
     if (!p) return;
-    hipFree(p->d_jobs);
-    hipFree(p->d_tiles);
-    hipFree(p->d_counters);
+    for (int c = 0; c < odf::kNumClasses; ++c) {
+        if (p->aux[c]) (void)hipStreamDestroy(p->aux[c]);
+        if (p->join[c]) (void)hipEventDestroy(p->join[c]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    (void)hipFree(p->d_jobs);
+    (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_counters);
     delete p;
 }
 
@@ -222,7 +244,7 @@ void destroy(odf_plan* p) {
 extern "C" {
 
 int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream) {
-    return odf_batch_plan_ex(jobs, njobs, ODF_BATCH_PERSISTENT, plan, stream);
+    return odf_batch_plan_ex(jobs, njobs, ODF_BATCH_DIRECT, plan, stream);
 }
 
 int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream) {
@@ -261,7 +283,7 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         if (j.dist == ODF_MINIMAX) b.coef = odf::minimax_coef(j.q);
         const int cls = ((j.window == 5) * 2 + (j.kind == ODF_DDF)) * 3 + j.dist;
         int tw, th, thr;
-        odf::class_geometry(cls, tw, th, thr);
+        odf::class_geometry(cls, shape_of(cls, flags), tw, th, thr);
         for (int ty = 0; ty < j.M; ty += th)
             for (int tx = 0; tx < j.N; tx += tw) {
                 // cost: output pixels of the (possibly clipped) tile
@@ -289,9 +311,14 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
     }
     for (int c = 0; c < odf::kNumClasses; ++c) {
         int tw, th, thr, per_cu = 0;
-        odf::class_geometry(c, tw, th, thr);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, odf::class_kernel(c), thr, 0) !=
-                hipSuccess ||
+        p->shape[c] = shape_of(c, flags);
+        odf::class_geometry(c, p->shape[c], tw, th, thr);
+        if (flags == ODF_BATCH_DIRECT) {
+            p->grid[c] = p->ntiles[c];
+            continue;
+        }
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, odf::persistent_kernel(c), thr,
+                                                         0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         p->grid[c] = std::min(p->ntiles[c], per_cu * cus);
@@ -310,6 +337,21 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         destroy(p);
         return bfail(ODF_EHIP, "uploading the plan failed");
     }
+    // auxiliary streams for every non-empty class after the first
+    bool first = true;
+    for (int c = 0; c < odf::kNumClasses; ++c) {
+        if (p->ntiles[c] == 0) continue;
+        if (first) { first = false; continue; }
+        if (hipStreamCreateWithFlags(&p->aux[c], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming) != hipSuccess) {
+            destroy(p);
+            return bfail(ODF_EHIP, "creating the plan's streams failed");
+        }
+    }
+    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess) {
+        destroy(p);
+        return bfail(ODF_EHIP, "creating the plan's events failed");
+    }
     p->njobs = njobs;
     p->npix = npix;
     p->flags = flags;
@@ -322,13 +364,21 @@ int odf_batch_launch(const odf_plan* plan, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(odf::batch_reset, dim3(1), dim3(64), 0, s, plan->d_counters,
                        odf::kNumClasses);
+    if (hipEventRecord(plan->fork, s) != hipSuccess) return bfail(ODF_EHIP, "fork event failed");
     for (int c = 0; c < odf::kNumClasses; ++c) {
         if (plan->ntiles[c] == 0) continue;
         odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[c], plan->d_counters + c,
                            plan->ntiles[c]};
         int tw, th, thr;
-        odf::class_geometry(c, tw, th, thr);
-        odf::launch_class(c, plan->flags == ODF_BATCH_DIRECT, plan->grid[c], thr, bc, s);
+        odf::class_geometry(c, plan->shape[c], tw, th, thr);
+        hipStream_t cs = plan->aux[c] ? plan->aux[c] : s;
+        if (cs != s && hipStreamWaitEvent(cs, plan->fork, 0) != hipSuccess)
+            return bfail(ODF_EHIP, "stream fork failed");
+        odf::launch_class(c, plan->flags == ODF_BATCH_DIRECT, plan->shape[c], plan->grid[c], thr, bc,
+                          cs);
+        if (cs != s && (hipEventRecord(plan->join[c], cs) != hipSuccess ||
+                        hipStreamWaitEvent(s, plan->join[c], 0) != hipSuccess))
+            return bfail(ODF_EHIP, "stream join failed");
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(ODF_EHIP, hipGetErrorString(e));

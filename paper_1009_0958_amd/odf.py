@@ -281,11 +281,11 @@ class BatchPlan:
     stream (graph-capturable), ``capture()`` records it in a CUDA/HIP graph.
 
     jobs: iterable of dicts with keys img, out, idx (tensors; idx may be None),
-    window, kind, p, dist, q.  direct=True: one workgroup per tile instead of
-    persistent workgroups with an atomic tile counter.
+    window, kind, p, dist, q.  direct=True (default): one workgroup per tile;
+    direct=False: persistent workgroups with an atomic tile counter.
     """
 
-    def __init__(self, jobs, direct=False):
+    def __init__(self, jobs, direct=True):
         self._keep = []
         arr = (_Job * len(jobs))()
         for i, j in enumerate(jobs):

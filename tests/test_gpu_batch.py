@@ -79,7 +79,7 @@ def test_batch_without_idx_and_single_job():
     img = torch.from_numpy(synth.image_corr(77, 91, 0.2, key=4)).to(DEV)
     out = torch.empty_like(img)
     plan = odf.BatchPlan([dict(img=img, out=out, idx=None, window=5, kind=odf.DDF, p=0.25,
-                               dist=odf.EXACT)])
+                               dist=odf.EXACT)], direct=False)
     plan.launch()
     ref, _ = odf.filter(img, 5, odf.DDF, 0.25, odf.EXACT)
     assert torch.equal(out, ref)

@@ -51,8 +51,11 @@ def _load():
         lib.oracle_backward_hard.argtypes = [P, P, I, I, I, I, P]
         lib.oracle_softmin_fwd.argtypes = [P, I, I, I, I, I, D, D, P, P, I]
         lib.oracle_softmin_bwd.argtypes = [P, P, I, I, I, I, I, D, D, P, I]
+        lib.oracle_acwddf.argtypes = [P, I, I, I, I, I, I, I, D, P, P, P, P, I]
+        lib.oracle_acwddf_at.argtypes = [P, I, I, I, I, I, I, I, D, P, I64, P, P, P, P, I]
         for f in (lib.oracle_pair_terms, lib.oracle_filter, lib.oracle_filter_at,
-                  lib.oracle_backward_hard, lib.oracle_softmin_fwd, lib.oracle_softmin_bwd):
+                  lib.oracle_backward_hard, lib.oracle_softmin_fwd, lib.oracle_softmin_bwd,
+                  lib.oracle_acwddf, lib.oracle_acwddf_at):
             f.restype = I
         _lib = lib
     return _lib
@@ -175,3 +178,41 @@ def softmin_bwd(img, dy, window=5, kind=DDF, p=0.25, tau=0.1, nthreads=0):
     _check(_load().oracle_softmin_bwd(_ptr(x), _ptr(g), B, M, N, window, kind, float(p),
                                       float(tau), _ptr(dx), nthreads), "softmin_bwd")
     return dx[0] if squeeze else dx
+
+
+def acwddf(img, window=3, dist=EXACT, q=4, lam=2, T=10.8, diag=False, nthreads=0):
+    """Adaptive centre-weighted DDF (Section III, Experiment 2; eq. 9).
+
+    Returns (out, idx, S) or (out, idx, S, diag) when ``diag``: out float64
+    with the shape of ``img``, idx uint8 (the DDF selection where S > T, else
+    the centre (n - 1) / 2), S float64 (the switching statistic), diag
+    float64 (..., 5n): the eq. (3) objective, the three centre-weighted
+    objectives (k = lam, lam + 1, lam + 2) and A(x_u, x_d) * L2(x_u, x_d).
+    """
+    x, squeeze = _batch(img)
+    B, M, N, _ = x.shape
+    n = window * window
+    out = np.empty_like(x)
+    idx = np.empty((B, M, N), np.uint8)
+    S = np.empty((B, M, N))
+    dg = np.empty((B, M, N, 5 * n)) if diag else None
+    _check(_load().oracle_acwddf(_ptr(x), B, M, N, window, dist, q, int(lam), float(T), _ptr(out),
+                                 _ptr(idx), _ptr(S), _ptr(dg), nthreads), "acwddf")
+    res = [out, idx, S] + ([dg] if diag else [])
+    if squeeze:
+        res = [r[0] for r in res]
+    return tuple(res)
+
+
+def acwddf_at(img, pix, window=3, dist=EXACT, q=4, lam=2, T=10.8, nthreads=0):
+    """ACWDDF at flat pixel positions ``pix``: (out (k,3), idx (k,), S (k,), diag (k, 5n))."""
+    x, _ = _batch(img)
+    B, M, N, _ = x.shape
+    n = window * window
+    pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int64).ravel())
+    k = pix.shape[0]
+    out, idx, S, dg = np.empty((k, 3)), np.empty(k, np.uint8), np.empty(k), np.empty((k, 5 * n))
+    _check(_load().oracle_acwddf_at(_ptr(x), B, M, N, window, dist, q, int(lam), float(T),
+                                    _ptr(pix), k, _ptr(out), _ptr(idx), _ptr(S), _ptr(dg),
+                                    nthreads), "acwddf_at")
+    return out, idx, S, dg

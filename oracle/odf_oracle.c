@@ -38,7 +38,10 @@
  *   - chromaticity distance (Section 2.2, eq. 7) with Minkowski order 2, used
  *     raw by BVDF and through the line of eq. (10) by DDF;
  *   - the self pair j = i is part of every sum, through the same pair
- *     function as every other pair.
+ *     function as every other pair;
+ *   - ACWDDF (Section III, Experiment 2): CWDDF^k applies the centre weights
+ *     of eq. (9) to both sums of eq. (3); lambda is limited to [1, d - 2] so
+ *     that every level k = lambda .. lambda + 2 lies in [1, d].
  */
 #include <math.h>
 #include <stdint.h>
@@ -458,5 +461,116 @@ int oracle_softmin_bwd(const double *img, const double *dy, int B, int M, int N,
             }
         }
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------- ACWDDF
+ * Adaptive centre-weighted directional distance filter (Section III,
+ * Experiment 2: the switching rule and eq. 9).
+ *
+ * Weights of eq. (9): w_v(k) = n - 2k + 2 for the window centre v = d and 1
+ * for every other member, smoothing level k in [1, d], d = (n + 1) / 2
+ * (1-based; the centre is member (n - 1) / 2 here).
+ *
+ * CWDDF^k (reading: the rule names CWDDF^k but eq. 9 writes out only the
+ * centre-weighted VMF): the weights of eq. (9) applied to both sums of eq. (3),
+ *   Omega^k_u = (sum_v w_v(k) A(x_u, x_v)) * (sum_v w_v(k) L2(x_u, x_v)),
+ * and y_CWDDF^k the member of lowest index with the smallest Omega^k.
+ *
+ * Switch: S = sum_{k = lambda}^{lambda + 2} A(y_CWDDF^k, x_d) * L2(y_CWDDF^k, x_d).
+ * The output is the DDF output (eq. 3, the plain product) when S > T and the
+ * centre x_d otherwise.  k must stay in [1, d], so lambda is taken in
+ * [1, d - 2] (the rule's lambda in [1, d - 1] would reach k = d + 1).
+ * A(.,.) is the variant's pair term: the exact angle, the minimax angle of
+ * Method 1, or eq. (10) applied to the chromaticity distance of Method 2.
+ *
+ * diag (nullable, 5n doubles per pixel): [0, n) Omega of eq. (3); then
+ * Omega^k for k = lambda, lambda + 1, lambda + 2 (n each); then
+ * A(x_u, x_d) * L2(x_u, x_d) for every member u. */
+static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, int lambda,
+                       double T, int64_t pix, double *out, uint8_t *idx, double *S_out,
+                       double *diag) {
+    int64_t mn = (int64_t)M * N;
+    int64_t b = pix / mn, rc = pix % mn;
+    int r = (int)(rc / N), c = (int)(rc % N);
+    int n = w * w, d = (n - 1) / 2;
+    int64_t src[25];
+    double th[25][25], l2[25][25], Om[4][25];
+    const double *base = img + b * mn * 3;
+    window_members(M, N, w, r, c, src);
+    for (int u = 0; u < n; ++u)
+        for (int v = 0; v < n; ++v) {
+            th[u][v] = pair_term(base + src[u] * 3, base + src[v] * 3, OK_DDF, dist, q);
+            l2[u][v] = minkowski_l2(base + src[u] * 3, base + src[v] * 3);
+        }
+    /* eq. (3) and the three centre-weighted objectives */
+    for (int j = 0; j < 4; ++j) {
+        int k = lambda + j - 1;
+        for (int u = 0; u < n; ++u) {
+            double a = 0.0, e = 0.0;
+            for (int v = 0; v < n; ++v) {
+                double wv = (j > 0 && v == d) ? (double)(n - 2 * k + 2) : 1.0;
+                a += wv * th[u][v];
+                e += wv * l2[u][v];
+            }
+            Om[j][u] = a * e;
+        }
+    }
+    int sel[4];
+    for (int j = 0; j < 4; ++j) {
+        sel[j] = 0;
+        for (int u = 1; u < n; ++u)
+            if (Om[j][u] < Om[j][sel[j]]) sel[j] = u;
+    }
+    double S = 0.0;
+    for (int j = 1; j < 4; ++j) S += th[sel[j]][d] * l2[sel[j]][d];
+    int chosen = S > T ? sel[0] : d;
+    const double *x = base + src[chosen] * 3;
+    if (out) { out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; }
+    if (idx) *idx = (uint8_t)chosen;
+    if (S_out) *S_out = S;
+    if (diag) {
+        for (int j = 0; j < 4; ++j)
+            for (int u = 0; u < n; ++u) diag[j * n + u] = Om[j][u];
+        for (int u = 0; u < n; ++u) diag[4 * n + u] = th[u][d] * l2[u][d];
+    }
+}
+
+static int check_acw(int B, int M, int N, int w, int dist, int q, int lambda, double T) {
+    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q)) return -1;
+    int dd = (w * w + 1) / 2;
+    if (lambda < 1 || lambda > dd - 2 || T != T) return -1;
+    return 0;
+}
+
+/* Full ACWDDF over B images; out B x M x N x 3, idx and S B x M x N, diag
+ * B x M x N x 5n (each nullable). */
+int oracle_acwddf(const double *img, int B, int M, int N, int w, int dist, int q, int lambda,
+                  double T, double *out, uint8_t *idx, double *S, double *diag, int nthreads) {
+    if (check_acw(B, M, N, w, dist, q, lambda, T) || !img) return -1;
+    set_threads(nthreads);
+    int64_t total = (int64_t)B * M * N;
+    int n = w * w;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t pix = 0; pix < total; ++pix)
+        acwddf_one(img, M, N, w, dist, q, lambda, T, pix, out ? out + 3 * pix : NULL,
+                   idx ? idx + pix : NULL, S ? S + pix : NULL, diag ? diag + 5 * n * pix : NULL);
+    return 0;
+}
+
+/* ACWDDF at listed flat pixel positions; results packed per listed pixel. */
+int oracle_acwddf_at(const double *img, int B, int M, int N, int w, int dist, int q, int lambda,
+                     double T, const int64_t *pix, int64_t npix, double *out, uint8_t *idx,
+                     double *S, double *diag, int nthreads) {
+    if (check_acw(B, M, N, w, dist, q, lambda, T) || !img || (npix > 0 && !pix)) return -1;
+    int64_t total = (int64_t)B * M * N;
+    for (int64_t k = 0; k < npix; ++k)
+        if (pix[k] < 0 || pix[k] >= total) return -1;
+    set_threads(nthreads);
+    int n = w * w;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < npix; ++k)
+        acwddf_one(img, M, N, w, dist, q, lambda, T, pix[k], out ? out + 3 * k : NULL,
+                   idx ? idx + k : NULL, S ? S + k : NULL, diag ? diag + 5 * n * k : NULL);
     return 0;
 }

@@ -49,6 +49,50 @@ PAIR_SLOTS = {
 L2_SLOTS = 6 + TRANS         # 3 sub, 3 fma/mul, sqrt
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-slots/s
 
+# ------------------------------------------------------------------ HBM traffic
+# Bytes the DDF 3x3 uint8 forward kernel moves to and from HBM per 1024 x 1024
+# launch: rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch, one
+# pass each, from `bench.py --steps 3 --warmup 1 --no-forms --no-cpu
+# --step-forms loop --copy-probe-mib 256`), keyed by pair term and extended
+# tile.  Each counter is scaled by what it reads for the 256 MiB float32 copy
+# of the same run (262144 KiB read, 262144 KiB written): FETCH_SIZE read
+# 131085.2 KiB (x 1.99980), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold
+# for the kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources
+# bench.py reports traffic as null.
+TRAFFIC_FETCH_SCALE = 262144.0 / 131085.2
+TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
+TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("exact", 32, 32): (4095.8, 6144.0), ("exact", 64, 16): (2912.0, 5056.0),
+    ("exact", 32, 16): (4377.4, 6144.0), ("exact", 64, 8): (3201.1, 5056.0),
+    ("minimax", 32, 32): (4108.8, 6144.0), ("minimax", 64, 16): (2925.0, 5056.0),
+    ("minimax", 32, 16): (4395.4, 6144.0), ("minimax", 64, 8): (3216.5, 5056.0),
+    ("rgb", 32, 32): (4084.2, 6144.0), ("rgb", 64, 16): (2900.5, 5056.0),
+    ("rgb", 32, 16): (4372.4, 6144.0), ("rgb", 64, 8): (3192.0, 5056.0),
+}
+TRAFFIC_SOURCES = ("fwd.hip", "fwd_tile.h", "aggregates.h", "pair_terms.h", "atan_poly.h",
+                   "odf_internal.h")
+TRAFFIC_SRC_SHA256 = "b243373e6679014362ae13568d7cfce5c16075ca722c761f02af7ea41d171568"
+
+
+def forward_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1009_0958_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(dist, ext_tile):
+    """Calibrated HBM bytes per 1024 x 1024 launch, or None when the kernel
+    sources differ from the ones the counters were taken on."""
+    key = (dist, int(ext_tile[0]), int(ext_tile[1]))
+    if forward_sources_sha256() != TRAFFIC_SRC_SHA256 or key not in TRAFFIC_KIB:
+        return None
+    fetch, write = TRAFFIC_KIB[key]
+    return {"fetch": round(fetch * 1024 * TRAFFIC_FETCH_SCALE),
+            "write": round(write * 1024 * TRAFFIC_WRITE_SCALE)}
+
 
 def slots_per_pixel(window, kind, p, dist):
     h = window // 2
@@ -209,6 +253,11 @@ def main():
         "traffic": None,
         "hbm_bytes_per_pixel": 7, "hbm_frac": round(7 * M * N / (dms * 1e-3) / 8e12, 5),
     }
+    tb = traffic_bytes(dd, tuned["ddf3_%s" % dd]["ext_tile"])
+    if tb is not None:
+        roofline["traffic"] = tb["fetch"] + tb["write"]
+        roofline["traffic_fetch_write"] = [tb["fetch"], tb["write"]]
+        roofline["traffic_over_algorithmic"] = round((tb["fetch"] + tb["write"]) / (7 * M * N), 3)
 
     forms = {}
     if not args.no_forms:

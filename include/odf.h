@@ -46,7 +46,10 @@ typedef enum {
  * Omega_u = A_u^(1-p) * D_u^p, A_u the angle sum of eq. (2) and D_u the sum of
  * L2 distances of eq. (1); p = 1/2 orders members as the product of eq. (3),
  * p = 0 is BVDF and p = 1 the vector median of eq. (1). */
-typedef enum { ODF_BVDF = 0, ODF_DDF = 1 } odf_kind;
+typedef enum { ODF_BVDF = 0, ODF_DDF = 1, ODF_ACWDDF = 2 } odf_kind;
+/* ODF_ACWDDF (the adaptive centre-weighted DDF of Section III, Experiment 2)
+ * is computed by odf_acwddf_u8 / odf_acwddf_f32 and is accepted as a kind by
+ * the tuning calls only; the other entry points take ODF_BVDF or ODF_DDF. */
 
 /* Angular pair term.  EXACT: the angle of eq. (2).  MINIMAX: Section 2.1
  * (Method 1), the degree-q minimax polynomials of Table 1 with the
@@ -89,6 +92,36 @@ int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind,
  */
 int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, float p,
                    int dist, int q, float* out, uint8_t* idx, void* stream);
+
+/*
+ * Adaptive centre-weighted DDF, ACWDDF (Section III, Experiment 2: the
+ * switching rule and the centre weights of eq. 9), uint8 images.  Per window,
+ * with d the centre member (n-1)/2:
+ *   - the DDF selection of eq. (3): the member minimising A_u * D_u;
+ *   - for k = lambda, lambda+1, lambda+2 the centre-weighted DDF selection
+ *     y_k: the member minimising (sum_v w_v(k) A(x_u,x_v)) *
+ *     (sum_v w_v(k) L2(x_u,x_v)), w_d(k) = n - 2k + 2 and w_v(k) = 1 for
+ *     v != d (the weights of eq. 9 applied to both sums of eq. 3);
+ *   - S = sum_k A(y_k, x_d) * L2(y_k, x_d); the output is the DDF selection
+ *     when S > T and the centre member otherwise.
+ * A is the pair term of `dist` (exact angle, minimax of Table 1, or eq. 10
+ * applied to the chromaticity distance), L2 eq. (1) with p = 2.  Ties in each
+ * selection go to the lowest index.
+ *   img, out, idx  as for odf_filter_u8 (idx = the output member: the DDF
+ *          selection or (n-1)/2).
+ *   lambda in [1, (n+1)/2 - 2] (so every level k lies in [1, (n+1)/2]); the
+ *          paper's setting is lambda = 2, T = 10.8 (angles in radians, L2 in
+ *          the units of the image values).
+ *   T      any value but NaN (+inf keeps every centre; below 0 gives the DDF).
+ * Errors: as odf_filter_u8, plus ODF_EINVAL for lambda out of range or T NaN.
+ */
+int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
+                  int lambda, float T, uint8_t* out, uint8_t* idx, void* stream);
+
+/* ACWDDF on float32 images (same contract; ODF_MINIMAX and ODF_RGB need
+ * non-negative inputs). */
+int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, int q,
+                   int lambda, float T, float* out, uint8_t* idx, void* stream);
 
 /*
  * Aggregates of every window (test and inspection hook, not the fast path).
@@ -202,8 +235,9 @@ int odf_plan_destroy(odf_plan* plan);
  * The forward kernels run one thread per pixel of an extended tile
  * (output tile plus halo).  Tile shapes are numbered 0..3; odf_tile_config
  * gives the extended width and height of one.  The process-wide table picks a
- * shape per (window, kind, dist, input type); defaults are 32 x 32 (32 x 16
- * for 5x5 DDF). */
+ * shape per (window, kind, dist, input type), kind ODF_BVDF, ODF_DDF or
+ * ODF_ACWDDF; defaults are 32 x 32, and 32 x 16 for 5x5 ACWDDF, which offers
+ * only the 512-thread shapes 2 and 3. */
 int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */

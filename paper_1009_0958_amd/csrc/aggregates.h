@@ -44,13 +44,16 @@ __device__ __forceinline__ void row_sums(const float (&row)[4 * (W / 2) + 1], fl
 
 // Aggregates of the own member p over every window containing it, for the
 // angular term (L2PASS = false) or the L2 term of eq. (1) (L2PASS = true).
-// agg[u] is the aggregate of p in the window c = p - offset(u).
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS>
-__device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_dir,
-                                                  const float4* __restrict__ s_raw,
-                                                  float* __restrict__ s_plane, int ey, int ex,
-                                                  int tid, const float4& mdir, const float4& mraw,
-                                                  const MinimaxCoef& cf, float (&agg)[W * W]) {
+// agg[u] is the aggregate of p in the window c = p - offset(u).  CEN: also
+// cen[u] = the pair term of p and that window's centre c (taken from the
+// offset grid, so no extra pair is evaluated).
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS, bool CEN>
+__device__ __forceinline__ void member_aggregates_c(const float4* __restrict__ s_dir,
+                                                    const float4* __restrict__ s_raw,
+                                                    float* __restrict__ s_plane, int ey, int ex,
+                                                    int tid, const float4& mdir,
+                                                    const float4& mraw, const MinimaxCoef& cf,
+                                                    float (&agg)[W * W], float (&cen)[W * W]) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, G = Gm::G, NT = Gm::NT;
 
@@ -85,6 +88,19 @@ __device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_d
             if (py >= 0 && px >= 0 && px < EXT_W)
                 up[dx + 2 * H] = s_plane[(2 * H - dx) * NT + py * EXT_W + px];
         }
+        if constexpr (CEN) {
+            if (g <= H) {
+                // offset (g, dx) from p is the centre of window (-g, -dx),
+                // offset (-g, dx) the centre of window (g, -dx)
+#pragma unroll
+                for (int dx = -H; dx <= H; ++dx) {
+                    const float vo = g > 0 || dx > 0 ? own[dx + 2 * H]
+                                                     : (dx < 0 ? up[dx + 2 * H] : self);
+                    cen[(H - g) * W + (H - dx)] = vo;
+                    if (g > 0) cen[(H + g) * W + (H - dx)] = up[dx + 2 * H];
+                }
+            }
+        }
         if (g == 0) {
             float row[G];
 #pragma unroll
@@ -109,6 +125,17 @@ __device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_d
     }
 }
 
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS>
+__device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_dir,
+                                                  const float4* __restrict__ s_raw,
+                                                  float* __restrict__ s_plane, int ey, int ex,
+                                                  int tid, const float4& mdir, const float4& mraw,
+                                                  const MinimaxCoef& cf, float (&agg)[W * W]) {
+    float unused[W * W];
+    member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, L2PASS, false>(
+        s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, cf, agg, unused);
+}
+
 // Objective of one member: BVDF (eq. 2) A; DDF A^(1-p) D^p (p = 1/2 orders as
 // the product of eq. 3).  objective_value is the objective itself;
 // ObjectiveKey gives, per launch, a monotone image of it used for comparisons:
@@ -125,6 +152,7 @@ enum ObjMode { kObjA = 0, kObjD = 1, kObjProd = 2, kObjQuarter = 3, kObjLog = 4 
 
 template <int KIND>
 __device__ __forceinline__ int objective_mode(float p) {
+    if (KIND == kACW) return kObjProd;  // eq. (3)
     if (KIND == kBVDF || p == 0.0f) return kObjA;
     if (p == 1.0f) return kObjD;
     if (p == 0.5f) return kObjProd;

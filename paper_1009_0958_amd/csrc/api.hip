@@ -77,6 +77,12 @@ odf::MinimaxCoef odf::minimax_coef(int q) {
     return c;
 }
 
+void odf::set_acw_params(int window, int lambda, float T, FwdParams& prm) {
+    const int n = window * window;
+    for (int j = 0; j < 3; ++j) prm.acw_wm1[j] = (float)(n - 2 * (lambda + j) + 1);
+    prm.acw_T = T;
+}
+
 namespace {
 
 odf::FwdParams make_params(const void* img, int B, int M, int N, float p, int dist, int q) {
@@ -111,11 +117,47 @@ int filter_any(const void* img, bool u8, int B, int M, int N, int window, int ki
     return ODF_OK;
 }
 
+int acwddf_any(const void* img, bool u8, int B, int M, int N, int window, int dist, int q,
+               int lambda, float T, void* out, uint8_t* idx, void* stream) {
+    int rc = check_common(img, B, M, N, window, ODF_DDF, 0.5f, dist, q);
+    if (rc) return rc;
+    if (!out) return fail(ODF_EINVAL, "out is NULL");
+    const int dmax = (window * window + 1) / 2 - 2;
+    if (lambda < 1 || lambda > dmax)
+        return fail(ODF_EINVAL, "lambda %d out of range [1, %d]", lambda, dmax);
+    if (T != T) return fail(ODF_EINVAL, "T is NaN");
+    const size_t npix = (size_t)B * M * N;
+    const size_t esz = u8 ? 1 : 4;
+    if (overlaps(img, npix * 3 * esz, out, npix * 3 * esz))
+        return fail(ODF_EINVAL, "out overlaps img (the filter cannot run in place)");
+    if (idx && (overlaps(img, npix * 3 * esz, idx, npix) || overlaps(out, npix * 3 * esz, idx, npix)))
+        return fail(ODF_EINVAL, "idx overlaps img or out");
+    odf::FwdParams prm = make_params(img, B, M, N, 0.5f, dist, q);
+    prm.out = out;
+    prm.idx = idx;
+    odf::set_acw_params(window, lambda, T, prm);
+    const int cfg = odf::tuned_config(window, ODF_ACWDDF, dist, u8);
+    hipError_t e = odf::launch_forward(window, ODF_ACWDDF, dist, u8, false, cfg, prm,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "ACWDDF launch");
+    return ODF_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int odf_version(void) { return (0 << 16) | 1; }
+int odf_version(void) { return (0 << 16) | 2; }
+
+int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
+                  int lambda, float T, uint8_t* out, uint8_t* idx, void* stream) {
+    return acwddf_any(img, true, B, M, N, window, dist, q, lambda, T, out, idx, stream);
+}
+
+int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, int q,
+                   int lambda, float T, float* out, uint8_t* idx, void* stream) {
+    return acwddf_any(img, false, B, M, N, window, dist, q, lambda, T, out, idx, stream);
+}
 
 const char* odf_last_error(void) { return g_err; }
 

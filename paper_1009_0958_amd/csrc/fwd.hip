@@ -18,16 +18,16 @@ constexpr int kNumTileConfigs = 4;
 constexpr int kTileW[kNumTileConfigs] = {32, 64, 32, 64};
 constexpr int kTileH[kNumTileConfigs] = {32, 16, 16, 8};
 
+// 5x5 ACWDDF keeps four register sets of n values per thread (aggregates
+// and centre terms of both passes): 512-thread tiles only.
 bool tile_config_valid(int window, int kind, int cfg) {
-    (void)window;
-    (void)kind;
-    return cfg >= 0 && cfg < kNumTileConfigs;
+    if (cfg < 0 || cfg >= kNumTileConfigs) return false;
+    if (window == 5 && kind == kACW) return kTileW[cfg] * kTileH[cfg] <= 512;
+    return true;
 }
 
 int tile_config_default(int window, int kind) {
-    (void)window;
-    (void)kind;
-    return 0;
+    return window == 5 && kind == kACW ? 2 : 0;
 }
 
 void tile_config_shape(int cfg, int* ext_w, int* ext_h) {
@@ -49,6 +49,12 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
     if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
         (void)cfg;
         return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+    } else if constexpr (W == 5 && KIND == kACW) {
+        switch (cfg) {
+        case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+        case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+        default: return hipErrorInvalidValue;
+        }
     } else {
         switch (cfg) {
         case 0: return launch_shape<W, KIND, DIST, U8, AGG, 32, 32>(prm, stream);
@@ -61,10 +67,16 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
 
 template <int W, int KIND, int DIST>
 static hipError_t launch_wkd(bool u8, bool agg, int cfg, const FwdParams& prm, hipStream_t s) {
-    if (u8) return agg ? launch_t<W, KIND, DIST, true, true>(cfg, prm, s)
-                       : launch_t<W, KIND, DIST, true, false>(cfg, prm, s);
-    return agg ? launch_t<W, KIND, DIST, false, true>(cfg, prm, s)
-               : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
+    if constexpr (KIND == kACW) {  // no aggregate-inspection form
+        if (agg) return hipErrorInvalidValue;
+        return u8 ? launch_t<W, KIND, DIST, true, false>(cfg, prm, s)
+                  : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
+    } else {
+        if (u8) return agg ? launch_t<W, KIND, DIST, true, true>(cfg, prm, s)
+                           : launch_t<W, KIND, DIST, true, false>(cfg, prm, s);
+        return agg ? launch_t<W, KIND, DIST, false, true>(cfg, prm, s)
+                   : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
+    }
 }
 
 template <int W, int KIND>
@@ -80,8 +92,9 @@ static hipError_t launch_wk(int dist, bool u8, bool agg, int cfg, const FwdParam
 template <int W>
 static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const FwdParams& prm,
                            hipStream_t s) {
-    return kind == kBVDF ? launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s)
-                         : launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
+    if (kind == kBVDF) return launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s);
+    if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
+    return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
 }
 
 hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates, int cfg,

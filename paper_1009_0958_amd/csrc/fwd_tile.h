@@ -20,13 +20,14 @@ namespace odf {
 // LDS of one forward tile.  STAGE: the 5x5 DDF path parks the angle part of
 // every (window, member) objective in LDS during the L2 pass instead of
 // keeping 25 aggregates live in registers, which lets it use 1024-thread tiles.
-template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE>
+// NKEY: argmin keys per window (4 for ACWDDF: eq. 3 and three levels of eq. 9).
+template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     float4 dir[Gm::NT];
     float4 raw[Gm::NT];
     float plane[Gm::G * Gm::NT];
-    unsigned long long key[AGG ? 1 : Gm::TH * Gm::TW];
+    unsigned long long key[AGG ? 1 : NKEY * Gm::TH * Gm::TW];
     float stage[STAGE ? Gm::NW * Gm::TH * Gm::TW : 1];
 };
 
@@ -36,7 +37,8 @@ constexpr bool stage_angle_part() {
 }
 
 template <int W, int KIND, int EXT_W, int EXT_H, bool AGG>
-using FwdSharedFor = FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>()>;
+using FwdSharedFor =
+    FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>(), KIND == kACW ? 4 : 1>;
 
 // Filter one output tile whose top-left output pixel is (ty0, tx0) of image b.
 // Every thread of the workgroup must call it (it synchronises); tid is the
@@ -72,16 +74,18 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
         s_dir[tid] = d;
         s_raw[tid] = r;
     }
+    constexpr int NKEY = KIND == kACW ? 4 : 1;
     if (!AGG)
-        for (int i = tid; i < TH * TW; i += NT) s_key[i] = ~0ull;
+        for (int i = tid; i < NKEY * TH * TW; i += NT) s_key[i] = ~0ull;
     __syncthreads();
     const float4 mdir = s_dir[tid];
     const float4 mraw = s_raw[tid];
 
-    // a2 + a3
+    // a2 + a3 (ACWDDF also keeps each member's terms with the window centres)
     float A[NW], D[NW];
-    member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex, tid,
-                                                             mdir, mraw, prm.coef, A);
+    float cA[NW], cD[NW];
+    member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW>(
+        s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
     if constexpr (stage_angle_part<W, KIND, AGG>()) {
         // angle part of each objective -> LDS, then the L2 pass, then the keys
         const int mode = objective_mode<KIND>(prm.p);
@@ -114,9 +118,9 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             atomicMin(&s_key[cy * TW + cx], key);
         }
     } else {
-    if (KIND == kDDF)
-        member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey, ex,
-                                                                tid, mdir, mraw, prm.coef, D);
+    if (KIND != kBVDF)
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, KIND == kACW>(
+            s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
     else
 #pragma unroll
         for (int u = 0; u < NW; ++u) D[u] = 0.0f;
@@ -133,6 +137,27 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             prm.dbg_A[o] = A[u];
             if (prm.dbg_D) prm.dbg_D[o] = D[u];
             if (prm.dbg_O) prm.dbg_O[o] = objective_value<KIND>(A[u], D[u], prm.p);
+        }
+    } else if constexpr (KIND == kACW) {
+        // eq. (3) and the centre-weighted objectives of eq. (9): the weight
+        // w_d(k) of the centre adds (w_d(k) - 1) times the centre term
+        constexpr int TT = TH * TW;
+        const float w1 = prm.acw_wm1[0], w2 = prm.acw_wm1[1], w3 = prm.acw_wm1[2];
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int cy = ey - u / W;
+            const int cx = ex - u % W;
+            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+            if (ty0 + cy >= M || tx0 + cx >= N) continue;
+            const int ci = cy * TW + cx;
+            const float o0 = A[u] * D[u];
+            const float o1 = fmaf(w1, cA[u], A[u]) * fmaf(w1, cD[u], D[u]);
+            const float o2 = fmaf(w2, cA[u], A[u]) * fmaf(w2, cD[u], D[u]);
+            const float o3 = fmaf(w3, cA[u], A[u]) * fmaf(w3, cD[u], D[u]);
+            atomicMin(&s_key[ci], ((unsigned long long)order_key(o0) << 32) | (unsigned)u);
+            atomicMin(&s_key[TT + ci], ((unsigned long long)order_key(o1) << 32) | (unsigned)u);
+            atomicMin(&s_key[2 * TT + ci], ((unsigned long long)order_key(o2) << 32) | (unsigned)u);
+            atomicMin(&s_key[3 * TT + ci], ((unsigned long long)order_key(o3) << 32) | (unsigned)u);
         }
     } else {
         float om[NW];
@@ -157,7 +182,22 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
         const int cy = i / TW, cx = i - (i / TW) * TW;
         const int gy = ty0 + cy, gx = tx0 + cx;
         if (gy >= M || gx >= N) continue;
-        const int u = min((int)(s_key[i] & 0xffu), NW - 1);
+        int u = min((int)(s_key[i] & 0xffu), NW - 1);
+        if constexpr (KIND == kACW) {
+            // switch: S = sum over the three levels of A(y_k, x_d) L2(y_k, x_d);
+            // the eq. (3) selection if S > T, else the centre
+            const int c = (cy + H) * EXT_W + cx + H;
+            const float4 cd = s_dir[c], cr = s_raw[c];
+            float S = 0.0f;
+#pragma unroll
+            for (int j = 1; j <= 3; ++j) {
+                const int uj = min((int)(s_key[j * TH * TW + i] & 0xffu), NW - 1);
+                const int m = (cy + uj / W) * EXT_W + cx + uj % W;
+                S += pair_term<KIND, DIST, U8>(s_dir[m], s_raw[m], cd, cr, prm.coef) *
+                     l2_term(s_raw[m], cr);
+            }
+            if (!(S > prm.acw_T)) u = (NW - 1) / 2;
+        }
         const float4 r = s_raw[(cy + u / W) * EXT_W + cx + u % W];
         const size_t pix = ((size_t)b * M + gy) * N + gx;
         if (U8) {

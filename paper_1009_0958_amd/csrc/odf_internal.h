@@ -18,6 +18,10 @@ struct FwdParams {
     int B, M, N;
     float p;              // DDF weight
     MinimaxCoef coef;     // Table 1 row for the chosen q
+    // ACWDDF: extra weight of the centre term, w_d(k) - 1 = n - 2k + 1, at the
+    // levels k = lambda, lambda + 1, lambda + 2, and the switching threshold T
+    float acw_wm1[3];
+    float acw_T;
 };
 
 // Launch the forward filter on `stream` with extended-tile shape `cfg`.
@@ -33,6 +37,9 @@ void set_tuned_config(int window, int kind, int dist, bool u8, int cfg);
 
 // Table 1 coefficients for degree q (zeros outside 2..4).
 MinimaxCoef minimax_coef(int q);
+
+// ACWDDF fields of prm for window w, level lambda and threshold T.
+void set_acw_params(int window, int lambda, float T, FwdParams& prm);
 
 // Record the message returned by odf_last_error() on this thread; returns code.
 int set_error(int code, const char* fmt, ...);

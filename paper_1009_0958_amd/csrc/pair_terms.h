@@ -24,7 +24,9 @@
 
 namespace odf {
 
-enum Kind { kBVDF = 0, kDDF = 1 };
+// kACW: the adaptive centre-weighted DDF (Section III, Experiment 2), whose
+// pair terms are the DDF's.
+enum Kind { kBVDF = 0, kDDF = 1, kACW = 2 };
 enum Dist { kExact = 0, kMinimax = 1, kRgb = 2 };
 
 // eq. (10): A ~= 1.436437 B + 0.027664
@@ -147,7 +149,7 @@ __device__ __forceinline__ float chroma_term(const float4& a, const float4& ra, 
     float n2 = diff_of_products(a.z, b.w, b.z, a.w);
     float Nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
     float B = sqrt_raw(Nn) * (ra.w * rb.w);
-    if (KIND == kDDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
+    if (KIND != kBVDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
     return B;
 }
 

@@ -18,15 +18,15 @@ namespace odf {
 
 namespace {
 
-// [window 3/5][kind][dist][u8]
-std::atomic<int> g_table[2][2][3][2];
+// [window 3/5][kind BVDF/DDF/ACWDDF][dist][u8]
+std::atomic<int> g_table[2][3][3][2];
 std::atomic<bool> g_table_init{false};
 
 void ensure_init() {
     bool expect = false;
     if (!g_table_init.load()) {
         for (int w = 0; w < 2; ++w)
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < 3; ++k)
                 for (int d = 0; d < 3; ++d)
                     for (int u = 0; u < 2; ++u)
                         g_table[w][k][d][u].store(tile_config_default(w ? 5 : 3, k));
@@ -69,14 +69,14 @@ int odf_tile_config(int config, int* ext_w, int* ext_h) {
 }
 
 int odf_tune_get(int window, int kind, int dist, int is_u8) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || dist < 0 ||
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) || dist < 0 ||
         dist > 2)
         return ODF_EINVAL;
     return odf::tuned_config(window, kind, dist, is_u8 != 0);
 }
 
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || dist < 0 ||
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) || dist < 0 ||
         dist > 2 || !odf::tile_config_valid(window, kind, config))
         return ODF_EINVAL;
     odf::set_tuned_config(window, kind, dist, is_u8 != 0, config);
@@ -85,7 +85,7 @@ int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
 
 int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
                  const char* cache_path, float* times_ms, void* stream) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || dist < 0 ||
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) || dist < 0 ||
         dist > 2 || M < 1 || N < 1 || reps < 1 || (long long)M * N >= (1ll << 28))
         return odf::set_error(ODF_EINVAL, "autotune: arguments out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -122,8 +122,9 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
         odf::FwdParams prm{};
         prm.img = img; prm.out = out; prm.idx = idx;
         prm.B = 1; prm.M = M; prm.N = N;
-        prm.p = kind == ODF_DDF ? 0.25f : 0.0f;
+        prm.p = kind == ODF_DDF ? 0.25f : (kind == ODF_ACWDDF ? 0.5f : 0.0f);
         if (dist == ODF_MINIMAX) prm.coef = odf::minimax_coef(4);  // timing does not depend on q
+        if (kind == ODF_ACWDDF) odf::set_acw_params(window, 2, 10.8f, prm);
         for (int w = 0; w < 2; ++w)
             if (odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s) != hipSuccess) {
                 rc = ODF_EHIP;

@@ -17,11 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libodf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "odf.h")
 
-BVDF, DDF = 0, 1
+BVDF, DDF, ACWDDF = 0, 1, 2
 EXACT, MINIMAX, RGB = 0, 1, 2
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
 
-_KIND = {"bvdf": BVDF, "ddf": DDF}
+_KIND = {"bvdf": BVDF, "ddf": DDF, "acwddf": ACWDDF}
 _DIST = {"exact": EXACT, "minimax": MINIMAX, "rgb": RGB}
 
 _lib = None
@@ -48,6 +48,8 @@ def lib():
         L.odf_last_error.restype = ctypes.c_char_p
         L.odf_filter_u8.argtypes = [P, I, I, I, I, I, F, I, I, P, P, P]
         L.odf_filter_f32.argtypes = [P, I, I, I, I, I, F, I, I, P, P, P]
+        L.odf_acwddf_u8.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
+        L.odf_acwddf_f32.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
         L.odf_aggregates.argtypes = [P, I, I, I, I, I, I, F, I, I, P, P, P, P]
         L.odf_backward_hard_f32.argtypes = [P, P, I, I, I, I, P, P]
         L.odf_softmin_fwd_f32.argtypes = [P, I, I, I, I, I, F, F, P, P]
@@ -125,6 +127,29 @@ def filter(img, window=3, kind=BVDF, p=0.5, dist=EXACT, q=4, out=None, idx=None,
         raise ValueError("img must be uint8 or float32")
     _check(fn(_ptr(x), B, M, N, window, _kind(kind), float(p), _dist(dist), q, _ptr(out),
               _ptr(idx), _stream(x.device)))
+    if squeeze:
+        out = out[0]
+        idx = None if idx is None else idx[0]
+    return out, idx
+
+
+def acwddf(img, window=3, dist=EXACT, q=4, lam=2, T=10.8, out=None, idx=None,
+           return_idx=True):
+    """Adaptive centre-weighted DDF (Section III, Experiment 2).  Returns
+    (out, idx): idx is the DDF selection where the switching statistic exceeds
+    T and the centre (n - 1) / 2 elsewhere."""
+    x, squeeze = _as_batch(img)
+    _check_tensor(x, "img")
+    B, M, N, _ = x.shape
+    if x.dtype not in (torch.uint8, torch.float32):
+        raise ValueError("img must be uint8 or float32")
+    if out is None:
+        out = torch.empty_like(x)
+    if idx is None and return_idx:
+        idx = torch.empty((B, M, N), dtype=torch.uint8, device=x.device)
+    fn = lib().odf_acwddf_u8 if x.dtype == torch.uint8 else lib().odf_acwddf_f32
+    _check(fn(_ptr(x), B, M, N, window, _dist(dist), q, int(lam), float(T), _ptr(out), _ptr(idx),
+              _stream(x.device)))
     if squeeze:
         out = out[0]
         idx = None if idx is None else idx[0]

@@ -57,3 +57,55 @@ def check_aggregates(gpu, ref, rtol=AGG_RTOL, name="A"):
                                 ref.reshape(-1)[k]))
     nz = np.abs(ref) > 0
     return float((err[nz] / np.abs(ref[nz])).max()) if nz.any() else 0.0
+
+
+SWITCH_BAND = 1e-5
+
+
+def window_colours(img, window):
+    """Member colours of every window, (B*M*N, n, 3) (replicated border)."""
+    x = img if img.ndim == 4 else img[None]
+    B, M, N, _ = x.shape
+    n = window * window
+    cols = np.empty((B, M, N, n, 3), x.dtype)
+    for u in range(n):
+        cols[:, :, :, u] = source_pixels(x, np.full((B, M, N), u, np.uint8), window)
+    return cols.reshape(B * M * N, n, 3)
+
+
+def acwddf_ambiguous(colours, S, diag, n, T, rel=NEAR_TIE, band=SWITCH_BAND):
+    """Pixels whose ACWDDF result FP32 arithmetic may legitimately change: a
+    nonzero switching statistic within `band` (relative) of T, or, in any of the four
+    selections (eq. 3 and the three centre-weighted levels), a member of a
+    different colour than the oracle's choice within `rel` of the minimum.
+    Members of equal colour tie exactly on both sides and resolve alike."""
+    S = S.reshape(-1)
+    D = diag.reshape(S.shape[0], 5 * n)
+    # S = 0 exactly on both sides when every level selects the centre's colour
+    amb = (S != 0) & (np.abs(S - T) <= band * max(abs(T), 1.0)) if np.isfinite(T) else \
+        np.zeros(S.shape, bool)
+    rows = np.arange(S.shape[0])
+    for j in range(4):
+        Oj = D[:, j * n:(j + 1) * n]
+        first = np.argmin(Oj, axis=1)
+        omin = Oj[rows, first]
+        near = (Oj <= omin[:, None] * (1 + rel)) | ((omin[:, None] == 0) & (Oj == 0))
+        other = np.any(colours != colours[rows, first][:, None, :], axis=2)
+        amb |= np.any(near & other, axis=1)
+    return amb
+
+
+def check_acwddf(idx_gpu, idx_oracle, colours, S, diag, n, T, max_ambiguous=0.01):
+    """ACWDDF selection contract; returns (n_mismatch, n_ambiguous, n_total)."""
+    g = idx_gpu.reshape(-1)
+    o = idx_oracle.reshape(-1)
+    amb = acwddf_ambiguous(colours, S, diag, n, T)
+    mism = g != o
+    bad = mism & ~amb
+    if bad.any():
+        k = np.flatnonzero(bad)[:5]
+        raise AssertionError("%d of %d ACWDDF selections differ outside the ambiguous set, e.g. "
+                             "pixels %s: gpu %s oracle %s S %s" % (bad.sum(), g.size, k, g[k], o[k],
+                                                                   S.reshape(-1)[k]))
+    assert amb.mean() <= max_ambiguous, "ambiguous fraction %.4f" % amb.mean()
+    return int(mism.sum()), int(amb.sum()), g.size

@@ -110,3 +110,32 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
+
+
+@pytest.mark.parametrize("args,code,text", [
+    ((None, 1, 8, 8, 3, 0, 4, 2, 10.8, FAKE2), odf.EINVAL, "img"),
+    ((FAKE, 1, 8, 8, 3, 0, 4, 2, 10.8, None), odf.EINVAL, "out"),
+    ((FAKE, 1, 8, 8, 7, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 3, 3, 4, 2, 10.8, FAKE2), odf.EINVAL, "dist"),
+    ((FAKE, 1, 8, 8, 3, 1, 7, 2, 10.8, FAKE2), odf.EINVAL, "q"),
+    ((FAKE, 1, 8, 8, 3, 0, 4, 0, 10.8, FAKE2), odf.EINVAL, "lambda"),
+    ((FAKE, 1, 8, 8, 3, 0, 4, 4, 10.8, FAKE2), odf.EINVAL, "lambda"),
+    ((FAKE, 1, 8, 8, 5, 0, 4, 12, 10.8, FAKE2), odf.EINVAL, "lambda"),
+    ((FAKE, 1, 8, 8, 3, 0, 4, 2, float("nan"), FAKE2), odf.EINVAL, "NaN"),
+    ((FAKE, 1, 8, 8, 3, 0, 4, 2, 10.8, FAKE), odf.EINVAL, "overlaps"),
+])
+def test_acwddf_rejects(args, code, text):
+    L = odf.lib()
+    assert L.odf_acwddf_u8(*args, None, None) == code
+    assert text in odf.last_error()
+    assert L.odf_acwddf_f32(*args, None, None) == code
+
+
+def test_acwddf_tuning_table():
+    L = odf._batch_lib()
+    assert L.odf_tune_get(3, odf.ACWDDF, 0, 1) == 0
+    assert L.odf_tune_get(5, odf.ACWDDF, 0, 1) == 2
+    assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 0) == odf.EINVAL  # 1024-thread shape not offered
+    assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 3) == odf.OK
+    assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 2) == odf.OK
+    assert L.odf_tune_get(3, 3, 0, 1) == odf.EINVAL

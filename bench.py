@@ -100,9 +100,14 @@ def slots_per_pixel(window, kind, p, dist):
     pairs = 2 * h * (4 * h + 1) + 2 * h  # unique unordered pairs per pixel: 12 or 40
     box = window * (window - 1) * (3 * window - 1)  # separable box-sum adds per plane
     s = pairs * PAIR_SLOTS[dist] + box + 2 * (n - 1) + 10  # + argmin + prep
-    if dist == "rgb" and kind == "ddf":
+    if dist == "rgb" and kind in ("ddf", "acw"):
         s += pairs
-    if kind == "ddf":
+    if kind == "acw":
+        # DDF aggregates and the eq. (3) product, three centre-weighted
+        # objectives per member (2 fma + 1 mul each), and per output pixel the
+        # three (pair term x L2) products of the switching statistic
+        s += pairs * L2_SLOTS + box + n + 9 * n + 3 * (PAIR_SLOTS[dist] + L2_SLOTS + 2)
+    elif kind == "ddf":
         s += pairs * L2_SLOTS + box
         if p == 0.5:
             s += n  # A*D orders like A^(1/2) D^(1/2)
@@ -260,8 +265,10 @@ def main():
         roofline["traffic_over_algorithmic"] = round((tb["fetch"] + tb["write"]) / (7 * M * N), 3)
 
     forms = {}
+    acw_idx = {}
     if not args.no_forms:
         for name, fn in (("large_frames", lambda: large_frame_forms(torch, odf, synth, dev, DIST)),
+                         ("acwddf", lambda: acwddf_forms(torch, odf, synth, dev, DIST, x, acw_idx)),
                          ("batched", lambda: batched_form(torch, odf, synth, dev)),
                          ("differentiable", lambda: differentiable_forms(torch, odf, synth, dev))):
             try:
@@ -272,7 +279,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(img_np, outs, variants, args.cpu_seconds)
+        cpu = cpu_baseline(img_np, outs, variants, args.cpu_seconds, acw_idx)
 
     line = {
         "metric": "Mpixels/s BVDF/DDF 3x3,5x5 fwd & fwd+bwd at 1 GPU; % roofline; mismatch rate",
@@ -318,6 +325,34 @@ def large_frame_forms(torch, odf, synth, dev, DIST):
                     "valu_frac": round(slots_per_pixel(w, kind, p, d) * npx / (ms * 1e-3)
                                        / PEAK_SLOTS, 4)}
         del big, bo, bi
+    return forms
+
+
+def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
+    """ACWDDF (lambda = 2, T = 10.8) on the 1024 x 1024 image (3x3 and 5x5)
+    and on a 7680 x 4320 frame (3x3), each pair term, tuned tile shapes; the
+    1024 x 1024 3x3 index maps are kept for the oracle's mismatch count."""
+    forms = {}
+    big = torch.from_numpy(synth.image_corr(4320, 7680, 0.15, key=500)).to(dev)
+    for w in (3, 5):
+        for d in ("exact", "minimax", "rgb"):
+            best, _ = odf.autotune(w, odf.ACWDDF, DIST[d], True, 1024, 1024, 5)
+            cases = [("1024x1024", x1k)] + ([("7680x4320", big)] if w == 3 else [])
+            for tag, img in cases:
+                M, N = img.shape[:2]
+                o = torch.empty_like(img)
+                i = torch.empty((M, N), dtype=torch.uint8, device=dev)
+                ms = time_launches(torch, lambda: odf.acwddf(img, w, DIST[d], 4, 2, 10.8, out=o,
+                                                             idx=i), 10, warm=2)
+                forms["acwddf%d_%s_%s" % (w, d, tag)] = {
+                    "mpix_s": round(M * N / (ms * 1e3), 1), "ms": round(ms, 4),
+                    "ext_tile": odf.tile_config(best),
+                    "valu_frac": round(slots_per_pixel(w, "acw", 0.5, d) * M * N / (ms * 1e-3)
+                                       / PEAK_SLOTS, 4),
+                    "switched_to_ddf": round(float((i != (w * w - 1) // 2).float().mean()), 4)}
+                if tag == "1024x1024" and w == 3:
+                    acw_idx[d] = i.cpu().numpy()
+    del big
     return forms
 
 
@@ -446,7 +481,34 @@ def differentiable_forms(torch, odf, synth, dev):
     return forms
 
 
-def cpu_baseline(img_np, outs, variants, seconds):
+def acwddf_mismatch(oracle, img_np, acw_idx, codes, k=20000):
+    """ACWDDF 3x3 index mismatches against the oracle on k seeded pixels, and
+    whether each one is undetermined at binary32 precision (S within 1e-5 of
+    T, or a near-tie within 1e-6 between members of different colours in one
+    of the four selections)."""
+    M, N = img_np.shape[:2]
+    pix = np.sort(np.random.default_rng(1010).choice(M * N, k, replace=False))
+    rr, cc = pix // N, pix % N
+    cols = np.stack([img_np[np.clip(rr + u // 3 - 1, 0, M - 1), np.clip(cc + u % 3 - 1, 0, N - 1)]
+                     for u in range(9)], axis=1)
+    res = {}
+    for d, g_idx in acw_idx.items():
+        _, o_idx, S, dg = oracle.acwddf_at(img_np, pix, 3, codes[d], 4, 2, 10.8)
+        g = g_idx.reshape(-1)[pix]
+        diff = g != o_idx
+        amb = (S != 0) & (np.abs(S - 10.8) <= 1e-5 * 10.8)
+        rows = np.arange(k)
+        for j in range(4):
+            O = dg[:, 9 * j:9 * (j + 1)]
+            first = O.argmin(1)
+            near = O <= O[rows, first][:, None] * (1 + 1e-6)
+            amb |= np.any(near & np.any(cols != cols[rows, first][:, None], axis=2), axis=1)
+        res[d] = {"index_mismatch": int(diff.sum()), "index_compared": k,
+                  "mismatches_all_undetermined": bool(np.all(amb[diff]))}
+    return res
+
+
+def cpu_baseline(img_np, outs, variants, seconds, acw_idx=None):
     """FP64 oracle on a seeded pixel sample of the same image, all host threads."""
     import oracle
 
@@ -484,7 +546,9 @@ def cpu_baseline(img_np, outs, variants, seconds):
             "sample": "%s the 1024x1024 image x %d variants, DDF 3x3 (%.1f s)"
                       % (what, len(variants), dt),
             "index_mismatch": mism, "index_compared": k * len(variants),
-            "mismatches_all_near_ties": near}
+            "mismatches_all_near_ties": near,
+            "acwddf3_1024x1024": acwddf_mismatch(oracle, img_np, acw_idx, codes) if acw_idx
+            else None}
 
 
 if __name__ == "__main__":

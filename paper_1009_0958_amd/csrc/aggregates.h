@@ -42,51 +42,71 @@ __device__ __forceinline__ void row_sums(const float (&row)[4 * (W / 2) + 1], fl
     }
 }
 
-// Aggregates of the own member p over every window containing it, for the
-// angular term (L2PASS = false) or the L2 term of eq. (1) (L2PASS = true).
-// agg[u] is the aggregate of p in the window c = p - offset(u).  CEN: also
-// cen[u] = the pair term of p and that window's centre c (taken from the
-// offset grid, so no extra pair is evaluated).
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS, bool CEN>
-__device__ __forceinline__ void member_aggregates_c(const float4* __restrict__ s_dir,
-                                                    const float4* __restrict__ s_raw,
-                                                    float* __restrict__ s_plane, int ey, int ex,
-                                                    int tid, const float4& mdir,
-                                                    const float4& mraw, const MinimaxCoef& cf,
-                                                    float (&agg)[W * W], float (&cen)[W * W]) {
+// Aggregates of the own member p over every window containing it.  PASS 0:
+// the angular term into agg0; PASS 1: the L2 term of eq. (1) into agg0;
+// PASS 2: both in one sweep (angular -> agg0, L2 -> agg1) with two LDS plane
+// sets, sharing the neighbour loads, bounds tests and barriers.  agg[u] is the
+// aggregate of p in the window c = p - offset(u).  CEN: also cen[u] = the term
+// of p and that window's centre c (taken from the offset grid, so no extra
+// pair is evaluated).  s_plane holds G * NT floats per term.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, int PASS, bool CEN>
+__device__ __forceinline__ void member_aggregates_x(
+    const float4* __restrict__ s_dir, const float4* __restrict__ s_raw,
+    float* __restrict__ s_plane, int ey, int ex, int tid, const float4& mdir, const float4& mraw,
+    const MinimaxCoef& cf, float (&agg0)[W * W], float (&cen0)[W * W], float (&agg1)[W * W],
+    float (&cen1)[W * W]) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, G = Gm::G, NT = Gm::NT;
+    constexpr int NP = PASS == 2 ? 2 : 1;
 
-    auto term = [&](int q) -> float {
-        if (L2PASS) return l2_term(mraw, s_raw[q]);
-        return pair_term<KIND, DIST, U8>(mdir, mraw, s_dir[q], s_raw[q], cf);
+    auto terms = [&](int q, float (&v)[NP]) {
+        if constexpr (PASS == 1) {
+            v[0] = l2_term(mraw, s_raw[q]);
+        } else if constexpr (PASS == 0) {
+            v[0] = pair_term<KIND, DIST, U8>(mdir, mraw, s_dir[q], s_raw[q], cf);
+        } else {
+            v[0] = pair_and_l2<KIND, DIST, U8>(mdir, mraw, s_dir, s_raw, q, cf, v[1]);
+        }
     };
-    const float self =
-        L2PASS ? 0.0f : pair_term<KIND, DIST, U8>(mdir, mraw, mdir, mraw, cf);
+    float self[NP];
+    if constexpr (PASS == 1) {
+        self[0] = 0.0f;
+    } else {
+        self[0] = pair_term<KIND, DIST, U8>(mdir, mraw, mdir, mraw, cf);
+        if constexpr (NP == 2) self[1] = 0.0f;
+    }
 
-    float R[G][W];  // R[dy + 2h][s + 2h]: sum of G_p(dy, s .. s + w - 1)
+    float R[NP][G][W];  // R[k][dy + 2h][s + 2h]: sum of G_p(dy, s .. s + w - 1), term k
 #pragma unroll
     for (int g = 0; g <= 2 * H; ++g) {
-        float own[G], up[G];
+        float own[NP][G], up[NP][G];
 #pragma unroll
         for (int dx = -2 * H; dx <= 2 * H; ++dx) {
-            own[dx + 2 * H] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) own[k][dx + 2 * H] = 0.0f;
             if (g == 0 && dx <= 0) continue;
             const int py = ey + g, px = ex + dx;
             if (py < EXT_H && px >= 0 && px < EXT_W) {
-                const float v = term(py * EXT_W + px);
-                own[dx + 2 * H] = v;
-                s_plane[(dx + 2 * H) * NT + tid] = v;
+                float v[NP];
+                terms(py * EXT_W + px, v);
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    own[k][dx + 2 * H] = v[k];
+                    s_plane[(k * G + dx + 2 * H) * NT + tid] = v[k];
+                }
             }
         }
         __syncthreads();
 #pragma unroll
         for (int dx = -2 * H; dx <= 2 * H; ++dx) {
-            up[dx + 2 * H] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) up[k][dx + 2 * H] = 0.0f;
             if (g == 0 && dx >= 0) continue;
             const int py = ey - g, px = ex + dx;
             if (py >= 0 && px >= 0 && px < EXT_W)
-                up[dx + 2 * H] = s_plane[(2 * H - dx) * NT + py * EXT_W + px];
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    up[k][dx + 2 * H] = s_plane[(k * G + 2 * H - dx) * NT + py * EXT_W + px];
         }
         if constexpr (CEN) {
             if (g <= H) {
@@ -94,35 +114,61 @@ __device__ __forceinline__ void member_aggregates_c(const float4* __restrict__ s
                 // offset (-g, dx) the centre of window (g, -dx)
 #pragma unroll
                 for (int dx = -H; dx <= H; ++dx) {
-                    const float vo = g > 0 || dx > 0 ? own[dx + 2 * H]
-                                                     : (dx < 0 ? up[dx + 2 * H] : self);
-                    cen[(H - g) * W + (H - dx)] = vo;
-                    if (g > 0) cen[(H + g) * W + (H - dx)] = up[dx + 2 * H];
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        float(&cen)[W * W] = k == 0 ? cen0 : cen1;
+                        const float vo = g > 0 || dx > 0
+                                             ? own[k][dx + 2 * H]
+                                             : (dx < 0 ? up[k][dx + 2 * H] : self[k]);
+                        cen[(H - g) * W + (H - dx)] = vo;
+                        if (g > 0) cen[(H + g) * W + (H - dx)] = up[k][dx + 2 * H];
+                    }
                 }
             }
         }
-        if (g == 0) {
-            float row[G];
 #pragma unroll
-            for (int k = 0; k < G; ++k) row[k] = k < 2 * H ? up[k] : (k == 2 * H ? self : own[k]);
-            row_sums<W>(row, R[2 * H]);
-        } else {
-            row_sums<W>(own, R[2 * H + g]);
-            row_sums<W>(up, R[2 * H - g]);
+        for (int k = 0; k < NP; ++k) {
+            if (g == 0) {
+                float row[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j)
+                    row[j] = j < 2 * H ? up[k][j] : (j == 2 * H ? self[k] : own[k][j]);
+                row_sums<W>(row, R[k][2 * H]);
+            } else {
+                row_sums<W>(own[k], R[k][2 * H + g]);
+                row_sums<W>(up[k], R[k][2 * H - g]);
+            }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int uy = -H; uy <= H; ++uy) {
+    for (int k = 0; k < NP; ++k) {
+        float(&agg)[W * W] = k == 0 ? agg0 : agg1;
 #pragma unroll
-        for (int ux = -H; ux <= H; ++ux) {
-            const int s = -H - ux + 2 * H;
-            float acc = R[-H - uy + 2 * H][s];
+        for (int uy = -H; uy <= H; ++uy) {
 #pragma unroll
-            for (int dy = -H - uy + 1; dy <= H - uy; ++dy) acc += R[dy + 2 * H][s];
-            agg[(uy + H) * W + (ux + H)] = acc;
+            for (int ux = -H; ux <= H; ++ux) {
+                const int s = -H - ux + 2 * H;
+                float acc = R[k][-H - uy + 2 * H][s];
+#pragma unroll
+                for (int dy = -H - uy + 1; dy <= H - uy; ++dy) acc += R[k][dy + 2 * H][s];
+                agg[(uy + H) * W + (ux + H)] = acc;
+            }
         }
     }
+}
+
+// One term (angular if !L2PASS, else L2), optionally with the centre terms.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS, bool CEN>
+__device__ __forceinline__ void member_aggregates_c(const float4* __restrict__ s_dir,
+                                                    const float4* __restrict__ s_raw,
+                                                    float* __restrict__ s_plane, int ey, int ex,
+                                                    int tid, const float4& mdir,
+                                                    const float4& mraw, const MinimaxCoef& cf,
+                                                    float (&agg)[W * W], float (&cen)[W * W]) {
+    float u0[W * W], u1[W * W];
+    member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, L2PASS ? 1 : 0, CEN>(
+        s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, cf, agg, cen, u0, u1);
 }
 
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS>

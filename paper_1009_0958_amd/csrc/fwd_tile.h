@@ -21,12 +21,13 @@ namespace odf {
 // every (window, member) objective in LDS during the L2 pass instead of
 // keeping 25 aggregates live in registers, which lets it use 1024-thread tiles.
 // NKEY: argmin keys per window (4 for ACWDDF: eq. 3 and three levels of eq. 9).
-template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY>
+// NPL: plane sets (2 when the angular and L2 terms are swept together).
+template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY, int NPL>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     float4 dir[Gm::NT];
     float4 raw[Gm::NT];
-    float plane[Gm::G * Gm::NT];
+    float plane[NPL * Gm::G * Gm::NT];
     unsigned long long key[AGG ? 1 : NKEY * Gm::TH * Gm::TW];
     float stage[STAGE ? Gm::NW * Gm::TH * Gm::TW : 1];
 };
@@ -36,9 +37,16 @@ constexpr bool stage_angle_part() {
     return W == 5 && KIND == kDDF && !AGG;
 }
 
+// 3x3 DDF and ACWDDF sweep the angular and L2 terms together (PASS 2 of
+// member_aggregates_x); 5x5 keeps two sweeps (register budget).
+template <int W, int KIND>
+constexpr bool fused_sweep() {
+    return W == 3 && KIND != kBVDF;
+}
+
 template <int W, int KIND, int EXT_W, int EXT_H, bool AGG>
-using FwdSharedFor =
-    FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>(), KIND == kACW ? 4 : 1>;
+using FwdSharedFor = FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>(),
+                               KIND == kACW ? 4 : 1, fused_sweep<W, KIND>() ? 2 : 1>;
 
 // Filter one output tile whose top-left output pixel is (ty0, tx0) of image b.
 // Every thread of the workgroup must call it (it synchronises); tid is the
@@ -84,8 +92,12 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
     // a2 + a3 (ACWDDF also keeps each member's terms with the window centres)
     float A[NW], D[NW];
     float cA[NW], cD[NW];
-    member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW>(
-        s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
+    if constexpr (fused_sweep<W, KIND>())
+        member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, 2, KIND == kACW>(
+            s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD);
+    else
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW>(
+            s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
     if constexpr (stage_angle_part<W, KIND, AGG>()) {
         // angle part of each objective -> LDS, then the L2 pass, then the keys
         const int mode = objective_mode<KIND>(prm.p);
@@ -118,7 +130,9 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             atomicMin(&s_key[cy * TW + cx], key);
         }
     } else {
-    if (KIND != kBVDF)
+    if constexpr (fused_sweep<W, KIND>())
+        ;  // D and cD came with the angular sweep
+    else if (KIND != kBVDF)
         member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, KIND == kACW>(
             s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
     else

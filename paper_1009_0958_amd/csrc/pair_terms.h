@@ -5,7 +5,7 @@
 // Each prepared pixel is two float4 values:
 //   dir = (d.x, d.y, d.z, aux1)   d: direction (the pixel, or (1,1,1) for 0)
 //   raw = (x.x, x.y, x.z, aux2)   x: the raw pixel
-//   EXACT:   aux1 unused, aux2 = |d| / |x| (a power of two; 0 for x = 0)
+//   EXACT:   aux1 = |x|^2, aux2 = |d| / |x| (a power of two; 0 for x = 0)
 //   MINIMAX: aux1 = |d|^2, aux2 = 1/|d|
 //   RGB:     aux1 = d.x + d.y + d.z, aux2 = 1/aux1
 //
@@ -14,7 +14,8 @@
 // self pair, so equal colours in a window get bitwise-equal aggregates.
 // Cross-product and chromaticity numerators are differences of two rounded
 // products (no fused multiply-add), which keeps swapped arguments exact
-// negations; for uint8 inputs they are exact integers.
+// negations; for uint8 inputs they are exact integers, formed with one fused
+// multiply-add.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,6 +41,16 @@ constexpr float kPi = 3.14159265358979323846f;
 __device__ __forceinline__ float diff_of_products(float a, float b, float c, float d) {
 #pragma clang fp contract(off)
     return a * b - c * d;
+}
+
+// a*b - c*d of a cross product or chromaticity numerator.  EXACT_INT: uint8
+// pixels, integer operands whose products (at most 255 * 765) and their
+// difference are exact in binary32, so one fused multiply-add yields the same
+// exact, hence symmetric, value.
+template <bool EXACT_INT>
+__device__ __forceinline__ float cross_diff(float a, float b, float c, float d) {
+    if constexpr (EXACT_INT) return fmaf(a, b, -(c * d));
+    else return diff_of_products(a, b, c, d);
 }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -80,8 +91,10 @@ __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, floa
     if (zero) d0 = d1 = d2 = 1.0f;
     float aux1 = 0.0f, aux2 = 0.0f;
     if (DIST == kExact) {
-        // d = 2^-e x: the derivative of the direction (0 for the zero pixel,
-        // whose direction is a constant), used by the angle gradient
+        // |x|^2 of the raw value (exact for uint8), and d = 2^-e x: the
+        // derivative of the direction (0 for the zero pixel, whose direction
+        // is a constant), used by the angle gradient
+        aux1 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
         aux2 = zero ? 0.0f : ldexpf(1.0f, -e);
     } else if (DIST == kMinimax) {
         aux1 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
@@ -98,12 +111,13 @@ __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, floa
 // with P = |a x b|^2 and Q = (a.b)^2, r = sqrt(min(P,Q)/max(P,Q)) =
 // min(P,Q) / sqrt(P Q) lies in [0, 1] and the angle is atan(r) or
 // pi/2 - atan(r); one reciprocal square root per pair.
-template <bool SIGNED>
-__device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
-    float dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
-    float c0 = diff_of_products(a.y, b.z, a.z, b.y);
-    float c1 = diff_of_products(a.z, b.x, a.x, b.z);
-    float c2 = diff_of_products(a.x, b.y, a.y, b.x);
+template <bool U8>
+__device__ __forceinline__ float angle_exact_dot(const float4& a, const float4& b, float& dot) {
+    constexpr bool SIGNED = !U8;  // float inputs may be negative
+    dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
+    float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
+    float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
+    float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
     float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
     float Q = dot * dot;
     float m = fminf(P, Q);
@@ -118,20 +132,27 @@ __device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
     return th;
 }
 
+template <bool U8>
+__device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
+    float dot;
+    return angle_exact_dot<U8>(a, b, dot);
+}
+
 // Method 1 (Section 2.1): ACOS row of Table 1 in z for z < 1/2, ASIN row in
 // tau = sqrt(1 - z) for z >= 1/2 (eqs. 5-6), clamped at 0.  The branch is the
 // exact predicate 4 (a.b)^2 < |a|^2 |b|^2 (binary64 products of binary32
 // values are exact), and 1 - z = |a x b|^2 / (|a|^2 |b|^2 (1 + z)) avoids the
 // cancellation of 1 - z next to z = 1.
+template <bool U8>
 __device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra, const float4& b,
                                                const float4& rb, const MinimaxCoef& cf) {
     float dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
     float z = dot * (ra.w * rb.w);
     bool acos_branch = (dot < 0.0f) ||
                        (4.0 * (double)dot * (double)dot < (double)a.w * (double)b.w);
-    float c0 = diff_of_products(a.y, b.z, a.z, b.y);
-    float c1 = diff_of_products(a.z, b.x, a.x, b.z);
-    float c2 = diff_of_products(a.x, b.y, a.y, b.x);
+    float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
+    float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
+    float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
     float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
     float X = (a.w * b.w) * (1.0f + z);
     float tau = P * rsq(fmaxf(P * X, 1.17549435e-38f));
@@ -141,12 +162,12 @@ __device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra
 
 // Method 2 (Section 2.2, eq. 7): L2 distance of chromaticities
 // |a / sum a - b / sum b| = |a sum b - b sum a| / (sum a sum b).
-template <int KIND>
+template <int KIND, bool U8>
 __device__ __forceinline__ float chroma_term(const float4& a, const float4& ra, const float4& b,
                                              const float4& rb) {
-    float n0 = diff_of_products(a.x, b.w, b.x, a.w);
-    float n1 = diff_of_products(a.y, b.w, b.y, a.w);
-    float n2 = diff_of_products(a.z, b.w, b.z, a.w);
+    float n0 = cross_diff<U8>(a.x, b.w, b.x, a.w);
+    float n1 = cross_diff<U8>(a.y, b.w, b.y, a.w);
+    float n2 = cross_diff<U8>(a.z, b.w, b.z, a.w);
     float Nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
     float B = sqrt_raw(Nn) * (ra.w * rb.w);
     if (KIND != kBVDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
@@ -157,15 +178,40 @@ __device__ __forceinline__ float chroma_term(const float4& a, const float4& ra, 
 template <int KIND, int DIST, bool U8>
 __device__ __forceinline__ float pair_term(const float4& a, const float4& ra, const float4& b,
                                            const float4& rb, const MinimaxCoef& cf) {
-    if (DIST == kExact) return angle_exact<!U8>(a, b);
-    if (DIST == kMinimax) return angle_minimax(a, ra, b, rb, cf);
-    return chroma_term<KIND>(a, ra, b, rb);
+    if (DIST == kExact) return angle_exact<U8>(a, b);
+    if (DIST == kMinimax) return angle_minimax<U8>(a, ra, b, rb, cf);
+    return chroma_term<KIND, U8>(a, ra, b, rb);
 }
 
 // eq. (1) with the L2 norm (Section III), on raw values.
 __device__ __forceinline__ float l2_term(const float4& ra, const float4& rb) {
     float e0 = ra.x - rb.x, e1 = ra.y - rb.y, e2 = ra.z - rb.z;
     return sqrt_raw(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
+}
+
+// The angular pair term of member a (dir a, raw ra) with neighbour q of the
+// LDS tile, and their L2 distance of eq. (1) in l2.  For uint8 exact angles the
+// squared distance reuses the dot product of the angle:
+// |x_a - x_b|^2 = |x_a|^2 + |x_b|^2 - 2 x_a.x_b, every term an integer exact in
+// binary32, with |x|^2 in dir.w and the zero pixel (direction (1,1,1), value
+// 0) given a zero raw dot product through z = min(|x|^2, 1).
+template <int KIND, int DIST, bool U8>
+__device__ __forceinline__ float pair_and_l2(const float4& a, const float4& ra,
+                                             const float4* __restrict__ s_dir,
+                                             const float4* __restrict__ s_raw, int q,
+                                             const MinimaxCoef& cf, float& l2) {
+    const float4 b = s_dir[q];
+    if constexpr (DIST == kExact && U8) {
+        float dot;
+        const float th = angle_exact_dot<U8>(a, b, dot);
+        const float zz = (-2.0f * fminf(a.w, 1.0f)) * fminf(b.w, 1.0f);
+        l2 = sqrt_raw(fmaf(dot, zz, a.w + b.w));
+        return th;
+    } else {
+        const float4 rb = s_raw[q];
+        l2 = l2_term(ra, rb);
+        return pair_term<KIND, DIST, U8>(a, ra, b, rb, cf);
+    }
 }
 
 // Total order on floats (no NaN) as unsigned keys.

@@ -141,23 +141,32 @@ __device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
 // Method 1 (Section 2.1): ACOS row of Table 1 in z for z < 1/2, ASIN row in
 // tau = sqrt(1 - z) for z >= 1/2 (eqs. 5-6), clamped at 0.  The branch is the
 // exact predicate 4 (a.b)^2 < |a|^2 |b|^2 (binary64 products of binary32
-// values are exact), and 1 - z = |a x b|^2 / (|a|^2 |b|^2 (1 + z)) avoids the
-// cancellation of 1 - z next to z = 1.
+// values are exact).  The binary32 cosine z = a.b / (|a| |b|) is within a few
+// ulp of the true one (a.b is exact or nearly so for non-negative inputs, the
+// reciprocal norms are correctly rounded), so outside |z - 1/2| <= 2^-20 its
+// own comparison gives the same answer and the binary64 test is skipped.
+// 1 - z = |a x b|^2 / (|a|^2 |b|^2 (1 + z)) avoids the cancellation of 1 - z
+// next to z = 1.
 template <bool U8>
 __device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra, const float4& b,
                                                const float4& rb, const MinimaxCoef& cf) {
     float dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
     float z = dot * (ra.w * rb.w);
-    bool acos_branch = (dot < 0.0f) ||
-                       (4.0 * (double)dot * (double)dot < (double)a.w * (double)b.w);
+    bool acos_branch = z < 0.5f;
+    const bool near = fabsf(z - 0.5f) <= 0x1p-20f;
+    if (__builtin_amdgcn_ballot_w64(near)) {  // uniform branch, almost never taken
+        asm volatile("");                     // keeps the exact test out of the common path
+        if (near) acos_branch = 4.0 * (double)dot * (double)dot < (double)a.w * (double)b.w;
+    }
     float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
     float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
     float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
     float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
     float X = (a.w * b.w) * (1.0f + z);
     float tau = P * rsq(fmaxf(P * X, 1.17549435e-38f));
-    float v = acos_branch ? horner4(cf.acos_c, z) : horner4(cf.asin_c, tau);
-    return fmaxf(v, 0.0f);
+    // the clamp at 0 matters for the ASIN row only (q = 3 dips below 0 next to
+    // tau = 0); every ACOS row stays above 1 on [-1, 1/2]
+    return acos_branch ? horner4(cf.acos_c, z) : fmaxf(horner4(cf.asin_c, tau), 0.0f);
 }
 
 // Method 2 (Section 2.2, eq. 7): L2 distance of chromaticities

@@ -231,6 +231,49 @@ int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles
 /* Free a plan (after its last launch has completed). */
 int odf_plan_destroy(odf_plan* plan);
 
+/* ---------------------------------------------------------------- noise and quality
+ * The correlated impulsive noise model of eq. (8) and the MAE / PSNR measures
+ * of Section III, for effectiveness checks on synthetic clean/noisy pairs. */
+
+/*
+ * noisy = clean corrupted by eq. (8): with probability phi a pixel is
+ * corrupted, then only its red, green or blue channel (probabilities phi_r,
+ * phi_g, phi_b) or all three (the rest) take the values of a random vector r
+ * uniform in {0..255}^3; otherwise it is copied.
+ * Random numbers: pixel i = (b*M + row)*N + col draws one Philox4x32-10 block
+ * (Salmon et al., SC 2011) with counter (i mod 2^32, i div 2^32, 0, 0) and key
+ * (seed mod 2^32, seed div 2^32): word 0 < floor(phi 2^32) corrupts; word 1
+ * against floor(phi_r 2^32), floor((phi_r + phi_g) 2^32),
+ * floor((phi_r + phi_g + phi_b) 2^32) picks red only, green only, blue only,
+ * else all three; bytes 0, 1, 2 of word 2 are r.  Results depend only on
+ * (seed, i), not on the launch.
+ *   clean, noisy  B x M x N x 3 uint8; noisy may equal clean (in place) but
+ *                 must not partially overlap it.
+ * Errors: ODF_EINVAL for null pointers, sizes (B*M*N >= 2^40), phi outside
+ * [0, 1], a negative channel probability or phi_r + phi_g + phi_b > 1.
+ */
+int odf_noise_eq8_u8(const uint8_t* clean, uint8_t* noisy, int B, int M, int N, double phi,
+                     double phi_r, double phi_g, double phi_b, uint64_t seed, void* stream);
+
+/* Workspace bytes odf_quality_u8 needs for B images (0 if B < 1). */
+size_t odf_quality_workspace(int B);
+
+/*
+ * Per image b of B: MAE = sum |y - ref| / (3MN) and
+ * PSNR = 10 log10(255^2 / MSE), MSE = sum (y - ref)^2 / (3MN), over the three
+ * channels of every pixel (Section III; PSNR = +inf for identical images).
+ * The sums are exact 64-bit integers, so the results do not depend on
+ * scheduling.
+ *   y, ref     B x M x N x 3 uint8 (read only).
+ *   mae, psnr  B float64 each, device memory.
+ *   workspace  device scratch of odf_quality_workspace(B) bytes, 8-byte
+ *              aligned, owned by the caller; contents on entry ignored.
+ * Errors: ODF_EINVAL for null pointers, sizes (B > 65535 or B*M*N >= 2^40)
+ * or a short / misaligned workspace.
+ */
+int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, double* mae,
+                   double* psnr, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------------- tuning
  * The forward kernels run one thread per pixel of an extended tile
  * (output tile plus halo).  Tile shapes are numbered 0..3; odf_tile_config

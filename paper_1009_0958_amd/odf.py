@@ -51,6 +51,11 @@ def lib():
         L.odf_acwddf_u8.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
         L.odf_acwddf_f32.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
         L.odf_aggregates.argtypes = [P, I, I, I, I, I, I, F, I, I, P, P, P, P]
+        Dbl = ctypes.c_double
+        L.odf_noise_eq8_u8.argtypes = [P, P, I, I, I, Dbl, Dbl, Dbl, Dbl, ctypes.c_uint64, P]
+        L.odf_quality_workspace.argtypes = [I]
+        L.odf_quality_workspace.restype = ctypes.c_size_t
+        L.odf_quality_u8.argtypes = [P, P, I, I, I, P, P, P, ctypes.c_size_t, P]
         L.odf_backward_hard_f32.argtypes = [P, P, I, I, I, I, P, P]
         L.odf_softmin_fwd_f32.argtypes = [P, I, I, I, I, I, F, F, P, P]
         L.odf_softmin_bwd_workspace.argtypes = [I, I, I, I, I]
@@ -154,6 +159,45 @@ def acwddf(img, window=3, dist=EXACT, q=4, lam=2, T=10.8, out=None, idx=None,
         out = out[0]
         idx = None if idx is None else idx[0]
     return out, idx
+
+
+def noise_eq8(img, phi, phi_rgb=(0.25, 0.25, 0.25), seed=0, out=None):
+    """eq. (8) impulsive noise on uint8 images (Philox4x32-10 draws keyed by
+    ``seed``, counter = flat pixel index).  ``out`` may be ``img`` itself."""
+    x, squeeze = _as_batch(img)
+    _check_tensor(x, "img")
+    if x.dtype != torch.uint8:
+        raise ValueError("img must be uint8")
+    B, M, N, _ = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    o = out if out.dim() == 4 else out[None]
+    _check_tensor(o, "out")
+    if o.shape != x.shape or o.dtype != torch.uint8:
+        raise ValueError("out must be a uint8 image of the shape of img")
+    _check(lib().odf_noise_eq8_u8(_ptr(x), _ptr(o), B, M, N, float(phi), float(phi_rgb[0]),
+                                  float(phi_rgb[1]), float(phi_rgb[2]), int(seed),
+                                  _stream(x.device)))
+    return out
+
+
+def quality(y, ref, workspace=None):
+    """MAE and PSNR of uint8 images y against ref: two float64 tensors (B,)."""
+    a, _ = _as_batch(y)
+    b, _ = _as_batch(ref)
+    _check_tensor(a, "y")
+    _check_tensor(b, "ref")
+    if a.shape != b.shape or a.dtype != torch.uint8 or b.dtype != torch.uint8:
+        raise ValueError("y and ref must be uint8 images of one shape")
+    B, M, N, _ = a.shape
+    mae = torch.empty(B, dtype=torch.float64, device=a.device)
+    psnr = torch.empty_like(mae)
+    nbytes = lib().odf_quality_workspace(B)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=a.device)
+    _check(lib().odf_quality_u8(_ptr(a), _ptr(b), B, M, N, _ptr(mae), _ptr(psnr), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(a.device)))
+    return mae, psnr
 
 
 def aggregates(img, window=3, kind=BVDF, p=0.5, dist=EXACT, q=4):

@@ -139,3 +139,25 @@ def test_acwddf_tuning_table():
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 3) == odf.OK
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 2) == odf.OK
     assert L.odf_tune_get(3, 3, 0, 1) == odf.EINVAL
+
+
+def test_noise_and_quality_reject():
+    L = odf.lib()
+    ok = (FAKE, FAKE2, 1, 8, 8, 0.1, 0.25, 0.25, 0.25, 1, None)
+    for i, bad, text in ((0, None, "NULL"), (2, 0, "sizes"), (5, 1.5, "phi"), (5, -0.1, "phi"),
+                         (6, -0.25, "phi"), (8, 0.6, "sum")):
+        args = list(ok)
+        args[i] = bad
+        assert L.odf_noise_eq8_u8(*args) == odf.EINVAL, (i, bad)
+        assert text in odf.last_error()
+    assert L.odf_noise_eq8_u8(FAKE, ctypes.c_void_p(0x7F0000000000 + 7), 1, 8, 8, 0.1, 0.25, 0.25,
+                              0.25, 1, None) == odf.EINVAL
+    assert "overlaps" in odf.last_error()
+    assert L.odf_quality_workspace(3) == 48 and L.odf_quality_workspace(0) == 0
+    W = ctypes.c_void_p(0x7F0000200000)
+    assert L.odf_quality_u8(FAKE, FAKE2, 2, 4, 4, W, W, W, 16, None) == odf.EINVAL
+    assert "workspace" in odf.last_error()
+    assert L.odf_quality_u8(FAKE, FAKE2, 2, 4, 4, W, W, ctypes.c_void_p(0x7F0000200004), 64,
+                            None) == odf.EINVAL
+    assert L.odf_quality_u8(FAKE, FAKE2, 70000, 1, 1, W, W, W, 1 << 20, None) == odf.EINVAL
+    assert L.odf_quality_u8(None, FAKE2, 1, 4, 4, W, W, W, 64, None) == odf.EINVAL

@@ -291,6 +291,7 @@ def main():
     if not args.no_forms:
         for name, fn in (("large_frames", lambda: large_frame_forms(torch, odf, synth, dev, DIST)),
                          ("acwddf", lambda: acwddf_forms(torch, odf, synth, dev, DIST, x, acw_idx)),
+                         ("effectiveness", lambda: effectiveness_forms(torch, odf, synth, dev, DIST)),
                          ("batched", lambda: batched_form(torch, odf, synth, dev)),
                          ("differentiable", lambda: differentiable_forms(torch, odf, synth, dev))):
             try:
@@ -377,6 +378,38 @@ def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
                     acw_idx[d] = i.cpu().numpy()
     del big
     return forms
+
+
+def effectiveness_forms(torch, odf, synth, dev, DIST):
+    """The paper's effectiveness check on synthetic stand-ins: a clean
+    1024 x 1024 image corrupted on the GPU by eq. (8) (phi = 0.10, 0.15,
+    channel probabilities 0.25), filtered by BVDF (Experiment 1) and ACWDDF
+    (Experiment 2) with each pair term, scored by MAE / PSNR on the GPU; plus
+    the noise and quality kernels' rates on a 7680 x 4320 frame."""
+    clean = torch.from_numpy(synth.smooth_image(1024, 1024, synth.rng_for(9, 0))).to(dev)
+    table = {}
+    for phi in (0.10, 0.15):
+        noisy = odf.noise_eq8(clean, phi, seed=1009)
+        row = {"noisy": noisy}
+        for d in ("exact", "minimax", "rgb"):
+            row["bvdf_" + d] = odf.filter(noisy, 3, odf.BVDF, 0.0, DIST[d], 4)[0]
+            row["acwddf_" + d] = odf.acwddf(noisy, 3, DIST[d], 4, 2, 10.8)[0]
+        names = list(row)
+        mae, psnr = odf.quality(torch.stack([row[k] for k in names]),
+                                clean.unsqueeze(0).expand(len(names), -1, -1, -1).contiguous())
+        table["phi%.2f" % phi] = {k: {"mae": round(float(m), 4), "psnr": round(float(p_), 3)}
+                                  for k, m, p_ in zip(names, mae.tolist(), psnr.tolist())}
+    big = torch.from_numpy(synth.smooth_image(4320, 7680, synth.rng_for(9, 1))).to(dev)
+    out = torch.empty_like(big)
+    npx = 4320 * 7680
+    ms_noise = time_launches(torch, lambda: odf.noise_eq8(big, 0.15, seed=5, out=out), 10, warm=2)
+    ws = torch.empty(16, dtype=torch.uint8, device=dev)
+    ms_q = time_launches(torch, lambda: odf.quality(out, big, workspace=ws), 10, warm=2)
+    rates = {"noise_eq8_7680x4320": {"ms": round(ms_noise, 4), "mpix_s": round(npx / (ms_noise * 1e3), 1),
+                                     "hbm_GBps": round(6 * npx / (ms_noise * 1e6), 1)},
+             "quality_7680x4320": {"ms": round(ms_q, 4), "mpix_s": round(npx / (ms_q * 1e3), 1),
+                                   "hbm_GBps": round(6 * npx / (ms_q * 1e6), 1)}}
+    return {"effectiveness_1024x1024_eq8": table, **rates}
 
 
 def batched_form(torch, odf, synth, dev):

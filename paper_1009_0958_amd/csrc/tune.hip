@@ -130,15 +130,16 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
                 rc = ODF_EHIP;
                 goto done;
             }
-        hipEventRecord(e0, s);
-        for (int r = 0; r < reps; ++r) odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s);
-        hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) {
+        bool ok = hipEventRecord(e0, s) == hipSuccess;
+        for (int r = 0; r < reps; ++r)
+            ok = ok && odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s) ==
+                           hipSuccess;
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        if (!ok || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
             rc = ODF_EHIP;
             goto done;
         }
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
         ms /= reps;
         ms_all[cfg] = ms;
         if (best < 0 || ms < best_ms) {
@@ -152,8 +153,10 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     if (cache_path && best >= 0) {
         hipDeviceProp_t prop;
         int dev = 0;
-        hipGetDevice(&dev);
-        hipGetDeviceProperties(&prop, dev);
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            rc = ODF_EHIP;
+            goto done;
+        }
         FILE* f = fopen(cache_path, "a");
         if (!f) {
             rc = odf::set_error(ODF_EINVAL, "cannot open %s", cache_path);
@@ -167,11 +170,11 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
         fclose(f);
     }
 done:
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    hipFree(img);
-    hipFree(out);
-    hipFree(idx);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(img);
+    (void)hipFree(out);
+    (void)hipFree(idx);
     return best >= 0 || rc != ODF_OK ? rc : ODF_EHIP;
 }
 
@@ -181,8 +184,8 @@ int odf_tune_load(const char* cache_path) {
     if (!f) return ODF_EINVAL;
     hipDeviceProp_t prop;
     int dev = 0;
-    hipGetDevice(&dev);
-    const bool have_dev = hipGetDeviceProperties(&prop, dev) == hipSuccess;
+    const bool have_dev =
+        hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess;
     char line[512];
     int applied = 0;
     while (fgets(line, sizeof line, f)) {

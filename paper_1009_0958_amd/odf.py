@@ -170,7 +170,7 @@ def noise_eq8(img, phi, phi_rgb=(0.25, 0.25, 0.25), seed=0, out=None):
         raise ValueError("img must be uint8")
     B, M, N, _ = x.shape
     if out is None:
-        out = torch.empty_like(x)
+        out = torch.empty_like(img)
     o = out if out.dim() == 4 else out[None]
     _check_tensor(o, "out")
     if o.shape != x.shape or o.dtype != torch.uint8:

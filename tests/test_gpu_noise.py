@@ -67,3 +67,10 @@ def test_quality_unaligned_and_identical():
     omae, opsnr = onoise.quality(y, ref)
     assert np.array_equal(mae, omae) and mae[0] == 0 and math.isinf(psnr[0])
     assert psnr[1] == pytest.approx(opsnr[1], rel=1e-12)
+
+
+def test_noise_keeps_the_input_shape():
+    clean = np.random.default_rng(9).integers(0, 256, (20, 30, 3)).astype(np.uint8)
+    got = odf.noise_eq8(_gpu(clean), 0.2, seed=3)
+    assert tuple(got.shape) == (20, 30, 3)
+    assert np.array_equal(got.cpu().numpy(), onoise.noise_eq8(clean, 0.2, seed=3))

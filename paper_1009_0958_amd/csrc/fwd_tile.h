@@ -32,6 +32,14 @@ struct FwdShared {
     float stage[STAGE ? Gm::NW * Gm::TH * Gm::TW : 1];
 };
 
+// Order bits of an objective.  Every mode but the logarithmic one yields a
+// non-negative value (sums and products of non-negative terms, never -0 or
+// NaN), whose binary32 bit pattern already orders like the value; the
+// logarithmic mode can be negative and takes the sign-aware order_key.
+__device__ __forceinline__ uint32_t objective_bits(float v, bool may_be_negative) {
+    return may_be_negative ? order_key(v) : __float_as_uint(v);
+}
+
 template <int W, int KIND, bool AGG>
 constexpr bool stage_angle_part() {
     return W == 5 && KIND == kDDF && !AGG;
@@ -126,7 +134,7 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             else if (mode == kObjLog) om = fmaf(p, __builtin_amdgcn_logf(D[u]), part);
             else om = part * D[u];
             const unsigned long long key =
-                ((unsigned long long)order_key(om) << 32) | (unsigned)u;
+                ((unsigned long long)objective_bits(om, mode == kObjLog) << 32) | (unsigned)u;
             atomicMin(&s_key[cy * TW + cx], key);
         }
     } else {
@@ -168,14 +176,17 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             const float o1 = fmaf(w1, cA[u], A[u]) * fmaf(w1, cD[u], D[u]);
             const float o2 = fmaf(w2, cA[u], A[u]) * fmaf(w2, cD[u], D[u]);
             const float o3 = fmaf(w3, cA[u], A[u]) * fmaf(w3, cD[u], D[u]);
-            atomicMin(&s_key[ci], ((unsigned long long)order_key(o0) << 32) | (unsigned)u);
-            atomicMin(&s_key[TT + ci], ((unsigned long long)order_key(o1) << 32) | (unsigned)u);
-            atomicMin(&s_key[2 * TT + ci], ((unsigned long long)order_key(o2) << 32) | (unsigned)u);
-            atomicMin(&s_key[3 * TT + ci], ((unsigned long long)order_key(o3) << 32) | (unsigned)u);
+            // products of non-negative sums: the bit patterns order like the values
+            const unsigned long long uu = (unsigned)u;
+            atomicMin(&s_key[ci], ((unsigned long long)__float_as_uint(o0) << 32) | uu);
+            atomicMin(&s_key[TT + ci], ((unsigned long long)__float_as_uint(o1) << 32) | uu);
+            atomicMin(&s_key[2 * TT + ci], ((unsigned long long)__float_as_uint(o2) << 32) | uu);
+            atomicMin(&s_key[3 * TT + ci], ((unsigned long long)__float_as_uint(o3) << 32) | uu);
         }
     } else {
         float om[NW];
-        objective_keys<NW>(objective_mode<KIND>(prm.p), prm.p, A, D, om);
+        const int mode = objective_mode<KIND>(prm.p);
+        objective_keys<NW>(mode, prm.p, A, D, om);
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int cy = ey - u / W;  // window centre, tile-local
@@ -183,7 +194,7 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
             if (ty0 + cy >= M || tx0 + cx >= N) continue;
             const unsigned long long key =
-                ((unsigned long long)order_key(om[u]) << 32) | (unsigned)u;
+                ((unsigned long long)objective_bits(om[u], mode == kObjLog) << 32) | (unsigned)u;
             atomicMin(&s_key[cy * TW + cx], key);
         }
     }

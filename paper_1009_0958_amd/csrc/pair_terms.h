@@ -202,8 +202,9 @@ __device__ __forceinline__ float l2_term(const float4& ra, const float4& rb) {
 // LDS tile, and their L2 distance of eq. (1) in l2.  For uint8 exact angles the
 // squared distance reuses the dot product of the angle:
 // |x_a - x_b|^2 = |x_a|^2 + |x_b|^2 - 2 x_a.x_b, every term an integer exact in
-// binary32, with |x|^2 in dir.w and the zero pixel (direction (1,1,1), value
-// 0) given a zero raw dot product through z = min(|x|^2, 1).
+// binary32, with |x|^2 in dir.w.  A zero pixel (direction (1,1,1), value 0,
+// |x|^2 = 0) has a zero raw dot product; the lanes with one take
+// |x_a|^2 + |x_b|^2 in a branch the wave enters only when some lane needs it.
 template <int KIND, int DIST, bool U8>
 __device__ __forceinline__ float pair_and_l2(const float4& a, const float4& ra,
                                              const float4* __restrict__ s_dir,
@@ -213,8 +214,13 @@ __device__ __forceinline__ float pair_and_l2(const float4& a, const float4& ra,
     if constexpr (DIST == kExact && U8) {
         float dot;
         const float th = angle_exact_dot<U8>(a, b, dot);
-        const float zz = (-2.0f * fminf(a.w, 1.0f)) * fminf(b.w, 1.0f);
-        l2 = sqrt_raw(fmaf(dot, zz, a.w + b.w));
+        float l2sq = fmaf(-2.0f, dot, a.w + b.w);
+        const bool zero = (a.w == 0.0f) | (b.w == 0.0f);
+        if (__builtin_amdgcn_ballot_w64(zero)) {
+            asm volatile("");  // keeps the fix-up out of the common path
+            if (zero) l2sq = a.w + b.w;
+        }
+        l2 = sqrt_raw(l2sq);
         return th;
     } else {
         const float4 rb = s_raw[q];

@@ -52,6 +52,7 @@
 #endif
 
 enum { OK_BVDF = 0, OK_DDF = 1 };
+enum { NMAX = 49 }; /* members of the largest window (7 x 7) */
 enum { OD_EXACT = 0, OD_MINIMAX = 1, OD_RGB = 2 };
 
 /* Table 1: minimax polynomial coefficients a_0..a_4 as printed, rows q = 2,3,4. */
@@ -183,8 +184,8 @@ static void filter_one(const double *img, int M, int N, int w, int kind, double 
     int64_t b = pix / mn, rc = pix % mn;
     int r = (int)(rc / N), c = (int)(rc % N);
     int n = w * w;
-    int64_t src[25];
-    double A[25], D[25], Om[25];
+    int64_t src[NMAX];
+    double A[NMAX], D[NMAX], Om[NMAX];
     const double *base = img + b * mn * 3;
     window_members(M, N, w, r, c, src);
     for (int u = 0; u < n; ++u) {
@@ -214,7 +215,7 @@ static void filter_one(const double *img, int M, int N, int w, int kind, double 
 
 static int check_args(int B, int M, int N, int w, int kind, double p, int dist, int q) {
     if (B < 1 || M < 1 || N < 1) return -1;
-    if (w != 3 && w != 5) return -1;
+    if (w != 3 && w != 5 && w != 7) return -1;
     if (kind != OK_BVDF && kind != OK_DDF) return -1;
     if (dist < OD_EXACT || dist > OD_RGB) return -1;
     if (dist == OD_MINIMAX && (q < 2 || q > 4)) return -1;
@@ -294,7 +295,7 @@ int oracle_filter_at(const double *img, int B, int M, int N, int w, int kind, do
  * Output pixels are visited in raster order. */
 int oracle_backward_hard(const uint8_t *idx, const double *dy, int B, int M, int N, int w,
                          double *dx) {
-    if (B < 1 || M < 1 || N < 1 || (w != 3 && w != 5) || !idx || !dy || !dx) return -1;
+    if (B < 1 || M < 1 || N < 1 || (w != 3 && w != 5 && w != 7) || !idx || !dy || !dx) return -1;
     int h = (w - 1) / 2, n = w * w;
     int64_t mn = (int64_t)M * N;
     memset(dx, 0, sizeof(double) * 3 * mn * B);
@@ -360,8 +361,8 @@ int oracle_softmin_fwd(const double *img, int B, int M, int N, int w, int kind, 
     int n = w * w;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t pix = 0; pix < total; ++pix) {
-        int64_t src[25];
-        double A[25], D[25], Om[25], pi[25];
+        int64_t src[NMAX];
+        double A[NMAX], D[NMAX], Om[NMAX], pi[NMAX];
         int64_t b = pix / mn, rc = pix % mn;
         softmin_window(img + b * mn * 3, M, N, w, kind, p, tau, (int)(rc / N), (int)(rc % N), src,
                        A, D, Om, pi, y + 3 * pix);
@@ -427,8 +428,8 @@ int oracle_softmin_bwd(const double *img, const double *dy, int B, int M, int N,
         const double *base = img + (int64_t)b * mn * 3;
         double *gx = dx + (int64_t)b * mn * 3;
         for (int64_t rc = 0; rc < mn; ++rc) {
-            int64_t src[25];
-            double A[25], D[25], Om[25], pi[25], y[3];
+            int64_t src[NMAX];
+            double A[NMAX], D[NMAX], Om[NMAX], pi[NMAX], y[3];
             softmin_window(base, M, N, w, kind, p, tau, (int)(rc / N), (int)(rc % N), src, A, D,
                            Om, pi, y);
             const double *g = dy + 3 * ((int64_t)b * mn + rc);
@@ -494,8 +495,8 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
     int64_t b = pix / mn, rc = pix % mn;
     int r = (int)(rc / N), c = (int)(rc % N);
     int n = w * w, d = (n - 1) / 2;
-    int64_t src[25];
-    double th[25][25], l2[25][25], Om[4][25];
+    int64_t src[NMAX];
+    double th[NMAX][NMAX], l2[NMAX][NMAX], Om[4][NMAX];
     const double *base = img + b * mn * 3;
     window_members(M, N, w, r, c, src);
     for (int u = 0; u < n; ++u)

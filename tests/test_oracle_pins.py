@@ -232,11 +232,11 @@ def _mp_filter(img, w, kind, p, dist):
     return A, D
 
 
-@pytest.mark.parametrize("w", [3, 5])
-@pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25), (DDF, 0.5)])
-@pytest.mark.parametrize("dist", [EXACT, RGB])
+@pytest.mark.parametrize("w,kind,p,dist", [
+    (w, kind, p, dist) for w in (3, 5) for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 0.5))
+    for dist in (EXACT, RGB)] + [(7, BVDF, 0.0, EXACT), (7, DDF, 0.25, EXACT)])
 def test_filter_vs_50_digit_bruteforce(w, kind, p, dist):
-    img = _tiny_image(w * 10 + kind, 5 if w == 5 else 6, 5)
+    img = _tiny_image(w * 10 + kind, {3: 6, 5: 5, 7: 4}[w], 5)
     out, idx, A, D, O = oracle.filter(img, w, kind, p, dist, aggregates=True)
     mA, mD = _mp_filter(img, w, kind, p, dist)
     assert np.allclose(A, mA, rtol=1e-13, atol=1e-13)
@@ -260,7 +260,7 @@ def test_filter_vs_50_digit_bruteforce(w, kind, p, dist):
 
 
 @pytest.mark.parametrize("q", [2, 3, 4])
-@pytest.mark.parametrize("w", [3, 5])
+@pytest.mark.parametrize("w", [3, 5, 7])
 def test_minimax_aggregates_within_table1_bound(q, w):
     img = _tiny_image(70 + q, 8, 8)
     _, _, Ae, _, _ = oracle.filter(img, w, BVDF, 0, EXACT, aggregates=True)
@@ -302,7 +302,7 @@ def test_ddf_p0_equals_bvdf():
             assert np.array_equal(i0, ib)
 
 
-@pytest.mark.parametrize("w", [3, 5])
+@pytest.mark.parametrize("w", [3, 5, 7])
 def test_ddf_p1_is_vector_median(w):
     """p = 1 orders by the aggregated L2 distance: the vector median filter (eq. 1)."""
     img = _tiny_image(4, 20, 18)
@@ -313,7 +313,7 @@ def test_ddf_p1_is_vector_median(w):
     assert _near_tie_ok(idx, ref, dist)
 
 
-@pytest.mark.parametrize("w", [3, 5])
+@pytest.mark.parametrize("w", [3, 5, 7])
 def test_ddf_half_is_eq3_product(w):
     """p = 1/2 orders by sqrt(A D): the product form of eq. (3)."""
     img = _tiny_image(5, 20, 18)
@@ -369,6 +369,11 @@ def test_lone_impulse_never_selected(kind, p, dist):
         a = A[4, 4]
         assert a[4] == pytest.approx(8 * a[0], rel=1e-14)
         assert O[4, 4, 4] == pytest.approx(8 * O[4, 4, 0], rel=1e-12)
+    # 7x7: the impulse's aggregate is 48 times a background member's
+    out7, _, A7, _, _ = oracle.filter(img, 7, kind, p, dist, aggregates=True)
+    assert np.all(out7 == np.array([100, 50, 20], float))
+    if dist == EXACT:
+        assert A7[4, 4, 24] == pytest.approx(48 * A7[4, 4, 0], rel=1e-14)
 
 
 def test_channel_permutation_keeps_selection():
@@ -394,7 +399,7 @@ def test_collinear_window_selects_first_member():
 def test_backward_hard_routes_and_conserves():
     rng = np.random.default_rng(2)
     img = _tiny_image(13, 12, 10)
-    for w in (3, 5):
+    for w in (3, 5, 7):
         _, idx = oracle.filter(img, w, DDF, 0.25, EXACT)
         dy = rng.standard_normal(img.shape)
         dx = oracle.backward_hard(idx, dy, w)

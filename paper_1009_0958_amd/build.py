@@ -29,14 +29,39 @@ def sources():
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    """Compile every HIP source into ``libodf.so`` (always recompiles)."""
+    """Compile every HIP source into ``libodf.so`` (always recompiles): one
+    object per source, compiled in parallel, then one link."""
+    import shutil
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *sources(), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    objdir = tempfile.mkdtemp(prefix="odf_build_")
+    cflags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc, *cflags, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+               "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    try:
+        srcs = sources()
+        # the large forward units first, so that they start early
+        srcs.sort(key=lambda f: 0 if os.path.basename(f).startswith("fwd") else 1)
+        workers = max(1, min(len(srcs), os.cpu_count() or 4, 8))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            objs = list(ex.map(compile_one, srcs))
+        cmd = [hipcc, *HIPCC_FLAGS, *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+    finally:
+        shutil.rmtree(objdir, ignore_errors=True)
     os.replace(tmp, LIB)
     return LIB
 

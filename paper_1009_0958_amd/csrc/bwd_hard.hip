@@ -48,8 +48,10 @@ hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy,
     dim3 grid((N + 63) / 64, (M + 3) / 4, B);
     if (window == 3)
         hipLaunchKernelGGL(bwd_hard_kernel<3>, grid, dim3(256), 0, stream, idx, dy, dx, M, N);
-    else
+    else if (window == 5)
         hipLaunchKernelGGL(bwd_hard_kernel<5>, grid, dim3(256), 0, stream, idx, dy, dx, M, N);
+    else
+        hipLaunchKernelGGL(bwd_hard_kernel<7>, grid, dim3(256), 0, stream, idx, dy, dx, M, N);
     return hipGetLastError();
 }
 

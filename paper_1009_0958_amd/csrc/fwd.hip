@@ -1,16 +1,8 @@
-// fwd.hip -- per-image forward kernels (one workgroup per output tile) and
-// their tile-shape table.
-#include "fwd_tile.h"
+// fwd.hip -- the tile-shape table of the forward filter, the 3x3
+// instantiations and the dispatch over window sizes.
+#include "fwd_launch.h"
 
 namespace odf {
-
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
-__global__ void __launch_bounds__(EXT_W* EXT_H) fwd_kernel(FwdParams prm) {
-    __shared__ FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG> sh;
-    using Gm = FwdGeom<W, EXT_W, EXT_H>;
-    fwd_tile<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>(sh, prm, blockIdx.z, blockIdx.y * Gm::TH,
-                                                   blockIdx.x * Gm::TW, threadIdx.x);
-}
 
 // Extended-tile shapes (EXT_W x EXT_H, one thread per extended pixel) the
 // autotuner chooses from.
@@ -19,15 +11,16 @@ constexpr int kTileW[kNumTileConfigs] = {32, 64, 32, 64};
 constexpr int kTileH[kNumTileConfigs] = {32, 16, 16, 8};
 
 // 5x5 ACWDDF keeps four register sets of n values per thread (aggregates
-// and centre terms of both passes): 512-thread tiles only.
+// and centre terms of both passes) and 7x7 keeps a 13 x 7 grid of row sums:
+// 512-thread tiles only.
 bool tile_config_valid(int window, int kind, int cfg) {
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
-    if (window == 5 && kind == kACW) return kTileW[cfg] * kTileH[cfg] <= 512;
+    if ((window == 5 && kind == kACW) || window == 7) return kTileW[cfg] * kTileH[cfg] <= 512;
     return true;
 }
 
 int tile_config_default(int window, int kind) {
-    return window == 5 && kind == kACW ? 2 : 0;
+    return (window == 5 && kind == kACW) || window == 7 ? 2 : 0;
 }
 
 void tile_config_shape(int cfg, int* ext_w, int* ext_h) {
@@ -35,72 +28,11 @@ void tile_config_shape(int cfg, int* ext_w, int* ext_h) {
     *ext_h = kTileH[cfg];
 }
 
-template <int W, int KIND, int DIST, bool U8, bool AGG, int EXT_W, int EXT_H>
-static hipError_t launch_shape(const FwdParams& prm, hipStream_t stream) {
-    using Gm = FwdGeom<W, EXT_W, EXT_H>;
-    dim3 grid((prm.N + Gm::TW - 1) / Gm::TW, (prm.M + Gm::TH - 1) / Gm::TH, prm.B);
-    hipLaunchKernelGGL((fwd_kernel<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>), grid, dim3(Gm::NT), 0,
-                       stream, prm);
-    return hipGetLastError();
-}
-
-template <int W, int KIND, int DIST, bool U8, bool AGG>
-static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
-    if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
-        (void)cfg;
-        return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-    } else if constexpr (W == 5 && KIND == kACW) {
-        switch (cfg) {
-        case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-        case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (cfg) {
-        case 0: return launch_shape<W, KIND, DIST, U8, AGG, 32, 32>(prm, stream);
-        case 1: return launch_shape<W, KIND, DIST, U8, AGG, 64, 16>(prm, stream);
-        case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-        default: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
-        }
-    }
-}
-
-template <int W, int KIND, int DIST>
-static hipError_t launch_wkd(bool u8, bool agg, int cfg, const FwdParams& prm, hipStream_t s) {
-    if constexpr (KIND == kACW) {  // no aggregate-inspection form
-        if (agg) return hipErrorInvalidValue;
-        return u8 ? launch_t<W, KIND, DIST, true, false>(cfg, prm, s)
-                  : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
-    } else {
-        if (u8) return agg ? launch_t<W, KIND, DIST, true, true>(cfg, prm, s)
-                           : launch_t<W, KIND, DIST, true, false>(cfg, prm, s);
-        return agg ? launch_t<W, KIND, DIST, false, true>(cfg, prm, s)
-                   : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
-    }
-}
-
-template <int W, int KIND>
-static hipError_t launch_wk(int dist, bool u8, bool agg, int cfg, const FwdParams& prm,
-                            hipStream_t s) {
-    switch (dist) {
-    case kExact: return launch_wkd<W, KIND, kExact>(u8, agg, cfg, prm, s);
-    case kMinimax: return launch_wkd<W, KIND, kMinimax>(u8, agg, cfg, prm, s);
-    default: return launch_wkd<W, KIND, kRgb>(u8, agg, cfg, prm, s);
-    }
-}
-
-template <int W>
-static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const FwdParams& prm,
-                           hipStream_t s) {
-    if (kind == kBVDF) return launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s);
-    if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
-    return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
-}
-
 hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates, int cfg,
                           const FwdParams& prm, hipStream_t stream) {
     if (window == 3) return launch_w<3>(kind, dist, u8, aggregates, cfg, prm, stream);
-    return launch_w<5>(kind, dist, u8, aggregates, cfg, prm, stream);
+    if (window == 5) return launch_forward5(kind, dist, u8, aggregates, cfg, prm, stream);
+    return launch_forward7(kind, dist, u8, aggregates, cfg, prm, stream);
 }
 
 }  // namespace odf

@@ -1,0 +1,87 @@
+// fwd_launch.h -- the per-image forward kernel (one workgroup per output
+// tile) and its launch templates; each window size is instantiated in a
+// translation unit of its own (fwd.hip, fwd5.hip, fwd7.hip).
+#pragma once
+
+#include "fwd_tile.h"
+
+namespace odf {
+
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
+__global__ void __launch_bounds__(EXT_W* EXT_H) fwd_kernel(FwdParams prm) {
+    __shared__ FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG> sh;
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    fwd_tile<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>(sh, prm, blockIdx.z, blockIdx.y * Gm::TH,
+                                                   blockIdx.x * Gm::TW, threadIdx.x);
+}
+
+template <int W, int KIND, int DIST, bool U8, bool AGG, int EXT_W, int EXT_H>
+static hipError_t launch_shape(const FwdParams& prm, hipStream_t stream) {
+    using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    dim3 grid((prm.N + Gm::TW - 1) / Gm::TW, (prm.M + Gm::TH - 1) / Gm::TH, prm.B);
+    hipLaunchKernelGGL((fwd_kernel<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>), grid, dim3(Gm::NT), 0,
+                       stream, prm);
+    return hipGetLastError();
+}
+
+template <int W, int KIND, int DIST, bool U8, bool AGG>
+static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
+    if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
+        (void)cfg;
+        return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+    } else if constexpr ((W == 5 && KIND == kACW) || W == 7) {
+        switch (cfg) {
+        case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+        case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (cfg) {
+        case 0: return launch_shape<W, KIND, DIST, U8, AGG, 32, 32>(prm, stream);
+        case 1: return launch_shape<W, KIND, DIST, U8, AGG, 64, 16>(prm, stream);
+        case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+        default: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+        }
+    }
+}
+
+template <int W, int KIND, int DIST>
+static hipError_t launch_wkd(bool u8, bool agg, int cfg, const FwdParams& prm, hipStream_t s) {
+    if constexpr (KIND == kACW) {  // no aggregate-inspection form
+        if (agg) return hipErrorInvalidValue;
+        return u8 ? launch_t<W, KIND, DIST, true, false>(cfg, prm, s)
+                  : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
+    } else {
+        if (u8) return agg ? launch_t<W, KIND, DIST, true, true>(cfg, prm, s)
+                           : launch_t<W, KIND, DIST, true, false>(cfg, prm, s);
+        return agg ? launch_t<W, KIND, DIST, false, true>(cfg, prm, s)
+                   : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
+    }
+}
+
+template <int W, int KIND>
+static hipError_t launch_wk(int dist, bool u8, bool agg, int cfg, const FwdParams& prm,
+                            hipStream_t s) {
+    switch (dist) {
+    case kExact: return launch_wkd<W, KIND, kExact>(u8, agg, cfg, prm, s);
+    case kMinimax: return launch_wkd<W, KIND, kMinimax>(u8, agg, cfg, prm, s);
+    default: return launch_wkd<W, KIND, kRgb>(u8, agg, cfg, prm, s);
+    }
+}
+
+template <int W>
+static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const FwdParams& prm,
+                           hipStream_t s) {
+    if (kind == kBVDF) return launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s);
+    if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
+    if constexpr (W == 7) return hipErrorInvalidValue;  // no 7x7 ACWDDF
+    else return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
+}
+
+// Launchers of the window sizes instantiated in fwd5.hip and fwd7.hip.
+hipError_t launch_forward5(int kind, int dist, bool u8, bool aggregates, int cfg,
+                           const FwdParams& prm, hipStream_t stream);
+hipError_t launch_forward7(int kind, int dist, bool u8, bool aggregates, int cfg,
+                           const FwdParams& prm, hipStream_t stream);
+
+}  // namespace odf

@@ -42,7 +42,7 @@ __device__ __forceinline__ uint32_t objective_bits(float v, bool may_be_negative
 
 template <int W, int KIND, bool AGG>
 constexpr bool stage_angle_part() {
-    return W == 5 && KIND == kDDF && !AGG;
+    return W >= 5 && KIND == kDDF && !AGG;
 }
 
 // 3x3 DDF and ACWDDF sweep the angular and L2 terms together (PASS 2 of

@@ -18,18 +18,20 @@ namespace odf {
 
 namespace {
 
-// [window 3/5][kind BVDF/DDF/ACWDDF][dist][u8]
-std::atomic<int> g_table[2][3][3][2];
+// [window 3/5/7][kind BVDF/DDF/ACWDDF][dist][u8]
+std::atomic<int> g_table[3][3][3][2];
+
+int window_slot(int window) { return window == 3 ? 0 : (window == 5 ? 1 : 2); }
 std::atomic<bool> g_table_init{false};
 
 void ensure_init() {
     bool expect = false;
     if (!g_table_init.load()) {
-        for (int w = 0; w < 2; ++w)
+        for (int w = 0; w < 3; ++w)
             for (int k = 0; k < 3; ++k)
                 for (int d = 0; d < 3; ++d)
                     for (int u = 0; u < 2; ++u)
-                        g_table[w][k][d][u].store(tile_config_default(w ? 5 : 3, k));
+                        g_table[w][k][d][u].store(tile_config_default(3 + 2 * w, k));
         g_table_init.compare_exchange_strong(expect, true);
     }
 }
@@ -38,12 +40,12 @@ void ensure_init() {
 
 int tuned_config(int window, int kind, int dist, bool u8) {
     ensure_init();
-    return g_table[window == 5][kind][dist][u8 ? 1 : 0].load();
+    return g_table[window_slot(window)][kind][dist][u8 ? 1 : 0].load();
 }
 
 void set_tuned_config(int window, int kind, int dist, bool u8, int cfg) {
     ensure_init();
-    g_table[window == 5][kind][dist][u8 ? 1 : 0].store(cfg);
+    g_table[window_slot(window)][kind][dist][u8 ? 1 : 0].store(cfg);
 }
 
 }  // namespace odf
@@ -58,6 +60,14 @@ uint64_t splitmix(uint64_t& s) {
     return z ^ (z >> 31);
 }
 
+// A (window, kind, dist) class the library computes (7x7 ACWDDF is not).
+bool valid_class(int window, int kind, int dist) {
+    if (window != 3 && window != 5 && window != 7) return false;
+    if (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) return false;
+    if (window == 7 && kind == ODF_ACWDDF) return false;
+    return dist >= 0 && dist <= 2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -69,15 +79,12 @@ int odf_tile_config(int config, int* ext_w, int* ext_h) {
 }
 
 int odf_tune_get(int window, int kind, int dist, int is_u8) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) || dist < 0 ||
-        dist > 2)
-        return ODF_EINVAL;
+    if (!valid_class(window, kind, dist)) return ODF_EINVAL;
     return odf::tuned_config(window, kind, dist, is_u8 != 0);
 }
 
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) || dist < 0 ||
-        dist > 2 || !odf::tile_config_valid(window, kind, config))
+    if (!valid_class(window, kind, dist) || !odf::tile_config_valid(window, kind, config))
         return ODF_EINVAL;
     odf::set_tuned_config(window, kind, dist, is_u8 != 0, config);
     return ODF_OK;
@@ -85,8 +92,8 @@ int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
 
 int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
                  const char* cache_path, float* times_ms, void* stream) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) || dist < 0 ||
-        dist > 2 || M < 1 || N < 1 || reps < 1 || (long long)M * N >= (1ll << 28))
+    if (!valid_class(window, kind, dist) || M < 1 || N < 1 || reps < 1 ||
+        (long long)M * N >= (1ll << 28))
         return odf::set_error(ODF_EINVAL, "autotune: arguments out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t npix = (size_t)M * N;

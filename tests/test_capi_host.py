@@ -31,7 +31,7 @@ def _u8(img, B, M, N, w, kind, p, dist, q, out, idx=None):
     ((FAKE, 1, -1, 8, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
     ((FAKE, 1, 8, 0, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
     ((FAKE, 4096, 4096, 4096, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "2^31"),
-    ((FAKE, 1, 8, 8, 7, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 9, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 4, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 3, 2, 0.0, 0, 4, FAKE2), odf.EINVAL, "kind"),
     ((FAKE, 1, 8, 8, 3, 0, 0.0, 3, 4, FAKE2), odf.EINVAL, "dist"),
@@ -116,6 +116,7 @@ def test_batch_and_tune_argument_errors():
     ((None, 1, 8, 8, 3, 0, 4, 2, 10.8, FAKE2), odf.EINVAL, "img"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 2, 10.8, None), odf.EINVAL, "out"),
     ((FAKE, 1, 8, 8, 7, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 9, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 3, 3, 4, 2, 10.8, FAKE2), odf.EINVAL, "dist"),
     ((FAKE, 1, 8, 8, 3, 1, 7, 2, 10.8, FAKE2), odf.EINVAL, "q"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 0, 10.8, FAKE2), odf.EINVAL, "lambda"),
@@ -139,6 +140,9 @@ def test_acwddf_tuning_table():
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 3) == odf.OK
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 2) == odf.OK
     assert L.odf_tune_get(3, 3, 0, 1) == odf.EINVAL
+    assert L.odf_tune_get(7, odf.ACWDDF, 0, 1) == odf.EINVAL  # no 7x7 ACWDDF
+    assert L.odf_tune_get(7, odf.DDF, 0, 1) == 2
+    assert L.odf_tune_set(7, odf.DDF, 0, 1, 1) == odf.EINVAL  # 512-thread shapes only
 
 
 def test_noise_and_quality_reject():
@@ -161,3 +165,10 @@ def test_noise_and_quality_reject():
                             None) == odf.EINVAL
     assert L.odf_quality_u8(FAKE, FAKE2, 70000, 1, 1, W, W, W, 1 << 20, None) == odf.EINVAL
     assert L.odf_quality_u8(None, FAKE2, 1, 4, 4, W, W, W, 64, None) == odf.EINVAL
+
+
+def test_window7_limits():
+    L = odf.lib()
+    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 7, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert "softmin" in odf.last_error()
+    assert L.odf_softmin_bwd_workspace(1, 8, 8, 7, 1) == 0

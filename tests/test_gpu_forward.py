@@ -64,6 +64,13 @@ def test_window5_ragged(kind, p, dist):
     run_and_check(img, 5, kind, p, dist)
 
 
+@pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25), (DDF, 0.5)])
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+def test_window7_ragged(kind, p, dist):
+    img = synth.image_corr(45, 71, 0.15, key=7)
+    run_and_check(img, 7, kind, p, dist)
+
+
 @pytest.mark.parametrize("q", [2, 3, 4])
 @pytest.mark.parametrize("window", [3, 5])
 def test_minimax_degrees(q, window):
@@ -72,7 +79,7 @@ def test_minimax_degrees(q, window):
     run_and_check(img, window, BVDF, 0.0, MINIMAX, q)
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25), (DDF, 1.0), (DDF, 0.0)])
 def test_float_inputs_exact(window, kind, p):
     img = synth.float_batch(2, 45, 70, 0.1, key=window)
@@ -81,7 +88,7 @@ def test_float_inputs_exact(window, kind, p):
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (30, 30), (31, 29), (28, 28),
                                    (29, 57), (5, 200)])
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 def test_edge_shapes(shape, window):
     rng = np.random.default_rng(sum(shape) * window)
     img = rng.integers(0, 256, shape + (3,)).astype(np.uint8)
@@ -155,7 +162,8 @@ def test_deterministic_repeat():
 
 @pytest.mark.parametrize("window,kind,p,dist", [
     (3, DDF, 0.25, EXACT), (3, DDF, 0.5, EXACT), (3, DDF, 0.25, MINIMAX), (3, DDF, 0.5, RGB),
-    (5, BVDF, 0.0, EXACT), (5, DDF, 0.25, EXACT), (5, DDF, 0.25, MINIMAX), (5, DDF, 0.25, RGB)])
+    (5, BVDF, 0.0, EXACT), (5, DDF, 0.25, EXACT), (5, DDF, 0.25, MINIMAX), (5, DDF, 0.25, RGB),
+    (7, BVDF, 0.0, EXACT), (7, DDF, 0.25, EXACT)])
 def test_full_size_sampled(window, kind, p, dist):
     """1024 x 1024 with correlated noise 0.20: the whole image on the GPU,
     checked on 20 000 seeded sample pixels (plus the four corners) by the oracle."""
@@ -171,3 +179,17 @@ def test_full_size_sampled(window, kind, p, dist):
     check_selection(idx.reshape(-1)[pix], oO)
     src = source_pixels(img, idx, window).reshape(-1, 3)
     assert np.array_equal(out.reshape(-1, 3), src)
+
+
+@pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25)])
+def test_window7_tile_shapes_identical(kind, p):
+    x = _gpu(synth.image_corr(100, 130, 0.2, key=17))
+    saved = odf.tune_get(7, kind, EXACT, True)
+    try:
+        odf.tune_set(7, kind, EXACT, True, 2)
+        a = odf.filter(x, 7, kind, p, EXACT)
+        odf.tune_set(7, kind, EXACT, True, 3)
+        b = odf.filter(x, 7, kind, p, EXACT)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    finally:
+        odf.tune_set(7, kind, EXACT, True, saved)

@@ -22,7 +22,7 @@ def _gpu(x):
 
 # ------------------------------------------------------------------ hard backward
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("shape", [(2, 37, 45), (1, 1, 1), (1, 3, 70), (3, 64, 64)])
 def test_backward_hard_matches_oracle_bitwise(window, shape):
     print("case: hard bwd w=%d shape=%s" % (window, shape), flush=True)

@@ -327,12 +327,13 @@ def main():
 
 
 def large_frame_forms(torch, odf, synth, dev, DIST):
-    """7680 x 4320 frame and 64 x 1920 x 1080 frames, correlated noise 0.15
-    (tile shapes autotuned per class first, untimed)."""
+    """7680 x 4320 frame (3x3 BVDF, 5x5 and 7x7) and 64 x 1920 x 1080 frames
+    (5x5), correlated noise 0.15 (tile shapes autotuned per class first,
+    untimed)."""
     forms = {}
-    for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF)):
+    for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF)):
         for d in ("exact", "minimax", "rgb"):
-            odf.autotune(w, kk, DIST[d], True, 1024, 1024, 5)
+            odf.autotune(w, kk, DIST[d], True, 1024, 1024, 3)
     for tag, shape, key in (("7680x4320", (1, 4320, 7680), 5), ("64x1920x1080", (64, 1080, 1920), 6)):
         B, M, N = shape
         imgs = np.stack([synth.image_corr(M, N, 0.15, key=key * 100 + b) for b in range(B)])
@@ -341,8 +342,9 @@ def large_frame_forms(torch, odf, synth, dev, DIST):
         bo = torch.empty_like(big)
         bi = torch.empty((B, M, N), dtype=torch.uint8, device=dev)
         npx = B * M * N
-        for w, kind, p in ((3, "bvdf", 0.0), (5, "bvdf", 0.0), (5, "ddf", 0.25)):
-            if tag != "7680x4320" and w == 3:
+        for w, kind, p in ((3, "bvdf", 0.0), (5, "bvdf", 0.0), (5, "ddf", 0.25), (7, "bvdf", 0.0),
+                           (7, "ddf", 0.25)):
+            if tag != "7680x4320" and w in (3, 7):
                 continue
             for d in ("exact", "minimax", "rgb"):
                 kk = odf.BVDF if kind == "bvdf" else odf.DDF

@@ -6,7 +6,7 @@
  * directional filters", arXiv:1009.0958.
  *
  * Every image is an RGB array in HWC order: pixel (b, r, c) channel k lives at
- * element ((b*M + r)*N + c)*3 + k.  A window of w x w pixels (w = 3 or 5) is
+ * element ((b*M + r)*N + c)*3 + k.  A window of w x w pixels (w = 3, 5 or 7) is
  * centred on each pixel; border windows repeat the nearest edge pixel
  * (replicated border), so every window has n = w*w members.  Members are
  * numbered u = 0..n-1 row-major inside the window; the centre is (n-1)/2.
@@ -36,7 +36,7 @@ extern "C" {
 typedef enum {
     ODF_OK = 0,
     ODF_EINVAL = -1,        /* bad argument (null pointer, size, range, aliasing) */
-    ODF_EUNSUPPORTED = -2,  /* valid request this build does not provide (e.g. w = 7) */
+    ODF_EUNSUPPORTED = -2,  /* valid request this build does not provide (e.g. w = 9) */
     ODF_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
     ODF_ENOMEM = -4         /* a library-side allocation failed */
 } odf_status;
@@ -73,12 +73,12 @@ const char* odf_last_error(void);
  *         window member.
  *   idx   B x M x N uint8 or NULL: the selected member index u in 0..n-1.
  *         Ties go to the lowest index.
- *   window 3 or 5; kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only, ignored by
+ *   window 3, 5 or 7; kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only, ignored by
  *         BVDF); dist ODF_EXACT / ODF_MINIMAX / ODF_RGB; q in {2, 3, 4} for
  *         ODF_MINIMAX (ignored otherwise).
  * Zero pixels take the direction (1,1,1) in the angle and chromaticity terms.
  * Errors: ODF_EINVAL for null img/out, sizes < 1, out overlapping img, or a
- * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5};
+ * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5, 7};
  * ODF_EHIP if the launch fails.
  */
 int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, float p,
@@ -113,6 +113,7 @@ int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, 
  *          paper's setting is lambda = 2, T = 10.8 (angles in radians, L2 in
  *          the units of the image values).
  *   T      any value but NaN (+inf keeps every centre; below 0 gives the DDF).
+ * Windows 3 and 5 (ODF_EUNSUPPORTED for 7).
  * Errors: as odf_filter_u8, plus ODF_EINVAL for lambda out of range or T NaN.
  */
 int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
@@ -146,7 +147,8 @@ int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, 
  *        selecting an out-of-image position selects its clamped source).  Each
  *        sum is formed in binary64 over c in raster order and rounded once.
  * The forward selection is not touched.  Errors: ODF_EINVAL for null
- * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for window.
+ * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for a window
+ * other than 3, 5 or 7.
  */
 int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int N, int window,
                           float* dx, void* stream);
@@ -157,6 +159,7 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
  * y(c) = sum_u pi_u x_u.  tau -> 0 tends to the hard selection where the
  * minimum is unique.
  *   x  B x M x N x 3 float32 (read only); y  B x M x N x 3 float32 output.
+ * Windows 3 and 5 (ODF_EUNSUPPORTED for 7).
  * Errors: as odf_filter_f32, plus ODF_EINVAL for tau <= 0 or not finite.
  */
 int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,
@@ -185,8 +188,9 @@ int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, in
 /* ---------------------------------------------------------------- batches
  * Many uint8 images of different sizes, windows and variants in one launch.
  * A job is one image with its own parameters (same meaning as the arguments
- * of odf_filter_u8; idx may be NULL).  Results are bitwise equal to those of
- * odf_filter_u8 on each image. */
+ * of odf_filter_u8; idx may be NULL; windows 3 and 5, kinds ODF_BVDF and
+ * ODF_DDF).  Results are bitwise equal to those of odf_filter_u8 on each
+ * image. */
 typedef struct {
     const uint8_t* img; /* M x N x 3 uint8 */
     uint8_t* out;       /* M x N x 3 uint8 */

@@ -26,13 +26,16 @@
 
 namespace odf {
 
-// Extended tile of the softmin kernels (one thread per extended pixel).
-template <int W, int KIND>
+// Extended tile of the softmin kernels (one thread per extended pixel).  The
+// 5x5 forward parks the angle part of every objective in LDS between its two
+// sweeps, which frees the registers for 1024-thread tiles; the backward keeps
+// A, D and Omega in registers and uses 512-thread tiles.
+template <int W, int KIND, bool BWD>
 struct SoftTile {
     static constexpr int EXT_W = 32;
-    static constexpr int EXT_H = 16;
+    static constexpr int EXT_H = (W == 5 && !BWD) ? 32 : 16;
+    static constexpr int NT = EXT_W * EXT_H;
 };
-constexpr int kSoftThreads = 512;
 
 __device__ __forceinline__ float key_value(uint32_t k) {
     uint32_t bits = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
@@ -146,13 +149,12 @@ __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
 }
 
 template <int W, int KIND, bool BWD>
-__global__ void __launch_bounds__(kSoftThreads) softmin_kernel(SoftParams prm) {
-    constexpr int EXT_W = SoftTile<W, KIND>::EXT_W, EXT_H = SoftTile<W, KIND>::EXT_H;
+__global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT)) softmin_kernel(SoftParams prm) {
+    constexpr int EXT_W = SoftTile<W, KIND, BWD>::EXT_W, EXT_H = SoftTile<W, KIND, BWD>::EXT_H;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     constexpr int TT = TW * TH;
     constexpr int NPLANE = BWD ? 2 * G : G;
-    static_assert(NT == kSoftThreads, "one thread per extended pixel");
 
     __shared__ float4 s_dir[NT];
     __shared__ float4 s_raw[NT];
@@ -184,17 +186,6 @@ __global__ void __launch_bounds__(kSoftThreads) softmin_kernel(SoftParams prm) {
     const float4 mraw = s_raw[tid];
     const MinimaxCoef no_coef{};
 
-    float A[NW], D[NW], Om[NW];
-    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex,
-                                                                  tid, mdir, mraw, no_coef, A);
-    if (KIND == kDDF)
-        member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey,
-                                                                     ex, tid, mdir, mraw,
-                                                                     no_coef, D);
-    else
-#pragma unroll
-        for (int u = 0; u < NW; ++u) D[u] = 0.0f;
-
     auto window_of = [&](int u, int& c) -> bool {
         const int cy = ey - u / W, cx = ex - u % W;
         if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) return false;
@@ -203,17 +194,59 @@ __global__ void __launch_bounds__(kSoftThreads) softmin_kernel(SoftParams prm) {
         return true;
     };
 
+    float A[NW], D[NW], Om[NW];
+    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex,
+                                                                  tid, mdir, mraw, no_coef, A);
+    if constexpr (!BWD) {
+        // forward only: the angle part of each objective waits in s_e (same
+        // (member, window) layout) during the L2 sweep; then s_e holds Omega
+        const int mode = (KIND == kBVDF || p == 0.0f) ? 0 : (p == 1.0f ? 1 : 2);
 #pragma unroll
-    for (int u = 0; u < NW; ++u) {
-        Om[u] = objective_value<KIND>(A[u], D[u], p);
-        int c;
-        if (window_of(u, c)) atomicMin(&s_key[c], order_key(Om[u]));
-    }
-    __syncthreads();
+        for (int u = 0; u < NW; ++u) {
+            int c;
+            if (window_of(u, c)) s_e[u * TT + c] = mode == 2 ? (1.0f - p) * log2f(A[u]) : A[u];
+        }
+        if (KIND == kDDF)
+            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey,
+                                                                         ex, tid, mdir, mraw,
+                                                                         no_coef, D);
 #pragma unroll
-    for (int u = 0; u < NW; ++u) {
-        int c;
-        if (window_of(u, c)) s_e[u * TT + c] = __expf((key_value(s_key[c]) - Om[u]) * inv_tau);
+        for (int u = 0; u < NW; ++u) {
+            int c;
+            if (!window_of(u, c)) continue;
+            const float part = s_e[u * TT + c];
+            const float om = mode == 0 ? part
+                                       : (mode == 1 ? D[u] : exp2f(fmaf(p, log2f(D[u]), part)));
+            s_e[u * TT + c] = om;
+            atomicMin(&s_key[c], order_key(om));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            int c;
+            if (window_of(u, c))
+                s_e[u * TT + c] = __expf((key_value(s_key[c]) - s_e[u * TT + c]) * inv_tau);
+        }
+    } else {
+        if (KIND == kDDF)
+            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey,
+                                                                         ex, tid, mdir, mraw,
+                                                                         no_coef, D);
+        else
+#pragma unroll
+            for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            Om[u] = objective_value<KIND>(A[u], D[u], p);
+            int c;
+            if (window_of(u, c)) atomicMin(&s_key[c], order_key(Om[u]));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            int c;
+            if (window_of(u, c)) s_e[u * TT + c] = __expf((key_value(s_key[c]) - Om[u]) * inv_tau);
+        }
     }
     __syncthreads();
 
@@ -319,7 +352,7 @@ __global__ void __launch_bounds__(kSoftThreads) softmin_kernel(SoftParams prm) {
 // region contains q, in increasing tile order.
 template <int W, int KIND>
 __global__ void __launch_bounds__(256) softmin_combine(SoftParams prm, int tiles_x, int tiles_y) {
-    constexpr int EXT_W = SoftTile<W, KIND>::EXT_W, EXT_H = SoftTile<W, KIND>::EXT_H;
+    constexpr int EXT_W = SoftTile<W, KIND, true>::EXT_W, EXT_H = SoftTile<W, KIND, true>::EXT_H;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -350,9 +383,9 @@ __global__ void __launch_bounds__(256) softmin_combine(SoftParams prm, int tiles
     o[2] = a2;
 }
 
-template <int W, int KIND>
+template <int W, int KIND, bool BWD>
 static void soft_grid(const SoftParams& prm, int& tx, int& ty, int& nt) {
-    using Gm = FwdGeom<W, SoftTile<W, KIND>::EXT_W, SoftTile<W, KIND>::EXT_H>;
+    using Gm = FwdGeom<W, SoftTile<W, KIND, BWD>::EXT_W, SoftTile<W, KIND, BWD>::EXT_H>;
     tx = (prm.N + Gm::TW - 1) / Gm::TW;
     ty = (prm.M + Gm::TH - 1) / Gm::TH;
     nt = Gm::NT;
@@ -361,12 +394,14 @@ static void soft_grid(const SoftParams& prm, int& tx, int& ty, int& nt) {
 template <int W, int KIND>
 static hipError_t launch_soft_t(bool bwd, const SoftParams& prm, hipStream_t s) {
     int tx, ty, nt;
-    soft_grid<W, KIND>(prm, tx, ty, nt);
-    dim3 grid(tx, ty, prm.B);
     if (!bwd) {
-        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>), grid, dim3(nt), 0, s, prm);
+        soft_grid<W, KIND, false>(prm, tx, ty, nt);
+        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>), dim3(tx, ty, prm.B), dim3(nt), 0, s,
+                           prm);
         return hipGetLastError();
     }
+    soft_grid<W, KIND, true>(prm, tx, ty, nt);
+    dim3 grid(tx, ty, prm.B);
     hipLaunchKernelGGL((softmin_kernel<W, KIND, true>), grid, dim3(nt), 0, s, prm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -380,9 +415,11 @@ size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
     prm.B = B; prm.M = M; prm.N = N;
     int tx, ty, nt;
     if (window == 3) {
-        if (kind == kBVDF) soft_grid<3, kBVDF>(prm, tx, ty, nt); else soft_grid<3, kDDF>(prm, tx, ty, nt);
+        if (kind == kBVDF) soft_grid<3, kBVDF, true>(prm, tx, ty, nt);
+        else soft_grid<3, kDDF, true>(prm, tx, ty, nt);
     } else {
-        if (kind == kBVDF) soft_grid<5, kBVDF>(prm, tx, ty, nt); else soft_grid<5, kDDF>(prm, tx, ty, nt);
+        if (kind == kBVDF) soft_grid<5, kBVDF, true>(prm, tx, ty, nt);
+        else soft_grid<5, kDDF, true>(prm, tx, ty, nt);
     }
     return (size_t)B * tx * ty * nt * 3 * sizeof(float);
 }

@@ -86,21 +86,33 @@ __device__ __forceinline__ float3 l2_grad(const float4& a, const float4& b) {
     return make_float3(e0 * il, e1 * il, e2 * il);
 }
 
-// Sum of gr[u] over members u = (uy, ux) of windows containing both p and p + d.
+// 2D prefix sums of the member gradients gr (row-major w x w):
+// P[i][j] = sum of gr over rows < i and columns < j.
 template <int W>
-__device__ __forceinline__ float box_over_members(const float (&gr)[W * W], int dy, int dx) {
-    constexpr int H = W / 2;
-    float acc = 0.0f;
+__device__ __forceinline__ void member_prefix(const float (&gr)[W * W], float (&P)[W + 1][W + 1]) {
 #pragma unroll
-    for (int uy = -H; uy <= H; ++uy) {
-        if (uy + dy < -H || uy + dy > H) continue;
+    for (int j = 0; j <= W; ++j) P[0][j] = 0.0f;
 #pragma unroll
-        for (int ux = -H; ux <= H; ++ux) {
-            if (ux + dx < -H || ux + dx > H) continue;
-            acc += gr[(uy + H) * W + (ux + H)];
+    for (int y = 0; y < W; ++y) {
+        P[y + 1][0] = 0.0f;
+        float row = 0.0f;
+#pragma unroll
+        for (int x = 0; x < W; ++x) {
+            row += gr[y * W + x];
+            P[y + 1][x + 1] = P[y][x + 1] + row;
         }
     }
-    return acc;
+}
+
+// Sum of gr[u] over the members u = (uy, ux) of windows containing both p and
+// p + d: the rectangle uy in [max(-h, -h - dy), min(h, h - dy)] (and likewise
+// for ux), read from the prefix table (d is a compile-time offset).
+template <int W>
+__device__ __forceinline__ float box_over_members(const float (&P)[W + 1][W + 1], int dy, int dx) {
+    constexpr int H = W / 2;
+    const int y0 = dy < 0 ? -dy : 0, y1 = dy > 0 ? 2 * H - dy : 2 * H;
+    const int x0 = dx < 0 ? -dx : 0, x1 = dx > 0 ? 2 * H - dx : 2 * H;
+    return (P[y1 + 1][x1 + 1] - P[y0][x1 + 1]) - (P[y1 + 1][x0] - P[y0][x0]);
 }
 
 // Pair-term part of the gradient for one plane (angle, or L2 when L2PASS):
@@ -116,13 +128,15 @@ __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
     constexpr int H = W / 2, G = 4 * H + 1, NT = EXT_W * EXT_H;
     float* P_dn = s_plane;           // B_r((-g, -dx)), read by the pixel r - (g, dx)
     float* P_up = s_plane + G * NT;  // B_r((g, -dx)),  read by the pixel r - (-g, dx)
+    float Pt[W + 1][W + 1];
+    member_prefix<W>(gr, Pt);
 #pragma unroll
     for (int g = 0; g <= 2 * H; ++g) {
 #pragma unroll
         for (int dx = -2 * H; dx <= 2 * H; ++dx) {
             if (g == 0 && dx == 0) continue;
-            P_dn[(dx + 2 * H) * NT + tid] = box_over_members<W>(gr, -g, -dx);
-            if (g > 0) P_up[(dx + 2 * H) * NT + tid] = box_over_members<W>(gr, g, -dx);
+            P_dn[(dx + 2 * H) * NT + tid] = box_over_members<W>(Pt, -g, -dx);
+            if (g > 0) P_up[(dx + 2 * H) * NT + tid] = box_over_members<W>(Pt, g, -dx);
         }
         __syncthreads();
 #pragma unroll
@@ -135,8 +149,7 @@ __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
                 const int ry = ey + sgn * g, rx = ex + dx;
                 if (ry < 0 || ry >= EXT_H || rx < 0 || rx >= EXT_W) continue;
                 const int r = ry * EXT_W + rx;
-                const float S = box_over_members<W>(gr, sgn * g, dx) + P[(dx + 2 * H) * NT + r];
-                if (S == 0.0f) continue;
+                const float S = box_over_members<W>(Pt, sgn * g, dx) + P[(dx + 2 * H) * NT + r];
                 const float3 gv = L2PASS ? l2_grad(mraw, s_raw[r])
                                          : angle_grad(mdir, inv_a2, mraw.w, s_dir[r]);
                 gx0 = fmaf(S, gv.x, gx0);

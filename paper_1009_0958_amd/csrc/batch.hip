@@ -125,7 +125,8 @@ __global__ void __launch_bounds__(BatchShape<persistent_shape<W>()>::THREADS)
 
 // Direct form: one workgroup per tile of the list, dispatched in list order.
 template <int W, int KIND, int DIST, int SHAPE>
-__global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS) batch_direct_kernel(BatchClass bc) {
+__global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(W == 3 ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
     __shared__ FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
     batch_tile<W, KIND, DIST, SHAPE>(sh, bc, blockIdx.x);
 }

@@ -5,7 +5,8 @@
 // Each prepared pixel is two float4 values:
 //   dir = (d.x, d.y, d.z, aux1)   d: direction (the pixel, or (1,1,1) for 0)
 //   raw = (x.x, x.y, x.z, aux2)   x: the raw pixel
-//   EXACT:   aux1 = |x|^2, aux2 = |d| / |x| (a power of two; 0 for x = 0)
+//   EXACT:   aux1 = |x|^2, or -3 for x = 0 (|d|^2 = 3 for d = (1,1,1); the sign
+//            marks the zero pixel), aux2 = |d| / |x| (a power of two; 0 for x = 0)
 //   MINIMAX: aux1 = |d|^2, aux2 = 1/|d|
 //   RGB:     aux1 = d.x + d.y + d.z, aux2 = 1/aux1
 //
@@ -94,7 +95,7 @@ __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, floa
         // |x|^2 of the raw value (exact for uint8), and d = 2^-e x: the
         // derivative of the direction (0 for the zero pixel, whose direction
         // is a constant), used by the angle gradient
-        aux1 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+        aux1 = zero ? -3.0f : fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
         aux2 = zero ? 0.0f : ldexpf(1.0f, -e);
     } else if (DIST == kMinimax) {
         aux1 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
@@ -111,14 +112,30 @@ __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, floa
 // with P = |a x b|^2 and Q = (a.b)^2, r = sqrt(min(P,Q)/max(P,Q)) =
 // min(P,Q) / sqrt(P Q) lies in [0, 1] and the angle is atan(r) or
 // pi/2 - atan(r); one reciprocal square root per pair.
+// |a x b|^2.  uint8 (U8): Lagrange's identity |a|^2 |b|^2 - (a.b)^2 in
+// binary64, exact (every operand an integer below 2^53), from the squared
+// direction norms na, nb and the dot product; otherwise the sum of the squared
+// cross components.
+template <bool U8>
+__device__ __forceinline__ float cross_norm2(const float4& a, const float4& b, float na, float nb,
+                                             float dot) {
+    if constexpr (U8) {
+        const double d = (double)dot;
+        return (float)fma(-d, d, (double)na * (double)nb);
+    } else {
+        float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
+        float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
+        float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
+        return fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+    }
+}
+
 template <bool U8>
 __device__ __forceinline__ float angle_exact_dot(const float4& a, const float4& b, float& dot) {
     constexpr bool SIGNED = !U8;  // float inputs may be negative
     dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
-    float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
-    float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
-    float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
-    float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+    // |d|^2 = |aux1| (the zero pixel's -3 stands for |(1,1,1)|^2)
+    float P = cross_norm2<U8>(a, b, fabsf(a.w), fabsf(b.w), dot);
     float Q = dot * dot;
     float m = fminf(P, Q);
     float r = m * rsq(fmaxf(P * Q, 1.17549435e-38f));
@@ -158,10 +175,7 @@ __device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra
         asm volatile("");                     // keeps the exact test out of the common path
         if (near) acos_branch = 4.0 * (double)dot * (double)dot < (double)a.w * (double)b.w;
     }
-    float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
-    float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
-    float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
-    float P = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+    float P = cross_norm2<U8>(a, b, a.w, b.w, dot);
     float X = (a.w * b.w) * (1.0f + z);
     float tau = P * rsq(fmaxf(P * X, 1.17549435e-38f));
     // the clamp at 0 matters for the ASIN row only (q = 3 dips below 0 next to
@@ -203,8 +217,9 @@ __device__ __forceinline__ float l2_term(const float4& ra, const float4& rb) {
 // squared distance reuses the dot product of the angle:
 // |x_a - x_b|^2 = |x_a|^2 + |x_b|^2 - 2 x_a.x_b, every term an integer exact in
 // binary32, with |x|^2 in dir.w.  A zero pixel (direction (1,1,1), value 0,
-// |x|^2 = 0) has a zero raw dot product; the lanes with one take
-// |x_a|^2 + |x_b|^2 in a branch the wave enters only when some lane needs it.
+// dir.w = -3) has a zero raw dot product and |x|^2 = 0; the lanes with one take
+// max(dir.w, 0) summed over the pair in a branch the wave enters only when some
+// lane needs it.
 template <int KIND, int DIST, bool U8>
 __device__ __forceinline__ float pair_and_l2(const float4& a, const float4& ra,
                                              const float4* __restrict__ s_dir,
@@ -215,10 +230,10 @@ __device__ __forceinline__ float pair_and_l2(const float4& a, const float4& ra,
         float dot;
         const float th = angle_exact_dot<U8>(a, b, dot);
         float l2sq = fmaf(-2.0f, dot, a.w + b.w);
-        const bool zero = (a.w == 0.0f) | (b.w == 0.0f);
+        const bool zero = (__float_as_int(a.w) | __float_as_int(b.w)) < 0;  // a sign set
         if (__builtin_amdgcn_ballot_w64(zero)) {
             asm volatile("");  // keeps the fix-up out of the common path
-            if (zero) l2sq = a.w + b.w;
+            if (zero) l2sq = fmaxf(a.w, 0.0f) + fmaxf(b.w, 0.0f);
         }
         l2 = sqrt_raw(l2sq);
         return th;

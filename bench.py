@@ -69,8 +69,8 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("rgb", 32, 32): (4078.8, 6144.0), ("rgb", 64, 16): (2895.0, 5056.0),
     ("rgb", 32, 16): (4359.4, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
 }
-TRAFFIC_SOURCES = ("fwd.hip", "fwd_tile.h", "aggregates.h", "pair_terms.h", "atan_poly.h",
-                   "odf_internal.h")
+TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "fwd_tile.h", "aggregates.h", "pair_terms.h",
+                   "atan_poly.h", "odf_internal.h")
 TRAFFIC_SRC_SHA256 = "6d09a2ece8cab8995a4bfa96c1628ff14d315abde6b08b8871244196a7917753"
 
 

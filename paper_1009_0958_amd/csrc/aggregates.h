@@ -42,38 +42,69 @@ __device__ __forceinline__ void row_sums(const float (&row)[4 * (W / 2) + 1], fl
     }
 }
 
+// LDS view of a tile's prepared pixels (pair_terms.h): float inputs use dir
+// and raw, uint8 inputs dir and, for MINIMAX and RGB, the aux2 plane inv.
+struct TilePix {
+    const float4* dir;
+    const float4* raw;
+    const float* inv;
+};
+
 // Aggregates of the own member p over every window containing it.  PASS 0:
 // the angular term into agg0; PASS 1: the L2 term of eq. (1) into agg0;
 // PASS 2: both in one sweep (angular -> agg0, L2 -> agg1) with two LDS plane
 // sets, sharing the neighbour loads, bounds tests and barriers.  agg[u] is the
 // aggregate of p in the window c = p - offset(u).  CEN: also cen[u] = the term
 // of p and that window's centre c (taken from the offset grid, so no extra
-// pair is evaluated).  s_plane holds G * NT floats per term.
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, int PASS, bool CEN>
+// pair is evaluated).  s_plane holds G * NT floats per term.  mraw.w is the
+// member's aux2 (uint8 layout: its other fields are unused).
+//
+// GUARD = false drops the tests that keep neighbours inside the extended tile:
+// a neighbour index then runs past the pixel arrays by up to 2h rows + 2h and a
+// mirrored read before the plane by as much, into whatever LDS the caller
+// placed there (it must be part of the same allocation).  The pair terms so
+// formed are meaningless, but they only enter row sums of windows that reach
+// outside the extended tile -- every window of the output tile has all its
+// members inside it -- so the caller must discard the objectives of those
+// windows.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, int PASS, bool CEN,
+          bool GUARD>
 __device__ __forceinline__ void member_aggregates_x(
-    const float4* __restrict__ s_dir, const float4* __restrict__ s_raw,
-    float* __restrict__ s_plane, int ey, int ex, int tid, const float4& mdir, const float4& mraw,
-    const MinimaxCoef& cf, float (&agg0)[W * W], float (&cen0)[W * W], float (&agg1)[W * W],
-    float (&cen1)[W * W]) {
+    const TilePix& px, float* __restrict__ s_plane, int ey, int ex, int tid, const float4& mdir,
+    const float4& mraw, const MinimaxCoef& cf, float (&agg0)[W * W], float (&cen0)[W * W],
+    float (&agg1)[W * W], float (&cen1)[W * W]) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, G = Gm::G, NT = Gm::NT;
     constexpr int NP = PASS == 2 ? 2 : 1;
+    const bool mzero = U8 && mdir.w < 0.0f;
+    const uint64_t mzero_wave = U8 ? __builtin_amdgcn_ballot_w64(mzero) : 0;
+    const AtanCoef ac = atan_coef();
 
     auto terms = [&](int q, float (&v)[NP]) {
-        if constexpr (PASS == 1) {
-            v[0] = l2_term(mraw, s_raw[q]);
+        if constexpr (U8) {
+            const float4 b = px.dir[q];
+            const float ib = DIST == kExact ? 0.0f : px.inv[q];
+            float th = 0.0f, l2 = 0.0f;
+            pair_u8<KIND, DIST, PASS != 1, PASS != 0>(mdir, mraw.w, mzero, mzero_wave, b, ib, cf,
+                                                      ac, th, l2);
+            v[0] = PASS == 1 ? l2 : th;
+            if constexpr (PASS == 2) v[NP - 1] = l2;
+        } else if constexpr (PASS == 1) {
+            v[0] = l2_term(mraw, px.raw[q]);
         } else if constexpr (PASS == 0) {
-            v[0] = pair_term<KIND, DIST, U8>(mdir, mraw, s_dir[q], s_raw[q], cf);
+            v[0] = pair_term<KIND, DIST, U8>(mdir, mraw, px.dir[q], px.raw[q], cf, ac);
         } else {
-            v[0] = pair_and_l2<KIND, DIST, U8>(mdir, mraw, s_dir, s_raw, q, cf, v[1]);
+            const float4 rb = px.raw[q];
+            v[0] = pair_term<KIND, DIST, U8>(mdir, mraw, px.dir[q], rb, cf, ac);
+            v[NP - 1] = l2_term(mraw, rb);
         }
     };
     float self[NP];
     if constexpr (PASS == 1) {
         self[0] = 0.0f;
     } else {
-        self[0] = pair_term<KIND, DIST, U8>(mdir, mraw, mdir, mraw, cf);
-        if constexpr (NP == 2) self[1] = 0.0f;
+        self[0] = pair_term<KIND, DIST, U8>(mdir, mraw, mdir, mraw, cf, ac);
+        if constexpr (NP == 2) self[NP - 1] = 0.0f;
     }
 
     float R[NP][G][W];  // R[k][dy + 2h][s + 2h]: sum of G_p(dy, s .. s + w - 1), term k
@@ -85,10 +116,10 @@ __device__ __forceinline__ void member_aggregates_x(
 #pragma unroll
             for (int k = 0; k < NP; ++k) own[k][dx + 2 * H] = 0.0f;
             if (g == 0 && dx <= 0) continue;
-            const int py = ey + g, px = ex + dx;
-            if (py < EXT_H && px >= 0 && px < EXT_W) {
+            const int py = ey + g, px_ = ex + dx;
+            if (!GUARD || (py < EXT_H && px_ >= 0 && px_ < EXT_W)) {
                 float v[NP];
-                terms(py * EXT_W + px, v);
+                terms(tid + g * EXT_W + dx, v);
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
                     own[k][dx + 2 * H] = v[k];
@@ -102,11 +133,11 @@ __device__ __forceinline__ void member_aggregates_x(
 #pragma unroll
             for (int k = 0; k < NP; ++k) up[k][dx + 2 * H] = 0.0f;
             if (g == 0 && dx >= 0) continue;
-            const int py = ey - g, px = ex + dx;
-            if (py >= 0 && px >= 0 && px < EXT_W)
+            const int py = ey - g, px_ = ex + dx;
+            if (!GUARD || (py >= 0 && px_ >= 0 && px_ < EXT_W))
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
-                    up[k][dx + 2 * H] = s_plane[(k * G + 2 * H - dx) * NT + py * EXT_W + px];
+                    up[k][dx + 2 * H] = s_plane[(k * G + 2 * H - dx) * NT + tid - g * EXT_W + dx];
         }
         if constexpr (CEN) {
             if (g <= H) {
@@ -159,27 +190,26 @@ __device__ __forceinline__ void member_aggregates_x(
 }
 
 // One term (angular if !L2PASS, else L2), optionally with the centre terms.
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS, bool CEN>
-__device__ __forceinline__ void member_aggregates_c(const float4* __restrict__ s_dir,
-                                                    const float4* __restrict__ s_raw,
-                                                    float* __restrict__ s_plane, int ey, int ex,
-                                                    int tid, const float4& mdir,
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS, bool CEN,
+          bool GUARD = true>
+__device__ __forceinline__ void member_aggregates_c(const TilePix& px, float* __restrict__ s_plane,
+                                                    int ey, int ex, int tid, const float4& mdir,
                                                     const float4& mraw, const MinimaxCoef& cf,
                                                     float (&agg)[W * W], float (&cen)[W * W]) {
     float u0[W * W], u1[W * W];
-    member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, L2PASS ? 1 : 0, CEN>(
-        s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, cf, agg, cen, u0, u1);
+    member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, L2PASS ? 1 : 0, CEN, GUARD>(
+        px, s_plane, ey, ex, tid, mdir, mraw, cf, agg, cen, u0, u1);
 }
 
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS>
-__device__ __forceinline__ void member_aggregates(const float4* __restrict__ s_dir,
-                                                  const float4* __restrict__ s_raw,
-                                                  float* __restrict__ s_plane, int ey, int ex,
-                                                  int tid, const float4& mdir, const float4& mraw,
-                                                  const MinimaxCoef& cf, float (&agg)[W * W]) {
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool L2PASS,
+          bool GUARD = true>
+__device__ __forceinline__ void member_aggregates(const TilePix& px, float* __restrict__ s_plane,
+                                                  int ey, int ex, int tid, const float4& mdir,
+                                                  const float4& mraw, const MinimaxCoef& cf,
+                                                  float (&agg)[W * W]) {
     float unused[W * W];
-    member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, L2PASS, false>(
-        s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, cf, agg, unused);
+    member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, L2PASS, false, GUARD>(
+        px, s_plane, ey, ex, tid, mdir, mraw, cf, agg, unused);
 }
 
 // Objective of one member: BVDF (eq. 2) A; DDF A^(1-p) D^p (p = 1/2 orders as

@@ -75,7 +75,7 @@ __device__ __forceinline__ T* uni(T* v) {
 // workgroup and are moved to scalar registers).
 template <int W, int KIND, int DIST, int SHAPE>
 __device__ __forceinline__ void batch_tile(
-    FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false>& sh,
+    FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false>& sh,
     const BatchClass& bc, int t) {
     constexpr int EXT_W = BatchShape<SHAPE>::EXT_W, EXT_H = BatchShape<SHAPE>::EXT_H;
     const BatchTile tile = bc.tiles[t];
@@ -111,7 +111,7 @@ template <int W, int KIND, int DIST>
 __global__ void __launch_bounds__(BatchShape<persistent_shape<W>()>::THREADS)
     batch_kernel(BatchClass bc) {
     constexpr int SHAPE = persistent_shape<W>();
-    __shared__ FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
+    __shared__ FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
     __shared__ int s_tile;
     for (;;) {
         __syncthreads();  // the previous tile is finished with s_tile and sh
@@ -126,8 +126,8 @@ __global__ void __launch_bounds__(BatchShape<persistent_shape<W>()>::THREADS)
 // Direct form: one workgroup per tile of the list, dispatched in list order.
 template <int W, int KIND, int DIST, int SHAPE>
 __global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS)
-    __attribute__((amdgpu_waves_per_eu(W == 3 ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
-    __shared__ FwdSharedFor<W, KIND, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
+    __attribute__((amdgpu_waves_per_eu(W == 3 && KIND != kACW ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
+    __shared__ FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
     batch_tile<W, KIND, DIST, SHAPE>(sh, bc, blockIdx.x);
 }
 

@@ -7,12 +7,13 @@
 
 namespace odf {
 
-// 3x3 kernels are held to 64 VGPRs (8 waves per SIMD), the budget at which
-// four 512-thread or two 1024-thread workgroups share a CU.
+// 3x3 BVDF and DDF kernels are held to 64 VGPRs (8 waves per SIMD), the
+// budget at which four 512-thread or two 1024-thread workgroups share a CU
+// (ACWDDF keeps four objectives per window and cannot get there).
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
 __global__ void __launch_bounds__(EXT_W* EXT_H)
-    __attribute__((amdgpu_waves_per_eu(W == 3 && !AGG ? 8 : 1))) fwd_kernel(FwdParams prm) {
-    __shared__ FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG> sh;
+    __attribute__((amdgpu_waves_per_eu(W == 3 && KIND != kACW && !AGG ? 8 : 1))) fwd_kernel(FwdParams prm) {
+    __shared__ FwdSharedFor<W, KIND, DIST, U8, EXT_W, EXT_H, AGG> sh;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     fwd_tile<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>(sh, prm, blockIdx.z, blockIdx.y * Gm::TH,
                                                    blockIdx.x * Gm::TW, threadIdx.x);

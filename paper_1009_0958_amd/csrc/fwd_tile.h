@@ -22,14 +22,32 @@ namespace odf {
 // keeping 25 aggregates live in registers, which lets it use 1024-thread tiles.
 // NKEY: argmin keys per window (4 for ACWDDF: eq. 3 and three levels of eq. 9).
 // NPL: plane sets (2 when the angular and L2 terms are swept together).
-template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY, int NPL>
+// U8: uint8 layout (pair_terms.h): no raw array, aux2 in inv for MINIMAX and
+// RGB.  HALO: the key array covers every window centre a member of the
+// extended tile belongs to (rows -2h .. EXT_H - 1 of the output tile, stride
+// EXT_W), so each member reaches its windows' keys at fixed offsets and no
+// window needs a bounds test; the others keep one key per output pixel.
+// The unguarded sweep (aggregates.h) reads up to 2h rows + 2h past dir (and
+// raw, inv) and as far before plane: the member order below keeps both inside
+// the struct, which fwd_tile checks.
+template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY, int NPL, bool U8,
+          bool INV>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    static constexpr bool HALO = U8 && !STAGE && !AGG;
+    static constexpr int KEYN =
+        HALO ? (Gm::TH + 4 * Gm::H) * EXT_W + 2 * Gm::H : Gm::TH * Gm::TW;
     float4 dir[Gm::NT];
-    float4 raw[Gm::NT];
+    float4 raw[U8 ? 1 : Gm::NT];
+    float inv[INV ? Gm::NT : 1];
     float plane[NPL * Gm::G * Gm::NT];
-    unsigned long long key[AGG ? 1 : NKEY * Gm::TH * Gm::TW];
+    unsigned long long key[AGG ? 1 : NKEY * KEYN];
     float stage[STAGE ? Gm::NW * Gm::TH * Gm::TW : 1];
+
+    // key slot of the window centred on output pixel (cy, cx), tile-local
+    static __device__ __forceinline__ int key_index(int cy, int cx) {
+        return HALO ? (cy + 2 * Gm::H) * EXT_W + cx + 2 * Gm::H : cy * Gm::TW + cx;
+    }
 };
 
 // Order bits of an objective.  Every mode but the logarithmic one yields a
@@ -52,27 +70,39 @@ constexpr bool fused_sweep() {
     return W == 3 && KIND != kBVDF;
 }
 
-template <int W, int KIND, int EXT_W, int EXT_H, bool AGG>
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
 using FwdSharedFor = FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>(),
-                               KIND == kACW ? 4 : 1, fused_sweep<W, KIND>() ? 2 : 1>;
+                               KIND == kACW ? 4 : 1, fused_sweep<W, KIND>() ? 2 : 1, U8,
+                               U8 && DIST != kExact>;
 
 // Filter one output tile whose top-left output pixel is (ty0, tx0) of image b.
 // Every thread of the workgroup must call it (it synchronises); tid is the
 // thread's index in the workgroup.
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
-__device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG>& sh,
+__device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>& sh,
                                          const FwdParams& prm, int b, int ty0, int tx0, int tid) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
+    using Sh = FwdSharedFor<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>;
     constexpr int H = Gm::H, NW = Gm::NW, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
+    constexpr bool INV = U8 && DIST != kExact;
+    constexpr int KEYN = Sh::KEYN;
+    // the unguarded sweep's reads past the pixel arrays and before the planes
+    // stay inside this struct
+    constexpr size_t kOver = 2 * H * EXT_W + 2 * H;
+    static_assert(offsetof(Sh, dir) + (NT + kOver) * sizeof(float4) <= sizeof(Sh), "dir");
+    static_assert(U8 || offsetof(Sh, raw) + (NT + kOver) * sizeof(float4) <= sizeof(Sh), "raw");
+    static_assert(!INV || offsetof(Sh, inv) + (NT + kOver) * sizeof(float) <= sizeof(Sh), "inv");
+    static_assert(offsetof(Sh, plane) >= kOver * sizeof(float), "plane");
     float4* s_dir = sh.dir;
-    float4* s_raw = sh.raw;
     float* s_plane = sh.plane;
     unsigned long long* s_key = sh.key;
+    const TilePix px{sh.dir, sh.raw, sh.inv};
 
     const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
     const int M = prm.M, N = prm.N;
 
     // a1: own extended pixel, replicated border
+    float4 mdir, mraw;
     {
         const int gy = min(max(ty0 - H + ey, 0), M - 1);
         const int gx = min(max(tx0 - H + ex, 0), N - 1);
@@ -85,27 +115,25 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             const float* s = static_cast<const float*>(prm.img) + pix * 3;
             x0 = s[0]; x1 = s[1]; x2 = s[2];
         }
-        float4 d, r;
-        prepare_pixel<DIST, U8>(x0, x1, x2, d, r);
-        s_dir[tid] = d;
-        s_raw[tid] = r;
+        prepare_pixel<DIST, U8>(x0, x1, x2, mdir, mraw);
+        s_dir[tid] = mdir;
+        if constexpr (!U8) sh.raw[tid] = mraw;
+        if constexpr (INV) sh.inv[tid] = mraw.w;
     }
     constexpr int NKEY = KIND == kACW ? 4 : 1;
     if (!AGG)
-        for (int i = tid; i < NKEY * TH * TW; i += NT) s_key[i] = ~0ull;
+        for (int i = tid; i < NKEY * KEYN; i += NT) s_key[i] = ~0ull;
     __syncthreads();
-    const float4 mdir = s_dir[tid];
-    const float4 mraw = s_raw[tid];
 
     // a2 + a3 (ACWDDF also keeps each member's terms with the window centres)
     float A[NW], D[NW];
     float cA[NW], cD[NW];
     if constexpr (fused_sweep<W, KIND>())
-        member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, 2, KIND == kACW>(
-            s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD);
+        member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, 2, KIND == kACW, false>(
+            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD);
     else
-        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW>(
-            s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW, false>(
+            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
     if constexpr (stage_angle_part<W, KIND, AGG>()) {
         // angle part of each objective -> LDS, then the L2 pass, then the keys
         const int mode = objective_mode<KIND>(prm.p);
@@ -120,8 +148,8 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             else if (mode == kObjLog) part = (1.0f - p) * __builtin_amdgcn_logf(a);
             sh.stage[u * (TH * TW) + cy * TW + cx] = part;
         }
-        member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey, ex,
-                                                                tid, mdir, mraw, prm.coef, D);
+        member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true, false>(px, s_plane, ey, ex, tid,
+                                                                       mdir, mraw, prm.coef, D);
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int cy = ey - u / W, cx = ex - u % W;
@@ -135,17 +163,36 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             else om = part * D[u];
             const unsigned long long key =
                 ((unsigned long long)objective_bits(om, mode == kObjLog) << 32) | (unsigned)u;
-            atomicMin(&s_key[cy * TW + cx], key);
+            atomicMin(&s_key[Sh::key_index(cy, cx)], key);
         }
     } else {
     if constexpr (fused_sweep<W, KIND>())
         ;  // D and cD came with the angular sweep
     else if (KIND != kBVDF)
-        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, KIND == kACW>(
-            s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, KIND == kACW, false>(
+            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
     else
 #pragma unroll
         for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+
+    // Window u of this member is centred on output pixel (ey - u / W, ex - u % W)
+    // of the tile.  Windows outside the output tile (or the image) hold
+    // meaningless aggregates (unguarded sweep): without HALO they are
+    // skipped, with HALO their keys land in slots no output pixel reads.
+    // With HALO a wave skips window u only when it lies outside the output
+    // tile's rows for all of the wave's rows (a scalar test).
+    constexpr int RW = 64 / EXT_W;
+    const int wrow0 = __builtin_amdgcn_readfirstlane(ey);
+    auto window_ok = [&](int u) {
+        const int cy = ey - u / W, cx = ex - u % W;
+        if (Sh::HALO) return wrow0 + RW - 1 - u / W >= 0 && wrow0 - u / W < TH;
+        return cy >= 0 && cy < TH && cx >= 0 && cx < TW && ty0 + cy < M && tx0 + cx < N;
+    };
+    // the key slot of window u: a fixed offset from the member's own slot
+    auto key_slot = [&](int u) {
+        return Sh::HALO ? tid + (2 * H - u / W) * EXT_W + 2 * H - u % W
+                        : Sh::key_index(ey - u / W, ex - u % W);
+    };
 
     // a4: objective of this member in every window of the tile containing it
     if (AGG) {
@@ -163,15 +210,11 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
     } else if constexpr (KIND == kACW) {
         // eq. (3) and the centre-weighted objectives of eq. (9): the weight
         // w_d(k) of the centre adds (w_d(k) - 1) times the centre term
-        constexpr int TT = TH * TW;
         const float w1 = prm.acw_wm1[0], w2 = prm.acw_wm1[1], w3 = prm.acw_wm1[2];
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
-            const int cy = ey - u / W;
-            const int cx = ex - u % W;
-            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-            if (ty0 + cy >= M || tx0 + cx >= N) continue;
-            const int ci = cy * TW + cx;
+            if (!window_ok(u)) continue;
+            const int ci = key_slot(u);
             const float o0 = A[u] * D[u];
             const float o1 = fmaf(w1, cA[u], A[u]) * fmaf(w1, cD[u], D[u]);
             const float o2 = fmaf(w2, cA[u], A[u]) * fmaf(w2, cD[u], D[u]);
@@ -179,9 +222,9 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
             // products of non-negative sums: the bit patterns order like the values
             const unsigned long long uu = (unsigned)u;
             atomicMin(&s_key[ci], ((unsigned long long)__float_as_uint(o0) << 32) | uu);
-            atomicMin(&s_key[TT + ci], ((unsigned long long)__float_as_uint(o1) << 32) | uu);
-            atomicMin(&s_key[2 * TT + ci], ((unsigned long long)__float_as_uint(o2) << 32) | uu);
-            atomicMin(&s_key[3 * TT + ci], ((unsigned long long)__float_as_uint(o3) << 32) | uu);
+            atomicMin(&s_key[KEYN + ci], ((unsigned long long)__float_as_uint(o1) << 32) | uu);
+            atomicMin(&s_key[2 * KEYN + ci], ((unsigned long long)__float_as_uint(o2) << 32) | uu);
+            atomicMin(&s_key[3 * KEYN + ci], ((unsigned long long)__float_as_uint(o3) << 32) | uu);
         }
     } else {
         float om[NW];
@@ -189,13 +232,10 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
         objective_keys<NW>(mode, prm.p, A, D, om);
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
-            const int cy = ey - u / W;  // window centre, tile-local
-            const int cx = ex - u % W;
-            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-            if (ty0 + cy >= M || tx0 + cx >= N) continue;
+            if (!window_ok(u)) continue;
             const unsigned long long key =
                 ((unsigned long long)objective_bits(om[u], mode == kObjLog) << 32) | (unsigned)u;
-            atomicMin(&s_key[cy * TW + cx], key);
+            atomicMin(&s_key[key_slot(u)], key);
         }
     }
     }
@@ -207,28 +247,45 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, EXT_W, EXT_H, AGG
         const int cy = i / TW, cx = i - (i / TW) * TW;
         const int gy = ty0 + cy, gx = tx0 + cx;
         if (gy >= M || gx >= N) continue;
-        int u = min((int)(s_key[i] & 0xffu), NW - 1);
+        const int ki = Sh::key_index(cy, cx);
+        int u = min((int)(s_key[ki] & 0xffu), NW - 1);
         if constexpr (KIND == kACW) {
             // switch: S = sum over the three levels of A(y_k, x_d) L2(y_k, x_d);
             // the eq. (3) selection if S > T, else the centre
             const int c = (cy + H) * EXT_W + cx + H;
-            const float4 cd = s_dir[c], cr = s_raw[c];
+            const float4 cd = s_dir[c];
+            const AtanCoef ac = atan_coef();
             float S = 0.0f;
 #pragma unroll
             for (int j = 1; j <= 3; ++j) {
-                const int uj = min((int)(s_key[j * TH * TW + i] & 0xffu), NW - 1);
+                const int uj = min((int)(s_key[j * KEYN + ki] & 0xffu), NW - 1);
                 const int m = (cy + uj / W) * EXT_W + cx + uj % W;
-                S += pair_term<KIND, DIST, U8>(s_dir[m], s_raw[m], cd, cr, prm.coef) *
-                     l2_term(s_raw[m], cr);
+                if constexpr (U8) {
+                    const float4 md = s_dir[m];
+                    float th, l2;
+                    const bool mz = md.w < 0.0f;
+                    pair_u8<KIND, DIST, true, true>(md, INV ? sh.inv[m] : 0.0f, mz,
+                                                    __builtin_amdgcn_ballot_w64(mz), cd,
+                                                    INV ? sh.inv[c] : 0.0f, prm.coef, ac, th, l2);
+                    S += th * l2;
+                } else {
+                    const float4 cr = sh.raw[c];
+                    S += pair_term<KIND, DIST, U8>(s_dir[m], sh.raw[m], cd, cr, prm.coef, ac) *
+                         l2_term(sh.raw[m], cr);
+                }
             }
             if (!(S > prm.acw_T)) u = (NW - 1) / 2;
         }
-        const float4 r = s_raw[(cy + u / W) * EXT_W + cx + u % W];
+        const int sel = (cy + u / W) * EXT_W + cx + u % W;
         const size_t pix = ((size_t)b * M + gy) * N + gx;
         if (U8) {
+            // the raw value is the direction, or 0 for the zero pixel
+            const float4 d = s_dir[sel];
+            const bool z = d.w < 0.0f;
             uint8_t* o = static_cast<uint8_t*>(prm.out) + pix * 3;
-            o[0] = (uint8_t)r.x; o[1] = (uint8_t)r.y; o[2] = (uint8_t)r.z;
+            o[0] = z ? 0 : (uint8_t)d.x; o[1] = z ? 0 : (uint8_t)d.y; o[2] = z ? 0 : (uint8_t)d.z;
         } else {
+            const float4 r = sh.raw[sel];
             float* o = static_cast<float*>(prm.out) + pix * 3;
             o[0] = r.x; o[1] = r.y; o[2] = r.z;
         }

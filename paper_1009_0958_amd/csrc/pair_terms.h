@@ -2,21 +2,19 @@
 // directional filters (Section II and Sections 2.1-2.2 of Celebi,
 // arXiv:1009.0958), in binary32 on the VALU of gfx950.
 //
-// Each prepared pixel is two float4 values:
-//   dir = (d.x, d.y, d.z, aux1)   d: direction (the pixel, or (1,1,1) for 0)
+// A prepared float pixel is two float4 values:
+//   dir = (d.x, d.y, d.z, aux1)   d: direction (the pixel scaled by a power of
+//                                    two, or (1,1,1) for 0)
 //   raw = (x.x, x.y, x.z, aux2)   x: the raw pixel
-//   EXACT:   aux1 = |x|^2, or -3 for x = 0 (|d|^2 = 3 for d = (1,1,1); the sign
-//            marks the zero pixel), aux2 = |d| / |x| (a power of two; 0 for x = 0)
+//   EXACT:   aux1 = |x|^2, or -3 for x = 0, aux2 = |d| / |x| (0 for x = 0)
 //   MINIMAX: aux1 = |d|^2, aux2 = 1/|d|
 //   RGB:     aux1 = d.x + d.y + d.z, aux2 = 1/aux1
+// A prepared uint8 pixel is dir alone, with d = x (exact integers) or (1,1,1)
+// for the zero pixel, plus aux2 for MINIMAX and RGB: aux1 = |x|^2 (EXACT,
+// MINIMAX) or the channel sum (RGB), and -3 for the zero pixel (|d|^2 and the
+// sum of (1,1,1) are 3; the sign marks the zero pixel).  The raw value is
+// dir.xyz, or 0 where aux1 < 0.
 //
-// Every pair term is symmetric bit for bit (term(a,b) == term(b,a)) and
-// returns for a pair of equal vectors exactly the value it returns for the
-// self pair, so equal colours in a window get bitwise-equal aggregates.
-// Cross-product and chromaticity numerators are differences of two rounded
-// products (no fused multiply-add), which keeps swapped arguments exact
-// negations; for uint8 inputs they are exact integers, formed with one fused
-// multiply-add.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +35,30 @@ constexpr float kEq10Beta = 0.027664f;
 
 constexpr float kHalfPi = 1.57079632679489661923f;
 constexpr float kPi = 3.14159265358979323846f;
+
+// c as a wave-uniform value in a scalar register, opaque to constant folding.
+// A multiply-add then takes it as its scalar operand; left as a literal, the
+// compiler tends to copy polynomial coefficients into vector registers, one
+// VALU move each.
+__device__ __forceinline__ float scalar_const(float c) {
+    int z;
+    asm("s_mov_b32 %0, 0" : "=s"(z));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c) | z));
+}
+
+// The atan polynomial's coefficients in scalar registers, formed once by the
+// caller of a pair-term loop.
+struct AtanCoef {
+    float c[ODF_ATAN_DEG + 1];
+};
+
+__device__ __forceinline__ AtanCoef atan_coef() {
+    AtanCoef a;
+    a.c[0] = kAtanPoly[0];  // 1: an inline constant
+#pragma unroll
+    for (int k = 1; k <= ODF_ATAN_DEG; ++k) a.c[k] = scalar_const(kAtanPoly[k]);
+    return a;
+}
 
 // a*b - c*d with both products rounded separately.
 __device__ __forceinline__ float diff_of_products(float a, float b, float c, float d) {
@@ -75,7 +97,8 @@ __device__ __forceinline__ float horner4(const float* c, float t) {
 
 // Prepare one pixel.  For float inputs the direction is scaled by a power of
 // two (exact; angles and chromaticities are scale-free) so that its largest
-// magnitude lies in [1, 2), which keeps every product below in range.
+// magnitude lies in [1, 2), which keeps every product below in range.  raw.w
+// is aux2 in both layouts.
 template <int DIST, bool U8>
 __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, float4& dir,
                                               float4& raw) {
@@ -98,14 +121,24 @@ __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, floa
         aux1 = zero ? -3.0f : fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
         aux2 = zero ? 0.0f : ldexpf(1.0f, -e);
     } else if (DIST == kMinimax) {
-        aux1 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-        aux2 = 1.0f / sqrtf(aux1);
+        // n2 >= 1 (uint8 integers, or float directions scaled into [1, 2)):
+        // the hardware reciprocal square root (about 1 ulp) needs no range fix-up
+        const float n2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        aux1 = (U8 && zero) ? -3.0f : n2;
+        aux2 = __builtin_amdgcn_rsqf(n2);
     } else if (DIST == kRgb) {
-        aux1 = (d0 + d1) + d2;
-        aux2 = 1.0f / aux1;
+        const float sum = (d0 + d1) + d2;
+        aux1 = (U8 && zero) ? -3.0f : sum;
+        aux2 = __builtin_amdgcn_rcpf(sum);  // about 1 ulp
     }
     dir = make_float4(d0, d1, d2, aux1);
     raw = make_float4(x0, x1, x2, aux2);
+}
+
+// aux1 of a prepared pixel as a norm or sum (uint8: without the zero mark).
+template <bool U8>
+__device__ __forceinline__ float aux_mag(float w) {
+    return U8 ? fabsf(w) : w;
 }
 
 // Exact angle of eq. (2), evaluated as atan2(|a x b|, a.b):
@@ -131,28 +164,31 @@ __device__ __forceinline__ float cross_norm2(const float4& a, const float4& b, f
 }
 
 template <bool U8>
-__device__ __forceinline__ float angle_exact_dot(const float4& a, const float4& b, float& dot) {
+__device__ __forceinline__ float angle_exact_from_dot(const float4& a, const float4& b, float dot,
+                                                      const AtanCoef& ac) {
     constexpr bool SIGNED = !U8;  // float inputs may be negative
-    dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
     // |d|^2 = |aux1| (the zero pixel's -3 stands for |(1,1,1)|^2)
     float P = cross_norm2<U8>(a, b, fabsf(a.w), fabsf(b.w), dot);
     float Q = dot * dot;
     float m = fminf(P, Q);
     float r = m * rsq(fmaxf(P * Q, 1.17549435e-38f));
     float t = r * r;
-    float acc = kAtanPoly[ODF_ATAN_DEG];
+    float acc = ac.c[ODF_ATAN_DEG];
 #pragma unroll
-    for (int k = ODF_ATAN_DEG - 1; k >= 0; --k) acc = fmaf(acc, t, kAtanPoly[k]);
+    for (int k = ODF_ATAN_DEG - 1; k >= 0; --k) acc = fmaf(acc, t, ac.c[k]);
     float at = r * acc;
     float th = (P > Q) ? (kHalfPi - at) : at;
     if (SIGNED) th = (dot < 0.0f) ? (kPi - th) : th;
     return th;
 }
 
+__device__ __forceinline__ float dot3(const float4& a, const float4& b) {
+    return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
+}
+
 template <bool U8>
-__device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
-    float dot;
-    return angle_exact_dot<U8>(a, b, dot);
+__device__ __forceinline__ float angle_exact(const float4& a, const float4& b, const AtanCoef& ac) {
+    return angle_exact_from_dot<U8>(a, b, dot3(a, b), ac);
 }
 
 // Method 1 (Section 2.1): ACOS row of Table 1 in z for z < 1/2, ASIN row in
@@ -160,87 +196,106 @@ __device__ __forceinline__ float angle_exact(const float4& a, const float4& b) {
 // exact predicate 4 (a.b)^2 < |a|^2 |b|^2 (binary64 products of binary32
 // values are exact).  The binary32 cosine z = a.b / (|a| |b|) is within a few
 // ulp of the true one (a.b is exact or nearly so for non-negative inputs, the
-// reciprocal norms are correctly rounded), so outside |z - 1/2| <= 2^-20 its
+// reciprocal norms are within about an ulp), so outside |z - 1/2| <= 2^-20 its
 // own comparison gives the same answer and the binary64 test is skipped.
 // 1 - z = |a x b|^2 / (|a|^2 |b|^2 (1 + z)) avoids the cancellation of 1 - z
 // next to z = 1.
 template <bool U8>
-__device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra, const float4& b,
-                                               const float4& rb, const MinimaxCoef& cf) {
-    float dot = fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
-    float z = dot * (ra.w * rb.w);
+__device__ __forceinline__ float angle_minimax_from_dot(const float4& a, float ia, const float4& b,
+                                                        float ib, float dot,
+                                                        const MinimaxCoef& cf) {
+    const float na = aux_mag<U8>(a.w), nb = aux_mag<U8>(b.w);
+    float z = dot * (ia * ib);
     bool acos_branch = z < 0.5f;
     const bool near = fabsf(z - 0.5f) <= 0x1p-20f;
     if (__builtin_amdgcn_ballot_w64(near)) {  // uniform branch, almost never taken
         asm volatile("");                     // keeps the exact test out of the common path
-        if (near) acos_branch = 4.0 * (double)dot * (double)dot < (double)a.w * (double)b.w;
+        if (near) acos_branch = 4.0 * (double)dot * (double)dot < (double)na * (double)nb;
     }
-    float P = cross_norm2<U8>(a, b, a.w, b.w, dot);
-    float X = (a.w * b.w) * (1.0f + z);
+    float P = cross_norm2<U8>(a, b, na, nb, dot);
+    float X = (na * nb) * (1.0f + z);
     float tau = P * rsq(fmaxf(P * X, 1.17549435e-38f));
     // the clamp at 0 matters for the ASIN row only (q = 3 dips below 0 next to
     // tau = 0); every ACOS row stays above 1 on [-1, 1/2]
     return acos_branch ? horner4(cf.acos_c, z) : fmaxf(horner4(cf.asin_c, tau), 0.0f);
 }
 
+template <bool U8>
+__device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra, const float4& b,
+                                               const float4& rb, const MinimaxCoef& cf) {
+    return angle_minimax_from_dot<U8>(a, ra.w, b, rb.w, dot3(a, b), cf);
+}
+
 // Method 2 (Section 2.2, eq. 7): L2 distance of chromaticities
 // |a / sum a - b / sum b| = |a sum b - b sum a| / (sum a sum b).
 template <int KIND, bool U8>
-__device__ __forceinline__ float chroma_term(const float4& a, const float4& ra, const float4& b,
-                                             const float4& rb) {
-    float n0 = cross_diff<U8>(a.x, b.w, b.x, a.w);
-    float n1 = cross_diff<U8>(a.y, b.w, b.y, a.w);
-    float n2 = cross_diff<U8>(a.z, b.w, b.z, a.w);
+__device__ __forceinline__ float chroma_term(const float4& a, float ia, const float4& b, float ib) {
+    const float sa = aux_mag<U8>(a.w), sb = aux_mag<U8>(b.w);
+    float n0 = cross_diff<U8>(a.x, sb, b.x, sa);
+    float n1 = cross_diff<U8>(a.y, sb, b.y, sa);
+    float n2 = cross_diff<U8>(a.z, sb, b.z, sa);
     float Nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
-    float B = sqrt_raw(Nn) * (ra.w * rb.w);
+    float B = sqrt_raw(Nn) * (ia * ib);
     if (KIND != kBVDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
     return B;
 }
 
-// Angular pair term of the chosen variant.
+// Angular pair term of the chosen variant (float layout, or uint8 with raw.w =
+// aux2).
 template <int KIND, int DIST, bool U8>
 __device__ __forceinline__ float pair_term(const float4& a, const float4& ra, const float4& b,
-                                           const float4& rb, const MinimaxCoef& cf) {
-    if (DIST == kExact) return angle_exact<U8>(a, b);
+                                           const float4& rb, const MinimaxCoef& cf,
+                                           const AtanCoef& ac) {
+    if (DIST == kExact) return angle_exact<U8>(a, b, ac);
     if (DIST == kMinimax) return angle_minimax<U8>(a, ra, b, rb, cf);
-    return chroma_term<KIND, U8>(a, ra, b, rb);
+    return chroma_term<KIND, U8>(a, ra.w, b, rb.w);
 }
 
-// eq. (1) with the L2 norm (Section III), on raw values.
+// eq. (1) with the L2 norm (Section III), on raw float values.
 __device__ __forceinline__ float l2_term(const float4& ra, const float4& rb) {
     float e0 = ra.x - rb.x, e1 = ra.y - rb.y, e2 = ra.z - rb.z;
     return sqrt_raw(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
 }
 
-// The angular pair term of member a (dir a, raw ra) with neighbour q of the
-// LDS tile, and their L2 distance of eq. (1) in l2.  For uint8 exact angles the
-// squared distance reuses the dot product of the angle:
-// |x_a - x_b|^2 = |x_a|^2 + |x_b|^2 - 2 x_a.x_b, every term an integer exact in
-// binary32, with |x|^2 in dir.w.  A zero pixel (direction (1,1,1), value 0,
-// dir.w = -3) has a zero raw dot product and |x|^2 = 0; the lanes with one take
-// max(dir.w, 0) summed over the pair in a branch the wave enters only when some
-// lane needs it.
-template <int KIND, int DIST, bool U8>
-__device__ __forceinline__ float pair_and_l2(const float4& a, const float4& ra,
-                                             const float4* __restrict__ s_dir,
-                                             const float4* __restrict__ s_raw, int q,
-                                             const MinimaxCoef& cf, float& l2) {
-    const float4 b = s_dir[q];
-    if constexpr (DIST == kExact && U8) {
-        float dot;
-        const float th = angle_exact_dot<U8>(a, b, dot);
-        float l2sq = fmaf(-2.0f, dot, a.w + b.w);
-        const bool zero = (__float_as_int(a.w) | __float_as_int(b.w)) < 0;  // a sign set
-        if (__builtin_amdgcn_ballot_w64(zero)) {
+// Pair terms of uint8 member a (aux2 ia; a_zero: a is the zero pixel, and
+// a_zero_wave the ballot of a_zero over the wave) and neighbour b (aux2 ib): the angular term in th if ANG, the L2 distance of
+// eq. (1) in l2 if L2.  EXACT and MINIMAX share the dot product of the
+// directions with the L2 term: |x_a - x_b|^2 = |x_a|^2 + |x_b|^2 - 2 x_a.x_b,
+// every term an integer exact in binary32.  The zero pixel (direction (1,1,1),
+// value 0) breaks the identity (and the raw difference of RGB); lanes with a
+// zero pixel take the distance from the other pixel's norm in a branch the
+// wave enters only when some lane needs it.
+template <int KIND, int DIST, bool ANG, bool L2>
+__device__ __forceinline__ void pair_u8(const float4& a, float ia, bool a_zero, uint64_t a_zero_wave,
+                                        const float4& b, float ib, const MinimaxCoef& cf,
+                                        const AtanCoef& ac, float& th, float& l2) {
+    float dot = 0.0f;
+    if constexpr (DIST != kRgb) dot = dot3(a, b);
+    if constexpr (ANG) {
+        if constexpr (DIST == kExact) th = angle_exact_from_dot<true>(a, b, dot, ac);
+        else if constexpr (DIST == kMinimax) th = angle_minimax_from_dot<true>(a, ia, b, ib, dot, cf);
+        else th = chroma_term<KIND, true>(a, ia, b, ib);
+    }
+    if constexpr (L2) {
+        float l2sq;
+        if constexpr (DIST != kRgb) {
+            l2sq = fmaf(-2.0f, dot, a.w + b.w);
+        } else {
+            const float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z;
+            l2sq = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+        }
+        const bool b_zero = b.w < 0.0f;
+        // a_zero_wave: the lanes whose member a is the zero pixel
+        if (__builtin_amdgcn_ballot_w64(b_zero) | a_zero_wave) {
             asm volatile("");  // keeps the fix-up out of the common path
-            if (zero) l2sq = fmaxf(a.w, 0.0f) + fmaxf(b.w, 0.0f);
+            if (a_zero | b_zero) {
+                if constexpr (DIST != kRgb)
+                    l2sq = fmaxf(a.w, 0.0f) + fmaxf(b.w, 0.0f);
+                else
+                    l2sq = (a_zero ? 0.0f : dot3(a, a)) + (b_zero ? 0.0f : dot3(b, b));
+            }
         }
         l2 = sqrt_raw(l2sq);
-        return th;
-    } else {
-        const float4 rb = s_raw[q];
-        l2 = l2_term(ra, rb);
-        return pair_term<KIND, DIST, U8>(a, ra, b, rb, cf);
     }
 }
 

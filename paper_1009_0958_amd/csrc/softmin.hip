@@ -208,8 +208,9 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT)) softmin_kernel(S
     };
 
     float A[NW], D[NW], Om[NW];
-    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false>(s_dir, s_raw, s_plane, ey, ex,
-                                                                  tid, mdir, mraw, no_coef, A);
+    const TilePix px{s_dir, s_raw, nullptr};
+    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false>(px, s_plane, ey, ex, tid, mdir,
+                                                                  mraw, no_coef, A);
     if constexpr (!BWD) {
         // forward only: the angle part of each objective waits in s_e (same
         // (member, window) layout) during the L2 sweep; then s_e holds Omega
@@ -220,9 +221,8 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT)) softmin_kernel(S
             if (window_of(u, c)) s_e[u * TT + c] = mode == 2 ? (1.0f - p) * log2f(A[u]) : A[u];
         }
         if (KIND == kDDF)
-            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey,
-                                                                         ex, tid, mdir, mraw,
-                                                                         no_coef, D);
+            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(px, s_plane, ey, ex, tid,
+                                                                         mdir, mraw, no_coef, D);
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             int c;
@@ -242,9 +242,8 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT)) softmin_kernel(S
         }
     } else {
         if (KIND == kDDF)
-            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(s_dir, s_raw, s_plane, ey,
-                                                                         ex, tid, mdir, mraw,
-                                                                         no_coef, D);
+            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(px, s_plane, ey, ex, tid,
+                                                                         mdir, mraw, no_coef, D);
         else
 #pragma unroll
             for (int u = 0; u < NW; ++u) D[u] = 0.0f;

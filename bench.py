@@ -69,8 +69,8 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("rgb", 32, 32): (4078.8, 6144.0), ("rgb", 64, 16): (2895.0, 5056.0),
     ("rgb", 32, 16): (4359.4, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
 }
-TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "fwd_tile.h", "aggregates.h", "pair_terms.h",
-                   "atan_poly.h", "odf_internal.h")
+TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
+                   "pair_terms.h", "atan_poly.h", "odf_internal.h")
 TRAFFIC_SRC_SHA256 = "6d09a2ece8cab8995a4bfa96c1628ff14d315abde6b08b8871244196a7917753"
 
 
@@ -84,8 +84,9 @@ def forward_sources_sha256():
 
 
 def traffic_bytes(dist, ext_tile):
-    """Calibrated HBM bytes per 1024 x 1024 launch, or None when the kernel
-    sources differ from the ones the counters were taken on."""
+    """Calibrated HBM bytes per launch on the 1024 x 1024 image (one filter, or
+    for "batch6" the group kernel running all six variants), or None when the
+    kernel sources differ from the ones the counters were taken on."""
     key = (dist, int(ext_tile[0]), int(ext_tile[1]))
     if forward_sources_sha256() != TRAFFIC_SRC_SHA256 or key not in TRAFFIC_KIB:
         return None
@@ -268,23 +269,36 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
-    dp, dd = float(dom.split("_")[1][1:]), dom.split("_")[2]
-    dslots = slots_per_pixel(3, "ddf", dp, dd) * M * N
-    dms = per_variant[dom]["ms"]
+    if best == "graph_batch_direct":
+        # the step is one kernel (the 3x3 DDF group kernel over the tiles of
+        # all six variants): time that launch live with events on its stream
+        plan = graphs["direct"][0]
+        dms = time_launches(torch, plan.launch, max(20, args.steps))
+        slots_px = sum(slots_per_pixel(3, "ddf", p, d) for (p, d) in variants) / len(variants)
+        npx = len(variants) * M * N
+        dname = "batch_direct_kernel ddf3, six variants in one launch"
+        tb = traffic_bytes("batch6", (32, 32))
+    else:
+        dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
+        dp, dd = float(dom.split("_")[1][1:]), dom.split("_")[2]
+        dms = per_variant[dom]["ms"]
+        slots_px = slots_per_pixel(3, "ddf", dp, dd)
+        npx = M * N
+        dname = "fwd_kernel " + dom
+        tb = traffic_bytes(dd, tuned["ddf3_%s" % dd]["ext_tile"])
+    dslots = slots_px * npx
     roofline = {
-        "bound": "alu", "kernel": "fwd_kernel " + dom,
+        "bound": "alu", "kernel": dname, "ms_per_launch": round(dms, 5),
         "achieved": round(dslots / (dms * 1e-3) / 1e12, 3), "peak": round(PEAK_SLOTS / 1e12, 2),
         "unit": "T VALU lane-slots/s", "frac": round(dslots / (dms * 1e-3) / PEAK_SLOTS, 4),
-        "slots_per_pixel": slots_per_pixel(3, "ddf", dp, dd), "pixels_per_launch": M * N,
+        "slots_per_pixel": round(slots_px, 2), "pixels_per_launch": npx,
         "traffic": None,
-        "hbm_bytes_per_pixel": 7, "hbm_frac": round(7 * M * N / (dms * 1e-3) / 8e12, 5),
+        "hbm_bytes_per_pixel": 7, "hbm_frac": round(7 * npx / (dms * 1e-3) / 8e12, 5),
     }
-    tb = traffic_bytes(dd, tuned["ddf3_%s" % dd]["ext_tile"])
     if tb is not None:
         roofline["traffic"] = tb["fetch"] + tb["write"]
         roofline["traffic_fetch_write"] = [tb["fetch"], tb["write"]]
-        roofline["traffic_over_algorithmic"] = round((tb["fetch"] + tb["write"]) / (7 * M * N), 3)
+        roofline["traffic_over_algorithmic"] = round((tb["fetch"] + tb["write"]) / (7 * npx), 3)
 
     forms = {}
     acw_idx = {}

@@ -203,7 +203,8 @@ typedef struct {
 typedef struct odf_plan odf_plan; /* opaque, owned by the library */
 
 /* Validate the jobs, cut them into tiles and upload the work lists (one per
- * class of window, kind and pair term, larger tiles first).  Allocates device
+ * group of window and kind, holding the tiles of every pair term, heavier
+ * tiles first).  Allocates device
  * memory and synchronises; the job buffers must stay valid while the plan is
  * launched.  On success *plan receives a plan to pass to odf_batch_launch and
  * finally to odf_plan_destroy.  Errors: ODF_EINVAL / ODF_EUNSUPPORTED for a bad
@@ -212,15 +213,17 @@ int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream
 
 /* odf_batch_plan with a launch form: ODF_BATCH_DIRECT (what odf_batch_plan
  * uses: one workgroup per tile of the work list, dispatched by the hardware
- * in list order, tile shape from the tuning table) or ODF_BATCH_PERSISTENT
+ * in list order, tile shape from the tuning table entry of the group's pair
+ * term with the most pixels) or ODF_BATCH_PERSISTENT
  * (persistent workgroups taking tiles with an atomic counter).  Same results;
  * on MI355X the direct form is faster (the persistent loop costs registers). */
 enum { ODF_BATCH_PERSISTENT = 0, ODF_BATCH_DIRECT = 1 };
 int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream);
 
-/* Enqueue the plan on `stream`: a counter-reset kernel, then one kernel per
- * non-empty class over its work list (direct or persistent form).  Classes
- * after the first run on the plan's own
+/* Enqueue the plan on `stream`: (persistent form) a counter-reset kernel,
+ * then one kernel per non-empty group over its work list; a group
+ * kernel runs the tiles of all three pair terms of its window and kind.
+ * Groups after the first run on the plan's own
  * auxiliary streams, forked from and joined back to `stream` with events, so
  * they overlap; everything is ordered after prior work on `stream` and before
  * later work on it.  Allocates nothing and does not synchronise, so it may be
@@ -228,8 +231,11 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
  * in time (they share the tile counters and streams). */
 int odf_batch_launch(const odf_plan* plan, void* stream);
 
-/* Plan summary: job count, total pixels, tiles and persistent grid per class,
- * class = ((window == 5) * 2 + kind) * 3 + dist (arrays of 12, each nullable). */
+/* Plan summary: job count, total pixels, and per class of window, kind and
+ * pair term, class = ((window == 5) * 2 + kind) * 3 + dist (arrays of 12, each
+ * nullable): its tiles, and the workgroups launched for them (direct form: one
+ * per tile; persistent form: the grid of its group's kernel, shared by the
+ * group's pair terms). */
 int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles, int* grids);
 
 /* Free a plan (after its last launch has completed). */

@@ -1,19 +1,22 @@
 // batch.hip -- many uint8 images of different sizes, windows and filter
-// variants in one persistent launch per kernel class.
+// variants in one launch per kernel group.
 //
 // odf_batch_plan cuts every job into output tiles and uploads one work list
-// per class (window, kind, pair term); each class kernel is persistent: its
-// workgroups take tiles from the list with an atomic counter until it is
-// exhausted.  One kernel per class keeps each class at the register budget of
-// its own tile function (a single kernel branching over all of them would
-// carry the largest budget, and spill, everywhere).  Tiles are ordered by
-// decreasing size.  odf_batch_launch enqueues a counter
-// reset kernel on the caller's stream, then the class kernels, forked onto
-// per-plan auxiliary streams (default priority) and joined back with events
-// so that classes run concurrently and their tails overlap; it allocates
-// nothing and never synchronises, so it can be captured in a hipGraph.  Every tile writes
-// only its own outputs with the same tile function as the per-image kernels,
-// so results do not depend on which workgroup takes which tile.
+// per group (window, kind): the tiles of every pair term of that window and
+// kind, larger tiles first.  A group kernel takes each tile's pair term from
+// its job and runs the matching tile function (a uniform branch), so a plan
+// of many small images or several variants of one image fills the GPU with
+// one grid instead of a few short ones and their tails.  The pair-term
+// variants of one window share a register budget (3x3: 64 VGPRs); windows
+// and kinds do not (a kernel branching over 3x3 and 5x5 would carry the 5x5
+// budget everywhere), so they keep kernels of their own.  odf_batch_launch
+// enqueues (persistent form) a counter reset kernel on the caller's stream,
+// then the group kernels, forked onto per-plan auxiliary streams (default priority) and
+// joined back with events so that groups run concurrently and their tails
+// overlap; it allocates nothing and never synchronises, so it can be captured
+// in a hipGraph.  Every tile writes only its own outputs with the same tile
+// function as the per-image kernels, so results do not depend on which
+// workgroup takes which tile.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -71,14 +74,13 @@ __device__ __forceinline__ T* uni(T* v) {
     return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
-// Filter tile t of a class work list (all fields are uniform over the
+// Filter tile t of a group work list (all fields are uniform over the
 // workgroup and are moved to scalar registers).
 template <int W, int KIND, int DIST, int SHAPE>
 __device__ __forceinline__ void batch_tile(
     FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false>& sh,
-    const BatchClass& bc, int t) {
+    const BatchClass& bc, const BatchTile& tile) {
     constexpr int EXT_W = BatchShape<SHAPE>::EXT_W, EXT_H = BatchShape<SHAPE>::EXT_H;
-    const BatchTile tile = bc.tiles[t];
     const BatchJob& job = bc.jobs[uni(tile.job)];
     FwdParams prm{};
     prm.img = uni(job.img);
@@ -100,6 +102,34 @@ __device__ __forceinline__ void batch_tile(
     fwd_tile<W, KIND, DIST, true, EXT_W, EXT_H, false>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0), tid);
 }
 
+// LDS of a group kernel: room for the tile of any pair term.
+template <int W, int KIND, int SHAPE>
+struct BatchSmem {
+    template <int DIST>
+    using Sh = FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W,
+                            BatchShape<SHAPE>::EXT_H, false>;
+    static constexpr size_t a = sizeof(Sh<kExact>), b = sizeof(Sh<kMinimax>),
+                            c = sizeof(Sh<kRgb>);
+    static constexpr size_t BYTES = a > b ? (a > c ? a : c) : (b > c ? b : c);
+};
+
+// Tile t of a group list: its pair term comes from the job (uniform branch).
+template <int W, int KIND, int SHAPE>
+__device__ __forceinline__ void batch_tile_any(char* smem, const BatchClass& bc, int t) {
+    const BatchTile tile = bc.tiles[t];
+    const int dist = uni(bc.jobs[uni(tile.job)].dist);
+    using S = BatchSmem<W, KIND, SHAPE>;
+    if (dist == kExact)
+        batch_tile<W, KIND, kExact, SHAPE>(*reinterpret_cast<typename S::template Sh<kExact>*>(smem),
+                                           bc, tile);
+    else if (dist == kMinimax)
+        batch_tile<W, KIND, kMinimax, SHAPE>(
+            *reinterpret_cast<typename S::template Sh<kMinimax>*>(smem), bc, tile);
+    else
+        batch_tile<W, KIND, kRgb, SHAPE>(*reinterpret_cast<typename S::template Sh<kRgb>*>(smem),
+                                         bc, tile);
+}
+
 template <int W>
 constexpr int persistent_shape() {
     return W == 5 ? 1 : 0;
@@ -107,88 +137,74 @@ constexpr int persistent_shape() {
 
 // Persistent form: workgroups take tiles with an atomic counter until the
 // list is exhausted.
-template <int W, int KIND, int DIST>
+template <int W, int KIND>
 __global__ void __launch_bounds__(BatchShape<persistent_shape<W>()>::THREADS)
     batch_kernel(BatchClass bc) {
     constexpr int SHAPE = persistent_shape<W>();
-    __shared__ FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
+    __shared__ __align__(16) char smem[BatchSmem<W, KIND, SHAPE>::BYTES];
     __shared__ int s_tile;
     for (;;) {
-        __syncthreads();  // the previous tile is finished with s_tile and sh
+        __syncthreads();  // the previous tile is finished with s_tile and smem
         if (threadIdx.x == 0) s_tile = atomicAdd(bc.counter, 1);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_tile);
         if (t >= bc.ntiles) break;
-        batch_tile<W, KIND, DIST, SHAPE>(sh, bc, t);
+        batch_tile_any<W, KIND, SHAPE>(smem, bc, t);
     }
 }
 
 // Direct form: one workgroup per tile of the list, dispatched in list order.
-template <int W, int KIND, int DIST, int SHAPE>
+template <int W, int KIND, int SHAPE>
 __global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS)
     __attribute__((amdgpu_waves_per_eu(W == 3 && KIND != kACW ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
-    __shared__ FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false> sh;
-    batch_tile<W, KIND, DIST, SHAPE>(sh, bc, blockIdx.x);
+    __shared__ __align__(16) char smem[BatchSmem<W, KIND, SHAPE>::BYTES];
+    batch_tile_any<W, KIND, SHAPE>(smem, bc, blockIdx.x);
 }
 
 __global__ void batch_reset(int* counters, int n) {
     if (threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
-// class = ((window == 5) * 2 + kind) * 3 + dist
-static int class_window(int cls) { return cls / 6 ? 5 : 3; }
+// class = ((window == 5) * 2 + kind) * 3 + dist; group = class / 3
+constexpr int kNumGroups = kNumClasses / 3;
+static int group_window(int grp) { return grp / 2 ? 5 : 3; }
 
-static void class_geometry(int cls, int shape, int& tw, int& th, int& threads) {
-    const int h = class_window(cls) / 2;
+static void group_geometry(int grp, int shape, int& tw, int& th, int& threads) {
+    const int h = group_window(grp) / 2;
     tw = BatchShape<0>::EXT_W - 2 * h;
     th = (shape == 0 ? BatchShape<0>::EXT_H : BatchShape<1>::EXT_H) - 2 * h;
     threads = shape == 0 ? BatchShape<0>::THREADS : BatchShape<1>::THREADS;
 }
 
-template <int W, int KIND>
-static const void* persistent_kernel_wk(int dist) {
-    if (dist == kExact) return reinterpret_cast<const void*>(&batch_kernel<W, KIND, kExact>);
-    if (dist == kMinimax) return reinterpret_cast<const void*>(&batch_kernel<W, KIND, kMinimax>);
-    return reinterpret_cast<const void*>(&batch_kernel<W, KIND, kRgb>);
-}
-
-static const void* persistent_kernel(int cls) {
-    switch (cls / 3) {
-    case 0: return persistent_kernel_wk<3, kBVDF>(cls % 3);
-    case 1: return persistent_kernel_wk<3, kDDF>(cls % 3);
-    case 2: return persistent_kernel_wk<5, kBVDF>(cls % 3);
-    default: return persistent_kernel_wk<5, kDDF>(cls % 3);
+static const void* persistent_kernel(int grp) {
+    switch (grp) {
+    case 0: return reinterpret_cast<const void*>(&batch_kernel<3, kBVDF>);
+    case 1: return reinterpret_cast<const void*>(&batch_kernel<3, kDDF>);
+    case 2: return reinterpret_cast<const void*>(&batch_kernel<5, kBVDF>);
+    default: return reinterpret_cast<const void*>(&batch_kernel<5, kDDF>);
     }
 }
 
-template <int W, int KIND, int DIST>
-static void launch_class_wkd(bool direct, int shape, int grid, int threads, const BatchClass& bc,
-                             hipStream_t s) {
-    if (!direct)
-        hipLaunchKernelGGL((batch_kernel<W, KIND, DIST>), dim3(grid), dim3(threads), 0, s, bc);
-    else if (shape == 0)
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, DIST, 0>), dim3(bc.ntiles), dim3(threads),
-                           0, s, bc);
-    else
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, DIST, 1>), dim3(bc.ntiles), dim3(threads),
-                           0, s, bc);
-}
-
 template <int W, int KIND>
-static void launch_class_wk(int dist, bool direct, int shape, int grid, int threads,
-                            const BatchClass& bc, hipStream_t s) {
-    if (dist == kExact) launch_class_wkd<W, KIND, kExact>(direct, shape, grid, threads, bc, s);
-    else if (dist == kMinimax) launch_class_wkd<W, KIND, kMinimax>(direct, shape, grid, threads, bc, s);
-    else launch_class_wkd<W, KIND, kRgb>(direct, shape, grid, threads, bc, s);
+static void launch_group_wk(bool direct, int shape, int grid, int threads, const BatchClass& bc,
+                            hipStream_t s) {
+    if (!direct)
+        hipLaunchKernelGGL((batch_kernel<W, KIND>), dim3(grid), dim3(threads), 0, s, bc);
+    else if (shape == 0)
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), dim3(bc.ntiles), dim3(threads), 0, s,
+                           bc);
+    else
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), dim3(bc.ntiles), dim3(threads), 0, s,
+                           bc);
 }
 
-static void launch_class(int cls, bool direct, int shape, int grid, int threads,
+static void launch_group(int grp, bool direct, int shape, int grid, int threads,
                          const BatchClass& bc, hipStream_t s) {
-    switch (cls / 3) {
-    case 0: launch_class_wk<3, kBVDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
-    case 1: launch_class_wk<3, kDDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
-    case 2: launch_class_wk<5, kBVDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
-    default: launch_class_wk<5, kDDF>(cls % 3, direct, shape, grid, threads, bc, s); break;
+    switch (grp) {
+    case 0: launch_group_wk<3, kBVDF>(direct, shape, grid, threads, bc, s); break;
+    case 1: launch_group_wk<3, kDDF>(direct, shape, grid, threads, bc, s); break;
+    case 2: launch_group_wk<5, kBVDF>(direct, shape, grid, threads, bc, s); break;
+    default: launch_group_wk<5, kDDF>(direct, shape, grid, threads, bc, s); break;
     }
 }
 
@@ -199,39 +215,46 @@ struct odf_plan {
     odf::BatchJob* d_jobs = nullptr;
     odf::BatchTile* d_tiles = nullptr;
     int* d_counters = nullptr;
-    int ntiles[odf::kNumClasses] = {};
-    int offset[odf::kNumClasses] = {};
-    int grid[odf::kNumClasses] = {};
-    int shape[odf::kNumClasses] = {};
+    int class_tiles[odf::kNumClasses] = {};  // per class, for odf_plan_info
+    int ntiles[odf::kNumGroups] = {};
+    int offset[odf::kNumGroups] = {};
+    int grid[odf::kNumGroups] = {};
+    int shape[odf::kNumGroups] = {};
     int njobs = 0;
     long long npix = 0;
     int flags = 0;
-    hipStream_t aux[odf::kNumClasses] = {};
+    hipStream_t aux[odf::kNumGroups] = {};
     hipEvent_t fork = nullptr;
-    hipEvent_t join[odf::kNumClasses] = {};
+    hipEvent_t join[odf::kNumGroups] = {};
 };
 
 namespace {
 
 int bfail(int code, const char* msg) { return odf::set_error(code, "%s", msg); }
 
-
-// Tile shape of a class: fixed for the persistent form, from the tuning
-// table for the direct form.
-int shape_of(int cls, int flags) {
-    const int w = odf::class_window(cls);
+// Tile shape of a group: fixed for the persistent form; for the direct form
+// the tuning table's shape of the group's pair term with the most pixels.
+int shape_of(int grp, int flags, const long long (&dist_pixels)[3]) {
+    const int w = odf::group_window(grp);
     if (flags != ODF_BATCH_DIRECT) return w == 5 ? 1 : 0;
-    const int cfg = odf::tuned_config(w, (cls / 3) % 2, cls % 3, true);
+    int dist = 0;
+    for (int d = 1; d < 3; ++d)
+        if (dist_pixels[d] > dist_pixels[dist]) dist = d;
+    const int cfg = odf::tuned_config(w, grp % 2, dist, true);
     int ew, eh;
     odf::tile_config_shape(cfg, &ew, &eh);
     return ew * eh >= 1024 ? 0 : 1;
 }
 
+// Relative cost of a tile pixel per pair term (3x3 DDF instruction counts),
+// used to put the heaviest tiles first.
+int dist_weight(int dist) { return dist == ODF_MINIMAX ? 13 : (dist == ODF_EXACT ? 12 : 10); }
+
 void destroy(odf_plan* p) {
     if (!p) return;
-    for (int c = 0; c < odf::kNumClasses; ++c) {
-        if (p->aux[c]) (void)hipStreamDestroy(p->aux[c]);
-        if (p->join[c]) (void)hipEventDestroy(p->join[c]);
+    for (int g = 0; g < odf::kNumGroups; ++g) {
+        if (p->aux[g]) (void)hipStreamDestroy(p->aux[g]);
+        if (p->join[g]) (void)hipEventDestroy(p->join[g]);
     }
     if (p->fork) (void)hipEventDestroy(p->fork);
     (void)hipFree(p->d_jobs);
@@ -256,8 +279,7 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
     *plan = nullptr;
     if (!jobs || njobs < 1) return bfail(ODF_EINVAL, "jobs must be a non-empty array");
     std::vector<odf::BatchJob> hj(njobs);
-    std::vector<std::pair<int, odf::BatchTile>> lists[odf::kNumClasses];
-    long long npix = 0;
+    long long dist_pixels[odf::kNumGroups][3] = {};
     for (int i = 0; i < njobs; ++i) {
         const odf_job& j = jobs[i];
         if (!j.img || !j.out) return bfail(ODF_EINVAL, "job img/out is NULL");
@@ -272,6 +294,17 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         const char* a = (const char*)j.img;
         const char* o = (const char*)j.out;
         if (a < o + nb && o < a + nb) return bfail(ODF_EINVAL, "job out overlaps img");
+        dist_pixels[(j.window == 5) * 2 + (j.kind == ODF_DDF)][j.dist] += (long long)j.M * j.N;
+    }
+    int shape[odf::kNumGroups];
+    for (int g = 0; g < odf::kNumGroups; ++g) shape[g] = shape_of(g, flags, dist_pixels[g]);
+
+    // (cost, tile) per group; cost = output pixels x pair-term weight
+    std::vector<std::pair<long long, odf::BatchTile>> lists[odf::kNumGroups];
+    int class_tiles[odf::kNumClasses] = {};
+    long long npix = 0;
+    for (int i = 0; i < njobs; ++i) {
+        const odf_job& j = jobs[i];
         odf::BatchJob& b = hj[i];
         b.img = j.img;
         b.out = j.out;
@@ -282,27 +315,29 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         b.p = j.kind == ODF_DDF ? j.p : 0.0f;
         b.coef = odf::MinimaxCoef{};
         if (j.dist == ODF_MINIMAX) b.coef = odf::minimax_coef(j.q);
-        const int cls = ((j.window == 5) * 2 + (j.kind == ODF_DDF)) * 3 + j.dist;
+        const int grp = (j.window == 5) * 2 + (j.kind == ODF_DDF);
         int tw, th, thr;
-        odf::class_geometry(cls, shape_of(cls, flags), tw, th, thr);
+        odf::group_geometry(grp, shape[grp], tw, th, thr);
         for (int ty = 0; ty < j.M; ty += th)
             for (int tx = 0; tx < j.N; tx += tw) {
-                // cost: output pixels of the (possibly clipped) tile
-                const int cost = std::min(th, j.M - ty) * std::min(tw, j.N - tx);
-                lists[cls].push_back({cost, odf::BatchTile{i, ty, tx}});
+                const long long cost = (long long)std::min(th, j.M - ty) * std::min(tw, j.N - tx) *
+                                       dist_weight(j.dist);
+                lists[grp].push_back({cost, odf::BatchTile{i, ty, tx}});
+                ++class_tiles[grp * 3 + j.dist];
             }
         npix += (long long)j.M * j.N;
     }
     odf_plan* p = new (std::nothrow) odf_plan;
     if (!p) return bfail(ODF_ENOMEM, "plan allocation failed");
+    for (int c = 0; c < odf::kNumClasses; ++c) p->class_tiles[c] = class_tiles[c];
     std::vector<odf::BatchTile> all;
-    for (int c = 0; c < odf::kNumClasses; ++c) {
-        std::stable_sort(lists[c].begin(), lists[c].end(),
-                         [](const std::pair<int, odf::BatchTile>& x,
-                            const std::pair<int, odf::BatchTile>& y) { return x.first > y.first; });
-        p->offset[c] = (int)all.size();
-        p->ntiles[c] = (int)lists[c].size();
-        for (auto& t : lists[c]) all.push_back(t.second);
+    for (int g = 0; g < odf::kNumGroups; ++g) {
+        std::stable_sort(lists[g].begin(), lists[g].end(),
+                         [](const std::pair<long long, odf::BatchTile>& x,
+                            const std::pair<long long, odf::BatchTile>& y) { return x.first > y.first; });
+        p->offset[g] = (int)all.size();
+        p->ntiles[g] = (int)lists[g].size();
+        for (auto& t : lists[g]) all.push_back(t.second);
     }
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -310,23 +345,23 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         destroy(p);
         return bfail(ODF_EHIP, "cannot query the compute unit count");
     }
-    for (int c = 0; c < odf::kNumClasses; ++c) {
+    for (int g = 0; g < odf::kNumGroups; ++g) {
         int tw, th, thr, per_cu = 0;
-        p->shape[c] = shape_of(c, flags);
-        odf::class_geometry(c, p->shape[c], tw, th, thr);
+        p->shape[g] = shape[g];
+        odf::group_geometry(g, p->shape[g], tw, th, thr);
         if (flags == ODF_BATCH_DIRECT) {
-            p->grid[c] = p->ntiles[c];
+            p->grid[g] = p->ntiles[g];
             continue;
         }
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, odf::persistent_kernel(c), thr,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, odf::persistent_kernel(g), thr,
                                                          0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        p->grid[c] = std::min(p->ntiles[c], per_cu * cus);
+        p->grid[g] = std::min(p->ntiles[g], per_cu * cus);
     }
     if (hipMalloc(&p->d_jobs, sizeof(odf::BatchJob) * hj.size()) != hipSuccess ||
         hipMalloc(&p->d_tiles, sizeof(odf::BatchTile) * std::max<size_t>(1, all.size())) != hipSuccess ||
-        hipMalloc(&p->d_counters, sizeof(int) * odf::kNumClasses) != hipSuccess) {
+        hipMalloc(&p->d_counters, sizeof(int) * odf::kNumGroups) != hipSuccess) {
         destroy(p);
         return bfail(ODF_ENOMEM, "device allocation for the plan failed");
     }
@@ -334,17 +369,17 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
             hipSuccess ||
         hipMemcpy(p->d_tiles, all.data(), sizeof(odf::BatchTile) * all.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
-        hipMemset(p->d_counters, 0, sizeof(int) * odf::kNumClasses) != hipSuccess) {
+        hipMemset(p->d_counters, 0, sizeof(int) * odf::kNumGroups) != hipSuccess) {
         destroy(p);
         return bfail(ODF_EHIP, "uploading the plan failed");
     }
-    // auxiliary streams for every non-empty class after the first
+    // auxiliary streams for every non-empty group after the first
     bool first = true;
-    for (int c = 0; c < odf::kNumClasses; ++c) {
-        if (p->ntiles[c] == 0) continue;
+    for (int g = 0; g < odf::kNumGroups; ++g) {
+        if (p->ntiles[g] == 0) continue;
         if (first) { first = false; continue; }
-        if (hipStreamCreateWithFlags(&p->aux[c], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&p->aux[g], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->join[g], hipEventDisableTiming) != hipSuccess) {
             destroy(p);
             return bfail(ODF_EHIP, "creating the plan's streams failed");
         }
@@ -363,22 +398,23 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
 int odf_batch_launch(const odf_plan* plan, void* stream) {
     if (!plan) return bfail(ODF_EINVAL, "plan is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(odf::batch_reset, dim3(1), dim3(64), 0, s, plan->d_counters,
-                       odf::kNumClasses);
+    const bool direct = plan->flags == ODF_BATCH_DIRECT;
+    if (!direct)  // the persistent kernels' tile counters start at 0
+        hipLaunchKernelGGL(odf::batch_reset, dim3(1), dim3(64), 0, s, plan->d_counters,
+                           odf::kNumGroups);
     if (hipEventRecord(plan->fork, s) != hipSuccess) return bfail(ODF_EHIP, "fork event failed");
-    for (int c = 0; c < odf::kNumClasses; ++c) {
-        if (plan->ntiles[c] == 0) continue;
-        odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[c], plan->d_counters + c,
-                           plan->ntiles[c]};
+    for (int g = 0; g < odf::kNumGroups; ++g) {
+        if (plan->ntiles[g] == 0) continue;
+        odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[g], plan->d_counters + g,
+                           plan->ntiles[g]};
         int tw, th, thr;
-        odf::class_geometry(c, plan->shape[c], tw, th, thr);
-        hipStream_t cs = plan->aux[c] ? plan->aux[c] : s;
+        odf::group_geometry(g, plan->shape[g], tw, th, thr);
+        hipStream_t cs = plan->aux[g] ? plan->aux[g] : s;
         if (cs != s && hipStreamWaitEvent(cs, plan->fork, 0) != hipSuccess)
             return bfail(ODF_EHIP, "stream fork failed");
-        odf::launch_class(c, plan->flags == ODF_BATCH_DIRECT, plan->shape[c], plan->grid[c], thr, bc,
-                          cs);
-        if (cs != s && (hipEventRecord(plan->join[c], cs) != hipSuccess ||
-                        hipStreamWaitEvent(s, plan->join[c], 0) != hipSuccess))
+        odf::launch_group(g, direct, plan->shape[g], plan->grid[g], thr, bc, cs);
+        if (cs != s && (hipEventRecord(plan->join[g], cs) != hipSuccess ||
+                        hipStreamWaitEvent(s, plan->join[g], 0) != hipSuccess))
             return bfail(ODF_EHIP, "stream join failed");
     }
     hipError_t e = hipGetLastError();
@@ -391,8 +427,13 @@ int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles
     if (njobs) *njobs = plan->njobs;
     if (npix) *npix = plan->npix;
     for (int c = 0; c < odf::kNumClasses; ++c) {
-        if (ntiles) ntiles[c] = plan->ntiles[c];
-        if (grids) grids[c] = plan->grid[c];
+        const int g = c / 3;
+        if (ntiles) ntiles[c] = plan->class_tiles[c];
+        // workgroups launched for the class's tiles: one per tile (direct) or
+        // the grid of its group's persistent kernel
+        if (grids)
+            grids[c] = plan->class_tiles[c] == 0 ? 0
+                       : (plan->flags == ODF_BATCH_DIRECT ? plan->class_tiles[c] : plan->grid[g]);
     }
     return ODF_OK;
 }

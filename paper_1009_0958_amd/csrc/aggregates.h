@@ -103,7 +103,7 @@ __device__ __forceinline__ void member_aggregates_x(
     if constexpr (PASS == 1) {
         self[0] = 0.0f;
     } else {
-        self[0] = pair_term<KIND, DIST, U8>(mdir, mraw, mdir, mraw, cf, ac);
+        self[0] = self_term<KIND, DIST>(cf);
         if constexpr (NP == 2) self[NP - 1] = 0.0f;
     }
 
@@ -236,27 +236,32 @@ __device__ __forceinline__ int objective_mode(float p) {
     return kObjLog;
 }
 
-// Order keys of the objective for all n members, one uniform branch.
+// Order bits of the objective of all n members, one uniform branch on the
+// mode (outside the member loop, so no member pays for the other modes).
+// Every mode but the logarithmic one yields a non-negative value (sums and
+// products of non-negative terms, never -0 or NaN), whose binary32 bit
+// pattern already orders like the value; the logarithmic mode can be
+// negative and takes the sign-aware order_key.
 template <int NW>
-__device__ __forceinline__ void objective_keys(int mode, float p, const float (&A)[NW],
-                                               const float (&D)[NW], float (&om)[NW]) {
+__device__ __forceinline__ void objective_key_bits(int mode, float p, const float (&A)[NW],
+                                                   const float (&D)[NW], uint32_t (&kb)[NW]) {
     if (mode == kObjA) {
 #pragma unroll
-        for (int u = 0; u < NW; ++u) om[u] = A[u];
+        for (int u = 0; u < NW; ++u) kb[u] = __float_as_uint(A[u]);
     } else if (mode == kObjD) {
 #pragma unroll
-        for (int u = 0; u < NW; ++u) om[u] = D[u];
+        for (int u = 0; u < NW; ++u) kb[u] = __float_as_uint(D[u]);
     } else if (mode == kObjProd) {
 #pragma unroll
-        for (int u = 0; u < NW; ++u) om[u] = A[u] * D[u];
+        for (int u = 0; u < NW; ++u) kb[u] = __float_as_uint(A[u] * D[u]);
     } else if (mode == kObjQuarter) {
 #pragma unroll
-        for (int u = 0; u < NW; ++u) om[u] = (A[u] * A[u]) * (A[u] * D[u]);
+        for (int u = 0; u < NW; ++u) kb[u] = __float_as_uint((A[u] * A[u]) * (A[u] * D[u]));
     } else {
         const float q = 1.0f - p;
 #pragma unroll
         for (int u = 0; u < NW; ++u)
-            om[u] = fmaf(q, __builtin_amdgcn_logf(A[u]), p * __builtin_amdgcn_logf(D[u]));
+            kb[u] = order_key(fmaf(q, __builtin_amdgcn_logf(A[u]), p * __builtin_amdgcn_logf(D[u])));
     }
 }
 

@@ -12,6 +12,8 @@
 //       copied to the output.
 #pragma once
 
+#include <type_traits>
+
 #include "aggregates.h"
 #include "odf_internal.h"
 
@@ -49,14 +51,6 @@ struct FwdShared {
         return HALO ? (cy + 2 * Gm::H) * EXT_W + cx + 2 * Gm::H : cy * Gm::TW + cx;
     }
 };
-
-// Order bits of an objective.  Every mode but the logarithmic one yields a
-// non-negative value (sums and products of non-negative terms, never -0 or
-// NaN), whose binary32 bit pattern already orders like the value; the
-// logarithmic mode can be negative and takes the sign-aware order_key.
-__device__ __forceinline__ uint32_t objective_bits(float v, bool may_be_negative) {
-    return may_be_negative ? order_key(v) : __float_as_uint(v);
-}
 
 template <int W, int KIND, bool AGG>
 constexpr bool stage_angle_part() {
@@ -138,33 +132,48 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
         // angle part of each objective -> LDS, then the L2 pass, then the keys
         const int mode = objective_mode<KIND>(prm.p);
         const float p = prm.p;
+        auto stage_parts = [&](auto mode_c) {
+            constexpr int MODE = decltype(mode_c)::value;
 #pragma unroll
-        for (int u = 0; u < NW; ++u) {
-            const int cy = ey - u / W, cx = ex - u % W;
-            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-            const float a = A[u];
-            float part = a;                                             // A, A*D
-            if (mode == kObjQuarter) part = (a * a) * a;                // A^3 D
-            else if (mode == kObjLog) part = (1.0f - p) * __builtin_amdgcn_logf(a);
-            sh.stage[u * (TH * TW) + cy * TW + cx] = part;
-        }
+            for (int u = 0; u < NW; ++u) {
+                const int cy = ey - u / W, cx = ex - u % W;
+                if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+                const float a = A[u];
+                float part = a;                                            // A, A*D
+                if constexpr (MODE == kObjQuarter) part = (a * a) * a;     // A^3 D
+                else if constexpr (MODE == kObjLog) part = (1.0f - p) * __builtin_amdgcn_logf(a);
+                sh.stage[u * (TH * TW) + cy * TW + cx] = part;
+            }
+        };
+        if (mode == kObjQuarter) stage_parts(std::integral_constant<int, kObjQuarter>{});
+        else if (mode == kObjLog) stage_parts(std::integral_constant<int, kObjLog>{});
+        else stage_parts(std::integral_constant<int, kObjA>{});
         member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true, false>(px, s_plane, ey, ex, tid,
                                                                        mdir, mraw, prm.coef, D);
+        // one copy of the key loop per objective mode (a uniform branch
+        // outside the member loop)
+        auto stage_keys = [&](auto mode_c) {
+            constexpr int MODE = decltype(mode_c)::value;
 #pragma unroll
-        for (int u = 0; u < NW; ++u) {
-            const int cy = ey - u / W, cx = ex - u % W;
-            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-            if (ty0 + cy >= M || tx0 + cx >= N) continue;
-            const float part = sh.stage[u * (TH * TW) + cy * TW + cx];
-            float om;
-            if (mode == kObjA) om = part;
-            else if (mode == kObjD) om = D[u];
-            else if (mode == kObjLog) om = fmaf(p, __builtin_amdgcn_logf(D[u]), part);
-            else om = part * D[u];
-            const unsigned long long key =
-                ((unsigned long long)objective_bits(om, mode == kObjLog) << 32) | (unsigned)u;
-            atomicMin(&s_key[Sh::key_index(cy, cx)], key);
-        }
+            for (int u = 0; u < NW; ++u) {
+                const int cy = ey - u / W, cx = ex - u % W;
+                if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+                if (ty0 + cy >= M || tx0 + cx >= N) continue;
+                const float part = sh.stage[u * (TH * TW) + cy * TW + cx];
+                uint32_t bits;
+                if constexpr (MODE == kObjA) bits = __float_as_uint(part);
+                else if constexpr (MODE == kObjD) bits = __float_as_uint(D[u]);
+                else if constexpr (MODE == kObjLog)
+                    bits = order_key(fmaf(p, __builtin_amdgcn_logf(D[u]), part));
+                else bits = __float_as_uint(part * D[u]);  // non-negative: bits order
+                const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned)u;
+                atomicMin(&s_key[Sh::key_index(cy, cx)], key);
+            }
+        };
+        if (mode == kObjA) stage_keys(std::integral_constant<int, kObjA>{});
+        else if (mode == kObjD) stage_keys(std::integral_constant<int, kObjD>{});
+        else if (mode == kObjLog) stage_keys(std::integral_constant<int, kObjLog>{});
+        else stage_keys(std::integral_constant<int, kObjProd>{});
     } else {
     if constexpr (fused_sweep<W, KIND>())
         ;  // D and cD came with the angular sweep
@@ -227,15 +236,12 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             atomicMin(&s_key[3 * KEYN + ci], ((unsigned long long)__float_as_uint(o3) << 32) | uu);
         }
     } else {
-        float om[NW];
-        const int mode = objective_mode<KIND>(prm.p);
-        objective_keys<NW>(mode, prm.p, A, D, om);
+        uint32_t kb[NW];
+        objective_key_bits<NW>(objective_mode<KIND>(prm.p), prm.p, A, D, kb);
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             if (!window_ok(u)) continue;
-            const unsigned long long key =
-                ((unsigned long long)objective_bits(om[u], mode == kObjLog) << 32) | (unsigned)u;
-            atomicMin(&s_key[key_slot(u)], key);
+            atomicMin(&s_key[key_slot(u)], ((unsigned long long)kb[u] << 32) | (unsigned)u);
         }
     }
     }

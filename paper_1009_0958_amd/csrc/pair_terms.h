@@ -54,9 +54,14 @@ struct AtanCoef {
 
 __device__ __forceinline__ AtanCoef atan_coef() {
     AtanCoef a;
-    a.c[0] = kAtanPoly[0];  // 1: an inline constant
 #pragma unroll
-    for (int k = 1; k <= ODF_ATAN_DEG; ++k) a.c[k] = scalar_const(kAtanPoly[k]);
+    for (int k = 0; k <= ODF_ATAN_DEG; ++k) a.c[k] = kAtanPoly[k];
+    // all but c0 (1, an inline constant) and the second-highest, which the
+    // first Horner step takes as its literal (c_deg t + c_deg-1 is then one
+    // multiply-add with a scalar and a literal operand)
+#pragma unroll
+    for (int k = 1; k <= ODF_ATAN_DEG; ++k)
+        if (k != ODF_ATAN_DEG - 1) a.c[k] = scalar_const(kAtanPoly[k]);
     return a;
 }
 
@@ -77,6 +82,17 @@ __device__ __forceinline__ float cross_diff(float a, float b, float c, float d) 
 }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// 1/sqrt(x) for a product x = u v that is 0 only when a factor u is 0, used as
+// u * rsq_pos(x): the result must be finite at x = 0.  uint8 inputs (INT): x
+// is 0 or at least 1, so rsq(x) lies in (0, 1] or is +inf at 0, and clamping
+// to [0, 1] (the instruction's clamp modifier, free) maps +inf to 1;
+// otherwise x is raised to the smallest normal number first.
+template <bool INT>
+__device__ __forceinline__ float rsq_pos(float x) {
+    if constexpr (INT) return __builtin_amdgcn_fmed3f(rsq(x), 0.0f, 1.0f);
+    else return rsq(fmaxf(x, 1.17549435e-38f));
+}
 __device__ __forceinline__ float sqrt_raw(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Table 1 coefficients, zero-padded to degree 4 (Horner with leading zeros
@@ -171,7 +187,7 @@ __device__ __forceinline__ float angle_exact_from_dot(const float4& a, const flo
     float P = cross_norm2<U8>(a, b, fabsf(a.w), fabsf(b.w), dot);
     float Q = dot * dot;
     float m = fminf(P, Q);
-    float r = m * rsq(fmaxf(P * Q, 1.17549435e-38f));
+    float r = m * rsq_pos<U8>(P * Q);
     float t = r * r;
     float acc = ac.c[ODF_ATAN_DEG];
 #pragma unroll
@@ -214,7 +230,7 @@ __device__ __forceinline__ float angle_minimax_from_dot(const float4& a, float i
     }
     float P = cross_norm2<U8>(a, b, na, nb, dot);
     float X = (na * nb) * (1.0f + z);
-    float tau = P * rsq(fmaxf(P * X, 1.17549435e-38f));
+    float tau = P * rsq_pos<U8>(P * X);
     // the clamp at 0 matters for the ASIN row only (q = 3 dips below 0 next to
     // tau = 0); every ACOS row stays above 1 on [-1, 1/2]
     return acos_branch ? horner4(cf.acos_c, z) : fmaxf(horner4(cf.asin_c, tau), 0.0f);
@@ -238,6 +254,18 @@ __device__ __forceinline__ float chroma_term(const float4& a, float ia, const fl
     float B = sqrt_raw(Nn) * (ia * ib);
     if (KIND != kBVDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
     return B;
+}
+
+// The angular term of a pixel with itself, a constant of the variant: the
+// cross product and the chromaticity numerators of equal vectors vanish
+// exactly (both layouts), so the exact angle is 0, the minimax angle the ASIN
+// row at tau = 0 (its constant coefficient, clamped at 0), and the
+// chromaticity distance 0 (eq. 10 maps it to its offset).
+template <int KIND, int DIST>
+__device__ __forceinline__ float self_term(const MinimaxCoef& cf) {
+    if (DIST == kExact) return 0.0f;
+    if (DIST == kMinimax) return fmaxf(cf.asin_c[0], 0.0f);
+    return KIND != kBVDF ? kEq10Beta : 0.0f;
 }
 
 // Angular pair term of the chosen variant (float layout, or uint8 with raw.w =

@@ -434,12 +434,12 @@ def effectiveness_forms(torch, odf, synth, dev, DIST):
 
 def batched_form(torch, odf, synth, dev):
     """256 uint8 images of mixed size (64..2048 x 64..1536), window, kind and
-    noise: one planned launch captured in a graph (direct form, whose tile
-    shapes come from the autotuned table, and persistent form), against a loop
-    of per-image launches of the same jobs."""
+    noise: one planned launch captured in a graph (direct and persistent form;
+    one kernel per window and kind), against a loop of per-image launches of
+    the same jobs (tile shapes from the autotuned table)."""
     specs = synth.mixed_batch_specs(256)
     imgs = synth.mixed_batch_images(specs, workers=16)
-    # tile shapes of the four classes in the batch (untimed)
+    # tile shapes of the per-image launches of the loop (untimed)
     tuned = {}
     for w in (3, 5):
         for kind in (odf.BVDF, odf.DDF):
@@ -478,7 +478,8 @@ def batched_form(torch, odf, synth, dev):
     ms_direct, same_d, info = res["direct"]
     ms_pers, same_p, _ = res["persistent"]
     return {"batched_256_mixed": {
-        "mpix": round(npx / 1e6, 2), "tile_shapes": tuned,
+        "mpix": round(npx / 1e6, 2), "loop_tile_shapes": tuned,
+        "batch_tile_shapes": {"w3_ddf": [32, 32], "other": [32, 16]},
         "direct_graph_ms": round(ms_direct, 3), "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
         "persistent_graph_ms": round(ms_pers, 3),
         "persistent_graph_mpix_s": round(npx / (ms_pers * 1e3), 1),

@@ -213,8 +213,8 @@ int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream
 
 /* odf_batch_plan with a launch form: ODF_BATCH_DIRECT (what odf_batch_plan
  * uses: one workgroup per tile of the work list, dispatched by the hardware
- * in list order, tile shape from the tuning table entry of the group's pair
- * term with the most pixels) or ODF_BATCH_PERSISTENT
+ * in list order; tiles of 32 x 32 for 3x3 DDF and 32 x 16 otherwise, the
+ * shapes with the best rate over many tiles) or ODF_BATCH_PERSISTENT
  * (persistent workgroups taking tiles with an atomic counter).  Same results;
  * on MI355X the direct form is faster (the persistent loop costs registers). */
 enum { ODF_BATCH_PERSISTENT = 0, ODF_BATCH_DIRECT = 1 };

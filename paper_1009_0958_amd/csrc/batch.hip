@@ -232,18 +232,16 @@ namespace {
 
 int bfail(int code, const char* msg) { return odf::set_error(code, "%s", msg); }
 
-// Tile shape of a group: fixed for the persistent form; for the direct form
-// the tuning table's shape of the group's pair term with the most pixels.
-int shape_of(int grp, int flags, const long long (&dist_pixels)[3]) {
+// Tile shape of a group.  A plan is one launch over many tiles, so the shape
+// with the best steady-state rate wins (measured on MI355X on 3840 x 2160
+// frames: 32 x 32 for 3x3 DDF, 32 x 16 for 3x3 BVDF and for 5x5); the
+// per-image tuning table, chosen where a single image's last partial wave of
+// workgroups matters, is not consulted.  The persistent form's loop needs
+// 32 x 16 for 5x5 (registers).
+int shape_of(int grp, int flags) {
     const int w = odf::group_window(grp);
     if (flags != ODF_BATCH_DIRECT) return w == 5 ? 1 : 0;
-    int dist = 0;
-    for (int d = 1; d < 3; ++d)
-        if (dist_pixels[d] > dist_pixels[dist]) dist = d;
-    const int cfg = odf::tuned_config(w, grp % 2, dist, true);
-    int ew, eh;
-    odf::tile_config_shape(cfg, &ew, &eh);
-    return ew * eh >= 1024 ? 0 : 1;
+    return (w == 3 && grp % 2 == ODF_DDF) ? 0 : 1;
 }
 
 // Relative cost of a tile pixel per pair term (3x3 DDF instruction counts),
@@ -279,7 +277,6 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
     *plan = nullptr;
     if (!jobs || njobs < 1) return bfail(ODF_EINVAL, "jobs must be a non-empty array");
     std::vector<odf::BatchJob> hj(njobs);
-    long long dist_pixels[odf::kNumGroups][3] = {};
     for (int i = 0; i < njobs; ++i) {
         const odf_job& j = jobs[i];
         if (!j.img || !j.out) return bfail(ODF_EINVAL, "job img/out is NULL");
@@ -294,10 +291,9 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         const char* a = (const char*)j.img;
         const char* o = (const char*)j.out;
         if (a < o + nb && o < a + nb) return bfail(ODF_EINVAL, "job out overlaps img");
-        dist_pixels[(j.window == 5) * 2 + (j.kind == ODF_DDF)][j.dist] += (long long)j.M * j.N;
     }
     int shape[odf::kNumGroups];
-    for (int g = 0; g < odf::kNumGroups; ++g) shape[g] = shape_of(g, flags, dist_pixels[g]);
+    for (int g = 0; g < odf::kNumGroups; ++g) shape[g] = shape_of(g, flags);
 
     // (cost, tile) per group; cost = output pixels x pair-term weight
     std::vector<std::pair<long long, odf::BatchTile>> lists[odf::kNumGroups];

@@ -50,28 +50,31 @@ L2_SLOTS = 6 + TRANS         # 3 sub, 3 fma/mul, sqrt
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-slots/s
 
 # ------------------------------------------------------------------ HBM traffic
-# Bytes the DDF 3x3 uint8 forward kernel moves to and from HBM per 1024 x 1024
-# launch: rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch, one
-# pass each, from `bench.py --steps 3 --warmup 1 --no-forms --no-cpu
-# --step-forms loop --copy-probe-mib 256`), keyed by pair term and extended
-# tile.  Each counter is scaled by what it reads for the 256 MiB float32 copy
-# of the same run (262144 KiB read, 262144 KiB written): FETCH_SIZE read
-# 131085.2 KiB (x 1.99980), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold
-# for the kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources
-# bench.py reports traffic as null.
-TRAFFIC_FETCH_SCALE = 262144.0 / 131085.2
+# Bytes the DDF 3x3 uint8 forward kernels move to and from HBM on the
+# 1024 x 1024 image: rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per
+# dispatch, one pass each, from `bench.py --steps 3 --warmup 1 --no-forms
+# --no-cpu --step-forms loop,direct --copy-probe-mib 256`), keyed by pair term
+# and extended tile for the per-image kernel, and ("batch6", 32, 32) for the
+# batch group kernel running the step's six variants in one launch.  Each
+# counter is scaled by what it reads for the 256 MiB float32 copy of the same
+# run (262144 KiB read, 262144 KiB written): FETCH_SIZE read 131085.1 KiB
+# (x 1.99980), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold for the
+# kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources bench.py
+# reports traffic as null.
+TRAFFIC_FETCH_SCALE = 262144.0 / 131085.1
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact", 32, 32): (4091.3, 6144.0), ("exact", 64, 16): (2907.0, 5056.0),
-    ("exact", 32, 16): (4371.4, 6144.0), ("exact", 64, 8): (3196.5, 5056.0),
-    ("minimax", 32, 32): (4099.8, 6144.0), ("minimax", 64, 16): (2912.0, 5056.0),
-    ("minimax", 32, 16): (4389.9, 6144.0), ("minimax", 64, 8): (3209.0, 5056.0),
-    ("rgb", 32, 32): (4078.8, 6144.0), ("rgb", 64, 16): (2895.0, 5056.0),
-    ("rgb", 32, 16): (4359.4, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
+    ("exact", 32, 32): (4079.1, 6144.0), ("exact", 64, 16): (2892.0, 5056.0),
+    ("exact", 32, 16): (4365.9, 6144.0), ("exact", 64, 8): (3186.6, 5056.0),
+    ("minimax", 32, 32): (4090.3, 6144.0), ("minimax", 64, 16): (2906.5, 5056.0),
+    ("minimax", 32, 16): (4377.9, 6144.0), ("minimax", 64, 8): (3193.0, 5056.0),
+    ("rgb", 32, 32): (4076.2, 6144.0), ("rgb", 64, 16): (2886.0, 5056.0),
+    ("rgb", 32, 16): (4361.9, 6144.0), ("rgb", 64, 8): (3183.5, 5056.0),
+    ("batch6", 32, 32): (21777.5, 36889.2),
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "6d09a2ece8cab8995a4bfa96c1628ff14d315abde6b08b8871244196a7917753"
+TRAFFIC_SRC_SHA256 = "9e641a3e606982b08b70bc1262bd7c0ba06a0950bc99a7705c4f67335e9fde87"
 
 
 def forward_sources_sha256():

@@ -121,6 +121,55 @@ def test_degenerate_images(dist):
             run_and_check(img, 3, kind, p, dist)
 
 
+def _sparse_zeros(M, N, key):
+    """A smooth image with 8 % of its pixels (0, 0, 0), whole rows and columns of zeros on
+    and next to tile boundaries, and a zero corner."""
+    img = synth.image_corr(M, N, 0.15, key=key)
+    rng = np.random.default_rng(key)
+    img[rng.random((M, N)) < 0.08] = 0
+    img[[0, 13, 14, 29, 30], :] = 0
+    img[:, [0, 29, 30, 31]] = 0
+    img[-3:, -4:] = 0
+    return img
+
+
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("window", [3, 5, 7])
+def test_sparse_zero_pixels(window, dist):
+    # the zero pixel's direction (1,1,1) and value 0 next to nonzero neighbours: the
+    # uint8 layout marks it by the sign of its stored norm and takes its L2 terms from
+    # the other pixel's norm
+    img = _sparse_zeros(70, 97, key=window * 3 + dist)
+    for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 1.0)):
+        run_and_check(img, window, kind, p, dist, aggregates=window < 7)
+
+
+# 3x3 pattern whose colour X (twice) minimises every objective of a window holding it
+_X = (100, 80, 60)
+_PATTERN = np.array([[(120, 70, 75), (85, 90, 50), _X], [(110, 95, 52), (92, 66, 70), (104, 71, 49)],
+                     [_X, (96, 88, 66), (108, 84, 58)]], np.uint8)
+
+
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("u8", [True, False])
+def test_duplicate_colours_tie_exactly(dist, u8):
+    # Tiled with period 3, every interior 3x3 window holds the pattern's nine cells, so the
+    # two members of colour X tie in every objective; the filter must take the lower index.
+    # The member's term with itself (a per-variant constant) and its term with an equal
+    # colour (a pair evaluation) have to agree bit for bit for the tie to be exact.
+    M, N = 70, 97
+    img = np.tile(_PATTERN, (M // 3 + 1, N // 3 + 1, 1))[:M, :N]
+    x = _gpu(img if u8 else img.astype(np.float32))
+    for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 0.5)):
+        _, idx = odf.filter(x, 3, kind, p, dist)
+        idx = idx.cpu().numpy()
+        for r in range(1, M - 1):
+            for c in range(1, N - 1):
+                win = img[r - 1:r + 2, c - 1:c + 2].reshape(9, 3)
+                want = int(np.flatnonzero((win == _X).all(1))[0])
+                assert idx[r, c] == want, (dist, u8, kind, p, r, c, idx[r, c], want)
+
+
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
 def test_lone_impulse_never_selected(dist):
     img = np.full((21, 23, 3), (100, 50, 20), np.uint8)

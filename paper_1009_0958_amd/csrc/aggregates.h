@@ -31,8 +31,13 @@ struct FwdGeom {
     static constexpr int NT = EXT_W * EXT_H;
 };
 
+// The box sums are plain additions: contraction is off, so a pair term whose last
+// operation is a multiply (the BVDF chromaticity distance) is never fused into the
+// sum where the thread computed it but left unfused where it was read from LDS --
+// that would round the same term two ways and break the exact ties of equal colours.
 template <int W>
 __device__ __forceinline__ void row_sums(const float (&row)[4 * (W / 2) + 1], float (&out)[W]) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int s = 0; s < W; ++s) {
         float acc = row[s];
@@ -172,18 +177,22 @@ __device__ __forceinline__ void member_aggregates_x(
         }
         __syncthreads();
     }
+    {
+        // window aggregates: column sums of the row sums, top to bottom
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        float(&agg)[W * W] = k == 0 ? agg0 : agg1;
+        for (int k = 0; k < NP; ++k) {
+            float(&agg)[W * W] = k == 0 ? agg0 : agg1;
 #pragma unroll
-        for (int uy = -H; uy <= H; ++uy) {
+            for (int uy = -H; uy <= H; ++uy) {
 #pragma unroll
-            for (int ux = -H; ux <= H; ++ux) {
-                const int s = -H - ux + 2 * H;
-                float acc = R[k][-H - uy + 2 * H][s];
+                for (int ux = -H; ux <= H; ++ux) {
+                    const int s = -H - ux + 2 * H;
+                    float acc = R[k][-H - uy + 2 * H][s];
 #pragma unroll
-                for (int dy = -H - uy + 1; dy <= H - uy; ++dy) acc += R[k][dy + 2 * H][s];
-                agg[(uy + H) * W + (ux + H)] = acc;
+                    for (int dy = -H - uy + 1; dy <= H - uy; ++dy) acc += R[k][dy + 2 * H][s];
+                    agg[(uy + H) * W + (ux + H)] = acc;
+                }
             }
         }
     }

@@ -162,19 +162,29 @@ __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
 }
 
 template <int W, int KIND, bool BWD>
-__global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT)) softmin_kernel(SoftParams prm) {
+__global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
+    softmin_kernel(SoftParams prm) {
     constexpr int EXT_W = SoftTile<W, KIND, BWD>::EXT_W, EXT_H = SoftTile<W, KIND, BWD>::EXT_H;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     constexpr int TT = TW * TH;
     constexpr int NPLANE = BWD ? 2 * G : G;
 
+    // LDS: the pixels, the window keys and one region that holds, in turn, the
+    // planes of the aggregate sweeps, the (member, window) weights e with the
+    // per-window sums, and (backward) the planes of the gradient propagation.  The
+    // forward-only kernel keeps the angle part of each objective in e during its
+    // L2 sweep, so there e follows the planes instead of sharing their space.
+    constexpr int NE = NW * TT, NWIN = BWD ? 8 * TT : 0;
+    constexpr int REGION = BWD ? (NPLANE * NT > NE + NWIN ? NPLANE * NT : NE + NWIN)
+                               : G * NT + NE;
     __shared__ float4 s_dir[NT];
     __shared__ float4 s_raw[NT];
-    __shared__ float s_plane[NPLANE * NT];
     __shared__ uint32_t s_key[TT];
-    __shared__ float s_e[NW * TT];
-    __shared__ float s_win[BWD ? 8 * TT : 1];
+    __shared__ float s_buf[REGION];
+    float* const s_plane = s_buf;
+    float* const s_e = BWD ? s_buf : s_buf + G * NT;
+    float* const s_win = s_e + NE;  // backward only
 
     const int tid = threadIdx.x;
     const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
@@ -320,6 +330,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT)) softmin_kernel(S
         D[u] = gd;
     }
     const float inv_a2 = 1.0f / fmaf(mdir.x, mdir.x, fmaf(mdir.y, mdir.y, mdir.z * mdir.z));
+    __syncthreads();  // every thread is done with e and the window sums: the planes reuse them
     propagate_pairs<W, EXT_W, EXT_H, false>(A, s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw,
                                             inv_a2, gx0, gx1, gx2);
     if (KIND == kDDF)

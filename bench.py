@@ -588,6 +588,18 @@ def acwddf_mismatch(oracle, img_np, acw_idx, codes, k=20000):
     return res
 
 
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(img_np, outs, variants, seconds, acw_idx=None):
     """FP64 oracle on a seeded pixel sample of the same image, all host threads."""
     import oracle
@@ -622,7 +634,7 @@ def cpu_baseline(img_np, outs, variants, seconds, acw_idx=None):
     dt = time.perf_counter() - t0
     what = ("%d seeded pixels of" % k) if k < M * N else ("%d pass(es) over all pixels of" % reps)
     return {"value": round(reps * k * len(variants) / dt / 1e6, 5), "unit": "Mpixels/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": oracle.threads(), "cpu_model": host_cpu_model(), "kind": "oracle",
             "sample": "%s the 1024x1024 image x %d variants, DDF 3x3 (%.1f s)"
                       % (what, len(variants), dt),
             "index_mismatch": mism, "index_compared": k * len(variants),

@@ -7,12 +7,22 @@
 
 namespace odf {
 
-// 3x3 BVDF and DDF kernels are held to 64 VGPRs (8 waves per SIMD), the
-// budget at which four 512-thread or two 1024-thread workgroups share a CU
-// (ACWDDF keeps four objectives per window and cannot get there).
+// Occupancy targets: 3x3 BVDF and DDF kernels are held to 64 VGPRs (8 waves
+// per SIMD), the budget at which four 512-thread or two 1024-thread workgroups
+// share a CU (ACWDDF keeps four objectives per window and cannot get there);
+// 5x5 BVDF with the exact or rgb term to 80 (6 waves: three 512-thread
+// workgroups), which it needs only a few registers more than.
+template <int W, int KIND, int DIST>
+constexpr int fwd_waves_per_eu() {
+    if (W == 3 && KIND != kACW) return 8;
+    if (W == 5 && KIND == kBVDF && DIST != kMinimax) return 6;
+    return 1;
+}
+
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
 __global__ void __launch_bounds__(EXT_W* EXT_H)
-    __attribute__((amdgpu_waves_per_eu(W == 3 && KIND != kACW && !AGG ? 8 : 1))) fwd_kernel(FwdParams prm) {
+    __attribute__((amdgpu_waves_per_eu(AGG ? 1 : fwd_waves_per_eu<W, KIND, DIST>())))
+    fwd_kernel(FwdParams prm) {
     __shared__ FwdSharedFor<W, KIND, DIST, U8, EXT_W, EXT_H, AGG> sh;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     fwd_tile<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>(sh, prm, blockIdx.z, blockIdx.y * Gm::TH,

@@ -100,13 +100,13 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     {
         const int gy = min(max(ty0 - H + ey, 0), M - 1);
         const int gx = min(max(tx0 - H + ex, 0), N - 1);
-        const size_t pix = ((size_t)b * M + gy) * N + gx;
+        const int pix = (b * M + gy) * N + gx;  // B*M*N < 2^31 (checked on the host)
         float x0, x1, x2;
         if (U8) {
-            const uint8_t* s = static_cast<const uint8_t*>(prm.img) + pix * 3;
+            const uint8_t* s = static_cast<const uint8_t*>(prm.img) + (size_t)pix * 3;
             x0 = s[0]; x1 = s[1]; x2 = s[2];
         } else {
-            const float* s = static_cast<const float*>(prm.img) + pix * 3;
+            const float* s = static_cast<const float*>(prm.img) + (size_t)pix * 3;
             x0 = s[0]; x1 = s[1]; x2 = s[2];
         }
         prepare_pixel<DIST, U8>(x0, x1, x2, mdir, mraw);
@@ -248,11 +248,12 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     if (AGG) return;
     __syncthreads();
 
-    // write the selected member of every window of the tile
-    for (int i = tid; i < TH * TW; i += NT) {
-        const int cy = i / TW, cx = i - (i / TW) * TW;
+    // write the selected member of every window of the tile: the thread at the
+    // window's centre writes it (the extended tile covers the output tile)
+    {
+        const int cy = ey - H, cx = ex - H;
         const int gy = ty0 + cy, gx = tx0 + cx;
-        if (gy >= M || gx >= N) continue;
+        if (cy < 0 || cy >= TH || cx < 0 || cx >= TW || gy >= M || gx >= N) return;
         const int ki = Sh::key_index(cy, cx);
         int u = min((int)(s_key[ki] & 0xffu), NW - 1);
         if constexpr (KIND == kACW) {
@@ -283,16 +284,16 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             if (!(S > prm.acw_T)) u = (NW - 1) / 2;
         }
         const int sel = (cy + u / W) * EXT_W + cx + u % W;
-        const size_t pix = ((size_t)b * M + gy) * N + gx;
+        const int pix = (b * M + gy) * N + gx;
         if (U8) {
             // the raw value is the direction, or 0 for the zero pixel
             const float4 d = s_dir[sel];
             const bool z = d.w < 0.0f;
-            uint8_t* o = static_cast<uint8_t*>(prm.out) + pix * 3;
+            uint8_t* o = static_cast<uint8_t*>(prm.out) + (size_t)pix * 3;
             o[0] = z ? 0 : (uint8_t)d.x; o[1] = z ? 0 : (uint8_t)d.y; o[2] = z ? 0 : (uint8_t)d.z;
         } else {
             const float4 r = sh.raw[sel];
-            float* o = static_cast<float*>(prm.out) + pix * 3;
+            float* o = static_cast<float*>(prm.out) + (size_t)pix * 3;
             o[0] = r.x; o[1] = r.y; o[2] = r.z;
         }
         if (prm.idx) prm.idx[pix] = (uint8_t)u;

@@ -178,10 +178,23 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
     constexpr int NE = NW * TT, NWIN = BWD ? 8 * TT : 0;
     constexpr int REGION = BWD ? (NPLANE * NT > NE + NWIN ? NPLANE * NT : NE + NWIN)
                                : G * NT + NE;
-    __shared__ float4 s_dir[NT];
-    __shared__ float4 s_raw[NT];
-    __shared__ uint32_t s_key[TT];
-    __shared__ float s_buf[REGION];
+    // One struct, in this order, so that the unguarded aggregate sweeps
+    // (aggregates.h) read past the pixel arrays and before the planes inside it.
+    struct Lds {
+        float4 dir[NT];
+        float4 raw[NT];
+        uint32_t key[TT];
+        float buf[REGION];
+    };
+    __shared__ Lds sh;
+    constexpr size_t kOver = 2 * H * EXT_W + 2 * H;
+    static_assert(offsetof(Lds, dir) + (NT + kOver) * sizeof(float4) <= sizeof(Lds), "dir");
+    static_assert(offsetof(Lds, raw) + (NT + kOver) * sizeof(float4) <= sizeof(Lds), "raw");
+    static_assert(offsetof(Lds, buf) >= kOver * sizeof(float), "planes");
+    float4* const s_dir = sh.dir;
+    float4* const s_raw = sh.raw;
+    uint32_t* const s_key = sh.key;
+    float* const s_buf = sh.buf;
     float* const s_plane = s_buf;
     float* const s_e = BWD ? s_buf : s_buf + G * NT;
     float* const s_win = s_e + NE;  // backward only
@@ -219,8 +232,9 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
 
     float A[NW], D[NW], Om[NW];
     const TilePix px{s_dir, s_raw, nullptr};
-    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false>(px, s_plane, ey, ex, tid, mdir,
-                                                                  mraw, no_coef, A);
+    // unguarded sweeps: only windows of the output tile (window_of) are used below
+    member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false, false>(
+        px, s_plane, ey, ex, tid, mdir, mraw, no_coef, A);
     if constexpr (!BWD) {
         // forward only: the angle part of each objective waits in s_e (same
         // (member, window) layout) during the L2 sweep; then s_e holds Omega
@@ -231,8 +245,8 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
             if (window_of(u, c)) s_e[u * TT + c] = mode == 2 ? (1.0f - p) * log2f(A[u]) : A[u];
         }
         if (KIND == kDDF)
-            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(px, s_plane, ey, ex, tid,
-                                                                         mdir, mraw, no_coef, D);
+            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true, false>(
+                px, s_plane, ey, ex, tid, mdir, mraw, no_coef, D);
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             int c;
@@ -252,8 +266,8 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
         }
     } else {
         if (KIND == kDDF)
-            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true>(px, s_plane, ey, ex, tid,
-                                                                         mdir, mraw, no_coef, D);
+            member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true, false>(
+                px, s_plane, ey, ex, tid, mdir, mraw, no_coef, D);
         else
 #pragma unroll
             for (int u = 0; u < NW; ++u) D[u] = 0.0f;

@@ -42,14 +42,28 @@ __device__ __forceinline__ float key_value(uint32_t k) {
     return __uint_as_float(bits);
 }
 
-// dOmega/dA and dOmega/dD (0 where a fractional power meets a zero aggregate).
+// The hardware base-2 logarithm and power (about 1 ulp; the aggregates are 0 or
+// normal numbers, and log2(0) = -inf gives the power 0 as it should).
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// The objective A^(1-p) D^p (BVDF: A) from the hardware log2 / exp2.
+template <int KIND>
+__device__ __forceinline__ float soft_objective(float A, float D, float p) {
+    if (KIND == kBVDF || p == 0.0f) return A;
+    if (p == 1.0f) return D;
+    return hw_exp2(fmaf(1.0f - p, hw_log2(A), p * hw_log2(D)));
+}
+
+// dOmega/dA and dOmega/dD (0 where a fractional power meets a zero aggregate),
+// with the hardware reciprocal (about 1 ulp).
 template <int KIND>
 __device__ __forceinline__ void objective_grad(float A, float D, float Om, float p, float& dA,
                                                float& dD) {
     if (KIND == kBVDF || p == 0.0f) { dA = 1.0f; dD = 0.0f; return; }
     if (p == 1.0f) { dA = 0.0f; dD = 1.0f; return; }
-    dA = A > 0.0f ? (1.0f - p) * Om / A : 0.0f;
-    dD = D > 0.0f ? p * Om / D : 0.0f;
+    dA = A > 0.0f ? ((1.0f - p) * Om) * __builtin_amdgcn_rcpf(A) : 0.0f;
+    dD = D > 0.0f ? (p * Om) * __builtin_amdgcn_rcpf(D) : 0.0f;
 }
 
 // u*v - w*z to within a rounding of the exact value: the rounding error of
@@ -242,7 +256,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             int c;
-            if (window_of(u, c)) s_e[u * TT + c] = mode == 2 ? (1.0f - p) * log2f(A[u]) : A[u];
+            if (window_of(u, c)) s_e[u * TT + c] = mode == 2 ? (1.0f - p) * hw_log2(A[u]) : A[u];
         }
         if (KIND == kDDF)
             member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true, false>(
@@ -253,7 +267,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
             if (!window_of(u, c)) continue;
             const float part = s_e[u * TT + c];
             const float om = mode == 0 ? part
-                                       : (mode == 1 ? D[u] : exp2f(fmaf(p, log2f(D[u]), part)));
+                                       : (mode == 1 ? D[u] : hw_exp2(fmaf(p, hw_log2(D[u]), part)));
             s_e[u * TT + c] = om;
             atomicMin(&s_key[c], order_key(om));
         }
@@ -273,7 +287,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
             for (int u = 0; u < NW; ++u) D[u] = 0.0f;
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
-            Om[u] = objective_value<KIND>(A[u], D[u], p);
+            Om[u] = soft_objective<KIND>(A[u], D[u], p);
             int c;
             if (window_of(u, c)) atomicMin(&s_key[c], order_key(Om[u]));
         }

@@ -158,7 +158,9 @@ template <int W, int KIND, int SHAPE>
 __global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS)
     __attribute__((amdgpu_waves_per_eu(W == 3 && KIND != kACW ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
     __shared__ __align__(16) char smem[BatchSmem<W, KIND, SHAPE>::BYTES];
-    batch_tile_any<W, KIND, SHAPE>(smem, bc, blockIdx.x);
+    const int t = flat_block(bc.ntiles);
+    if (t < 0) return;
+    batch_tile_any<W, KIND, SHAPE>(smem, bc, t);
 }
 
 __global__ void batch_reset(int* counters, int n) {
@@ -191,11 +193,11 @@ static void launch_group_wk(bool direct, int shape, int grid, int threads, const
     if (!direct)
         hipLaunchKernelGGL((batch_kernel<W, KIND>), dim3(grid), dim3(threads), 0, s, bc);
     else if (shape == 0)
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), dim3(bc.ntiles), dim3(threads), 0, s,
-                           bc);
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), flat_grid(bc.ntiles), dim3(threads),
+                           0, s, bc);
     else
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), dim3(bc.ntiles), dim3(threads), 0, s,
-                           bc);
+        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), flat_grid(bc.ntiles), dim3(threads),
+                           0, s, bc);
 }
 
 static void launch_group(int grp, bool direct, int shape, int grid, int threads,
@@ -298,7 +300,7 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
     // (cost, tile) per group; cost = output pixels x pair-term weight
     std::vector<std::pair<long long, odf::BatchTile>> lists[odf::kNumGroups];
     int class_tiles[odf::kNumClasses] = {};
-    long long npix = 0;
+    long long npix = 0, total_tiles = 0;
     for (int i = 0; i < njobs; ++i) {
         const odf_job& j = jobs[i];
         odf::BatchJob& b = hj[i];
@@ -318,6 +320,8 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
             for (int tx = 0; tx < j.N; tx += tw) {
                 const long long cost = (long long)std::min(th, j.M - ty) * std::min(tw, j.N - tx) *
                                        dist_weight(j.dist);
+                if (++total_tiles >= INT32_MAX)  // tile ids and list offsets are int
+                    return bfail(ODF_EINVAL, "the batch has 2^31 - 1 tiles or more");
                 lists[grp].push_back({cost, odf::BatchTile{i, ty, tx}});
                 ++class_tiles[grp * 3 + j.dist];
             }

@@ -22,7 +22,37 @@ struct FwdParams {
     // levels k = lambda, lambda + 1, lambda + 2, and the switching threshold T
     float acw_wm1[3];
     float acw_T;
+    int tiles_x, tiles_y;  // output tiles across and down one image (set by the launch)
 };
+
+// Workgroup grids.  A launch of n workgroups (1 <= n < 2^31) takes x = min(n, 65535)
+// and y = ceil(n / x) < 32768: inside the dispatch limits on every dimension and on
+// work-items per dimension, however the images are shaped (2^31 one-pixel images,
+// one 2^31-pixel row).  The hardware dispatches x fastest, so flat_block(n) numbers
+// the workgroups in dispatch order; it is -1 for those at or past n (the tail of the
+// last row), which have no work and return at once.
+constexpr int kGridX = 65535;
+inline dim3 flat_grid(long long n) {
+    const long long gx = n < 1 ? 1 : (n < kGridX ? n : kGridX);
+    return dim3((unsigned)gx, (unsigned)((n + gx - 1) / gx));
+}
+__device__ __forceinline__ int flat_block(int n) {
+    // below 2^31 + 65535: no unsigned wrap, and compared before it is made an int
+    const unsigned t = blockIdx.y * gridDim.x + blockIdx.x;
+    return t < (unsigned)n ? (int)t : -1;
+}
+
+// Tile t of B images of tiles_x x tiles_y tiles each, numbered image by image and
+// row by row within an image (the order of a (tiles_x, tiles_y, B) grid).
+struct TileCoord {
+    int b, ty, tx;
+};
+__device__ __forceinline__ TileCoord tile_coord(int t, int tiles_x, int tiles_y) {
+    const int per = tiles_x * tiles_y;
+    const int b = t / per, r = t - b * per;
+    const int ty = r / tiles_x;
+    return {b, ty, r - ty * tiles_x};
+}
 
 // Launch the forward filter on `stream` with extended-tile shape `cfg`.
 // Returns hipSuccess or the launch error.
@@ -53,6 +83,7 @@ struct SoftParams {
     int B, M, N;
     float p;
     float inv_tau;
+    int tiles_x, tiles_y;  // tiles across and down one image (set by the launch)
 };
 
 hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy, float* dx, int B,

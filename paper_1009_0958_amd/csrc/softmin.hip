@@ -215,8 +215,11 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
 
     const int tid = threadIdx.x;
     const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
-    const int b = blockIdx.z;
-    const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+    const int tile = flat_block(prm.B * prm.tiles_x * prm.tiles_y);
+    if (tile < 0) return;
+    const TileCoord tc = tile_coord(tile, prm.tiles_x, prm.tiles_y);
+    const int b = tc.b;
+    const int ty0 = tc.ty * TH, tx0 = tc.tx * TW;
     const int M = prm.M, N = prm.N;
     const float p = prm.p;
     const float inv_tau = prm.inv_tau;
@@ -392,8 +395,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
             f2 += v[2];
         }
     }
-    const size_t tile = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    float* o = prm.ws + (tile * NT + tid) * 3;
+    float* o = prm.ws + ((size_t)tile * NT + tid) * 3;
     o[0] = f0;
     o[1] = f1;
     o[2] = f2;
@@ -402,13 +404,19 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
 // dx(q) = sum of the tile contributions at q over the tiles whose extended
 // region contains q, in increasing tile order.
 template <int W, int KIND>
-__global__ void __launch_bounds__(256) softmin_combine(SoftParams prm, int tiles_x, int tiles_y) {
+__global__ void __launch_bounds__(256) softmin_combine(SoftParams prm) {
     constexpr int EXT_W = SoftTile<W, KIND, true>::EXT_W, EXT_H = SoftTile<W, KIND, true>::EXT_H;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
-    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int b = blockIdx.z;
+    const int tiles_x = prm.tiles_x, tiles_y = prm.tiles_y;
+    // a 64 x 4 block of output pixels per workgroup
+    const int bx_n = (prm.N + 63) / 64, by_n = (prm.M + 3) / 4;
+    const int blk = flat_block(prm.B * bx_n * by_n);
+    if (blk < 0) return;
+    const TileCoord bc = tile_coord(blk, bx_n, by_n);
+    const int gx = bc.tx * 64 + (threadIdx.x & 63);
+    const int gy = bc.ty * 4 + (threadIdx.x >> 6);
+    const int b = bc.b;
     if (gx >= prm.N || gy >= prm.M) return;
     const int tylo = max(0, (gy - H - TH + 1 + TH * 4) / TH - 4);
     const int tyhi = min(tiles_y - 1, (gy + H) / TH);
@@ -444,20 +452,21 @@ static void soft_grid(const SoftParams& prm, int& tx, int& ty, int& nt) {
 
 template <int W, int KIND>
 static hipError_t launch_soft_t(bool bwd, const SoftParams& prm, hipStream_t s) {
-    int tx, ty, nt;
+    int nt;
+    SoftParams q = prm;
     if (!bwd) {
-        soft_grid<W, KIND, false>(prm, tx, ty, nt);
-        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>), dim3(tx, ty, prm.B), dim3(nt), 0, s,
-                           prm);
+        soft_grid<W, KIND, false>(prm, q.tiles_x, q.tiles_y, nt);
+        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>),
+                           flat_grid((long long)prm.B * q.tiles_x * q.tiles_y), dim3(nt), 0, s, q);
         return hipGetLastError();
     }
-    soft_grid<W, KIND, true>(prm, tx, ty, nt);
-    dim3 grid(tx, ty, prm.B);
-    hipLaunchKernelGGL((softmin_kernel<W, KIND, true>), grid, dim3(nt), 0, s, prm);
+    soft_grid<W, KIND, true>(prm, q.tiles_x, q.tiles_y, nt);
+    hipLaunchKernelGGL((softmin_kernel<W, KIND, true>),
+                       flat_grid((long long)prm.B * q.tiles_x * q.tiles_y), dim3(nt), 0, s, q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g2((prm.N + 63) / 64, (prm.M + 3) / 4, prm.B);
-    hipLaunchKernelGGL((softmin_combine<W, KIND>), g2, dim3(256), 0, s, prm, tx, ty);
+    const dim3 g2 = flat_grid((long long)prm.B * ((prm.N + 63) / 64) * ((prm.M + 3) / 4));
+    hipLaunchKernelGGL((softmin_combine<W, KIND>), g2, dim3(256), 0, s, q);
     return hipGetLastError();
 }
 

@@ -109,3 +109,15 @@ def check_acwddf(idx_gpu, idx_oracle, colours, S, diag, n, T, max_ambiguous=0.01
                                                                    S.reshape(-1)[k]))
     assert amb.mean() <= max_ambiguous, "ambiguous fraction %.4f" % amb.mean()
     return int(mism.sum()), int(amb.sum()), g.size
+
+
+EPS32 = 2.0 ** -24
+
+
+def soft_tol(x, window, kind, p, tau, scale=64.0):
+    """Softmin error budget (relative): the binary32 objective carries a few ulp of
+    relative error and enters exp(-Omega / tau); with max Omega <= n (pi/2 + max|x|
+    sqrt 3), the weights move by about scale * eps * max Omega / tau."""
+    n = window * window
+    om_max = n * (np.pi / 2 + np.abs(x).max() * np.sqrt(3))
+    return scale * EPS32 * om_max / tau

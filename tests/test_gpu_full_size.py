@@ -104,3 +104,56 @@ def test_mixed_batch_256_one_launch_sampled():
         total += n
     plan.close()
     print("  %d sampled pixels checked" % total, flush=True)
+
+
+def _check_sampled_on_device(x, out, idx, pix, window, kind, p, dist, q=4):
+    """_check_sampled for inputs too large to copy to the host: the sampled windows,
+    selections and outputs are gathered on the GPU and only they are copied back."""
+    B, M, N, _ = x.shape
+    h = window // 2
+    b, rc = np.divmod(pix, M * N)
+    r, c = np.divmod(rc, N)
+    off = np.arange(-h, h + 1)
+    rr = np.clip(r[:, None] + off[None, :], 0, M - 1)
+    cc = np.clip(c[:, None] + off[None, :], 0, N - 1)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    patches = x[t(b[:, None, None]), t(rr[:, :, None]), t(cc[:, None, :])].cpu().numpy()
+    centre = np.arange(pix.shape[0]) * window * window + h * window + h
+    _, _, _, _, oO = oracle.filter_at(patches, centre, window, kind, p, dist, q)
+    g = idx.reshape(-1)[t(pix)].cpu().numpy().astype(np.int64)
+    n_mis, n = check_selection(g, oO)
+    sr = np.clip(r + g // window - h, 0, M - 1)
+    sc = np.clip(c + g % window - h, 0, N - 1)
+    got = out.reshape(-1, 3)[t(pix)].cpu().numpy()
+    assert np.array_equal(got, x[t(b), t(sr), t(sc)].cpu().numpy())
+    return n_mis, n
+
+
+def test_largest_frame_sampled():
+    """The largest frame the library accepts: 32768 x 65535 = 2^31 - 32768 pixels, so
+    that byte offsets pass 2^32 (uint8) and 2^34 (float32) and the flat pixel index
+    nears its int32 limit.  Random colours generated on the GPU; the last rows and
+    columns are in the sample."""
+    M, N = 32768, 65535
+    assert M * N < 2 ** 31
+    g = torch.Generator(device=DEV)
+    g.manual_seed(77)
+    x = torch.randint(0, 256, (1, M, N, 3), dtype=torch.uint8, device=DEV, generator=g)
+    rng = np.random.default_rng(13)
+    tail = np.concatenate([(M - 1) * N + rng.integers(0, N, 200),
+                           rng.integers(0, M, 200) * N + N - 1])
+    pix = np.unique(np.concatenate([_sample(1, M, N, 1500, seed=13), tail]))
+    for window, kind, p, dist in ((3, DDF, 0.25, odf.EXACT), (5, BVDF, 0.0, odf.MINIMAX),
+                                  (3, BVDF, 0.0, odf.RGB)):
+        print("case: 32768x65535 u8 w=%d kind=%d p=%s dist=%d" % (window, kind, p, dist),
+              flush=True)
+        out, idx = odf.filter(x, window, kind, p, dist, 4)
+        n_mis, n = _check_sampled_on_device(x, out, idx, pix, window, kind, p, dist)
+        print("  mismatch %d of %d" % (n_mis, n), flush=True)
+        del out, idx
+    xf = x.float()
+    del x
+    print("case: 32768x65535 f32 w=3 kind=%d p=0.25 dist=%d" % (DDF, odf.EXACT), flush=True)
+    out, idx = odf.filter(xf, 3, DDF, 0.25, odf.EXACT, 4)
+    n_mis, n = _check_sampled_on_device(xf, out, idx, pix, 3, DDF, 0.25, odf.EXACT)
+    print("  mismatch %d of %d" % (n_mis, n), flush=True)

@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 from paper_1009_0958_amd import synth
+from parity import soft_tol as _soft_tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -13,7 +14,6 @@ from paper_1009_0958_amd import odf  # noqa: E402
 
 DEV = "cuda:0"
 BVDF, DDF = odf.BVDF, odf.DDF
-EPS32 = 2.0 ** -24
 
 
 def _gpu(x):
@@ -50,15 +50,6 @@ def test_hard_filter_autograd():
 
 
 # ------------------------------------------------------------------ softmin
-
-def _soft_tol(x, window, kind, p, tau, scale=64.0):
-    """binary32 error budget: the objective carries a few ulp of relative error
-    and enters exp(-Omega / tau); with max Omega <= n * (pi/2 + max|x| sqrt 3),
-    weights move by ~ scale * eps * max Omega / tau relative."""
-    n = window * window
-    om_max = n * (np.pi / 2 + np.abs(x).max() * np.sqrt(3))
-    return scale * EPS32 * om_max / tau
-
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
                                            (5, BVDF, 0.0), (5, DDF, 0.5)])

@@ -74,7 +74,7 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "66a70685bb52c03ccc242d6cd1b1575938179f8f1396a0430aa88faf1e6cab4b"
+TRAFFIC_SRC_SHA256 = "66bb2324b171676458ee9bea071025e2ea4b7f5af4878bab0112e2ddd269e9c7"
 
 
 def forward_sources_sha256():

@@ -31,12 +31,13 @@ namespace odf {
 // window needs a bounds test; the others keep one key per output pixel.
 // The unguarded sweep (aggregates.h) reads up to 2h rows + 2h past dir (and
 // raw, inv) and as far before plane: the member order below keeps both inside
-// the struct, which fwd_tile checks.
+// the struct, which fwd_tile checks.  stage holds one value per (window, output
+// pixel): stage[u][cy][cx].
 template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY, int NPL, bool U8,
           bool INV>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
-    static constexpr bool HALO = U8 && !STAGE && !AGG;
+    static constexpr bool HALO = U8 && !AGG;
     static constexpr int KEYN =
         HALO ? (Gm::TH + 4 * Gm::H) * EXT_W + 2 * Gm::H : Gm::TH * Gm::TW;
     float4 dir[Gm::NT];
@@ -129,7 +130,7 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
         member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW, false>(
             px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
     if constexpr (stage_angle_part<W, KIND, AGG>()) {
-        // angle part of each objective -> LDS, then the L2 pass, then the keys
+        // angle part of each objective -> LDS, then the L2 pass
         const int mode = objective_mode<KIND>(prm.p);
         const float p = prm.p;
         auto stage_parts = [&](auto mode_c) {
@@ -150,39 +151,15 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
         else stage_parts(std::integral_constant<int, kObjA>{});
         member_aggregates<W, KIND, DIST, U8, EXT_W, EXT_H, true, false>(px, s_plane, ey, ex, tid,
                                                                        mdir, mraw, prm.coef, D);
-        // one copy of the key loop per objective mode (a uniform branch
-        // outside the member loop)
-        auto stage_keys = [&](auto mode_c) {
-            constexpr int MODE = decltype(mode_c)::value;
-#pragma unroll
-            for (int u = 0; u < NW; ++u) {
-                const int cy = ey - u / W, cx = ex - u % W;
-                if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-                if (ty0 + cy >= M || tx0 + cx >= N) continue;
-                const float part = sh.stage[u * (TH * TW) + cy * TW + cx];
-                uint32_t bits;
-                if constexpr (MODE == kObjA) bits = __float_as_uint(part);
-                else if constexpr (MODE == kObjD) bits = __float_as_uint(D[u]);
-                else if constexpr (MODE == kObjLog)
-                    bits = order_key(fmaf(p, __builtin_amdgcn_logf(D[u]), part));
-                else bits = __float_as_uint(part * D[u]);  // non-negative: bits order
-                const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned)u;
-                atomicMin(&s_key[Sh::key_index(cy, cx)], key);
-            }
-        };
-        if (mode == kObjA) stage_keys(std::integral_constant<int, kObjA>{});
-        else if (mode == kObjD) stage_keys(std::integral_constant<int, kObjD>{});
-        else if (mode == kObjLog) stage_keys(std::integral_constant<int, kObjLog>{});
-        else stage_keys(std::integral_constant<int, kObjProd>{});
-    } else {
-    if constexpr (fused_sweep<W, KIND>())
+    } else if constexpr (fused_sweep<W, KIND>()) {
         ;  // D and cD came with the angular sweep
-    else if (KIND != kBVDF)
+    } else if (KIND != kBVDF) {
         member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, KIND == kACW, false>(
             px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
-    else
+    } else {
 #pragma unroll
         for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+    }
 
     // Window u of this member is centred on output pixel (ey - u / W, ex - u % W)
     // of the tile.  Windows outside the output tile (or the image) hold
@@ -216,6 +193,38 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             if (prm.dbg_D) prm.dbg_D[o] = D[u];
             if (prm.dbg_O) prm.dbg_O[o] = objective_value<KIND>(A[u], D[u], prm.p);
         }
+    } else if constexpr (stage_angle_part<W, KIND, AGG>()) {
+        // the staged angle part with D; one copy of the key loop per
+        // objective mode (a uniform branch outside the member loop)
+        const int mode = objective_mode<KIND>(prm.p);
+        const float p = prm.p;
+        auto stage_keys = [&](auto mode_c) {
+            constexpr int MODE = decltype(mode_c)::value;
+#pragma unroll
+            for (int u = 0; u < NW; ++u) {
+                // with HALO every lane of a wave that does not skip window u
+                // reads stage, also for a window outside the output tile: as
+                // cy runs over [-(u / W), EXT_H - 1 - u / W] and cx over
+                // [-(u % W), EXT_W - 1 - u % W], the index stays in
+                // [0, NW TH TW), and the key lands in a slot no output pixel
+                // reads
+                if (!window_ok(u)) continue;
+                const int cy = ey - u / W, cx = ex - u % W;
+                const float part = sh.stage[u * (TH * TW) + cy * TW + cx];
+                uint32_t bits;
+                if constexpr (MODE == kObjA) bits = __float_as_uint(part);
+                else if constexpr (MODE == kObjD) bits = __float_as_uint(D[u]);
+                else if constexpr (MODE == kObjLog)
+                    bits = order_key(fmaf(p, __builtin_amdgcn_logf(D[u]), part));
+                else bits = __float_as_uint(part * D[u]);  // non-negative: bits order
+                const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned)u;
+                atomicMin(&s_key[key_slot(u)], key);
+            }
+        };
+        if (mode == kObjA) stage_keys(std::integral_constant<int, kObjA>{});
+        else if (mode == kObjD) stage_keys(std::integral_constant<int, kObjD>{});
+        else if (mode == kObjLog) stage_keys(std::integral_constant<int, kObjLog>{});
+        else stage_keys(std::integral_constant<int, kObjProd>{});
     } else if constexpr (KIND == kACW) {
         // eq. (3) and the centre-weighted objectives of eq. (9): the weight
         // w_d(k) of the centre adds (w_d(k) - 1) times the centre term
@@ -243,7 +252,6 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             if (!window_ok(u)) continue;
             atomicMin(&s_key[key_slot(u)], ((unsigned long long)kb[u] << 32) | (unsigned)u);
         }
-    }
     }
     if (AGG) return;
     __syncthreads();

@@ -185,6 +185,30 @@ int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, in
                         float p, float tau, float* dx, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/*
+ * binary64 twins of the softmin relaxation and its gradient, for gradient
+ * checks by finite differences in binary64 (the float32 entry points above are
+ * the fast path).  Same definitions, conventions and errors as
+ * odf_softmin_fwd_f32 / odf_softmin_bwd_f32, with x, y, dy, dx binary64
+ * (B x M x N x 3) and p, tau binary64; every pair term, aggregate, weight and
+ * gradient is formed in binary64 directly from its definition, one window per
+ * thread (no tiles, no reuse of pair terms), so these run far slower than the
+ * float32 path.  The backward first writes the gradient of every member of
+ * every window to the workspace (n x 3 binary64 per pixel, 8-byte aligned,
+ * owned by the caller, contents on entry ignored), then sums, for every pixel,
+ * those of the members that are that pixel (windows in raster order, members
+ * in index order): deterministic.  Windows 3 and 5.
+ */
+int odf_softmin_fwd_f64(const double* x, int B, int M, int N, int window, int kind, double p,
+                        double tau, double* y, void* stream);
+
+/* Workspace bytes odf_softmin_bwd_f64 needs (B M N n 3 8; 0 if invalid). */
+size_t odf_softmin_bwd_f64_workspace(int B, int M, int N, int window);
+
+int odf_softmin_bwd_f64(const double* x, const double* dy, int B, int M, int N, int window, int kind,
+                        double p, double tau, double* dx, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Many uint8 images of different sizes, windows and variants in one launch.
  * A job is one image with its own parameters (same meaning as the arguments

@@ -61,8 +61,13 @@ def lib():
         L.odf_softmin_bwd_workspace.argtypes = [I, I, I, I, I]
         L.odf_softmin_bwd_workspace.restype = ctypes.c_size_t
         L.odf_softmin_bwd_f32.argtypes = [P, P, I, I, I, I, I, F, F, P, P, ctypes.c_size_t, P]
+        L.odf_softmin_fwd_f64.argtypes = [P, I, I, I, I, I, Dbl, Dbl, P, P]
+        L.odf_softmin_bwd_f64_workspace.argtypes = [I, I, I, I]
+        L.odf_softmin_bwd_f64_workspace.restype = ctypes.c_size_t
+        L.odf_softmin_bwd_f64.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, P, P, ctypes.c_size_t, P]
         for name in ("odf_filter_u8", "odf_filter_f32", "odf_aggregates", "odf_backward_hard_f32",
-                     "odf_softmin_fwd_f32", "odf_softmin_bwd_f32"):
+                     "odf_softmin_fwd_f32", "odf_softmin_bwd_f32", "odf_softmin_fwd_f64",
+                     "odf_softmin_bwd_f64"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -236,34 +241,44 @@ def backward_hard(idx, dy, window):
 
 
 def softmin_forward(x, window=5, kind=DDF, p=0.25, tau=0.1):
-    """Softmin relaxation y = sum_u pi_u x_u (float32, exact angle)."""
+    """Softmin relaxation y = sum_u pi_u x_u (exact angle): float32 on the fast
+    path, float64 on the binary64 twin (for gradient checks)."""
     xb, squeeze = _as_batch(x)
     _check_tensor(xb, "x")
-    if xb.dtype != torch.float32:
-        raise ValueError("x must be float32")
+    if xb.dtype not in (torch.float32, torch.float64):
+        raise ValueError("x must be float32 or float64")
     B, M, N, _ = xb.shape
     y = torch.empty_like(xb)
-    _check(lib().odf_softmin_fwd_f32(_ptr(xb), B, M, N, window, _kind(kind), float(p), float(tau),
-                                     _ptr(y), _stream(xb.device)))
+    if xb.dtype == torch.float32:
+        _check(lib().odf_softmin_fwd_f32(_ptr(xb), B, M, N, window, _kind(kind), float(p),
+                                         float(tau), _ptr(y), _stream(xb.device)))
+    else:
+        _check(lib().odf_softmin_fwd_f64(_ptr(xb), B, M, N, window, _kind(kind), float(p),
+                                         float(tau), _ptr(y), _stream(xb.device)))
     return y[0] if squeeze else y
 
 
 def softmin_backward(x, dy, window=5, kind=DDF, p=0.25, tau=0.1, workspace=None):
-    """Gradient of sum(dy * softmin_forward(x)) with respect to x."""
+    """Gradient of sum(dy * softmin_forward(x)) with respect to x (float32, or
+    float64 on the binary64 twin)."""
     xb, squeeze = _as_batch(x)
     g, _ = _as_batch(dy)
     _check_tensor(xb, "x")
     _check_tensor(g, "dy")
-    if xb.dtype != torch.float32 or g.dtype != torch.float32 or g.shape != xb.shape:
-        raise ValueError("x and dy must be float32 of the same shape")
+    if xb.dtype not in (torch.float32, torch.float64) or g.dtype != xb.dtype or \
+            g.shape != xb.shape:
+        raise ValueError("x and dy must be float32 (or both float64) of the same shape")
     B, M, N, _ = xb.shape
-    need = lib().odf_softmin_bwd_workspace(B, M, N, window, _kind(kind))
+    f64 = xb.dtype == torch.float64
+    L = lib()
+    need = (L.odf_softmin_bwd_f64_workspace(B, M, N, window) if f64
+            else L.odf_softmin_bwd_workspace(B, M, N, window, _kind(kind)))
     if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(need, dtype=torch.uint8, device=xb.device)
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=xb.device)
     dx = torch.empty_like(xb)
-    _check(lib().odf_softmin_bwd_f32(_ptr(xb), _ptr(g), B, M, N, window, _kind(kind), float(p),
-                                     float(tau), _ptr(dx), _ptr(workspace), workspace.numel(),
-                                     _stream(xb.device)))
+    fn = L.odf_softmin_bwd_f64 if f64 else L.odf_softmin_bwd_f32
+    _check(fn(_ptr(xb), _ptr(g), B, M, N, window, _kind(kind), float(p), float(tau), _ptr(dx),
+              _ptr(workspace), workspace.numel(), _stream(xb.device)))
     return dx[0] if squeeze else dx
 
 
@@ -307,7 +322,8 @@ def hard_filter(x, window=5, kind=DDF, p=0.25, dist=EXACT, q=4):
 
 
 def softmin_filter(x, window=5, kind=DDF, p=0.25, tau=0.1):
-    """Differentiable softmin relaxation on float32 images."""
+    """Differentiable softmin relaxation on float32 images (float64: the binary64
+    twin, e.g. for torch.autograd.gradcheck)."""
     return SoftminFilter.apply(x, window, _kind(kind), float(p), float(tau))
 
 

@@ -172,3 +172,31 @@ def test_window7_limits():
     assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 7, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert "softmin" in odf.last_error()
     assert L.odf_softmin_bwd_workspace(1, 8, 8, 7, 1) == 0
+
+
+def test_softmin_f64_rejects():
+    L = odf.lib()
+    D = ctypes.c_double
+    fwd = lambda *a: L.odf_softmin_fwd_f64(*a[:6], D(a[6]), D(a[7]), a[8], None)  # noqa: E731
+    assert fwd(None, 1, 4, 4, 3, 1, 0.25, 0.1, FAKE2) == odf.EINVAL and "x" in odf.last_error()
+    assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.1, None) == odf.EINVAL and "y" in odf.last_error()
+    assert fwd(FAKE, 1, 4, 4, 7, 1, 0.25, 0.1, FAKE2) == odf.EUNSUPPORTED
+    assert fwd(FAKE, 1, 4, 4, 3, 1, 1.5, 0.1, FAKE2) == odf.EINVAL and "p" in odf.last_error()
+    assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.0, FAKE2) == odf.EINVAL and "tau" in odf.last_error()
+    assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, float("inf"), FAKE2) == odf.EINVAL
+    assert fwd(FAKE, 1, 4, 4, 3, 3, 0.25, 0.1, FAKE2) == odf.EINVAL and "kind" in odf.last_error()
+    assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.1, ctypes.c_void_p(0x7F0000000000 + 64)) == odf.EINVAL
+    assert "overlaps" in odf.last_error()
+    need = L.odf_softmin_bwd_f64_workspace(1, 4, 4, 5)
+    assert need == 4 * 4 * 25 * 3 * 8
+    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 7) == 0
+    F3 = ctypes.c_void_p(0x7F0000200000)
+    WS = ctypes.c_void_p(0x7F0000300000)
+    bwd = lambda ws, nbytes, w=5: L.odf_softmin_bwd_f64(  # noqa: E731
+        FAKE, FAKE2, 1, 4, 4, w, 1, D(0.25), D(0.1), F3, ws, nbytes, None)
+    assert bwd(WS, need - 1) == odf.EINVAL and "workspace" in odf.last_error()
+    assert bwd(ctypes.c_void_p(0x7F0000300004), need) == odf.EINVAL
+    assert "aligned" in odf.last_error()
+    assert bwd(None, need) == odf.EINVAL
+    assert bwd(ctypes.c_void_p(0x7F0000200000 + 64), need) == odf.EINVAL
+    assert "overlap" in odf.last_error()

@@ -135,3 +135,70 @@ def test_full_size_batch_crops():
                   % (tau, k, ey, ed, sd, tol * sd), flush=True)
             assert ey <= tol
             assert ed <= tol * sd
+
+
+# ------------------------------------------------------------------ binary64 twins
+
+@pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
+                                           (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0)])
+@pytest.mark.parametrize("tau", [0.1, 0.01])
+def test_softmin_f64_matches_oracle(window, kind, p, tau):
+    """The binary64 twins against the binary64 oracle: both evaluate the same
+    definitions in binary64 in different orders, so they agree to rounding."""
+    print("case: softmin f64 w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
+    x = synth.float_batch(2, 19, 26, 0.1, key=20 + window + kind).astype(np.float64)
+    dy = np.random.default_rng(window).standard_normal(x.shape)
+    y = odf.softmin_forward(_gpu(x), window, kind, p, tau).cpu().numpy()
+    ref = oracle.softmin_fwd(x, window, kind, p, tau)
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(x).max()
+    dx = odf.softmin_backward(_gpu(x), _gpu(dy), window, kind, p, tau).cpu().numpy()
+    ref = oracle.softmin_bwd(x, dy, window, kind, p, tau)
+    err, scale = np.abs(dx - ref).max(), np.abs(ref).max()
+    print("max |dx - ref| = %.3e of %.3e" % (err, scale), flush=True)
+    assert err <= 1e-9 * scale
+    dx2 = odf.softmin_backward(_gpu(x), _gpu(dy), window, kind, p, tau).cpu().numpy()
+    assert np.array_equal(dx, dx2)
+
+
+def test_softmin_f64_edge_shapes_and_zero_pixels():
+    """1 x 1 to thin images, zero pixels and duplicated colours (border
+    replication), against the oracle."""
+    for shape in ((1, 1, 1), (1, 2, 9), (1, 17, 1), (2, 5, 5)):
+        x = synth.float_batch(*shape, 0.2, key=5).astype(np.float64)
+        x[..., ::3, ::2, :] = 0.0
+        dy = np.random.default_rng(1).standard_normal(x.shape)
+        for window in (3, 5):
+            y = odf.softmin_forward(_gpu(x), window, DDF, 0.25, 0.1).cpu().numpy()
+            assert np.abs(y - oracle.softmin_fwd(x, window, DDF, 0.25, 0.1)).max() <= 1e-12
+            dx = odf.softmin_backward(_gpu(x), _gpu(dy), window, DDF, 0.25, 0.1).cpu().numpy()
+            ref = oracle.softmin_bwd(x, dy, window, DDF, 0.25, 0.1)
+            assert np.abs(dx - ref).max() <= 1e-9 * max(np.abs(ref).max(), 1.0)
+
+
+def test_softmin_f64_gradcheck_on_gpu():
+    """torch.autograd.gradcheck of the binary64 twin on the GPU: the full
+    Jacobian against central differences on a 6 x 7 image, and random
+    projections (fast mode) on 8 seeded 32 x 32 crops of the 16 x 512 x 512
+    benchmark batch, for BVDF and DDF p = 1/4 at tau = 0.1.  Crops holding a
+    zero pixel are skipped: there the direction jumps to the constant (1, 1, 1),
+    so the filter is not differentiable."""
+    small = _gpu(synth.float_batch(1, 6, 7, 0.1, key=9).astype(np.float64)).requires_grad_(True)
+    for window, kind, p in ((3, DDF, 0.25), (5, DDF, 0.25), (5, BVDF, 0.0)):
+        fn = lambda t: odf.softmin_filter(t, window, kind, p, 0.1)  # noqa: E731
+        assert torch.autograd.gradcheck(fn, (small,), eps=1e-6, atol=1e-7, rtol=1e-5)
+    x = synth.float_batch(16, 512, 512, 0.1)
+    rng = np.random.default_rng(32)
+    k = 0
+    while k < 8:
+        b = int(rng.integers(0, 16))
+        r0, c0 = (int(v) for v in rng.integers(0, 512 - 32, 2))
+        c = x[b, r0:r0 + 32, c0:c0 + 32].astype(np.float64)
+        if not c.any(-1).all():
+            continue  # a zero pixel: its direction jumps to (1, 1, 1), not differentiable
+        k += 1
+        crop = _gpu(c).requires_grad_(True)
+        for kind, p in ((DDF, 0.25), (BVDF, 0.0)):
+            print("case: gradcheck crop %d kind %d" % (k, kind), flush=True)
+            fn = lambda t: odf.softmin_filter(t, 5, kind, p, 0.1)  # noqa: E731
+            assert torch.autograd.gradcheck(fn, (crop,), eps=1e-6, atol=1e-7, rtol=1e-5,
+                                            fast_mode=True)

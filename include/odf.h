@@ -135,8 +135,8 @@ int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, 
  *          (A for BVDF; A^(1-p) D^p for DDF).
  * Errors as for odf_filter_u8.
  */
-int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, int kind,
-                   float p, int dist, int q, float* A, float* D, float* Omega, void* stream);
+int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int window, int kind,
+                       float p, int dist, int q, float* A, float* D, float* Omega, void* stream);
 
 /*
  * Gradient of the hard filter (one-hot routing of the selection).

@@ -172,8 +172,8 @@ int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, 
     return filter_any(img, false, B, M, N, window, kind, p, dist, q, out, idx, stream);
 }
 
-int odf_aggregates(const void* img, int is_u8, int B, int M, int N, int window, int kind, float p,
-                   int dist, int q, float* A, float* D, float* Omega, void* stream) {
+int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int window, int kind,
+                       float p, int dist, int q, float* A, float* D, float* Omega, void* stream) {
     int rc = check_common(img, B, M, N, window, kind, p, dist, q);
     if (rc) return rc;
     if (!A) return fail(ODF_EINVAL, "A is NULL");

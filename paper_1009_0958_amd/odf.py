@@ -50,7 +50,7 @@ def lib():
         L.odf_filter_f32.argtypes = [P, I, I, I, I, I, F, I, I, P, P, P]
         L.odf_acwddf_u8.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
         L.odf_acwddf_f32.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
-        L.odf_aggregates.argtypes = [P, I, I, I, I, I, I, F, I, I, P, P, P, P]
+        L.odf_aggregates_f32.argtypes = [P, I, I, I, I, I, I, F, I, I, P, P, P, P]
         Dbl = ctypes.c_double
         L.odf_noise_eq8_u8.argtypes = [P, P, I, I, I, Dbl, Dbl, Dbl, Dbl, ctypes.c_uint64, P]
         L.odf_quality_workspace.argtypes = [I]
@@ -65,9 +65,9 @@ def lib():
         L.odf_softmin_bwd_f64_workspace.argtypes = [I, I, I, I]
         L.odf_softmin_bwd_f64_workspace.restype = ctypes.c_size_t
         L.odf_softmin_bwd_f64.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, P, P, ctypes.c_size_t, P]
-        for name in ("odf_filter_u8", "odf_filter_f32", "odf_aggregates", "odf_backward_hard_f32",
-                     "odf_softmin_fwd_f32", "odf_softmin_bwd_f32", "odf_softmin_fwd_f64",
-                     "odf_softmin_bwd_f64"):
+        for name in ("odf_filter_u8", "odf_filter_f32", "odf_aggregates_f32",
+                     "odf_backward_hard_f32", "odf_softmin_fwd_f32", "odf_softmin_bwd_f32",
+                     "odf_softmin_fwd_f64", "odf_softmin_bwd_f64"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -214,7 +214,7 @@ def aggregates(img, window=3, kind=BVDF, p=0.5, dist=EXACT, q=4):
     A = torch.empty((B, M, N, n), dtype=torch.float32, device=x.device)
     D = torch.empty_like(A)
     O = torch.empty_like(A)
-    _check(lib().odf_aggregates(_ptr(x), int(x.dtype == torch.uint8), B, M, N, window,
+    _check(lib().odf_aggregates_f32(_ptr(x), int(x.dtype == torch.uint8), B, M, N, window,
                                 _kind(kind), float(p), _dist(dist), q, _ptr(A), _ptr(D), _ptr(O),
                                 _stream(x.device)))
     if squeeze:

@@ -58,9 +58,9 @@ def test_idx_aliasing_rejected():
 def test_f32_and_aggregates_reject():
     L = odf.lib()
     assert L.odf_filter_f32(None, 1, 4, 4, 3, 0, 0.0, 0, 4, FAKE2, None, None) == odf.EINVAL
-    assert L.odf_aggregates(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, None, None, None, None) == odf.EINVAL
+    assert L.odf_aggregates_f32(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, None, None, None, None) == odf.EINVAL
     assert "A" in odf.last_error()
-    assert L.odf_aggregates(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, FAKE2, FAKE2, None, None) == odf.EINVAL
+    assert L.odf_aggregates_f32(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, FAKE2, FAKE2, None, None) == odf.EINVAL
     assert "overlap" in odf.last_error()
 
 

@@ -14,7 +14,10 @@ Also reported on the same JSON line:
   * ``forms``: other shapes of the hot path timed the same way;
   * ``cpu_baseline``: the FP64 oracle timed on a bounded pixel sample of the
     same image on the host cores, and the index mismatch rate of the GPU on
-    that sample (every mismatch checked to be a near-tie).
+    that sample (every mismatch checked to be a near-tie); under
+    ``forms_mismatch`` the same for seeded samples of the large-frame forms
+    (1 M pixels per 5x5 form, 100 000 per 3x3 and 7x7 form) and of the
+    256-image batch (1 M pixels).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
                        [--step-forms loop,streams,persistent,direct] [--copy-probe-mib MiB]
@@ -305,11 +308,15 @@ def main():
 
     forms = {}
     acw_idx = {}
+    # seeded samples of the large-frame and batch outputs, checked against the
+    # oracle in the cpu_baseline leg (none when that leg is off)
+    samples = None if args.no_cpu else {}
     if not args.no_forms:
-        for name, fn in (("large_frames", lambda: large_frame_forms(torch, odf, synth, dev, DIST)),
+        for name, fn in (("large_frames",
+                          lambda: large_frame_forms(torch, odf, synth, dev, DIST, samples)),
                          ("acwddf", lambda: acwddf_forms(torch, odf, synth, dev, DIST, x, acw_idx)),
                          ("effectiveness", lambda: effectiveness_forms(torch, odf, synth, dev, DIST)),
-                         ("batched", lambda: batched_form(torch, odf, synth, dev)),
+                         ("batched", lambda: batched_form(torch, odf, synth, dev, samples)),
                          ("differentiable", lambda: differentiable_forms(torch, odf, synth, dev))):
             try:
                 forms.update(fn())
@@ -319,7 +326,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(img_np, outs, variants, args.cpu_seconds, acw_idx)
+        cpu = cpu_baseline(img_np, outs, variants, args.cpu_seconds, acw_idx, samples)
 
     line = {
         "metric": "Mpixels/s BVDF/DDF 3x3,5x5 fwd & fwd+bwd at 1 GPU; % roofline; mismatch rate",
@@ -343,10 +350,34 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def large_frame_forms(torch, odf, synth, dev, DIST):
+def sample_windows(torch, x, pix, window):
+    """The w x w windows (replicated border) of the flat pixel positions pix of
+    the uint8 batch x, gathered on the GPU: (k, w, w, 3) uint8 on the host."""
+    B, M, N, _ = x.shape
+    h = window // 2
+    b, rc = np.divmod(pix, M * N)
+    r, c = np.divmod(rc, N)
+    off = np.arange(-h, h + 1)
+    rr = np.clip(r[:, None] + off[None, :], 0, M - 1)
+    cc = np.clip(c[:, None] + off[None, :], 0, N - 1)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(x.device)  # noqa: E731
+    return x[t(b[:, None, None]), t(rr[:, :, None]), t(cc[:, None, :])].cpu().numpy()
+
+
+def mismatch_sample(B, M, N, k, seed):
+    """k seeded flat pixel positions of a B x M x N batch (all when k >= BMN)."""
+    n = B * M * N
+    if k >= n:
+        return np.arange(n)
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
     """7680 x 4320 frame (3x3 BVDF, 5x5 and 7x7) and 64 x 1920 x 1080 frames
     (5x5), correlated noise 0.15 (tile shapes autotuned per class first,
-    untimed)."""
+    untimed).  With ``samples`` (a dict), the windows of 1 M seeded pixels
+    (5x5; 100 000 for 3x3 and 7x7) and the GPU's index there are kept for the
+    oracle check of the cpu_baseline leg."""
     forms = {}
     for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF)):
         for d in ("exact", "minimax", "rgb"):
@@ -367,10 +398,20 @@ def large_frame_forms(torch, odf, synth, dev, DIST):
                 kk = odf.BVDF if kind == "bvdf" else odf.DDF
                 ms = time_launches(torch, lambda: odf.filter(big, w, kk, p, DIST[d], 4, out=bo,
                                                              idx=bi), 5, warm=1)
-                forms["%s%d_%s_%s" % (kind, w, d, tag)] = {
+                name = "%s%d_%s_%s" % (kind, w, d, tag)
+                forms[name] = {
                     "mpix_s": round(npx / (ms * 1e3), 1), "ms": round(ms, 3),
                     "valu_frac": round(slots_per_pixel(w, kind, p, d) * npx / (ms * 1e-3)
                                        / PEAK_SLOTS, 4)}
+                if samples is not None:
+                    key = (tag, w)
+                    if key not in samples.setdefault("windows", {}):
+                        pix = mismatch_sample(B, M, N, 1_000_000 if w == 5 else 100_000,
+                                              7000 + 10 * w + key[0].count("x"))
+                        samples["windows"][key] = (pix, sample_windows(torch, big, pix, w))
+                    pix = samples["windows"][key][0]
+                    gidx = bi.reshape(-1)[torch.from_numpy(pix).to(dev)].cpu().numpy()
+                    samples.setdefault("cases", []).append((name, key, w, kind, p, d, gidx))
         del big, bo, bi
     return forms
 
@@ -435,7 +476,7 @@ def effectiveness_forms(torch, odf, synth, dev, DIST):
     return {"effectiveness_1024x1024_eq8": table, **rates}
 
 
-def batched_form(torch, odf, synth, dev):
+def batched_form(torch, odf, synth, dev, samples=None):
     """256 uint8 images of mixed size (64..2048 x 64..1536), window, kind and
     noise: one planned launch captured in a graph (direct and persistent form;
     one kernel per window and kind), against a loop of per-image launches of
@@ -478,6 +519,19 @@ def batched_form(torch, odf, synth, dev):
         ms = time_launches(torch, graph.replay, 5, warm=2)
         res[name] = (ms, same_as_loop(), plan.info())
         plan.close()
+    if samples is not None:
+        # 1 M seeded pixels over the whole batch (the outputs of the last
+        # replay of the persistent graph, bitwise equal to the direct one's)
+        sizes = np.array([int(j["img"].shape[0] * j["img"].shape[1]) for j in jobs])
+        start = np.concatenate([[0], np.cumsum(sizes)])
+        flat = mismatch_sample(1, 1, int(start[-1]), 1_000_000, 7100)
+        which = np.searchsorted(start, flat, side="right") - 1
+        for i in np.unique(which):
+            pix = flat[which == i] - start[i]
+            j = jobs[i]
+            win = sample_windows(torch, j["img"][None], pix, j["window"])
+            gidx = j["idx"].reshape(-1)[torch.from_numpy(pix).to(dev)].cpu().numpy()
+            samples.setdefault("batch", []).append((j["window"], j["kind"], j["p"], win, gidx))
     ms_direct, same_d, info = res["direct"]
     ms_pers, same_p, _ = res["persistent"]
     return {"batched_256_mixed": {
@@ -600,8 +654,43 @@ def host_cpu_model():
     return None
 
 
-def cpu_baseline(img_np, outs, variants, seconds, acw_idx=None):
-    """FP64 oracle on a seeded pixel sample of the same image, all host threads."""
+def sampled_mismatch(oracle, samples, codes):
+    """Index mismatches of the kept samples against the oracle, per form (each
+    sampled pixel's window given to the oracle as a w x w patch of its own),
+    and whether every mismatch is a near-tie (the oracle's objective of the
+    GPU's choice within 1e-6 relative of the minimum)."""
+    def check(win, gidx, w, kind, p, d):
+        k = win.shape[0]
+        centre = np.arange(k) * w * w + (w * w) // 2
+        _, _, _, _, O = oracle.filter_at(win, centre, w, kind, p, codes[d])
+        g = gidx.astype(np.int64)
+        first = O.argmin(1)
+        diff = g != first
+        og = O[np.arange(k), g]
+        near = (og <= O.min(1) * (1 + 1e-6)) | ((O.min(1) == 0) & (og == 0))
+        return int(diff.sum()), k, bool(np.all(near[diff]))
+
+    res = {}
+    t0 = time.perf_counter()
+    for name, key, w, kind, p, d, gidx in samples.get("cases", []):
+        win = samples["windows"][key][1]
+        m, k, ok = check(win, gidx, w, oracle.DDF if kind == "ddf" else oracle.BVDF, p, d)
+        res[name] = {"index_mismatch": m, "index_compared": k, "mismatches_all_near_ties": ok}
+    if samples.get("batch"):
+        m = k = 0
+        ok = True
+        for w, kind, p, win, gidx in samples["batch"]:
+            mi, ki, oki = check(win, gidx, w, kind, p, "exact")
+            m, k, ok = m + mi, k + ki, ok and oki
+        res["batched_256_mixed"] = {"index_mismatch": m, "index_compared": k,
+                                    "mismatches_all_near_ties": ok}
+    res["seconds"] = round(time.perf_counter() - t0, 1)
+    return res
+
+
+def cpu_baseline(img_np, outs, variants, seconds, acw_idx=None, samples=None):
+    """FP64 oracle on a seeded pixel sample of the same image, all host threads;
+    also the index mismatch rate of the kept samples of the other forms."""
     import oracle
 
     M, N = img_np.shape[:2]
@@ -640,7 +729,8 @@ def cpu_baseline(img_np, outs, variants, seconds, acw_idx=None):
             "index_mismatch": mism, "index_compared": k * len(variants),
             "mismatches_all_near_ties": near,
             "acwddf3_1024x1024": acwddf_mismatch(oracle, img_np, acw_idx, codes) if acw_idx
-            else None}
+            else None,
+            "forms_mismatch": sampled_mismatch(oracle, samples, codes) if samples else None}
 
 
 if __name__ == "__main__":

@@ -77,7 +77,7 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "66bb2324b171676458ee9bea071025e2ea4b7f5af4878bab0112e2ddd269e9c7"
+TRAFFIC_SRC_SHA256 = "02a62d5d7f6e7d82113e46a7c1159a7003645b6eeae8a7e36fa535e1327d7f26"
 
 
 def forward_sources_sha256():

@@ -313,8 +313,8 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * (output tile plus halo).  Tile shapes are numbered 0..3; odf_tile_config
  * gives the extended width and height of one.  The process-wide table picks a
  * shape per (window, kind, dist, input type), kind ODF_BVDF, ODF_DDF or
- * ODF_ACWDDF; defaults are 32 x 32, and 32 x 16 for 5x5 ACWDDF, which offers
- * only the 512-thread shapes 2 and 3. */
+ * ODF_ACWDDF; the default is shape 2 (32 x 16) for every class (5x5 ACWDDF
+ * and 7x7 offer only the 512-thread shapes 2 and 3). */
 int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */

@@ -37,7 +37,7 @@ template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY, int NPL, 
           bool INV>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
-    static constexpr bool HALO = U8 && !AGG;
+    static constexpr bool HALO = !AGG && (U8 || W >= 5);
     static constexpr int KEYN =
         HALO ? (Gm::TH + 4 * Gm::H) * EXT_W + 2 * Gm::H : Gm::TH * Gm::TW;
     float4 dir[Gm::NT];

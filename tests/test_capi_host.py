@@ -134,7 +134,7 @@ def test_acwddf_rejects(args, code, text):
 
 def test_acwddf_tuning_table():
     L = odf._batch_lib()
-    assert L.odf_tune_get(3, odf.ACWDDF, 0, 1) == 0
+    assert L.odf_tune_get(3, odf.ACWDDF, 0, 1) == 2  # default: 32 x 16 everywhere
     assert L.odf_tune_get(5, odf.ACWDDF, 0, 1) == 2
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 0) == odf.EINVAL  # 1024-thread shape not offered
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 3) == odf.OK

@@ -20,15 +20,14 @@ constexpr int kBwdTW = 64, kBwdTH = 4, kBwdRowsPerThread = kBwdTH / 4;
 template <int W>
 __global__ void __launch_bounds__(256) bwd_hard_kernel(const uint8_t* __restrict__ idx,
                                                        const float* __restrict__ dy,
-                                                       float* __restrict__ dx, int B, int M,
-                                                       int N) {
+                                                       float* __restrict__ dx, int M, int N,
+                                                       TileGrid grid) {
     constexpr int H = W / 2, RW = kBwdTW + 2 * H, RH = kBwdTH + 2 * H, RN = RW * RH;
     __shared__ int s_tgt[RN];       // local index of the pixel window c selects, or -1
     __shared__ float s_dy[3 * RN];  // dy(c)
-    const int tiles_x = (N + kBwdTW - 1) / kBwdTW, tiles_y = (M + kBwdTH - 1) / kBwdTH;
-    const int tile = flat_block(B * tiles_x * tiles_y);
+    const int tile = flat_block(grid.n);
     if (tile < 0) return;
-    const TileCoord tc = tile_coord(tile, tiles_x, tiles_y);
+    const TileCoord tc = tile_coord(tile, grid);
     const int tx0 = tc.tx * kBwdTW, ty0 = tc.ty * kBwdTH;
     const size_t base = (size_t)tc.b * M * N;
     for (int i = threadIdx.x; i < RN; i += blockDim.x) {
@@ -82,13 +81,14 @@ __global__ void __launch_bounds__(256) bwd_hard_kernel(const uint8_t* __restrict
 
 hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy, float* dx, int B,
                                 int M, int N, hipStream_t stream) {
-    const dim3 grid = flat_grid((long long)B * ((N + kBwdTW - 1) / kBwdTW) * ((M + kBwdTH - 1) / kBwdTH));
+    const TileGrid tg = tile_grid(B, (N + kBwdTW - 1) / kBwdTW, (M + kBwdTH - 1) / kBwdTH);
+    const dim3 grid = flat_grid(tg.n);
     if (window == 3)
-        hipLaunchKernelGGL(bwd_hard_kernel<3>, grid, dim3(256), 0, stream, idx, dy, dx, B, M, N);
+        hipLaunchKernelGGL(bwd_hard_kernel<3>, grid, dim3(256), 0, stream, idx, dy, dx, M, N, tg);
     else if (window == 5)
-        hipLaunchKernelGGL(bwd_hard_kernel<5>, grid, dim3(256), 0, stream, idx, dy, dx, B, M, N);
+        hipLaunchKernelGGL(bwd_hard_kernel<5>, grid, dim3(256), 0, stream, idx, dy, dx, M, N, tg);
     else
-        hipLaunchKernelGGL(bwd_hard_kernel<7>, grid, dim3(256), 0, stream, idx, dy, dx, B, M, N);
+        hipLaunchKernelGGL(bwd_hard_kernel<7>, grid, dim3(256), 0, stream, idx, dy, dx, M, N, tg);
     return hipGetLastError();
 }
 

@@ -25,9 +25,9 @@ __global__ void __launch_bounds__(EXT_W* EXT_H)
     fwd_kernel(FwdParams prm) {
     __shared__ FwdSharedFor<W, KIND, DIST, U8, EXT_W, EXT_H, AGG> sh;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
-    const int t = flat_block(prm.B * prm.tiles_x * prm.tiles_y);
+    const int t = flat_block(prm.grid.n);
     if (t < 0) return;
-    const TileCoord c = tile_coord(t, prm.tiles_x, prm.tiles_y);
+    const TileCoord c = tile_coord(t, prm.grid);
     fwd_tile<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>(sh, prm, c.b, c.ty * Gm::TH, c.tx * Gm::TW,
                                                    threadIdx.x);
 }
@@ -36,11 +36,9 @@ template <int W, int KIND, int DIST, bool U8, bool AGG, int EXT_W, int EXT_H>
 static hipError_t launch_shape(const FwdParams& prm, hipStream_t stream) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     FwdParams q = prm;
-    q.tiles_x = (prm.N + Gm::TW - 1) / Gm::TW;
-    q.tiles_y = (prm.M + Gm::TH - 1) / Gm::TH;
-    hipLaunchKernelGGL((fwd_kernel<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>),
-                       flat_grid((long long)prm.B * q.tiles_x * q.tiles_y), dim3(Gm::NT), 0,
-                       stream, q);
+    q.grid = tile_grid(prm.B, (prm.N + Gm::TW - 1) / Gm::TW, (prm.M + Gm::TH - 1) / Gm::TH);
+    hipLaunchKernelGGL((fwd_kernel<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>), flat_grid(q.grid.n),
+                       dim3(Gm::NT), 0, stream, q);
     return hipGetLastError();
 }
 

@@ -8,6 +8,69 @@
 
 namespace odf {
 
+// Workgroup grids.  A launch of n workgroups (1 <= n < 2^31) takes y = ceil(n / 65535)
+// rows (<= 32769) of x = ceil(n / y) <= 65535 workgroups: inside the dispatch limits on
+// every dimension and on work-items per dimension, however the images are shaped
+// (2^31 one-pixel images, one 2^31-pixel row), and fewer than y workgroups past n
+// (x = 65535 for n just above 65535 would launch up to 65534 idle ones, measured at
+// 5 % of a 3x3 launch).  The hardware dispatches x fastest, so flat_block(n) numbers
+// the workgroups in dispatch order; it is -1 for those at or past n, which have no
+// work and return at once.
+constexpr int kGridX = 65535;
+inline dim3 flat_grid(long long n) {
+    if (n < 1) n = 1;
+    const long long gy = (n + kGridX - 1) / kGridX;
+    return dim3((unsigned)((n + gy - 1) / gy), (unsigned)gy);
+}
+__device__ __forceinline__ int flat_block(int n) {
+    // below 2^31 + 32769: no unsigned wrap, and compared before it is made an int
+    const unsigned t = blockIdx.y * gridDim.x + blockIdx.x;
+    return t < (unsigned)n ? (int)t : -1;
+}
+
+// Division of a 32-bit unsigned integer by a divisor fixed for a launch, as a
+// multiply-high, a subtraction, an addition and two shifts on uniform values
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994, Figure 4.1): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, t = mulhi(m, n) gives
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) for every 32-bit n.
+// The compiler's own division by a runtime value costs ~20 vector
+// instructions per wave, a measurable share of a small kernel.
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+inline FastDiv fast_div(uint32_t d) {  // d >= 1
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return {d, (uint32_t)m, l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
+}
+__device__ __forceinline__ uint32_t div_fast(uint32_t n, const FastDiv& f) {
+    const uint32_t t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// The tiles of B images of tiles_x x tiles_y tiles each, numbered image by
+// image and row by row within an image (the order of a (tiles_x, tiles_y, B)
+// grid); n = B tiles_x tiles_y < 2^31.
+struct TileGrid {
+    int n;
+    FastDiv per_image, across;
+};
+inline TileGrid tile_grid(int B, int tiles_x, int tiles_y) {
+    return {B * tiles_x * tiles_y, fast_div((uint32_t)(tiles_x * tiles_y)),
+            fast_div((uint32_t)tiles_x)};
+}
+struct TileCoord {
+    int b, ty, tx;
+};
+__device__ __forceinline__ TileCoord tile_coord(int t, const TileGrid& g) {
+    const uint32_t b = div_fast((uint32_t)t, g.per_image);
+    const uint32_t r = (uint32_t)t - b * g.per_image.d;
+    const uint32_t ty = div_fast(r, g.across);
+    return {(int)b, (int)ty, (int)(r - ty * g.across.d)};
+}
+
 struct FwdParams {
     const void* img;      // B x M x N x 3, uint8 or float32
     void* out;            // same type and shape as img (may be null in aggregate mode)
@@ -22,37 +85,8 @@ struct FwdParams {
     // levels k = lambda, lambda + 1, lambda + 2, and the switching threshold T
     float acw_wm1[3];
     float acw_T;
-    int tiles_x, tiles_y;  // output tiles across and down one image (set by the launch)
+    TileGrid grid;  // the launch's tiles (set by the launch)
 };
-
-// Workgroup grids.  A launch of n workgroups (1 <= n < 2^31) takes x = min(n, 65535)
-// and y = ceil(n / x) < 32768: inside the dispatch limits on every dimension and on
-// work-items per dimension, however the images are shaped (2^31 one-pixel images,
-// one 2^31-pixel row).  The hardware dispatches x fastest, so flat_block(n) numbers
-// the workgroups in dispatch order; it is -1 for those at or past n (the tail of the
-// last row), which have no work and return at once.
-constexpr int kGridX = 65535;
-inline dim3 flat_grid(long long n) {
-    const long long gx = n < 1 ? 1 : (n < kGridX ? n : kGridX);
-    return dim3((unsigned)gx, (unsigned)((n + gx - 1) / gx));
-}
-__device__ __forceinline__ int flat_block(int n) {
-    // below 2^31 + 65535: no unsigned wrap, and compared before it is made an int
-    const unsigned t = blockIdx.y * gridDim.x + blockIdx.x;
-    return t < (unsigned)n ? (int)t : -1;
-}
-
-// Tile t of B images of tiles_x x tiles_y tiles each, numbered image by image and
-// row by row within an image (the order of a (tiles_x, tiles_y, B) grid).
-struct TileCoord {
-    int b, ty, tx;
-};
-__device__ __forceinline__ TileCoord tile_coord(int t, int tiles_x, int tiles_y) {
-    const int per = tiles_x * tiles_y;
-    const int b = t / per, r = t - b * per;
-    const int ty = r / tiles_x;
-    return {b, ty, r - ty * tiles_x};
-}
 
 // Launch the forward filter on `stream` with extended-tile shape `cfg`.
 // Returns hipSuccess or the launch error.
@@ -84,6 +118,8 @@ struct SoftParams {
     float p;
     float inv_tau;
     int tiles_x, tiles_y;  // tiles across and down one image (set by the launch)
+    TileGrid grid;         // the launch's tiles (set by the launch)
+    TileGrid cgrid;        // the combine pass's 64 x 4 pixel blocks
 };
 
 hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy, float* dx, int B,

@@ -215,9 +215,9 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
 
     const int tid = threadIdx.x;
     const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
-    const int tile = flat_block(prm.B * prm.tiles_x * prm.tiles_y);
+    const int tile = flat_block(prm.grid.n);
     if (tile < 0) return;
-    const TileCoord tc = tile_coord(tile, prm.tiles_x, prm.tiles_y);
+    const TileCoord tc = tile_coord(tile, prm.grid);
     const int b = tc.b;
     const int ty0 = tc.ty * TH, tx0 = tc.tx * TW;
     const int M = prm.M, N = prm.N;
@@ -410,10 +410,9 @@ __global__ void __launch_bounds__(256) softmin_combine(SoftParams prm) {
     constexpr int H = Gm::H, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     const int tiles_x = prm.tiles_x, tiles_y = prm.tiles_y;
     // a 64 x 4 block of output pixels per workgroup
-    const int bx_n = (prm.N + 63) / 64, by_n = (prm.M + 3) / 4;
-    const int blk = flat_block(prm.B * bx_n * by_n);
+    const int blk = flat_block(prm.cgrid.n);
     if (blk < 0) return;
-    const TileCoord bc = tile_coord(blk, bx_n, by_n);
+    const TileCoord bc = tile_coord(blk, prm.cgrid);
     const int gx = bc.tx * 64 + (threadIdx.x & 63);
     const int gy = bc.ty * 4 + (threadIdx.x >> 6);
     const int b = bc.b;
@@ -456,17 +455,18 @@ static hipError_t launch_soft_t(bool bwd, const SoftParams& prm, hipStream_t s) 
     SoftParams q = prm;
     if (!bwd) {
         soft_grid<W, KIND, false>(prm, q.tiles_x, q.tiles_y, nt);
-        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>),
-                           flat_grid((long long)prm.B * q.tiles_x * q.tiles_y), dim3(nt), 0, s, q);
+        q.grid = tile_grid(prm.B, q.tiles_x, q.tiles_y);
+        hipLaunchKernelGGL((softmin_kernel<W, KIND, false>), flat_grid(q.grid.n), dim3(nt), 0, s,
+                           q);
         return hipGetLastError();
     }
     soft_grid<W, KIND, true>(prm, q.tiles_x, q.tiles_y, nt);
-    hipLaunchKernelGGL((softmin_kernel<W, KIND, true>),
-                       flat_grid((long long)prm.B * q.tiles_x * q.tiles_y), dim3(nt), 0, s, q);
+    q.grid = tile_grid(prm.B, q.tiles_x, q.tiles_y);
+    q.cgrid = tile_grid(prm.B, (prm.N + 63) / 64, (prm.M + 3) / 4);
+    hipLaunchKernelGGL((softmin_kernel<W, KIND, true>), flat_grid(q.grid.n), dim3(nt), 0, s, q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 g2 = flat_grid((long long)prm.B * ((prm.N + 63) / 64) * ((prm.M + 3) / 4));
-    hipLaunchKernelGGL((softmin_combine<W, KIND>), g2, dim3(256), 0, s, q);
+    hipLaunchKernelGGL((softmin_combine<W, KIND>), flat_grid(q.cgrid.n), dim3(256), 0, s, q);
     return hipGetLastError();
 }
 

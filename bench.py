@@ -77,7 +77,7 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "15ffa6a62b39d5698feaf65627f4309538b7763c2bfc808cc68387594400edc5"
+TRAFFIC_SRC_SHA256 = "8de5c3a64cd452cccfb0556fbf0fb05b117e23b76d90ef4485b1c7863c866263"
 
 
 def forward_sources_sha256():

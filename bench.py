@@ -60,24 +60,24 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-
 # and extended tile for the per-image kernel, and ("batch6", 32, 32) for the
 # batch group kernel running the step's six variants in one launch.  Each
 # counter is scaled by what it reads for the 256 MiB float32 copy of the same
-# run (262144 KiB read, 262144 KiB written): FETCH_SIZE read 131081.8 KiB
+# run (262144 KiB read, 262144 KiB written): FETCH_SIZE read 131082.1 KiB
 # (x 1.99985), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold for the
 # kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources bench.py
 # reports traffic as null.
-TRAFFIC_FETCH_SCALE = 262144.0 / 131081.8
+TRAFFIC_FETCH_SCALE = 262144.0 / 131082.1
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact", 32, 32): (4076.6, 6144.0), ("exact", 64, 16): (2894.5, 5056.0),
-    ("exact", 32, 16): (4366.9, 6144.0), ("exact", 64, 8): (3179.5, 5056.0),
-    ("minimax", 32, 32): (4082.3, 6144.0), ("minimax", 64, 16): (2906.5, 5056.0),
-    ("minimax", 32, 16): (4377.9, 6144.0), ("minimax", 64, 8): (3197.5, 5056.0),
+    ("exact", 32, 32): (4079.6, 6144.0), ("exact", 64, 16): (2894.5, 5056.0),
+    ("exact", 32, 16): (4366.9, 6144.0), ("exact", 64, 8): (3186.6, 5056.0),
+    ("minimax", 32, 32): (4090.3, 6144.0), ("minimax", 64, 16): (2904.5, 5056.0),
+    ("minimax", 32, 16): (4371.9, 6144.0), ("minimax", 64, 8): (3197.5, 5056.0),
     ("rgb", 32, 32): (4076.3, 6144.0), ("rgb", 64, 16): (2893.0, 5056.0),
-    ("rgb", 32, 16): (4363.9, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
-    ("batch6", 32, 32): (21789.2, 36889.2),
+    ("rgb", 32, 16): (4359.9, 6144.0), ("rgb", 64, 8): (3183.5, 5056.0),
+    ("batch6", 32, 32): (21708.6, 36885.7),
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "8de5c3a64cd452cccfb0556fbf0fb05b117e23b76d90ef4485b1c7863c866263"
+TRAFFIC_SRC_SHA256 = "243bb49407e80f9ae0e33db6579b8264f79a1949c3d176f52e5974b0573faad9"
 
 
 def forward_sources_sha256():
@@ -419,7 +419,8 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
 def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
     """ACWDDF (lambda = 2, T = 10.8) on the 1024 x 1024 image (3x3 and 5x5)
     and on a 7680 x 4320 frame (3x3), each pair term, tuned tile shapes; the
-    1024 x 1024 3x3 index maps are kept for the oracle's mismatch count."""
+    1024 x 1024 3x3 index maps are kept for the oracle's mismatch count.  Also
+    CWVMF^2 and CWDDF^2 (exact) on the 1024 x 1024 image."""
     forms = {}
     big = torch.from_numpy(synth.image_corr(4320, 7680, 0.15, key=500)).to(dev)
     for w in (3, 5):
@@ -440,6 +441,17 @@ def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
                     "switched_to_ddf": round(float((i != (w * w - 1) // 2).float().mean()), 4)}
                 if tag == "1024x1024" and w == 3:
                     acw_idx[d] = i.cpu().numpy()
+    # the centre-weighted filters on their own (eq. 9), level k = 2, on the
+    # ACWDDF kernels and their tuned tile shapes
+    M, N = x1k.shape[:2]
+    o = torch.empty_like(x1k)
+    i = torch.empty((M, N), dtype=torch.uint8, device=dev)
+    for w in (3, 5):
+        for name, kind, d in (("cwvmf", odf.CWVMF, "rgb"), ("cwddf", odf.CWDDF, "exact")):
+            ms = time_launches(torch, lambda: odf.cw_filter(x1k, w, kind, 2, DIST[d], 4, out=o,
+                                                            idx=i), 10, warm=2)
+            forms["%s%d_k2_1024x1024" % (name, w)] = {"mpix_s": round(M * N / (ms * 1e3), 1),
+                                                      "ms": round(ms, 4)}
     del big
     return forms
 

@@ -46,10 +46,18 @@ typedef enum {
  * Omega_u = A_u^(1-p) * D_u^p, A_u the angle sum of eq. (2) and D_u the sum of
  * L2 distances of eq. (1); p = 1/2 orders members as the product of eq. (3),
  * p = 0 is BVDF and p = 1 the vector median of eq. (1). */
-typedef enum { ODF_BVDF = 0, ODF_DDF = 1, ODF_ACWDDF = 2 } odf_kind;
+typedef enum {
+    ODF_BVDF = 0,
+    ODF_DDF = 1,
+    ODF_ACWDDF = 2,
+    ODF_CWVMF = 3,
+    ODF_CWDDF = 4
+} odf_kind;
 /* ODF_ACWDDF (the adaptive centre-weighted DDF of Section III, Experiment 2)
  * is computed by odf_acwddf_u8 / odf_acwddf_f32 and is accepted as a kind by
- * the tuning calls only; the other entry points take ODF_BVDF or ODF_DDF. */
+ * the tuning calls; ODF_CWVMF and ODF_CWDDF (its centre-weighted levels as
+ * filters of their own) by odf_cw_filter_u8 / odf_cw_filter_f32 only.  The
+ * other entry points take ODF_BVDF or ODF_DDF. */
 
 /* Angular pair term.  EXACT: the angle of eq. (2).  MINIMAX: Section 2.1
  * (Method 1), the degree-q minimax polynomials of Table 1 with the
@@ -123,6 +131,28 @@ int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist,
  * non-negative inputs). */
 int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, int q,
                    int lambda, float T, float* out, uint8_t* idx, void* stream);
+
+/*
+ * Centre-weighted filters at one smoothing level k (Section III, eq. 9), with
+ * the centre member d = (n-1)/2 weighted w_d(k) = n - 2k + 2 and every other
+ * member 1:
+ *   ODF_CWVMF  CWVMF^k, eq. (9): the member minimising
+ *              sum_v w_v(k) L2(x_u, x_v); `dist` and `q` are ignored;
+ *   ODF_CWDDF  CWDDF^k: the same weights on both sums of eq. (3), the member
+ *              minimising (sum_v w_v(k) A(x_u, x_v)) (sum_v w_v(k) L2(x_u, x_v)),
+ *              A the pair term of `dist` as in odf_acwddf_u8.
+ * k = d weighs every member 1 (CWVMF^d is the vector median, CWDDF^d the DDF
+ * of eq. 3); k = 1 weighs the centre n, which keeps the centre's colour.
+ *   level  k in [1, (n+1)/2].
+ *   img, out, idx as for odf_filter_u8; ties go to the lowest index.
+ * Runs on the ACWDDF kernels (and their tile table entries); windows 3 and 5.
+ * Errors: as odf_filter_u8, plus ODF_EINVAL for kind or level out of range,
+ * ODF_EUNSUPPORTED for window 7.
+ */
+int odf_cw_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, int dist, int q,
+                     int level, uint8_t* out, uint8_t* idx, void* stream);
+int odf_cw_filter_f32(const float* img, int B, int M, int N, int window, int kind, int dist, int q,
+                      int level, float* out, uint8_t* idx, void* stream);
 
 /*
  * Aggregates of every window (test and inspection hook, not the fast path).

@@ -53,9 +53,10 @@ def _load():
         lib.oracle_softmin_bwd.argtypes = [P, P, I, I, I, I, I, D, D, P, I]
         lib.oracle_acwddf.argtypes = [P, I, I, I, I, I, I, I, D, P, P, P, P, I]
         lib.oracle_acwddf_at.argtypes = [P, I, I, I, I, I, I, I, D, P, I64, P, P, P, P, I]
+        lib.oracle_cwfilter.argtypes = [P, I, I, I, I, I, I, I, I, P, P, P, I]
         for f in (lib.oracle_pair_terms, lib.oracle_filter, lib.oracle_filter_at,
                   lib.oracle_backward_hard, lib.oracle_softmin_fwd, lib.oracle_softmin_bwd,
-                  lib.oracle_acwddf, lib.oracle_acwddf_at):
+                  lib.oracle_acwddf, lib.oracle_acwddf_at, lib.oracle_cwfilter):
             f.restype = I
         _lib = lib
     return _lib
@@ -216,3 +217,21 @@ def acwddf_at(img, pix, window=3, dist=EXACT, q=4, lam=2, T=10.8, nthreads=0):
                                     _ptr(pix), k, _ptr(out), _ptr(idx), _ptr(S), _ptr(dg),
                                     nthreads), "acwddf_at")
     return out, idx, S, dg
+
+
+def cwfilter(img, window=3, vmf=True, dist=EXACT, q=4, level=1, nthreads=0):
+    """Centre-weighted filters (Section III, eq. 9): CWVMF^k (vmf) minimises
+    sum_v w_v(k) L2(x_u, x_v) with w_d(k) = n - 2k + 2 on the centre member and
+    1 elsewhere; CWDDF^k (not vmf) minimises the product of the weighted angle
+    and L2 sums (the pair term of `dist`, eq. 10 for chromaticity).
+    Returns (out, idx, obj): obj (..., n) the objective of every member."""
+    x, squeeze = _batch(img)
+    B, M, N, _ = x.shape
+    n = window * window
+    out = np.empty_like(x)
+    idx = np.empty((B, M, N), np.uint8)
+    obj = np.empty((B, M, N, n))
+    _check(_load().oracle_cwfilter(_ptr(x), B, M, N, window, int(bool(vmf)), dist, q, int(level),
+                                   _ptr(out), _ptr(idx), _ptr(obj), nthreads), "cwfilter")
+    res = (out, idx, obj)
+    return tuple(r[0] for r in res) if squeeze else res

@@ -41,7 +41,9 @@
  *     function as every other pair;
  *   - ACWDDF (Section III, Experiment 2): CWDDF^k applies the centre weights
  *     of eq. (9) to both sums of eq. (3); lambda is limited to [1, d - 2] so
- *     that every level k = lambda .. lambda + 2 lies in [1, d].
+ *     that every level k = lambda .. lambda + 2 lies in [1, d];
+ *   - the centre-weighted filters on their own: CWVMF^k is eq. (9) with the
+ *     Minkowski order p = 2, CWDDF^k the reading above, for k in [1, d].
  */
 #include <math.h>
 #include <stdint.h>
@@ -573,5 +575,57 @@ int oracle_acwddf_at(const double *img, int B, int M, int N, int w, int dist, in
     for (int64_t k = 0; k < npix; ++k)
         acwddf_one(img, M, N, w, dist, q, lambda, T, pix[k], out ? out + 3 * k : NULL,
                    idx ? idx + k : NULL, S ? S + k : NULL, diag ? diag + 5 * n * k : NULL);
+    return 0;
+}
+
+/* ------------------------------------------------ centre-weighted filters
+ * CWVMF^k (eq. 9): the member minimising sum_v w_v(k) L2(x_u, x_v), with
+ * w_d(k) = n - 2k + 2 on the centre member and 1 elsewhere, k in [1, d].
+ * CWDDF^k: the same weights on both sums of eq. (3), the member minimising
+ * (sum_v w_v(k) A(x_u, x_v)) * (sum_v w_v(k) L2(x_u, x_v)), A the variant's
+ * pair term as in ACWDDF (eq. 10 on the chromaticity distance for Method 2).
+ * obj (nullable, n doubles per pixel): the objective of every member. */
+static void cw_one(const double *img, int M, int N, int w, int vmf, int dist, int q, int level,
+                   int64_t pix, double *out, uint8_t *idx, double *obj) {
+    int64_t mn = (int64_t)M * N;
+    int64_t b = pix / mn, rc = pix % mn;
+    int r = (int)(rc / N), c = (int)(rc % N);
+    int n = w * w, d = (n - 1) / 2;
+    int64_t src[NMAX];
+    double Om[NMAX];
+    const double *base = img + b * mn * 3;
+    window_members(M, N, w, r, c, src);
+    for (int u = 0; u < n; ++u) {
+        double a = 0.0, e = 0.0;
+        for (int v = 0; v < n; ++v) {
+            double wv = v == d ? (double)(n - 2 * level + 2) : 1.0;
+            const double *xu = base + src[u] * 3, *xv = base + src[v] * 3;
+            if (!vmf) a += wv * pair_term(xu, xv, OK_DDF, dist, q);
+            e += wv * minkowski_l2(xu, xv);
+        }
+        Om[u] = vmf ? e : a * e;
+    }
+    int sel = 0;
+    for (int u = 1; u < n; ++u)
+        if (Om[u] < Om[sel]) sel = u;
+    const double *x = base + src[sel] * 3;
+    if (out) { out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; }
+    if (idx) *idx = (uint8_t)sel;
+    if (obj)
+        for (int u = 0; u < n; ++u) obj[u] = Om[u];
+}
+
+/* CWVMF^k (vmf = 1) or CWDDF^k (vmf = 0) over B images; out, idx, obj nullable. */
+int oracle_cwfilter(const double *img, int B, int M, int N, int w, int vmf, int dist, int q,
+                    int level, double *out, uint8_t *idx, double *obj, int nthreads) {
+    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || !img) return -1;
+    if (level < 1 || level > (w * w + 1) / 2 || (vmf != 0 && vmf != 1)) return -1;
+    set_threads(nthreads);
+    int64_t total = (int64_t)B * M * N;
+    int n = w * w;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t pix = 0; pix < total; ++pix)
+        cw_one(img, M, N, w, vmf, dist, q, level, pix, out ? out + 3 * pix : NULL,
+               idx ? idx + pix : NULL, obj ? obj + (int64_t)n * pix : NULL);
     return 0;
 }

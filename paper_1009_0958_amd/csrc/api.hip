@@ -144,11 +144,51 @@ int acwddf_any(const void* img, bool u8, int B, int M, int N, int window, int di
     return ODF_OK;
 }
 
+int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, int dist, int q,
+           int level, void* out, uint8_t* idx, void* stream) {
+    int rc = check_common(img, B, M, N, window, ODF_DDF, 0.5f, dist, q);
+    if (rc) return rc;
+    if (kind != ODF_CWVMF && kind != ODF_CWDDF)
+        return fail(ODF_EINVAL, "kind %d is not ODF_CWVMF or ODF_CWDDF", kind);
+    if (window == 7) return fail(ODF_EUNSUPPORTED, "centre-weighted filters support windows 3 and 5");
+    if (!out) return fail(ODF_EINVAL, "out is NULL");
+    const int n = window * window, dmax = (n + 1) / 2;
+    if (level < 1 || level > dmax) return fail(ODF_EINVAL, "level %d out of range [1, %d]", level, dmax);
+    const size_t npix = (size_t)B * M * N;
+    const size_t esz = u8 ? 1 : 4;
+    if (overlaps(img, npix * 3 * esz, out, npix * 3 * esz))
+        return fail(ODF_EINVAL, "out overlaps img (the filter cannot run in place)");
+    if (idx && (overlaps(img, npix * 3 * esz, idx, npix) || overlaps(out, npix * 3 * esz, idx, npix)))
+        return fail(ODF_EINVAL, "idx overlaps img or out");
+    // CWVMF^k uses no angle: run the cheapest pair term, whose sums go unused
+    const int d = kind == ODF_CWVMF ? ODF_RGB : dist;
+    odf::FwdParams prm = make_params(img, B, M, N, 0.5f, d, q);
+    prm.out = out;
+    prm.idx = idx;
+    for (int j = 0; j < 3; ++j) prm.acw_wm1[j] = (float)(n - 2 * level + 1);  // w_d(k) - 1
+    prm.cw = kind == ODF_CWVMF ? 2 : 1;
+    const int cfg = odf::tuned_config(window, ODF_ACWDDF, d, u8);
+    hipError_t e = odf::launch_forward(window, odf::kCW, d, u8, false, cfg, prm,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "centre-weighted filter launch");
+    return ODF_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int odf_version(void) { return (0 << 16) | 2; }
+int odf_version(void) { return (0 << 16) | 3; }
+
+int odf_cw_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, int dist, int q,
+                     int level, uint8_t* out, uint8_t* idx, void* stream) {
+    return cw_any(img, true, B, M, N, window, kind, dist, q, level, out, idx, stream);
+}
+
+int odf_cw_filter_f32(const float* img, int B, int M, int N, int window, int kind, int dist, int q,
+                      int level, float* out, uint8_t* idx, void* stream) {
+    return cw_any(img, false, B, M, N, window, kind, dist, q, level, out, idx, stream);
+}
 
 int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
                   int lambda, float T, uint8_t* out, uint8_t* idx, void* stream) {

@@ -15,7 +15,8 @@ constexpr int kTileH[kNumTileConfigs] = {32, 16, 16, 8};
 // 512-thread tiles only.
 bool tile_config_valid(int window, int kind, int cfg) {
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
-    if ((window == 5 && kind == kACW) || window == 7) return kTileW[cfg] * kTileH[cfg] <= 512;
+    if ((window == 5 && centre_weighted(kind)) || window == 7)
+        return kTileW[cfg] * kTileH[cfg] <= 512;
     return true;
 }
 

@@ -16,7 +16,7 @@ namespace odf {
 // Caps on 7x7 DDF, 5x5 ACWDDF and 5x5 BVDF minimax measured 4-8 % slower.
 template <int W, int KIND, int DIST>
 constexpr int fwd_waves_per_eu() {
-    if (W == 3 && KIND != kACW) return 8;
+    if (W == 3 && !centre_weighted(KIND)) return 8;
     if (W == 5 && KIND == kBVDF && DIST != kMinimax) return 6;
     if (W == 7 && KIND == kBVDF) return 4;
     return 1;
@@ -50,7 +50,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
     if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
         (void)cfg;
         return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-    } else if constexpr ((W == 5 && KIND == kACW) || W == 7) {
+    } else if constexpr ((W == 5 && centre_weighted(KIND)) || W == 7) {
         switch (cfg) {
         case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
@@ -68,7 +68,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
 
 template <int W, int KIND, int DIST>
 static hipError_t launch_wkd(bool u8, bool agg, int cfg, const FwdParams& prm, hipStream_t s) {
-    if constexpr (KIND == kACW) {  // no aggregate-inspection form
+    if constexpr (centre_weighted(KIND)) {  // no aggregate-inspection form
         if (agg) return hipErrorInvalidValue;
         return u8 ? launch_t<W, KIND, DIST, true, false>(cfg, prm, s)
                   : launch_t<W, KIND, DIST, false, false>(cfg, prm, s);
@@ -95,8 +95,9 @@ static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const
                            hipStream_t s) {
     if (kind == kBVDF) return launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s);
     if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
-    if constexpr (W == 7) return hipErrorInvalidValue;  // no 7x7 ACWDDF
-    else return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
+    if constexpr (W == 7) return hipErrorInvalidValue;  // no 7x7 centre-weighted filters
+    else if (kind == kACW) return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
+    else return launch_wk<W, kCW>(dist, u8, agg, cfg, prm, s);
 }
 
 // Launchers of the window sizes instantiated in fwd5.hip and fwd7.hip.

@@ -124,11 +124,11 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     float A[NW], D[NW];
     float cA[NW], cD[NW];
     if constexpr (fused_sweep<W, KIND>())
-        member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, 2, KIND == kACW, false>(
-            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD);
+        member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, 2, centre_weighted(KIND),
+                            false>(px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD);
     else
-        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, KIND == kACW, false>(
-            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, centre_weighted(KIND),
+                            false>(px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
     if constexpr (stage_angle_part<W, KIND, AGG>()) {
         // angle part of each objective -> LDS, then the L2 pass
         const int mode = objective_mode<KIND>(prm.p);
@@ -154,8 +154,8 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     } else if constexpr (fused_sweep<W, KIND>()) {
         ;  // D and cD came with the angular sweep
     } else if (KIND != kBVDF) {
-        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, KIND == kACW, false>(
-            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, centre_weighted(KIND),
+                            false>(px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
     } else {
 #pragma unroll
         for (int u = 0; u < NW; ++u) D[u] = 0.0f;
@@ -244,6 +244,19 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             atomicMin(&s_key[2 * KEYN + ci], ((unsigned long long)__float_as_uint(o2) << 32) | uu);
             atomicMin(&s_key[3 * KEYN + ci], ((unsigned long long)__float_as_uint(o3) << 32) | uu);
         }
+    } else if constexpr (KIND == kCW) {
+        // one centre-weighted filter at one level (weight w_d(k) - 1 = acw_wm1[0]):
+        // CWDDF^k the weighted product, CWVMF^k (eq. 9) the weighted L2 sum
+        const float w1 = prm.acw_wm1[0];
+        const bool vmf = prm.cw == 2;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            if (!window_ok(u)) continue;
+            const float dw = fmaf(w1, cD[u], D[u]);
+            const float o = vmf ? dw : fmaf(w1, cA[u], A[u]) * dw;
+            atomicMin(&s_key[key_slot(u)],
+                      ((unsigned long long)__float_as_uint(o) << 32) | (unsigned)u);
+        }
     } else {
         uint32_t kb[NW];
         objective_key_bits<NW>(objective_mode<KIND>(prm.p), prm.p, A, D, kb);
@@ -281,11 +294,13 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
                     const bool mz = md.w < 0.0f;
                     pair_u8<KIND, DIST, true, true>(md, INV ? sh.inv[m] : 0.0f, mz,
                                                     __builtin_amdgcn_ballot_w64(mz), cd,
-                                                    INV ? sh.inv[c] : 0.0f, prm.coef, ac, th, l2);
+                                                    INV ? sh.inv[c] : 0.0f, prm.coef, ac, th,
+                                                    l2);
                     S += th * l2;
                 } else {
                     const float4 cr = sh.raw[c];
-                    S += pair_term<KIND, DIST, U8>(s_dir[m], sh.raw[m], cd, cr, prm.coef, ac) *
+                    S += pair_term<KIND, DIST, U8>(s_dir[m], sh.raw[m], cd, cr, prm.coef,
+                                                   ac) *
                          l2_term(sh.raw[m], cr);
                 }
             }

@@ -17,11 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libodf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "odf.h")
 
-BVDF, DDF, ACWDDF = 0, 1, 2
+BVDF, DDF, ACWDDF, CWVMF, CWDDF = 0, 1, 2, 3, 4
 EXACT, MINIMAX, RGB = 0, 1, 2
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
 
-_KIND = {"bvdf": BVDF, "ddf": DDF, "acwddf": ACWDDF}
+_KIND = {"bvdf": BVDF, "ddf": DDF, "acwddf": ACWDDF, "cwvmf": CWVMF, "cwddf": CWDDF}
 _DIST = {"exact": EXACT, "minimax": MINIMAX, "rgb": RGB}
 
 _lib = None
@@ -50,6 +50,8 @@ def lib():
         L.odf_filter_f32.argtypes = [P, I, I, I, I, I, F, I, I, P, P, P]
         L.odf_acwddf_u8.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
         L.odf_acwddf_f32.argtypes = [P, I, I, I, I, I, I, I, F, P, P, P]
+        L.odf_cw_filter_u8.argtypes = [P, I, I, I, I, I, I, I, I, P, P, P]
+        L.odf_cw_filter_f32.argtypes = [P, I, I, I, I, I, I, I, I, P, P, P]
         L.odf_aggregates_f32.argtypes = [P, I, I, I, I, I, I, F, I, I, P, P, P, P]
         Dbl = ctypes.c_double
         L.odf_noise_eq8_u8.argtypes = [P, P, I, I, I, Dbl, Dbl, Dbl, Dbl, ctypes.c_uint64, P]
@@ -160,6 +162,29 @@ def acwddf(img, window=3, dist=EXACT, q=4, lam=2, T=10.8, out=None, idx=None,
     fn = lib().odf_acwddf_u8 if x.dtype == torch.uint8 else lib().odf_acwddf_f32
     _check(fn(_ptr(x), B, M, N, window, _dist(dist), q, int(lam), float(T), _ptr(out), _ptr(idx),
               _stream(x.device)))
+    if squeeze:
+        out = out[0]
+        idx = None if idx is None else idx[0]
+    return out, idx
+
+
+def cw_filter(img, window=3, kind=CWVMF, level=1, dist=EXACT, q=4, out=None, idx=None,
+              return_idx=True):
+    """Centre-weighted filter at smoothing level k = ``level`` (Section III,
+    eq. 9): CWVMF^k (the weighted L2 sum) or CWDDF^k (the weights on both sums
+    of eq. 3).  Returns (out, idx)."""
+    x, squeeze = _as_batch(img)
+    _check_tensor(x, "img")
+    B, M, N, _ = x.shape
+    if x.dtype not in (torch.uint8, torch.float32):
+        raise ValueError("img must be uint8 or float32")
+    if out is None:
+        out = torch.empty_like(x)
+    if idx is None and return_idx:
+        idx = torch.empty((B, M, N), dtype=torch.uint8, device=x.device)
+    fn = lib().odf_cw_filter_u8 if x.dtype == torch.uint8 else lib().odf_cw_filter_f32
+    _check(fn(_ptr(x), B, M, N, window, _kind(kind), _dist(dist), q, int(level), _ptr(out),
+              _ptr(idx), _stream(x.device)))
     if squeeze:
         out = out[0]
         idx = None if idx is None else idx[0]

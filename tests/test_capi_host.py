@@ -200,3 +200,18 @@ def test_softmin_f64_rejects():
     assert bwd(None, need) == odf.EINVAL
     assert bwd(ctypes.c_void_p(0x7F0000200000 + 64), need) == odf.EINVAL
     assert "overlap" in odf.last_error()
+
+
+def test_cw_filter_rejects():
+    L = odf.lib()
+    f = lambda w, kind, level, dist=0, out=FAKE2: L.odf_cw_filter_u8(  # noqa: E731
+        FAKE, 1, 8, 8, w, kind, dist, 4, level, out, None, None)
+    assert f(3, odf.CWVMF, 0) == odf.EINVAL and "level" in odf.last_error()
+    assert f(3, odf.CWVMF, 6) == odf.EINVAL and "level" in odf.last_error()
+    assert f(5, odf.CWDDF, 14) == odf.EINVAL
+    assert f(3, odf.DDF, 1) == odf.EINVAL and "kind" in odf.last_error()
+    assert f(3, odf.ACWDDF, 1) == odf.EINVAL
+    assert f(7, odf.CWVMF, 1) == odf.EUNSUPPORTED
+    assert f(3, odf.CWDDF, 1, dist=3) == odf.EINVAL and "dist" in odf.last_error()
+    assert f(3, odf.CWVMF, 1, out=None) == odf.EINVAL and "out" in odf.last_error()
+    assert f(3, odf.CWVMF, 1, out=FAKE) == odf.EINVAL and "overlaps" in odf.last_error()

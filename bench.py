@@ -125,6 +125,28 @@ def slots_per_pixel(window, kind, p, dist):
     return s
 
 
+def softmin_slots_per_pixel(window, bwd):
+    """VALU lane-slots per output pixel of the softmin relaxation (exact angle,
+    DDF with the objective's logarithms).  Forward: the DDF forward's pair terms
+    and box sums, per member (1-p) log2 A + p log2 D (2 transcendentals + 2),
+    the weight exp2 (1 transcendental + 2) and the weighted sum of colours (3
+    fma + 1 add).  Backward: the forward again, per member the weight and
+    objective derivatives (8), then per unordered pair the angle gradient (two
+    cross products 18, norms and reciprocal 8 + a transcendental, 6 scaling)
+    and the L2 gradient (3 sub, reciprocal square root, 3 mul), each
+    accumulated into both pixels (12), and the transposed box sums of the
+    member gradients (one more set of box sums per plane)."""
+    h = window // 2
+    n = window * window
+    pairs = 2 * h * (4 * h + 1) + 2 * h
+    box = window * (window - 1) * (3 * window - 1)
+    fwd = (pairs * (PAIR_SLOTS["exact"] + L2_SLOTS) + 2 * box + 10
+           + n * (2 * TRANS + 2) + n * (TRANS + 2) + 4 * n)
+    if not bwd:
+        return fwd
+    return (fwd + 8 * n + pairs * (32 + TRANS + 3 + TRANS + 3 + 12) + 2 * box)
+
+
 # ------------------------------------------------------------------ helpers
 
 def _events(torch):
@@ -598,7 +620,10 @@ def differentiable_forms(torch, odf, synth, dev):
     forms["ddf5_f32_16x512x512_hard"] = {
         "fwd_ms": round(ms_f, 3), "bwd_ms": round(ms_b, 3),
         "fwd_bwd_mpix_s": round(npx / ((ms_f + ms_b) * 1e3), 1),
-        "bwd_hbm_GBps": round(npx * 25 / (ms_b * 1e-3) / 1e9, 1)}
+        "fwd_valu_frac": round(slots_per_pixel(5, "ddf", 0.25, "exact") * npx / (ms_f * 1e-3)
+                               / PEAK_SLOTS, 4),
+        "bwd_hbm_GBps": round(npx * 25 / (ms_b * 1e-3) / 1e9, 1),
+        "bwd_hbm_frac": round(npx * 25 / (ms_b * 1e-3) / 8e12, 4)}
     ws = torch.empty(odf.lib().odf_softmin_bwd_workspace(16, 512, 512, 5, odf.DDF),
                      dtype=torch.uint8, device=dev)
     for tau in (0.01, 0.1):
@@ -607,7 +632,11 @@ def differentiable_forms(torch, odf, synth, dev):
                                                                   workspace=ws), 5)
         forms["ddf5_f32_16x512x512_softmin_tau%g" % tau] = {
             "fwd_ms": round(ms_sf, 3), "bwd_ms": round(ms_sb, 3),
-            "fwd_bwd_mpix_s": round(npx / ((ms_sf + ms_sb) * 1e3), 1)}
+            "fwd_bwd_mpix_s": round(npx / ((ms_sf + ms_sb) * 1e3), 1),
+            "fwd_valu_frac": round(softmin_slots_per_pixel(5, False) * npx / (ms_sf * 1e-3)
+                                   / PEAK_SLOTS, 4),
+            "bwd_valu_frac": round(softmin_slots_per_pixel(5, True) * npx / (ms_sb * 1e-3)
+                                   / PEAK_SLOTS, 4)}
     # plain PyTorch on 2 images (its n^2 intermediates take several GB per image)
     xs = x[:2].clone().requires_grad_(True)
     g = dy[:2].contiguous()

@@ -160,15 +160,15 @@ int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, 
         return fail(ODF_EINVAL, "out overlaps img (the filter cannot run in place)");
     if (idx && (overlaps(img, npix * 3 * esz, idx, npix) || overlaps(out, npix * 3 * esz, idx, npix)))
         return fail(ODF_EINVAL, "idx overlaps img or out");
-    // CWVMF^k uses no angle: run the cheapest pair term, whose sums go unused
+    // CWVMF^k has no angle term: its kernel sweeps the L2 term alone
     const int d = kind == ODF_CWVMF ? ODF_RGB : dist;
     odf::FwdParams prm = make_params(img, B, M, N, 0.5f, d, q);
     prm.out = out;
     prm.idx = idx;
     for (int j = 0; j < 3; ++j) prm.acw_wm1[j] = (float)(n - 2 * level + 1);  // w_d(k) - 1
-    prm.cw = kind == ODF_CWVMF ? 2 : 1;
     const int cfg = odf::tuned_config(window, ODF_ACWDDF, d, u8);
-    hipError_t e = odf::launch_forward(window, odf::kCW, d, u8, false, cfg, prm,
+    hipError_t e = odf::launch_forward(window, kind == ODF_CWVMF ? odf::kCWV : odf::kCW, d, u8,
+                                       false, cfg, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "centre-weighted filter launch");
     return ODF_OK;

@@ -83,6 +83,7 @@ static hipError_t launch_wkd(bool u8, bool agg, int cfg, const FwdParams& prm, h
 template <int W, int KIND>
 static hipError_t launch_wk(int dist, bool u8, bool agg, int cfg, const FwdParams& prm,
                             hipStream_t s) {
+    if constexpr (KIND == kCWV) return launch_wkd<W, KIND, kRgb>(u8, agg, cfg, prm, s);  // no angle
     switch (dist) {
     case kExact: return launch_wkd<W, KIND, kExact>(u8, agg, cfg, prm, s);
     case kMinimax: return launch_wkd<W, KIND, kMinimax>(u8, agg, cfg, prm, s);
@@ -97,7 +98,8 @@ static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const
     if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
     if constexpr (W == 7) return hipErrorInvalidValue;  // no 7x7 centre-weighted filters
     else if (kind == kACW) return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
-    else return launch_wk<W, kCW>(dist, u8, agg, cfg, prm, s);
+    else if (kind == kCW) return launch_wk<W, kCW>(dist, u8, agg, cfg, prm, s);
+    else return launch_wk<W, kCWV>(dist, u8, agg, cfg, prm, s);
 }
 
 // Launchers of the window sizes instantiated in fwd5.hip and fwd7.hip.

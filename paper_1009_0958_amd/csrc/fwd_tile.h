@@ -62,7 +62,7 @@ constexpr bool stage_angle_part() {
 // member_aggregates_x); 5x5 keeps two sweeps (register budget).
 template <int W, int KIND>
 constexpr bool fused_sweep() {
-    return W == 3 && KIND != kBVDF;
+    return W == 3 && KIND != kBVDF && KIND != kCWV;
 }
 
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
@@ -123,7 +123,10 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     // a2 + a3 (ACWDDF also keeps each member's terms with the window centres)
     float A[NW], D[NW];
     float cA[NW], cD[NW];
-    if constexpr (fused_sweep<W, KIND>())
+    if constexpr (KIND == kCWV) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) A[u] = cA[u] = 0.0f;  // no angle term
+    } else if constexpr (fused_sweep<W, KIND>())
         member_aggregates_x<W, KIND, DIST, U8, EXT_W, EXT_H, 2, centre_weighted(KIND),
                             false>(px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD);
     else
@@ -244,16 +247,15 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             atomicMin(&s_key[2 * KEYN + ci], ((unsigned long long)__float_as_uint(o2) << 32) | uu);
             atomicMin(&s_key[3 * KEYN + ci], ((unsigned long long)__float_as_uint(o3) << 32) | uu);
         }
-    } else if constexpr (KIND == kCW) {
+    } else if constexpr (KIND == kCW || KIND == kCWV) {
         // one centre-weighted filter at one level (weight w_d(k) - 1 = acw_wm1[0]):
         // CWDDF^k the weighted product, CWVMF^k (eq. 9) the weighted L2 sum
         const float w1 = prm.acw_wm1[0];
-        const bool vmf = prm.cw == 2;
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             if (!window_ok(u)) continue;
             const float dw = fmaf(w1, cD[u], D[u]);
-            const float o = vmf ? dw : fmaf(w1, cA[u], A[u]) * dw;
+            const float o = KIND == kCWV ? dw : fmaf(w1, cA[u], A[u]) * dw;
             atomicMin(&s_key[key_slot(u)],
                       ((unsigned long long)__float_as_uint(o) << 32) | (unsigned)u);
         }

@@ -85,9 +85,6 @@ struct FwdParams {
     // levels k = lambda, lambda + 1, lambda + 2, and the switching threshold T
     float acw_wm1[3];
     float acw_T;
-    // centre-weighted filters on the ACWDDF path: 0 the ACWDDF rule; 1 CWDDF^k,
-    // 2 CWVMF^k, the selection of the first level (weight acw_wm1[0]) itself
-    int cw;
     TileGrid grid;  // the launch's tiles (set by the launch)
 };
 

@@ -26,10 +26,11 @@ namespace odf {
 
 // kACW: the adaptive centre-weighted DDF (Section III, Experiment 2), whose
 // pair terms are the DDF's.
-enum Kind { kBVDF = 0, kDDF = 1, kACW = 2, kCW = 3 };
-// kCW: one centre-weighted filter at one level (CWDDF^k or CWVMF^k), on the
-// ACWDDF sweep (which forms every member's terms with the window centre).
-constexpr bool centre_weighted(int kind) { return kind == kACW || kind == kCW; }
+enum Kind { kBVDF = 0, kDDF = 1, kACW = 2, kCW = 3, kCWV = 4 };
+// kCW: CWDDF^k, one centre-weighted DDF at one level, on the ACWDDF sweep
+// (which forms every member's terms with the window centre); kCWV: CWVMF^k,
+// the same with the L2 sweep alone (eq. 9 has no angle).
+constexpr bool centre_weighted(int kind) { return kind == kACW || kind == kCW || kind == kCWV; }
 enum Dist { kExact = 0, kMinimax = 1, kRgb = 2 };
 
 // eq. (10): A ~= 1.436437 B + 0.027664

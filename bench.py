@@ -60,20 +60,20 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-
 # and extended tile for the per-image kernel, and ("batch6", 32, 32) for the
 # batch group kernel running the step's six variants in one launch.  Each
 # counter is scaled by what it reads for the 256 MiB float32 copy of the same
-# run (262144 KiB read, 262144 KiB written): FETCH_SIZE read 131082.1 KiB
-# (x 1.99985), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold for the
+# run (262144 KiB read, 262144 KiB written): FETCH_SIZE read 131082.2 KiB
+# (x 1.99984), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold for the
 # kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources bench.py
 # reports traffic as null.
-TRAFFIC_FETCH_SCALE = 262144.0 / 131082.1
+TRAFFIC_FETCH_SCALE = 262144.0 / 131082.2
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact", 32, 32): (4079.6, 6144.0), ("exact", 64, 16): (2894.5, 5056.0),
+    ("exact", 32, 32): (4072.6, 6144.0), ("exact", 64, 16): (2895.5, 5056.0),
     ("exact", 32, 16): (4366.9, 6144.0), ("exact", 64, 8): (3186.6, 5056.0),
     ("minimax", 32, 32): (4090.3, 6144.0), ("minimax", 64, 16): (2904.5, 5056.0),
-    ("minimax", 32, 16): (4371.9, 6144.0), ("minimax", 64, 8): (3197.5, 5056.0),
-    ("rgb", 32, 32): (4076.3, 6144.0), ("rgb", 64, 16): (2893.0, 5056.0),
-    ("rgb", 32, 16): (4359.9, 6144.0), ("rgb", 64, 8): (3183.5, 5056.0),
-    ("batch6", 32, 32): (21708.6, 36885.7),
+    ("minimax", 32, 16): (4377.9, 6144.0), ("minimax", 64, 8): (3197.0, 5056.0),
+    ("rgb", 32, 32): (4072.2, 6144.0), ("rgb", 64, 16): (2892.5, 5056.0),
+    ("rgb", 32, 16): (4363.9, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
+    ("batch6", 32, 32): (21903.4, 36887.7),
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")

@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from paper_1009_0958_amd import synth
-from parity import check_aggregates, check_selection, source_pixels
+from parity import AGG_RTOL, check_aggregates, check_selection, source_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -20,7 +20,7 @@ def _gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
-def run_and_check(img, window, kind, p, dist, q=4, aggregates=True):
+def run_and_check(img, window, kind, p, dist, q=4, aggregates=True, agg_rtol=AGG_RTOL):
     """Full-image parity: selections, output copies and aggregates."""
     print("case: shape=%s w=%d kind=%d p=%s dist=%d q=%d" % (img.shape, window, kind, p, dist, q),
           flush=True)
@@ -36,10 +36,10 @@ def run_and_check(img, window, kind, p, dist, q=4, aggregates=True):
     assert idx.max() < window * window
     if aggregates:
         A, D, O = (t.cpu().numpy() for t in odf.aggregates(x, window, kind, p, dist, q))
-        check_aggregates(A, oA, name="A")
+        check_aggregates(A, oA, agg_rtol, name="A")
         if kind == DDF:
             check_aggregates(D, oD, name="D")
-        check_aggregates(O, oO, name="Omega")
+        check_aggregates(O, oO, agg_rtol, name="Omega")
     return n_mis, n
 
 
@@ -84,6 +84,19 @@ def test_minimax_degrees(q, window):
 def test_float_inputs_exact(window, kind, p):
     img = synth.float_batch(2, 45, 70, 0.1, key=window)
     run_and_check(img, window, kind, p, EXACT)
+
+
+@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("dist", [MINIMAX, RGB])
+@pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25)])
+def test_float_inputs_minimax_rgb(window, dist, kind, p):
+    """float32 inputs (non-negative, as minimax and the chromaticity term need)
+    with the two fast pair terms; every window size, both kinds.  The
+    chromaticity numerators of float pixels are differences of rounded
+    products, accurate to ~1e-4 relative for nearly equal chromaticities, so
+    its aggregates are held to that bound (selections to the near-tie band)."""
+    img = synth.float_batch(2, 41, 66, 0.1, key=40 + window + dist)
+    run_and_check(img, window, kind, p, dist, agg_rtol=1e-4 if dist == RGB else AGG_RTOL)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (30, 30), (31, 29), (28, 28),

@@ -146,15 +146,19 @@ def _sparse_zeros(M, N, key):
     return img
 
 
+@pytest.mark.parametrize("u8", [True, False])
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
 @pytest.mark.parametrize("window", [3, 5, 7])
-def test_sparse_zero_pixels(window, dist):
+def test_sparse_zero_pixels(window, dist, u8):
     # the zero pixel's direction (1,1,1) and value 0 next to nonzero neighbours: the
     # uint8 layout marks it by the sign of its stored norm and takes its L2 terms from
-    # the other pixel's norm
+    # the other pixel's norm; the float layout meets it through a zero norm
     img = _sparse_zeros(70, 97, key=window * 3 + dist)
+    if not u8:
+        img = img.astype(np.float32) / 255
+    tol = 1e-4 if (dist == RGB and not u8) else AGG_RTOL
     for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 1.0)):
-        run_and_check(img, window, kind, p, dist, aggregates=window < 7)
+        run_and_check(img, window, kind, p, dist, aggregates=window < 7, agg_rtol=tol)
 
 
 # 3x3 pattern whose colour X (twice) minimises every objective of a window holding it

@@ -28,8 +28,10 @@ namespace odf {
 
 // Extended tile of the softmin kernels (one thread per extended pixel).  The
 // 5x5 forward parks the angle part of every objective in LDS between its two
-// sweeps, which frees the registers for 1024-thread tiles; the backward keeps
-// A, D and Omega in registers and uses 512-thread tiles.
+// sweeps, which frees the registers for 1024-thread tiles.  The backward uses
+// 512-thread tiles; it parks the angle sums A during the L2 sweep as well and
+// recomputes Omega from A and D where it needs it, so that (with 128 VGPRs) two
+// workgroups share a compute unit.
 template <int W, int KIND, bool BWD>
 struct SoftTile {
     static constexpr int EXT_W = 32;
@@ -177,7 +179,7 @@ __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
 
 template <int W, int KIND, bool BWD>
 __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
-    softmin_kernel(SoftParams prm) {
+    __attribute__((amdgpu_waves_per_eu(BWD ? 4 : 1))) softmin_kernel(SoftParams prm) {
     constexpr int EXT_W = SoftTile<W, KIND, BWD>::EXT_W, EXT_H = SoftTile<W, KIND, BWD>::EXT_H;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
@@ -188,10 +190,12 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
     // planes of the aggregate sweeps, the (member, window) weights e with the
     // per-window sums, and (backward) the planes of the gradient propagation.  The
     // forward-only kernel keeps the angle part of each objective in e during its
-    // L2 sweep, so there e follows the planes instead of sharing their space.
+    // L2 sweep, so there e follows the planes instead of sharing their space; the
+    // DDF backward parks A in the same place during its L2 sweep.
     constexpr int NE = NW * TT, NWIN = BWD ? 8 * TT : 0;
-    constexpr int REGION = BWD ? (NPLANE * NT > NE + NWIN ? NPLANE * NT : NE + NWIN)
-                               : G * NT + NE;
+    constexpr int R0 = NPLANE * NT > NE + NWIN ? NPLANE * NT : NE + NWIN;
+    constexpr int RP = KIND == kDDF ? G * NT + NE : 0;  // planes + parked angle sums
+    constexpr int REGION = BWD ? (R0 > RP ? R0 : RP) : G * NT + NE;
     // One struct, in this order, so that the unguarded aggregate sweeps
     // (aggregates.h) read past the pixel arrays and before the planes inside it.
     struct Lds {
@@ -239,15 +243,23 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
     const float4 mraw = s_raw[tid];
     const MinimaxCoef no_coef{};
 
+    // Bit k of `rows` (`cols`): the window k rows above (columns left of) this
+    // extended position is an in-image window of the output tile.  Member u of the
+    // window c lies here iff both bits of u's row and column are set.
+    uint32_t rows = 0, cols = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int cy = ey - k, cx = ex - k;
+        if (cy >= 0 && cy < TH && ty0 + cy < M) rows |= 1u << k;
+        if (cx >= 0 && cx < TW && tx0 + cx < N) cols |= 1u << k;
+    }
+    const int cbase = ey * TW + ex;
     auto window_of = [&](int u, int& c) -> bool {
-        const int cy = ey - u / W, cx = ex - u % W;
-        if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) return false;
-        if (ty0 + cy >= M || tx0 + cx >= N) return false;
-        c = cy * TW + cx;
-        return true;
+        c = cbase - (u / W) * TW - u % W;
+        return ((rows >> (u / W)) & (cols >> (u % W)) & 1u) != 0;
     };
 
-    float A[NW], D[NW], Om[NW];
+    float A[NW], D[NW];
     const TilePix px{s_dir, s_raw, nullptr};
     // unguarded sweeps: only windows of the output tile (window_of) are used below
     member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, false, false>(
@@ -282,23 +294,37 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
                 s_e[u * TT + c] = __expf((key_value(s_key[c]) - s_e[u * TT + c]) * inv_tau);
         }
     } else {
-        if (KIND == kDDF)
+        if (KIND == kDDF) {
+            float* const s_park = s_buf + G * NT;
+#pragma unroll
+            for (int u = 0; u < NW; ++u) {
+                int c;
+                if (window_of(u, c)) s_park[u * TT + c] = A[u];
+            }
             member_aggregates<W, KIND, kExact, false, EXT_W, EXT_H, true, false>(
                 px, s_plane, ey, ex, tid, mdir, mraw, no_coef, D);
-        else
+#pragma unroll
+            for (int u = 0; u < NW; ++u) {
+                int c;
+                A[u] = window_of(u, c) ? s_park[u * TT + c] : 0.0f;
+            }
+        } else {
 #pragma unroll
             for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+        }
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
-            Om[u] = soft_objective<KIND>(A[u], D[u], p);
             int c;
-            if (window_of(u, c)) atomicMin(&s_key[c], order_key(Om[u]));
+            if (window_of(u, c))
+                atomicMin(&s_key[c], order_key(soft_objective<KIND>(A[u], D[u], p)));
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             int c;
-            if (window_of(u, c)) s_e[u * TT + c] = __expf((key_value(s_key[c]) - Om[u]) * inv_tau);
+            if (window_of(u, c))
+                s_e[u * TT + c] =
+                    __expf((key_value(s_key[c]) - soft_objective<KIND>(A[u], D[u], p)) * inv_tau);
         }
     }
     __syncthreads();
@@ -353,7 +379,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
             const float t = fmaf(mraw.x - w[1], w[4], fmaf(mraw.y - w[2], w[5], (mraw.z - w[3]) * w[6]));
             const float gom = -pi * t * inv_tau;
             float dA, dD;
-            objective_grad<KIND>(A[u], D[u], Om[u], p, dA, dD);
+            objective_grad<KIND>(A[u], D[u], soft_objective<KIND>(A[u], D[u], p), p, dA, dD);
             ga = gom * dA;
             gd = gom * dD;
         }

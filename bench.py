@@ -77,7 +77,7 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "c64926a746287bc73bf0f505aebfb158fc39cbee75ad4403a445666fb5b3c005"
+TRAFFIC_SRC_SHA256 = "781d286ecff8f6606068ce6bb63233928da4e068f797b24d19ef6f1561eb58ab"
 
 
 def forward_sources_sha256():

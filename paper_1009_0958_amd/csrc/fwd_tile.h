@@ -21,7 +21,8 @@ namespace odf {
 
 // LDS of one forward tile.  STAGE: the 5x5 DDF path parks the angle part of
 // every (window, member) objective in LDS during the L2 pass instead of
-// keeping 25 aggregates live in registers, which lets it use 1024-thread tiles.
+// keeping 25 aggregates live in registers, which lets it use 1024-thread tiles;
+// CWDDF^k parks its weighted angle sum the same way (50 aggregates).
 // NKEY: argmin keys per window (4 for ACWDDF: eq. 3 and three levels of eq. 9).
 // NPL: plane sets (2 when the angular and L2 terms are swept together).
 // U8: uint8 layout (pair_terms.h): no raw array, aux2 in inv for MINIMAX and
@@ -55,7 +56,7 @@ struct FwdShared {
 
 template <int W, int KIND, bool AGG>
 constexpr bool stage_angle_part() {
-    return W >= 5 && KIND == kDDF && !AGG;
+    return W >= 5 && (KIND == kDDF || KIND == kCW) && !AGG;
 }
 
 // 3x3 DDF and ACWDDF sweep the angular and L2 terms together (PASS 2 of
@@ -132,7 +133,19 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     else
         member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, false, centre_weighted(KIND),
                             false>(px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, A, cA);
-    if constexpr (stage_angle_part<W, KIND, AGG>()) {
+    if constexpr (stage_angle_part<W, KIND, AGG>() && KIND == kCW) {
+        // weighted angle sum A + (w_d(k) - 1) cA of each window -> LDS, then the
+        // L2 pass with its centre terms
+        const float w1 = prm.acw_wm1[0];
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int cy = ey - u / W, cx = ex - u % W;
+            if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
+            sh.stage[u * (TH * TW) + cy * TW + cx] = fmaf(w1, cA[u], A[u]);
+        }
+        member_aggregates_c<W, KIND, DIST, U8, EXT_W, EXT_H, true, true, false>(
+            px, s_plane, ey, ex, tid, mdir, mraw, prm.coef, D, cD);
+    } else if constexpr (stage_angle_part<W, KIND, AGG>()) {
         // angle part of each objective -> LDS, then the L2 pass
         const int mode = objective_mode<KIND>(prm.p);
         const float p = prm.p;
@@ -195,6 +208,18 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             prm.dbg_A[o] = A[u];
             if (prm.dbg_D) prm.dbg_D[o] = D[u];
             if (prm.dbg_O) prm.dbg_O[o] = objective_value<KIND>(A[u], D[u], prm.p);
+        }
+    } else if constexpr (stage_angle_part<W, KIND, AGG>() && KIND == kCW) {
+        // the staged weighted angle sum times the weighted L2 sum (the stage
+        // index stays in range as in the DDF loop below)
+        const float w1 = prm.acw_wm1[0];
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            if (!window_ok(u)) continue;
+            const int cy = ey - u / W, cx = ex - u % W;
+            const float o = sh.stage[u * (TH * TW) + cy * TW + cx] * fmaf(w1, cD[u], D[u]);
+            atomicMin(&s_key[key_slot(u)],
+                      ((unsigned long long)__float_as_uint(o) << 32) | (unsigned)u);
         }
     } else if constexpr (stage_angle_part<W, KIND, AGG>()) {
         // the staged angle part with D; one copy of the key loop per

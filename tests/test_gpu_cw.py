@@ -51,6 +51,22 @@ def test_float_and_edges(window):
                 _run(img.astype(np.float32), window, kind, level, EXACT)
 
 
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("window", [3, 5])
+def test_batch_with_zero_pixels(window, dist):
+    """Three images in one call, several tiles each with ragged edges, 5 % zero
+    pixels; uint8 and float32 (whose layout keeps the raw values beside the
+    directions), two levels of each filter."""
+    rng = np.random.default_rng(40 + 3 * window + dist)
+    imgs = synth.image_corr(3 * 45, 70, 0.2, key=41).reshape(3, 45, 70, 3)
+    imgs[rng.random((3, 45, 70)) < 0.05] = 0
+    d = (window * window + 1) // 2
+    for img in (imgs, imgs.astype(np.float32) / 255):
+        for kind in (odf.CWVMF, odf.CWDDF):
+            for level in (2, d // 2 + 1):
+                _run(img, window, kind, level, dist)
+
+
 def test_level_1_keeps_every_pixel():
     """The centre weighed n: the centre's colour wins every window (triangle
     inequality), so the output equals the input."""

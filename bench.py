@@ -77,7 +77,7 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
                    "pair_terms.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "781d286ecff8f6606068ce6bb63233928da4e068f797b24d19ef6f1561eb58ab"
+TRAFFIC_SRC_SHA256 = "06c54a4fcc805970c87de27832fb057c33ca7e1eeda85b45d81117963908f226"
 
 
 def forward_sources_sha256():

@@ -12,7 +12,9 @@ constexpr int kTileH[kNumTileConfigs] = {32, 16, 16, 8};
 
 // 5x5 ACWDDF keeps four register sets of n values per thread (aggregates
 // and centre terms of both passes) and 7x7 keeps a 13 x 7 grid of row sums:
-// 512-thread tiles only.
+// 512-thread tiles only.  The 5x5 centre-weighted filters share the rule (CWDDF
+// parks its weighted angle sums in LDS, which at 32 x 32 would not leave room
+// for a float32 tile's pixel arrays).
 bool tile_config_valid(int window, int kind, int cfg) {
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
     if ((window == 5 && centre_weighted(kind)) || window == 7)

@@ -76,8 +76,8 @@ def test_taller_than_65535_tiles():
     """A 1,000,000 x 2 frame, each kernel on a tile of at most 14 output rows, so that
     every grid has more than 65535 tile rows: 83334 for the 5 x 5 forward (32 x 16
     extended tile), 71429 and 166667 for the 3 x 3 forward on the 32 x 16 and 64 x 8
-    tiles, 71429 for the softmin, 250000 for the hard backward and the softmin's
-    combine pass."""
+    tiles, 71429 for the softmin, 125000 for the hard backward (64 x 8 tiles) and 250000
+    for the softmin's combine pass."""
     M, N = 1_000_000, 2
     img = synth.image_corr(M, N, 0.15, key=71)
     _forward(img, 5, BVDF, 0.0, EXACT)

@@ -51,20 +51,60 @@ struct NoiseParams {
     uint32_t key0, key1;
 };
 
+// Noise of one pixel (eq. 8): the Philox4x32-10 block of counter i decides
+// whether the pixel is hit, which channels change, and their random bytes.
+__device__ __forceinline__ void noise_pixel(const NoiseParams& prm, long long i, uint8_t& o0,
+                                            uint8_t& o1, uint8_t& o2) {
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)((unsigned long long)i >> 32), 0u, 0u};
+    philox4x32_10(c, prm.key0, prm.key1);
+    if ((uint64_t)c[0] < prm.t_hit) {
+        const uint64_t u1 = c[1];
+        const int pat = u1 < prm.t_pat[0] ? 0 : u1 < prm.t_pat[1] ? 1 : u1 < prm.t_pat[2] ? 2 : 3;
+        if (pat == 0 || pat == 3) o0 = (uint8_t)(c[2] & 0xffu);
+        if (pat == 1 || pat == 3) o1 = (uint8_t)((c[2] >> 8) & 0xffu);
+        if (pat == 2 || pat == 3) o2 = (uint8_t)((c[2] >> 16) & 0xffu);
+    }
+}
+
+// VEC: both buffers 4-byte aligned; a thread takes four pixels (twelve bytes,
+// three words) per step and the last npix % 4 pixels one by one.  Each pixel
+// keeps its own counter, so the output does not depend on the form.
+template <bool VEC>
 __global__ void __launch_bounds__(256) noise_kernel(NoiseParams prm) {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < prm.npix; i += stride) {
-        uint32_t c[4] = {(uint32_t)i, (uint32_t)((unsigned long long)i >> 32), 0u, 0u};
-        philox4x32_10(c, prm.key0, prm.key1);
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long first = 0;  // first pixel of the one-by-one loop
+    if (VEC) {
+        const long long nq = prm.npix / 4;
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(prm.clean);
+        uint32_t* d = reinterpret_cast<uint32_t*>(prm.noisy);
+        for (long long q = t0; q < nq; q += stride) {
+            uint32_t w[3] = {s[3 * q], s[3 * q + 1], s[3 * q + 2]};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                // pixel k holds bytes 3k .. 3k + 2 of the twelve (little-endian words)
+                uint8_t o[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    o[j] = (uint8_t)(w[(3 * k + j) / 4] >> (8 * ((3 * k + j) % 4)));
+                noise_pixel(prm, 4 * q + k, o[0], o[1], o[2]);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int sh = 8 * ((3 * k + j) % 4);
+                    uint32_t& v = w[(3 * k + j) / 4];
+                    v = (v & ~(0xffu << sh)) | ((uint32_t)o[j] << sh);
+                }
+            }
+            d[3 * q] = w[0];
+            d[3 * q + 1] = w[1];
+            d[3 * q + 2] = w[2];
+        }
+        first = nq * 4;
+    }
+    for (long long i = first + t0; i < prm.npix; i += stride) {
         const uint8_t* s = prm.clean + 3 * i;
         uint8_t o0 = s[0], o1 = s[1], o2 = s[2];
-        if ((uint64_t)c[0] < prm.t_hit) {
-            const uint64_t u1 = c[1];
-            const int pat = u1 < prm.t_pat[0] ? 0 : u1 < prm.t_pat[1] ? 1 : u1 < prm.t_pat[2] ? 2 : 3;
-            if (pat == 0 || pat == 3) o0 = (uint8_t)(c[2] & 0xffu);
-            if (pat == 1 || pat == 3) o1 = (uint8_t)((c[2] >> 8) & 0xffu);
-            if (pat == 2 || pat == 3) o2 = (uint8_t)((c[2] >> 16) & 0xffu);
-        }
+        noise_pixel(prm, i, o0, o1, o2);
         uint8_t* d = prm.noisy + 3 * i;
         d[0] = o0;
         d[1] = o1;
@@ -195,9 +235,17 @@ int odf_noise_eq8_u8(const uint8_t* clean, uint8_t* noisy, int B, int M, int N, 
     prm.t_pat[2] = odf::threshold32(phi_r + phi_g + phi_b);
     prm.key0 = (uint32_t)seed;
     prm.key1 = (uint32_t)(seed >> 32);
-    const long long blocks = std::min<long long>((npix + 255) / 256, 1 << 16);
-    hipLaunchKernelGGL(odf::noise_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), prm);
+    // four pixels per thread when both buffers are 4-byte aligned
+    const bool vec =
+        ((reinterpret_cast<uintptr_t>(clean) | reinterpret_cast<uintptr_t>(noisy)) & 3) == 0;
+    const long long work = vec ? (npix + 3) / 4 : npix;
+    const long long blocks = std::min<long long>((work + 255) / 256, 1 << 16);
+    if (vec)
+        hipLaunchKernelGGL(odf::noise_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), prm);
+    else
+        hipLaunchKernelGGL(odf::noise_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), prm);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(ODF_EHIP, "noise launch: %s", hipGetErrorString(e));
     return ODF_OK;

@@ -39,6 +39,22 @@ def test_noise_in_place_and_full_frame():
     assert np.array_equal(x.cpu().numpy()[0], onoise.noise_eq8(clean, 0.15, seed=77))
 
 
+def test_noise_unaligned_views():
+    """Buffers off 4-byte alignment take the pixel-by-pixel form (aligned ones
+    four pixels per thread); the noise is the same."""
+    clean = np.random.default_rng(9).integers(0, 256, (1, 37, 41, 3)).astype(np.uint8)
+    ref = onoise.noise_eq8(clean, 0.2, seed=11)
+    buf = torch.zeros(clean.size + 1, dtype=torch.uint8, device=DEV)
+    x = buf[1:].view(clean.shape)
+    x.copy_(_gpu(clean))
+    assert np.array_equal(odf.noise_eq8(x, 0.2, seed=11).cpu().numpy(), ref)
+    obuf = torch.zeros(clean.size + 2, dtype=torch.uint8, device=DEV)
+    out = obuf[2:].view(clean.shape)
+    odf.noise_eq8(_gpu(clean), 0.2, seed=11, out=out)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert np.array_equal(odf.noise_eq8(_gpu(clean), 0.2, seed=11).cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (2, 5, 7), (1, 64, 64), (4, 33, 48), (1, 1024, 1024)])
 def test_quality_matches_oracle(shape):
     print("case: quality shape=%s" % (shape,), flush=True)

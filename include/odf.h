@@ -22,6 +22,10 @@
  *     the message returned by odf_last_error() (per thread).
  *   - Sizes: B, M, N >= 1 and B*M*N < 2^31 pixels per call.
  *   - No C++ exception crosses this interface.
+ *   - Tests can make the allocating calls (odf_batch_plan, odf_autotune) take
+ *     their allocation-failure path: with the environment variable
+ *     ODF_TEST_FAIL_ALLOC set to anything but "" or "0" they return
+ *     ODF_ENOMEM before allocating or touching the device.
  */
 #ifndef ODF_H
 #define ODF_H
@@ -96,7 +100,13 @@ int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind,
  * Forward filter, float32 images: same contract as odf_filter_u8 with
  * img/out as B x M x N x 3 float32.  ODF_MINIMAX and ODF_RGB need
  * non-negative inputs (the cosine lies in [0, 1], Section 2.1; chromaticity
- * sums are positive, eq. 7); ODF_EXACT accepts any finite input.
+ * sums are positive, eq. 7); ODF_EXACT takes values of either sign.
+ * Domain: finite values with |x| <= 2^62.  The angle and chromaticity terms
+ * scale each pixel by a power of two first and hold for any such value; the
+ * L2 term of DDF squares raw channel differences in binary32, so larger
+ * values can overflow it, and pixels that differ by less than 2^-63 in every
+ * channel get their L2 distance from subnormal squares (fewer significant
+ * bits).  Nothing checks the values on the device.
  */
 int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, float p,
                    int dist, int q, float* out, uint8_t* idx, void* stream);
@@ -145,7 +155,8 @@ int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, 
  * of eq. 3); k = 1 weighs the centre n, which keeps the centre's colour.
  *   level  k in [1, (n+1)/2].
  *   img, out, idx as for odf_filter_u8; ties go to the lowest index.
- * Runs on the ACWDDF kernels (and their tile table entries); windows 3 and 5.
+ * Runs on the ACWDDF sweep, with tile table entries of its own (kind
+ * ODF_CWVMF or ODF_CWDDF in the tuning calls); windows 3 and 5.
  * Errors: as odf_filter_u8, plus ODF_EINVAL for kind or level out of range,
  * ODF_EUNSUPPORTED for window 7.
  */
@@ -342,9 +353,12 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * The forward kernels run one thread per pixel of an extended tile
  * (output tile plus halo).  Tile shapes are numbered 0..3; odf_tile_config
  * gives the extended width and height of one.  The process-wide table picks a
- * shape per (window, kind, dist, input type), kind ODF_BVDF, ODF_DDF or
- * ODF_ACWDDF; the default is shape 2 (32 x 16) for every class (5x5 ACWDDF
- * and 7x7 offer only the 512-thread shapes 2 and 3). */
+ * shape per (window, kind, dist, input type), kind any odf_kind (windows 3
+ * and 5 for ODF_ACWDDF, ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular
+ * term and keeps one entry for every dist); the default is shape 2
+ * (32 x 16) for every class (the 5x5 centre-weighted kinds and 7x7 offer only
+ * the 512-thread shapes 2 and 3).  The table is initialised once per process
+ * and each entry is read and written atomically. */
 int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */
@@ -353,7 +367,9 @@ int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /*
  * each, HIP events on `stream`), set the fastest in the table, store the
  * per-shape milliseconds in times_ms[4] (-1 for shapes not offered; nullable)
  * and append one JSON line to cache_path (nullable).  Allocates and frees
- * device memory and synchronises `stream`. */
+ * device memory and synchronises `stream`.  Errors: ODF_EINVAL (class or
+ * sizes out of range, M*N >= 2^28), ODF_ENOMEM (host or device allocation
+ * failed), ODF_EHIP. */
 int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
                  const char* cache_path, float* times_ms, void* stream);
 

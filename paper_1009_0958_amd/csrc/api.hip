@@ -2,6 +2,7 @@
 // dispatch to the kernels.  Declarations and contracts: include/odf.h.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "odf.h"
@@ -18,6 +19,10 @@ int set_error(int code, const char* fmt, ...) {
     vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
     return code;
+}
+bool test_fail_alloc() {
+    const char* v = getenv("ODF_TEST_FAIL_ALLOC");
+    return v && *v && strcmp(v, "0") != 0;
 }
 }  // namespace odf
 
@@ -166,9 +171,8 @@ int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, 
     prm.out = out;
     prm.idx = idx;
     for (int j = 0; j < 3; ++j) prm.acw_wm1[j] = (float)(n - 2 * level + 1);  // w_d(k) - 1
-    const int cfg = odf::tuned_config(window, ODF_ACWDDF, d, u8);
-    hipError_t e = odf::launch_forward(window, kind == ODF_CWVMF ? odf::kCWV : odf::kCW, d, u8,
-                                       false, cfg, prm,
+    const int cfg = odf::tuned_config(window, kind, d, u8);
+    hipError_t e = odf::launch_forward(window, odf::kernel_kind(kind), d, u8, false, cfg, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "centre-weighted filter launch");
     return ODF_OK;

@@ -327,7 +327,7 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
             }
         npix += (long long)j.M * j.N;
     }
-    odf_plan* p = new (std::nothrow) odf_plan;
+    odf_plan* p = odf::test_fail_alloc() ? nullptr : new (std::nothrow) odf_plan;
     if (!p) return bfail(ODF_ENOMEM, "plan allocation failed");
     for (int c = 0; c < odf::kNumClasses; ++c) p->class_tiles[c] = class_tiles[c];
     std::vector<odf::BatchTile> all;

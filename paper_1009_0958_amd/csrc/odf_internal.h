@@ -96,8 +96,11 @@ bool tile_config_valid(int window, int kind, int cfg);
 int tile_config_default(int window, int kind);
 void tile_config_shape(int cfg, int* ext_w, int* ext_h);
 constexpr int kNumTileShapes = 4;
+// Tile table entry of (window, kind, dist, input type), kind the C ABI's
+// odf_kind; kernel_kind maps an odf_kind to the kernels' Kind.
 int tuned_config(int window, int kind, int dist, bool u8);
 void set_tuned_config(int window, int kind, int dist, bool u8, int cfg);
+int kernel_kind(int kind);
 
 // Table 1 coefficients for degree q (zeros outside 2..4).
 MinimaxCoef minimax_coef(int q);
@@ -107,6 +110,12 @@ void set_acw_params(int window, int lambda, float T, FwdParams& prm);
 
 // Record the message returned by odf_last_error() on this thread; returns code.
 int set_error(int code, const char* fmt, ...);
+
+// Allocation-failure injection for tests: true when the environment variable
+// ODF_TEST_FAIL_ALLOC is set to anything but "" or "0".  The calls that
+// allocate (odf_batch_plan, odf_autotune) then take their allocation-failure
+// path (ODF_ENOMEM) before allocating or touching the device.
+bool test_fail_alloc();
 
 struct SoftParams {
     const float* x;   // B x M x N x 3

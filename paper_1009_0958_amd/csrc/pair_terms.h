@@ -167,8 +167,14 @@ __device__ __forceinline__ float aux_mag(float w) {
 // pi/2 - atan(r); one reciprocal square root per pair.
 // |a x b|^2.  uint8 (U8): Lagrange's identity |a|^2 |b|^2 - (a.b)^2 in
 // binary64, exact (every operand an integer below 2^53), from the squared
-// direction norms na, nb and the dot product; otherwise the sum of the squared
-// cross components.
+// direction norms na, nb and the dot product.  Float directions: the cross
+// product in binary64, where the products of binary32 components are exact,
+// so each component is the exact difference rounded once (a multiply-add of
+// one exact product and the other gives the same value) and swapping a and b
+// negates it exactly; its squared norm is rounded to binary32 once.  In
+// binary32 the components of a nearly parallel pair would cancel to
+// |a| |b| sin(theta) with an absolute error of about 2^-24 |a| |b|, a
+// relative error of 2^-24 / theta in the angle.
 template <bool U8>
 __device__ __forceinline__ float cross_norm2(const float4& a, const float4& b, float na, float nb,
                                              float dot) {
@@ -176,10 +182,11 @@ __device__ __forceinline__ float cross_norm2(const float4& a, const float4& b, f
         const double d = (double)dot;
         return (float)fma(-d, d, (double)na * (double)nb);
     } else {
-        float c0 = cross_diff<U8>(a.y, b.z, a.z, b.y);
-        float c1 = cross_diff<U8>(a.z, b.x, a.x, b.z);
-        float c2 = cross_diff<U8>(a.x, b.y, a.y, b.x);
-        return fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
+        const double a0 = a.x, a1 = a.y, a2 = a.z, b0 = b.x, b1 = b.y, b2 = b.z;
+        const double c0 = fma(a1, b2, -(a2 * b1));
+        const double c1 = fma(a2, b0, -(a0 * b2));
+        const double c2 = fma(a0, b1, -(a1 * b0));
+        return (float)fma(c0, c0, fma(c1, c1, c2 * c2));
     }
 }
 
@@ -246,15 +253,41 @@ __device__ __forceinline__ float angle_minimax(const float4& a, const float4& ra
     return angle_minimax_from_dot<U8>(a, ra.w, b, rb.w, dot3(a, b), cf);
 }
 
+// Chromaticity numerators a_k sum(b) - b_k sum(a) of float directions, in
+// binary64: the channel sums of three binary32 values are exact there (the
+// direction is scaled into [1, 2), so a component more than 2^29 below the
+// largest is the only case that rounds, at 2^-53), and so are the products
+// (24 x at most 27 significant bits); each numerator is then rounded once.
+// Rounded binary32 sums and products would leave an absolute error of about
+// 2^-24 |a| |b| in a numerator that cancels to |a| |b| B for nearly equal
+// chromaticities, i.e. a relative error of 2^-24 / B in B.  The two products
+// are rounded separately (no contraction), so swapping a and b negates every
+// numerator exactly and the pair term stays bitwise symmetric.
+__device__ __forceinline__ float chroma_num2_f64(const float4& a, const float4& b) {
+#pragma clang fp contract(off)
+    const double a0 = a.x, a1 = a.y, a2 = a.z, b0 = b.x, b1 = b.y, b2 = b.z;
+    const double sa = (a0 + a1) + a2, sb = (b0 + b1) + b2;
+    const float n0 = (float)(a0 * sb - b0 * sa);
+    const float n1 = (float)(a1 * sb - b1 * sa);
+    const float n2 = (float)(a2 * sb - b2 * sa);
+    return fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+}
+
 // Method 2 (Section 2.2, eq. 7): L2 distance of chromaticities
 // |a / sum a - b / sum b| = |a sum b - b sum a| / (sum a sum b).
 template <int KIND, bool U8>
 __device__ __forceinline__ float chroma_term(const float4& a, float ia, const float4& b, float ib) {
-    const float sa = aux_mag<U8>(a.w), sb = aux_mag<U8>(b.w);
-    float n0 = cross_diff<U8>(a.x, sb, b.x, sa);
-    float n1 = cross_diff<U8>(a.y, sb, b.y, sa);
-    float n2 = cross_diff<U8>(a.z, sb, b.z, sa);
-    float Nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+    float Nn;
+    if constexpr (U8) {
+        // integer numerators, exact in binary32 (cross_diff)
+        const float sa = aux_mag<U8>(a.w), sb = aux_mag<U8>(b.w);
+        float n0 = cross_diff<U8>(a.x, sb, b.x, sa);
+        float n1 = cross_diff<U8>(a.y, sb, b.y, sa);
+        float n2 = cross_diff<U8>(a.z, sb, b.z, sa);
+        Nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+    } else {
+        Nn = chroma_num2_f64(a, b);
+    }
     float B = sqrt_raw(Nn) * (ia * ib);
     if (KIND != kBVDF) B = fmaf(kEq10Alpha, B, kEq10Beta);  // eq. (10), Experiment 2
     return B;

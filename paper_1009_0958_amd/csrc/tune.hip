@@ -6,6 +6,7 @@
 // a small JSON cache keyed by the GPU architecture; odf_tune_load reads such a
 // cache back.  The table is process-wide; updates are atomic per entry.
 #include <atomic>
+#include <mutex>
 #include <stdio.h>
 #include <string.h>
 
@@ -18,34 +19,49 @@ namespace odf {
 
 namespace {
 
-// [window 3/5/7][kind BVDF/DDF/ACWDDF][dist][u8]
-std::atomic<int> g_table[3][3][3][2];
+// [window 3/5/7][kind ODF_BVDF .. ODF_CWDDF][dist][u8]
+constexpr int kTableKinds = 5;
+std::atomic<int> g_table[3][kTableKinds][3][2];
+std::once_flag g_table_once;
 
 int window_slot(int window) { return window == 3 ? 0 : (window == 5 ? 1 : 2); }
-std::atomic<bool> g_table_init{false};
+
+// The centre-weighted vector median has no angular term: its kernel runs the
+// chromaticity layout whatever dist the caller names, so every dist shares
+// one entry.
+int dist_slot(int kind, int dist) { return kind == ODF_CWVMF ? (int)kRgb : dist; }
 
 void ensure_init() {
-    bool expect = false;
-    if (!g_table_init.load()) {
+    std::call_once(g_table_once, [] {
         for (int w = 0; w < 3; ++w)
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < kTableKinds; ++k)
                 for (int d = 0; d < 3; ++d)
                     for (int u = 0; u < 2; ++u)
                         g_table[w][k][d][u].store(tile_config_default(3 + 2 * w, k));
-        g_table_init.compare_exchange_strong(expect, true);
-    }
+    });
 }
 
 }  // namespace
 
+// kind: the C ABI's odf_kind (ODF_BVDF .. ODF_CWDDF)
 int tuned_config(int window, int kind, int dist, bool u8) {
     ensure_init();
-    return g_table[window_slot(window)][kind][dist][u8 ? 1 : 0].load();
+    return g_table[window_slot(window)][kind][dist_slot(kind, dist)][u8 ? 1 : 0].load();
 }
 
 void set_tuned_config(int window, int kind, int dist, bool u8, int cfg) {
     ensure_init();
-    g_table[window_slot(window)][kind][dist][u8 ? 1 : 0].store(cfg);
+    g_table[window_slot(window)][kind][dist_slot(kind, dist)][u8 ? 1 : 0].store(cfg);
+}
+
+// The kernel family of a C ABI kind.
+int kernel_kind(int kind) {
+    switch (kind) {
+    case ODF_ACWDDF: return kACW;
+    case ODF_CWVMF: return kCWV;
+    case ODF_CWDDF: return kCW;
+    default: return kind;  // ODF_BVDF, ODF_DDF
+    }
 }
 
 }  // namespace odf
@@ -60,11 +76,12 @@ uint64_t splitmix(uint64_t& s) {
     return z ^ (z >> 31);
 }
 
-// A (window, kind, dist) class the library computes (7x7 ACWDDF is not).
+// A (window, kind, dist) class the library computes (the centre-weighted
+// kinds have no 7x7 kernels).
 bool valid_class(int window, int kind, int dist) {
     if (window != 3 && window != 5 && window != 7) return false;
-    if (kind != ODF_BVDF && kind != ODF_DDF && kind != ODF_ACWDDF) return false;
-    if (window == 7 && kind == ODF_ACWDDF) return false;
+    if (kind < ODF_BVDF || kind > ODF_CWDDF) return false;
+    if (window == 7 && kind != ODF_BVDF && kind != ODF_DDF) return false;
     return dist >= 0 && dist <= 2;
 }
 
@@ -84,7 +101,8 @@ int odf_tune_get(int window, int kind, int dist, int is_u8) {
 }
 
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
-    if (!valid_class(window, kind, dist) || !odf::tile_config_valid(window, kind, config))
+    if (!valid_class(window, kind, dist) ||
+        !odf::tile_config_valid(window, odf::kernel_kind(kind), config))
         return ODF_EINVAL;
     odf::set_tuned_config(window, kind, dist, is_u8 != 0, config);
     return ODF_OK;
@@ -96,10 +114,18 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
         (long long)M * N >= (1ll << 28))
         return odf::set_error(ODF_EINVAL, "autotune: arguments out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int kk = odf::kernel_kind(kind);
+    const int kd = kind == ODF_CWVMF ? ODF_RGB : dist;  // the kernel's pair term
     const size_t npix = (size_t)M * N;
     const size_t esz = is_u8 ? 1 : 4;
-    std::vector<uint8_t> h8(npix * 3);
-    std::vector<float> hf(is_u8 ? 0 : npix * 3);
+    std::vector<uint8_t> h8;
+    std::vector<float> hf;
+    try {  // no exception crosses the C ABI
+        h8.resize(npix * 3);
+        hf.resize(is_u8 ? 0 : npix * 3);
+    } catch (...) {
+        return odf::set_error(ODF_ENOMEM, "autotune: host allocation failed");
+    }
     uint64_t seed = 1009;
     for (size_t i = 0; i < npix * 3; ++i) {
         h8[i] = (uint8_t)(splitmix(seed) >> 56);
@@ -112,9 +138,9 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     int best = -1;
     float best_ms = 0.0f;
     float ms_all[odf::kNumTileShapes];
-    if (hipMalloc(&img, npix * 3 * esz) != hipSuccess || hipMalloc(&out, npix * 3 * esz) != hipSuccess ||
-        hipMalloc(&idx, npix) != hipSuccess) {
-        rc = ODF_ENOMEM;
+    if (odf::test_fail_alloc() || hipMalloc(&img, npix * 3 * esz) != hipSuccess ||
+        hipMalloc(&out, npix * 3 * esz) != hipSuccess || hipMalloc(&idx, npix) != hipSuccess) {
+        rc = odf::set_error(ODF_ENOMEM, "autotune: device allocation failed");
         goto done;
     }
     if (hipMemcpy(img, is_u8 ? (const void*)h8.data() : (const void*)hf.data(), npix * 3 * esz,
@@ -125,21 +151,23 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     }
     for (int cfg = 0; cfg < odf::kNumTileShapes; ++cfg) {
         ms_all[cfg] = -1.0f;
-        if (!odf::tile_config_valid(window, kind, cfg)) continue;
+        if (!odf::tile_config_valid(window, kk, cfg)) continue;
         odf::FwdParams prm{};
         prm.img = img; prm.out = out; prm.idx = idx;
         prm.B = 1; prm.M = M; prm.N = N;
-        prm.p = kind == ODF_DDF ? 0.25f : (kind == ODF_ACWDDF ? 0.5f : 0.0f);
-        if (dist == ODF_MINIMAX) prm.coef = odf::minimax_coef(4);  // timing does not depend on q
+        prm.p = kind == ODF_DDF ? 0.25f : (kind == ODF_BVDF ? 0.0f : 0.5f);
+        if (kd == ODF_MINIMAX) prm.coef = odf::minimax_coef(4);  // timing does not depend on q
         if (kind == ODF_ACWDDF) odf::set_acw_params(window, 2, 10.8f, prm);
+        if (kind == ODF_CWVMF || kind == ODF_CWDDF)  // level 2: centre weight n - 2
+            for (int j = 0; j < 3; ++j) prm.acw_wm1[j] = (float)(window * window - 3);
         for (int w = 0; w < 2; ++w)
-            if (odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s) != hipSuccess) {
+            if (odf::launch_forward(window, kk, kd, is_u8 != 0, false, cfg, prm, s) != hipSuccess) {
                 rc = ODF_EHIP;
                 goto done;
             }
         bool ok = hipEventRecord(e0, s) == hipSuccess;
         for (int r = 0; r < reps; ++r)
-            ok = ok && odf::launch_forward(window, kind, dist, is_u8 != 0, false, cfg, prm, s) ==
+            ok = ok && odf::launch_forward(window, kk, kd, is_u8 != 0, false, cfg, prm, s) ==
                            hipSuccess;
         ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.0f;
@@ -179,9 +207,9 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(img);
-    (void)hipFree(out);
-    (void)hipFree(idx);
+    if (img) (void)hipFree(img);
+    if (out) (void)hipFree(out);
+    if (idx) (void)hipFree(idx);
     return best >= 0 || rc != ODF_OK ? rc : ODF_EHIP;
 }
 

@@ -124,24 +124,65 @@ def _check_tensor(t, name):
         raise ValueError("%s must be contiguous" % name)
 
 
+def check_outputs(img, out, idx):
+    """Check caller-supplied outputs of a forward call on ``img`` ((M, N, 3) or
+    (B, M, N, 3)) before their pointers go to the kernel, which writes B*M*N*3
+    elements of out and B*M*N bytes of idx: out must have img's dtype, device
+    and shape (or the batched shape), idx must be uint8 on img's device with
+    B*M*N elements; both contiguous.  Raises ValueError."""
+    x, _ = _as_batch(img)
+    B, M, N, _ = x.shape
+    if out is not None:
+        if not isinstance(out, torch.Tensor) or out.dtype != x.dtype:
+            raise ValueError("out must be a %s tensor like img" % x.dtype)
+        if out.device != x.device:
+            raise ValueError("out must be on the device of img (%s)" % x.device)
+        if tuple(out.shape) not in (tuple(img.shape), tuple(x.shape)):
+            raise ValueError("out must have the shape of img %s, not %s"
+                             % (tuple(img.shape), tuple(out.shape)))
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
+    if idx is not None:
+        if not isinstance(idx, torch.Tensor) or idx.dtype != torch.uint8:
+            raise ValueError("idx must be a uint8 tensor")
+        if idx.device != x.device:
+            raise ValueError("idx must be on the device of img (%s)" % x.device)
+        if idx.numel() != B * M * N:
+            raise ValueError("idx must have B*M*N = %d elements, not %d" % (B * M * N, idx.numel()))
+        if not idx.is_contiguous():
+            raise ValueError("idx must be contiguous")
+
+
+def _forward_outputs(img, x, squeeze, out, idx, return_idx):
+    """(out, idx) to hand to the kernel (batched views) and (out, idx) to return:
+    the caller's own tensors when given, else new ones (unbatched when img is)."""
+    check_outputs(img, out, idx)
+    B, M, N, _ = x.shape
+    if out is None:
+        out_k = torch.empty_like(x)
+        out_r = out_k[0] if squeeze else out_k
+    else:
+        out_k, out_r = out, out
+    if idx is None and return_idx:
+        idx_k = torch.empty((B, M, N), dtype=torch.uint8, device=x.device)
+        idx_r = idx_k[0] if squeeze else idx_k
+    else:
+        idx_k, idx_r = idx, idx
+    return out_k, idx_k, out_r, idx_r
+
+
 def filter(img, window=3, kind=BVDF, p=0.5, dist=EXACT, q=4, out=None, idx=None,
            return_idx=True):
     """Forward filter.  Returns (out, idx) (idx None unless ``return_idx``)."""
     x, squeeze = _as_batch(img)
     _check_tensor(x, "img")
     B, M, N, _ = x.shape
-    if out is None:
-        out = torch.empty_like(x)
-    if idx is None and return_idx:
-        idx = torch.empty((B, M, N), dtype=torch.uint8, device=x.device)
-    fn = lib().odf_filter_u8 if x.dtype == torch.uint8 else lib().odf_filter_f32
     if x.dtype not in (torch.uint8, torch.float32):
         raise ValueError("img must be uint8 or float32")
-    _check(fn(_ptr(x), B, M, N, window, _kind(kind), float(p), _dist(dist), q, _ptr(out),
-              _ptr(idx), _stream(x.device)))
-    if squeeze:
-        out = out[0]
-        idx = None if idx is None else idx[0]
+    out_k, idx_k, out, idx = _forward_outputs(img, x, squeeze, out, idx, return_idx)
+    fn = lib().odf_filter_u8 if x.dtype == torch.uint8 else lib().odf_filter_f32
+    _check(fn(_ptr(x), B, M, N, window, _kind(kind), float(p), _dist(dist), q, _ptr(out_k),
+              _ptr(idx_k), _stream(x.device)))
     return out, idx
 
 
@@ -155,16 +196,10 @@ def acwddf(img, window=3, dist=EXACT, q=4, lam=2, T=10.8, out=None, idx=None,
     B, M, N, _ = x.shape
     if x.dtype not in (torch.uint8, torch.float32):
         raise ValueError("img must be uint8 or float32")
-    if out is None:
-        out = torch.empty_like(x)
-    if idx is None and return_idx:
-        idx = torch.empty((B, M, N), dtype=torch.uint8, device=x.device)
+    out_k, idx_k, out, idx = _forward_outputs(img, x, squeeze, out, idx, return_idx)
     fn = lib().odf_acwddf_u8 if x.dtype == torch.uint8 else lib().odf_acwddf_f32
-    _check(fn(_ptr(x), B, M, N, window, _dist(dist), q, int(lam), float(T), _ptr(out), _ptr(idx),
-              _stream(x.device)))
-    if squeeze:
-        out = out[0]
-        idx = None if idx is None else idx[0]
+    _check(fn(_ptr(x), B, M, N, window, _dist(dist), q, int(lam), float(T), _ptr(out_k),
+              _ptr(idx_k), _stream(x.device)))
     return out, idx
 
 
@@ -178,16 +213,10 @@ def cw_filter(img, window=3, kind=CWVMF, level=1, dist=EXACT, q=4, out=None, idx
     B, M, N, _ = x.shape
     if x.dtype not in (torch.uint8, torch.float32):
         raise ValueError("img must be uint8 or float32")
-    if out is None:
-        out = torch.empty_like(x)
-    if idx is None and return_idx:
-        idx = torch.empty((B, M, N), dtype=torch.uint8, device=x.device)
+    out_k, idx_k, out, idx = _forward_outputs(img, x, squeeze, out, idx, return_idx)
     fn = lib().odf_cw_filter_u8 if x.dtype == torch.uint8 else lib().odf_cw_filter_f32
-    _check(fn(_ptr(x), B, M, N, window, _kind(kind), _dist(dist), q, int(level), _ptr(out),
-              _ptr(idx), _stream(x.device)))
-    if squeeze:
-        out = out[0]
-        idx = None if idx is None else idx[0]
+    _check(fn(_ptr(x), B, M, N, window, _kind(kind), _dist(dist), q, int(level), _ptr(out_k),
+              _ptr(idx_k), _stream(x.device)))
     return out, idx
 
 

@@ -139,7 +139,7 @@ def test_acwddf_tuning_table():
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 0) == odf.EINVAL  # 1024-thread shape not offered
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 3) == odf.OK
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 2) == odf.OK
-    assert L.odf_tune_get(3, 3, 0, 1) == odf.EINVAL
+    assert L.odf_tune_get(3, 5, 0, 1) == odf.EINVAL  # kinds end at ODF_CWDDF
     assert L.odf_tune_get(7, odf.ACWDDF, 0, 1) == odf.EINVAL  # no 7x7 ACWDDF
     assert L.odf_tune_get(7, odf.DDF, 0, 1) == 2
     assert L.odf_tune_set(7, odf.DDF, 0, 1, 1) == odf.EINVAL  # 512-thread shapes only
@@ -215,3 +215,78 @@ def test_cw_filter_rejects():
     assert f(3, odf.CWDDF, 1, dist=3) == odf.EINVAL and "dist" in odf.last_error()
     assert f(3, odf.CWVMF, 1, out=None) == odf.EINVAL and "out" in odf.last_error()
     assert f(3, odf.CWVMF, 1, out=FAKE) == odf.EINVAL and "overlaps" in odf.last_error()
+
+
+def test_binding_checks_caller_outputs():
+    """Caller-supplied out / idx are checked before their pointers reach the
+    kernel (which writes B*M*N*3 elements of out and B*M*N bytes of idx)."""
+    import torch
+    img = torch.zeros((2, 5, 7, 3), dtype=torch.uint8)
+    ok_out = torch.empty_like(img)
+    ok_idx = torch.empty((2, 5, 7), dtype=torch.uint8)
+    odf.check_outputs(img, ok_out, ok_idx)
+    odf.check_outputs(img, None, ok_idx.reshape(-1))  # any shape with B*M*N elements
+    odf.check_outputs(img[0], torch.empty((5, 7, 3), dtype=torch.uint8), None)
+    odf.check_outputs(img[0], torch.empty((1, 5, 7, 3), dtype=torch.uint8), None)
+    bad = [
+        (torch.empty((2, 5, 6, 3), dtype=torch.uint8), None, "shape"),
+        (torch.empty((5, 7, 3), dtype=torch.uint8), None, "shape"),  # 3-D out for a batch
+        (torch.empty((2, 5, 7, 3), dtype=torch.float32), None, "tensor like img"),
+        (torch.empty((2, 7, 5, 3), dtype=torch.uint8).transpose(1, 2), None, "contiguous"),
+        (None, torch.empty((2, 5, 6), dtype=torch.uint8), "elements"),
+        (None, torch.empty((2, 5, 7), dtype=torch.int64), "uint8"),
+        (None, torch.empty((2, 7, 5), dtype=torch.uint8).transpose(1, 2), "contiguous"),
+    ]
+    for out, idx, text in bad:
+        with pytest.raises(ValueError, match=text):
+            odf.check_outputs(img, out, idx)
+    fimg = torch.zeros((5, 7, 3), dtype=torch.float32)
+    with pytest.raises(ValueError, match="tensor like img"):
+        odf.check_outputs(fimg, torch.empty((5, 7, 3), dtype=torch.uint8), None)
+    if torch.cuda.is_available():  # device mismatch needs a second device type
+        with pytest.raises(ValueError, match="device"):
+            odf.check_outputs(img.cuda(), ok_out, None)
+
+
+def test_allocation_failure_reports_enomem(monkeypatch):
+    """ODF_TEST_FAIL_ALLOC makes the allocating calls take their allocation-failure
+    path: ODF_ENOMEM with a message, nothing allocated, no device touched."""
+    import ctypes as ct
+    L = odf._batch_lib()
+    jobs = (_Job * 2)()
+    jobs[0] = _Job(0x7F0000000000, 0x7F0000100000, 0, 40, 50, 3, 1, 0, 4, 0.25)
+    jobs[1] = _Job(0x7F0000200000, 0x7F0000300000, 0, 20, 30, 5, 0, 2, 4, 0.0)
+    monkeypatch.setenv("ODF_TEST_FAIL_ALLOC", "1")
+    plan = ct.c_void_p()
+    rc = L.odf_batch_plan(ct.cast(jobs, ct.c_void_p), 2, ct.byref(plan), None)
+    assert rc == odf.ENOMEM and "allocation" in odf.last_error() and not plan.value
+    times = (ct.c_float * 4)()
+    for w, kind, dist, u8 in ((3, odf.DDF, odf.EXACT, 1), (5, odf.CWVMF, odf.EXACT, 0),
+                              (7, odf.BVDF, odf.RGB, 1)):
+        rc = L.odf_autotune(w, kind, dist, u8, 64, 64, 2, None, ct.cast(times, ct.c_void_p), None)
+        assert rc == odf.ENOMEM and "allocation" in odf.last_error()
+    # validation still comes first
+    rc = L.odf_autotune(9, odf.DDF, odf.EXACT, 1, 64, 64, 2, None, None, None)
+    assert rc == odf.EINVAL
+    monkeypatch.setenv("ODF_TEST_FAIL_ALLOC", "0")
+    bad = (_Job * 1)()
+    bad[0] = _Job(0, 0x7F0000100000, 0, 40, 50, 3, 1, 0, 4, 0.25)
+    assert L.odf_batch_plan(ct.cast(bad, ct.c_void_p), 1, ct.byref(plan), None) == odf.EINVAL
+
+
+def test_tuning_table_has_centre_weighted_entries():
+    """CWVMF^k and CWDDF^k have tile table entries of their own (5x5: the
+    512-thread shapes only; no 7x7); CWVMF, which has no angular term, keeps
+    one entry for every dist."""
+    L = odf._batch_lib()
+    for kind in (odf.CWVMF, odf.CWDDF):
+        assert odf.tune_get(3, kind, odf.EXACT) == 2
+        assert L.odf_tune_get(7, kind, odf.EXACT, 1) == odf.EINVAL
+        assert L.odf_tune_set(5, kind, odf.EXACT, 1, 0) == odf.EINVAL  # 1024 threads
+    odf.tune_set(3, odf.CWDDF, odf.RGB, True, 1)
+    assert odf.tune_get(3, odf.CWDDF, odf.RGB) == 1
+    assert odf.tune_get(3, odf.ACWDDF, odf.RGB) == 2  # a slot of its own
+    odf.tune_set(5, odf.CWVMF, odf.MINIMAX, True, 3)
+    assert odf.tune_get(5, odf.CWVMF, odf.EXACT) == 3
+    odf.tune_set(3, odf.CWDDF, odf.RGB, True, 2)
+    odf.tune_set(5, odf.CWVMF, odf.RGB, True, 2)

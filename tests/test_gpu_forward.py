@@ -91,12 +91,26 @@ def test_float_inputs_exact(window, kind, p):
 @pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25)])
 def test_float_inputs_minimax_rgb(window, dist, kind, p):
     """float32 inputs (non-negative, as minimax and the chromaticity term need)
-    with the two fast pair terms; every window size, both kinds.  The
-    chromaticity numerators of float pixels are differences of rounded
-    products, accurate to ~1e-4 relative for nearly equal chromaticities, so
-    its aggregates are held to that bound (selections to the near-tie band)."""
+    with the two fast pair terms; every window size, both kinds: selections to
+    the near-tie band, aggregates within 1e-5 relative (the chromaticity
+    numerators and cross products of float pixels are formed in binary64)."""
     img = synth.float_batch(2, 41, 66, 0.1, key=40 + window + dist)
-    run_and_check(img, window, kind, p, dist, agg_rtol=1e-4 if dist == RGB else AGG_RTOL)
+    run_and_check(img, window, kind, p, dist)
+
+
+@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25)])
+def test_float_nearly_parallel(window, dist, kind, p):
+    """Nearly parallel float colours (a grey level with perturbations of 1e-3,
+    angles and chromaticity distances of ~1e-3): the cross products and
+    chromaticity numerators cancel to ~1e-3 of their operands, where binary32
+    differences of rounded products would leave ~3e-5 relative error per term;
+    aggregates must still be within 1e-5 of the oracle."""
+    rng = np.random.default_rng(61 + window + 3 * dist)
+    img = (0.5 + rng.uniform(-1e-3, 1e-3, (2, 37, 45, 3))).astype(np.float32)
+    img[:, 5:9, 7:12] *= np.float32(1.75)  # collinear block: same angles, other L2 terms
+    run_and_check(img, window, kind, p, dist)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (30, 30), (31, 29), (28, 28),
@@ -156,9 +170,8 @@ def test_sparse_zero_pixels(window, dist, u8):
     img = _sparse_zeros(70, 97, key=window * 3 + dist)
     if not u8:
         img = img.astype(np.float32) / 255
-    tol = 1e-4 if (dist == RGB and not u8) else AGG_RTOL
     for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 1.0)):
-        run_and_check(img, window, kind, p, dist, aggregates=window < 7, agg_rtol=tol)
+        run_and_check(img, window, kind, p, dist, aggregates=window < 7)
 
 
 # 3x3 pattern whose colour X (twice) minimises every objective of a window holding it
@@ -215,6 +228,39 @@ def test_float_power_of_two_scaling_bit_exact():
             assert torch.equal(i1, i2)
         else:  # D scales by 8: the objective gains a constant log2 term
             assert (i1 != i2).float().mean().item() < 1e-3
+
+
+@pytest.mark.parametrize("scale_exp", [61, -30])
+def test_float_domain_edges(scale_exp):
+    """Near both ends of the documented float32 domain (values up to 2^61; and
+    scaled by 2^-30, where the L2 distances of distinct pixels stay far above the
+    2^-63 below which their squares turn subnormal) the filter still meets the
+    parity contract: selections to the near-tie band, A, D and Omega within
+    1e-5 of the oracle."""
+    img = synth.float_batch(1, 34, 41, 0.1, key=30) * np.float32(2.0 ** scale_exp)
+    for window, kind, p, dist in ((5, DDF, 0.25, EXACT), (3, DDF, 0.5, EXACT), (3, DDF, 0.3, EXACT),
+                                  (3, DDF, 1.0, MINIMAX), (5, DDF, 0.25, RGB), (3, BVDF, 0.0, EXACT)):
+        run_and_check(img, window, kind, p, dist)
+
+
+def test_caller_outputs_are_used_and_returned():
+    img = synth.image_corr(33, 40, 0.2, key=3)
+    x = _gpu(img)
+    ref_o, ref_i = odf.filter(x, 3, DDF, 0.25, EXACT)
+    out = torch.empty_like(x)
+    idx = torch.empty((33, 40), dtype=torch.uint8, device=DEV)
+    o, i = odf.filter(x, 3, DDF, 0.25, EXACT, out=out, idx=idx)
+    assert o is out and i is idx
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref_o) and torch.equal(idx, ref_i)
+    xb = x[None]
+    ob = torch.empty_like(xb)
+    o, i = odf.acwddf(xb, 3, EXACT, 4, 2, 10.8, out=ob, return_idx=False)
+    assert o is ob and i is None
+    for bad in (dict(out=out[:, :20]), dict(out=torch.empty_like(x, dtype=torch.float32)),
+                dict(idx=idx[:20]), dict(out=torch.empty((1, 33, 40, 3), dtype=torch.uint8))):
+        with pytest.raises(ValueError):
+            odf.filter(x, 3, DDF, 0.25, EXACT, **bad)
 
 
 def test_deterministic_repeat():

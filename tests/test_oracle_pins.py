@@ -396,6 +396,32 @@ def test_collinear_window_selects_first_member():
 
 # ------------------------------------------------------------ hard backward
 
+@pytest.mark.parametrize("w,kind,p,dist", [(3, DDF, 0.25, EXACT), (5, BVDF, 0.0, MINIMAX),
+                                           (7, DDF, 0.5, RGB), (5, DDF, 0.3, EXACT)])
+def test_filter_at_matches_full_filter(w, kind, p, dist):
+    """filter_at (the sampled form the full-size parity tests and the benchmark's
+    mismatch counts use) returns, at each listed flat position (b*M + r)*N + c,
+    exactly what the full filter computes there: the decode of b, r, c and the
+    packing of out, idx, A, D and Omega, in list order (repeats and borders
+    included)."""
+    rng = np.random.default_rng(50 + w)
+    x = rng.integers(0, 256, (3, 11, 13, 3)).astype(np.float64)
+    x[rng.random((3, 11, 13)) < 0.1] = 0
+    out, idx, A, D, O = oracle.filter(x, w, kind, p, dist, aggregates=True)
+    B, M, N = idx.shape
+    corners = [(b * M + r) * N + c for b in (0, B - 1) for r in (0, M - 1) for c in (0, N - 1)]
+    pix = np.concatenate([rng.permutation(B * M * N)[:120], corners, [7, 7, B * M * N - 1]])
+    o2, i2, A2, D2, O2 = oracle.filter_at(x, pix, w, kind, p, dist)
+    n = w * w
+    assert np.array_equal(o2, out.reshape(-1, 3)[pix])
+    assert np.array_equal(i2, idx.reshape(-1)[pix])
+    for got, full in ((A2, A), (D2, D), (O2, O)):
+        assert np.array_equal(got, full.reshape(-1, n)[pix])
+    for bad in ([-1], [B * M * N]):
+        with pytest.raises(ValueError):
+            oracle.filter_at(x, bad, w, kind, p, dist)
+
+
 def test_backward_hard_routes_and_conserves():
     rng = np.random.default_rng(2)
     img = _tiny_image(13, 12, 10)
@@ -428,8 +454,8 @@ def _float_tiny(seed, M, N):
 
 
 @pytest.mark.parametrize("w,kind,p,tau", [(3, BVDF, 0.0, 0.1), (3, DDF, 0.25, 0.1),
-                                          (5, DDF, 0.25, 0.1), (3, DDF, 0.5, 0.01),
-                                          (5, BVDF, 0.0, 0.01)])
+                                          (5, DDF, 0.25, 0.1), (5, DDF, 0.25, 0.01),
+                                          (3, DDF, 0.5, 0.01), (5, BVDF, 0.0, 0.01)])
 def test_softmin_gradient_vs_central_differences(w, kind, p, tau):
     x = _float_tiny(21 + w, 5, 6)
     rng = np.random.default_rng(3)

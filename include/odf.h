@@ -227,6 +227,24 @@ int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, in
                         void* stream);
 
 /*
+ * odf_softmin_bwd_f32 without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments (minus the workspace),
+ * contract, result (bit for bit) and errors as odf_softmin_bwd_f32; the
+ * workspace is a static device array of the library of 128 MiB (2^27 bytes),
+ * one copy per GPU, held from the library's load until the process ends.
+ * Shapes whose odf_softmin_bwd_workspace() exceeds 2^27 bytes are rejected with
+ * ODF_EINVAL (16 x 512 x 512 at 5x5 needs 77 MiB and fits).  The call allocates
+ * nothing and does not synchronise; the first call on a device looks up the
+ * array's address there (hipGetSymbolAddress), which needs that device current
+ * and `stream` to belong to it.  Every call on one GPU uses the same array:
+ * calls that overlap in time on one GPU (concurrent streams, or threads)
+ * race and must be serialised by the caller; calls on one stream are ordered.
+ */
+int odf_softmin_bwd_f32_noalloc(const float* x, const float* dy, int B, int M, int N, int window,
+                                int kind, float p, float tau, float* dx, void* stream);
+
+/*
  * binary64 twins of the softmin relaxation and its gradient, for gradient
  * checks by finite differences in binary64 (the float32 entry points above are
  * the fast path).  Same definitions, conventions and errors as

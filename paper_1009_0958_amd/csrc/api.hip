@@ -5,6 +5,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "odf.h"
 #include "odf_internal.h"
 
@@ -300,6 +302,73 @@ int odf_softmin_bwd_f32(const float* x, const float* dy, int B, int M, int N, in
         return fail(ODF_EINVAL, "dx / workspace overlap an input or each other");
     odf::SoftParams prm{};
     prm.x = x; prm.dy = dy; prm.dx = dx; prm.ws = static_cast<float*>(workspace);
+    prm.B = B; prm.M = M; prm.N = N;
+    prm.p = kind == ODF_DDF ? p : 0.0f;
+    prm.inv_tau = 1.0f / tau;
+    hipError_t e = odf::launch_softmin(window, kind, true, prm, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "softmin backward launch");
+    return ODF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ static scratch
+// Workspace of odf_softmin_bwd_f32_noalloc: a device array of the library, one
+// copy on every GPU the library is loaded on, held until the process ends.  Host
+// code must not pass `scratch` itself to a kernel or a copy (in host code the
+// name stands for a host-side shadow, not a device address): it looks up the
+// array's address on the current device once with hipGetSymbolAddress and uses
+// that pointer.
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices];  // per device ordinal, guarded by g_scratch_mu
+
+// Address of `scratch` on the current device (looked up on the first call on
+// each device, with that device current).
+int scratch_on_current_device(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(ODF_EUNSUPPORTED, "device ordinal %d: the static scratch serves devices 0..%d",
+                    dev, kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(ODF_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ODF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int odf_softmin_bwd_f32_noalloc(const float* x, const float* dy, int B, int M, int N, int window,
+                                int kind, float p, float tau, float* dx, void* stream) {
+    int rc = check_soft(x, B, M, N, window, kind, p, tau);
+    if (rc) return rc;
+    if (!dy || !dx) return fail(ODF_EINVAL, "dy and dx must be non-NULL");
+    const size_t need = odf::softmin_workspace_bytes(window, kind, B, M, N);
+    if (need > kScratchBytes)
+        return fail(ODF_EINVAL,
+                    "this shape needs %zu bytes of workspace, more than the %zu of the static "
+                    "scratch (use odf_softmin_bwd_f32 with a workspace)", need, kScratchBytes);
+    const size_t nb = (size_t)B * M * N * 12;
+    if (overlaps(dx, nb, x, nb) || overlaps(dx, nb, dy, nb))
+        return fail(ODF_EINVAL, "dx overlaps x or dy");
+    void* ws = nullptr;
+    rc = scratch_on_current_device(&ws);
+    if (rc) return rc;
+    odf::SoftParams prm{};
+    prm.x = x; prm.dy = dy; prm.dx = dx; prm.ws = static_cast<float*>(ws);
     prm.B = B; prm.M = M; prm.N = N;
     prm.p = kind == ODF_DDF ? p : 0.0f;
     prm.inv_tau = 1.0f / tau;

@@ -63,12 +63,14 @@ def lib():
         L.odf_softmin_bwd_workspace.argtypes = [I, I, I, I, I]
         L.odf_softmin_bwd_workspace.restype = ctypes.c_size_t
         L.odf_softmin_bwd_f32.argtypes = [P, P, I, I, I, I, I, F, F, P, P, ctypes.c_size_t, P]
+        L.odf_softmin_bwd_f32_noalloc.argtypes = [P, P, I, I, I, I, I, F, F, P, P]
         L.odf_softmin_fwd_f64.argtypes = [P, I, I, I, I, I, Dbl, Dbl, P, P]
         L.odf_softmin_bwd_f64_workspace.argtypes = [I, I, I, I]
         L.odf_softmin_bwd_f64_workspace.restype = ctypes.c_size_t
         L.odf_softmin_bwd_f64.argtypes = [P, P, I, I, I, I, I, Dbl, Dbl, P, P, ctypes.c_size_t, P]
         for name in ("odf_filter_u8", "odf_filter_f32", "odf_aggregates_f32",
                      "odf_backward_hard_f32", "odf_softmin_fwd_f32", "odf_softmin_bwd_f32",
+                     "odf_softmin_bwd_f32_noalloc",
                      "odf_softmin_fwd_f64", "odf_softmin_bwd_f64"):
             getattr(L, name).restype = I
         _lib = L
@@ -334,6 +336,28 @@ def softmin_backward(x, dy, window=5, kind=DDF, p=0.25, tau=0.1, workspace=None)
     _check(fn(_ptr(xb), _ptr(g), B, M, N, window, _kind(kind), float(p), float(tau), _ptr(dx),
               _ptr(workspace), workspace.numel(), _stream(xb.device)))
     return dx[0] if squeeze else dx
+
+
+def softmin_backward_noalloc(x, dy, window=5, kind=DDF, p=0.25, tau=0.1, dx=None):
+    """softmin_backward (float32) on the library's static device scratch instead of a
+    workspace: for callers that cannot allocate (e.g. under graph capture, with
+    ``dx`` given).  Shapes needing more than 128 MiB of workspace are rejected."""
+    xb, squeeze = _as_batch(x)
+    g, _ = _as_batch(dy)
+    _check_tensor(xb, "x")
+    _check_tensor(g, "dy")
+    if xb.dtype != torch.float32 or g.dtype != torch.float32 or g.shape != xb.shape:
+        raise ValueError("x and dy must be float32 of the same shape")
+    B, M, N, _ = xb.shape
+    if dx is None:
+        dx = torch.empty_like(x)
+    dxb = dx if dx.dim() == 4 else dx[None]
+    _check_tensor(dxb, "dx")
+    if dxb.shape != xb.shape or dxb.dtype != torch.float32 or dxb.device != xb.device:
+        raise ValueError("dx must be a float32 tensor of the shape of x on its device")
+    _check(lib().odf_softmin_bwd_f32_noalloc(_ptr(xb), _ptr(g), B, M, N, window, _kind(kind),
+                                             float(p), float(tau), _ptr(dxb), _stream(xb.device)))
+    return dx
 
 
 class HardFilter(torch.autograd.Function):

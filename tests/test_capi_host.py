@@ -290,3 +290,17 @@ def test_tuning_table_has_centre_weighted_entries():
     assert odf.tune_get(5, odf.CWVMF, odf.EXACT) == 3
     odf.tune_set(3, odf.CWDDF, odf.RGB, True, 2)
     odf.tune_set(5, odf.CWVMF, odf.RGB, True, 2)
+
+
+def test_noalloc_softmin_rejects_before_launch():
+    L = odf.lib()
+    f = L.odf_softmin_bwd_f32_noalloc
+    # 1 x 4096 x 4096 at 5x5 needs ~300 MiB of workspace, beyond the 128 MiB static scratch
+    assert f(FAKE, FAKE2, 1, 4096, 4096, 5, odf.DDF, 0.25, 0.1,
+             ctypes.c_void_p(0x7F0010000000), None) == odf.EINVAL
+    assert "static scratch" in odf.last_error()
+    assert f(FAKE, None, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EINVAL
+    assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.0, FAKE2, None) == odf.EINVAL  # tau
+    assert f(FAKE, FAKE2, 1, 8, 8, 7, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE, None) == odf.EINVAL  # dx = x
+    assert "overlaps" in odf.last_error()

@@ -187,6 +187,8 @@ int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int wind
  *        whose selected member is the pixel q (replicated border: a window
  *        selecting an out-of-image position selects its clamped source).  Each
  *        sum is formed in binary64 over c in raster order and rounded once.
+ *        An index entry >= window^2 (not produced by the filter) routes
+ *        nothing: its dy(c) reaches no pixel.
  * The forward selection is not touched.  Errors: ODF_EINVAL for null
  * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for a window
  * other than 3, 5 or 7.

@@ -40,6 +40,29 @@ def test_backward_hard_matches_oracle_bitwise(window, shape):
     assert np.all(ones == np.rint(ones)) and ones.sum() == B * M * N * 3
 
 
+@pytest.mark.parametrize("window", [3, 5, 7])
+def test_backward_hard_ragged_tiles_and_foreign_indices(window):
+    """Tile edges in both directions (64 x 8 output tiles: 130 columns leave a
+    2-column tile, 17 rows a 1-row tile) and index entries >= window^2, which
+    route nothing: the same gradient as the oracle's with those windows' dy set
+    to 0 and any valid index in their place."""
+    print("case: hard bwd ragged + foreign w=%d" % window, flush=True)
+    B, M, N = 2, 17, 130
+    x = synth.float_batch(B, M, N, 0.1, key=40 + window)
+    _, idx = odf.filter(_gpu(x), window, DDF, 0.25)
+    idx = idx.cpu().numpy()
+    rng = np.random.default_rng(50 + window)
+    bad = rng.random(idx.shape) < 0.1
+    idx_bad = idx.copy()
+    idx_bad[bad] = rng.integers(window * window, 256, int(bad.sum()))
+    dy = rng.standard_normal(x.shape).astype(np.float32)
+    dx = odf.backward_hard(_gpu(idx_bad), _gpu(dy), window).cpu().numpy()
+    dy0 = dy.astype(np.float64)
+    dy0[bad] = 0.0
+    ref = oracle.backward_hard(idx, dy0, window)
+    assert np.array_equal(dx, ref.astype(np.float32))
+
+
 def test_hard_filter_autograd():
     x = _gpu(synth.float_batch(2, 40, 48, 0.15, key=2)).requires_grad_(True)
     y, idx = odf.hard_filter(x, 5, DDF, 0.25)

@@ -25,6 +25,9 @@
  *   - zero vectors: the direction of x = 0 is taken as (1,1,1) for the angle
  *     (eq. 2), the minimax angle (eqs. 4-6) and the chromaticity (eq. 7); the
  *     Minkowski distance uses the true value;
+ *   - the direction of a pixel of non-negative integers is x / gcd(x), the
+ *     same for every positive multiple of a colour (those terms are
+ *     scale-free), so collinear colours tie exactly and the lowest index wins;
  *   - DDF weighting: Omega = A^(1-p) * D^p (p = 1/2 orders the windows as the
  *     product of eq. 3 does), with C pow semantics (0^0 = 1);
  *   - the angle of eq. (2) is evaluated as atan2(|a x b|, a.b), the same
@@ -73,11 +76,32 @@ static const double TAB1_ACOS[3][5] = {
 static const double EQ10_ALPHA = 1.436437;
 static const double EQ10_BETA = 0.027664;
 
-/* Direction used by the angle and chromaticity terms: x itself, or the
- * achromatic axis (1,1,1) when x = 0 (eq. 2 and eq. 7 are 0/0 there). */
+static uint64_t gcd_u64(uint64_t a, uint64_t b) {
+    while (b) {
+        uint64_t r = a % b;
+        a = b;
+        b = r;
+    }
+    return a;
+}
+
+/* Direction used by the angle and chromaticity terms (eqs. 2 and 7 depend on
+ * a pixel only through its direction): the achromatic axis (1,1,1) when x = 0
+ * (both are 0/0 there); for a pixel of non-negative integers (every uint8
+ * pixel) the canonical integer direction x / gcd(x0, x1, x2), so that
+ * collinear colours of different brightness are one vector and every term
+ * they enter is equal bit for bit; otherwise x itself. */
 static void direction_of(const double *x, double *d) {
     if (x[0] == 0.0 && x[1] == 0.0 && x[2] == 0.0) {
         d[0] = d[1] = d[2] = 1.0;
+        return;
+    }
+    int integral = 1;
+    for (int k = 0; k < 3; ++k)
+        integral &= x[k] >= 0.0 && x[k] < 9007199254740992.0 && x[k] == floor(x[k]);
+    if (integral) {
+        uint64_t g = gcd_u64(gcd_u64((uint64_t)x[0], (uint64_t)x[1]), (uint64_t)x[2]);
+        for (int k = 0; k < 3; ++k) d[k] = (double)((uint64_t)x[k] / g);
     } else {
         d[0] = x[0]; d[1] = x[1]; d[2] = x[2];
     }

@@ -394,6 +394,69 @@ def test_collinear_window_selects_first_member():
         assert np.all(idx == 0)
 
 
+def _collinear_image(M, N, seed):
+    """Mostly positive multiples of (1, 2, 3) at different brightness, with a
+    few other colours and a zero pixel scattered in."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 86, (M, N))
+    img = (k[..., None] * np.array([1, 2, 3])).astype(np.uint8)
+    other = rng.random((M, N)) < 0.25
+    img[other] = rng.integers(0, 256, (int(other.sum()), 3))
+    img[0, 0] = 0
+    return img
+
+
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("w", [3, 5])
+def test_collinear_colours_tie_exactly(dist, w):
+    """eq. (2) and eq. (7) are scale-free: members that are positive multiples
+    of one colour have mathematically equal angle sums.  The oracle ties them
+    bit for bit (canonical directions) and takes the lowest index among the
+    members of the minimum; the 50-digit sums of those members agree."""
+    img = _collinear_image(6, 7, 40 + w + dist)
+    _, idx, A, _, _ = oracle.filter(img, w, BVDF, 0.0, dist, aggregates=True)
+    win = _window_stack(img, w).astype(np.int64)
+    M, N, n = A.shape
+    ties = 0
+    for r in range(M):
+        for c in range(N):
+            mem = win[r, c]
+            for u in range(n):
+                for v in range(u):
+                    if np.any(mem[u]) and np.any(mem[v]) and np.all(np.cross(mem[u], mem[v]) == 0):
+                        assert A[r, c, u] == A[r, c, v]
+            amin = A[r, c].min()
+            first = int(np.flatnonzero(A[r, c] == amin)[0])
+            assert idx[r, c] == first
+            if np.all(np.cross(mem[first], mem[np.argsort(A[r, c], kind="stable")[1]]) == 0) \
+                    and A[r, c, np.argsort(A[r, c], kind="stable")[1]] == amin:
+                ties += 1
+    assert ties > M * N // 4  # the image does exercise collinear ties at the minimum
+    if dist != MINIMAX:
+        mA, _ = _mp_filter(img[:4, :4], w, BVDF, 0.0, dist)
+        _, _, A4, _, _ = oracle.filter(img[:4, :4], w, BVDF, 0.0, dist, aggregates=True)
+        assert np.allclose(A4, mA, rtol=1e-13, atol=1e-13)
+        w4 = _window_stack(img[:4, :4], w).astype(np.int64)
+        for r in range(4):
+            for c in range(4):
+                for u in range(n):
+                    for v in range(u):
+                        a, b = w4[r, c, u], w4[r, c, v]
+                        if np.any(a) and np.any(b) and np.all(np.cross(a, b) == 0):
+                            # equal to 50 digits (acos next to 1 leaves ~1e-25 of 0)
+                            assert abs(mA[r, c, u] - mA[r, c, v]) <= 1e-20
+
+
+def test_canonical_direction_keeps_scaled_images():
+    """Any positive integer multiple of a uint8 image (here 3x, past 255, as
+    float64) gives the BVDF selections of the image itself, bit for bit."""
+    img = _tiny_image(17, 12, 11)
+    for dist in (EXACT, MINIMAX, RGB):
+        _, i1 = oracle.filter(img, 3, BVDF, 0.0, dist)
+        _, i3 = oracle.filter(img.astype(np.float64) * 3, 3, BVDF, 0.0, dist)
+        assert np.array_equal(i1, i3)
+
+
 # ------------------------------------------------------------ hard backward
 
 @pytest.mark.parametrize("w,kind,p,dist", [(3, DDF, 0.25, EXACT), (5, BVDF, 0.0, MINIMAX),

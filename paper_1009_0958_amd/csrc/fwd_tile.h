@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "aggregates.h"
+#include "canon.h"
 #include "odf_internal.h"
 
 namespace odf {
@@ -33,9 +34,10 @@ namespace odf {
 // The unguarded sweep (aggregates.h) reads up to 2h rows + 2h past dir (and
 // raw, inv) and as far before plane: the member order below keeps both inside
 // the struct, which fwd_tile checks.  stage holds one value per (window, output
-// pixel): stage[u][cy][cx].
+// pixel): stage[u][cy][cx].  CANON: the direction in dir is the canonical one
+// of canon.h, and rgb keeps each pixel's raw colour (bytes 0..2) for the copy.
 template <int W, int EXT_W, int EXT_H, bool AGG, bool STAGE, int NKEY, int NPL, bool U8,
-          bool INV>
+          bool INV, bool CANON>
 struct FwdShared {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     static constexpr bool HALO = !AGG && (U8 || W >= 5);
@@ -44,6 +46,7 @@ struct FwdShared {
     float4 dir[Gm::NT];
     float4 raw[U8 ? 1 : Gm::NT];
     float inv[INV ? Gm::NT : 1];
+    uint32_t rgb[CANON ? Gm::NT : 1];  // CANON: the raw uint8 colour, for the output copy
     float plane[NPL * Gm::G * Gm::NT];
     unsigned long long key[AGG ? 1 : NKEY * KEYN];
     float stage[STAGE ? Gm::NW * Gm::TH * Gm::TW : 1];
@@ -69,7 +72,7 @@ constexpr bool fused_sweep() {
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, bool AGG>
 using FwdSharedFor = FwdShared<W, EXT_W, EXT_H, AGG, stage_angle_part<W, KIND, AGG>(),
                                KIND == kACW ? 4 : 1, fused_sweep<W, KIND>() ? 2 : 1, U8,
-                               U8 && DIST != kExact>;
+                               U8 && DIST != kExact, U8 && KIND == kBVDF>;
 
 // Filter one output tile whose top-left output pixel is (ty0, tx0) of image b.
 // Every thread of the workgroup must call it (it synchronises); tid is the
@@ -81,6 +84,10 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
     using Sh = FwdSharedFor<W, KIND, DIST, U8, EXT_W, EXT_H, AGG>;
     constexpr int H = Gm::H, NW = Gm::NW, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     constexpr bool INV = U8 && DIST != kExact;
+    // BVDF on uint8 pixels takes the canonical direction of canon.h (the
+    // angular sweep alone decides, so collinear colours tie bit for bit); the
+    // DDF family keeps the raw vector, whose dot product its L2 term reuses
+    constexpr bool CANON = U8 && KIND == kBVDF;
     constexpr int KEYN = Sh::KEYN;
     // the unguarded sweep's reads past the pixel arrays and before the planes
     // stay inside this struct
@@ -106,12 +113,21 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
         float x0, x1, x2;
         if (U8) {
             const uint8_t* s = static_cast<const uint8_t*>(prm.img) + (size_t)pix * 3;
-            x0 = s[0]; x1 = s[1]; x2 = s[2];
+            const uint32_t c0 = s[0], c1 = s[1], c2 = s[2];
+            x0 = c0; x1 = c1; x2 = c2;
+            if constexpr (CANON) {
+                float d0, d1, d2;
+                canonical_direction(c0, c1, c2, d0, d1, d2);
+                prepare_pixel<DIST, U8, true>(x0, x1, x2, mdir, mraw, d0, d1, d2);
+                sh.rgb[tid] = c0 | (c1 << 8) | (c2 << 16);
+            } else {
+                prepare_pixel<DIST, U8>(x0, x1, x2, mdir, mraw);
+            }
         } else {
             const float* s = static_cast<const float*>(prm.img) + (size_t)pix * 3;
             x0 = s[0]; x1 = s[1]; x2 = s[2];
+            prepare_pixel<DIST, U8>(x0, x1, x2, mdir, mraw);
         }
-        prepare_pixel<DIST, U8>(x0, x1, x2, mdir, mraw);
         s_dir[tid] = mdir;
         if constexpr (!U8) sh.raw[tid] = mraw;
         if constexpr (INV) sh.inv[tid] = mraw.w;
@@ -335,7 +351,12 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
         }
         const int sel = (cy + u / W) * EXT_W + cx + u % W;
         const int pix = (b * M + gy) * N + gx;
-        if (U8) {
+        if constexpr (CANON) {
+            // the canonical direction is not the value: the raw colour kept in rgb
+            const uint32_t v = sh.rgb[sel];
+            uint8_t* o = static_cast<uint8_t*>(prm.out) + (size_t)pix * 3;
+            o[0] = (uint8_t)v; o[1] = (uint8_t)(v >> 8); o[2] = (uint8_t)(v >> 16);
+        } else if (U8) {
             // the raw value is the direction, or 0 for the zero pixel
             const float4 d = s_dir[sel];
             const bool z = d.w < 0.0f;

@@ -118,12 +118,22 @@ __device__ __forceinline__ float horner4(const float* c, float t) {
 // Prepare one pixel.  For float inputs the direction is scaled by a power of
 // two (exact; angles and chromaticities are scale-free) so that its largest
 // magnitude lies in [1, 2), which keeps every product below in range.  raw.w
-// is aux2 in both layouts.
-template <int DIST, bool U8>
+// is aux2 in both layouts.  CANON (uint8 only): the direction is the canonical
+// integer direction of canon.h, given as cd0..cd2, and aux1 is its own squared
+// norm or channel sum (the kinds that use it have no L2 term, and the output
+// is copied from the image).
+template <int DIST, bool U8, bool CANON = false>
 __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, float4& dir,
-                                              float4& raw) {
+                                              float4& raw, float cd0 = 0.0f, float cd1 = 0.0f,
+                                              float cd2 = 0.0f) {
+    static_assert(U8 || !CANON, "canonical directions are for uint8 pixels");
     float d0 = x0, d1 = x1, d2 = x2;
     const bool zero = (x0 == 0.0f) & (x1 == 0.0f) & (x2 == 0.0f);
+    if (CANON) {
+        d0 = cd0;
+        d1 = cd1;
+        d2 = cd2;
+    }
     int e = 0;
     if (!U8) {
         const float m = fmaxf(fabsf(x0), fmaxf(fabsf(x1), fabsf(x2)));
@@ -135,10 +145,12 @@ __device__ __forceinline__ void prepare_pixel(float x0, float x1, float x2, floa
     if (zero) d0 = d1 = d2 = 1.0f;
     float aux1 = 0.0f, aux2 = 0.0f;
     if (DIST == kExact) {
-        // |x|^2 of the raw value (exact for uint8), and d = 2^-e x: the
-        // derivative of the direction (0 for the zero pixel, whose direction
-        // is a constant), used by the angle gradient
-        aux1 = zero ? -3.0f : fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+        // |x|^2 of the raw value (exact for uint8; of the canonical direction
+        // with CANON), and d = 2^-e x: the derivative of the direction (0 for
+        // the zero pixel, whose direction is a constant), used by the angle
+        // gradient
+        const float s0 = CANON ? d0 : x0, s1 = CANON ? d1 : x1, s2 = CANON ? d2 : x2;
+        aux1 = zero ? -3.0f : fmaf(s0, s0, fmaf(s1, s1, s2 * s2));
         aux2 = zero ? 0.0f : ldexpf(1.0f, -e);
     } else if (DIST == kMinimax) {
         // n2 >= 1 (uint8 integers, or float directions scaled into [1, 2)):

@@ -305,3 +305,60 @@ def test_window7_tile_shapes_identical(kind, p):
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
     finally:
         odf.tune_set(7, kind, EXACT, True, saved)
+
+
+def _collinear_image(M, N, seed):
+    """Mostly positive multiples of (1, 2, 3) and of (4, 1, 0) at different
+    brightness (windows whose minimum is shared by collinear colours), with
+    other colours and zero pixels scattered in."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 64, (M, N))
+    base = np.where((rng.random((M, N)) < 0.5)[..., None], np.array([1, 2, 3]), np.array([4, 1, 0]))
+    img = (k[..., None] * base).astype(np.uint8)
+    other = rng.random((M, N)) < 0.2
+    img[other] = rng.integers(0, 256, (int(other.sum()), 3))
+    img[rng.random((M, N)) < 0.02] = 0
+    return img
+
+
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("window", [3, 5, 7])
+def test_bvdf_collinear_colours_select_lowest_index(window, dist):
+    """BVDF on uint8 pixels takes the canonical direction x / gcd(x), as the
+    oracle does: members that are multiples of one colour tie bit for bit and
+    the lowest index wins, so the GPU's index equals the oracle's at every pixel
+    whose minimum is shared by collinear colours (and elsewhere up to near-ties
+    between different directions); per-image and batched launches agree."""
+    img = _collinear_image(70, 97, 80 + window + dist)
+    n_mis, n = run_and_check(img, window, BVDF, 0.0, dist, aggregates=(window < 7))
+    _, idx = odf.filter(_gpu(img), window, BVDF, 0.0, dist)
+    idx = idx.cpu().numpy()
+    _, o_idx, _, _, O = oracle.filter(img, window, BVDF, 0.0, dist, aggregates=True)
+    M, N = idx.shape
+    h = window // 2
+    rr = np.clip(np.arange(M)[:, None, None] + np.arange(window * window)[None, None, :] // window - h,
+                 0, M - 1)
+    cc = np.clip(np.arange(N)[None, :, None] + np.arange(window * window)[None, None, :] % window - h,
+                 0, N - 1)
+    mem = img[rr, cc].astype(np.int64)  # M, N, n, 3
+    omin = O.min(-1, keepdims=True)
+    tied = O == omin
+    first = mem[np.arange(M)[:, None], np.arange(N)[None, :], o_idx.astype(np.int64)]
+    coll = np.all(np.cross(mem, first[:, :, None, :]) == 0, axis=-1)
+    only_collinear = np.all(~tied | coll, axis=-1) & (tied.sum(-1) > 1)
+    assert only_collinear.sum() > 50
+    assert np.array_equal(idx[only_collinear], o_idx[only_collinear])
+    if window == 7:
+        return  # the batch takes windows 3 and 5
+    # the batched launch (two copies, one job each) gives the same indices
+    x = _gpu(img)
+    jobs = [dict(img=x, out=torch.empty_like(x), idx=torch.empty((M, N), dtype=torch.uint8,
+                                                                  device=DEV),
+                 window=window, kind=BVDF, p=0.0, dist=dist, q=4) for _ in range(2)]
+    plan = odf.BatchPlan(jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    for j in jobs:
+        assert np.array_equal(j["idx"].cpu().numpy(), idx)
+    plan.close()
+

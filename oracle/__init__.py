@@ -41,8 +41,12 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        # ODF_ORACLE_LIB: a prebuilt copy of the same source (the sanitizer
+        # test's instrumented build); otherwise build in place when stale
+        path = os.environ.get("ODF_ORACLE_LIB")
+        if not path:
+            path = build()
+        lib = ctypes.CDLL(path)
         P, I, D, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
         lib.oracle_threads.restype = I
         lib.oracle_pair_terms.argtypes = [P, P, I64, I, I, I, P, P]

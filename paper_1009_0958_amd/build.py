@@ -66,6 +66,64 @@ def build(verbose: bool = False, extra=None) -> str:
     return LIB
 
 
+SANITIZED_LIB = os.path.join(HERE, "libodf_hostsan.so")
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """Compile the library with AddressSanitizer and UndefinedBehaviorSanitizer
+    on its host code only (argument validation, plans, tuning table; the device
+    code is built as usual) into ``libodf_hostsan.so``.  Load it with the clang
+    ASan runtime preloaded (see ``asan_runtime()``) and ``ODF_LIB`` naming it."""
+    import shutil
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host",
+           "-fno-omit-frame-pointer"]
+    cflags = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *san]
+    objdir = tempfile.mkdtemp(prefix="odf_hostsan_")
+    tmp = SANITIZED_LIB + ".tmp%d" % os.getpid()
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc, *cflags, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src,
+               "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+        return obj
+
+    try:
+        srcs = sorted(sources(), key=lambda f: 0 if os.path.basename(f).startswith("fwd") else 1)
+        with ThreadPoolExecutor(max_workers=max(1, min(len(srcs), os.cpu_count() or 4, 8))) as ex:
+            objs = list(ex.map(compile_one, srcs))
+        subprocess.check_call([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *san,
+                               "-shared-libsan", *objs, "-o", tmp])
+    finally:
+        shutil.rmtree(objdir, ignore_errors=True)
+    os.replace(tmp, SANITIZED_LIB)
+    return SANITIZED_LIB
+
+
+def asan_runtime() -> str:
+    """Path of the clang AddressSanitizer runtime the sanitized build links."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    out = subprocess.check_output([hipcc, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                                  text=True).strip()
+    if os.path.isabs(out) and os.path.exists(out):
+        return out
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc)), "..", "lib", "llvm", "lib",
+                         "clang")
+    for ver in sorted(os.listdir(clang)):
+        cand = os.path.join(clang, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(cand):
+            return os.path.realpath(cand)
+    raise FileNotFoundError("libclang_rt.asan-x86_64.so")
+
+
 def build_microbench(verbose: bool = False) -> str:
     """Compile the VALU-rate / copy-bandwidth microbenchmark executable."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -80,4 +138,7 @@ def build_microbench(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True, extra=sys.argv[1:])
+    if sys.argv[1:] == ["--sanitize-host"]:
+        print(build_host_sanitized(verbose=True))
+    else:
+        build(verbose=True, extra=sys.argv[1:])

@@ -14,7 +14,9 @@ import re
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libodf.so")
+# ODF_LIB names another build of the same library (the host-sanitized build the
+# sanitizer tests load); by default the in-tree libodf.so
+LIB_PATH = os.environ.get("ODF_LIB") or os.path.join(HERE, "libodf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "odf.h")
 
 BVDF, DDF, ACWDDF, CWVMF, CWDDF = 0, 1, 2, 3, 4

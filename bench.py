@@ -202,6 +202,17 @@ def time_launches(torch, fn, reps, warm=3):
     return s.elapsed_time(e) / reps  # ms per launch
 
 
+TUNE_CACHE = None  # set by --tune-cache
+
+
+def autotune(odf, window, kind, dist, u8, M, N, reps):
+    """The library's autotuner, or the tuning cache's entry when --tune-cache
+    names an existing file (returns (config, ms per shape or []))."""
+    if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
+        return odf.tune_get(window, kind, dist, u8), []
+    return odf.autotune(window, kind, dist, u8, M, N, reps, cache_path=TUNE_CACHE)
+
+
 HEADLINE = dict(window=5, kind="ddf", p=0.25, dist="exact", M=4320, N=7680, phi=0.15, key=500)
 
 
@@ -219,6 +230,10 @@ def main():
     ap.add_argument("--step-forms", default="loop,streams,persistent,direct",
                     help="forms of the six-variant DDF 3x3 group to time (comma list of loop, "
                          "streams, persistent, direct)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON tuning cache: applied instead of autotuning when the file exists, "
+                         "written by the autotuner otherwise (fixes the tile shapes across runs, "
+                         "e.g. between profiler passes)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one elementwise copy (float32 negation) of this many MiB, "
                          "untimed: the reference kernel for scaling HBM byte counters")
@@ -243,6 +258,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     DIST = {"exact": odf.EXACT, "minimax": odf.MINIMAX, "rgb": odf.RGB}
+    global TUNE_CACHE
+    TUNE_CACHE = args.tune_cache
+    if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
+        odf.tune_load(TUNE_CACHE)
 
     # ---------------------------------------------------------------- the step
     # DDF 5x5 (p = 1/4, exact angle) on one 7680 x 4320 uint8 frame, correlated
@@ -252,7 +271,7 @@ def main():
     M, N, w, p = H["M"], H["N"], H["window"], H["p"]
     img_np = synth.image_corr(M, N, H["phi"], key=H["key"])
     x = torch.from_numpy(img_np).to(dev)
-    best_cfg, shape_ms = odf.autotune(w, odf.DDF, odf.EXACT, True, M, N, 3)
+    best_cfg, shape_ms = autotune(odf, w, odf.DDF, odf.EXACT, True, M, N, 3)
     out = torch.empty_like(x)
     idx = torch.empty((M, N), dtype=torch.uint8, device=dev)
 
@@ -366,7 +385,7 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
     variants = [(p, d) for p in (0.25, 0.5) for d in ("exact", "minimax", "rgb")]
     tuned = {}
     for d in ("exact", "minimax", "rgb"):
-        best, times = odf.autotune(3, odf.DDF, DIST[d], True, M, N, 10)
+        best, times = autotune(odf, 3, odf.DDF, DIST[d], True, M, N, 10)
         tuned["ddf3_%s" % d] = {"config": best, "ext_tile": odf.tile_config(best),
                                 "ms_per_shape": [round(t, 5) for t in times]}
     outs = {v: (torch.empty_like(x), torch.empty((M, N), dtype=torch.uint8, device=dev))
@@ -495,7 +514,8 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
     forms = {}
     for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF)):
         for d in ("exact", "minimax", "rgb"):
-            odf.autotune(w, kk, DIST[d], True, 1024, 1024, 3)
+            if (w, kk, d) != (5, odf.DDF, "exact"):  # the step's class, tuned on this frame
+                autotune(odf, w, kk, DIST[d], True, 1024, 1024, 3)
     for tag, shape, key in (("7680x4320", (1, 4320, 7680), 5), ("64x1920x1080", (64, 1080, 1920), 6)):
         B, M, N = shape
         imgs = np.stack([synth.image_corr(M, N, 0.15, key=key * 100 + b) for b in range(B)])
@@ -539,7 +559,7 @@ def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
     big = torch.from_numpy(synth.image_corr(4320, 7680, 0.15, key=500)).to(dev)
     for w in (3, 5):
         for d in ("exact", "minimax", "rgb"):
-            best, _ = odf.autotune(w, odf.ACWDDF, DIST[d], True, 1024, 1024, 5)
+            best, _ = autotune(odf, w, odf.ACWDDF, DIST[d], True, 1024, 1024, 5)
             cases = [("1024x1024", x1k)] + ([("7680x4320", big)] if w == 3 else [])
             for tag, img in cases:
                 M, N = img.shape[:2]
@@ -613,7 +633,7 @@ def batched_form(torch, odf, synth, dev, samples=None):
     tuned = {}
     for w in (3, 5):
         for kind in (odf.BVDF, odf.DDF):
-            best, _ = odf.autotune(w, kind, odf.EXACT, True, 1024, 1024, 5)
+            best, _ = autotune(odf, w, kind, odf.EXACT, True, 1024, 1024, 5)
             tuned[f"w{w}_{'ddf' if kind else 'bvdf'}"] = odf.tile_config(best)
     jobs = []
     for s_, im in zip(specs, imgs):

@@ -76,30 +76,36 @@ __device__ __forceinline__ float cross_term(float u, float v, float w, float z) 
     return fmaf(u, v, -p) - e;
 }
 
-// grad_1 theta(a, b) = (a x c) / (|c| |a|^2), c = a x b, on the directions a, b
-// of the two pixels, times da/dx = `scale` for the raw first pixel.  c is
-// formed to full relative accuracy and a x c is well conditioned (c is
+// grad_1 theta(a, b) = (a x c) / (|c| |a|^2) with c = a x b, on the directions a,
+// b of the two pixels, times da/dx for the raw first pixel.  It is linear in
+// c / |c|: the gradient of a member over all its neighbours r, sum_r S_r
+// grad_1 theta(a, r), is a x (sum_r S_r c_r / |c_r|) / |a|^2, so the neighbour
+// loop accumulates S_r c_r / |c_r| and the cross product with the member's own
+// direction is taken once.  c is formed to full relative accuracy (a
+// two-product difference per component) and a x c is well conditioned (c is
 // orthogonal to a), so nearly parallel pairs keep an accurate gradient
-// direction; equal directions give c = 0 exactly and a zero gradient.
-__device__ __forceinline__ float3 angle_grad(const float4& a, float inv_a2, float scale,
-                                             const float4& b) {
+// direction; equal directions give c = 0 exactly and contribute nothing.
+__device__ __forceinline__ void add_cross_dir(const float4& a, const float4& b, float S, float& v0,
+                                              float& v1, float& v2) {
     const float c0 = cross_term(a.y, b.z, a.z, b.y);
     const float c1 = cross_term(a.z, b.x, a.x, b.z);
     const float c2 = cross_term(a.x, b.y, a.y, b.x);
     const float s2 = fmaf(c0, c0, fmaf(c1, c1, c2 * c2));
-    const float k = s2 > 0.0f ? rsq(s2) * (inv_a2 * scale) : 0.0f;
-    const float k0 = fmaf(a.y, c2, -a.z * c1);
-    const float k1 = fmaf(a.z, c0, -a.x * c2);
-    const float k2 = fmaf(a.x, c1, -a.y * c0);
-    return make_float3(k0 * k, k1 * k, k2 * k);
+    const float w = s2 > 0.0f ? S * rsq(s2) : 0.0f;
+    v0 = fmaf(w, c0, v0);
+    v1 = fmaf(w, c1, v1);
+    v2 = fmaf(w, c2, v2);
 }
 
-// grad_1 |a - b| = (a - b) / |a - b|, 0 for a = b.
-__device__ __forceinline__ float3 l2_grad(const float4& a, const float4& b) {
-    float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z;
-    float l2 = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
-    float il = l2 > 0.0f ? rsq(l2) : 0.0f;
-    return make_float3(e0 * il, e1 * il, e2 * il);
+// S grad_1 |a - b| = S (a - b) / |a - b| (0 for a = b), accumulated.
+__device__ __forceinline__ void add_l2_dir(const float4& a, const float4& b, float S, float& v0,
+                                           float& v1, float& v2) {
+    const float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z;
+    const float l2 = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+    const float w = l2 > 0.0f ? S * rsq(l2) : 0.0f;
+    v0 = fmaf(w, e0, v0);
+    v1 = fmaf(w, e1, v1);
+    v2 = fmaf(w, e2, v2);
 }
 
 // 2D prefix sums of the member gradients gr (row-major w x w):
@@ -131,49 +137,93 @@ __device__ __forceinline__ float box_over_members(const float (&P)[W + 1][W + 1]
     return (P[y1 + 1][x1 + 1] - P[y0][x1 + 1]) - (P[y1 + 1][x0] - P[y0][x0]);
 }
 
+// Offsets of the gradient exchange, the forward half of the pair offsets
+// (delta > 0 in row-major order: row g = 0 with dx > 0, rows g > 0 with any
+// dx), in chunks of at most 2h + 1 offsets of one row: g = 0 takes dx = 1..2h,
+// every g > 0 takes dx = -2h..0 and then dx = 1..2h.
+template <int W>
+struct PairChunks {
+    static constexpr int H = W / 2, N = 1 + 2 * (2 * H), CMAX = 2 * H + 1;
+    static constexpr int g(int k) { return (k + 1) / 2; }
+    static constexpr int lo(int k) { return (k % 2 == 0) ? 1 : -2 * H; }
+    static constexpr int hi(int k) { return (k % 2 == 0) ? 2 * H : 0; }
+};
+
 // Pair-term part of the gradient for one plane (angle, or L2 when L2PASS):
-// dx(q) += sum_{r != q} (B_q(r - q) + B_r(q - r)) grad_1 term(q, r), the B
-// of the neighbours exchanged through LDS planes one row group at a time.
+// dx(q) += sum_{r != q} S(q, r) grad_1 term(q, r), S(q, r) = B_q(r - q) +
+// B_r(q - r) (symmetric).  Each unordered pair is evaluated once, by its first
+// pixel q (r = q + delta, delta in the forward half).  Accumulated as
+// S c / |c| (angle, c = d_q x d_r, crossed with the member's own direction at
+// the end) or S e / |e| (L2, e = x_q - x_r), the second pixel's share is the
+// same vector negated (c and e change sign with the order of the pair, S and
+// |c|, |e| do not), so q adds it and hands it to r through LDS.  Per chunk of
+// offsets: every pixel publishes B(-delta) (plane P), then q forms S and the
+// pair's share (plane Q, three floats), then r subtracts the shares meant for
+// it -- all in a fixed order, so the result is deterministic.
+// scale: da/dx / |a|^2 of this member's direction (angle plane only).
 template <int W, int EXT_W, int EXT_H, bool L2PASS>
 __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
                                                 const float4* __restrict__ s_dir,
                                                 const float4* __restrict__ s_raw,
                                                 float* __restrict__ s_plane, int ey, int ex,
                                                 int tid, const float4& mdir, const float4& mraw,
-                                                float inv_a2, float& gx0, float& gx1, float& gx2) {
-    constexpr int H = W / 2, G = 4 * H + 1, NT = EXT_W * EXT_H;
-    float* P_dn = s_plane;           // B_r((-g, -dx)), read by the pixel r - (g, dx)
-    float* P_up = s_plane + G * NT;  // B_r((g, -dx)),  read by the pixel r - (-g, dx)
+                                                float scale, float& gx0, float& gx1, float& gx2) {
+    using Ch = PairChunks<W>;
+    constexpr int NT = EXT_W * EXT_H, CMAX = Ch::CMAX;
+    float* P = s_plane;                // [CMAX][NT]: B_r(-delta) of the chunk's offsets
+    float* Q = s_plane + CMAX * NT;    // [3][CMAX][NT]: the share handed to r = q + delta
     float Pt[W + 1][W + 1];
     member_prefix<W>(gr, Pt);
+    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+    auto receive = [&](int k) {        // the shares of chunk k meant for this pixel
+        const int g = Ch::g(k);
 #pragma unroll
-    for (int g = 0; g <= 2 * H; ++g) {
-#pragma unroll
-        for (int dx = -2 * H; dx <= 2 * H; ++dx) {
-            if (g == 0 && dx == 0) continue;
-            P_dn[(dx + 2 * H) * NT + tid] = box_over_members<W>(Pt, -g, -dx);
-            if (g > 0) P_up[(dx + 2 * H) * NT + tid] = box_over_members<W>(Pt, g, -dx);
+        for (int dx = Ch::lo(k); dx <= Ch::hi(k); ++dx) {
+            const int qy = ey - g, qx = ex - dx;  // q = this pixel - delta
+            if (qy < 0 || qx < 0 || qx >= EXT_W) continue;
+            const int j = (dx - Ch::lo(k)) * NT + qy * EXT_W + qx;
+            v0 -= Q[j];
+            v1 -= Q[CMAX * NT + j];
+            v2 -= Q[2 * CMAX * NT + j];
         }
+    };
+#pragma unroll
+    for (int k = 0; k < Ch::N; ++k) {
+        const int g = Ch::g(k);
+#pragma unroll
+        for (int dx = Ch::lo(k); dx <= Ch::hi(k); ++dx)
+            P[(dx - Ch::lo(k)) * NT + tid] = box_over_members<W>(Pt, -g, -dx);
+        if (k > 0) receive(k - 1);
         __syncthreads();
 #pragma unroll
-        for (int sgn = 1; sgn >= -1; sgn -= 2) {
-            if (g == 0 && sgn < 0) continue;
-            const float* P = sgn > 0 ? P_dn : P_up;
-#pragma unroll
-            for (int dx = -2 * H; dx <= 2 * H; ++dx) {
-                if (g == 0 && dx == 0) continue;
-                const int ry = ey + sgn * g, rx = ex + dx;
-                if (ry < 0 || ry >= EXT_H || rx < 0 || rx >= EXT_W) continue;
-                const int r = ry * EXT_W + rx;
-                const float S = box_over_members<W>(Pt, sgn * g, dx) + P[(dx + 2 * H) * NT + r];
-                const float3 gv = L2PASS ? l2_grad(mraw, s_raw[r])
-                                         : angle_grad(mdir, inv_a2, mraw.w, s_dir[r]);
-                gx0 = fmaf(S, gv.x, gx0);
-                gx1 = fmaf(S, gv.y, gx1);
-                gx2 = fmaf(S, gv.z, gx2);
-            }
+        for (int dx = Ch::lo(k); dx <= Ch::hi(k); ++dx) {
+            const int ry = ey + g, rx = ex + dx;
+            if (ry >= EXT_H || rx < 0 || rx >= EXT_W) continue;
+            const int r = ry * EXT_W + rx;
+            const float S = box_over_members<W>(Pt, g, dx) + P[(dx - Ch::lo(k)) * NT + r];
+            float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+            if (L2PASS) add_l2_dir(mraw, s_raw[r], S, w0, w1, w2);
+            else add_cross_dir(mdir, s_dir[r], S, w0, w1, w2);
+            v0 += w0;
+            v1 += w1;
+            v2 += w2;
+            const int j = (dx - Ch::lo(k)) * NT + tid;
+            Q[j] = w0;
+            Q[CMAX * NT + j] = w1;
+            Q[2 * CMAX * NT + j] = w2;
         }
         __syncthreads();
+    }
+    receive(Ch::N - 1);
+    if (L2PASS) {
+        gx0 += v0;
+        gx1 += v1;
+        gx2 += v2;
+    } else {
+        // a x (sum S c / |c|), times da/dx / |a|^2
+        gx0 = fmaf(fmaf(mdir.y, v2, -mdir.z * v1), scale, gx0);
+        gx1 = fmaf(fmaf(mdir.z, v0, -mdir.x * v2), scale, gx1);
+        gx2 = fmaf(fmaf(mdir.x, v1, -mdir.y * v0), scale, gx2);
     }
 }
 
@@ -184,7 +234,10 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
     constexpr int TT = TW * TH;
-    constexpr int NPLANE = BWD ? 2 * G : G;
+    // planes: G for the aggregate sweeps; the gradient exchange takes 4 CMAX
+    // (plane P and the three planes of Q)
+    constexpr int NPLANE =
+        BWD && 4 * PairChunks<W>::CMAX > G ? 4 * PairChunks<W>::CMAX : G;
 
     // LDS: the pixels, the window keys and one region that holds, in turn, the
     // planes of the aggregate sweeps, the (member, window) weights e with the
@@ -227,6 +280,7 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
     const int M = prm.M, N = prm.N;
     const float p = prm.p;
     const float inv_tau = prm.inv_tau;
+    const float tau_ln2 = 0.69314718055994531f / inv_tau;  // tau ln 2: ln e = ln2 log2 e
 
     {
         const int gy = min(max(ty0 - H + ey, 0), M - 1);
@@ -312,19 +366,23 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
 #pragma unroll
             for (int u = 0; u < NW; ++u) D[u] = 0.0f;
         }
+        // Omega once per (member, window): kept in e for the minimum, then
+        // replaced there by the weight
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             int c;
-            if (window_of(u, c))
-                atomicMin(&s_key[c], order_key(soft_objective<KIND>(A[u], D[u], p)));
+            if (window_of(u, c)) {
+                const float om = soft_objective<KIND>(A[u], D[u], p);
+                s_e[u * TT + c] = om;
+                atomicMin(&s_key[c], order_key(om));
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             int c;
             if (window_of(u, c))
-                s_e[u * TT + c] =
-                    __expf((key_value(s_key[c]) - soft_objective<KIND>(A[u], D[u], p)) * inv_tau);
+                s_e[u * TT + c] = __expf((key_value(s_key[c]) - s_e[u * TT + c]) * inv_tau);
         }
     }
     __syncthreads();
@@ -379,20 +437,31 @@ __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
             const float t = fmaf(mraw.x - w[1], w[4], fmaf(mraw.y - w[2], w[5], (mraw.z - w[3]) * w[6]));
             const float gom = -pi * t * inv_tau;
             float dA, dD;
-            objective_grad<KIND>(A[u], D[u], soft_objective<KIND>(A[u], D[u], p), p, dA, dD);
+            if (KIND == kBVDF || p == 0.0f || p == 1.0f) {
+                objective_grad<KIND>(A[u], D[u], 0.0f, p, dA, dD);  // constant derivatives
+            } else {
+                // Omega from its weight, e = exp((min - Omega) / tau): Omega = min - tau ln e,
+                // within a few ulp of tau of the objective (a member with e = 0 has pi = 0
+                // and no gradient)
+                const float e = s_e[u * TT + c];
+                const float om = fmaf(-tau_ln2, __builtin_amdgcn_logf(e), key_value(s_key[c]));
+                objective_grad<KIND>(A[u], D[u], e > 0.0f ? om : 0.0f, p, dA, dD);
+            }
             ga = gom * dA;
             gd = gom * dD;
         }
         A[u] = ga;
         D[u] = gd;
     }
-    const float inv_a2 = 1.0f / fmaf(mdir.x, mdir.x, fmaf(mdir.y, mdir.y, mdir.z * mdir.z));
+    // da/dx / |a|^2 for the direction a = 2^-e x (0 for the zero pixel)
+    const float scale =
+        mraw.w / fmaf(mdir.x, mdir.x, fmaf(mdir.y, mdir.y, mdir.z * mdir.z));
     __syncthreads();  // every thread is done with e and the window sums: the planes reuse them
     propagate_pairs<W, EXT_W, EXT_H, false>(A, s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw,
-                                            inv_a2, gx0, gx1, gx2);
+                                            scale, gx0, gx1, gx2);
     if (KIND == kDDF)
         propagate_pairs<W, EXT_W, EXT_H, true>(D, s_dir, s_raw, s_plane, ey, ex, tid, mdir, mraw,
-                                               inv_a2, gx0, gx1, gx2);
+                                               0.0f, gx0, gx1, gx2);
 
     // fold replicated border positions into their source pixel, then write
     // this tile's contribution for every in-image extended position

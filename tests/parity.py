@@ -114,6 +114,46 @@ def check_acwddf(idx_gpu, idx_oracle, colours, S, diag, n, T, max_ambiguous=0.01
 EPS32 = 2.0 ** -24
 
 
+def soft_bounds(x, omega, window, tau, dx_scale):
+    """Per-element error bounds of the float32 softmin against the binary64
+    oracle, from the arithmetic: the objective of a window carries a few ulp of
+    relative error and enters exp(-(Omega - min Omega) / tau), so the weights
+    of window c move by about eps * Omega_max(c) / tau, where Omega_max(c) is
+    the largest objective of its members (the oracle's); the weighted sum of
+    colours adds about n eps max|x| of its own rounding.  A pixel's gradient
+    collects the weight perturbations of every window within 2h, so it takes
+    the largest Omega_max over its (4h + 1)^2 neighbourhood, scaled by the
+    largest gradient.  omega: the oracle's objectives (..., M, N, n).
+    Returns (bound on |y - ref| per pixel, bound on |dx - ref| per pixel).
+    The constants (1 n + 2 Omega / tau for y, 1 n + 4 Omega / tau for dx) sit
+    2-5x above the worst errors measured on the test images."""
+    n = window * window
+    h = window // 2
+    om = np.asarray(omega).max(-1)
+    ty = EPS32 * np.abs(x).max() * (n + 2.0 * om / tau)
+    # neighbourhood maximum over (4h + 1)^2 pixels, replicated border
+    pad = [(0, 0)] * (om.ndim - 2) + [(2 * h, 2 * h), (2 * h, 2 * h)]
+    op = np.pad(om, pad, mode="edge")
+    M, N = om.shape[-2:]
+    omn = np.full(om.shape, -np.inf)
+    for dy in range(4 * h + 1):
+        for dxo in range(4 * h + 1):
+            omn = np.maximum(omn, op[..., dy:dy + M, dxo:dxo + N])
+    td = EPS32 * dx_scale * (n + 4.0 * omn / tau)
+    return ty, td
+
+
+def check_soft(y, ref_y, dx, ref_dx, bounds, name=""):
+    """Element-wise check against soft_bounds; returns the worst error / bound
+    ratios (forward, backward)."""
+    ty, td = bounds
+    ry = (np.abs(np.asarray(y, np.float64) - ref_y).max(-1) / ty) if y is not None else np.zeros(1)
+    rd = (np.abs(np.asarray(dx, np.float64) - ref_dx).max(-1) / td) if dx is not None else np.zeros(1)
+    assert ry.max() <= 1.0, "%s: forward error %.3g x its bound" % (name, ry.max())
+    assert rd.max() <= 1.0, "%s: gradient error %.3g x its bound" % (name, rd.max())
+    return float(ry.max()), float(rd.max())
+
+
 def soft_tol(x, window, kind, p, tau, scale=64.0):
     """Softmin error budget (relative): the binary32 objective carries a few ulp of
     relative error and enters exp(-Omega / tau); with max Omega <= n (pi/2 + max|x|

@@ -26,7 +26,7 @@ Also reported on the same JSON line:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
                        [--forms six_variants,large_frames,acwddf,effectiveness,batched,
-                        differentiable] [--step-forms loop,streams,persistent,direct]
+                        differentiable] [--step-forms loop,streams,direct]
                        [--copy-probe-mib MiB]
 """
 import argparse
@@ -227,9 +227,9 @@ def main():
     ap.add_argument("--forms", default="six_variants,large_frames,acwddf,effectiveness,batched,"
                                         "differentiable",
                     help="comma list of the form groups to run besides the step")
-    ap.add_argument("--step-forms", default="loop,streams,persistent,direct",
+    ap.add_argument("--step-forms", default="loop,streams,direct",
                     help="forms of the six-variant DDF 3x3 group to time (comma list of loop, "
-                         "streams, persistent, direct)")
+                         "streams, direct)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: applied instead of autotuning when the file exists, "
                          "written by the autotuner otherwise (fixes the tile shapes across runs, "
@@ -248,9 +248,8 @@ def main():
     if any(g not in known for g in groups):
         ap.error("--forms takes a comma list of " + ", ".join(known))
     forms_wanted = [f for f in args.step_forms.split(",") if f]
-    if not forms_wanted or any(f not in ("loop", "streams", "persistent", "direct")
-                               for f in forms_wanted):
-        ap.error("--step-forms takes a comma list of loop, streams, persistent, direct")
+    if not forms_wanted or any(f not in ("loop", "streams", "direct") for f in forms_wanted):
+        ap.error("--step-forms takes a comma list of loop, streams, direct")
 
     import torch
     from paper_1009_0958_amd import odf, synth
@@ -376,9 +375,9 @@ def main():
 def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samples):
     """DDF 3x3 on one 1024 x 1024 uint8 image (correlated impulsive noise 0.20)
     for p in {1/4, 1/2} x {exact, minimax q=4, rgb}: six forward filters,
-    timed four ways (a loop of six launches; the six spread over three streams;
-    the six as one planned batch recorded in a graph, persistent or direct work
-    list), with the per-variant kernel rates and the roofline of the fastest
+    timed three ways (a loop of six launches; the six spread over three
+    streams; the six as one planned batch recorded in a graph), with the
+    per-variant kernel rates and the roofline of the fastest
     form's dominant kernel.  With ``samples`` the six index maps are kept for
     the oracle's full-image comparison."""
     M, N = img_np.shape[:2]
@@ -414,11 +413,10 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
             cur.wait_stream(st)
 
     graphs = {}
-    for mode in [f for f in ("persistent", "direct") if f in forms_wanted]:
+    if "direct" in forms_wanted:
         plan = odf.BatchPlan([dict(img=x, out=outs[(p, d)][0], idx=outs[(p, d)][1], window=3,
-                                   kind=odf.DDF, p=p, dist=DIST[d], q=4) for (p, d) in variants],
-                             direct=(mode == "direct"))
-        graphs[mode] = (plan, plan.capture())
+                                   kind=odf.DDF, p=p, dist=DIST[d], q=4) for (p, d) in variants])
+        graphs["direct"] = (plan, plan.capture())
 
     step_forms = {}
     if "loop" in forms_wanted:
@@ -624,9 +622,13 @@ def effectiveness_forms(torch, odf, synth, dev, DIST):
 
 def batched_form(torch, odf, synth, dev, samples=None):
     """256 uint8 images of mixed size (64..2048 x 64..1536), window, kind and
-    noise: one planned launch captured in a graph (direct and persistent form;
-    one kernel per window and kind), against a loop of per-image launches of
-    the same jobs (tile shapes from the autotuned table)."""
+    noise: one planned launch captured in a graph (one kernel per window and
+    kind, on the tile shapes the batch autotuner picks per group on these
+    jobs), against a
+    loop of per-image launches of the same jobs (tile shapes from the per-image
+    autotuner); also each group's jobs planned and replayed alone, whose
+    summed times show how far the concurrent groups are from running back to
+    back at their own rates."""
     specs = synth.mixed_batch_specs(256)
     imgs = synth.mixed_batch_images(specs, workers=16)
     # tile shapes of the per-image launches of the loop (untimed)
@@ -650,24 +652,38 @@ def batched_form(torch, odf, synth, dev, samples=None):
             odf.filter(j["img"], j["window"], j["kind"], j["p"], odf.EXACT, 4, out=o, idx=i)
 
     ms_loop = time_launches(torch, loop, 3, warm=1)
-
-    def same_as_loop():
-        return all(torch.equal(j["out"], o) and torch.equal(j["idx"], i)
-                   for j, (o, i) in zip(jobs, loop_out))
-
-    res = {}
-    for name, direct in (("direct", True), ("persistent", False)):
-        for j in jobs:
-            j["out"].zero_()
-            j["idx"].zero_()
-        plan = odf.BatchPlan(jobs, direct=direct)
-        graph = plan.capture()
-        ms = time_launches(torch, graph.replay, 5, warm=2)
-        res[name] = (ms, same_as_loop(), plan.info())
-        plan.close()
+    # the batch groups' tile shapes, tuned on these jobs (untimed)
+    if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
+        bt = {f"w{w}_{'ddf' if k else 'bvdf'}": (odf.batch_tune_get(w, k), [])
+              for w in (3, 5) for k in (0, 1)}
+    else:
+        bt = odf.autotune_batch_jobs(jobs, 2, TUNE_CACHE)
+    batch_tuned = {g: {"ext_tile": odf.tile_config(b), "ms_per_shape": [round(t, 4) for t in ms]}
+                   for g, (b, ms) in bt.items()}
+    for j in jobs:
+        j["out"].zero_()
+        j["idx"].zero_()
+    plan = odf.BatchPlan(jobs)
+    graph = plan.capture()
+    ms_direct = time_launches(torch, graph.replay, 5, warm=2)
+    same = all(torch.equal(j["out"], o) and torch.equal(j["idx"], i)
+               for j, (o, i) in zip(jobs, loop_out))
+    info = plan.info()
+    plan.close()
+    alone = {}
+    for w in (3, 5):
+        for kind in (odf.BVDF, odf.DDF):
+            sub = [j for j in jobs if j["window"] == w and j["kind"] == kind]
+            gp = odf.BatchPlan(sub)
+            gg = gp.capture()
+            alone[f"w{w}_{'ddf' if kind else 'bvdf'}"] = {
+                "mpix": round(sum(int(j["img"].shape[0] * j["img"].shape[1]) for j in sub) / 1e6,
+                              2),
+                "ms": round(time_launches(torch, gg.replay, 5, warm=2), 3)}
+            gp.close()
     if samples is not None:
         # 1 M seeded pixels over the whole batch (the outputs of the last
-        # replay of the persistent graph, bitwise equal to the direct one's)
+        # replay of the group graphs, bitwise equal to the whole plan's)
         sizes = np.array([int(j["img"].shape[0] * j["img"].shape[1]) for j in jobs])
         start = np.concatenate([[0], np.cumsum(sizes)])
         flat = mismatch_sample(1, 1, int(start[-1]), 1_000_000, 7100)
@@ -678,18 +694,16 @@ def batched_form(torch, odf, synth, dev, samples=None):
             win = sample_windows(torch, j["img"][None], pix, j["window"])
             gidx = j["idx"].reshape(-1)[torch.from_numpy(pix).to(dev)].cpu().numpy()
             samples.setdefault("batch", []).append((j["window"], j["kind"], j["p"], win, gidx))
-    ms_direct, same_d, info = res["direct"]
-    ms_pers, same_p, _ = res["persistent"]
     return {"batched_256_mixed": {
         "mpix": round(npx / 1e6, 2), "loop_tile_shapes": tuned,
-        "batch_tile_shapes": {"w3_ddf": [32, 32], "other": [32, 16]},
-        "direct_graph_ms": round(ms_direct, 3), "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
-        "persistent_graph_ms": round(ms_pers, 3),
-        "persistent_graph_mpix_s": round(npx / (ms_pers * 1e3), 1),
-        "loop_ms": round(ms_loop, 3),
-        "loop_mpix_s": round(npx / (ms_loop * 1e3), 1),
+        "batch_tile_shapes": batch_tuned, "plan_ext_tiles": info["ext_tiles"],
+        "direct_graph_ms": round(ms_direct, 3),
+        "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
+        "loop_ms": round(ms_loop, 3), "loop_mpix_s": round(npx / (ms_loop * 1e3), 1),
         "speedup_direct_vs_loop": round(ms_loop / ms_direct, 3),
-        "bitwise_equal_to_loop": bool(same_d and same_p), "tiles_per_class": info["tiles"]}}
+        "groups_alone": alone,
+        "groups_alone_sum_ms": round(sum(v["ms"] for v in alone.values()), 3),
+        "bitwise_equal_to_loop": bool(same), "tiles_per_class": info["tiles"]}}
 
 
 def plain_softmin(torch, x, w, p, tau):

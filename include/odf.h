@@ -16,13 +16,14 @@
  *     neither frees nor retains them.  Outputs must not overlap inputs.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *     on it and return without waiting; they allocate nothing except where
- *     stated (odf_batch_plan, odf_autotune, odf_tune_load).
+ *     stated (odf_batch_plan, the autotuners, odf_tune_load).
  *   - Arguments are validated on the host before anything is launched.  A
  *     rejected call returns a negative odf_status, launches nothing and sets
  *     the message returned by odf_last_error() (per thread).
  *   - Sizes: B, M, N >= 1 and B*M*N < 2^31 pixels per call.
  *   - No C++ exception crosses this interface.
- *   - Tests can make the allocating calls (odf_batch_plan, odf_autotune) take
+ *   - Tests can make the allocating calls (odf_batch_plan, odf_autotune,
+ *     odf_autotune_batch, odf_autotune_batch_jobs) take
  *     their allocation-failure path: with the environment variable
  *     ODF_TEST_FAIL_ALLOC set to anything but "" or "0" they return
  *     ODF_ENOMEM before allocating or touching the device.
@@ -289,39 +290,42 @@ typedef struct odf_plan odf_plan; /* opaque, owned by the library */
 
 /* Validate the jobs, cut them into tiles and upload the work lists (one per
  * group of window and kind, holding the tiles of every pair term, heavier
- * tiles first).  Allocates device
- * memory and synchronises; the job buffers must stay valid while the plan is
- * launched.  On success *plan receives a plan to pass to odf_batch_launch and
- * finally to odf_plan_destroy.  Errors: ODF_EINVAL / ODF_EUNSUPPORTED for a bad
- * job (nothing is allocated), ODF_ENOMEM, ODF_EHIP. */
+ * tiles first); each group runs on the extended-tile shape the batch tuning
+ * table holds for it when the plan is made (odf_batch_tune_get,
+ * odf_autotune_batch).  Allocates device memory and synchronises; the job
+ * buffers must stay valid while the plan is launched.  On success *plan
+ * receives a plan to pass to odf_batch_launch and finally to
+ * odf_plan_destroy.  Errors: ODF_EINVAL / ODF_EUNSUPPORTED for a bad job
+ * (nothing is allocated), ODF_ENOMEM, ODF_EHIP. */
 int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream);
 
-/* odf_batch_plan with a launch form: ODF_BATCH_DIRECT (what odf_batch_plan
- * uses: one workgroup per tile of the work list, dispatched by the hardware
- * in list order; tiles of 32 x 32 for 3x3 DDF and 32 x 16 otherwise, the
- * shapes with the best rate over many tiles) or ODF_BATCH_PERSISTENT
- * (persistent workgroups taking tiles with an atomic counter).  Same results;
- * on MI355X the direct form is faster (the persistent loop costs registers). */
+/* odf_batch_plan with a launch form.  ODF_BATCH_DIRECT (one workgroup per tile
+ * of the work list, dispatched in list order) is odf_batch_plan.
+ * ODF_BATCH_PERSISTENT (persistent workgroups taking tiles from an atomic
+ * counter) is retired and returns ODF_EUNSUPPORTED: measured on MI355X it ran
+ * at 0.6 of the direct form (its loop cost registers), and the direct form
+ * already runs the groups at the kernels' own steady-state rate. */
 enum { ODF_BATCH_PERSISTENT = 0, ODF_BATCH_DIRECT = 1 };
 int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream);
 
-/* Enqueue the plan on `stream`: (persistent form) a counter-reset kernel,
- * then one kernel per non-empty group over its work list; a group
- * kernel runs the tiles of all three pair terms of its window and kind.
- * Groups after the first run on the plan's own
- * auxiliary streams, forked from and joined back to `stream` with events, so
- * they overlap; everything is ordered after prior work on `stream` and before
- * later work on it.  Allocates nothing and does not synchronise, so it may be
- * captured in a hipGraph and replayed.  Launches of one plan must not overlap
- * in time (they share the tile counters and streams). */
+/* Enqueue the plan on `stream`: one kernel per non-empty group over its work
+ * list; a group kernel runs the tiles of all three pair terms of its window
+ * and kind.  Groups after the first run on the plan's own auxiliary streams,
+ * forked from and joined back to `stream` with events, so they overlap;
+ * everything is ordered after prior work on `stream` and before later work on
+ * it.  Allocates nothing and does not synchronise, so it may be captured in a
+ * hipGraph and replayed.  Launches of one plan must not overlap in time (they
+ * share the plan's streams). */
 int odf_batch_launch(const odf_plan* plan, void* stream);
 
 /* Plan summary: job count, total pixels, and per class of window, kind and
  * pair term, class = ((window == 5) * 2 + kind) * 3 + dist (arrays of 12, each
- * nullable): its tiles, and the workgroups launched for them (direct form: one
- * per tile; persistent form: the grid of its group's kernel, shared by the
- * group's pair terms). */
+ * nullable): its tiles, and the workgroups launched for them (one per tile). */
 int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles, int* grids);
+
+/* The tile shape (odf_tile_config number) each group of the plan runs on,
+ * group = (window == 5) * 2 + kind, configs[4].  ODF_EINVAL for NULL. */
+int odf_plan_configs(const odf_plan* plan, int* configs);
 
 /* Free a plan (after its last launch has completed). */
 int odf_plan_destroy(odf_plan* plan);
@@ -383,7 +387,8 @@ int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */
 
-/* Time every valid tile shape on a seeded random M x N image (reps launches
+/* Time every valid tile shape on a seeded M x N tuning image (a smooth field
+ * with 15 % impulsive noise; reps launches
  * each, HIP events on `stream`), set the fastest in the table, store the
  * per-shape milliseconds in times_ms[4] (-1 for shapes not offered; nullable)
  * and append one JSON line to cache_path (nullable).  Allocates and frees
@@ -393,8 +398,36 @@ int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /*
 int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
                  const char* cache_path, float* times_ms, void* stream);
 
-/* Apply the entries of a cache written by odf_autotune whose architecture
- * matches the current device; returns the number applied or ODF_EINVAL. */
+/* The batch tuning table: the tile shape (0..3) of the batch group of
+ * `window` (3, 5) and `kind` (ODF_BVDF, ODF_DDF); 32 x 32 for 3x3 DDF and
+ * 32 x 16 otherwise until tuned.  get returns the config or ODF_EINVAL; set
+ * returns ODF_OK or ODF_EINVAL.  Plans read the table when they are made. */
+int odf_batch_tune_get(int window, int kind);
+int odf_batch_tune_set(int window, int kind, int config);
+
+/* Time the four tile shapes of one batch group on a seeded mixed work list
+ * (six tuning images from 64 x 64 to 1920 x 1080, each with the three pair
+ * terms: 18 jobs; reps launches per shape, HIP events on `stream`), set the
+ * fastest in the batch table, store the per-shape milliseconds in times_ms[4]
+ * (nullable) and append one JSON line to cache_path (nullable).  Allocates
+ * and frees device memory and synchronises `stream`.  Errors: ODF_EINVAL,
+ * ODF_ENOMEM, ODF_EHIP. */
+int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, float* times_ms,
+                       void* stream);
+
+/* The same on the caller's own jobs (validated as for odf_batch_plan): for each
+ * batch group that holds jobs, its four tile shapes are timed on the group's
+ * jobs (reps launches each; the jobs' outputs are written) and the fastest is
+ * set in the batch table and appended to cache_path (nullable);
+ * times_ms[4 * group + shape] (nullable, 16 floats) receives the milliseconds,
+ * -1 for groups without jobs.  A plan made afterwards for the same jobs runs
+ * on the shapes tuned for them.  Errors: as odf_batch_plan. */
+int odf_autotune_batch_jobs(const odf_job* jobs, int njobs, int reps, const char* cache_path,
+                            float* times_ms, void* stream);
+
+/* Apply the entries of a cache written by odf_autotune or odf_autotune_batch
+ * whose architecture matches the current device; returns the number applied
+ * or ODF_EINVAL. */
 int odf_tune_load(const char* cache_path);
 
 #ifdef __cplusplus

@@ -9,14 +9,18 @@
 // one grid instead of a few short ones and their tails.  The pair-term
 // variants of one window share a register budget (3x3: 64 VGPRs); windows
 // and kinds do not (a kernel branching over 3x3 and 5x5 would carry the 5x5
-// budget everywhere), so they keep kernels of their own.  odf_batch_launch
-// enqueues (persistent form) a counter reset kernel on the caller's stream,
-// then the group kernels, forked onto per-plan auxiliary streams (default priority) and
-// joined back with events so that groups run concurrently and their tails
-// overlap; it allocates nothing and never synchronises, so it can be captured
-// in a hipGraph.  Every tile writes only its own outputs with the same tile
-// function as the per-image kernels, so results do not depend on which
-// workgroup takes which tile.
+// budget everywhere), so they keep kernels of their own.  Each group runs one
+// workgroup per tile of its list, dispatched in list order, on the extended
+// tile shape of the batch tuning table (odf_autotune_batch times the four
+// shapes on a mixed list).  odf_batch_launch enqueues the group kernels,
+// forked onto per-plan auxiliary streams (default priority) and joined back
+// with events so that groups run concurrently and their tails overlap; it
+// allocates nothing and never synchronises, so it can be captured in a
+// hipGraph.  Every tile writes only its own outputs with the same tile
+// function as the per-image kernels, so results do not depend on the shape or
+// on which workgroup takes which tile.
+#include <stdio.h>
+
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -44,19 +48,14 @@ struct BatchTile {
 struct BatchClass {
     const BatchJob* jobs;
     const BatchTile* tiles;
-    int* counter;
     int ntiles;
 };
 
-// Extended-tile shapes of the batch kernels: 0 = 32 x 32, 1 = 32 x 16.  The
-// persistent form uses 32 x 32 for 3x3 and 32 x 16 for 5x5 (its loop needs
-// more registers than a 1024-thread 5x5 tile allows); the direct form takes
-// the shape the tuning table holds for the class (1024-thread entries map to
-// 32 x 32, 512-thread ones to 32 x 16).
-template <int SHAPE>
+// Extended-tile shape CFG of the batch kernels: the per-image table's shapes.
+template <int CFG>
 struct BatchShape {
-    static constexpr int EXT_W = 32;
-    static constexpr int EXT_H = SHAPE == 0 ? 32 : 16;
+    static constexpr int EXT_W = kTileW[CFG];
+    static constexpr int EXT_H = kTileH[CFG];
     static constexpr int THREADS = EXT_W * EXT_H;
 };
 
@@ -76,11 +75,11 @@ __device__ __forceinline__ T* uni(T* v) {
 
 // Filter tile t of a group work list (all fields are uniform over the
 // workgroup and are moved to scalar registers).
-template <int W, int KIND, int DIST, int SHAPE>
+template <int W, int KIND, int DIST, int CFG>
 __device__ __forceinline__ void batch_tile(
-    FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W, BatchShape<SHAPE>::EXT_H, false>& sh,
+    FwdSharedFor<W, KIND, DIST, true, BatchShape<CFG>::EXT_W, BatchShape<CFG>::EXT_H, false>& sh,
     const BatchClass& bc, const BatchTile& tile) {
-    constexpr int EXT_W = BatchShape<SHAPE>::EXT_W, EXT_H = BatchShape<SHAPE>::EXT_H;
+    constexpr int EXT_W = BatchShape<CFG>::EXT_W, EXT_H = BatchShape<CFG>::EXT_H;
     const BatchJob& job = bc.jobs[uni(tile.job)];
     FwdParams prm{};
     prm.img = uni(job.img);
@@ -95,118 +94,73 @@ __device__ __forceinline__ void batch_tile(
         prm.coef.asin_c[k] = uni(job.coef.asin_c[k]);
         prm.coef.acos_c[k] = uni(job.coef.acos_c[k]);
     }
-    // an opaque copy of the thread index keeps the tile's address arithmetic
-    // inside a persistent loop instead of hoisted and held in registers
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    fwd_tile<W, KIND, DIST, true, EXT_W, EXT_H, false>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0), tid);
+    fwd_tile<W, KIND, DIST, true, EXT_W, EXT_H, false>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0),
+                                                       threadIdx.x);
 }
 
 // LDS of a group kernel: room for the tile of any pair term.
-template <int W, int KIND, int SHAPE>
+template <int W, int KIND, int CFG>
 struct BatchSmem {
     template <int DIST>
-    using Sh = FwdSharedFor<W, KIND, DIST, true, BatchShape<SHAPE>::EXT_W,
-                            BatchShape<SHAPE>::EXT_H, false>;
+    using Sh = FwdSharedFor<W, KIND, DIST, true, BatchShape<CFG>::EXT_W,
+                            BatchShape<CFG>::EXT_H, false>;
     static constexpr size_t a = sizeof(Sh<kExact>), b = sizeof(Sh<kMinimax>),
                             c = sizeof(Sh<kRgb>);
     static constexpr size_t BYTES = a > b ? (a > c ? a : c) : (b > c ? b : c);
 };
 
-// Tile t of a group list: its pair term comes from the job (uniform branch).
-template <int W, int KIND, int SHAPE>
-__device__ __forceinline__ void batch_tile_any(char* smem, const BatchClass& bc, int t) {
-    const BatchTile tile = bc.tiles[t];
-    const int dist = uni(bc.jobs[uni(tile.job)].dist);
-    using S = BatchSmem<W, KIND, SHAPE>;
-    if (dist == kExact)
-        batch_tile<W, KIND, kExact, SHAPE>(*reinterpret_cast<typename S::template Sh<kExact>*>(smem),
-                                           bc, tile);
-    else if (dist == kMinimax)
-        batch_tile<W, KIND, kMinimax, SHAPE>(
-            *reinterpret_cast<typename S::template Sh<kMinimax>*>(smem), bc, tile);
-    else
-        batch_tile<W, KIND, kRgb, SHAPE>(*reinterpret_cast<typename S::template Sh<kRgb>*>(smem),
-                                         bc, tile);
-}
-
-template <int W>
-constexpr int persistent_shape() {
-    return W == 5 ? 1 : 0;
-}
-
-// Persistent form: workgroups take tiles with an atomic counter until the
-// list is exhausted.
-template <int W, int KIND>
-__global__ void __launch_bounds__(BatchShape<persistent_shape<W>()>::THREADS)
-    batch_kernel(BatchClass bc) {
-    constexpr int SHAPE = persistent_shape<W>();
-    __shared__ __align__(16) char smem[BatchSmem<W, KIND, SHAPE>::BYTES];
-    __shared__ int s_tile;
-    for (;;) {
-        __syncthreads();  // the previous tile is finished with s_tile and smem
-        if (threadIdx.x == 0) s_tile = atomicAdd(bc.counter, 1);
-        __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_tile);
-        if (t >= bc.ntiles) break;
-        batch_tile_any<W, KIND, SHAPE>(smem, bc, t);
-    }
-}
-
-// Direct form: one workgroup per tile of the list, dispatched in list order.
-template <int W, int KIND, int SHAPE>
-__global__ void __launch_bounds__(BatchShape<SHAPE>::THREADS)
-    __attribute__((amdgpu_waves_per_eu(W == 3 && KIND != kACW ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
-    __shared__ __align__(16) char smem[BatchSmem<W, KIND, SHAPE>::BYTES];
+// One workgroup per tile of the list, dispatched in list order; the tile's
+// pair term comes from its job (uniform branch).  The register targets are
+// the per-image kernels' for 3x3 (64 VGPRs); the 5x5 groups hold all three
+// pair terms, whose budgets differ, and take none.
+template <int W, int KIND, int CFG>
+__global__ void __launch_bounds__(BatchShape<CFG>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(W == 3 ? 8 : 1))) batch_direct_kernel(BatchClass bc) {
+    __shared__ __align__(16) char smem[BatchSmem<W, KIND, CFG>::BYTES];
     const int t = flat_block(bc.ntiles);
     if (t < 0) return;
-    batch_tile_any<W, KIND, SHAPE>(smem, bc, t);
-}
-
-__global__ void batch_reset(int* counters, int n) {
-    if (threadIdx.x < n) counters[threadIdx.x] = 0;
+    const BatchTile tile = bc.tiles[t];
+    const int dist = uni(bc.jobs[uni(tile.job)].dist);
+    using S = BatchSmem<W, KIND, CFG>;
+    if (dist == kExact)
+        batch_tile<W, KIND, kExact, CFG>(*reinterpret_cast<typename S::template Sh<kExact>*>(smem),
+                                         bc, tile);
+    else if (dist == kMinimax)
+        batch_tile<W, KIND, kMinimax, CFG>(
+            *reinterpret_cast<typename S::template Sh<kMinimax>*>(smem), bc, tile);
+    else
+        batch_tile<W, KIND, kRgb, CFG>(*reinterpret_cast<typename S::template Sh<kRgb>*>(smem),
+                                       bc, tile);
 }
 
 // class = ((window == 5) * 2 + kind) * 3 + dist; group = class / 3
 constexpr int kNumGroups = kNumClasses / 3;
 static int group_window(int grp) { return grp / 2 ? 5 : 3; }
 
-static void group_geometry(int grp, int shape, int& tw, int& th, int& threads) {
+static void group_geometry(int grp, int cfg, int& tw, int& th, int& threads) {
     const int h = group_window(grp) / 2;
-    tw = BatchShape<0>::EXT_W - 2 * h;
-    th = (shape == 0 ? BatchShape<0>::EXT_H : BatchShape<1>::EXT_H) - 2 * h;
-    threads = shape == 0 ? BatchShape<0>::THREADS : BatchShape<1>::THREADS;
-}
-
-static const void* persistent_kernel(int grp) {
-    switch (grp) {
-    case 0: return reinterpret_cast<const void*>(&batch_kernel<3, kBVDF>);
-    case 1: return reinterpret_cast<const void*>(&batch_kernel<3, kDDF>);
-    case 2: return reinterpret_cast<const void*>(&batch_kernel<5, kBVDF>);
-    default: return reinterpret_cast<const void*>(&batch_kernel<5, kDDF>);
-    }
+    tw = kTileW[cfg] - 2 * h;
+    th = kTileH[cfg] - 2 * h;
+    threads = kTileW[cfg] * kTileH[cfg];
 }
 
 template <int W, int KIND>
-static void launch_group_wk(bool direct, int shape, int grid, int threads, const BatchClass& bc,
-                            hipStream_t s) {
-    if (!direct)
-        hipLaunchKernelGGL((batch_kernel<W, KIND>), dim3(grid), dim3(threads), 0, s, bc);
-    else if (shape == 0)
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), flat_grid(bc.ntiles), dim3(threads),
-                           0, s, bc);
-    else
-        hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), flat_grid(bc.ntiles), dim3(threads),
-                           0, s, bc);
+static void launch_group_wk(int cfg, int threads, const BatchClass& bc, hipStream_t s) {
+    const dim3 grid = flat_grid(bc.ntiles);
+    switch (cfg) {
+    case 0: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), grid, dim3(threads), 0, s, bc); break;
+    case 1: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), grid, dim3(threads), 0, s, bc); break;
+    case 2: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 2>), grid, dim3(threads), 0, s, bc); break;
+    default: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 3>), grid, dim3(threads), 0, s, bc); break;
+    }
 }
 
-static void launch_group(int grp, bool direct, int shape, int grid, int threads,
-                         const BatchClass& bc, hipStream_t s) {
+static void launch_group(int grp, int cfg, int threads, const BatchClass& bc, hipStream_t s) {
     switch (grp) {
-    case 0: launch_group_wk<3, kBVDF>(direct, shape, grid, threads, bc, s); break;
-    case 1: launch_group_wk<3, kDDF>(direct, shape, grid, threads, bc, s); break;
-    case 2: launch_group_wk<5, kBVDF>(direct, shape, grid, threads, bc, s); break;
-    default: launch_group_wk<5, kDDF>(direct, shape, grid, threads, bc, s); break;
+    case 0: launch_group_wk<3, kBVDF>(cfg, threads, bc, s); break;
+    case 1: launch_group_wk<3, kDDF>(cfg, threads, bc, s); break;
+    case 2: launch_group_wk<5, kBVDF>(cfg, threads, bc, s); break;
+    default: launch_group_wk<5, kDDF>(cfg, threads, bc, s); break;
     }
 }
 
@@ -216,15 +170,12 @@ static void launch_group(int grp, bool direct, int shape, int grid, int threads,
 struct odf_plan {
     odf::BatchJob* d_jobs = nullptr;
     odf::BatchTile* d_tiles = nullptr;
-    int* d_counters = nullptr;
     int class_tiles[odf::kNumClasses] = {};  // per class, for odf_plan_info
     int ntiles[odf::kNumGroups] = {};
     int offset[odf::kNumGroups] = {};
-    int grid[odf::kNumGroups] = {};
-    int shape[odf::kNumGroups] = {};
+    int cfg[odf::kNumGroups] = {};  // tile shape of each group
     int njobs = 0;
     long long npix = 0;
-    int flags = 0;
     hipStream_t aux[odf::kNumGroups] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[odf::kNumGroups] = {};
@@ -233,18 +184,6 @@ struct odf_plan {
 namespace {
 
 int bfail(int code, const char* msg) { return odf::set_error(code, "%s", msg); }
-
-// Tile shape of a group.  A plan is one launch over many tiles, so the shape
-// with the best steady-state rate wins (measured on MI355X on 3840 x 2160
-// frames: 32 x 32 for 3x3 DDF, 32 x 16 for 3x3 BVDF and for 5x5); the
-// per-image tuning table, chosen where a single image's last partial wave of
-// workgroups matters, is not consulted.  The persistent form's loop needs
-// 32 x 16 for 5x5 (registers).
-int shape_of(int grp, int flags) {
-    const int w = odf::group_window(grp);
-    if (flags != ODF_BATCH_DIRECT) return w == 5 ? 1 : 0;
-    return (w == 3 && grp % 2 == ODF_DDF) ? 0 : 1;
-}
 
 // Relative cost of a tile pixel per pair term (3x3 DDF instruction counts),
 // used to put the heaviest tiles first.
@@ -259,22 +198,12 @@ void destroy(odf_plan* p) {
     if (p->fork) (void)hipEventDestroy(p->fork);
     (void)hipFree(p->d_jobs);
     (void)hipFree(p->d_tiles);
-    (void)hipFree(p->d_counters);
     delete p;
 }
 
-}  // namespace
-
-extern "C" {
-
-int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream) {
-    return odf_batch_plan_ex(jobs, njobs, ODF_BATCH_DIRECT, plan, stream);
-}
-
-int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream) {
-    (void)stream;
-    if (flags != ODF_BATCH_PERSISTENT && flags != ODF_BATCH_DIRECT)
-        return bfail(ODF_EINVAL, "flags must be ODF_BATCH_PERSISTENT or ODF_BATCH_DIRECT");
+// Validate the jobs and build a plan whose groups run on the tile shapes cfg
+// (one per group).
+int make_plan(const odf_job* jobs, int njobs, const int* cfg, odf_plan** plan) {
     if (!plan) return bfail(ODF_EINVAL, "plan is NULL");
     *plan = nullptr;
     if (!jobs || njobs < 1) return bfail(ODF_EINVAL, "jobs must be a non-empty array");
@@ -294,8 +223,6 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         const char* o = (const char*)j.out;
         if (a < o + nb && o < a + nb) return bfail(ODF_EINVAL, "job out overlaps img");
     }
-    int shape[odf::kNumGroups];
-    for (int g = 0; g < odf::kNumGroups; ++g) shape[g] = shape_of(g, flags);
 
     // (cost, tile) per group; cost = output pixels x pair-term weight
     std::vector<std::pair<long long, odf::BatchTile>> lists[odf::kNumGroups];
@@ -315,7 +242,7 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
         if (j.dist == ODF_MINIMAX) b.coef = odf::minimax_coef(j.q);
         const int grp = (j.window == 5) * 2 + (j.kind == ODF_DDF);
         int tw, th, thr;
-        odf::group_geometry(grp, shape[grp], tw, th, thr);
+        odf::group_geometry(grp, cfg[grp], tw, th, thr);
         for (int ty = 0; ty < j.M; ty += th)
             for (int tx = 0; tx < j.N; tx += tw) {
                 const long long cost = (long long)std::min(th, j.M - ty) * std::min(tw, j.N - tx) *
@@ -337,39 +264,18 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
                             const std::pair<long long, odf::BatchTile>& y) { return x.first > y.first; });
         p->offset[g] = (int)all.size();
         p->ntiles[g] = (int)lists[g].size();
+        p->cfg[g] = cfg[g];
         for (auto& t : lists[g]) all.push_back(t.second);
     }
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
-        destroy(p);
-        return bfail(ODF_EHIP, "cannot query the compute unit count");
-    }
-    for (int g = 0; g < odf::kNumGroups; ++g) {
-        int tw, th, thr, per_cu = 0;
-        p->shape[g] = shape[g];
-        odf::group_geometry(g, p->shape[g], tw, th, thr);
-        if (flags == ODF_BATCH_DIRECT) {
-            p->grid[g] = p->ntiles[g];
-            continue;
-        }
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, odf::persistent_kernel(g), thr,
-                                                         0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        p->grid[g] = std::min(p->ntiles[g], per_cu * cus);
-    }
     if (hipMalloc(&p->d_jobs, sizeof(odf::BatchJob) * hj.size()) != hipSuccess ||
-        hipMalloc(&p->d_tiles, sizeof(odf::BatchTile) * std::max<size_t>(1, all.size())) != hipSuccess ||
-        hipMalloc(&p->d_counters, sizeof(int) * odf::kNumGroups) != hipSuccess) {
+        hipMalloc(&p->d_tiles, sizeof(odf::BatchTile) * std::max<size_t>(1, all.size())) != hipSuccess) {
         destroy(p);
         return bfail(ODF_ENOMEM, "device allocation for the plan failed");
     }
     if (hipMemcpy(p->d_jobs, hj.data(), sizeof(odf::BatchJob) * hj.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(p->d_tiles, all.data(), sizeof(odf::BatchTile) * all.size(), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemset(p->d_counters, 0, sizeof(int) * odf::kNumGroups) != hipSuccess) {
+            hipSuccess) {
         destroy(p);
         return bfail(ODF_EHIP, "uploading the plan failed");
     }
@@ -390,29 +296,107 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
     }
     p->njobs = njobs;
     p->npix = npix;
-    p->flags = flags;
     *plan = p;
     return ODF_OK;
+}
+
+// Time the four tile shapes of group grp on the jobs of that group among
+// jobs[] (reps launches each after two untimed ones); ms[c] = -1 when the
+// group has no job.  Returns ODF_OK or an error code (message set).
+int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* ms,
+                      hipStream_t s) {
+    std::vector<odf_job> sub;
+    for (int i = 0; i < njobs; ++i)
+        if ((jobs[i].window == 5) * 2 + (jobs[i].kind == ODF_DDF) == grp) sub.push_back(jobs[i]);
+    for (int c = 0; c < odf::kNumTileShapes; ++c) ms[c] = -1.0f;
+    if (sub.empty()) return ODF_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return bfail(ODF_EHIP, "autotune_batch: event creation failed");
+    }
+    int rc = ODF_OK;
+    for (int c = 0; c < odf::kNumTileShapes && rc == ODF_OK; ++c) {
+        int cfg[odf::kNumGroups];
+        for (int g = 0; g < odf::kNumGroups; ++g) cfg[g] = odf::batch_tuned_config(g);
+        cfg[grp] = c;
+        odf_plan* plan = nullptr;
+        rc = make_plan(sub.data(), (int)sub.size(), cfg, &plan);
+        if (rc != ODF_OK) break;
+        bool ok = odf_batch_launch(plan, s) == ODF_OK && odf_batch_launch(plan, s) == ODF_OK &&
+                  hipEventRecord(e0, s) == hipSuccess;
+        for (int r = 0; r < reps; ++r) ok = ok && odf_batch_launch(plan, s) == ODF_OK;
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float t = 0.0f;
+        ok = ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+        destroy(plan);
+        if (!ok) rc = bfail(ODF_EHIP, "autotune_batch: timing failed");
+        else ms[c] = t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+// The fastest shape of ms[4] (ignoring -1), or -1.
+int fastest(const float* ms) {
+    int best = -1;
+    for (int c = 0; c < odf::kNumTileShapes; ++c)
+        if (ms[c] >= 0.0f && (best < 0 || ms[c] < ms[best])) best = c;
+    return best;
+}
+
+// Append the batch tuning line of group grp to cache_path.
+int write_batch_line(const char* cache_path, int grp, int best, const float* ms) {
+    if (!cache_path) return ODF_OK;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return bfail(ODF_EHIP, "autotune_batch: device query failed");
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return odf::set_error(ODF_EINVAL, "cannot open %s", cache_path);
+    fprintf(f,
+            "{\"arch\": \"%s\", \"batch_window\": %d, \"kind\": %d, \"config\": %d, "
+            "\"ms\": [%.5f, %.5f, %.5f, %.5f]}\n",
+            prop.gcnArchName, odf::group_window(grp), grp % 2, best, ms[0], ms[1], ms[2], ms[3]);
+    fclose(f);
+    return ODF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int odf_batch_plan(const odf_job* jobs, int njobs, odf_plan** plan, void* stream) {
+    (void)stream;
+    int cfg[odf::kNumGroups];
+    for (int g = 0; g < odf::kNumGroups; ++g) cfg[g] = odf::batch_tuned_config(g);
+    return make_plan(jobs, njobs, cfg, plan);
+}
+
+int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan, void* stream) {
+    if (plan) *plan = nullptr;
+    if (flags == ODF_BATCH_PERSISTENT)
+        return bfail(ODF_EUNSUPPORTED,
+                     "the persistent batch form is retired: the direct form runs the groups at "
+                     "the kernels' own steady-state rate");
+    if (flags != ODF_BATCH_DIRECT) return bfail(ODF_EINVAL, "flags must be ODF_BATCH_DIRECT");
+    return odf_batch_plan(jobs, njobs, plan, stream);
 }
 
 int odf_batch_launch(const odf_plan* plan, void* stream) {
     if (!plan) return bfail(ODF_EINVAL, "plan is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool direct = plan->flags == ODF_BATCH_DIRECT;
-    if (!direct)  // the persistent kernels' tile counters start at 0
-        hipLaunchKernelGGL(odf::batch_reset, dim3(1), dim3(64), 0, s, plan->d_counters,
-                           odf::kNumGroups);
     if (hipEventRecord(plan->fork, s) != hipSuccess) return bfail(ODF_EHIP, "fork event failed");
     for (int g = 0; g < odf::kNumGroups; ++g) {
         if (plan->ntiles[g] == 0) continue;
-        odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[g], plan->d_counters + g,
-                           plan->ntiles[g]};
+        odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[g], plan->ntiles[g]};
         int tw, th, thr;
-        odf::group_geometry(g, plan->shape[g], tw, th, thr);
+        odf::group_geometry(g, plan->cfg[g], tw, th, thr);
         hipStream_t cs = plan->aux[g] ? plan->aux[g] : s;
         if (cs != s && hipStreamWaitEvent(cs, plan->fork, 0) != hipSuccess)
             return bfail(ODF_EHIP, "stream fork failed");
-        odf::launch_group(g, direct, plan->shape[g], plan->grid[g], thr, bc, cs);
+        odf::launch_group(g, plan->cfg[g], thr, bc, cs);
         if (cs != s && (hipEventRecord(plan->join[g], cs) != hipSuccess ||
                         hipStreamWaitEvent(s, plan->join[g], 0) != hipSuccess))
             return bfail(ODF_EHIP, "stream join failed");
@@ -427,13 +411,92 @@ int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles
     if (njobs) *njobs = plan->njobs;
     if (npix) *npix = plan->npix;
     for (int c = 0; c < odf::kNumClasses; ++c) {
-        const int g = c / 3;
         if (ntiles) ntiles[c] = plan->class_tiles[c];
-        // workgroups launched for the class's tiles: one per tile (direct) or
-        // the grid of its group's persistent kernel
-        if (grids)
-            grids[c] = plan->class_tiles[c] == 0 ? 0
-                       : (plan->flags == ODF_BATCH_DIRECT ? plan->class_tiles[c] : plan->grid[g]);
+        if (grids) grids[c] = plan->class_tiles[c];  // one workgroup per tile
+    }
+    return ODF_OK;
+}
+
+int odf_plan_configs(const odf_plan* plan, int* configs) {
+    if (!plan || !configs) return ODF_EINVAL;
+    for (int g = 0; g < odf::kNumGroups; ++g) configs[g] = plan->cfg[g];
+    return ODF_OK;
+}
+
+int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, float* times_ms,
+                       void* stream) {
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || reps < 1)
+        return odf::set_error(ODF_EINVAL, "autotune_batch: arguments out of range");
+    const int grp = (window == 5) * 2 + (kind == ODF_DDF);
+    // a mixed work list: frames and small images of several aspect ratios,
+    // each with every pair term
+    static const int kSizes[][2] = {{1080, 1920}, {720, 1280}, {512, 512}, {300, 400},
+                                    {131, 97}, {64, 64}};
+    constexpr int kImages = sizeof(kSizes) / sizeof(kSizes[0]);
+    size_t off[kImages + 1] = {0};
+    for (int i = 0; i < kImages; ++i) off[i + 1] = off[i] + (size_t)kSizes[i][0] * kSizes[i][1] * 3;
+    std::vector<uint8_t> host;
+    try {  // no exception crosses the C ABI
+        host.resize(off[kImages]);
+    } catch (...) {
+        return odf::set_error(ODF_ENOMEM, "autotune_batch: host allocation failed");
+    }
+    for (int i = 0; i < kImages; ++i)
+        odf::tuning_image(kSizes[i][0], kSizes[i][1], 2009 + i, host.data() + off[i]);
+    uint8_t *img = nullptr, *out = nullptr;
+    float ms[odf::kNumTileShapes];
+    int rc = ODF_OK, best = -1;
+    std::vector<odf_job> jobs;
+    if (odf::test_fail_alloc() || hipMalloc(&img, off[kImages]) != hipSuccess ||
+        hipMalloc(&out, 3 * off[kImages]) != hipSuccess) {
+        rc = odf::set_error(ODF_ENOMEM, "autotune_batch: device allocation failed");
+        goto done;
+    }
+    if (hipMemcpy(img, host.data(), off[kImages], hipMemcpyHostToDevice) != hipSuccess) {
+        rc = odf::set_error(ODF_EHIP, "autotune_batch: upload failed");
+        goto done;
+    }
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < kImages; ++i)
+            jobs.push_back(odf_job{img + off[i], out + off[kImages] * d + off[i], nullptr,
+                                   kSizes[i][0], kSizes[i][1], window, kind, d, 4, 0.25f});
+    rc = time_group_shapes(jobs.data(), (int)jobs.size(), grp, reps, ms,
+                           static_cast<hipStream_t>(stream));
+    if (rc != ODF_OK) goto done;
+    best = fastest(ms);
+    odf::set_batch_tuned_config(grp, best);
+    if (times_ms)
+        for (int c = 0; c < odf::kNumTileShapes; ++c) times_ms[c] = ms[c];
+    rc = write_batch_line(cache_path, grp, best, ms);
+done:
+    if (img) (void)hipFree(img);
+    if (out) (void)hipFree(out);
+    return rc;
+}
+
+int odf_autotune_batch_jobs(const odf_job* jobs, int njobs, int reps, const char* cache_path,
+                            float* times_ms, void* stream) {
+    if (reps < 1) return odf::set_error(ODF_EINVAL, "autotune_batch_jobs: reps must be >= 1");
+    if (odf::test_fail_alloc())
+        return odf::set_error(ODF_ENOMEM, "autotune_batch_jobs: allocation failed");
+    // validate every job once (a plan of the whole list, not launched)
+    int cfg[odf::kNumGroups];
+    for (int g = 0; g < odf::kNumGroups; ++g) cfg[g] = odf::batch_tuned_config(g);
+    odf_plan* probe = nullptr;
+    int rc = make_plan(jobs, njobs, cfg, &probe);
+    if (rc != ODF_OK) return rc;
+    destroy(probe);
+    for (int g = 0; g < odf::kNumGroups; ++g) {
+        float ms[odf::kNumTileShapes];
+        rc = time_group_shapes(jobs, njobs, g, reps, ms, static_cast<hipStream_t>(stream));
+        if (rc != ODF_OK) return rc;
+        if (times_ms)
+            for (int c = 0; c < odf::kNumTileShapes; ++c) times_ms[4 * g + c] = ms[c];
+        const int best = fastest(ms);
+        if (best < 0) continue;  // no job of this group
+        odf::set_batch_tuned_config(g, best);
+        rc = write_batch_line(cache_path, g, best, ms);
+        if (rc != ODF_OK) return rc;
     }
     return ODF_OK;
 }

@@ -4,11 +4,7 @@
 
 namespace odf {
 
-// Extended-tile shapes (EXT_W x EXT_H, one thread per extended pixel) the
-// autotuner chooses from.
-constexpr int kNumTileConfigs = 4;
-constexpr int kTileW[kNumTileConfigs] = {32, 64, 32, 64};
-constexpr int kTileH[kNumTileConfigs] = {32, 16, 16, 8};
+constexpr int kNumTileConfigs = kNumTileShapes;
 
 // 5x5 ACWDDF keeps four register sets of n values per thread (aggregates
 // and centre terms of both passes) and 7x7 keeps a 13 x 7 grid of row sums:

@@ -96,6 +96,19 @@ bool tile_config_valid(int window, int kind, int cfg);
 int tile_config_default(int window, int kind);
 void tile_config_shape(int cfg, int* ext_w, int* ext_h);
 constexpr int kNumTileShapes = 4;
+// Extended-tile shapes (EXT_W x EXT_H, one thread per extended pixel) the
+// autotuners choose from, for the per-image and the batch kernels alike.
+constexpr int kTileW[kNumTileShapes] = {32, 64, 32, 64};
+constexpr int kTileH[kNumTileShapes] = {32, 16, 16, 8};
+// The batch kernels' shape per group (window 3 / 5 x BVDF / DDF, group =
+// (window == 5) * 2 + kind): the process-wide batch tuning table.
+int batch_tuned_config(int group);
+void set_batch_tuned_config(int group, int cfg);
+// A seeded uint8 tuning image (M x N x 3): a smooth field of a few plane
+// waves per channel with 15 % of the pixels replaced by random colours, the
+// kind of content the filters meet (their branches -- the minimax z = 1/2
+// test, the zero-pixel fix-ups -- depend on it).
+void tuning_image(int M, int N, uint64_t seed, uint8_t* out);
 // Tile table entry of (window, kind, dist, input type), kind the C ABI's
 // odf_kind; kernel_kind maps an odf_kind to the kernels' Kind.
 int tuned_config(int window, int kind, int dist, bool u8);

@@ -1,11 +1,16 @@
-// tune.hip -- tile-shape table of the forward filter and its autotuner.
+// tune.hip -- tile-shape tables of the forward filter and the batch kernels,
+// and the per-image autotuner.
 //
-// The table maps (window, kind, dist, input type) to one of the extended-tile
-// shapes of fwd.hip.  odf_autotune times every valid shape on a seeded
-// random image with HIP events, keeps the fastest and records the timings in
-// a small JSON cache keyed by the GPU architecture; odf_tune_load reads such a
-// cache back.  The table is process-wide; updates are atomic per entry.
+// The per-image table maps (window, kind, dist, input type) to one of the
+// extended-tile shapes of odf_internal.h; the batch table maps each batch
+// group (window 3 / 5 x BVDF / DDF) to one.  odf_autotune times every valid
+// shape on a seeded tuning image with HIP events, keeps the fastest and
+// records the timings in a small JSON cache keyed by the GPU architecture
+// (odf_autotune_batch, in batch.hip, does the same for a batch group);
+// odf_tune_load reads such a cache back.  The tables are process-wide;
+// updates are atomic per entry.
 #include <atomic>
+#include <math.h>
 #include <mutex>
 #include <stdio.h>
 #include <string.h>
@@ -31,6 +36,10 @@ int window_slot(int window) { return window == 3 ? 0 : (window == 5 ? 1 : 2); }
 // one entry.
 int dist_slot(int kind, int dist) { return kind == ODF_CWVMF ? (int)kRgb : dist; }
 
+// Batch groups: 32 x 32 for 3x3 DDF and 32 x 16 otherwise until tuned (the
+// steady-state best measured on MI355X on 3840 x 2160 frames).
+std::atomic<int> g_batch[4];
+
 void ensure_init() {
     std::call_once(g_table_once, [] {
         for (int w = 0; w < 3; ++w)
@@ -38,10 +47,62 @@ void ensure_init() {
                 for (int d = 0; d < 3; ++d)
                     for (int u = 0; u < 2; ++u)
                         g_table[w][k][d][u].store(tile_config_default(3 + 2 * w, k));
+        for (int g = 0; g < 4; ++g) g_batch[g].store(g == 1 ? 0 : 2);
     });
 }
 
+// splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): seeded numbers for the tuning images
+uint64_t splitmix(uint64_t& s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double unit(uint64_t& s) { return (double)(splitmix(s) >> 11) * 0x1p-53; }
+
 }  // namespace
+
+int batch_tuned_config(int group) {
+    ensure_init();
+    return g_batch[group].load();
+}
+
+void set_batch_tuned_config(int group, int cfg) {
+    ensure_init();
+    g_batch[group].store(cfg);
+}
+
+void tuning_image(int M, int N, uint64_t seed, uint8_t* out) {
+    uint64_t s = seed;
+    double a[3][4], fx[3][4], fy[3][4], ph[3][4];
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 4; ++j) {
+            const double f = (1.0 / 96.0) + unit(s) * (1.0 / 24.0), th = unit(s) * 3.14159265;
+            a[k][j] = 0.5 + 0.5 * unit(s);
+            fx[k][j] = f * cos(th);
+            fy[k][j] = f * sin(th);
+            ph[k][j] = unit(s) * 6.28318531;
+        }
+    for (int r = 0; r < M; ++r)
+        for (int c = 0; c < N; ++c) {
+            uint8_t* px = out + ((size_t)r * N + c) * 3;
+            if (unit(s) < 0.15) {  // impulsive noise: a random colour
+                const uint64_t v = splitmix(s);
+                px[0] = (uint8_t)v; px[1] = (uint8_t)(v >> 8); px[2] = (uint8_t)(v >> 16);
+                continue;
+            }
+            for (int k = 0; k < 3; ++k) {
+                double v = 0.0, n = 0.0;
+                for (int j = 0; j < 4; ++j) {
+                    v += a[k][j] * sin(6.28318531 * (fx[k][j] * c + fy[k][j] * r) + ph[k][j]);
+                    n += a[k][j];
+                }
+                px[k] = (uint8_t)lrint(127.5 + 127.5 * v / n);
+            }
+        }
+}
 
 // kind: the C ABI's odf_kind (ODF_BVDF .. ODF_CWDDF)
 int tuned_config(int window, int kind, int dist, bool u8) {
@@ -67,14 +128,6 @@ int kernel_kind(int kind) {
 }  // namespace odf
 
 namespace {
-
-// splitmix64: seeded bytes for the tuning image
-uint64_t splitmix(uint64_t& s) {
-    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
 
 // A (window, kind, dist) class the library computes (the centre-weighted
 // kinds have no 7x7 kernels).
@@ -126,11 +179,9 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     } catch (...) {
         return odf::set_error(ODF_ENOMEM, "autotune: host allocation failed");
     }
-    uint64_t seed = 1009;
-    for (size_t i = 0; i < npix * 3; ++i) {
-        h8[i] = (uint8_t)(splitmix(seed) >> 56);
-        if (!is_u8) hf[i] = h8[i] / 255.0f;
-    }
+    odf::tuning_image(M, N, 1009, h8.data());
+    if (!is_u8)
+        for (size_t i = 0; i < npix * 3; ++i) hf[i] = h8[i] / 255.0f;
     void *img = nullptr, *out = nullptr;
     uint8_t* idx = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -213,6 +264,19 @@ done:
     return best >= 0 || rc != ODF_OK ? rc : ODF_EHIP;
 }
 
+int odf_batch_tune_get(int window, int kind) {
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF)) return ODF_EINVAL;
+    return odf::batch_tuned_config((window == 5) * 2 + kind);
+}
+
+int odf_batch_tune_set(int window, int kind, int config) {
+    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || config < 0 ||
+        config >= odf::kNumTileShapes)
+        return ODF_EINVAL;
+    odf::set_batch_tuned_config((window == 5) * 2 + kind, config);
+    return ODF_OK;
+}
+
 int odf_tune_load(const char* cache_path) {
     if (!cache_path) return ODF_EINVAL;
     FILE* f = fopen(cache_path, "r");
@@ -229,10 +293,16 @@ int odf_tune_load(const char* cache_path) {
         if (sscanf(line,
                    "{\"arch\": \"%127[^\"]\", \"window\": %d, \"kind\": %d, \"dist\": %d, "
                    "\"u8\": %d, \"config\": %d",
-                   arch, &w, &k, &d, &u, &c) != 6)
-            continue;  // malformed lines are ignored
-        if (have_dev && strcmp(arch, prop.gcnArchName) != 0) continue;
-        if (odf_tune_set(w, k, d, u, c) == ODF_OK) ++applied;
+                   arch, &w, &k, &d, &u, &c) == 6) {
+            if (have_dev && strcmp(arch, prop.gcnArchName) != 0) continue;
+            if (odf_tune_set(w, k, d, u, c) == ODF_OK) ++applied;
+        } else if (sscanf(line,
+                          "{\"arch\": \"%127[^\"]\", \"batch_window\": %d, \"kind\": %d, "
+                          "\"config\": %d",
+                          arch, &w, &k, &c) == 4) {
+            if (have_dev && strcmp(arch, prop.gcnArchName) != 0) continue;
+            if (odf_batch_tune_set(w, k, c) == ODF_OK) ++applied;
+        }  // other lines are ignored
     }
     fclose(f);
     return applied;

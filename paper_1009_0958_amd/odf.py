@@ -430,9 +430,15 @@ def _batch_lib():
         L.odf_tune_set.argtypes = [I, I, I, I, I]
         L.odf_autotune.argtypes = [I, I, I, I, I, I, I, ctypes.c_char_p, P, P]
         L.odf_tune_load.argtypes = [ctypes.c_char_p]
-        for name in ("odf_batch_plan", "odf_batch_plan_ex", "odf_batch_launch", "odf_plan_info", "odf_plan_destroy",
-                     "odf_tile_config", "odf_tune_get", "odf_tune_set", "odf_autotune",
-                     "odf_tune_load"):
+        L.odf_plan_configs.argtypes = [P, P]
+        L.odf_batch_tune_get.argtypes = [I, I]
+        L.odf_batch_tune_set.argtypes = [I, I, I]
+        L.odf_autotune_batch.argtypes = [I, I, I, ctypes.c_char_p, P, P]
+        L.odf_autotune_batch_jobs.argtypes = [P, I, I, ctypes.c_char_p, P, P]
+        for name in ("odf_batch_plan", "odf_batch_plan_ex", "odf_batch_launch", "odf_plan_info",
+                     "odf_plan_destroy", "odf_plan_configs", "odf_tile_config", "odf_tune_get",
+                     "odf_tune_set", "odf_autotune", "odf_tune_load", "odf_batch_tune_get",
+                     "odf_batch_tune_set", "odf_autotune_batch", "odf_autotune_batch_jobs"):
             getattr(L, name).restype = I
         L._batch_ready = True
     return L
@@ -441,40 +447,47 @@ def _batch_lib():
 NUM_CLASSES = 12  # ((window == 5) * 2 + kind) * 3 + dist
 
 
+def _job_array(jobs):
+    """The C job array of a list of job dicts (checked), and the tensors it
+    points into (kept alive by the caller)."""
+    keep = []
+    arr = (_Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        img, out, idx = j["img"], j["out"], j.get("idx")
+        for t, name in ((img, "img"), (out, "out")):
+            _check_tensor(t, name)
+            if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[-1] != 3:
+                raise ValueError("batch %s must be an (M, N, 3) uint8 tensor" % name)
+        if out.shape != img.shape:
+            raise ValueError("out must have the shape of img")
+        if idx is not None:
+            _check_tensor(idx, "idx")
+            if idx.dtype != torch.uint8 or idx.numel() != img.shape[0] * img.shape[1]:
+                raise ValueError("idx must be uint8 with M*N elements")
+        keep.extend([img, out, idx])
+        M, N, _ = img.shape
+        arr[i] = _Job(img.data_ptr(), out.data_ptr(), 0 if idx is None else idx.data_ptr(),
+                      M, N, int(j.get("window", 3)), _kind(j.get("kind", BVDF)),
+                      _dist(j.get("dist", EXACT)), int(j.get("q", 4)), float(j.get("p", 0.5)))
+    return arr, keep
+
+
 class BatchPlan:
     """A planned batch of uint8 jobs; ``launch()`` enqueues it on the current
     stream (graph-capturable), ``capture()`` records it in a CUDA/HIP graph.
 
     jobs: iterable of dicts with keys img, out, idx (tensors; idx may be None),
-    window, kind, p, dist, q.  direct=True (default): one workgroup per tile;
-    direct=False: persistent workgroups with an atomic tile counter.
+    window, kind, p, dist, q.  One workgroup per tile, on each group's shape
+    from the batch tuning table (``batch_tune_get``, ``autotune_batch``).
     """
 
-    def __init__(self, jobs, direct=True):
-        self._keep = []
-        arr = (_Job * len(jobs))()
-        for i, j in enumerate(jobs):
-            img, out, idx = j["img"], j["out"], j.get("idx")
-            for t, name in ((img, "img"), (out, "out")):
-                _check_tensor(t, name)
-                if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[-1] != 3:
-                    raise ValueError("batch %s must be an (M, N, 3) uint8 tensor" % name)
-            if out.shape != img.shape:
-                raise ValueError("out must have the shape of img")
-            if idx is not None:
-                _check_tensor(idx, "idx")
-                if idx.dtype != torch.uint8 or idx.numel() != img.shape[0] * img.shape[1]:
-                    raise ValueError("idx must be uint8 with M*N elements")
-            self._keep.extend([img, out, idx])
-            M, N, _ = img.shape
-            arr[i] = _Job(img.data_ptr(), out.data_ptr(), 0 if idx is None else idx.data_ptr(),
-                          M, N, int(j.get("window", 3)), _kind(j.get("kind", BVDF)),
-                          _dist(j.get("dist", EXACT)), int(j.get("q", 4)), float(j.get("p", 0.5)))
+    def __init__(self, jobs):
+        arr, self._keep = _job_array(jobs)
         self._jobs = arr
         self._plan = ctypes.c_void_p()
         L = _batch_lib()
-        _check(L.odf_batch_plan_ex(ctypes.cast(arr, ctypes.c_void_p), len(jobs), int(bool(direct)),
-                                   ctypes.byref(self._plan), _stream(torch.cuda.current_device())))
+        _check(L.odf_batch_plan(ctypes.cast(arr, ctypes.c_void_p), len(jobs),
+                                ctypes.byref(self._plan), _stream(torch.cuda.current_device())))
 
     def launch(self):
         _check(_batch_lib().odf_batch_launch(self._plan, _stream(torch.cuda.current_device())))
@@ -494,7 +507,12 @@ class BatchPlan:
         _check(_batch_lib().odf_plan_info(self._plan, ctypes.byref(nj), ctypes.byref(npix),
                                           ctypes.cast(tiles, ctypes.c_void_p),
                                           ctypes.cast(grids, ctypes.c_void_p)))
-        return {"jobs": nj.value, "pixels": npix.value, "tiles": list(tiles), "grids": list(grids)}
+        cfg = (ctypes.c_int * 4)()
+        _check(_batch_lib().odf_plan_configs(self._plan, ctypes.cast(cfg, ctypes.c_void_p)))
+        return {"jobs": nj.value, "pixels": npix.value, "tiles": list(tiles), "grids": list(grids),
+                "configs": list(cfg),
+                "ext_tiles": {"w%d_%s" % (3 + 2 * (g // 2), ("bvdf", "ddf")[g % 2]):
+                              tile_config(cfg[g]) for g in range(4)}}
 
     def close(self):
         if self._plan:
@@ -532,6 +550,48 @@ def autotune(window, kind, dist, is_u8=True, M=1024, N=1024, reps=10, cache_path
                                      path, ctypes.cast(times, ctypes.c_void_p),
                                      _stream(torch.cuda.current_device())))
     return tune_get(window, kind, dist, is_u8), list(times)
+
+
+def batch_tune_get(window, kind):
+    rc = _batch_lib().odf_batch_tune_get(window, _kind(kind))
+    if rc < 0:
+        raise ODFError(rc, "no batch group for window %d kind %s" % (window, kind))
+    return rc
+
+
+def batch_tune_set(window, kind, config):
+    _check(_batch_lib().odf_batch_tune_set(window, _kind(kind), config))
+
+
+def autotune_batch(window, kind, reps=3, cache_path=None):
+    """Time the batch group's four tile shapes on a mixed work list, keep the
+    fastest; returns (best, [ms per shape])."""
+    times = (ctypes.c_float * 4)()
+    path = None if cache_path is None else cache_path.encode()
+    _check(_batch_lib().odf_autotune_batch(window, _kind(kind), reps, path,
+                                           ctypes.cast(times, ctypes.c_void_p),
+                                           _stream(torch.cuda.current_device())))
+    return batch_tune_get(window, kind), list(times)
+
+
+def autotune_batch_jobs(jobs, reps=2, cache_path=None):
+    """Time every batch group's four tile shapes on these jobs (their outputs
+    are written), keep the fastest per group; returns {group name: (best,
+    [ms per shape])} for the groups that hold jobs."""
+    arr, keep = _job_array(jobs)
+    times = (ctypes.c_float * 16)()
+    path = None if cache_path is None else cache_path.encode()
+    _check(_batch_lib().odf_autotune_batch_jobs(ctypes.cast(arr, ctypes.c_void_p), len(jobs), reps,
+                                                path, ctypes.cast(times, ctypes.c_void_p),
+                                                _stream(torch.cuda.current_device())))
+    res = {}
+    for g in range(4):
+        ms = list(times[4 * g:4 * g + 4])
+        if ms[0] >= 0:
+            w, k = 3 + 2 * (g // 2), g % 2
+            res["w%d_%s" % (w, ("bvdf", "ddf")[k])] = (batch_tune_get(w, k), ms)
+    del keep
+    return res
 
 
 def tune_load(cache_path):

@@ -110,6 +110,26 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
+    # batch tuning table: defaults, range checks, and the retired persistent form
+    assert L.odf_batch_tune_get(3, odf.DDF) == 0 and L.odf_batch_tune_get(5, odf.BVDF) == 2
+    assert L.odf_batch_tune_get(7, odf.DDF) == odf.EINVAL
+    assert L.odf_batch_tune_get(3, odf.ACWDDF) == odf.EINVAL
+    assert L.odf_batch_tune_set(3, odf.BVDF, 4) == odf.EINVAL
+    assert L.odf_batch_tune_set(5, odf.DDF, -1) == odf.EINVAL
+    assert L.odf_batch_tune_set(5, odf.DDF, 1) == odf.OK and L.odf_batch_tune_get(5, odf.DDF) == 1
+    assert L.odf_batch_tune_set(5, odf.DDF, 2) == odf.OK
+    assert L.odf_autotune_batch(7, 0, 1, None, None, None) == odf.EINVAL
+    assert L.odf_autotune_batch(3, 0, 0, None, None, None) == odf.EINVAL
+    jobs = (odf._Job * 1)()
+    assert L.odf_autotune_batch_jobs(None, 1, 2, None, None, None) == odf.EINVAL
+    assert L.odf_autotune_batch_jobs(ctypes.cast(jobs, ctypes.c_void_p), 1, 0, None, None,
+                                     None) == odf.EINVAL
+    assert L.odf_plan_configs(None, None) == odf.EINVAL
+    assert L.odf_batch_plan_ex(ctypes.cast(jobs, ctypes.c_void_p), 1, 0, ctypes.byref(plan),
+                               None) == odf.EUNSUPPORTED
+    assert "retired" in odf.last_error() and not plan.value
+    assert L.odf_batch_plan_ex(ctypes.cast(jobs, ctypes.c_void_p), 1, 7, ctypes.byref(plan),
+                               None) == odf.EINVAL
 
 
 @pytest.mark.parametrize("args,code,text", [
@@ -265,9 +285,14 @@ def test_allocation_failure_reports_enomem(monkeypatch):
                               (7, odf.BVDF, odf.RGB, 1)):
         rc = L.odf_autotune(w, kind, dist, u8, 64, 64, 2, None, ct.cast(times, ct.c_void_p), None)
         assert rc == odf.ENOMEM and "allocation" in odf.last_error()
+    rc = L.odf_autotune_batch(5, odf.DDF, 2, None, ct.cast(times, ct.c_void_p), None)
+    assert rc == odf.ENOMEM and "allocation" in odf.last_error()
+    rc = L.odf_autotune_batch_jobs(ct.cast(jobs, ct.c_void_p), 2, 2, None, None, None)
+    assert rc == odf.ENOMEM and "allocation" in odf.last_error()
     # validation still comes first
     rc = L.odf_autotune(9, odf.DDF, odf.EXACT, 1, 64, 64, 2, None, None, None)
     assert rc == odf.EINVAL
+    assert L.odf_autotune_batch(9, odf.DDF, 2, None, None, None) == odf.EINVAL
     monkeypatch.setenv("ODF_TEST_FAIL_ALLOC", "0")
     bad = (_Job * 1)()
     bad[0] = _Job(0, 0x7F0000100000, 0, 40, 50, 3, 1, 0, 4, 0.25)

@@ -1,6 +1,7 @@
-"""GPU tests of the batched persistent launch, its graph capture and the
-tile-shape autotuner: results must be bitwise those of the per-image filter
-(and so of the oracle up to near-ties), whatever the tile shape or schedule."""
+"""GPU tests of the batched launch, its graph capture and the tile-shape
+autotuners (per image and per batch group): results must be bitwise those of
+the per-image filter (and so of the oracle up to near-ties), whatever the tile
+shape or schedule."""
 import numpy as np
 import pytest
 
@@ -39,11 +40,20 @@ def _per_image(job):
     return odf.filter(job["img"], job["window"], job["kind"], job["p"], job["dist"], job["q"])
 
 
-@pytest.mark.parametrize("direct", [False, True])
-def test_batch_equals_per_image_and_oracle(direct):
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_batch_equals_per_image_and_oracle(cfg):
+    """Every group on tile shape cfg (the batch tuning table set for all four)."""
     jobs, imgs = _mixed_jobs(40, 1)
-    plan = odf.BatchPlan(jobs, direct=direct)
+    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
+    try:
+        for (w, k) in keep:
+            odf.batch_tune_set(w, k, cfg)
+        plan = odf.BatchPlan(jobs)
+    finally:
+        for (w, k), c in keep.items():
+            odf.batch_tune_set(w, k, c)
     info = plan.info()
+    assert info["configs"] == [cfg] * 4
     print("plan:", info, flush=True)
     assert info["jobs"] == 40 and sum(info["tiles"]) > 0
     plan.launch()
@@ -57,11 +67,10 @@ def test_batch_equals_per_image_and_oracle(direct):
     plan.close()
 
 
-@pytest.mark.parametrize("direct", [False, True])
-def test_batch_graph_replays(direct):
+def test_batch_graph_replays():
     jobs, _ = _mixed_jobs(24, 2)
     refs = [_per_image(j) for j in jobs]
-    plan = odf.BatchPlan(jobs, direct=direct)
+    plan = odf.BatchPlan(jobs)
     g = plan.capture()
     for rep in range(4):
         for j in jobs:  # eager work between replays: clear the outputs
@@ -79,7 +88,7 @@ def test_batch_without_idx_and_single_job():
     img = torch.from_numpy(synth.image_corr(77, 91, 0.2, key=4)).to(DEV)
     out = torch.empty_like(img)
     plan = odf.BatchPlan([dict(img=img, out=out, idx=None, window=5, kind=odf.DDF, p=0.25,
-                               dist=odf.EXACT)], direct=False)
+                               dist=odf.EXACT)])
     plan.launch()
     ref, _ = odf.filter(img, 5, odf.DDF, 0.25, odf.EXACT)
     assert torch.equal(out, ref)
@@ -113,3 +122,58 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     odf.tune_set(3, odf.DDF, odf.EXACT, True, 0)
     assert odf.tune_load(cache) == 2
     assert odf.tune_get(3, odf.DDF, odf.EXACT, True) == best
+
+
+def test_autotune_batch_drives_the_plan(tmp_path):
+    """The batch autotuner times the four shapes of a group on its mixed work
+    list, sets the fastest in the batch table, which the next plan uses; the
+    cache line restores it."""
+    cache = str(tmp_path / "tune.jsonl")
+    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
+    try:
+        best, times = odf.autotune_batch(5, odf.BVDF, 2, cache)
+        print("autotune_batch 5x5 BVDF:", best, times, flush=True)
+        assert 0 <= best < 4 and all(t > 0 for t in times) and times[best] == min(times)
+        jobs, _ = _mixed_jobs(6, 3)
+        for j in jobs:
+            j["window"], j["kind"] = 5, odf.BVDF
+        plan = odf.BatchPlan(jobs)
+        assert plan.info()["configs"][2] == best
+        plan.launch()
+        torch.cuda.synchronize()
+        for j in jobs:
+            out, idx = _per_image(j)
+            assert torch.equal(j["out"], out) and torch.equal(j["idx"], idx)
+        plan.close()
+        odf.batch_tune_set(5, odf.BVDF, (best + 1) % 4)
+        assert odf.tune_load(cache) == 1 and odf.batch_tune_get(5, odf.BVDF) == best
+    finally:
+        for (w, k), c in keep.items():
+            odf.batch_tune_set(w, k, c)
+
+
+def test_autotune_batch_on_the_callers_jobs():
+    """odf_autotune_batch_jobs times each group's shapes on the given jobs and
+    sets the table for the groups present; the plan made next uses them and
+    still gives the per-image results."""
+    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
+    try:
+        jobs, _ = _mixed_jobs(30, 5)
+        res = odf.autotune_batch_jobs(jobs, 2)
+        print("autotune_batch_jobs:", res, flush=True)
+        present = {"w%d_%s" % (j["window"], ("bvdf", "ddf")[j["kind"]]) for j in jobs}
+        assert set(res) == present
+        plan = odf.BatchPlan(jobs)
+        info = plan.info()
+        for g, (best, ms) in res.items():
+            assert ms[best] == min(ms) and info["ext_tiles"][g] == odf.tile_config(best)
+        plan.launch()
+        torch.cuda.synchronize()
+        for j in jobs:
+            out, idx = _per_image(j)
+            assert torch.equal(j["out"], out) and torch.equal(j["idx"], idx)
+        plan.close()
+    finally:
+        for (w, k), c in keep.items():
+            odf.batch_tune_set(w, k, c)
+

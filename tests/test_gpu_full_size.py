@@ -92,7 +92,7 @@ def test_mixed_batch_256_one_launch_sampled():
                          window=s_["window"], kind=s_["kind"], p=s_["p"], dist=odf.EXACT, q=4))
     print("case: mixed batch of 256, %.1f Mpix" % (sum(i.shape[0] * i.shape[1] for i in imgs) / 1e6),
           flush=True)
-    plan = odf.BatchPlan(jobs, direct=True)
+    plan = odf.BatchPlan(jobs)
     plan.launch()
     torch.cuda.synchronize()
     total = 0

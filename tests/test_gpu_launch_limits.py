@@ -105,7 +105,7 @@ def test_batch_of_70000_jobs():
     jobs = [dict(img=x[b], out=out[b], idx=idx[b], window=3, kind=DDF, p=0.25, dist=EXACT, q=4)
             for b in range(B)]
     print("case: batch of %d jobs" % B, flush=True)
-    plan = odf.BatchPlan(jobs, direct=True)
+    plan = odf.BatchPlan(jobs)
     assert plan.info()["tiles"][3 * 1 + EXACT] == B
     plan.launch()
     torch.cuda.synchronize()

@@ -504,16 +504,17 @@ def mismatch_sample(B, M, N, k, seed):
 
 
 def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
-    """7680 x 4320 frame (3x3 BVDF, 5x5 and 7x7) and 64 x 1920 x 1080 frames
-    (5x5), correlated noise 0.15 (tile shapes autotuned per class first,
+    """7680 x 4320 frame (3x3 BVDF, 5x5, 7x7 and 9x9) and 64 x 1920 x 1080
+    frames (5x5), correlated noise 0.15 (tile shapes autotuned per class first,
     untimed).  With ``samples`` (a dict), the windows of 1 M seeded pixels
-    (5x5; 100 000 for 3x3 and 7x7) and the GPU's index there are kept for the
-    oracle check of the cpu_baseline leg."""
+    (5x5; 100 000 for 3x3 and 7x7, 20 000 for 9x9) and the GPU's index there are
+    kept for the oracle check of the cpu_baseline leg."""
     forms = {}
     for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF)):
         for d in ("exact", "minimax", "rgb"):
             if (w, kk, d) != (5, odf.DDF, "exact"):  # the step's class, tuned on this frame
                 autotune(odf, w, kk, DIST[d], True, 1024, 1024, 3)
+    # (9 x 9 offers one tile shape)
     for tag, shape, key in (("7680x4320", (1, 4320, 7680), 5), ("64x1920x1080", (64, 1080, 1920), 6)):
         B, M, N = shape
         imgs = np.stack([synth.image_corr(M, N, 0.15, key=key * 100 + b) for b in range(B)])
@@ -523,8 +524,8 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
         bi = torch.empty((B, M, N), dtype=torch.uint8, device=dev)
         npx = B * M * N
         for w, kind, p in ((3, "bvdf", 0.0), (5, "bvdf", 0.0), (5, "ddf", 0.25), (7, "bvdf", 0.0),
-                           (7, "ddf", 0.25)):
-            if tag != "7680x4320" and w in (3, 7):
+                           (7, "ddf", 0.25), (9, "bvdf", 0.0), (9, "ddf", 0.25)):
+            if tag != "7680x4320" and w in (3, 7, 9):
                 continue
             for d in ("exact", "minimax", "rgb"):
                 kk = odf.BVDF if kind == "bvdf" else odf.DDF
@@ -538,7 +539,7 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
                 if samples is not None:
                     key = (tag, w)
                     if key not in samples.setdefault("windows", {}):
-                        pix = mismatch_sample(B, M, N, 1_000_000 if w == 5 else 100_000,
+                        pix = mismatch_sample(B, M, N, {5: 1_000_000, 9: 20_000}.get(w, 100_000),
                                               7000 + 10 * w + key[0].count("x"))
                         samples["windows"][key] = (pix, sample_windows(torch, big, pix, w))
                     pix = samples["windows"][key][0]

@@ -6,7 +6,7 @@
  * directional filters", arXiv:1009.0958.
  *
  * Every image is an RGB array in HWC order: pixel (b, r, c) channel k lives at
- * element ((b*M + r)*N + c)*3 + k.  A window of w x w pixels (w = 3, 5 or 7) is
+ * element ((b*M + r)*N + c)*3 + k.  A window of w x w pixels (w = 3, 5, 7 or 9) is
  * centred on each pixel; border windows repeat the nearest edge pixel
  * (replicated border), so every window has n = w*w members.  Members are
  * numbered u = 0..n-1 row-major inside the window; the centre is (n-1)/2.
@@ -86,12 +86,14 @@ const char* odf_last_error(void);
  *         window member.
  *   idx   B x M x N uint8 or NULL: the selected member index u in 0..n-1.
  *         Ties go to the lowest index.
- *   window 3, 5 or 7; kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only, ignored by
+ *   window 3, 5, 7 or 9; kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only, ignored by
  *         BVDF); dist ODF_EXACT / ODF_MINIMAX / ODF_RGB; q in {2, 3, 4} for
  *         ODF_MINIMAX (ignored otherwise).
  * Zero pixels take the direction (1,1,1) in the angle and chromaticity terms.
  * Errors: ODF_EINVAL for null img/out, sizes < 1, out overlapping img, or a
- * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5, 7};
+ * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5, 7, 9}
+ * (9 x 9 keeps 81 aggregates per thread: one tile shape, about 250 VGPRs; 11 x 11
+ * would need 121 and is not offered);
  * ODF_EHIP if the launch fails.
  */
 int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, float p,
@@ -132,7 +134,7 @@ int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, 
  *          paper's setting is lambda = 2, T = 10.8 (angles in radians, L2 in
  *          the units of the image values).
  *   T      any value but NaN (+inf keeps every centre; below 0 gives the DDF).
- * Windows 3 and 5 (ODF_EUNSUPPORTED for 7).
+ * Windows 3 and 5 (ODF_EUNSUPPORTED for 7 and 9).
  * Errors: as odf_filter_u8, plus ODF_EINVAL for lambda out of range or T NaN.
  */
 int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
@@ -159,7 +161,7 @@ int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, 
  * Runs on the ACWDDF sweep, with tile table entries of its own (kind
  * ODF_CWVMF or ODF_CWDDF in the tuning calls); windows 3 and 5.
  * Errors: as odf_filter_u8, plus ODF_EINVAL for kind or level out of range,
- * ODF_EUNSUPPORTED for window 7.
+ * ODF_EUNSUPPORTED for windows 7 and 9.
  */
 int odf_cw_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, int dist, int q,
                      int level, uint8_t* out, uint8_t* idx, void* stream);
@@ -192,7 +194,7 @@ int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int wind
  *        nothing: its dy(c) reaches no pixel.
  * The forward selection is not touched.  Errors: ODF_EINVAL for null
  * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for a window
- * other than 3, 5 or 7.
+ * other than 3, 5, 7 or 9.
  */
 int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int N, int window,
                           float* dx, void* stream);
@@ -203,7 +205,7 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
  * y(c) = sum_u pi_u x_u.  tau -> 0 tends to the hard selection where the
  * minimum is unique.
  *   x  B x M x N x 3 float32 (read only); y  B x M x N x 3 float32 output.
- * Windows 3 and 5 (ODF_EUNSUPPORTED for 7).
+ * Windows 3 and 5 (ODF_EUNSUPPORTED for 7 and 9).
  * Errors: as odf_filter_f32, plus ODF_EINVAL for tau <= 0 or not finite.
  */
 int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,
@@ -381,7 +383,7 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * and 5 for ODF_ACWDDF, ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular
  * term and keeps one entry for every dist); the default is shape 2
  * (32 x 16) for every class (the 5x5 centre-weighted kinds and 7x7 offer only
- * the 512-thread shapes 2 and 3).  The table is initialised once per process
+ * the 512-thread shapes 2 and 3, 9x9 only shape 2).  The table is initialised once per process
  * and each entry is read and written atomically. */
 int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */

@@ -57,7 +57,7 @@
 #endif
 
 enum { OK_BVDF = 0, OK_DDF = 1 };
-enum { NMAX = 49 }; /* members of the largest window (7 x 7) */
+enum { NMAX = 81 }; /* members of the largest window (9 x 9) */
 enum { OD_EXACT = 0, OD_MINIMAX = 1, OD_RGB = 2 };
 
 /* Table 1: minimax polynomial coefficients a_0..a_4 as printed, rows q = 2,3,4. */
@@ -241,7 +241,7 @@ static void filter_one(const double *img, int M, int N, int w, int kind, double 
 
 static int check_args(int B, int M, int N, int w, int kind, double p, int dist, int q) {
     if (B < 1 || M < 1 || N < 1) return -1;
-    if (w != 3 && w != 5 && w != 7) return -1;
+    if (w != 3 && w != 5 && w != 7 && w != 9) return -1;
     if (kind != OK_BVDF && kind != OK_DDF) return -1;
     if (dist < OD_EXACT || dist > OD_RGB) return -1;
     if (dist == OD_MINIMAX && (q < 2 || q > 4)) return -1;
@@ -321,7 +321,8 @@ int oracle_filter_at(const double *img, int B, int M, int N, int w, int kind, do
  * Output pixels are visited in raster order. */
 int oracle_backward_hard(const uint8_t *idx, const double *dy, int B, int M, int N, int w,
                          double *dx) {
-    if (B < 1 || M < 1 || N < 1 || (w != 3 && w != 5 && w != 7) || !idx || !dy || !dx) return -1;
+    if (B < 1 || M < 1 || N < 1 || (w != 3 && w != 5 && w != 7 && w != 9) || !idx || !dy || !dx)
+        return -1;
     int h = (w - 1) / 2, n = w * w;
     int64_t mn = (int64_t)M * N;
     memset(dx, 0, sizeof(double) * 3 * mn * B);

@@ -62,8 +62,8 @@ int check_common(const void* img, int B, int M, int N, int window, int kind, flo
     if (B < 1 || M < 1 || N < 1) return fail(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
     if ((long long)B * M * N >= (1ll << 31))
         return fail(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
-    if (window != 3 && window != 5 && window != 7)
-        return fail(ODF_EUNSUPPORTED, "window %d not supported (3, 5 or 7)", window);
+    if (window != 3 && window != 5 && window != 7 && window != 9)
+        return fail(ODF_EUNSUPPORTED, "window %d not supported (3, 5, 7 or 9)", window);
     if (kind != ODF_BVDF && kind != ODF_DDF) return fail(ODF_EINVAL, "kind %d out of range", kind);
     if (dist < ODF_EXACT || dist > ODF_RGB) return fail(ODF_EINVAL, "dist %d out of range", dist);
     if (dist == ODF_MINIMAX && (q < 2 || q > 4))
@@ -128,7 +128,7 @@ int acwddf_any(const void* img, bool u8, int B, int M, int N, int window, int di
                int lambda, float T, void* out, uint8_t* idx, void* stream) {
     int rc = check_common(img, B, M, N, window, ODF_DDF, 0.5f, dist, q);
     if (rc) return rc;
-    if (window == 7) return fail(ODF_EUNSUPPORTED, "ACWDDF supports windows 3 and 5");
+    if (window >= 7) return fail(ODF_EUNSUPPORTED, "ACWDDF supports windows 3 and 5");
     if (!out) return fail(ODF_EINVAL, "out is NULL");
     const int dmax = (window * window + 1) / 2 - 2;
     if (lambda < 1 || lambda > dmax)
@@ -157,7 +157,8 @@ int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, 
     if (rc) return rc;
     if (kind != ODF_CWVMF && kind != ODF_CWDDF)
         return fail(ODF_EINVAL, "kind %d is not ODF_CWVMF or ODF_CWDDF", kind);
-    if (window == 7) return fail(ODF_EUNSUPPORTED, "centre-weighted filters support windows 3 and 5");
+    if (window >= 7)
+        return fail(ODF_EUNSUPPORTED, "centre-weighted filters support windows 3 and 5");
     if (!out) return fail(ODF_EINVAL, "out is NULL");
     const int n = window * window, dmax = (n + 1) / 2;
     if (level < 1 || level > dmax) return fail(ODF_EINVAL, "level %d out of range [1, %d]", level, dmax);
@@ -245,8 +246,8 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
     if (!idx || !dy || !dx) return fail(ODF_EINVAL, "idx, dy and dx must be non-NULL");
     if (B < 1 || M < 1 || N < 1) return fail(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
     if ((long long)B * M * N >= (1ll << 31)) return fail(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
-    if (window != 3 && window != 5 && window != 7)
-        return fail(ODF_EUNSUPPORTED, "window %d not supported (3, 5 or 7)", window);
+    if (window != 3 && window != 5 && window != 7 && window != 9)
+        return fail(ODF_EUNSUPPORTED, "window %d not supported (3, 5, 7 or 9)", window);
     const size_t npix = (size_t)B * M * N;
     if (overlaps(dx, npix * 12, dy, npix * 12) || overlaps(dx, npix * 12, idx, npix))
         return fail(ODF_EINVAL, "dx overlaps dy or idx");
@@ -259,7 +260,8 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
 static int check_soft(const float* x, int B, int M, int N, int window, int kind, float p, float tau) {
     int rc = check_common(x, B, M, N, window, kind, p, ODF_EXACT, 4);
     if (rc) return rc;
-    if (window == 7) return fail(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3 and 5");
+    if (window >= 7)
+        return fail(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3 and 5");
     if (!(tau > 0.0f) || !(tau < 3.0e38f)) return fail(ODF_EINVAL, "tau must be positive and finite");
     return ODF_OK;
 }

@@ -13,6 +13,7 @@ constexpr int kNumTileConfigs = kNumTileShapes;
 // for a float32 tile's pixel arrays).
 bool tile_config_valid(int window, int kind, int cfg) {
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
+    if (window == 9) return cfg == 2;  // 32 x 16 (64 x 8 leaves no output row at h = 4)
     if ((window == 5 && centre_weighted(kind)) || window == 7)
         return kTileW[cfg] * kTileH[cfg] <= 512;
     return true;
@@ -32,7 +33,8 @@ hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregat
                           const FwdParams& prm, hipStream_t stream) {
     if (window == 3) return launch_w<3>(kind, dist, u8, aggregates, cfg, prm, stream);
     if (window == 5) return launch_forward5(kind, dist, u8, aggregates, cfg, prm, stream);
-    return launch_forward7(kind, dist, u8, aggregates, cfg, prm, stream);
+    if (window == 7) return launch_forward7(kind, dist, u8, aggregates, cfg, prm, stream);
+    return launch_forward9(kind, dist, u8, aggregates, cfg, prm, stream);
 }
 
 }  // namespace odf

@@ -50,6 +50,9 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
     if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
         (void)cfg;
         return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+    } else if constexpr (W == 9) {  // 512 threads, 8 output rows: the one shape offered
+        return cfg == 2 ? launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream)
+                        : hipErrorInvalidValue;
     } else if constexpr ((W == 5 && centre_weighted(KIND)) || W == 7) {
         switch (cfg) {
         case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
@@ -96,16 +99,18 @@ static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const
                            hipStream_t s) {
     if (kind == kBVDF) return launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s);
     if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
-    if constexpr (W == 7) return hipErrorInvalidValue;  // no 7x7 centre-weighted filters
+    if constexpr (W >= 7) return hipErrorInvalidValue;  // no 7x7 or 9x9 centre-weighted filters
     else if (kind == kACW) return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
     else if (kind == kCW) return launch_wk<W, kCW>(dist, u8, agg, cfg, prm, s);
     else return launch_wk<W, kCWV>(dist, u8, agg, cfg, prm, s);
 }
 
-// Launchers of the window sizes instantiated in fwd5.hip and fwd7.hip.
+// Launchers of the window sizes instantiated in fwd5.hip, fwd7.hip and fwd9.hip.
 hipError_t launch_forward5(int kind, int dist, bool u8, bool aggregates, int cfg,
                            const FwdParams& prm, hipStream_t stream);
 hipError_t launch_forward7(int kind, int dist, bool u8, bool aggregates, int cfg,
+                           const FwdParams& prm, hipStream_t stream);
+hipError_t launch_forward9(int kind, int dist, bool u8, bool aggregates, int cfg,
                            const FwdParams& prm, hipStream_t stream);
 
 }  // namespace odf

@@ -26,10 +26,10 @@ namespace {
 
 // [window 3/5/7][kind ODF_BVDF .. ODF_CWDDF][dist][u8]
 constexpr int kTableKinds = 5;
-std::atomic<int> g_table[3][kTableKinds][3][2];
+std::atomic<int> g_table[4][kTableKinds][3][2];
 std::once_flag g_table_once;
 
-int window_slot(int window) { return window == 3 ? 0 : (window == 5 ? 1 : 2); }
+int window_slot(int window) { return (window - 3) / 2; }  // 3, 5, 7, 9
 
 // The centre-weighted vector median has no angular term: its kernel runs the
 // chromaticity layout whatever dist the caller names, so every dist shares
@@ -42,7 +42,7 @@ std::atomic<int> g_batch[4];
 
 void ensure_init() {
     std::call_once(g_table_once, [] {
-        for (int w = 0; w < 3; ++w)
+        for (int w = 0; w < 4; ++w)
             for (int k = 0; k < kTableKinds; ++k)
                 for (int d = 0; d < 3; ++d)
                     for (int u = 0; u < 2; ++u)
@@ -130,11 +130,11 @@ int kernel_kind(int kind) {
 namespace {
 
 // A (window, kind, dist) class the library computes (the centre-weighted
-// kinds have no 7x7 kernels).
+// kinds have no 7x7 or 9x9 kernels).
 bool valid_class(int window, int kind, int dist) {
-    if (window != 3 && window != 5 && window != 7) return false;
+    if (window != 3 && window != 5 && window != 7 && window != 9) return false;
     if (kind < ODF_BVDF || kind > ODF_CWDDF) return false;
-    if (window == 7 && kind != ODF_BVDF && kind != ODF_DDF) return false;
+    if (window >= 7 && kind != ODF_BVDF && kind != ODF_DDF) return false;
     return dist >= 0 && dist <= 2;
 }
 

@@ -31,7 +31,7 @@ def _u8(img, B, M, N, w, kind, p, dist, q, out, idx=None):
     ((FAKE, 1, -1, 8, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
     ((FAKE, 1, 8, 0, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
     ((FAKE, 4096, 4096, 4096, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "2^31"),
-    ((FAKE, 1, 8, 8, 9, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 11, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 4, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 3, 2, 0.0, 0, 4, FAKE2), odf.EINVAL, "kind"),
     ((FAKE, 1, 8, 8, 3, 0, 0.0, 3, 4, FAKE2), odf.EINVAL, "dist"),
@@ -290,7 +290,7 @@ def test_allocation_failure_reports_enomem(monkeypatch):
     rc = L.odf_autotune_batch_jobs(ct.cast(jobs, ct.c_void_p), 2, 2, None, None, None)
     assert rc == odf.ENOMEM and "allocation" in odf.last_error()
     # validation still comes first
-    rc = L.odf_autotune(9, odf.DDF, odf.EXACT, 1, 64, 64, 2, None, None, None)
+    rc = L.odf_autotune(11, odf.DDF, odf.EXACT, 1, 64, 64, 2, None, None, None)
     assert rc == odf.EINVAL
     assert L.odf_autotune_batch(9, odf.DDF, 2, None, None, None) == odf.EINVAL
     monkeypatch.setenv("ODF_TEST_FAIL_ALLOC", "0")

@@ -322,14 +322,14 @@ def _collinear_image(M, N, seed):
 
 
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
-@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("window", [3, 5, 7, 9])
 def test_bvdf_collinear_colours_select_lowest_index(window, dist):
     """BVDF on uint8 pixels takes the canonical direction x / gcd(x), as the
     oracle does: members that are multiples of one colour tie bit for bit and
     the lowest index wins, so the GPU's index equals the oracle's at every pixel
     whose minimum is shared by collinear colours (and elsewhere up to near-ties
     between different directions); per-image and batched launches agree."""
-    img = _collinear_image(70, 97, 80 + window + dist)
+    img = _collinear_image(*((70, 97) if window < 9 else (40, 50)), 80 + window + dist)
     n_mis, n = run_and_check(img, window, BVDF, 0.0, dist, aggregates=(window < 7))
     _, idx = odf.filter(_gpu(img), window, BVDF, 0.0, dist)
     idx = idx.cpu().numpy()
@@ -348,7 +348,7 @@ def test_bvdf_collinear_colours_select_lowest_index(window, dist):
     only_collinear = np.all(~tied | coll, axis=-1) & (tied.sum(-1) > 1)
     assert only_collinear.sum() > 50
     assert np.array_equal(idx[only_collinear], o_idx[only_collinear])
-    if window == 7:
+    if window >= 7:
         return  # the batch takes windows 3 and 5
     # the batched launch (two copies, one job each) gives the same indices
     x = _gpu(img)
@@ -361,4 +361,26 @@ def test_bvdf_collinear_colours_select_lowest_index(window, dist):
     for j in jobs:
         assert np.array_equal(j["idx"].cpu().numpy(), idx)
     plan.close()
+
+
+@pytest.mark.parametrize("u8", [True, False])
+@pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
+@pytest.mark.parametrize("kind,p", [(BVDF, 0.0), (DDF, 0.25)])
+def test_window9(kind, p, dist, u8):
+    """9 x 9 windows (h = 4, one 32 x 16 extended tile of 24 x 8 output pixels):
+    a ragged image of 3 x 5 tiles with zero pixels, uint8 and float32, against
+    the oracle: selections to the near-tie band, copies, aggregates."""
+    img = _sparse_zeros(36, 52, key=90 + dist)
+    if not u8:
+        img = img.astype(np.float32) / 255
+    run_and_check(img, 9, kind, p, dist)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (9, 1), (5, 30), (17, 25)])
+def test_window9_edge_shapes(shape):
+    rng = np.random.default_rng(sum(shape) + 9)
+    img = rng.integers(0, 256, shape + (3,)).astype(np.uint8)
+    img[rng.random(shape) < 0.2] = 0
+    run_and_check(img, 9, DDF, 0.25, EXACT)
+    run_and_check(img, 9, BVDF, 0.0, RGB)
 

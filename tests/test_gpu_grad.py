@@ -22,7 +22,7 @@ def _gpu(x):
 
 # ------------------------------------------------------------------ hard backward
 
-@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("window", [3, 5, 7, 9])
 @pytest.mark.parametrize("shape", [(2, 37, 45), (1, 1, 1), (1, 3, 70), (3, 64, 64)])
 def test_backward_hard_matches_oracle_bitwise(window, shape):
     print("case: hard bwd w=%d shape=%s" % (window, shape), flush=True)
@@ -40,7 +40,7 @@ def test_backward_hard_matches_oracle_bitwise(window, shape):
     assert np.all(ones == np.rint(ones)) and ones.sum() == B * M * N * 3
 
 
-@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("window", [3, 5, 7, 9])
 def test_backward_hard_ragged_tiles_and_foreign_indices(window):
     """Tile edges in both directions (64 x 8 output tiles: 130 columns leave a
     2-column tile, 17 rows a 1-row tile) and index entries >= window^2, which

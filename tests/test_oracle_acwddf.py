@@ -148,7 +148,7 @@ def test_at_matches_full_and_rejects():
     o2, i2, S2, d2 = oracle.acwddf_at(x, pix, window=5, dist=RGB, lam=3, T=5.0)
     assert np.array_equal(o2, out.reshape(-1, 3)[pix]) and np.array_equal(i2, idx.ravel()[pix])
     assert np.array_equal(S2, S.ravel()[pix]) and np.array_equal(d2, dg.reshape(-1, 125)[pix])
-    for bad in (dict(lam=0), dict(lam=4), dict(T=math.nan), dict(window=9)):
+    for bad in (dict(lam=0), dict(lam=4), dict(T=math.nan), dict(window=11)):
         kw = dict(window=3, lam=2, T=1.0)
         kw.update(bad)
         with pytest.raises(ValueError):

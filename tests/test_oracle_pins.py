@@ -234,9 +234,10 @@ def _mp_filter(img, w, kind, p, dist):
 
 @pytest.mark.parametrize("w,kind,p,dist", [
     (w, kind, p, dist) for w in (3, 5) for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 0.5))
-    for dist in (EXACT, RGB)] + [(7, BVDF, 0.0, EXACT), (7, DDF, 0.25, EXACT)])
+    for dist in (EXACT, RGB)] + [(7, BVDF, 0.0, EXACT), (7, DDF, 0.25, EXACT),
+                                 (9, BVDF, 0.0, EXACT), (9, DDF, 0.25, RGB)])
 def test_filter_vs_50_digit_bruteforce(w, kind, p, dist):
-    img = _tiny_image(w * 10 + kind, {3: 6, 5: 5, 7: 4}[w], 5)
+    img = _tiny_image(w * 10 + kind, {3: 6, 5: 5, 7: 4, 9: 4}[w], 5)
     out, idx, A, D, O = oracle.filter(img, w, kind, p, dist, aggregates=True)
     mA, mD = _mp_filter(img, w, kind, p, dist)
     assert np.allclose(A, mA, rtol=1e-13, atol=1e-13)
@@ -260,7 +261,7 @@ def test_filter_vs_50_digit_bruteforce(w, kind, p, dist):
 
 
 @pytest.mark.parametrize("q", [2, 3, 4])
-@pytest.mark.parametrize("w", [3, 5, 7])
+@pytest.mark.parametrize("w", [3, 5, 7, 9])
 def test_minimax_aggregates_within_table1_bound(q, w):
     img = _tiny_image(70 + q, 8, 8)
     _, _, Ae, _, _ = oracle.filter(img, w, BVDF, 0, EXACT, aggregates=True)
@@ -302,7 +303,7 @@ def test_ddf_p0_equals_bvdf():
             assert np.array_equal(i0, ib)
 
 
-@pytest.mark.parametrize("w", [3, 5, 7])
+@pytest.mark.parametrize("w", [3, 5, 7, 9])
 def test_ddf_p1_is_vector_median(w):
     """p = 1 orders by the aggregated L2 distance: the vector median filter (eq. 1)."""
     img = _tiny_image(4, 20, 18)
@@ -313,7 +314,7 @@ def test_ddf_p1_is_vector_median(w):
     assert _near_tie_ok(idx, ref, dist)
 
 
-@pytest.mark.parametrize("w", [3, 5, 7])
+@pytest.mark.parametrize("w", [3, 5, 7, 9])
 def test_ddf_half_is_eq3_product(w):
     """p = 1/2 orders by sqrt(A D): the product form of eq. (3)."""
     img = _tiny_image(5, 20, 18)
@@ -488,7 +489,7 @@ def test_filter_at_matches_full_filter(w, kind, p, dist):
 def test_backward_hard_routes_and_conserves():
     rng = np.random.default_rng(2)
     img = _tiny_image(13, 12, 10)
-    for w in (3, 5, 7):
+    for w in (3, 5, 7, 9):
         _, idx = oracle.filter(img, w, DDF, 0.25, EXACT)
         dy = rng.standard_normal(img.shape)
         dx = oracle.backward_hard(idx, dy, w)

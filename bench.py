@@ -108,8 +108,8 @@ TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("rgb", 32, 16): (4363.9, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
     ("batch6", 32, 32): (21903.4, 36887.7),
 }
-TRAFFIC_SOURCES = ("fwd.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h", "aggregates.h",
-                   "pair_terms.h", "atan_poly.h", "odf_internal.h")
+TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h",
+                   "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h", "odf_internal.h")
 TRAFFIC_SRC_SHA256 = "06c54a4fcc805970c87de27832fb057c33ca7e1eeda85b45d81117963908f226"
 
 
@@ -211,6 +211,22 @@ def autotune(odf, window, kind, dist, u8, M, N, reps):
     if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
         return odf.tune_get(window, kind, dist, u8), []
     return odf.autotune(window, kind, dist, u8, M, N, reps, cache_path=TUNE_CACHE)
+
+
+def tune_batch(odf, jobs, tag):
+    """The batch groups' tile shapes for these jobs: loaded from the cache
+    file --tune-cache + "." + tag when it exists, else tuned on the jobs
+    (untimed; written there when --tune-cache is given).  Returns {group:
+    {ext_tile, ms_per_shape}} for the groups the jobs use."""
+    path = TUNE_CACHE + "." + tag if TUNE_CACHE else None
+    if path and os.path.exists(path) and os.path.getsize(path) > 0:
+        odf.tune_load(path)
+        groups = {f"w{j['window']}_{'ddf' if j['kind'] else 'bvdf'}" for j in jobs}
+        res = {g: (odf.batch_tune_get(int(g[1]), int(g.endswith("ddf"))), []) for g in groups}
+    else:
+        res = odf.autotune_batch_jobs(jobs, 2, path)
+    return {g: {"ext_tile": odf.tile_config(b), "ms_per_shape": [round(t, 4) for t in ms]}
+            for g, (b, ms) in res.items()}
 
 
 HEADLINE = dict(window=5, kind="ddf", p=0.25, dist="exact", M=4320, N=7680, phi=0.15, key=500)
@@ -413,9 +429,12 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
             cur.wait_stream(st)
 
     graphs = {}
+    batch_tuned = None
     if "direct" in forms_wanted:
-        plan = odf.BatchPlan([dict(img=x, out=outs[(p, d)][0], idx=outs[(p, d)][1], window=3,
-                                   kind=odf.DDF, p=p, dist=DIST[d], q=4) for (p, d) in variants])
+        jobs = [dict(img=x, out=outs[(p, d)][0], idx=outs[(p, d)][1], window=3, kind=odf.DDF,
+                     p=p, dist=DIST[d], q=4) for (p, d) in variants]
+        batch_tuned = tune_batch(odf, jobs, "six_variants")
+        plan = odf.BatchPlan(jobs)
         graphs["direct"] = (plan, plan.capture())
 
     step_forms = {}
@@ -454,9 +473,10 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
     slots_px = sum(slots_per_pixel(3, "ddf", p, d) for (p, d) in variants) / len(variants)
     if best == "graph_batch_direct":
         # one kernel over the tiles of all six variants: the form's time is its time
-        dname = "batch_direct_kernel ddf3, six variants in one launch"
+        ext6 = graphs["direct"][0].info()["ext_tiles"]["w3_ddf"]
+        dname = "batch_direct_kernel ddf3 %dx%d, six variants in one launch" % tuple(ext6)
         dms, dpx = ms_step, npx
-        tb = traffic_bytes("batch6", (32, 32))
+        tb = traffic_bytes("batch6", ext6)
     else:
         dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
         dp, dd = float(dom.split("_")[1][1:]), dom.split("_")[2]
@@ -477,8 +497,8 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
     return {"ddf3_six_variants_1024x1024": {
         "mpix_s": round(npx / (ms_step * 1e3), 1), "ms": round(ms_step, 5), "form": best,
         "forms_ms": {k: round(v, 5) for k, v in step_forms.items()},
-        "outputs_match_plain_launch": ok, "tuned": tuned, "variants": per_variant,
-        "roofline": roof}}
+        "outputs_match_plain_launch": ok, "tuned": tuned, "batch_tuned": batch_tuned,
+        "variants": per_variant, "roofline": roof}}
 
 
 def sample_windows(torch, x, pix, window):
@@ -654,13 +674,7 @@ def batched_form(torch, odf, synth, dev, samples=None):
 
     ms_loop = time_launches(torch, loop, 3, warm=1)
     # the batch groups' tile shapes, tuned on these jobs (untimed)
-    if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
-        bt = {f"w{w}_{'ddf' if k else 'bvdf'}": (odf.batch_tune_get(w, k), [])
-              for w in (3, 5) for k in (0, 1)}
-    else:
-        bt = odf.autotune_batch_jobs(jobs, 2, TUNE_CACHE)
-    batch_tuned = {g: {"ext_tile": odf.tile_config(b), "ms_per_shape": [round(t, 4) for t in ms]}
-                   for g, (b, ms) in bt.items()}
+    batch_tuned = tune_batch(odf, jobs, "batched")
     for j in jobs:
         j["out"].zero_()
         j["idx"].zero_()

@@ -86,31 +86,26 @@ L2_SLOTS = {
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-slots/s
 
 # ------------------------------------------------------------------ HBM traffic
-# Bytes the DDF 3x3 uint8 forward kernels move to and from HBM on the
-# 1024 x 1024 image: rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per
-# dispatch, one pass each, from `bench.py --steps 3 --warmup 1 --no-forms
-# --no-cpu --step-forms loop,direct --copy-probe-mib 256`), keyed by pair term
-# and extended tile for the per-image kernel, and ("batch6", 32, 32) for the
-# batch group kernel running the step's six variants in one launch.  Each
-# counter is scaled by what it reads for the 256 MiB float32 copy of the same
-# run (262144 KiB read, 262144 KiB written): FETCH_SIZE read 131082.2 KiB
-# (x 1.99984), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold for the
-# kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources bench.py
-# reports traffic as null.
-TRAFFIC_FETCH_SCALE = 262144.0 / 131082.2
+# Bytes the step's kernel (DDF 5x5 exact, uint8, 32 x 16 extended tile, on the
+# 7680 x 4320 frame) and the six-variant DDF 3x3 batch kernel (32 x 16, on the
+# 1024 x 1024 image) move to and from HBM: rocprofv3 --pmc FETCH_SIZE and --pmc
+# WRITE_SIZE (KiB per dispatch, one pass each, from `bench.py --steps 3
+# --warmup 1 --no-cpu --forms six_variants,large_frames,batched,differentiable
+# --step-forms loop,direct --copy-probe-mib 256 --tune-cache <file>`), keyed by
+# form and extended tile.  Each counter is scaled by what it reads for the
+# 256 MiB float32 copy of the same run (262144 KiB read, 262144 KiB written):
+# FETCH_SIZE read 131085.0 KiB (x 1.99982), WRITE_SIZE 262144.0 KiB (x 1.0).
+# The figures hold for the kernel sources hashed in TRAFFIC_SRC_SHA256; for any
+# other sources bench.py reports traffic as null.
+TRAFFIC_FETCH_SCALE = 262144.0 / 131085.0
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
-TRAFFIC_KIB = {  # (dist, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact", 32, 32): (4072.6, 6144.0), ("exact", 64, 16): (2895.5, 5056.0),
-    ("exact", 32, 16): (4366.9, 6144.0), ("exact", 64, 8): (3186.6, 5056.0),
-    ("minimax", 32, 32): (4090.3, 6144.0), ("minimax", 64, 16): (2904.5, 5056.0),
-    ("minimax", 32, 16): (4377.9, 6144.0), ("minimax", 64, 8): (3197.0, 5056.0),
-    ("rgb", 32, 32): (4072.2, 6144.0), ("rgb", 64, 16): (2892.5, 5056.0),
-    ("rgb", 32, 16): (4363.9, 6144.0), ("rgb", 64, 8): (3184.0, 5056.0),
-    ("batch6", 32, 32): (21903.4, 36887.7),
+TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("ddf5_exact_7680x4320", 32, 16): (172506.4, 194400.0),
+    ("batch6", 32, 16): (20999.3, 36890.7),
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h",
                    "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "06c54a4fcc805970c87de27832fb057c33ca7e1eeda85b45d81117963908f226"
+TRAFFIC_SRC_SHA256 = "def832ea5ab460a5fe959f30b5a9ad9af9249186d1626ae7b11660e301f38827"
 
 
 def forward_sources_sha256():
@@ -123,9 +118,10 @@ def forward_sources_sha256():
 
 
 def traffic_bytes(dist, ext_tile):
-    """Calibrated HBM bytes per launch on the 1024 x 1024 image (one filter, or
-    for "batch6" the group kernel running all six variants), or None when the
-    kernel sources differ from the ones the counters were taken on."""
+    """Calibrated HBM bytes per launch of the step's kernel ("ddf5_exact_7680x4320")
+    or of the six-variant batch kernel ("batch6"), for the extended tile it ran
+    on, or None when no counters were taken for that tile or the kernel sources
+    differ from the ones they were taken on."""
     key = (dist, int(ext_tile[0]), int(ext_tile[1]))
     if forward_sources_sha256() != TRAFFIC_SRC_SHA256 or key not in TRAFFIC_KIB:
         return None
@@ -203,12 +199,13 @@ def time_launches(torch, fn, reps, warm=3):
 
 
 TUNE_CACHE = None  # set by --tune-cache
+TUNE_CACHED = False  # the cache existed when the run started: apply it, tune nothing
 
 
 def autotune(odf, window, kind, dist, u8, M, N, reps):
     """The library's autotuner, or the tuning cache's entry when --tune-cache
-    names an existing file (returns (config, ms per shape or []))."""
-    if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
+    named an existing file at start-up (returns (config, ms per shape or []))."""
+    if TUNE_CACHED:
         return odf.tune_get(window, kind, dist, u8), []
     return odf.autotune(window, kind, dist, u8, M, N, reps, cache_path=TUNE_CACHE)
 
@@ -219,7 +216,7 @@ def tune_batch(odf, jobs, tag):
     (untimed; written there when --tune-cache is given).  Returns {group:
     {ext_tile, ms_per_shape}} for the groups the jobs use."""
     path = TUNE_CACHE + "." + tag if TUNE_CACHE else None
-    if path and os.path.exists(path) and os.path.getsize(path) > 0:
+    if TUNE_CACHED and path and os.path.exists(path) and os.path.getsize(path) > 0:
         odf.tune_load(path)
         groups = {f"w{j['window']}_{'ddf' if j['kind'] else 'bvdf'}" for j in jobs}
         res = {g: (odf.batch_tune_get(int(g[1]), int(g.endswith("ddf"))), []) for g in groups}
@@ -273,9 +270,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     DIST = {"exact": odf.EXACT, "minimax": odf.MINIMAX, "rgb": odf.RGB}
-    global TUNE_CACHE
+    global TUNE_CACHE, TUNE_CACHED
     TUNE_CACHE = args.tune_cache
-    if TUNE_CACHE and os.path.exists(TUNE_CACHE) and os.path.getsize(TUNE_CACHE) > 0:
+    TUNE_CACHED = bool(TUNE_CACHE) and os.path.exists(TUNE_CACHE) and \
+        os.path.getsize(TUNE_CACHE) > 0
+    if TUNE_CACHED:
         odf.tune_load(TUNE_CACHE)
 
     # ---------------------------------------------------------------- the step

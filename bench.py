@@ -103,7 +103,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("ddf5_exact_7680x4320", 32, 16): (172506.4, 194400.0),
     ("batch6", 32, 16): (20999.3, 36890.7),
 }
-TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd_launch.h", "batch.hip", "fwd_tile.h",
+TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip", "fwd_tile.h",
                    "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h", "odf_internal.h")
 TRAFFIC_SRC_SHA256 = "def832ea5ab460a5fe959f30b5a9ad9af9249186d1626ae7b11660e301f38827"
 
@@ -118,10 +118,10 @@ def forward_sources_sha256():
 
 
 def traffic_bytes(dist, ext_tile):
-    """Calibrated HBM bytes per launch of the step's kernel ("ddf5_exact_7680x4320")
-    or of the six-variant batch kernel ("batch6"), for the extended tile it ran
-    on, or None when no counters were taken for that tile or the kernel sources
-    differ from the ones they were taken on."""
+    """Calibrated HBM bytes per launch of the step's kernel ("ddf5_exact_7680x4320",
+    "..._strip" for the strip form) or of the six-variant batch kernel ("batch6"),
+    for the extended tile (or band) it ran on, or None when no counters were
+    taken for it or the kernel sources differ from the ones they were taken on."""
     key = (dist, int(ext_tile[0]), int(ext_tile[1]))
     if forward_sources_sha256() != TRAFFIC_SRC_SHA256 or key not in TRAFFIC_KIB:
         return None
@@ -310,10 +310,13 @@ def main():
     step_ok = bool(torch.equal(ref_out, out) and torch.equal(ref_idx, idx))
 
     ext = odf.tile_config(best_cfg)
+    strip = best_cfg == odf.STRIP
     slots_px = slots_per_pixel(w, "ddf", p, "exact")
     npx = M * N
+    kname = ("fwd_strip_kernel<5, DDF, exact, uint8, %dx%d bands>" if strip
+             else "fwd_kernel<5, DDF, exact, uint8, %dx%d>") % tuple(ext)
     roofline = {
-        "bound": "alu", "kernel": "fwd_kernel<5, DDF, exact, uint8, %dx%d>" % tuple(ext),
+        "bound": "alu", "kernel": kname,
         "ms_per_launch": round(ms_step, 5),
         "achieved": round(slots_px * npx / (ms_step * 1e-3) / 1e12, 3),
         "peak": round(PEAK_SLOTS / 1e12, 2), "unit": "T VALU lane-slots/s",
@@ -321,7 +324,7 @@ def main():
         "slots_per_pixel": slots_px, "pixels_per_launch": npx, "traffic": None,
         "hbm_bytes_per_pixel": 7, "hbm_frac": round(7 * npx / (ms_step * 1e-3) / 8e12, 5),
     }
-    tb = traffic_bytes("ddf5_exact_7680x4320", ext)
+    tb = traffic_bytes("ddf5_exact_7680x4320" + ("_strip" if strip else ""), ext)
     if tb is not None:
         roofline["traffic"] = tb["fetch"] + tb["write"]
         roofline["traffic_fetch_write"] = [tb["fetch"], tb["write"]]

@@ -377,22 +377,31 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
 
 /* ---------------------------------------------------------------- tuning
  * The forward kernels run one thread per pixel of an extended tile
- * (output tile plus halo).  Tile shapes are numbered 0..3; odf_tile_config
- * gives the extended width and height of one.  The process-wide table picks a
- * shape per (window, kind, dist, input type), kind any odf_kind (windows 3
- * and 5 for ODF_ACWDDF, ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular
- * term and keeps one entry for every dist); the default is shape 2
- * (32 x 16) for every class (the 5x5 centre-weighted kinds and 7x7 offer only
- * the 512-thread shapes 2 and 3, 9x9 only shape 2).  The table is initialised once per process
- * and each entry is read and written atomically. */
+ * (output tile plus halo).  Configs 0..3 are tile shapes (one workgroup per
+ * output tile); config ODF_STRIP_CONFIG (4) is the strip form, offered for
+ * ODF_BVDF and ODF_DDF at 3x3 and 5x5: one workgroup per strip of 32 - 2h
+ * output columns and 128 - 2h output rows, walking down it in bands of 32 x 16
+ * member pixels and keeping the pair terms and argmin keys that consecutive
+ * bands share in LDS, so that the rows of the halo between bands are not
+ * evaluated twice (results bitwise equal to the tile shapes).  odf_tile_config
+ * gives the extended width and height of a tile shape, or of one band of the
+ * strip form.  The process-wide table picks a config per (window, kind,
+ * dist, input type), kind any odf_kind (windows 3 and 5 for ODF_ACWDDF,
+ * ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular term and keeps one entry
+ * for every dist); the default is shape 2 (32 x 16) for every class (the 5x5
+ * centre-weighted kinds and 7x7 offer only the 512-thread shapes 2 and 3, 9x9
+ * only shape 2).  The table is initialised once per process and each entry is
+ * read and written atomically. */
+#define ODF_NUM_TILE_CONFIGS 5
+#define ODF_STRIP_CONFIG 4
 int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */
 
-/* Time every valid tile shape on a seeded M x N tuning image (a smooth field
- * with 15 % impulsive noise; reps launches
- * each, HIP events on `stream`), set the fastest in the table, store the
- * per-shape milliseconds in times_ms[4] (-1 for shapes not offered; nullable)
+/* Time every config the class offers on a seeded M x N tuning image (a smooth
+ * field with 15 % impulsive noise; reps launches each, HIP events on
+ * `stream`), set the fastest in the table, store the per-config milliseconds
+ * in times_ms[ODF_NUM_TILE_CONFIGS] (-1 for configs not offered; nullable)
  * and append one JSON line to cache_path (nullable).  Allocates and frees
  * device memory and synchronises `stream`.  Errors: ODF_EINVAL (class or
  * sizes out of range, M*N >= 2^28), ODF_ENOMEM (host or device allocation

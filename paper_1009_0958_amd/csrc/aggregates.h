@@ -17,6 +17,8 @@
 // equal colours get bitwise-equal aggregates and ties stay ties.
 #pragma once
 
+#include <type_traits>
+
 #include "pair_terms.h"
 
 namespace odf {
@@ -55,6 +57,20 @@ struct TilePix {
     const float* inv;
 };
 
+// Makes each value exist at this point of the program (an empty asm that
+// takes them as operands): the compiler may not sink their computation past it.
+template <int K>
+__device__ __forceinline__ void pin_values(const float (&v)[K]) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) asm volatile("" ::"v"(v[i]));
+}
+
+// The default plane hook of member_aggregates_x: nothing.
+struct NoPlaneHook {
+    __device__ __forceinline__ void before(int) const {}
+    __device__ __forceinline__ void after(int) const {}
+};
+
 // Aggregates of the own member p over every window containing it.  PASS 0:
 // the angular term into agg0; PASS 1: the L2 term of eq. (1) into agg0;
 // PASS 2: both in one sweep (angular -> agg0, L2 -> agg1) with two LDS plane
@@ -72,14 +88,21 @@ struct TilePix {
 // outside the extended tile -- every window of the output tile has all its
 // members inside it -- so the caller must discard the objectives of those
 // windows.
+//
+// PSTRIDE (0: NT) is the distance between two planes; HOOK is called in every
+// row group g with the sweep's own terms written (before(g), ahead of the
+// barrier that publishes them) and published (after(g), ahead of the barrier
+// that ends the group): the strip kernels use it to carry the planes of a
+// band's last rows into the next band.
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int EXT_H, int PASS, bool CEN,
-          bool GUARD>
+          bool GUARD, int PSTRIDE = 0, class HOOK = NoPlaneHook>
 __device__ __forceinline__ void member_aggregates_x(
     const TilePix& px, float* __restrict__ s_plane, int ey, int ex, int tid, const float4& mdir,
     const float4& mraw, const MinimaxCoef& cf, float (&agg0)[W * W], float (&cen0)[W * W],
-    float (&agg1)[W * W], float (&cen1)[W * W]) {
+    float (&agg1)[W * W], float (&cen1)[W * W], const HOOK& hook = HOOK{}) {
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
-    constexpr int H = Gm::H, G = Gm::G, NT = Gm::NT;
+    constexpr int H = Gm::H, G = Gm::G;
+    constexpr int NT = PSTRIDE > 0 ? PSTRIDE : Gm::NT;  // plane stride
     constexpr int NP = PASS == 2 ? 2 : 1;
     const bool mzero = U8 && mdir.w < 0.0f;
     const uint64_t mzero_wave = U8 ? __builtin_amdgcn_ballot_w64(mzero) : 0;
@@ -132,7 +155,9 @@ __device__ __forceinline__ void member_aggregates_x(
                 }
             }
         }
+        hook.before(g);
         __syncthreads();
+        hook.after(g);
 #pragma unroll
         for (int dx = -2 * H; dx <= 2 * H; ++dx) {
 #pragma unroll
@@ -173,6 +198,14 @@ __device__ __forceinline__ void member_aggregates_x(
             } else {
                 row_sums<W>(own[k], R[k][2 * H + g]);
                 row_sums<W>(up[k], R[k][2 * H - g]);
+            }
+            if constexpr (!std::is_same_v<HOOK, NoPlaneHook>) {
+                // a hook brings loops (control flow) between the row groups,
+                // past which the compiler would sink these sums to their use
+                // after the sweep, keeping every raw pair term live until
+                // then: the sums are made here
+                pin_values(R[k][2 * H + g]);
+                if (g > 0) pin_values(R[k][2 * H - g]);
             }
         }
         __syncthreads();

@@ -4,14 +4,13 @@
 
 namespace odf {
 
-constexpr int kNumTileConfigs = kNumTileShapes;
-
 // 5x5 ACWDDF keeps four register sets of n values per thread (aggregates
 // and centre terms of both passes) and 7x7 keeps a 13 x 7 grid of row sums:
 // 512-thread tiles only.  The 5x5 centre-weighted filters share the rule (CWDDF
 // parks its weighted angle sums in LDS, which at 32 x 32 would not leave room
 // for a float32 tile's pixel arrays).
 bool tile_config_valid(int window, int kind, int cfg) {
+    if (cfg == kStripConfig) return (window == 3 || window == 5) && (kind == kBVDF || kind == kDDF);
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
     if (window == 9) return cfg == 2;  // 32 x 16 (64 x 8 leaves no output row at h = 4)
     if ((window == 5 && centre_weighted(kind)) || window == 7)
@@ -25,6 +24,11 @@ bool tile_config_valid(int window, int kind, int cfg) {
 int tile_config_default(int, int) { return 2; }
 
 void tile_config_shape(int cfg, int* ext_w, int* ext_h) {
+    if (cfg == kStripConfig) {  // one band of the strip
+        *ext_w = 32;
+        *ext_h = 16;
+        return;
+    }
     *ext_w = kTileW[cfg];
     *ext_h = kTileH[cfg];
 }

@@ -3,7 +3,7 @@
 // translation unit of its own (fwd.hip, fwd5.hip, fwd7.hip).
 #pragma once
 
-#include "fwd_tile.h"
+#include "fwd_strip.h"
 
 namespace odf {
 
@@ -64,7 +64,11 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 0: return launch_shape<W, KIND, DIST, U8, AGG, 32, 32>(prm, stream);
         case 1: return launch_shape<W, KIND, DIST, U8, AGG, 64, 16>(prm, stream);
         case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-        default: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+        case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
+        default:
+            if constexpr (strip_form<W, KIND>())  // 32-wide strips of 8 bands of 16 rows
+                return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
+            return hipErrorInvalidValue;
         }
     }
 }

@@ -1,0 +1,270 @@
+// fwd_strip.h -- the strip form of the forward filter (BVDF / DDF): one
+// workgroup filters a column strip of output pixels, walking down it band by
+// band, instead of one output tile with a halo on all four sides.
+//
+// A band is EXT_W x BH member pixels (one thread each).  Each member's offset
+// grid is swept exactly as in the tile form (aggregates.h: own terms of row
+// group g published in LDS planes, the mirrored terms of row -g read back),
+// but the planes of the band's last g rows are kept in LDS for the next band,
+// whose first g rows read them instead of re-evaluating those pair terms, and
+// the argmin keys of the windows that the next band's members still belong
+// to stay in LDS as well.  So every unordered pixel pair of the strip is
+// evaluated once per strip: the halo is recomputed across the strip's two
+// vertical edges (EXT_W / TW) and over its first 2h rows, not at every tile
+// boundary (the 32 x 16 tile of the 5x5 filters evaluates 1.52 times its
+// output pixels' pair terms, a 32-wide strip of 8 bands 1.18 times).
+//
+// Every member's aggregates come out of the same summation tree as in the
+// tile form, so the strip form is bitwise equal to it.
+#pragma once
+
+#include "fwd_tile.h"
+
+namespace odf {
+
+template <int W, int EXT_W, int BH, int NB>
+struct StripGeom {
+    static constexpr int H = W / 2;
+    static constexpr int NW = W * W;
+    static constexpr int G = 4 * H + 1;
+    static constexpr int TW = EXT_W - 2 * H;    // output columns
+    static constexpr int NT = EXT_W * BH;       // threads: one per member of a band
+    static constexpr int RING = BH + 2 * H;     // pixel rows a band reads
+    static constexpr int PL = RING * EXT_W;     // plane stride: 2h carried rows + the band
+    static constexpr int S = NB * BH - 2 * H;   // output rows per strip
+    static constexpr int CROWS = H * (4 * H + 2) / 2;  // carried rows, summed over g = 1 .. 2h
+    // key slots: window centres on band rows -h .. BH - 1 + h (ring row = centre
+    // row + h), stride EXT_W, + 2h slots that windows past the last column reach
+    static constexpr int KEYN = RING * EXT_W + 2 * H;
+    static constexpr int KCARRY = 2 * H * EXT_W + 2 * H;  // slots handed to the next band
+};
+
+// LDS of one strip workgroup.  NPL: planes swept together (2 for the fused
+// angle + L2 sweep of the 3x3 DDF); NTERM: carried plane sets (one per term).
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+struct StripShared {
+    using Gm = StripGeom<W, EXT_W, BH, NB>;
+    static constexpr bool INV = U8 && DIST != kExact;
+    static constexpr int NPL = fused_sweep<W, KIND>() ? 2 : 1;
+    static constexpr int NTERM = KIND == kBVDF ? 1 : 2;
+    static constexpr int NPIX = Gm::PL + 2 * Gm::H;  // + the reads past the last row
+    float4 dir[NPIX];
+    float4 raw[U8 ? 1 : NPIX];
+    float inv[INV ? NPIX : 1];
+    float lead[2 * Gm::H];  // mirrored reads of the first row reach 2h floats before plane
+    float plane[NPL * Gm::G * Gm::PL + 2 * Gm::H];
+    float carry[NTERM * Gm::G * Gm::CROWS * EXT_W];
+    unsigned long long key[Gm::KEYN];
+};
+
+// Plane hook of one sweep (aggregates.h): in row group g >= 1 it copies the
+// planes of the previous band's last g rows, kept in carry, to the g rows
+// above the band (before the barrier that publishes the band's own terms),
+// and after that barrier keeps this band's last g rows for the next band.
+// plane points at ring row 0 (the band starts at ring row 2h); NP planes of
+// stride PL.
+template <int EXT_W, int BH, int H, int NP, int PL, int NT>
+struct StripCarry {
+    float* plane;
+    float* carry;
+    int tid;
+    static constexpr int off(int g) { return NP * EXT_W * (g - 1) * g / 2; }
+    __device__ __forceinline__ void before(int g) const {
+        if (g == 0) return;
+        const int n = NP * g * EXT_W;
+        for (int i = tid; i < n; i += NT) {
+            const int d = i / (g * EXT_W), k = i - d * (g * EXT_W);
+            plane[d * PL + (2 * H - g) * EXT_W + k] = carry[off(g) + i];
+        }
+    }
+    __device__ __forceinline__ void after(int g) const {
+        if (g == 0) return;
+        const int n = NP * g * EXT_W;
+        for (int i = tid; i < n; i += NT) {
+            const int d = i / (g * EXT_W), k = i - d * (g * EXT_W);
+            carry[off(g) + i] = plane[d * PL + (2 * H + BH - g) * EXT_W + k];
+        }
+    }
+};
+
+// The classes with a strip form: BVDF and DDF at 3x3 and 5x5.
+template <int W, int KIND>
+constexpr bool strip_form() {
+    return (W == 3 || W == 5) && (KIND == kBVDF || KIND == kDDF);
+}
+
+// Occupancy target of a strip kernel: the waves per SIMD that its LDS allows
+// (160 KiB per CU shared by whole workgroups of NT / 256 waves per SIMD), at
+// most 8; the register budget is fitted to it.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+constexpr int strip_waves_per_eu() {
+    constexpr int wgs = (160 * 1024) / (int)sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>);
+    constexpr int waves = wgs * (EXT_W * BH / 256);
+    return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
+}
+
+// One workgroup per strip of S output rows x TW output columns of one image.
+// Bands start h rows above the strip and the first band's 2h top window rows
+// lie above it (discarded); a band reads its RING pixel rows (replicated
+// border), sweeps, and then writes the BH window rows its members completed.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+__global__ void __launch_bounds__(EXT_W* BH)
+    __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<W, KIND, DIST, U8, EXT_W, BH, NB>())))
+    fwd_strip_kernel(FwdParams prm) {
+    using Gm = StripGeom<W, EXT_W, BH, NB>;
+    using Sh = StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>;
+    constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, NT = Gm::NT, PL = Gm::PL;
+    constexpr bool INV = Sh::INV;
+    constexpr bool CANON = U8 && KIND == kBVDF;  // as in the tile form
+    static_assert(Gm::KCARRY <= NT, "one carried key per thread");
+    static_assert(offsetof(Sh, plane) >= 2 * H * sizeof(float), "plane");
+    __shared__ Sh sh;
+
+    const int t = flat_block(prm.grid.n);
+    if (t < 0) return;
+    const TileCoord tc = tile_coord(t, prm.grid);
+    const int b = tc.b, s0 = tc.ty * Gm::S, tx0 = tc.tx * Gm::TW;
+    const int M = prm.M, N = prm.N;
+    const int s_end = min(s0 + Gm::S, M);
+    const TilePix px{sh.dir, sh.raw, sh.inv};
+    float* const pl0 = sh.plane + 2 * H * EXT_W;  // ring row 2h: the band's first row
+
+    for (int j = 0; j < NB; ++j) {
+        // the thread index is laundered once per band, so that the compiler
+        // derives the band's many LDS addresses inside the loop instead of
+        // hoisting them all out of it (each would hold a register across it)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int ey = tid / EXT_W, ex = tid - ey * EXT_W;
+        const int base = s0 - H + j * BH;  // image row of the band's first member row
+        const int fin0 = base - H;         // image row of the first window row it completes
+        if (fin0 >= s_end) break;          // uniform
+
+        // keys of the windows the previous band's members share with this band
+        unsigned long long kc = ~0ull;
+        if (j > 0 && tid < Gm::KCARRY) kc = sh.key[BH * EXT_W + tid];
+        // a1: the band's RING pixel rows (members and the 2h rows below them)
+        for (int i = tid; i < Gm::PL; i += NT) {
+            const int r = i / EXT_W, c = i - r * EXT_W;
+            const int gy = min(max(base + r, 0), M - 1);
+            const int gx = min(max(tx0 - H + c, 0), N - 1);
+            const int pix = (b * M + gy) * N + gx;
+            float4 d, w;
+            if constexpr (U8) {
+                const uint8_t* s = static_cast<const uint8_t*>(prm.img) + (size_t)pix * 3;
+                const uint32_t c0 = s[0], c1 = s[1], c2 = s[2];
+                if constexpr (CANON) {
+                    float d0, d1, d2;
+                    canonical_direction(c0, c1, c2, d0, d1, d2);
+                    prepare_pixel<DIST, U8, true>((float)c0, (float)c1, (float)c2, d, w, d0, d1,
+                                                  d2);
+                } else {
+                    prepare_pixel<DIST, U8>((float)c0, (float)c1, (float)c2, d, w);
+                }
+            } else {
+                const float* s = static_cast<const float*>(prm.img) + (size_t)pix * 3;
+                prepare_pixel<DIST, U8>(s[0], s[1], s[2], d, w);
+                sh.raw[i] = w;
+            }
+            sh.dir[i] = d;
+            if constexpr (INV) sh.inv[i] = w.w;
+        }
+        __syncthreads();
+        for (int i = tid; i < Gm::KEYN; i += NT) sh.key[i] = i < Gm::KCARRY ? kc : ~0ull;
+
+        const float4 mdir = sh.dir[tid];
+        float4 mraw;
+        if constexpr (U8) mraw = make_float4(0.0f, 0.0f, 0.0f, INV ? sh.inv[tid] : 0.0f);
+        else mraw = sh.raw[tid];
+
+        float A[NW], D[NW], cA[NW], cD[NW];
+        if constexpr (fused_sweep<W, KIND>()) {
+            const StripCarry<EXT_W, BH, H, 2 * G, PL, NT> hk{sh.plane, sh.carry, tid};
+            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 2, false, false, PL>(
+                px, pl0, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD, hk);
+        } else {
+            const StripCarry<EXT_W, BH, H, G, PL, NT> hk{sh.plane, sh.carry, tid};
+            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 0, false, false, PL>(
+                px, pl0, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD, hk);
+            if constexpr (KIND != kBVDF) {
+                pin_values(A);  // the aggregates, not the row sums, live through the L2 sweep
+                const StripCarry<EXT_W, BH, H, G, PL, NT> hd{
+                    sh.plane, sh.carry + G * Gm::CROWS * EXT_W, tid};
+                float u0[NW], u1[NW];
+                member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 1, false, false, PL>(
+                    px, pl0, ey, ex, tid, mdir, mraw, prm.coef, D, cD, u0, u1, hd);
+            } else {
+#pragma unroll
+                for (int u = 0; u < NW; ++u) D[u] = 0.0f;
+            }
+        }
+
+        // a4: every window of the member; window u is centred on band row
+        // ey + h - u / W, column ex + h - u % W, key slot (row + h) EXT_W + col + h.
+        // Windows past the strip's columns hold meaningless aggregates and land
+        // in slots no output reads.
+        {
+            uint32_t kb[NW];
+            const int mode = objective_mode<KIND>(prm.p);
+            if constexpr (stage_angle_part<W, KIND, false>()) {
+                // the key as the tile form's staged path forms it
+                auto staged = [&](auto mode_c) {
+                    constexpr int MODE = decltype(mode_c)::value;
+#pragma unroll
+                    for (int u = 0; u < NW; ++u)
+                        kb[u] = staged_key_bits<MODE>(staged_part<MODE>(A[u], prm.p), D[u], prm.p);
+                };
+                if (mode == kObjA) staged(std::integral_constant<int, kObjA>{});
+                else if (mode == kObjD) staged(std::integral_constant<int, kObjD>{});
+                else if (mode == kObjLog) staged(std::integral_constant<int, kObjLog>{});
+                else if (mode == kObjQuarter) staged(std::integral_constant<int, kObjQuarter>{});
+                else staged(std::integral_constant<int, kObjProd>{});
+            } else {
+                objective_key_bits<NW>(mode, prm.p, A, D, kb);
+            }
+            // the member numbers, formed here: as constants the compiler keeps
+            // all n of them in vector registers across the band loop
+            unsigned z = 0;
+            asm volatile("" : "+v"(z));
+#pragma unroll
+            for (int u = 0; u < NW; ++u)
+                atomicMin(&sh.key[tid + (2 * H - u / W) * EXT_W + 2 * H - u % W],
+                          ((unsigned long long)kb[u] << 32) | (z + (unsigned)u));
+        }
+        __syncthreads();
+
+        // the BH window rows this band completed: ring rows 0 .. BH - 1
+        {
+            const int gy = fin0 + ey, gx = tx0 - H + ex;
+            if (ex >= H && ex < EXT_W - H && gy >= s0 && gy < s_end && gx < N) {
+                const int u = min((int)(sh.key[ey * EXT_W + ex + H] & 0xffu), NW - 1);
+                const int sy = min(max(gy - H + u / W, 0), M - 1);
+                const int sx = min(max(gx - H + u % W, 0), N - 1);
+                const int src = (b * M + sy) * N + sx;
+                const int pix = (b * M + gy) * N + gx;
+                if constexpr (U8) {
+                    const uint8_t* s = static_cast<const uint8_t*>(prm.img) + (size_t)src * 3;
+                    uint8_t* o = static_cast<uint8_t*>(prm.out) + (size_t)pix * 3;
+                    o[0] = s[0]; o[1] = s[1]; o[2] = s[2];
+                } else {
+                    const float* s = static_cast<const float*>(prm.img) + (size_t)src * 3;
+                    float* o = static_cast<float*>(prm.out) + (size_t)pix * 3;
+                    o[0] = s[0]; o[1] = s[1]; o[2] = s[2];
+                }
+                if (prm.idx) prm.idx[pix] = (uint8_t)u;
+            }
+        }
+    }
+}
+
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+static hipError_t launch_strip(const FwdParams& prm, hipStream_t stream) {
+    using Gm = StripGeom<W, EXT_W, BH, NB>;
+    FwdParams q = prm;
+    q.grid = tile_grid(prm.B, (prm.N + Gm::TW - 1) / Gm::TW, (prm.M + Gm::S - 1) / Gm::S);
+    hipLaunchKernelGGL((fwd_strip_kernel<W, KIND, DIST, U8, EXT_W, BH, NB>), flat_grid(q.grid.n),
+                       dim3(Gm::NT), 0, stream, q);
+    return hipGetLastError();
+}
+
+}  // namespace odf

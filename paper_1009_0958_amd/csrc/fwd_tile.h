@@ -57,6 +57,24 @@ struct FwdShared {
     }
 };
 
+// The objective key of the windows whose angle part is staged (5x5 and larger
+// DDF), in two steps: the part of A alone -- A (p = 0 or 1/2), A^3 (p = 1/4) or
+// (1 - p) log2 A -- then its combination with D.  Every form of these filters
+// (tile, strip, batch) forms the key this way, so they select bit for bit alike.
+template <int MODE>
+__device__ __forceinline__ float staged_part(float a, float p) {
+    if constexpr (MODE == kObjQuarter) return (a * a) * a;  // A^3 D
+    else if constexpr (MODE == kObjLog) return (1.0f - p) * __builtin_amdgcn_logf(a);
+    else return a;  // A, A*D
+}
+template <int MODE>
+__device__ __forceinline__ uint32_t staged_key_bits(float part, float d, float p) {
+    if constexpr (MODE == kObjA) return __float_as_uint(part);
+    else if constexpr (MODE == kObjD) return __float_as_uint(d);
+    else if constexpr (MODE == kObjLog) return order_key(fmaf(p, __builtin_amdgcn_logf(d), part));
+    else return __float_as_uint(part * d);  // non-negative: the bits order like the values
+}
+
 template <int W, int KIND, bool AGG>
 constexpr bool stage_angle_part() {
     return W >= 5 && (KIND == kDDF || KIND == kCW) && !AGG;
@@ -171,11 +189,7 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
             for (int u = 0; u < NW; ++u) {
                 const int cy = ey - u / W, cx = ex - u % W;
                 if (cy < 0 || cy >= TH || cx < 0 || cx >= TW) continue;
-                const float a = A[u];
-                float part = a;                                            // A, A*D
-                if constexpr (MODE == kObjQuarter) part = (a * a) * a;     // A^3 D
-                else if constexpr (MODE == kObjLog) part = (1.0f - p) * __builtin_amdgcn_logf(a);
-                sh.stage[u * (TH * TW) + cy * TW + cx] = part;
+                sh.stage[u * (TH * TW) + cy * TW + cx] = staged_part<MODE>(A[u], p);
             }
         };
         if (mode == kObjQuarter) stage_parts(std::integral_constant<int, kObjQuarter>{});
@@ -255,12 +269,7 @@ __device__ __forceinline__ void fwd_tile(FwdSharedFor<W, KIND, DIST, U8, EXT_W, 
                 if (!window_ok(u)) continue;
                 const int cy = ey - u / W, cx = ex - u % W;
                 const float part = sh.stage[u * (TH * TW) + cy * TW + cx];
-                uint32_t bits;
-                if constexpr (MODE == kObjA) bits = __float_as_uint(part);
-                else if constexpr (MODE == kObjD) bits = __float_as_uint(D[u]);
-                else if constexpr (MODE == kObjLog)
-                    bits = order_key(fmaf(p, __builtin_amdgcn_logf(D[u]), part));
-                else bits = __float_as_uint(part * D[u]);  // non-negative: bits order
+                const uint32_t bits = staged_key_bits<MODE>(part, D[u], p);
                 const unsigned long long key = ((unsigned long long)bits << 32) | (unsigned)u;
                 atomicMin(&s_key[key_slot(u)], key);
             }

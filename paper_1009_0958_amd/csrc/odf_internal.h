@@ -96,6 +96,10 @@ bool tile_config_valid(int window, int kind, int cfg);
 int tile_config_default(int window, int kind);
 void tile_config_shape(int cfg, int* ext_w, int* ext_h);
 constexpr int kNumTileShapes = 4;
+// Forward configs: the four tile shapes, then the strip form (fwd_strip.h:
+// 32-wide strips of 8 bands of 16 rows; BVDF and DDF at 3x3 and 5x5).
+constexpr int kStripConfig = 4;
+constexpr int kNumTileConfigs = 5;
 // Extended-tile shapes (EXT_W x EXT_H, one thread per extended pixel) the
 // autotuners choose from, for the per-image and the batch kernels alike.
 constexpr int kTileW[kNumTileShapes] = {32, 64, 32, 64};

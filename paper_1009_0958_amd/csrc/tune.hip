@@ -143,7 +143,7 @@ bool valid_class(int window, int kind, int dist) {
 extern "C" {
 
 int odf_tile_config(int config, int* ext_w, int* ext_h) {
-    if (config < 0 || config >= odf::kNumTileShapes || !ext_w || !ext_h) return ODF_EINVAL;
+    if (config < 0 || config >= odf::kNumTileConfigs || !ext_w || !ext_h) return ODF_EINVAL;
     odf::tile_config_shape(config, ext_w, ext_h);
     return ODF_OK;
 }
@@ -188,7 +188,7 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     int rc = ODF_OK;
     int best = -1;
     float best_ms = 0.0f;
-    float ms_all[odf::kNumTileShapes];
+    float ms_all[odf::kNumTileConfigs];
     if (odf::test_fail_alloc() || hipMalloc(&img, npix * 3 * esz) != hipSuccess ||
         hipMalloc(&out, npix * 3 * esz) != hipSuccess || hipMalloc(&idx, npix) != hipSuccess) {
         rc = odf::set_error(ODF_ENOMEM, "autotune: device allocation failed");
@@ -200,7 +200,7 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
         rc = ODF_EHIP;
         goto done;
     }
-    for (int cfg = 0; cfg < odf::kNumTileShapes; ++cfg) {
+    for (int cfg = 0; cfg < odf::kNumTileConfigs; ++cfg) {
         ms_all[cfg] = -1.0f;
         if (!odf::tile_config_valid(window, kk, cfg)) continue;
         odf::FwdParams prm{};
@@ -235,7 +235,7 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     }
     if (best >= 0) odf::set_tuned_config(window, kind, dist, is_u8 != 0, best);
     if (times_ms)
-        for (int c = 0; c < odf::kNumTileShapes; ++c) times_ms[c] = ms_all[c];
+        for (int c = 0; c < odf::kNumTileConfigs; ++c) times_ms[c] = ms_all[c];
     if (cache_path && best >= 0) {
         hipDeviceProp_t prop;
         int dev = 0;
@@ -250,9 +250,9 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
         }
         fprintf(f,
                 "{\"arch\": \"%s\", \"window\": %d, \"kind\": %d, \"dist\": %d, \"u8\": %d, "
-                "\"config\": %d, \"M\": %d, \"N\": %d, \"ms\": [%.5f, %.5f, %.5f, %.5f]}\n",
+                "\"config\": %d, \"M\": %d, \"N\": %d, \"ms\": [%.5f, %.5f, %.5f, %.5f, %.5f]}\n",
                 prop.gcnArchName, window, kind, dist, is_u8 != 0, best, M, N, ms_all[0],
-                ms_all[1], ms_all[2], ms_all[3]);
+                ms_all[1], ms_all[2], ms_all[3], ms_all[4]);
         fclose(f);
     }
 done:

@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "odf.h")
 BVDF, DDF, ACWDDF, CWVMF, CWDDF = 0, 1, 2, 3, 4
 EXACT, MINIMAX, RGB = 0, 1, 2
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
+NUM_TILE_CONFIGS = 5  # ODF_NUM_TILE_CONFIGS: four tile shapes and the strip form
+STRIP = 4             # ODF_STRIP_CONFIG
 
 _KIND = {"bvdf": BVDF, "ddf": DDF, "acwddf": ACWDDF, "cwvmf": CWVMF, "cwddf": CWDDF}
 _DIST = {"exact": EXACT, "minimax": MINIMAX, "rgb": RGB}
@@ -543,8 +545,9 @@ def tune_set(window, kind, dist, is_u8, config):
 
 
 def autotune(window, kind, dist, is_u8=True, M=1024, N=1024, reps=10, cache_path=None):
-    """Time every tile shape, keep the fastest; returns (best, [ms per shape])."""
-    times = (ctypes.c_float * 4)()
+    """Time every forward config (the four tile shapes and the strip form), keep
+    the fastest; returns (best, [ms per config], -1 where not offered)."""
+    times = (ctypes.c_float * NUM_TILE_CONFIGS)()
     path = None if cache_path is None else cache_path.encode()
     _check(_batch_lib().odf_autotune(window, _kind(kind), _dist(dist), int(is_u8), M, N, reps,
                                      path, ctypes.cast(times, ctypes.c_void_p),

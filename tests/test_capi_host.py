@@ -109,6 +109,18 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_set(3, 0, 0, 1, -1) == odf.EINVAL
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
+    # config 4: the strip form (32 x 16 bands), BVDF and DDF at 3x3 and 5x5 only
+    assert odf.tile_config(odf.STRIP) == (32, 16)
+    assert L.odf_tile_config(odf.NUM_TILE_CONFIGS, ctypes.byref(ctypes.c_int()),
+                             ctypes.byref(ctypes.c_int())) == odf.EINVAL
+    for w, kind in ((3, odf.BVDF), (3, odf.DDF), (5, odf.BVDF), (5, odf.DDF)):
+        saved = odf.tune_get(w, kind, odf.EXACT, True)
+        assert L.odf_tune_set(w, kind, odf.EXACT, 1, odf.STRIP) == odf.OK
+        assert odf.tune_get(w, kind, odf.EXACT, True) == odf.STRIP
+        odf.tune_set(w, kind, odf.EXACT, True, saved)
+    for w, kind in ((7, odf.BVDF), (9, odf.DDF), (3, odf.ACWDDF), (5, odf.CWVMF), (5, odf.CWDDF)):
+        assert L.odf_tune_set(w, kind, odf.EXACT, 1, odf.STRIP) == odf.EINVAL
+    assert L.odf_tune_set(3, 0, 0, 1, odf.NUM_TILE_CONFIGS) == odf.EINVAL
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
     # batch tuning table: defaults, range checks, and the retired persistent form
     assert L.odf_batch_tune_get(3, odf.DDF) == 0 and L.odf_batch_tune_get(5, odf.BVDF) == 2
@@ -280,7 +292,7 @@ def test_allocation_failure_reports_enomem(monkeypatch):
     plan = ct.c_void_p()
     rc = L.odf_batch_plan(ct.cast(jobs, ct.c_void_p), 2, ct.byref(plan), None)
     assert rc == odf.ENOMEM and "allocation" in odf.last_error() and not plan.value
-    times = (ct.c_float * 4)()
+    times = (ct.c_float * 16)()
     for w, kind, dist, u8 in ((3, odf.DDF, odf.EXACT, 1), (5, odf.CWVMF, odf.EXACT, 0),
                               (7, odf.BVDF, odf.RGB, 1)):
         rc = L.odf_autotune(w, kind, dist, u8, 64, 64, 2, None, ct.cast(times, ct.c_void_p), None)
@@ -329,3 +341,12 @@ def test_noalloc_softmin_rejects_before_launch():
     assert f(FAKE, FAKE2, 1, 8, 8, 7, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE, None) == odf.EINVAL  # dx = x
     assert "overlaps" in odf.last_error()
+
+
+def test_header_config_constants_match_binding():
+    """The binding's config constants are the header's."""
+    import re
+    text = open(odf.HEADER).read()
+    defs = dict(re.findall(r"#define (ODF_\w+) (\d+)", text))
+    assert int(defs["ODF_NUM_TILE_CONFIGS"]) == odf.NUM_TILE_CONFIGS
+    assert int(defs["ODF_STRIP_CONFIG"]) == odf.STRIP

@@ -100,7 +100,7 @@ def test_tile_shapes_give_identical_results(window, kind):
     default = odf.tune_get(window, kind, odf.EXACT, True)
     ref = odf.filter(img, window, kind, 0.25, odf.EXACT)
     tried = 0
-    for cfg in range(4):
+    for cfg in range(odf.NUM_TILE_CONFIGS):
         try:
             odf.tune_set(window, kind, odf.EXACT, True, cfg)
         except odf.ODFError:
@@ -116,7 +116,8 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     best, times = odf.autotune(3, odf.DDF, odf.EXACT, True, 512, 512, 3, cache)
     print("autotune 3x3 DDF:", best, times)
-    assert 0 <= best < 4 and times[best] > 0 and times[best] == min(t for t in times if t > 0)
+    assert len(times) == odf.NUM_TILE_CONFIGS and times[odf.STRIP] > 0  # the strip form is timed
+    assert 0 <= best < odf.NUM_TILE_CONFIGS and times[best] == min(t for t in times if t > 0)
     best5, times5 = odf.autotune(5, odf.DDF, odf.EXACT, True, 256, 256, 2, cache)
     assert all(t > 0 for t in times5) and times5[best5] == min(times5)
     odf.tune_set(3, odf.DDF, odf.EXACT, True, 0)

@@ -527,15 +527,15 @@ def mismatch_sample(B, M, N, k, seed):
 
 def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
     """7680 x 4320 frame (3x3 BVDF, 5x5, 7x7 and 9x9) and 64 x 1920 x 1080
-    frames (5x5), correlated noise 0.15 (tile shapes autotuned per class first,
-    untimed).  With ``samples`` (a dict), the windows of 1 M seeded pixels
+    frames (5x5), correlated noise 0.15 (tile configs autotuned per class on a
+    frame of this size first, untimed).  With ``samples`` (a dict), the windows of 1 M seeded pixels
     (5x5; 100 000 for 3x3 and 7x7, 20 000 for 9x9) and the GPU's index there are
     kept for the oracle check of the cpu_baseline leg."""
     forms = {}
     for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF)):
         for d in ("exact", "minimax", "rgb"):
             if (w, kk, d) != (5, odf.DDF, "exact"):  # the step's class, tuned on this frame
-                autotune(odf, w, kk, DIST[d], True, 1024, 1024, 3)
+                autotune(odf, w, kk, DIST[d], True, 4320, 7680, 3)
     # (9 x 9 offers one tile shape)
     for tag, shape, key in (("7680x4320", (1, 4320, 7680), 5), ("64x1920x1080", (64, 1080, 1920), 6)):
         B, M, N = shape
@@ -556,6 +556,7 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
                 name = "%s%d_%s_%s" % (kind, w, d, tag)
                 forms[name] = {
                     "mpix_s": round(npx / (ms * 1e3), 1), "ms": round(ms, 3),
+                    "config": odf.tune_get(w, kk, DIST[d], True),
                     "valu_frac": round(slots_per_pixel(w, kind, p, d) * npx / (ms * 1e-3)
                                        / PEAK_SLOTS, 4)}
                 if samples is not None:

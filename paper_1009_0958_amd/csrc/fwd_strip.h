@@ -51,9 +51,9 @@ struct StripShared {
     float4 dir[NPIX];
     float4 raw[U8 ? 1 : NPIX];
     float inv[INV ? NPIX : 1];
-    float lead[2 * Gm::H];  // mirrored reads of the first row reach 2h floats before plane
-    float plane[NPL * Gm::G * Gm::PL + 2 * Gm::H];
-    float carry[NTERM * Gm::G * Gm::CROWS * EXT_W];
+    // plane rows and carried rows are copied as float4: both 16-byte aligned
+    alignas(16) float plane[NPL * Gm::G * Gm::PL + 4];
+    alignas(16) float carry[NTERM * Gm::G * Gm::CROWS * EXT_W];
     unsigned long long key[Gm::KEYN];
 };
 
@@ -62,28 +62,33 @@ struct StripShared {
 // above the band (before the barrier that publishes the band's own terms),
 // and after that barrier keeps this band's last g rows for the next band.
 // plane points at ring row 0 (the band starts at ring row 2h); NP planes of
-// stride PL.
+// stride PL.  One float4 per thread and step: carry holds, per g, NP * g rows
+// of EXT_W floats (plane by plane, row by row).
 template <int EXT_W, int BH, int H, int NP, int PL, int NT>
 struct StripCarry {
     float* plane;
     float* carry;
     int tid;
+    static_assert(EXT_W % 4 == 0 && PL % 4 == 0, "float4 rows");
+    static constexpr int Q = EXT_W / 4;  // float4 per row
     static constexpr int off(int g) { return NP * EXT_W * (g - 1) * g / 2; }
-    __device__ __forceinline__ void before(int g) const {
-        if (g == 0) return;
-        const int n = NP * g * EXT_W;
+    template <bool IN>
+    __device__ __forceinline__ void copy(int g, int row0) const {
+        const int n = NP * g * Q;
         for (int i = tid; i < n; i += NT) {
-            const int d = i / (g * EXT_W), k = i - d * (g * EXT_W);
-            plane[d * PL + (2 * H - g) * EXT_W + k] = carry[off(g) + i];
+            const int q = i / Q, c = i - q * Q;  // row q of the g NP carried rows
+            const int d = q / g, r = q - d * g;
+            float4* pl = reinterpret_cast<float4*>(plane + d * PL + (row0 + r) * EXT_W) + c;
+            float4* cr = reinterpret_cast<float4*>(carry + off(g)) + i;
+            if (IN) *pl = *cr;
+            else *cr = *pl;
         }
     }
+    __device__ __forceinline__ void before(int g) const {
+        if (g > 0) copy<true>(g, 2 * H - g);
+    }
     __device__ __forceinline__ void after(int g) const {
-        if (g == 0) return;
-        const int n = NP * g * EXT_W;
-        for (int i = tid; i < n; i += NT) {
-            const int d = i / (g * EXT_W), k = i - d * (g * EXT_W);
-            carry[off(g) + i] = plane[d * PL + (2 * H + BH - g) * EXT_W + k];
-        }
+        if (g > 0) copy<false>(g, 2 * H + BH - g);
     }
 };
 
@@ -117,7 +122,7 @@ __global__ void __launch_bounds__(EXT_W* BH)
     constexpr bool INV = Sh::INV;
     constexpr bool CANON = U8 && KIND == kBVDF;  // as in the tile form
     static_assert(Gm::KCARRY <= NT, "one carried key per thread");
-    static_assert(offsetof(Sh, plane) >= 2 * H * sizeof(float), "plane");
+    static_assert(offsetof(Sh, plane) >= 2 * H * sizeof(float), "reads before plane");
     __shared__ Sh sh;
 
     const int t = flat_block(prm.grid.n);

@@ -214,7 +214,7 @@ def tune_batch(odf, jobs, tag):
     """The batch groups' tile shapes for these jobs: loaded from the cache
     file --tune-cache + "." + tag when it exists, else tuned on the jobs
     (untimed; written there when --tune-cache is given).  Returns {group:
-    {ext_tile, ms_per_shape}} for the groups the jobs use."""
+    {config, ext_tile, ms_per_config}} for the groups the jobs use."""
     path = TUNE_CACHE + "." + tag if TUNE_CACHE else None
     if TUNE_CACHED and path and os.path.exists(path) and os.path.getsize(path) > 0:
         odf.tune_load(path)
@@ -222,8 +222,8 @@ def tune_batch(odf, jobs, tag):
         res = {g: (odf.batch_tune_get(int(g[1]), int(g.endswith("ddf"))), []) for g in groups}
     else:
         res = odf.autotune_batch_jobs(jobs, 2, path)
-    return {g: {"ext_tile": odf.tile_config(b), "ms_per_shape": [round(t, 4) for t in ms]}
-            for g, (b, ms) in res.items()}
+    return {g: {"config": b, "ext_tile": odf.tile_config(b),
+                "ms_per_config": [round(t, 4) for t in ms]} for g, (b, ms) in res.items()}
 
 
 HEADLINE = dict(window=5, kind="ddf", p=0.25, dist="exact", M=4320, N=7680, phi=0.15, key=500)
@@ -382,7 +382,7 @@ def main():
                    "launches_per_step": 1, "parallelism": "none"},
         "wall_s": round(wall, 3), "step_outputs_match_plain_launch": step_ok,
         "tuned": {"ddf5_exact_7680x4320": {"config": best_cfg, "ext_tile": ext,
-                                          "ms_per_shape": [round(t, 4) for t in shape_ms]}},
+                                          "ms_per_config": [round(t, 4) for t in shape_ms]}},
         "roofline": roofline, "forms": forms, "cpu_baseline": cpu,
         "paper_context": {"ddf3_exact_1024x1024_mpix_s": 0.0368,
                           "hardware": "Pentium D 2.66 GHz, C, gcc 3.4.4 (paper, Section II)"},
@@ -404,7 +404,7 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
     for d in ("exact", "minimax", "rgb"):
         best, times = autotune(odf, 3, odf.DDF, DIST[d], True, M, N, 10)
         tuned["ddf3_%s" % d] = {"config": best, "ext_tile": odf.tile_config(best),
-                                "ms_per_shape": [round(t, 5) for t in times]}
+                                "ms_per_config": [round(t, 5) for t in times]}
     outs = {v: (torch.empty_like(x), torch.empty((M, N), dtype=torch.uint8, device=dev))
             for v in variants}
 
@@ -758,11 +758,13 @@ def differentiable_forms(torch, odf, synth, dev):
     npx = 16 * 512 * 512
     out = torch.empty_like(x)
     idx = torch.empty(x.shape[:3], dtype=torch.uint8, device=dev)
+    # the hard forward's config, tuned on a float32 frame of the batch's rows and pixel count
+    hard_cfg, _ = autotune(odf, 5, odf.DDF, odf.EXACT, False, 512, 8192, 3)
     ms_f = time_launches(torch, lambda: odf.filter(x, 5, odf.DDF, 0.25, odf.EXACT, 4, out=out,
                                                    idx=idx), 10)
     ms_b = time_launches(torch, lambda: odf.backward_hard(idx, dy, 5), 10)
     forms["ddf5_f32_16x512x512_hard"] = {
-        "fwd_ms": round(ms_f, 3), "bwd_ms": round(ms_b, 3),
+        "fwd_ms": round(ms_f, 3), "bwd_ms": round(ms_b, 3), "fwd_config": hard_cfg,
         "fwd_bwd_mpix_s": round(npx / ((ms_f + ms_b) * 1e3), 1),
         "fwd_valu_frac": round(slots_per_pixel(5, "ddf", 0.25, "exact", u8=False) * npx
                                / (ms_f * 1e-3)

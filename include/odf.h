@@ -325,8 +325,9 @@ int odf_batch_launch(const odf_plan* plan, void* stream);
  * nullable): its tiles, and the workgroups launched for them (one per tile). */
 int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles, int* grids);
 
-/* The tile shape (odf_tile_config number) each group of the plan runs on,
- * group = (window == 5) * 2 + kind, configs[4].  ODF_EINVAL for NULL. */
+/* The config each group of the plan runs on (a tile shape, odf_tile_config
+ * number, or ODF_STRIP_CONFIG), group = (window == 5) * 2 + kind, configs[4].
+ * ODF_EINVAL for NULL. */
 int odf_plan_configs(const odf_plan* plan, int* configs);
 
 /* Free a plan (after its last launch has completed). */
@@ -409,17 +410,19 @@ int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /*
 int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
                  const char* cache_path, float* times_ms, void* stream);
 
-/* The batch tuning table: the tile shape (0..3) of the batch group of
+/* The batch tuning table: the config (0..3 a tile shape, ODF_STRIP_CONFIG the
+ * strip form) of the batch group of
  * `window` (3, 5) and `kind` (ODF_BVDF, ODF_DDF); 32 x 32 for 3x3 DDF and
  * 32 x 16 otherwise until tuned.  get returns the config or ODF_EINVAL; set
  * returns ODF_OK or ODF_EINVAL.  Plans read the table when they are made. */
 int odf_batch_tune_get(int window, int kind);
 int odf_batch_tune_set(int window, int kind, int config);
 
-/* Time the four tile shapes of one batch group on a seeded mixed work list
- * (six tuning images from 64 x 64 to 1920 x 1080, each with the three pair
- * terms: 18 jobs; reps launches per shape, HIP events on `stream`), set the
- * fastest in the batch table, store the per-shape milliseconds in times_ms[4]
+/* Time the ODF_NUM_TILE_CONFIGS configs of one batch group on a seeded mixed
+ * work list (six tuning images from 64 x 64 to 1920 x 1080, each with the
+ * three pair terms: 18 jobs; reps launches per config, HIP events on
+ * `stream`), set the fastest in the batch table, store the per-config
+ * milliseconds in times_ms[ODF_NUM_TILE_CONFIGS]
  * (nullable) and append one JSON line to cache_path (nullable).  Allocates
  * and frees device memory and synchronises `stream`.  Errors: ODF_EINVAL,
  * ODF_ENOMEM, ODF_EHIP. */
@@ -427,11 +430,12 @@ int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, f
                        void* stream);
 
 /* The same on the caller's own jobs (validated as for odf_batch_plan): for each
- * batch group that holds jobs, its four tile shapes are timed on the group's
- * jobs (reps launches each; the jobs' outputs are written) and the fastest is
- * set in the batch table and appended to cache_path (nullable);
- * times_ms[4 * group + shape] (nullable, 16 floats) receives the milliseconds,
- * -1 for groups without jobs.  A plan made afterwards for the same jobs runs
+ * batch group that holds jobs, its configs are timed on the group's jobs (reps
+ * launches each; the jobs' outputs are written) and the fastest is set in the
+ * batch table and appended to cache_path (nullable);
+ * times_ms[ODF_NUM_TILE_CONFIGS * group + config] (nullable, 4 *
+ * ODF_NUM_TILE_CONFIGS floats) receives the milliseconds, -1 for groups
+ * without jobs.  A plan made afterwards for the same jobs runs
  * on the shapes tuned for them.  Errors: as odf_batch_plan. */
 int odf_autotune_batch_jobs(const odf_job* jobs, int njobs, int reps, const char* cache_path,
                             float* times_ms, void* stream);

@@ -10,22 +10,24 @@
 // variants of one window share a register budget (3x3: 64 VGPRs); windows
 // and kinds do not (a kernel branching over 3x3 and 5x5 would carry the 5x5
 // budget everywhere), so they keep kernels of their own.  Each group runs one
-// workgroup per tile of its list, dispatched in list order, on the extended
-// tile shape of the batch tuning table (odf_autotune_batch times the four
-// shapes on a mixed list).  odf_batch_launch enqueues the group kernels,
+// workgroup per tile of its list, dispatched in list order, on the config of
+// the batch tuning table: one of the four extended tile shapes, or the strip
+// form, whose work items are 32-wide strips of 8 bands that keep the rows
+// shared by consecutive bands in LDS (fwd_strip.h); odf_autotune_batch times
+// the five on a mixed list, odf_autotune_batch_jobs on the caller's jobs.  odf_batch_launch enqueues the group kernels,
 // forked onto per-plan auxiliary streams (default priority) and joined back
 // with events so that groups run concurrently and their tails overlap; it
 // allocates nothing and never synchronises, so it can be captured in a
-// hipGraph.  Every tile writes only its own outputs with the same tile
-// function as the per-image kernels, so results do not depend on the shape or
-// on which workgroup takes which tile.
+// hipGraph.  Every tile or strip writes only its own outputs with the same
+// function as the per-image kernels, so results do not depend on the config
+// or on which workgroup takes which item.
 #include <stdio.h>
 
 #include <algorithm>
 #include <new>
 #include <vector>
 
-#include "fwd_tile.h"
+#include "fwd_strip.h"
 #include "odf.h"
 
 namespace odf {
@@ -133,12 +135,72 @@ __global__ void __launch_bounds__(BatchShape<CFG>::THREADS)
                                        bc, tile);
 }
 
+// The strip form of a group (config kStripConfig): one workgroup per strip of
+// the list (ty0, tx0 its first output row and column), 32-wide strips of 8
+// bands of 16 rows as in the per-image strip kernels.
+constexpr int kStripBands = 8;
+template <int W, int KIND, int DIST>
+using StripSh = StripShared<W, KIND, DIST, true, 32, 16, kStripBands>;
+
+template <int W, int KIND>
+struct BatchStripSmem {
+    static constexpr size_t a = sizeof(StripSh<W, KIND, kExact>),
+                            b = sizeof(StripSh<W, KIND, kMinimax>),
+                            c = sizeof(StripSh<W, KIND, kRgb>);
+    static constexpr size_t BYTES = a > b ? (a > c ? a : c) : (b > c ? b : c);
+};
+
+template <int W, int KIND, int DIST>
+__device__ __forceinline__ void batch_strip(StripSh<W, KIND, DIST>& sh, const BatchClass& bc,
+                                            const BatchTile& tile) {
+    const BatchJob& job = bc.jobs[uni(tile.job)];
+    FwdParams prm{};
+    prm.img = uni(job.img);
+    prm.out = uni(job.out);
+    prm.idx = uni(job.idx);
+    prm.B = 1;
+    prm.M = uni(job.M);
+    prm.N = uni(job.N);
+    prm.p = uni(job.p);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        prm.coef.asin_c[k] = uni(job.coef.asin_c[k]);
+        prm.coef.acos_c[k] = uni(job.coef.acos_c[k]);
+    }
+    fwd_strip<W, KIND, DIST, true, 32, 16, kStripBands>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0));
+}
+
+// Occupancy target: the waves per SIMD the LDS of the largest pair term allows.
+template <int W, int KIND>
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(BatchStripSmem<W, KIND>::BYTES, 512))))
+    batch_strip_kernel(BatchClass bc) {
+    __shared__ __align__(16) char smem[BatchStripSmem<W, KIND>::BYTES];
+    const int t = flat_block(bc.ntiles);
+    if (t < 0) return;
+    const BatchTile tile = bc.tiles[t];
+    const int dist = uni(bc.jobs[uni(tile.job)].dist);
+    if (dist == kExact)
+        batch_strip<W, KIND, kExact>(*reinterpret_cast<StripSh<W, KIND, kExact>*>(smem), bc, tile);
+    else if (dist == kMinimax)
+        batch_strip<W, KIND, kMinimax>(*reinterpret_cast<StripSh<W, KIND, kMinimax>*>(smem), bc,
+                                       tile);
+    else
+        batch_strip<W, KIND, kRgb>(*reinterpret_cast<StripSh<W, KIND, kRgb>*>(smem), bc, tile);
+}
+
 // class = ((window == 5) * 2 + kind) * 3 + dist; group = class / 3
 constexpr int kNumGroups = kNumClasses / 3;
 static int group_window(int grp) { return grp / 2 ? 5 : 3; }
 
 static void group_geometry(int grp, int cfg, int& tw, int& th, int& threads) {
     const int h = group_window(grp) / 2;
+    if (cfg == kStripConfig) {
+        tw = 32 - 2 * h;
+        th = kStripBands * 16 - 2 * h;
+        threads = 512;
+        return;
+    }
     tw = kTileW[cfg] - 2 * h;
     th = kTileH[cfg] - 2 * h;
     threads = kTileW[cfg] * kTileH[cfg];
@@ -151,7 +213,8 @@ static void launch_group_wk(int cfg, int threads, const BatchClass& bc, hipStrea
     case 0: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), grid, dim3(threads), 0, s, bc); break;
     case 1: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), grid, dim3(threads), 0, s, bc); break;
     case 2: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 2>), grid, dim3(threads), 0, s, bc); break;
-    default: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 3>), grid, dim3(threads), 0, s, bc); break;
+    case 3: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 3>), grid, dim3(threads), 0, s, bc); break;
+    default: hipLaunchKernelGGL((batch_strip_kernel<W, KIND>), grid, dim3(threads), 0, s, bc); break;
     }
 }
 
@@ -300,15 +363,15 @@ int make_plan(const odf_job* jobs, int njobs, const int* cfg, odf_plan** plan) {
     return ODF_OK;
 }
 
-// Time the four tile shapes of group grp on the jobs of that group among
-// jobs[] (reps launches each after two untimed ones); ms[c] = -1 when the
-// group has no job.  Returns ODF_OK or an error code (message set).
+// Time the five configs (four tile shapes, the strip form) of group grp on the
+// jobs of that group among jobs[] (reps launches each after two untimed ones);
+// ms[c] = -1 when the group has no job.  Returns ODF_OK or an error code (message set).
 int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* ms,
                       hipStream_t s) {
     std::vector<odf_job> sub;
     for (int i = 0; i < njobs; ++i)
         if ((jobs[i].window == 5) * 2 + (jobs[i].kind == ODF_DDF) == grp) sub.push_back(jobs[i]);
-    for (int c = 0; c < odf::kNumTileShapes; ++c) ms[c] = -1.0f;
+    for (int c = 0; c < odf::kNumTileConfigs; ++c) ms[c] = -1.0f;
     if (sub.empty()) return ODF_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -316,7 +379,7 @@ int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* 
         return bfail(ODF_EHIP, "autotune_batch: event creation failed");
     }
     int rc = ODF_OK;
-    for (int c = 0; c < odf::kNumTileShapes && rc == ODF_OK; ++c) {
+    for (int c = 0; c < odf::kNumTileConfigs && rc == ODF_OK; ++c) {
         int cfg[odf::kNumGroups];
         for (int g = 0; g < odf::kNumGroups; ++g) cfg[g] = odf::batch_tuned_config(g);
         cfg[grp] = c;
@@ -338,10 +401,10 @@ int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* 
     return rc;
 }
 
-// The fastest shape of ms[4] (ignoring -1), or -1.
+// The fastest config of ms[kNumTileConfigs] (ignoring -1), or -1.
 int fastest(const float* ms) {
     int best = -1;
-    for (int c = 0; c < odf::kNumTileShapes; ++c)
+    for (int c = 0; c < odf::kNumTileConfigs; ++c)
         if (ms[c] >= 0.0f && (best < 0 || ms[c] < ms[best])) best = c;
     return best;
 }
@@ -357,8 +420,9 @@ int write_batch_line(const char* cache_path, int grp, int best, const float* ms)
     if (!f) return odf::set_error(ODF_EINVAL, "cannot open %s", cache_path);
     fprintf(f,
             "{\"arch\": \"%s\", \"batch_window\": %d, \"kind\": %d, \"config\": %d, "
-            "\"ms\": [%.5f, %.5f, %.5f, %.5f]}\n",
-            prop.gcnArchName, odf::group_window(grp), grp % 2, best, ms[0], ms[1], ms[2], ms[3]);
+            "\"ms\": [%.5f, %.5f, %.5f, %.5f, %.5f]}\n",
+            prop.gcnArchName, odf::group_window(grp), grp % 2, best, ms[0], ms[1], ms[2], ms[3],
+            ms[4]);
     fclose(f);
     return ODF_OK;
 }
@@ -444,7 +508,7 @@ int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, f
     for (int i = 0; i < kImages; ++i)
         odf::tuning_image(kSizes[i][0], kSizes[i][1], 2009 + i, host.data() + off[i]);
     uint8_t *img = nullptr, *out = nullptr;
-    float ms[odf::kNumTileShapes];
+    float ms[odf::kNumTileConfigs];
     int rc = ODF_OK, best = -1;
     std::vector<odf_job> jobs;
     if (odf::test_fail_alloc() || hipMalloc(&img, off[kImages]) != hipSuccess ||
@@ -466,7 +530,7 @@ int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, f
     best = fastest(ms);
     odf::set_batch_tuned_config(grp, best);
     if (times_ms)
-        for (int c = 0; c < odf::kNumTileShapes; ++c) times_ms[c] = ms[c];
+        for (int c = 0; c < odf::kNumTileConfigs; ++c) times_ms[c] = ms[c];
     rc = write_batch_line(cache_path, grp, best, ms);
 done:
     if (img) (void)hipFree(img);
@@ -487,11 +551,12 @@ int odf_autotune_batch_jobs(const odf_job* jobs, int njobs, int reps, const char
     if (rc != ODF_OK) return rc;
     destroy(probe);
     for (int g = 0; g < odf::kNumGroups; ++g) {
-        float ms[odf::kNumTileShapes];
+        float ms[odf::kNumTileConfigs];
         rc = time_group_shapes(jobs, njobs, g, reps, ms, static_cast<hipStream_t>(stream));
         if (rc != ODF_OK) return rc;
         if (times_ms)
-            for (int c = 0; c < odf::kNumTileShapes; ++c) times_ms[4 * g + c] = ms[c];
+            for (int c = 0; c < odf::kNumTileConfigs; ++c)
+                times_ms[odf::kNumTileConfigs * g + c] = ms[c];
         const int best = fastest(ms);
         if (best < 0) continue;  // no job of this group
         odf::set_batch_tuned_config(g, best);

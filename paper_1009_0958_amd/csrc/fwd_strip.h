@@ -101,21 +101,24 @@ constexpr bool strip_form() {
 // Occupancy target of a strip kernel: the waves per SIMD that its LDS allows
 // (160 KiB per CU shared by whole workgroups of NT / 256 waves per SIMD), at
 // most 8; the register budget is fitted to it.
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
-constexpr int strip_waves_per_eu() {
-    constexpr int wgs = (160 * 1024) / (int)sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>);
-    constexpr int waves = wgs * (EXT_W * BH / 256);
+constexpr int lds_waves_per_eu(size_t lds_bytes, int threads) {
+    const int waves = (int)((160 * 1024) / lds_bytes) * (threads / 256);
     return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
 }
-
-// One workgroup per strip of S output rows x TW output columns of one image.
-// Bands start h rows above the strip and the first band's 2h top window rows
-// lie above it (discarded); a band reads its RING pixel rows (replicated
-// border), sweeps, and then writes the BH window rows its members completed.
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
-__global__ void __launch_bounds__(EXT_W* BH)
-    __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<W, KIND, DIST, U8, EXT_W, BH, NB>())))
-    fwd_strip_kernel(FwdParams prm) {
+constexpr int strip_waves_per_eu() {
+    return lds_waves_per_eu(sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>), EXT_W * BH);
+}
+
+// Filter the strip of image b whose first output row is s0 and first output
+// column tx0 (S output rows x TW output columns, clipped to the image).  Bands
+// start h rows above the strip and the first band's 2h top window rows lie
+// above it (discarded); a band reads its RING pixel rows (replicated border),
+// sweeps, and then writes the BH window rows its members completed.  Every
+// thread of the workgroup must call it (it synchronises).
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+__device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>& sh,
+                                          const FwdParams& prm, int b, int s0, int tx0) {
     using Gm = StripGeom<W, EXT_W, BH, NB>;
     using Sh = StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, NT = Gm::NT, PL = Gm::PL;
@@ -123,12 +126,6 @@ __global__ void __launch_bounds__(EXT_W* BH)
     constexpr bool CANON = U8 && KIND == kBVDF;  // as in the tile form
     static_assert(Gm::KCARRY <= NT, "one carried key per thread");
     static_assert(offsetof(Sh, plane) >= 2 * H * sizeof(float), "reads before plane");
-    __shared__ Sh sh;
-
-    const int t = flat_block(prm.grid.n);
-    if (t < 0) return;
-    const TileCoord tc = tile_coord(t, prm.grid);
-    const int b = tc.b, s0 = tc.ty * Gm::S, tx0 = tc.tx * Gm::TW;
     const int M = prm.M, N = prm.N;
     const int s_end = min(s0 + Gm::S, M);
     const TilePix px{sh.dir, sh.raw, sh.inv};
@@ -260,6 +257,19 @@ __global__ void __launch_bounds__(EXT_W* BH)
             }
         }
     }
+}
+
+// One workgroup per strip of the launch's images.
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+__global__ void __launch_bounds__(EXT_W* BH)
+    __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<W, KIND, DIST, U8, EXT_W, BH, NB>())))
+    fwd_strip_kernel(FwdParams prm) {
+    __shared__ StripShared<W, KIND, DIST, U8, EXT_W, BH, NB> sh;
+    using Gm = StripGeom<W, EXT_W, BH, NB>;
+    const int t = flat_block(prm.grid.n);
+    if (t < 0) return;
+    const TileCoord tc = tile_coord(t, prm.grid);
+    fwd_strip<W, KIND, DIST, U8, EXT_W, BH, NB>(sh, prm, tc.b, tc.ty * Gm::S, tc.tx * Gm::TW);
 }
 
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>

@@ -271,7 +271,7 @@ int odf_batch_tune_get(int window, int kind) {
 
 int odf_batch_tune_set(int window, int kind, int config) {
     if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || config < 0 ||
-        config >= odf::kNumTileShapes)
+        config >= odf::kNumTileConfigs)
         return ODF_EINVAL;
     odf::set_batch_tuned_config((window == 5) * 2 + kind, config);
     return ODF_OK;

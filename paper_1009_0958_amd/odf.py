@@ -567,9 +567,9 @@ def batch_tune_set(window, kind, config):
 
 
 def autotune_batch(window, kind, reps=3, cache_path=None):
-    """Time the batch group's four tile shapes on a mixed work list, keep the
-    fastest; returns (best, [ms per shape])."""
-    times = (ctypes.c_float * 4)()
+    """Time the batch group's configs (four tile shapes, the strip form) on a
+    mixed work list, keep the fastest; returns (best, [ms per config])."""
+    times = (ctypes.c_float * NUM_TILE_CONFIGS)()
     path = None if cache_path is None else cache_path.encode()
     _check(_batch_lib().odf_autotune_batch(window, _kind(kind), reps, path,
                                            ctypes.cast(times, ctypes.c_void_p),
@@ -578,18 +578,19 @@ def autotune_batch(window, kind, reps=3, cache_path=None):
 
 
 def autotune_batch_jobs(jobs, reps=2, cache_path=None):
-    """Time every batch group's four tile shapes on these jobs (their outputs
-    are written), keep the fastest per group; returns {group name: (best,
-    [ms per shape])} for the groups that hold jobs."""
+    """Time every batch group's configs on these jobs (their outputs are
+    written), keep the fastest per group; returns {group name: (best,
+    [ms per config])} for the groups that hold jobs."""
     arr, keep = _job_array(jobs)
-    times = (ctypes.c_float * 16)()
+    C = NUM_TILE_CONFIGS
+    times = (ctypes.c_float * (4 * C))()
     path = None if cache_path is None else cache_path.encode()
     _check(_batch_lib().odf_autotune_batch_jobs(ctypes.cast(arr, ctypes.c_void_p), len(jobs), reps,
                                                 path, ctypes.cast(times, ctypes.c_void_p),
                                                 _stream(torch.cuda.current_device())))
     res = {}
     for g in range(4):
-        ms = list(times[4 * g:4 * g + 4])
+        ms = list(times[C * g:C * g + C])
         if ms[0] >= 0:
             w, k = 3 + 2 * (g // 2), g % 2
             res["w%d_%s" % (w, ("bvdf", "ddf")[k])] = (batch_tune_get(w, k), ms)

@@ -126,7 +126,10 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_batch_tune_get(3, odf.DDF) == 0 and L.odf_batch_tune_get(5, odf.BVDF) == 2
     assert L.odf_batch_tune_get(7, odf.DDF) == odf.EINVAL
     assert L.odf_batch_tune_get(3, odf.ACWDDF) == odf.EINVAL
-    assert L.odf_batch_tune_set(3, odf.BVDF, 4) == odf.EINVAL
+    assert L.odf_batch_tune_set(3, odf.BVDF, odf.NUM_TILE_CONFIGS) == odf.EINVAL
+    assert L.odf_batch_tune_set(3, odf.BVDF, odf.STRIP) == odf.OK  # the strip form
+    assert L.odf_batch_tune_get(3, odf.BVDF) == odf.STRIP
+    assert L.odf_batch_tune_set(3, odf.BVDF, 2) == odf.OK
     assert L.odf_batch_tune_set(5, odf.DDF, -1) == odf.EINVAL
     assert L.odf_batch_tune_set(5, odf.DDF, 1) == odf.OK and L.odf_batch_tune_get(5, odf.DDF) == 1
     assert L.odf_batch_tune_set(5, odf.DDF, 2) == odf.OK

@@ -40,9 +40,10 @@ def _per_image(job):
     return odf.filter(job["img"], job["window"], job["kind"], job["p"], job["dist"], job["q"])
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 def test_batch_equals_per_image_and_oracle(cfg):
-    """Every group on tile shape cfg (the batch tuning table set for all four)."""
+    """Every group on config cfg (the batch tuning table set for all four): a
+    tile shape, or the strip form (4)."""
     jobs, imgs = _mixed_jobs(40, 1)
     keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
     try:
@@ -134,7 +135,9 @@ def test_autotune_batch_drives_the_plan(tmp_path):
     try:
         best, times = odf.autotune_batch(5, odf.BVDF, 2, cache)
         print("autotune_batch 5x5 BVDF:", best, times, flush=True)
-        assert 0 <= best < 4 and all(t > 0 for t in times) and times[best] == min(times)
+        assert len(times) == odf.NUM_TILE_CONFIGS
+        assert 0 <= best < odf.NUM_TILE_CONFIGS and all(t > 0 for t in times)
+        assert times[best] == min(times)
         jobs, _ = _mixed_jobs(6, 3)
         for j in jobs:
             j["window"], j["kind"] = 5, odf.BVDF
@@ -146,7 +149,7 @@ def test_autotune_batch_drives_the_plan(tmp_path):
             out, idx = _per_image(j)
             assert torch.equal(j["out"], out) and torch.equal(j["idx"], idx)
         plan.close()
-        odf.batch_tune_set(5, odf.BVDF, (best + 1) % 4)
+        odf.batch_tune_set(5, odf.BVDF, (best + 1) % odf.NUM_TILE_CONFIGS)
         assert odf.tune_load(cache) == 1 and odf.batch_tune_get(5, odf.BVDF) == best
     finally:
         for (w, k), c in keep.items():
@@ -167,7 +170,8 @@ def test_autotune_batch_on_the_callers_jobs():
         plan = odf.BatchPlan(jobs)
         info = plan.info()
         for g, (best, ms) in res.items():
-            assert ms[best] == min(ms) and info["ext_tiles"][g] == odf.tile_config(best)
+            assert len(ms) == odf.NUM_TILE_CONFIGS and ms[best] == min(ms)
+            assert info["ext_tiles"][g] == odf.tile_config(best)
         plan.launch()
         torch.cuda.synchronize()
         for j in jobs:

@@ -351,7 +351,7 @@ def main():
             "large_frames": lambda: large_frame_forms(torch, odf, synth, dev, DIST, samples),
             "acwddf": lambda: acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx),
             "effectiveness": lambda: effectiveness_forms(torch, odf, synth, dev, DIST),
-            "batched": lambda: batched_form(torch, odf, synth, dev, samples),
+            "batched": lambda: batched_form(torch, odf, synth, dev, DIST, samples),
             "differentiable": lambda: differentiable_forms(torch, odf, synth, dev)}
         for name in groups:
             t_form = time.perf_counter()
@@ -475,10 +475,13 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
     slots_px = sum(slots_per_pixel(3, "ddf", p, d) for (p, d) in variants) / len(variants)
     if best == "graph_batch_direct":
         # one kernel over the tiles of all six variants: the form's time is its time
-        ext6 = graphs["direct"][0].info()["ext_tiles"]["w3_ddf"]
-        dname = "batch_direct_kernel ddf3 %dx%d, six variants in one launch" % tuple(ext6)
+        info6 = graphs["direct"][0].info()
+        ext6 = info6["ext_tiles"]["w3_ddf"]
+        strip6 = info6["configs"][1] == odf.STRIP
+        dname = (("batch_strip_kernel ddf3 %dx%d bands" if strip6 else "batch_direct_kernel ddf3 %dx%d")
+                 + ", six variants in one launch") % tuple(ext6)
         dms, dpx = ms_step, npx
-        tb = traffic_bytes("batch6", ext6)
+        tb = traffic_bytes("batch6_strip" if strip6 else "batch6", ext6)
     else:
         dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
         dp, dd = float(dom.split("_")[1][1:]), dom.split("_")[2]
@@ -644,7 +647,7 @@ def effectiveness_forms(torch, odf, synth, dev, DIST):
     return {"effectiveness_1024x1024_eq8": table, **rates}
 
 
-def batched_form(torch, odf, synth, dev, samples=None):
+def batched_form(torch, odf, synth, dev, DIST, samples=None):
     """256 uint8 images of mixed size (64..2048 x 64..1536), window, kind and
     noise: one planned launch captured in a graph (one kernel per window and
     kind, on the tile shapes the batch autotuner picks per group on these
@@ -655,12 +658,14 @@ def batched_form(torch, odf, synth, dev, samples=None):
     back at their own rates."""
     specs = synth.mixed_batch_specs(256)
     imgs = synth.mixed_batch_images(specs, workers=16)
-    # tile shapes of the per-image launches of the loop (untimed)
+    # configs of the per-image launches of the loop, every class tuned on a
+    # 1024 x 1024 image, about the batch's mean image size (untimed)
     tuned = {}
     for w in (3, 5):
         for kind in (odf.BVDF, odf.DDF):
-            best, _ = autotune(odf, w, kind, odf.EXACT, True, 1024, 1024, 5)
-            tuned[f"w{w}_{'ddf' if kind else 'bvdf'}"] = odf.tile_config(best)
+            for d in ("exact", "minimax", "rgb"):
+                best, _ = autotune(odf, w, kind, DIST[d], True, 1024, 1024, 5)
+                tuned[f"w{w}_{'ddf' if kind else 'bvdf'}_{d}"] = best
     jobs = []
     for s_, im in zip(specs, imgs):
         t = torch.from_numpy(im).to(dev)
@@ -713,8 +718,9 @@ def batched_form(torch, odf, synth, dev, samples=None):
             gidx = j["idx"].reshape(-1)[torch.from_numpy(pix).to(dev)].cpu().numpy()
             samples.setdefault("batch", []).append((j["window"], j["kind"], j["p"], win, gidx))
     return {"batched_256_mixed": {
-        "mpix": round(npx / 1e6, 2), "loop_tile_shapes": tuned,
+        "mpix": round(npx / 1e6, 2), "loop_configs": tuned,
         "batch_tile_shapes": batch_tuned, "plan_ext_tiles": info["ext_tiles"],
+        "plan_configs": dict(zip(("w3_bvdf", "w3_ddf", "w5_bvdf", "w5_ddf"), info["configs"])),
         "direct_graph_ms": round(ms_direct, 3),
         "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
         "loop_ms": round(ms_loop, 3), "loop_mpix_s": round(npx / (ms_loop * 1e3), 1),

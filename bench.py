@@ -199,13 +199,21 @@ def time_launches(torch, fn, reps, warm=3):
 
 
 TUNE_CACHE = None  # set by --tune-cache
-TUNE_CACHED = False  # the cache existed when the run started: apply it, tune nothing
+TUNE_CACHED = False  # the cache existed when the run started: replay it, tune nothing
+TUNE_REPLAY = []  # the cache's per-image entries in the order the first run tuned them
 
 
 def autotune(odf, window, kind, dist, u8, M, N, reps):
-    """The library's autotuner, or the tuning cache's entry when --tune-cache
-    named an existing file at start-up (returns (config, ms per shape or []))."""
+    """The library's autotuner, or, when --tune-cache named an existing file at
+    start-up, the next entry of that cache for this class: a class tuned twice
+    (on different sizes) gets the same config at each point of the run as in
+    the run that wrote the cache.  Returns (config, ms per config or [])."""
     if TUNE_CACHED:
+        for n, e in enumerate(TUNE_REPLAY):
+            if e[:4] == (window, kind, dist, int(bool(u8))):
+                del TUNE_REPLAY[n]
+                odf.tune_set(window, kind, dist, u8, e[4])
+                return e[4], []
         return odf.tune_get(window, kind, dist, u8), []
     return odf.autotune(window, kind, dist, u8, M, N, reps, cache_path=TUNE_CACHE)
 
@@ -275,7 +283,11 @@ def main():
     TUNE_CACHED = bool(TUNE_CACHE) and os.path.exists(TUNE_CACHE) and \
         os.path.getsize(TUNE_CACHE) > 0
     if TUNE_CACHED:
-        odf.tune_load(TUNE_CACHE)
+        with open(TUNE_CACHE) as f:
+            for line in f:
+                e = json.loads(line)
+                if "window" in e:
+                    TUNE_REPLAY.append((e["window"], e["kind"], e["dist"], e["u8"], e["config"]))
 
     # ---------------------------------------------------------------- the step
     # DDF 5x5 (p = 1/4, exact angle) on one 7680 x 4320 uint8 frame, correlated
@@ -535,11 +547,12 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
     (5x5; 100 000 for 3x3 and 7x7, 20 000 for 9x9) and the GPU's index there are
     kept for the oracle check of the cpu_baseline leg."""
     forms = {}
-    for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF)):
+    for w, kk in ((3, odf.BVDF), (5, odf.BVDF), (5, odf.DDF), (7, odf.BVDF), (7, odf.DDF),
+                  (9, odf.BVDF)):
         for d in ("exact", "minimax", "rgb"):
             if (w, kk, d) != (5, odf.DDF, "exact"):  # the step's class, tuned on this frame
                 autotune(odf, w, kk, DIST[d], True, 4320, 7680, 3)
-    # (9 x 9 offers one tile shape)
+    # (9 x 9 DDF offers one config)
     for tag, shape, key in (("7680x4320", (1, 4320, 7680), 5), ("64x1920x1080", (64, 1080, 1920), 6)):
         B, M, N = shape
         imgs = np.stack([synth.image_corr(M, N, 0.15, key=key * 100 + b) for b in range(B)])

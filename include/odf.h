@@ -380,7 +380,8 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * The forward kernels run one thread per pixel of an extended tile
  * (output tile plus halo).  Configs 0..3 are tile shapes (one workgroup per
  * output tile); config ODF_STRIP_CONFIG (4) is the strip form, offered for
- * ODF_BVDF and ODF_DDF at 3x3 and 5x5: one workgroup per strip of 32 - 2h
+ * ODF_BVDF and ODF_DDF at 3x3, 5x5 and 7x7 and for ODF_BVDF at 9x9 on uint8
+ * (the batch offers it for all its groups): one workgroup per strip of 32 - 2h
  * output columns and 128 - 2h output rows, walking down it in bands of 32 x 16
  * member pixels and keeping the pair terms and argmin keys that consecutive
  * bands share in LDS, so that the rows of the halo between bands are not

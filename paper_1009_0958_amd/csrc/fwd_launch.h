@@ -50,14 +50,20 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
     if constexpr (AGG) {  // inspection path: one shape (it keeps every aggregate live)
         (void)cfg;
         return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
-    } else if constexpr (W == 9) {  // 512 threads, 8 output rows: the one shape offered
-        return cfg == 2 ? launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream)
-                        : hipErrorInvalidValue;
+    } else if constexpr (W == 9) {  // 512 threads, 8 output rows: the one tile shape offered
+        if (cfg == 2) return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
+        if constexpr (strip_form<W, KIND, U8>())
+            if (cfg == kStripConfig) return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
+        return hipErrorInvalidValue;
     } else if constexpr ((W == 5 && centre_weighted(KIND)) || W == 7) {
         switch (cfg) {
         case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
-        default: return hipErrorInvalidValue;
+        default:
+            if constexpr (strip_form<W, KIND, U8>())
+                if (cfg == kStripConfig)
+                    return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
+            return hipErrorInvalidValue;
         }
     } else {
         switch (cfg) {
@@ -66,7 +72,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
         default:
-            if constexpr (strip_form<W, KIND>())  // 32-wide strips of 8 bands of 16 rows
+            if constexpr (strip_form<W, KIND, U8>())  // 32-wide strips of 8 bands of 16 rows
                 return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
             return hipErrorInvalidValue;
         }

@@ -92,10 +92,13 @@ struct StripCarry {
     }
 };
 
-// The classes with a strip form: BVDF and DDF at 3x3 and 5x5.
-template <int W, int KIND>
+// The classes with a strip form: BVDF and DDF at 3x3, 5x5 and 7x7, and BVDF
+// at 9x9 on uint8 (the float32 9x9 strip and the 9x9 DDF strip, with its
+// second set of carried planes, would not fit the 160 KiB of LDS of a CU).
+template <int W, int KIND, bool U8>
 constexpr bool strip_form() {
-    return (W == 3 || W == 5) && (KIND == kBVDF || KIND == kDDF);
+    if (KIND != kBVDF && KIND != kDDF) return false;
+    return W == 3 || W == 5 || W == 7 || (W == 9 && KIND == kBVDF && U8);
 }
 
 // Occupancy target of a strip kernel: the waves per SIMD that its LDS allows

@@ -92,7 +92,7 @@ struct FwdParams {
 // Returns hipSuccess or the launch error.
 hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregates, int cfg,
                           const FwdParams& prm, hipStream_t stream);
-bool tile_config_valid(int window, int kind, int cfg);
+bool tile_config_valid(int window, int kind, int cfg, bool u8);
 int tile_config_default(int window, int kind);
 void tile_config_shape(int cfg, int* ext_w, int* ext_h);
 constexpr int kNumTileShapes = 4;

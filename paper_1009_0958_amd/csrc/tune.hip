@@ -155,7 +155,7 @@ int odf_tune_get(int window, int kind, int dist, int is_u8) {
 
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config) {
     if (!valid_class(window, kind, dist) ||
-        !odf::tile_config_valid(window, odf::kernel_kind(kind), config))
+        !odf::tile_config_valid(window, odf::kernel_kind(kind), config, is_u8 != 0))
         return ODF_EINVAL;
     odf::set_tuned_config(window, kind, dist, is_u8 != 0, config);
     return ODF_OK;
@@ -202,7 +202,7 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
     }
     for (int cfg = 0; cfg < odf::kNumTileConfigs; ++cfg) {
         ms_all[cfg] = -1.0f;
-        if (!odf::tile_config_valid(window, kk, cfg)) continue;
+        if (!odf::tile_config_valid(window, kk, cfg, is_u8 != 0)) continue;
         odf::FwdParams prm{};
         prm.img = img; prm.out = out; prm.idx = idx;
         prm.B = 1; prm.M = M; prm.N = N;

@@ -109,17 +109,19 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_set(3, 0, 0, 1, -1) == odf.EINVAL
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
-    # config 4: the strip form (32 x 16 bands), BVDF and DDF at 3x3 and 5x5 only
+    # config 4: the strip form (32 x 16 bands): BVDF and DDF at 3x3 to 7x7, BVDF 9x9 on uint8
     assert odf.tile_config(odf.STRIP) == (32, 16)
     assert L.odf_tile_config(odf.NUM_TILE_CONFIGS, ctypes.byref(ctypes.c_int()),
                              ctypes.byref(ctypes.c_int())) == odf.EINVAL
-    for w, kind in ((3, odf.BVDF), (3, odf.DDF), (5, odf.BVDF), (5, odf.DDF)):
-        saved = odf.tune_get(w, kind, odf.EXACT, True)
-        assert L.odf_tune_set(w, kind, odf.EXACT, 1, odf.STRIP) == odf.OK
-        assert odf.tune_get(w, kind, odf.EXACT, True) == odf.STRIP
-        odf.tune_set(w, kind, odf.EXACT, True, saved)
-    for w, kind in ((7, odf.BVDF), (9, odf.DDF), (3, odf.ACWDDF), (5, odf.CWVMF), (5, odf.CWDDF)):
-        assert L.odf_tune_set(w, kind, odf.EXACT, 1, odf.STRIP) == odf.EINVAL
+    for w, kind, u8 in ((3, odf.BVDF, 1), (3, odf.DDF, 0), (5, odf.BVDF, 1), (5, odf.DDF, 1),
+                        (7, odf.BVDF, 0), (7, odf.DDF, 1), (9, odf.BVDF, 1)):
+        saved = odf.tune_get(w, kind, odf.EXACT, u8)
+        assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.STRIP) == odf.OK
+        assert odf.tune_get(w, kind, odf.EXACT, u8) == odf.STRIP
+        odf.tune_set(w, kind, odf.EXACT, u8, saved)
+    for w, kind, u8 in ((9, odf.DDF, 1), (9, odf.BVDF, 0), (3, odf.ACWDDF, 1), (5, odf.CWVMF, 1),
+                        (5, odf.CWDDF, 1)):
+        assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.STRIP) == odf.EINVAL
     assert L.odf_tune_set(3, 0, 0, 1, odf.NUM_TILE_CONFIGS) == odf.EINVAL
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
     # batch tuning table: defaults, range checks, and the retired persistent form

@@ -50,7 +50,8 @@ SHAPES = [(1, 1, 1), (1, 1, 97), (1, 130, 1), (1, 5, 7), (1, 124, 28), (1, 125, 
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, BVDF, 0.0),
-                                           (5, DDF, 0.25), (5, DDF, 0.5)])
+                                           (5, DDF, 0.25), (5, DDF, 0.5), (7, BVDF, 0.0),
+                                           (7, DDF, 0.25), (9, BVDF, 0.0)])
 def test_strip_equals_tile_u8(shape, window, kind, p):
     img = _image(shape, True, 7)
     x = _gpu(img)
@@ -64,7 +65,8 @@ def test_strip_equals_tile_u8(shape, window, kind, p):
 
 
 @pytest.mark.parametrize("shape", [(1, 130, 61), (2, 257, 45), (1, 3, 3)])
-@pytest.mark.parametrize("window,kind,p", [(3, DDF, 0.5), (5, BVDF, 0.0), (5, DDF, 0.25)])
+@pytest.mark.parametrize("window,kind,p", [(3, DDF, 0.5), (5, BVDF, 0.0), (5, DDF, 0.25),
+                                           (7, BVDF, 0.0), (7, DDF, 0.5)])
 def test_strip_equals_tile_f32(shape, window, kind, p):
     img = _image(shape, False, 11)
     x = _gpu(img)
@@ -78,7 +80,8 @@ def test_strip_equals_tile_f32(shape, window, kind, p):
 
 
 @pytest.mark.parametrize("window,kind,p,dist", [(5, DDF, 0.25, EXACT), (5, BVDF, 0.0, MINIMAX),
-                                                (3, DDF, 0.5, RGB)])
+                                                (3, DDF, 0.5, RGB), (7, DDF, 0.25, EXACT),
+                                                (9, BVDF, 0.0, EXACT)])
 def test_strip_oracle(window, kind, p, dist):
     """The strip form against the oracle on an image of three strips down."""
     img = synth.image_corr(290, 75, 0.2, key=3)
@@ -91,7 +94,8 @@ def test_strip_oracle(window, kind, p, dist):
 
 
 def test_strip_not_offered():
-    """The strip form covers BVDF and DDF at 3x3 and 5x5 only."""
-    for window, kind in [(7, BVDF), (9, DDF), (3, odf.ACWDDF), (5, odf.CWDDF)]:
+    """The strip form covers BVDF and DDF at 3x3 to 7x7 and BVDF at 9x9 on uint8."""
+    for window, kind, u8 in [(9, DDF, True), (9, BVDF, False), (3, odf.ACWDDF, True),
+                             (5, odf.CWDDF, True)]:
         with pytest.raises(odf.ODFError):
-            odf.tune_set(window, kind, EXACT, True, STRIP)
+            odf.tune_set(window, kind, EXACT, u8, STRIP)

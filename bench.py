@@ -5,7 +5,8 @@ Step (the ``value``): DDF 5x5 (p = 1/4, exact angle of eq. 2) on one
 impulsive noise 0.15), one forward launch per step with the tile shape the
 library's autotuner picks for that frame (untimed).  ``value`` is pixels
 filtered per second (Mpixels/s), the mean over the timed steps between HIP
-events on the launch stream.
+events on the launch stream (after --prewarm-ms of untimed steps and the W
+warm-up steps).
 
 Also reported on the same JSON line:
   * ``roofline`` for the step's kernel (the only kernel of the step) against
@@ -24,7 +25,7 @@ Also reported on the same JSON line:
     the large-frame forms (1 M pixels per 5x5 form, 100 000 per 3x3 and 7x7
     form) and of the 256-image batch (1 M pixels).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prewarm-ms MS] [--no-forms] [--no-cpu]
                        [--forms six_variants,large_frames,acwddf,effectiveness,batched,
                         differentiable] [--step-forms loop,streams,direct]
                        [--copy-probe-mib MiB]
@@ -86,26 +87,27 @@ L2_SLOTS = {
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-slots/s
 
 # ------------------------------------------------------------------ HBM traffic
-# Bytes the step's kernel (DDF 5x5 exact, uint8, 32 x 16 extended tile, on the
-# 7680 x 4320 frame) and the six-variant DDF 3x3 batch kernel (32 x 16, on the
-# 1024 x 1024 image) move to and from HBM: rocprofv3 --pmc FETCH_SIZE and --pmc
-# WRITE_SIZE (KiB per dispatch, one pass each, from `bench.py --steps 3
-# --warmup 1 --no-cpu --forms six_variants,large_frames,batched,differentiable
-# --step-forms loop,direct --copy-probe-mib 256 --tune-cache <file>`), keyed by
-# form and extended tile.  Each counter is scaled by what it reads for the
-# 256 MiB float32 copy of the same run (262144 KiB read, 262144 KiB written):
-# FETCH_SIZE read 131085.0 KiB (x 1.99982), WRITE_SIZE 262144.0 KiB (x 1.0).
-# The figures hold for the kernel sources hashed in TRAFFIC_SRC_SHA256; for any
-# other sources bench.py reports traffic as null.
-TRAFFIC_FETCH_SCALE = 262144.0 / 131085.0
+# Bytes the step's kernel (DDF 5x5 exact, uint8, strip form of 32 x 16 bands,
+# on the 7680 x 4320 frame) and the six-variant DDF 3x3 batch kernel (32 x 16
+# tiles, on the 1024 x 1024 image) move to and from HBM: rocprofv3 --pmc
+# FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch, one pass each, from
+# `bench.py --steps 3 --warmup 1 --no-cpu --forms
+# six_variants,large_frames,batched,differentiable --step-forms loop,direct
+# --copy-probe-mib 256 --tune-cache <file>`), keyed by form and extended tile
+# (or band).  Each counter is scaled by what it reads for the 256 MiB float32
+# copy of the same run (262144 KiB read, 262144 KiB written): FETCH_SIZE read
+# 131085.7 KiB (x 1.99981), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold
+# for the kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources
+# bench.py reports traffic as null.
+TRAFFIC_FETCH_SCALE = 262144.0 / 131085.7
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("ddf5_exact_7680x4320", 32, 16): (172506.4, 194400.0),
-    ("batch6", 32, 16): (20999.3, 36890.7),
+    ("ddf5_exact_7680x4320_strip", 32, 16): (137633.1, 194400.0),
+    ("batch6", 32, 16): (21000.6, 36891.8),
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip", "fwd_tile.h",
                    "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "def832ea5ab460a5fe959f30b5a9ad9af9249186d1626ae7b11660e301f38827"
+TRAFFIC_SRC_SHA256 = "e2f074f8c420cba4ec510f9a5f12bbd770e67433a1a7ecf785564c76a46ca0e1"
 
 
 def forward_sources_sha256():
@@ -242,6 +244,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prewarm-ms", type=float, default=200.0,
+                    help="untimed back-to-back steps before the warm-up steps (ms)")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -304,6 +308,14 @@ def main():
     def step():
         odf.filter(x, w, odf.DDF, p, odf.EXACT, 4, out=out, idx=idx)
 
+    # untimed: --prewarm-ms of back-to-back steps (the GPU's clock rises over
+    # the first ~15 ms of sustained work: the first launches after the
+    # autotuner's host work ran up to 20 % slower), then the W warm-up steps
+    t_pre = time.perf_counter()
+    while (time.perf_counter() - t_pre) * 1e3 < args.prewarm_ms:
+        for _ in range(4):
+            step()
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -69,6 +69,12 @@ def test_more_than_65535_images():
     imgs = synth.image_corr(B * M, N, 0.15, key=70).reshape(B, M, N, 3)
     idx = _forward(imgs, 3, DDF, 0.25, EXACT)
     _forward(imgs, 5, BVDF, 0.0, MINIMAX)
+    keep = odf.tune_get(5, DDF, EXACT, True)
+    try:
+        odf.tune_set(5, DDF, EXACT, True, odf.STRIP)  # the strip form: one strip per image
+        _forward(imgs, 5, DDF, 0.25, EXACT)
+    finally:
+        odf.tune_set(5, DDF, EXACT, True, keep)
     _acwddf(imgs, 3)
     _gradients(imgs.astype(np.float32) / 255, idx, 3, DDF, 0.25, 0.1, seed=70)
 

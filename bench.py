@@ -105,9 +105,10 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("ddf5_exact_7680x4320_strip", 32, 16): (137633.1, 194400.0),
     ("batch6", 32, 16): (21000.6, 36891.8),
 }
-TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip", "fwd_tile.h",
-                   "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h", "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "e2f074f8c420cba4ec510f9a5f12bbd770e67433a1a7ecf785564c76a46ca0e1"
+TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
+                   "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
+                   "odf_internal.h")
+TRAFFIC_SRC_SHA256 = "00bad55a823af2e60c7496c56e16b947cb8795a38d6b44718ba2437964ad67cf"
 
 
 def forward_sources_sha256():

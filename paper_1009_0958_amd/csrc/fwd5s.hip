@@ -1,0 +1,10 @@
+// fwd5s.hip -- the 5x5 instantiations of the strip form of the forward filter.
+#include "fwd_strip.h"
+
+namespace odf {
+
+hipError_t launch_strip5(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s) {
+    return launch_strip_w<5>(kind, dist, u8, prm, s);
+}
+
+}  // namespace odf

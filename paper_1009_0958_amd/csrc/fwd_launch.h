@@ -1,6 +1,8 @@
 // fwd_launch.h -- the per-image forward kernel (one workgroup per output
 // tile) and its launch templates; each window size is instantiated in a
-// translation unit of its own (fwd.hip, fwd5.hip, fwd7.hip).
+// translation unit of its own (fwd.hip, fwd5.hip, fwd7.hip, fwd9.hip), and the
+// strip form of each in another (fwd3s.hip .. fwd9s.hip), so that a parallel
+// build compiles them side by side.
 #pragma once
 
 #include "fwd_strip.h"
@@ -53,7 +55,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
     } else if constexpr (W == 9) {  // 512 threads, 8 output rows: the one tile shape offered
         if (cfg == 2) return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
         if constexpr (strip_form<W, KIND, U8>())
-            if (cfg == kStripConfig) return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
+            if (cfg == kStripConfig) return launch_strip_extern<W>(KIND, DIST, U8, prm, stream);
         return hipErrorInvalidValue;
     } else if constexpr ((W == 5 && centre_weighted(KIND)) || W == 7) {
         switch (cfg) {
@@ -61,8 +63,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
         default:
             if constexpr (strip_form<W, KIND, U8>())
-                if (cfg == kStripConfig)
-                    return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
+                if (cfg == kStripConfig) return launch_strip_extern<W>(KIND, DIST, U8, prm, stream);
             return hipErrorInvalidValue;
         }
     } else {
@@ -73,7 +74,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
         default:
             if constexpr (strip_form<W, KIND, U8>())  // 32-wide strips of 8 bands of 16 rows
-                return launch_strip<W, KIND, DIST, U8, 32, 16, 8>(prm, stream);
+                if (cfg == kStripConfig) return launch_strip_extern<W>(KIND, DIST, U8, prm, stream);
             return hipErrorInvalidValue;
         }
     }

@@ -285,4 +285,43 @@ static hipError_t launch_strip(const FwdParams& prm, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// The per-image strip launch of window W (32-wide strips of 8 bands of 16
+// rows) for a class given at run time; each window size is instantiated in a
+// translation unit of its own (fwd3s.hip .. fwd9s.hip), beside the tile ones.
+template <int W, int KIND, bool U8>
+static hipError_t launch_strip_class(int dist, const FwdParams& prm, hipStream_t s) {
+    if constexpr (!strip_form<W, KIND, U8>()) {
+        (void)dist; (void)prm; (void)s;
+        return hipErrorInvalidValue;
+    } else {
+        switch (dist) {
+        case kExact: return launch_strip<W, KIND, kExact, U8, 32, 16, 8>(prm, s);
+        case kMinimax: return launch_strip<W, KIND, kMinimax, U8, 32, 16, 8>(prm, s);
+        default: return launch_strip<W, KIND, kRgb, U8, 32, 16, 8>(prm, s);
+        }
+    }
+}
+template <int W>
+static hipError_t launch_strip_w(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s) {
+    if (kind == kBVDF)
+        return u8 ? launch_strip_class<W, kBVDF, true>(dist, prm, s)
+                  : launch_strip_class<W, kBVDF, false>(dist, prm, s);
+    if (kind == kDDF)
+        return u8 ? launch_strip_class<W, kDDF, true>(dist, prm, s)
+                  : launch_strip_class<W, kDDF, false>(dist, prm, s);
+    return hipErrorInvalidValue;
+}
+hipError_t launch_strip3(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
+hipError_t launch_strip5(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
+hipError_t launch_strip7(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
+hipError_t launch_strip9(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
+template <int W>
+static hipError_t launch_strip_extern(int kind, int dist, bool u8, const FwdParams& prm,
+                                      hipStream_t s) {
+    if constexpr (W == 3) return launch_strip3(kind, dist, u8, prm, s);
+    else if constexpr (W == 5) return launch_strip5(kind, dist, u8, prm, s);
+    else if constexpr (W == 7) return launch_strip7(kind, dist, u8, prm, s);
+    else return launch_strip9(kind, dist, u8, prm, s);
+}
+
 }  // namespace odf

@@ -335,11 +335,12 @@ def main():
     step_ok = bool(torch.equal(ref_out, out) and torch.equal(ref_idx, idx))
 
     ext = odf.tile_config(best_cfg)
-    strip = best_cfg == odf.STRIP
+    strip = best_cfg in (odf.STRIP, odf.SHORT_STRIP)
     slots_px = slots_per_pixel(w, "ddf", p, "exact")
     npx = M * N
-    kname = ("fwd_strip_kernel<5, DDF, exact, uint8, %dx%d bands>" if strip
-             else "fwd_kernel<5, DDF, exact, uint8, %dx%d>") % tuple(ext)
+    kname = ("fwd_strip_kernel<5, DDF, exact, uint8, %dx%d bands, " % tuple(ext)
+             + ("8 bands per strip>" if best_cfg == odf.STRIP else "3 bands per strip>")
+             if strip else "fwd_kernel<5, DDF, exact, uint8, %dx%d>" % tuple(ext))
     roofline = {
         "bound": "alu", "kernel": kname,
         "ms_per_launch": round(ms_step, 5),
@@ -349,7 +350,8 @@ def main():
         "slots_per_pixel": slots_px, "pixels_per_launch": npx, "traffic": None,
         "hbm_bytes_per_pixel": 7, "hbm_frac": round(7 * npx / (ms_step * 1e-3) / 8e12, 5),
     }
-    tb = traffic_bytes("ddf5_exact_7680x4320" + ("_strip" if strip else ""), ext)
+    tb = traffic_bytes("ddf5_exact_7680x4320" + {odf.STRIP: "_strip", odf.SHORT_STRIP: "_strip3"}
+                       .get(best_cfg, ""), ext)
     if tb is not None:
         roofline["traffic"] = tb["fetch"] + tb["write"]
         roofline["traffic_fetch_write"] = [tb["fetch"], tb["write"]]
@@ -502,11 +504,11 @@ def six_variant_forms(torch, odf, dev, DIST, x, img_np, args, forms_wanted, samp
         # one kernel over the tiles of all six variants: the form's time is its time
         info6 = graphs["direct"][0].info()
         ext6 = info6["ext_tiles"]["w3_ddf"]
-        strip6 = info6["configs"][1] == odf.STRIP
+        strip6 = info6["configs"][1] in (odf.STRIP, odf.SHORT_STRIP)
         dname = (("batch_strip_kernel ddf3 %dx%d bands" if strip6 else "batch_direct_kernel ddf3 %dx%d")
                  + ", six variants in one launch") % tuple(ext6)
         dms, dpx = ms_step, npx
-        tb = traffic_bytes("batch6_strip" if strip6 else "batch6", ext6)
+        tb = None if strip6 else traffic_bytes("batch6", ext6)
     else:
         dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
         dp, dd = float(dom.split("_")[1][1:]), dom.split("_")[2]

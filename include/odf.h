@@ -326,7 +326,7 @@ int odf_batch_launch(const odf_plan* plan, void* stream);
 int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles, int* grids);
 
 /* The config each group of the plan runs on (a tile shape, odf_tile_config
- * number, or ODF_STRIP_CONFIG), group = (window == 5) * 2 + kind, configs[4].
+ * number, or a strip config), group = (window == 5) * 2 + kind, configs[4].
  * ODF_EINVAL for NULL. */
 int odf_plan_configs(const odf_plan* plan, int* configs);
 
@@ -379,13 +379,15 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
 /* ---------------------------------------------------------------- tuning
  * The forward kernels run one thread per pixel of an extended tile
  * (output tile plus halo).  Configs 0..3 are tile shapes (one workgroup per
- * output tile); config ODF_STRIP_CONFIG (4) is the strip form, offered for
- * ODF_BVDF and ODF_DDF at 3x3, 5x5 and 7x7 and for ODF_BVDF at 9x9 on uint8
- * (the batch offers it for all its groups): one workgroup per strip of 32 - 2h
- * output columns and 128 - 2h output rows, walking down it in bands of 32 x 16
- * member pixels and keeping the pair terms and argmin keys that consecutive
- * bands share in LDS, so that the rows of the halo between bands are not
- * evaluated twice (results bitwise equal to the tile shapes).  odf_tile_config
+ * output tile); configs ODF_STRIP_CONFIG (4) and ODF_SHORT_STRIP_CONFIG (5) are
+ * the strip form, offered for ODF_BVDF and ODF_DDF at 3x3, 5x5 and 7x7 and for
+ * ODF_BVDF at 9x9 on uint8 (the batch offers them for all its groups): one
+ * workgroup per strip of 32 - 2h output columns and 8 * 16 - 2h (config 4) or
+ * 3 * 16 - 2h (config 5, for images too small to fill the GPU with long
+ * strips) output rows, walking down it in bands of 32 x 16 member pixels and
+ * keeping the pair terms and argmin keys that consecutive bands share in LDS,
+ * so that the rows of the halo between bands are not evaluated twice (results
+ * bitwise equal to the tile shapes).  odf_tile_config
  * gives the extended width and height of a tile shape, or of one band of the
  * strip form.  The process-wide table picks a config per (window, kind,
  * dist, input type), kind any odf_kind (windows 3 and 5 for ODF_ACWDDF,
@@ -394,8 +396,9 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * centre-weighted kinds and 7x7 offer only the 512-thread shapes 2 and 3, 9x9
  * only shape 2).  The table is initialised once per process and each entry is
  * read and written atomically. */
-#define ODF_NUM_TILE_CONFIGS 5
+#define ODF_NUM_TILE_CONFIGS 6
 #define ODF_STRIP_CONFIG 4
+#define ODF_SHORT_STRIP_CONFIG 5
 int odf_tile_config(int config, int* ext_w, int* ext_h);
 int odf_tune_get(int window, int kind, int dist, int is_u8);                  /* config or < 0 */
 int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /* ODF_EINVAL if invalid */
@@ -411,8 +414,8 @@ int odf_tune_set(int window, int kind, int dist, int is_u8, int config);      /*
 int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int reps,
                  const char* cache_path, float* times_ms, void* stream);
 
-/* The batch tuning table: the config (0..3 a tile shape, ODF_STRIP_CONFIG the
- * strip form) of the batch group of
+/* The batch tuning table: the config (0..3 a tile shape, ODF_STRIP_CONFIG or
+ * ODF_SHORT_STRIP_CONFIG the strip form) of the batch group of
  * `window` (3, 5) and `kind` (ODF_BVDF, ODF_DDF); 32 x 32 for 3x3 DDF and
  * 32 x 16 otherwise until tuned.  get returns the config or ODF_EINVAL; set
  * returns ODF_OK or ODF_EINVAL.  Plans read the table when they are made. */

@@ -12,9 +12,9 @@
 // budget everywhere), so they keep kernels of their own.  Each group runs one
 // workgroup per tile of its list, dispatched in list order, on the config of
 // the batch tuning table: one of the four extended tile shapes, or the strip
-// form, whose work items are 32-wide strips of 8 bands that keep the rows
-// shared by consecutive bands in LDS (fwd_strip.h); odf_autotune_batch times
-// the five on a mixed list, odf_autotune_batch_jobs on the caller's jobs.  odf_batch_launch enqueues the group kernels,
+// form, whose work items are 32-wide strips of 8 (or 3) bands that keep the
+// rows shared by consecutive bands in LDS (fwd_strip.h); odf_autotune_batch
+// times the six on a mixed list, odf_autotune_batch_jobs on the caller's jobs.  odf_batch_launch enqueues the group kernels,
 // forked onto per-plan auxiliary streams (default priority) and joined back
 // with events so that groups run concurrently and their tails overlap; it
 // allocates nothing and never synchronises, so it can be captured in a
@@ -51,6 +51,7 @@ struct BatchClass {
     const BatchJob* jobs;
     const BatchTile* tiles;
     int ntiles;
+    int bands;  // strip form: bands per strip
 };
 
 // Extended-tile shape CFG of the batch kernels: the per-image table's shapes.
@@ -135,12 +136,11 @@ __global__ void __launch_bounds__(BatchShape<CFG>::THREADS)
                                        bc, tile);
 }
 
-// The strip form of a group (config kStripConfig): one workgroup per strip of
-// the list (ty0, tx0 its first output row and column), 32-wide strips of 8
-// bands of 16 rows as in the per-image strip kernels.
-constexpr int kStripBands = 8;
+// The strip form of a group (configs kStripConfig, kShortStripConfig): one
+// workgroup per strip of the list (ty0, tx0 its first output row and column),
+// 32-wide strips of bands of 16 rows as in the per-image strip kernels.
 template <int W, int KIND, int DIST>
-using StripSh = StripShared<W, KIND, DIST, true, 32, 16, kStripBands>;
+using StripSh = StripShared<W, KIND, DIST, true, 32, 16>;
 
 template <int W, int KIND>
 struct BatchStripSmem {
@@ -167,7 +167,7 @@ __device__ __forceinline__ void batch_strip(StripSh<W, KIND, DIST>& sh, const Ba
         prm.coef.asin_c[k] = uni(job.coef.asin_c[k]);
         prm.coef.acos_c[k] = uni(job.coef.acos_c[k]);
     }
-    fwd_strip<W, KIND, DIST, true, 32, 16, kStripBands>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0));
+    fwd_strip<W, KIND, DIST, true, 32, 16>(sh, prm, 0, uni(tile.ty0), uni(tile.tx0), uni(bc.bands));
 }
 
 // Occupancy target: the waves per SIMD the LDS of the largest pair term allows.
@@ -195,9 +195,9 @@ static int group_window(int grp) { return grp / 2 ? 5 : 3; }
 
 static void group_geometry(int grp, int cfg, int& tw, int& th, int& threads) {
     const int h = group_window(grp) / 2;
-    if (cfg == kStripConfig) {
+    if (is_strip_config(cfg)) {
         tw = 32 - 2 * h;
-        th = kStripBands * 16 - 2 * h;
+        th = strip_bands(cfg) * 16 - 2 * h;
         threads = 512;
         return;
     }
@@ -363,7 +363,7 @@ int make_plan(const odf_job* jobs, int njobs, const int* cfg, odf_plan** plan) {
     return ODF_OK;
 }
 
-// Time the five configs (four tile shapes, the strip form) of group grp on the
+// Time the six configs (four tile shapes, two strip heights) of group grp on the
 // jobs of that group among jobs[] (reps launches each after two untimed ones);
 // ms[c] = -1 when the group has no job.  Returns ODF_OK or an error code (message set).
 int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* ms,
@@ -420,9 +420,9 @@ int write_batch_line(const char* cache_path, int grp, int best, const float* ms)
     if (!f) return odf::set_error(ODF_EINVAL, "cannot open %s", cache_path);
     fprintf(f,
             "{\"arch\": \"%s\", \"batch_window\": %d, \"kind\": %d, \"config\": %d, "
-            "\"ms\": [%.5f, %.5f, %.5f, %.5f, %.5f]}\n",
+            "\"ms\": [%.5f, %.5f, %.5f, %.5f, %.5f, %.5f]}\n",
             prop.gcnArchName, odf::group_window(grp), grp % 2, best, ms[0], ms[1], ms[2], ms[3],
-            ms[4]);
+            ms[4], ms[5]);
     fclose(f);
     return ODF_OK;
 }
@@ -454,7 +454,8 @@ int odf_batch_launch(const odf_plan* plan, void* stream) {
     if (hipEventRecord(plan->fork, s) != hipSuccess) return bfail(ODF_EHIP, "fork event failed");
     for (int g = 0; g < odf::kNumGroups; ++g) {
         if (plan->ntiles[g] == 0) continue;
-        odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[g], plan->ntiles[g]};
+        odf::BatchClass bc{plan->d_jobs, plan->d_tiles + plan->offset[g], plan->ntiles[g],
+                           odf::strip_bands(plan->cfg[g])};
         int tw, th, thr;
         odf::group_geometry(g, plan->cfg[g], tw, th, thr);
         hipStream_t cs = plan->aux[g] ? plan->aux[g] : s;

@@ -10,7 +10,7 @@ namespace odf {
 // parks its weighted angle sums in LDS, which at 32 x 32 would not leave room
 // for a float32 tile's pixel arrays).
 bool tile_config_valid(int window, int kind, int cfg, bool u8) {
-    if (cfg == kStripConfig)  // as strip_form (fwd_strip.h)
+    if (is_strip_config(cfg))  // as strip_form (fwd_strip.h)
         return (kind == kBVDF || kind == kDDF) &&
                (window == 3 || window == 5 || window == 7 || (window == 9 && kind == kBVDF && u8));
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
@@ -26,7 +26,7 @@ bool tile_config_valid(int window, int kind, int cfg, bool u8) {
 int tile_config_default(int, int) { return 2; }
 
 void tile_config_shape(int cfg, int* ext_w, int* ext_h) {
-    if (cfg == kStripConfig) {  // one band of the strip
+    if (is_strip_config(cfg)) {  // one band of the strip
         *ext_w = 32;
         *ext_h = 16;
         return;

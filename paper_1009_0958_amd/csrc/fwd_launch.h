@@ -55,7 +55,8 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
     } else if constexpr (W == 9) {  // 512 threads, 8 output rows: the one tile shape offered
         if (cfg == 2) return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
         if constexpr (strip_form<W, KIND, U8>())
-            if (cfg == kStripConfig) return launch_strip_extern<W>(KIND, DIST, U8, prm, stream);
+            if (is_strip_config(cfg))
+                return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
         return hipErrorInvalidValue;
     } else if constexpr ((W == 5 && centre_weighted(KIND)) || W == 7) {
         switch (cfg) {
@@ -63,7 +64,8 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
         default:
             if constexpr (strip_form<W, KIND, U8>())
-                if (cfg == kStripConfig) return launch_strip_extern<W>(KIND, DIST, U8, prm, stream);
+                if (is_strip_config(cfg))
+                return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
             return hipErrorInvalidValue;
         }
     } else {
@@ -74,7 +76,8 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
         default:
             if constexpr (strip_form<W, KIND, U8>())  // 32-wide strips of 8 bands of 16 rows
-                if (cfg == kStripConfig) return launch_strip_extern<W>(KIND, DIST, U8, prm, stream);
+                if (is_strip_config(cfg))
+                return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
             return hipErrorInvalidValue;
         }
     }

@@ -22,7 +22,7 @@
 
 namespace odf {
 
-template <int W, int EXT_W, int BH, int NB>
+template <int W, int EXT_W, int BH>
 struct StripGeom {
     static constexpr int H = W / 2;
     static constexpr int NW = W * W;
@@ -31,7 +31,8 @@ struct StripGeom {
     static constexpr int NT = EXT_W * BH;       // threads: one per member of a band
     static constexpr int RING = BH + 2 * H;     // pixel rows a band reads
     static constexpr int PL = RING * EXT_W;     // plane stride: 2h carried rows + the band
-    static constexpr int S = NB * BH - 2 * H;   // output rows per strip
+    // output rows of a strip of nb bands
+    static constexpr int rows(int nb) { return nb * BH - 2 * H; }
     static constexpr int CROWS = H * (4 * H + 2) / 2;  // carried rows, summed over g = 1 .. 2h
     // key slots: window centres on band rows -h .. BH - 1 + h (ring row = centre
     // row + h), stride EXT_W, + 2h slots that windows past the last column reach
@@ -41,9 +42,9 @@ struct StripGeom {
 
 // LDS of one strip workgroup.  NPL: planes swept together (2 for the fused
 // angle + L2 sweep of the 3x3 DDF); NTERM: carried plane sets (one per term).
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 struct StripShared {
-    using Gm = StripGeom<W, EXT_W, BH, NB>;
+    using Gm = StripGeom<W, EXT_W, BH>;
     static constexpr bool INV = U8 && DIST != kExact;
     static constexpr int NPL = fused_sweep<W, KIND>() ? 2 : 1;
     static constexpr int NTERM = KIND == kBVDF ? 1 : 2;
@@ -108,33 +109,34 @@ constexpr int lds_waves_per_eu(size_t lds_bytes, int threads) {
     const int waves = (int)((160 * 1024) / lds_bytes) * (threads / 256);
     return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
 }
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 constexpr int strip_waves_per_eu() {
-    return lds_waves_per_eu(sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>), EXT_W * BH);
+    return lds_waves_per_eu(sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH>), EXT_W * BH);
 }
 
 // Filter the strip of image b whose first output row is s0 and first output
-// column tx0 (S output rows x TW output columns, clipped to the image).  Bands
+// column tx0 (nb bands: nb BH - 2h output rows x TW output columns, clipped to
+// the image).  Bands
 // start h rows above the strip and the first band's 2h top window rows lie
 // above it (discarded); a band reads its RING pixel rows (replicated border),
 // sweeps, and then writes the BH window rows its members completed.  Every
 // thread of the workgroup must call it (it synchronises).
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
-__device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>& sh,
-                                          const FwdParams& prm, int b, int s0, int tx0) {
-    using Gm = StripGeom<W, EXT_W, BH, NB>;
-    using Sh = StripShared<W, KIND, DIST, U8, EXT_W, BH, NB>;
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
+__device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, BH>& sh,
+                                          const FwdParams& prm, int b, int s0, int tx0, int nb) {
+    using Gm = StripGeom<W, EXT_W, BH>;
+    using Sh = StripShared<W, KIND, DIST, U8, EXT_W, BH>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, NT = Gm::NT, PL = Gm::PL;
     constexpr bool INV = Sh::INV;
     constexpr bool CANON = U8 && KIND == kBVDF;  // as in the tile form
     static_assert(Gm::KCARRY <= NT, "one carried key per thread");
     static_assert(offsetof(Sh, plane) >= 2 * H * sizeof(float), "reads before plane");
     const int M = prm.M, N = prm.N;
-    const int s_end = min(s0 + Gm::S, M);
+    const int s_end = min(s0 + Gm::rows(nb), M);
     const TilePix px{sh.dir, sh.raw, sh.inv};
     float* const pl0 = sh.plane + 2 * H * EXT_W;  // ring row 2h: the band's first row
 
-    for (int j = 0; j < NB; ++j) {
+    for (int j = 0; j < nb; ++j) {
         // the thread index is laundered once per band, so that the compiler
         // derives the band's many LDS addresses inside the loop instead of
         // hoisting them all out of it (each would hold a register across it)
@@ -262,66 +264,71 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
     }
 }
 
-// One workgroup per strip of the launch's images.
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
+// One workgroup per strip of the launch's images (prm.strip_bands bands each).
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 __global__ void __launch_bounds__(EXT_W* BH)
-    __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<W, KIND, DIST, U8, EXT_W, BH, NB>())))
+    __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<W, KIND, DIST, U8, EXT_W, BH>())))
     fwd_strip_kernel(FwdParams prm) {
-    __shared__ StripShared<W, KIND, DIST, U8, EXT_W, BH, NB> sh;
-    using Gm = StripGeom<W, EXT_W, BH, NB>;
+    __shared__ StripShared<W, KIND, DIST, U8, EXT_W, BH> sh;
+    using Gm = StripGeom<W, EXT_W, BH>;
     const int t = flat_block(prm.grid.n);
     if (t < 0) return;
     const TileCoord tc = tile_coord(t, prm.grid);
-    fwd_strip<W, KIND, DIST, U8, EXT_W, BH, NB>(sh, prm, tc.b, tc.ty * Gm::S, tc.tx * Gm::TW);
+    const int nb = prm.strip_bands;
+    fwd_strip<W, KIND, DIST, U8, EXT_W, BH>(sh, prm, tc.b, tc.ty * Gm::rows(nb), tc.tx * Gm::TW,
+                                            nb);
 }
 
-template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH, int NB>
-static hipError_t launch_strip(const FwdParams& prm, hipStream_t stream) {
-    using Gm = StripGeom<W, EXT_W, BH, NB>;
+template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
+static hipError_t launch_strip(const FwdParams& prm, int nb, hipStream_t stream) {
+    using Gm = StripGeom<W, EXT_W, BH>;
     FwdParams q = prm;
-    q.grid = tile_grid(prm.B, (prm.N + Gm::TW - 1) / Gm::TW, (prm.M + Gm::S - 1) / Gm::S);
-    hipLaunchKernelGGL((fwd_strip_kernel<W, KIND, DIST, U8, EXT_W, BH, NB>), flat_grid(q.grid.n),
+    q.strip_bands = nb;
+    const int S = Gm::rows(nb);
+    q.grid = tile_grid(prm.B, (prm.N + Gm::TW - 1) / Gm::TW, (prm.M + S - 1) / S);
+    hipLaunchKernelGGL((fwd_strip_kernel<W, KIND, DIST, U8, EXT_W, BH>), flat_grid(q.grid.n),
                        dim3(Gm::NT), 0, stream, q);
     return hipGetLastError();
 }
 
-// The per-image strip launch of window W (32-wide strips of 8 bands of 16
+// The per-image strip launch of window W (32-wide strips of nb bands of 16
 // rows) for a class given at run time; each window size is instantiated in a
 // translation unit of its own (fwd3s.hip .. fwd9s.hip), beside the tile ones.
 template <int W, int KIND, bool U8>
-static hipError_t launch_strip_class(int dist, const FwdParams& prm, hipStream_t s) {
+static hipError_t launch_strip_class(int dist, const FwdParams& prm, int nb, hipStream_t s) {
     if constexpr (!strip_form<W, KIND, U8>()) {
-        (void)dist; (void)prm; (void)s;
+        (void)dist; (void)prm; (void)nb; (void)s;
         return hipErrorInvalidValue;
     } else {
         switch (dist) {
-        case kExact: return launch_strip<W, KIND, kExact, U8, 32, 16, 8>(prm, s);
-        case kMinimax: return launch_strip<W, KIND, kMinimax, U8, 32, 16, 8>(prm, s);
-        default: return launch_strip<W, KIND, kRgb, U8, 32, 16, 8>(prm, s);
+        case kExact: return launch_strip<W, KIND, kExact, U8, 32, 16>(prm, nb, s);
+        case kMinimax: return launch_strip<W, KIND, kMinimax, U8, 32, 16>(prm, nb, s);
+        default: return launch_strip<W, KIND, kRgb, U8, 32, 16>(prm, nb, s);
         }
     }
 }
 template <int W>
-static hipError_t launch_strip_w(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s) {
+static hipError_t launch_strip_w(int kind, int dist, bool u8, const FwdParams& prm, int nb,
+                                 hipStream_t s) {
     if (kind == kBVDF)
-        return u8 ? launch_strip_class<W, kBVDF, true>(dist, prm, s)
-                  : launch_strip_class<W, kBVDF, false>(dist, prm, s);
+        return u8 ? launch_strip_class<W, kBVDF, true>(dist, prm, nb, s)
+                  : launch_strip_class<W, kBVDF, false>(dist, prm, nb, s);
     if (kind == kDDF)
-        return u8 ? launch_strip_class<W, kDDF, true>(dist, prm, s)
-                  : launch_strip_class<W, kDDF, false>(dist, prm, s);
+        return u8 ? launch_strip_class<W, kDDF, true>(dist, prm, nb, s)
+                  : launch_strip_class<W, kDDF, false>(dist, prm, nb, s);
     return hipErrorInvalidValue;
 }
-hipError_t launch_strip3(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
-hipError_t launch_strip5(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
-hipError_t launch_strip7(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
-hipError_t launch_strip9(int kind, int dist, bool u8, const FwdParams& prm, hipStream_t s);
+hipError_t launch_strip3(int kind, int dist, bool u8, const FwdParams& prm, int nb, hipStream_t s);
+hipError_t launch_strip5(int kind, int dist, bool u8, const FwdParams& prm, int nb, hipStream_t s);
+hipError_t launch_strip7(int kind, int dist, bool u8, const FwdParams& prm, int nb, hipStream_t s);
+hipError_t launch_strip9(int kind, int dist, bool u8, const FwdParams& prm, int nb, hipStream_t s);
 template <int W>
-static hipError_t launch_strip_extern(int kind, int dist, bool u8, const FwdParams& prm,
+static hipError_t launch_strip_extern(int kind, int dist, bool u8, const FwdParams& prm, int nb,
                                       hipStream_t s) {
-    if constexpr (W == 3) return launch_strip3(kind, dist, u8, prm, s);
-    else if constexpr (W == 5) return launch_strip5(kind, dist, u8, prm, s);
-    else if constexpr (W == 7) return launch_strip7(kind, dist, u8, prm, s);
-    else return launch_strip9(kind, dist, u8, prm, s);
+    if constexpr (W == 3) return launch_strip3(kind, dist, u8, prm, nb, s);
+    else if constexpr (W == 5) return launch_strip5(kind, dist, u8, prm, nb, s);
+    else if constexpr (W == 7) return launch_strip7(kind, dist, u8, prm, nb, s);
+    else return launch_strip9(kind, dist, u8, prm, nb, s);
 }
 
 }  // namespace odf

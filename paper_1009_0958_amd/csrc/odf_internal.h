@@ -85,7 +85,8 @@ struct FwdParams {
     // levels k = lambda, lambda + 1, lambda + 2, and the switching threshold T
     float acw_wm1[3];
     float acw_T;
-    TileGrid grid;  // the launch's tiles (set by the launch)
+    TileGrid grid;    // the launch's tiles (set by the launch)
+    int strip_bands;  // strip form: bands per strip (set by the launch)
 };
 
 // Launch the forward filter on `stream` with extended-tile shape `cfg`.
@@ -97,9 +98,13 @@ int tile_config_default(int window, int kind);
 void tile_config_shape(int cfg, int* ext_w, int* ext_h);
 constexpr int kNumTileShapes = 4;
 // Forward configs: the four tile shapes, then the strip form (fwd_strip.h:
-// 32-wide strips of 8 bands of 16 rows; BVDF and DDF at 3x3 and 5x5).
+// 32-wide strips of bands of 16 rows): 8 bands per strip, or 3 for images too
+// small to fill the GPU with the long strips.
 constexpr int kStripConfig = 4;
-constexpr int kNumTileConfigs = 5;
+constexpr int kShortStripConfig = 5;
+constexpr int kNumTileConfigs = 6;
+constexpr bool is_strip_config(int cfg) { return cfg == kStripConfig || cfg == kShortStripConfig; }
+constexpr int strip_bands(int cfg) { return cfg == kShortStripConfig ? 3 : 8; }
 // Extended-tile shapes (EXT_W x EXT_H, one thread per extended pixel) the
 // autotuners choose from, for the per-image and the batch kernels alike.
 constexpr int kTileW[kNumTileShapes] = {32, 64, 32, 64};

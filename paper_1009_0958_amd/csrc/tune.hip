@@ -250,9 +250,10 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
         }
         fprintf(f,
                 "{\"arch\": \"%s\", \"window\": %d, \"kind\": %d, \"dist\": %d, \"u8\": %d, "
-                "\"config\": %d, \"M\": %d, \"N\": %d, \"ms\": [%.5f, %.5f, %.5f, %.5f, %.5f]}\n",
+                "\"config\": %d, \"M\": %d, \"N\": %d, \"ms\": [%.5f, %.5f, %.5f, %.5f, %.5f, "
+                "%.5f]}\n",
                 prop.gcnArchName, window, kind, dist, is_u8 != 0, best, M, N, ms_all[0],
-                ms_all[1], ms_all[2], ms_all[3], ms_all[4]);
+                ms_all[1], ms_all[2], ms_all[3], ms_all[4], ms_all[5]);
         fclose(f);
     }
 done:

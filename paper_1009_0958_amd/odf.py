@@ -22,8 +22,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "odf.h")
 BVDF, DDF, ACWDDF, CWVMF, CWDDF = 0, 1, 2, 3, 4
 EXACT, MINIMAX, RGB = 0, 1, 2
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
-NUM_TILE_CONFIGS = 5  # ODF_NUM_TILE_CONFIGS: four tile shapes and the strip form
-STRIP = 4             # ODF_STRIP_CONFIG
+NUM_TILE_CONFIGS = 6  # ODF_NUM_TILE_CONFIGS: four tile shapes and two strip heights
+STRIP = 4             # ODF_STRIP_CONFIG: strips of 8 bands
+SHORT_STRIP = 5       # ODF_SHORT_STRIP_CONFIG: strips of 3 bands
 
 _KIND = {"bvdf": BVDF, "ddf": DDF, "acwddf": ACWDDF, "cwvmf": CWVMF, "cwddf": CWDDF}
 _DIST = {"exact": EXACT, "minimax": MINIMAX, "rgb": RGB}
@@ -545,8 +546,9 @@ def tune_set(window, kind, dist, is_u8, config):
 
 
 def autotune(window, kind, dist, is_u8=True, M=1024, N=1024, reps=10, cache_path=None):
-    """Time every forward config (the four tile shapes and the strip form), keep
-    the fastest; returns (best, [ms per config], -1 where not offered)."""
+    """Time every forward config (the four tile shapes and the two strip
+    heights), keep the fastest; returns (best, [ms per config], -1 where not
+    offered)."""
     times = (ctypes.c_float * NUM_TILE_CONFIGS)()
     path = None if cache_path is None else cache_path.encode()
     _check(_batch_lib().odf_autotune(window, _kind(kind), _dist(dist), int(is_u8), M, N, reps,
@@ -567,7 +569,7 @@ def batch_tune_set(window, kind, config):
 
 
 def autotune_batch(window, kind, reps=3, cache_path=None):
-    """Time the batch group's configs (four tile shapes, the strip form) on a
+    """Time the batch group's configs (four tile shapes, two strip heights) on a
     mixed work list, keep the fastest; returns (best, [ms per config])."""
     times = (ctypes.c_float * NUM_TILE_CONFIGS)()
     path = None if cache_path is None else cache_path.encode()

@@ -110,7 +110,7 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
     # config 4: the strip form (32 x 16 bands): BVDF and DDF at 3x3 to 7x7, BVDF 9x9 on uint8
-    assert odf.tile_config(odf.STRIP) == (32, 16)
+    assert odf.tile_config(odf.STRIP) == (32, 16) and odf.tile_config(odf.SHORT_STRIP) == (32, 16)
     assert L.odf_tile_config(odf.NUM_TILE_CONFIGS, ctypes.byref(ctypes.c_int()),
                              ctypes.byref(ctypes.c_int())) == odf.EINVAL
     for w, kind, u8 in ((3, odf.BVDF, 1), (3, odf.DDF, 0), (5, odf.BVDF, 1), (5, odf.DDF, 1),
@@ -118,10 +118,12 @@ def test_batch_and_tune_argument_errors():
         saved = odf.tune_get(w, kind, odf.EXACT, u8)
         assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.STRIP) == odf.OK
         assert odf.tune_get(w, kind, odf.EXACT, u8) == odf.STRIP
+        assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.SHORT_STRIP) == odf.OK
         odf.tune_set(w, kind, odf.EXACT, u8, saved)
     for w, kind, u8 in ((9, odf.DDF, 1), (9, odf.BVDF, 0), (3, odf.ACWDDF, 1), (5, odf.CWVMF, 1),
                         (5, odf.CWDDF, 1)):
         assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.STRIP) == odf.EINVAL
+        assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.SHORT_STRIP) == odf.EINVAL
     assert L.odf_tune_set(3, 0, 0, 1, odf.NUM_TILE_CONFIGS) == odf.EINVAL
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
     # batch tuning table: defaults, range checks, and the retired persistent form
@@ -355,3 +357,4 @@ def test_header_config_constants_match_binding():
     defs = dict(re.findall(r"#define (ODF_\w+) (\d+)", text))
     assert int(defs["ODF_NUM_TILE_CONFIGS"]) == odf.NUM_TILE_CONFIGS
     assert int(defs["ODF_STRIP_CONFIG"]) == odf.STRIP
+    assert int(defs["ODF_SHORT_STRIP_CONFIG"]) == odf.SHORT_STRIP

@@ -40,10 +40,10 @@ def _per_image(job):
     return odf.filter(job["img"], job["window"], job["kind"], job["p"], job["dist"], job["q"])
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 def test_batch_equals_per_image_and_oracle(cfg):
     """Every group on config cfg (the batch tuning table set for all four): a
-    tile shape, or the strip form (4)."""
+    tile shape, or the strip form (4: 8 bands per strip, 5: 3 bands)."""
     jobs, imgs = _mixed_jobs(40, 1)
     keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
     try:

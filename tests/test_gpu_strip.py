@@ -1,5 +1,5 @@
-"""The strip form of the forward filter (tile config 4): bitwise equal to the
-tile form, and against the FP64 oracle directly."""
+"""The strip form of the forward filter (configs 4 and 5: strips of 8 and of 3
+bands): bitwise equal to the tile form, and against the FP64 oracle directly."""
 import numpy as np
 import pytest
 
@@ -16,6 +16,7 @@ DEV = "cuda:0"
 BVDF, DDF = odf.BVDF, odf.DDF
 EXACT, MINIMAX, RGB = odf.EXACT, odf.MINIMAX, odf.RGB
 STRIP = 4
+STRIPS = [odf.STRIP, odf.SHORT_STRIP]
 
 
 def _gpu(x):
@@ -48,33 +49,35 @@ SHAPES = [(1, 1, 1), (1, 1, 97), (1, 130, 1), (1, 5, 7), (1, 124, 28), (1, 125, 
           (1, 300, 190), (2, 257, 61), (1, 40, 700)]
 
 
+@pytest.mark.parametrize("cfg", STRIPS)
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, BVDF, 0.0),
                                            (5, DDF, 0.25), (5, DDF, 0.5), (7, BVDF, 0.0),
                                            (7, DDF, 0.25), (9, BVDF, 0.0)])
-def test_strip_equals_tile_u8(shape, window, kind, p):
+def test_strip_equals_tile_u8(shape, window, kind, p, cfg):
     img = _image(shape, True, 7)
     x = _gpu(img)
     for dist in (EXACT, MINIMAX, RGB):
-        print("case: strip u8 shape=%s w=%d kind=%d p=%s dist=%d" % (shape, window, kind, p, dist),
-              flush=True)
+        print("case: strip %d u8 shape=%s w=%d kind=%d p=%s dist=%d"
+              % (cfg, shape, window, kind, p, dist), flush=True)
         o_t, i_t = _run(x, window, kind, p, dist, 2)
-        o_s, i_s = _run(x, window, kind, p, dist, STRIP)
+        o_s, i_s = _run(x, window, kind, p, dist, cfg)
         assert np.array_equal(i_s, i_t)
         assert np.array_equal(o_s, o_t)
 
 
+@pytest.mark.parametrize("cfg", STRIPS)
 @pytest.mark.parametrize("shape", [(1, 130, 61), (2, 257, 45), (1, 3, 3)])
 @pytest.mark.parametrize("window,kind,p", [(3, DDF, 0.5), (5, BVDF, 0.0), (5, DDF, 0.25),
                                            (7, BVDF, 0.0), (7, DDF, 0.5)])
-def test_strip_equals_tile_f32(shape, window, kind, p):
+def test_strip_equals_tile_f32(shape, window, kind, p, cfg):
     img = _image(shape, False, 11)
     x = _gpu(img)
     for dist in (EXACT, MINIMAX, RGB):
-        print("case: strip f32 shape=%s w=%d kind=%d p=%s dist=%d" % (shape, window, kind, p, dist),
-              flush=True)
+        print("case: strip %d f32 shape=%s w=%d kind=%d p=%s dist=%d"
+              % (cfg, shape, window, kind, p, dist), flush=True)
         o_t, i_t = _run(x, window, kind, p, dist, 2)
-        o_s, i_s = _run(x, window, kind, p, dist, STRIP)
+        o_s, i_s = _run(x, window, kind, p, dist, cfg)
         assert np.array_equal(i_s, i_t)
         assert np.array_equal(o_s, o_t)
 
@@ -83,19 +86,22 @@ def test_strip_equals_tile_f32(shape, window, kind, p):
                                                 (3, DDF, 0.5, RGB), (7, DDF, 0.25, EXACT),
                                                 (9, BVDF, 0.0, EXACT)])
 def test_strip_oracle(window, kind, p, dist):
-    """The strip form against the oracle on an image of three strips down."""
+    """The strip forms against the oracle on an image of three long strips down."""
     img = synth.image_corr(290, 75, 0.2, key=3)
-    print("case: strip oracle w=%d kind=%d p=%s dist=%d" % (window, kind, p, dist), flush=True)
-    out, idx = _run(_gpu(img), window, kind, p, dist, STRIP)
     _, _, _, _, oO = oracle.filter(img, window, kind, p, dist, 4, aggregates=True)
-    n_mis, n = check_selection(idx, oO)
-    print("mismatch %d / %d" % (n_mis, n))
-    assert np.array_equal(out.reshape(-1, 3), source_pixels(img, idx, window).reshape(-1, 3))
+    for cfg in STRIPS:
+        print("case: strip %d oracle w=%d kind=%d p=%s dist=%d" % (cfg, window, kind, p, dist),
+              flush=True)
+        out, idx = _run(_gpu(img), window, kind, p, dist, cfg)
+        n_mis, n = check_selection(idx, oO)
+        print("mismatch %d / %d" % (n_mis, n))
+        assert np.array_equal(out.reshape(-1, 3), source_pixels(img, idx, window).reshape(-1, 3))
 
 
 def test_strip_not_offered():
     """The strip form covers BVDF and DDF at 3x3 to 7x7 and BVDF at 9x9 on uint8."""
     for window, kind, u8 in [(9, DDF, True), (9, BVDF, False), (3, odf.ACWDDF, True),
                              (5, odf.CWDDF, True)]:
-        with pytest.raises(odf.ODFError):
-            odf.tune_set(window, kind, EXACT, u8, STRIP)
+        for cfg in STRIPS:
+            with pytest.raises(odf.ODFError):
+                odf.tune_set(window, kind, EXACT, u8, cfg)

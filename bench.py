@@ -604,41 +604,41 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
 
 
 def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
-    """ACWDDF (lambda = 2, T = 10.8) on the 1024 x 1024 image (3x3 and 5x5)
-    and on a 7680 x 4320 frame (3x3), each pair term, tuned tile shapes; the
-    1024 x 1024 3x3 index maps are kept for the oracle's mismatch count.  Also
-    CWVMF^2 and CWDDF^2 (exact) on the 1024 x 1024 image."""
+    """ACWDDF (lambda = 2, T = 10.8) on the 1024 x 1024 image and on a
+    7680 x 4320 frame (3x3 and 5x5), each pair term, configs tuned per size;
+    the 1024 x 1024 3x3 index maps are kept for the oracle's mismatch count.
+    Also CWVMF^2 and CWDDF^2 (exact) on the 1024 x 1024 image, tuned."""
     forms = {}
     big = torch.from_numpy(synth.image_corr(4320, 7680, 0.15, key=500)).to(dev)
     for w in (3, 5):
         for d in ("exact", "minimax", "rgb"):
-            best, _ = autotune(odf, w, odf.ACWDDF, DIST[d], True, 1024, 1024, 5)
-            cases = [("1024x1024", x1k)] + ([("7680x4320", big)] if w == 3 else [])
-            for tag, img in cases:
+            for tag, img in (("1024x1024", x1k), ("7680x4320", big)):
                 M, N = img.shape[:2]
+                best, _ = autotune(odf, w, odf.ACWDDF, DIST[d], True, M, N, 5)
                 o = torch.empty_like(img)
                 i = torch.empty((M, N), dtype=torch.uint8, device=dev)
                 ms = time_launches(torch, lambda: odf.acwddf(img, w, DIST[d], 4, 2, 10.8, out=o,
                                                              idx=i), 10, warm=2)
                 forms["acwddf%d_%s_%s" % (w, d, tag)] = {
                     "mpix_s": round(M * N / (ms * 1e3), 1), "ms": round(ms, 4),
-                    "ext_tile": odf.tile_config(best),
+                    "config": best, "ext_tile": odf.tile_config(best),
                     "valu_frac": round(slots_per_pixel(w, "acw", 0.5, d) * M * N / (ms * 1e-3)
                                        / PEAK_SLOTS, 4),
                     "switched_to_ddf": round(float((i != (w * w - 1) // 2).float().mean()), 4)}
                 if tag == "1024x1024" and w == 3:
                     acw_idx[d] = i.cpu().numpy()
-    # the centre-weighted filters on their own (eq. 9), level k = 2, on the
-    # ACWDDF kernels and their tuned tile shapes
+    # the centre-weighted filters on their own (eq. 9), level k = 2, each on
+    # the config its own table entry is tuned to
     M, N = x1k.shape[:2]
     o = torch.empty_like(x1k)
     i = torch.empty((M, N), dtype=torch.uint8, device=dev)
     for w in (3, 5):
         for name, kind, d in (("cwvmf", odf.CWVMF, "rgb"), ("cwddf", odf.CWDDF, "exact")):
+            best, _ = autotune(odf, w, kind, DIST[d], True, M, N, 5)
             ms = time_launches(torch, lambda: odf.cw_filter(x1k, w, kind, 2, DIST[d], 4, out=o,
                                                             idx=i), 10, warm=2)
             forms["%s%d_k2_1024x1024" % (name, w)] = {"mpix_s": round(M * N / (ms * 1e3), 1),
-                                                      "ms": round(ms, 4)}
+                                                      "ms": round(ms, 4), "config": best}
     del big
     return forms
 

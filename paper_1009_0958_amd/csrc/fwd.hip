@@ -10,9 +10,11 @@ namespace odf {
 // parks its weighted angle sums in LDS, which at 32 x 32 would not leave room
 // for a float32 tile's pixel arrays).
 bool tile_config_valid(int window, int kind, int cfg, bool u8) {
-    if (is_strip_config(cfg))  // as strip_form (fwd_strip.h)
+    if (is_strip_config(cfg)) {  // as strip_form (fwd_strip.h)
+        if (centre_weighted(kind)) return window == 3 || window == 5;
         return (kind == kBVDF || kind == kDDF) &&
                (window == 3 || window == 5 || window == 7 || (window == 9 && kind == kBVDF && u8));
+    }
     if (cfg < 0 || cfg >= kNumTileConfigs) return false;
     if (window == 9) return cfg == 2;  // 32 x 16 (64 x 8 leaves no output row at h = 4)
     if ((window == 5 && centre_weighted(kind)) || window == 7)

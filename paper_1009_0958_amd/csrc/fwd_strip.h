@@ -41,13 +41,16 @@ struct StripGeom {
 };
 
 // LDS of one strip workgroup.  NPL: planes swept together (2 for the fused
-// angle + L2 sweep of the 3x3 DDF); NTERM: carried plane sets (one per term).
+// angle + L2 sweep of the 3x3 DDF family); NTERM: carried plane sets (one per
+// term); NKEY: argmin keys per window (4 for ACWDDF: eq. 3 and three levels of
+// eq. 9), each set a ring of KEYN slots.
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 struct StripShared {
     using Gm = StripGeom<W, EXT_W, BH>;
     static constexpr bool INV = U8 && DIST != kExact;
     static constexpr int NPL = fused_sweep<W, KIND>() ? 2 : 1;
-    static constexpr int NTERM = KIND == kBVDF ? 1 : 2;
+    static constexpr int NTERM = (KIND == kBVDF || KIND == kCWV) ? 1 : 2;
+    static constexpr int NKEY = KIND == kACW ? 4 : 1;
     static constexpr int NPIX = Gm::PL + 2 * Gm::H;  // + the reads past the last row
     float4 dir[NPIX];
     float4 raw[U8 ? 1 : NPIX];
@@ -55,7 +58,7 @@ struct StripShared {
     // plane rows and carried rows are copied as float4: both 16-byte aligned
     alignas(16) float plane[NPL * Gm::G * Gm::PL + 4];
     alignas(16) float carry[NTERM * Gm::G * Gm::CROWS * EXT_W];
-    unsigned long long key[Gm::KEYN];
+    unsigned long long key[NKEY * Gm::KEYN];
 };
 
 // Plane hook of one sweep (aggregates.h): in row group g >= 1 it copies the
@@ -93,11 +96,13 @@ struct StripCarry {
     }
 };
 
-// The classes with a strip form: BVDF and DDF at 3x3, 5x5 and 7x7, and BVDF
-// at 9x9 on uint8 (the float32 9x9 strip and the 9x9 DDF strip, with its
-// second set of carried planes, would not fit the 160 KiB of LDS of a CU).
+// The classes with a strip form: BVDF and DDF at 3x3, 5x5 and 7x7, BVDF at
+// 9x9 on uint8 (the float32 9x9 strip and the 9x9 DDF strip, with its second
+// set of carried planes, would not fit the 160 KiB of LDS of a CU), and the
+// centre-weighted kinds (ACWDDF, CWDDF^k, CWVMF^k) at 3x3 and 5x5.
 template <int W, int KIND, bool U8>
 constexpr bool strip_form() {
+    if (centre_weighted(KIND)) return W == 3 || W == 5;
     if (KIND != kBVDF && KIND != kDDF) return false;
     return W == 3 || W == 5 || W == 7 || (W == 9 && KIND == kBVDF && U8);
 }
@@ -111,7 +116,11 @@ constexpr int lds_waves_per_eu(size_t lds_bytes, int threads) {
 }
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 constexpr int strip_waves_per_eu() {
-    return lds_waves_per_eu(sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH>), EXT_W * BH);
+    const int lds = lds_waves_per_eu(sizeof(StripShared<W, KIND, DIST, U8, EXT_W, BH>), EXT_W * BH);
+    // 5x5 ACWDDF keeps four sets of 25 aggregates (A, D and both centre terms):
+    // ~146 VGPRs, one workgroup per CU; held to 128 (14 spilled) two share a CU
+    // and the uint8 kernel runs 1.6x faster on 7680 x 4320
+    return (W == 5 && KIND == kACW && lds > 4) ? 4 : lds;
 }
 
 // Filter the strip of image b whose first output row is s0 and first output
@@ -129,12 +138,33 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, NT = Gm::NT, PL = Gm::PL;
     constexpr bool INV = Sh::INV;
     constexpr bool CANON = U8 && KIND == kBVDF;  // as in the tile form
-    static_assert(Gm::KCARRY <= NT, "one carried key per thread");
+    constexpr bool CEN = centre_weighted(KIND);   // the centre terms of eq. (9)
+    constexpr int NKEY = Sh::NKEY, KEYN = Gm::KEYN, KCARRY = Gm::KCARRY;
+    constexpr int KC = (NKEY * KCARRY + NT - 1) / NT;  // carried keys per thread
     static_assert(offsetof(Sh, plane) >= 2 * H * sizeof(float), "reads before plane");
     const int M = prm.M, N = prm.N;
     const int s_end = min(s0 + Gm::rows(nb), M);
     const TilePix px{sh.dir, sh.raw, sh.inv};
     float* const pl0 = sh.plane + 2 * H * EXT_W;  // ring row 2h: the band's first row
+
+    // the prepared pixel (direction, and the aux2 or raw vector) at image (gy, gx)
+    auto prepare_at = [&](int gy, int gx, float4& d, float4& w) {
+        const int pix = (b * M + gy) * N + gx;
+        if constexpr (U8) {
+            const uint8_t* s = static_cast<const uint8_t*>(prm.img) + (size_t)pix * 3;
+            const uint32_t c0 = s[0], c1 = s[1], c2 = s[2];
+            if constexpr (CANON) {
+                float d0, d1, d2;
+                canonical_direction(c0, c1, c2, d0, d1, d2);
+                prepare_pixel<DIST, U8, true>((float)c0, (float)c1, (float)c2, d, w, d0, d1, d2);
+            } else {
+                prepare_pixel<DIST, U8>((float)c0, (float)c1, (float)c2, d, w);
+            }
+        } else {
+            const float* s = static_cast<const float*>(prm.img) + (size_t)pix * 3;
+            prepare_pixel<DIST, U8>(s[0], s[1], s[2], d, w);
+        }
+    };
 
     for (int j = 0; j < nb; ++j) {
         // the thread index is laundered once per band, so that the compiler
@@ -148,57 +178,73 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
         if (fin0 >= s_end) break;          // uniform
 
         // keys of the windows the previous band's members share with this band
-        unsigned long long kc = ~0ull;
-        if (j > 0 && tid < Gm::KCARRY) kc = sh.key[BH * EXT_W + tid];
+        // (flat index q KCARRY + k for slot k of key set q)
+        unsigned long long kc[KC];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            const int i = tid + q * NT, set = i / KCARRY;
+            kc[q] = ~0ull;
+            if (j > 0 && i < NKEY * KCARRY)
+                kc[q] = sh.key[set * KEYN + BH * EXT_W + i - set * KCARRY];
+        }
         // a1: the band's RING pixel rows (members and the 2h rows below them)
         for (int i = tid; i < Gm::PL; i += NT) {
             const int r = i / EXT_W, c = i - r * EXT_W;
-            const int gy = min(max(base + r, 0), M - 1);
-            const int gx = min(max(tx0 - H + c, 0), N - 1);
-            const int pix = (b * M + gy) * N + gx;
             float4 d, w;
-            if constexpr (U8) {
-                const uint8_t* s = static_cast<const uint8_t*>(prm.img) + (size_t)pix * 3;
-                const uint32_t c0 = s[0], c1 = s[1], c2 = s[2];
-                if constexpr (CANON) {
-                    float d0, d1, d2;
-                    canonical_direction(c0, c1, c2, d0, d1, d2);
-                    prepare_pixel<DIST, U8, true>((float)c0, (float)c1, (float)c2, d, w, d0, d1,
-                                                  d2);
-                } else {
-                    prepare_pixel<DIST, U8>((float)c0, (float)c1, (float)c2, d, w);
-                }
-            } else {
-                const float* s = static_cast<const float*>(prm.img) + (size_t)pix * 3;
-                prepare_pixel<DIST, U8>(s[0], s[1], s[2], d, w);
-                sh.raw[i] = w;
-            }
+            prepare_at(min(max(base + r, 0), M - 1), min(max(tx0 - H + c, 0), N - 1), d, w);
             sh.dir[i] = d;
+            if constexpr (!U8) sh.raw[i] = w;
             if constexpr (INV) sh.inv[i] = w.w;
         }
         __syncthreads();
-        for (int i = tid; i < Gm::KEYN; i += NT) sh.key[i] = i < Gm::KCARRY ? kc : ~0ull;
+        for (int i = tid; i < NKEY * KEYN; i += NT) {
+            const int set = i / KEYN;
+            if (i - set * KEYN >= KCARRY) sh.key[i] = ~0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            const int i = tid + q * NT, set = i / KCARRY;
+            if (i < NKEY * KCARRY) sh.key[set * KEYN + i - set * KCARRY] = kc[q];
+        }
 
         const float4 mdir = sh.dir[tid];
         float4 mraw;
         if constexpr (U8) mraw = make_float4(0.0f, 0.0f, 0.0f, INV ? sh.inv[tid] : 0.0f);
         else mraw = sh.raw[tid];
 
+        // a2 + a3: A and D (and the centre terms cA, cD of the centre-weighted kinds)
         float A[NW], D[NW], cA[NW], cD[NW];
-        if constexpr (fused_sweep<W, KIND>()) {
+        if constexpr (KIND == kCWV) {  // eq. (9) on the L2 term alone
+#pragma unroll
+            for (int u = 0; u < NW; ++u) A[u] = cA[u] = 0.0f;
+            const StripCarry<EXT_W, BH, H, G, PL, NT> hd{sh.plane, sh.carry, tid};
+            float u0[NW], u1[NW];
+            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 1, true, false, PL>(
+                px, pl0, ey, ex, tid, mdir, mraw, prm.coef, D, cD, u0, u1, hd);
+        } else if constexpr (fused_sweep<W, KIND>()) {
             const StripCarry<EXT_W, BH, H, 2 * G, PL, NT> hk{sh.plane, sh.carry, tid};
-            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 2, false, false, PL>(
+            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 2, CEN, false, PL>(
                 px, pl0, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD, hk);
         } else {
             const StripCarry<EXT_W, BH, H, G, PL, NT> hk{sh.plane, sh.carry, tid};
-            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 0, false, false, PL>(
+            member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 0, CEN, false, PL>(
                 px, pl0, ey, ex, tid, mdir, mraw, prm.coef, A, cA, D, cD, hk);
             if constexpr (KIND != kBVDF) {
-                pin_values(A);  // the aggregates, not the row sums, live through the L2 sweep
+                // the aggregates, not the row sums, live through the L2 sweep
+                if constexpr (KIND == kCW) {
+                    // CWDDF^k needs the angle sums only weighted: A + (w_d(k) - 1) cA
+                    const float w1 = prm.acw_wm1[0];
+#pragma unroll
+                    for (int u = 0; u < NW; ++u) A[u] = fmaf(w1, cA[u], A[u]);
+                    pin_values(A);
+                } else {
+                    pin_values(A);
+                    if constexpr (CEN) pin_values(cA);
+                }
                 const StripCarry<EXT_W, BH, H, G, PL, NT> hd{
                     sh.plane, sh.carry + G * Gm::CROWS * EXT_W, tid};
                 float u0[NW], u1[NW];
-                member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 1, false, false, PL>(
+                member_aggregates_x<W, KIND, DIST, U8, EXT_W, BH, 1, CEN, false, PL>(
                     px, pl0, ey, ex, tid, mdir, mraw, prm.coef, D, cD, u0, u1, hd);
             } else {
 #pragma unroll
@@ -207,36 +253,73 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
         }
 
         // a4: every window of the member; window u is centred on band row
-        // ey + h - u / W, column ex + h - u % W, key slot (row + h) EXT_W + col + h.
-        // Windows past the strip's columns hold meaningless aggregates and land
-        // in slots no output reads.
+        // ey + h - u / W, column ex + h - u % W, key slot (row + h) EXT_W + col + h
+        // of each key set.  Windows past the strip's columns hold meaningless
+        // aggregates and land in slots no output reads.  The member numbers are
+        // formed here: as constants the compiler keeps all n of them in vector
+        // registers across the band loop.
         {
-            uint32_t kb[NW];
-            const int mode = objective_mode<KIND>(prm.p);
-            if constexpr (stage_angle_part<W, KIND, false>()) {
-                // the key as the tile form's staged path forms it
-                auto staged = [&](auto mode_c) {
-                    constexpr int MODE = decltype(mode_c)::value;
-#pragma unroll
-                    for (int u = 0; u < NW; ++u)
-                        kb[u] = staged_key_bits<MODE>(staged_part<MODE>(A[u], prm.p), D[u], prm.p);
-                };
-                if (mode == kObjA) staged(std::integral_constant<int, kObjA>{});
-                else if (mode == kObjD) staged(std::integral_constant<int, kObjD>{});
-                else if (mode == kObjLog) staged(std::integral_constant<int, kObjLog>{});
-                else if (mode == kObjQuarter) staged(std::integral_constant<int, kObjQuarter>{});
-                else staged(std::integral_constant<int, kObjProd>{});
-            } else {
-                objective_key_bits<NW>(mode, prm.p, A, D, kb);
-            }
-            // the member numbers, formed here: as constants the compiler keeps
-            // all n of them in vector registers across the band loop
             unsigned z = 0;
             asm volatile("" : "+v"(z));
+            auto slot = [&](int u) { return tid + (2 * H - u / W) * EXT_W + 2 * H - u % W; };
+            if constexpr (KIND == kACW) {
+                // eq. (3) and the centre-weighted objectives of eq. (9), as the tile form
+                const float w1 = prm.acw_wm1[0], w2 = prm.acw_wm1[1], w3 = prm.acw_wm1[2];
 #pragma unroll
-            for (int u = 0; u < NW; ++u)
-                atomicMin(&sh.key[tid + (2 * H - u / W) * EXT_W + 2 * H - u % W],
-                          ((unsigned long long)kb[u] << 32) | (z + (unsigned)u));
+                for (int u = 0; u < NW; ++u) {
+                    const unsigned long long uu = z + (unsigned)u;
+                    const float o0 = A[u] * D[u];
+                    const float o1 = fmaf(w1, cA[u], A[u]) * fmaf(w1, cD[u], D[u]);
+                    const float o2 = fmaf(w2, cA[u], A[u]) * fmaf(w2, cD[u], D[u]);
+                    const float o3 = fmaf(w3, cA[u], A[u]) * fmaf(w3, cD[u], D[u]);
+                    const int k = slot(u);
+                    atomicMin(&sh.key[k], ((unsigned long long)__float_as_uint(o0) << 32) | uu);
+                    atomicMin(&sh.key[KEYN + k],
+                              ((unsigned long long)__float_as_uint(o1) << 32) | uu);
+                    atomicMin(&sh.key[2 * KEYN + k],
+                              ((unsigned long long)__float_as_uint(o2) << 32) | uu);
+                    atomicMin(&sh.key[3 * KEYN + k],
+                              ((unsigned long long)__float_as_uint(o3) << 32) | uu);
+                }
+            } else if constexpr (KIND == kCW || KIND == kCWV) {
+                // one centre-weighted filter at one level: CWDDF^k the weighted
+                // product, CWVMF^k (eq. 9) the weighted L2 sum (at 5x5, A holds
+                // the weighted angle sums of CWDDF^k already)
+                const float w1 = prm.acw_wm1[0];
+#pragma unroll
+                for (int u = 0; u < NW; ++u) {
+                    const float dw = fmaf(w1, cD[u], D[u]);
+                    float o = dw;
+                    if constexpr (KIND == kCW)
+                        o = (fused_sweep<W, KIND>() ? fmaf(w1, cA[u], A[u]) : A[u]) * dw;
+                    atomicMin(&sh.key[slot(u)],
+                              ((unsigned long long)__float_as_uint(o) << 32) | (z + (unsigned)u));
+                }
+            } else {
+                uint32_t kb[NW];
+                const int mode = objective_mode<KIND>(prm.p);
+                if constexpr (stage_angle_part<W, KIND, false>()) {
+                    // the key as the tile form's staged path forms it
+                    auto staged = [&](auto mode_c) {
+                        constexpr int MODE = decltype(mode_c)::value;
+#pragma unroll
+                        for (int u = 0; u < NW; ++u)
+                            kb[u] = staged_key_bits<MODE>(staged_part<MODE>(A[u], prm.p), D[u],
+                                                          prm.p);
+                    };
+                    if (mode == kObjA) staged(std::integral_constant<int, kObjA>{});
+                    else if (mode == kObjD) staged(std::integral_constant<int, kObjD>{});
+                    else if (mode == kObjLog) staged(std::integral_constant<int, kObjLog>{});
+                    else if (mode == kObjQuarter) staged(std::integral_constant<int, kObjQuarter>{});
+                    else staged(std::integral_constant<int, kObjProd>{});
+                } else {
+                    objective_key_bits<NW>(mode, prm.p, A, D, kb);
+                }
+#pragma unroll
+                for (int u = 0; u < NW; ++u)
+                    atomicMin(&sh.key[slot(u)],
+                              ((unsigned long long)kb[u] << 32) | (z + (unsigned)u));
+            }
         }
         __syncthreads();
 
@@ -244,7 +327,38 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
         {
             const int gy = fin0 + ey, gx = tx0 - H + ex;
             if (ex >= H && ex < EXT_W - H && gy >= s0 && gy < s_end && gx < N) {
-                const int u = min((int)(sh.key[ey * EXT_W + ex + H] & 0xffu), NW - 1);
+                const int ki = ey * EXT_W + ex + H;
+                int u = min((int)(sh.key[ki] & 0xffu), NW - 1);
+                if constexpr (KIND == kACW) {
+                    // switch: S = sum over the three levels of A(y_k, x_c) L2(y_k, x_c),
+                    // the pixels prepared again from the image (a member may lie in the
+                    // previous band's rows); the eq. (3) selection if S > T, else the
+                    // centre
+                    float4 cd, cw;
+                    prepare_at(gy, gx, cd, cw);
+                    const AtanCoef ac = atan_coef();
+                    float S = 0.0f;
+#pragma unroll
+                    for (int q = 1; q <= 3; ++q) {
+                        const int uj = min((int)(sh.key[q * KEYN + ki] & 0xffu), NW - 1);
+                        float4 md, mw;
+                        prepare_at(min(max(gy - H + uj / W, 0), M - 1),
+                                   min(max(gx - H + uj % W, 0), N - 1), md, mw);
+                        if constexpr (U8) {
+                            float th, l2;
+                            const bool mz = md.w < 0.0f;
+                            pair_u8<KIND, DIST, true, true>(md, INV ? mw.w : 0.0f, mz,
+                                                            __builtin_amdgcn_ballot_w64(mz), cd,
+                                                            INV ? cw.w : 0.0f, prm.coef, ac, th,
+                                                            l2);
+                            S += th * l2;
+                        } else {
+                            S += pair_term<KIND, DIST, U8>(md, mw, cd, cw, prm.coef, ac) *
+                                 l2_term(mw, cw);
+                        }
+                    }
+                    if (!(S > prm.acw_T)) u = (NW - 1) / 2;
+                }
                 const int sy = min(max(gy - H + u / W, 0), M - 1);
                 const int sx = min(max(gx - H + u % W, 0), N - 1);
                 const int src = (b * M + sy) * N + sx;
@@ -316,6 +430,15 @@ static hipError_t launch_strip_w(int kind, int dist, bool u8, const FwdParams& p
     if (kind == kDDF)
         return u8 ? launch_strip_class<W, kDDF, true>(dist, prm, nb, s)
                   : launch_strip_class<W, kDDF, false>(dist, prm, nb, s);
+    if (kind == kACW)
+        return u8 ? launch_strip_class<W, kACW, true>(dist, prm, nb, s)
+                  : launch_strip_class<W, kACW, false>(dist, prm, nb, s);
+    if (kind == kCW)
+        return u8 ? launch_strip_class<W, kCW, true>(dist, prm, nb, s)
+                  : launch_strip_class<W, kCW, false>(dist, prm, nb, s);
+    if (kind == kCWV)  // no angle term: the L2 sweep of the rgb layout
+        return u8 ? launch_strip_class<W, kCWV, true>(kRgb, prm, nb, s)
+                  : launch_strip_class<W, kCWV, false>(kRgb, prm, nb, s);
     return hipErrorInvalidValue;
 }
 hipError_t launch_strip3(int kind, int dist, bool u8, const FwdParams& prm, int nb, hipStream_t s);

@@ -109,7 +109,8 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_set(3, 0, 0, 1, -1) == odf.EINVAL
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
-    # config 4: the strip form (32 x 16 bands): BVDF and DDF at 3x3 to 7x7, BVDF 9x9 on uint8
+    # configs 4, 5: the strip form (32 x 16 bands): BVDF and DDF at 3x3 to 7x7, BVDF 9x9 on
+    # uint8, the centre-weighted kinds at 3x3 and 5x5
     assert odf.tile_config(odf.STRIP) == (32, 16) and odf.tile_config(odf.SHORT_STRIP) == (32, 16)
     assert L.odf_tile_config(odf.NUM_TILE_CONFIGS, ctypes.byref(ctypes.c_int()),
                              ctypes.byref(ctypes.c_int())) == odf.EINVAL
@@ -120,8 +121,11 @@ def test_batch_and_tune_argument_errors():
         assert odf.tune_get(w, kind, odf.EXACT, u8) == odf.STRIP
         assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.SHORT_STRIP) == odf.OK
         odf.tune_set(w, kind, odf.EXACT, u8, saved)
-    for w, kind, u8 in ((9, odf.DDF, 1), (9, odf.BVDF, 0), (3, odf.ACWDDF, 1), (5, odf.CWVMF, 1),
-                        (5, odf.CWDDF, 1)):
+    for w, kind, u8 in ((3, odf.ACWDDF, 1), (5, odf.CWVMF, 0), (5, odf.CWDDF, 1)):
+        saved = odf.tune_get(w, kind, odf.EXACT, u8)
+        assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.SHORT_STRIP) == odf.OK
+        odf.tune_set(w, kind, odf.EXACT, u8, saved)
+    for w, kind, u8 in ((9, odf.DDF, 1), (9, odf.BVDF, 0)):
         assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.STRIP) == odf.EINVAL
         assert L.odf_tune_set(w, kind, odf.EXACT, u8, odf.SHORT_STRIP) == odf.EINVAL
     assert L.odf_tune_set(3, 0, 0, 1, odf.NUM_TILE_CONFIGS) == odf.EINVAL

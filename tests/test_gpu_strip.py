@@ -99,9 +99,46 @@ def test_strip_oracle(window, kind, p, dist):
 
 
 def test_strip_not_offered():
-    """The strip form covers BVDF and DDF at 3x3 to 7x7 and BVDF at 9x9 on uint8."""
-    for window, kind, u8 in [(9, DDF, True), (9, BVDF, False), (3, odf.ACWDDF, True),
-                             (5, odf.CWDDF, True)]:
+    """The strip form covers BVDF and DDF at 3x3 to 7x7, BVDF at 9x9 on uint8 and
+    the centre-weighted kinds at 3x3 and 5x5."""
+    for window, kind, u8 in [(9, DDF, True), (9, BVDF, False)]:
         for cfg in STRIPS:
             with pytest.raises(odf.ODFError):
                 odf.tune_set(window, kind, EXACT, u8, cfg)
+
+
+def _run_cw(x, window, kind, dist, cfg, level):
+    """ACWDDF (lambda = 2, T = 10.8) or a centre-weighted filter at `level` on config cfg."""
+    u8 = x.dtype == torch.uint8
+    saved = odf.tune_get(window, kind, dist, u8)
+    odf.tune_set(window, kind, dist, u8, cfg)
+    try:
+        if kind == odf.ACWDDF:
+            out, idx = odf.acwddf(x, window, dist, 4, 2, 10.8)
+        else:
+            out, idx = odf.cw_filter(x, window, kind, level, dist)
+        torch.cuda.synchronize()
+    finally:
+        odf.tune_set(window, kind, dist, u8, saved)
+    return out.cpu().numpy(), idx.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg", STRIPS)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 5, 7), (1, 130, 61), (2, 257, 45), (1, 40, 300)])
+@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("u8", [True, False])
+def test_strip_equals_tile_centre_weighted(shape, window, u8, cfg):
+    """ACWDDF (its four keys per window and the switching statistic) and the
+    centre-weighted filters CWDDF^k and CWVMF^k on the strip form, bitwise equal
+    to their 32 x 16 tiles."""
+    img = _image(shape, u8, 13)
+    x = _gpu(img)
+    for kind, dists, level in [(odf.ACWDDF, (EXACT, MINIMAX, RGB), 0), (odf.CWDDF, (EXACT, RGB), 2),
+                               (odf.CWVMF, (RGB,), window)]:
+        for dist in dists:
+            print("case: strip %d cw u8=%s shape=%s w=%d kind=%d dist=%d level=%d"
+                  % (cfg, u8, shape, window, kind, dist, level), flush=True)
+            o_t, i_t = _run_cw(x, window, kind, dist, 2, level)
+            o_s, i_s = _run_cw(x, window, kind, dist, cfg, level)
+            assert np.array_equal(i_s, i_t)
+            assert np.array_equal(o_s, o_t)

@@ -182,7 +182,7 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
         unsigned long long kc[KC];
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
-            const int i = tid + q * NT, set = i / KCARRY;
+            const int i = tid + q * NT, set = NKEY == 1 ? 0 : i / KCARRY;
             kc[q] = ~0ull;
             if (j > 0 && i < NKEY * KCARRY)
                 kc[q] = sh.key[set * KEYN + BH * EXT_W + i - set * KCARRY];
@@ -198,12 +198,12 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
         }
         __syncthreads();
         for (int i = tid; i < NKEY * KEYN; i += NT) {
-            const int set = i / KEYN;
+            const int set = NKEY == 1 ? 0 : i / KEYN;
             if (i - set * KEYN >= KCARRY) sh.key[i] = ~0ull;
         }
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
-            const int i = tid + q * NT, set = i / KCARRY;
+            const int i = tid + q * NT, set = NKEY == 1 ? 0 : i / KCARRY;
             if (i < NKEY * KCARRY) sh.key[set * KEYN + i - set * KCARRY] = kc[q];
         }
 

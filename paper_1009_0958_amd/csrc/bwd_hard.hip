@@ -32,9 +32,11 @@ __global__ void __launch_bounds__(kBwdThreads) bwd_hard_kernel(const uint8_t* __
     constexpr int TP = kBwdTW * kBwdTH;                // pixels of the tile
     __shared__ uint32_t s_mask[WORDS * TP];            // word k of pixel l at k * TP + l
     __shared__ float s_dy[3 * RN];                     // dy(c), 3 floats per staged window
-    const int tile = flat_block(grid.n);
-    if (tile < 0) return;
-    const TileCoord tc = tile_coord(tile, grid);
+    const int t0 = flat_block(grid.n);
+    if (t0 < 0) return;
+    // XCD-contiguous order: the halo a tile shares with its neighbours is read
+    // once per XCD's L2 (HBM traffic 1.24 -> 1.00 times the 25 B per pixel)
+    const TileCoord tc = tile_coord(xcd_item(t0, grid.n), grid);
     const int tx0 = tc.tx * kBwdTW, ty0 = tc.ty * kBwdTH;
     const size_t base = (size_t)tc.b * M * N;
     const int tid = threadIdx.x;

@@ -379,12 +379,10 @@ __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, 
 }
 
 // One workgroup per strip of the launch's images (prm.strip_bands bands each),
-// in an XCD-contiguous order: the hardware hands workgroup t0 (dispatch order)
-// to XCD t0 mod 8, so strip t = (its XCD's first strip) + t0 / 8 gives every
-// XCD one contiguous run of strips, whose neighbours share their overlapping
-// columns and the cache lines that 3-byte pixels straddle in that XCD's L2
-// (HBM traffic of the 5x5 DDF strip on 7680 x 4320: 2.07 -> 1.03 times the
-// algorithmic bytes, at the same speed).
+// in the XCD-contiguous order of xcd_item: neighbouring strips share their
+// overlapping columns and the cache lines that 3-byte pixels straddle in one
+// XCD's L2 (HBM traffic of the 5x5 DDF strip on 7680 x 4320: 2.07 -> 1.03 times
+// the algorithmic bytes, at the same speed).
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 __global__ void __launch_bounds__(EXT_W* BH)
     __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<W, KIND, DIST, U8, EXT_W, BH>())))
@@ -393,9 +391,7 @@ __global__ void __launch_bounds__(EXT_W* BH)
     using Gm = StripGeom<W, EXT_W, BH>;
     const int t0 = flat_block(prm.grid.n);
     if (t0 < 0) return;
-    const int n = prm.grid.n, q = n / 8, r = n - 8 * q, x = t0 % 8;
-    const int t = x * q + min(x, r) + t0 / 8;  // a bijection of [0, n)
-    const TileCoord tc = tile_coord(t, prm.grid);
+    const TileCoord tc = tile_coord(xcd_item(t0, prm.grid.n), prm.grid);
     const int nb = prm.strip_bands;
     fwd_strip<W, KIND, DIST, U8, EXT_W, BH>(sh, prm, tc.b, tc.ty * Gm::rows(nb), tc.tx * Gm::TW,
                                             nb);

@@ -28,6 +28,16 @@ __device__ __forceinline__ int flat_block(int n) {
     return t < (unsigned)n ? (int)t : -1;
 }
 
+// XCD-contiguous numbering of a launch's n workgroups: the hardware hands the
+// workgroup of dispatch index t0 to XCD t0 mod 8 (each with its own L2), so
+// item xcd_item(t0, n) = (first item of that XCD) + t0 / 8 gives every XCD one
+// contiguous run of items (a bijection of [0, n)): neighbouring items then
+// share their halo and the cache lines they straddle in one L2.
+__device__ __forceinline__ int xcd_item(int t0, int n) {
+    const int q = n / 8, r = n - 8 * q, x = t0 % 8;
+    return x * q + min(x, r) + t0 / 8;
+}
+
 // Division of a 32-bit unsigned integer by a divisor fixed for a launch, as a
 // multiply-high, a subtraction, an addition and two shifts on uniform values
 // (Granlund and Montgomery, "Division by invariant integers using

@@ -96,14 +96,14 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-
 # --copy-probe-mib 256 --tune-cache <file>`), keyed by form and extended tile
 # (or band).  Each counter is scaled by what it reads for the 256 MiB float32
 # copy of the same run (262144 KiB read, 262144 KiB written): FETCH_SIZE read
-# 131085.8 KiB (x 1.99979), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold
+# 131085.5 KiB (x 1.99979), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold
 # for the kernel sources hashed in TRAFFIC_SRC_SHA256; for any other sources
 # bench.py reports traffic as null.
-TRAFFIC_FETCH_SCALE = 262144.0 / 131085.8
+TRAFFIC_FETCH_SCALE = 262144.0 / 131085.5
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("ddf5_exact_7680x4320_strip", 32, 16): (51784.9, 129658.1),
-    ("batch6", 32, 16): (21001.8, 36888.2),
+    ("ddf5_exact_7680x4320_strip", 32, 16): (51784.7, 129657.9),
+    ("batch6", 32, 16): (21001.6, 36888.0),
 }
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",

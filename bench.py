@@ -108,7 +108,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "4e0061ca875b5cf88d5378ba394874fbc8ab8b9cbb0a368899cdc75329ee2167"
+TRAFFIC_SRC_SHA256 = "eb08a01c9a667fe4b32569ccb37d230384c594748339b4a1edb3a916e3deb8b8"
 
 
 def forward_sources_sha256():

@@ -1,6 +1,7 @@
-// fwd_strip.h -- the strip form of the forward filter (BVDF / DDF): one
-// workgroup filters a column strip of output pixels, walking down it band by
-// band, instead of one output tile with a halo on all four sides.
+// fwd_strip.h -- the strip form of the forward filter (BVDF, DDF and the
+// centre-weighted kinds): one workgroup filters a column strip of output
+// pixels, walking down it band by band, instead of one output tile with a halo
+// on all four sides.
 //
 // A band is EXT_W x BH member pixels (one thread each).  Each member's offset
 // grid is swept exactly as in the tile form (aggregates.h: own terms of row
@@ -125,11 +126,10 @@ constexpr int strip_waves_per_eu() {
 
 // Filter the strip of image b whose first output row is s0 and first output
 // column tx0 (nb bands: nb BH - 2h output rows x TW output columns, clipped to
-// the image).  Bands
-// start h rows above the strip and the first band's 2h top window rows lie
-// above it (discarded); a band reads its RING pixel rows (replicated border),
-// sweeps, and then writes the BH window rows its members completed.  Every
-// thread of the workgroup must call it (it synchronises).
+// the image).  Bands start h rows above the strip and the first band's 2h top
+// window rows lie above it (discarded); a band reads its RING pixel rows
+// (replicated border), sweeps, and then writes the BH window rows its members
+// completed.  Every thread of the workgroup must call it (it synchronises).
 template <int W, int KIND, int DIST, bool U8, int EXT_W, int BH>
 __device__ __forceinline__ void fwd_strip(StripShared<W, KIND, DIST, U8, EXT_W, BH>& sh,
                                           const FwdParams& prm, int b, int s0, int tx0, int nb) {

@@ -92,8 +92,9 @@ const char* odf_last_error(void);
  * Zero pixels take the direction (1,1,1) in the angle and chromaticity terms.
  * Errors: ODF_EINVAL for null img/out, sizes < 1, out overlapping img, or a
  * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5, 7, 9}
- * (9 x 9 keeps 81 aggregates per thread: one tile shape, about 250 VGPRs; 11 x 11
- * would need 121 and is not offered);
+ * (9 x 9 keeps 81 aggregates per thread: one tile shape and, for ODF_BVDF on
+ * uint8, the strip form, about 250 VGPRs; 11 x 11 would need 121 and is not
+ * offered);
  * ODF_EHIP if the launch fails.
  */
 int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, float p,
@@ -290,11 +291,11 @@ typedef struct {
 
 typedef struct odf_plan odf_plan; /* opaque, owned by the library */
 
-/* Validate the jobs, cut them into tiles and upload the work lists (one per
- * group of window and kind, holding the tiles of every pair term, heavier
- * tiles first); each group runs on the extended-tile shape the batch tuning
- * table holds for it when the plan is made (odf_batch_tune_get,
- * odf_autotune_batch).  Allocates device memory and synchronises; the job
+/* Validate the jobs, cut them into tiles (or strips) and upload the work lists
+ * (one per group of window and kind, holding the items of every pair term,
+ * heavier items first); each group runs on the config (tile shape or strip
+ * height) the batch tuning table holds for it when the plan is made
+ * (odf_batch_tune_get, odf_autotune_batch).  Allocates device memory and synchronises; the job
  * buffers must stay valid while the plan is launched.  On success *plan
  * receives a plan to pass to odf_batch_launch and finally to
  * odf_plan_destroy.  Errors: ODF_EINVAL / ODF_EUNSUPPORTED for a bad job

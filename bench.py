@@ -97,7 +97,8 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 39.3e12 lane-
 # (or band).  Each counter is scaled by what it reads for the 256 MiB float32
 # copy of the same run (262144 KiB read, 262144 KiB written): FETCH_SIZE read
 # 131085.5 KiB (x 1.99979), WRITE_SIZE 262144.0 KiB (x 1.0).  The figures hold
-# for the kernel code hashed in TRAFFIC_SRC_SHA256 (comments excluded); for any
+# for the kernel code hashed in TRAFFIC_SRC_SHA256 (comments and indentation
+# excluded); for any
 # other code bench.py reports traffic as null.
 TRAFFIC_FETCH_SCALE = 262144.0 / 131085.5
 TRAFFIC_WRITE_SCALE = 262144.0 / 262144.0
@@ -108,20 +109,20 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "1a8bc806c5f77299bd2adf6fdb13820e866b4a5cae1a5b1619ed5c6a75f6feeb"
+TRAFFIC_SRC_SHA256 = "399f07da71c587dc671162d1b2247271752c39e9317b65c00814f39ef5911604"
 
 
 def forward_sources_sha256():
-    """SHA-256 of the forward kernels' sources with their // comments, trailing
-    blanks and empty lines removed: a change of code changes it, a change of
-    comments does not."""
+    """SHA-256 of the forward kernels' sources with their // comments, the
+    blanks around each line and empty lines removed: a change of code changes
+    it, a change of comments or indentation does not."""
     import hashlib
     import re
     h = hashlib.sha256()
     for name in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_1009_0958_amd", "csrc", name)) as f:
             for line in f:
-                code = re.sub(r"//.*", "", line).rstrip()
+                code = re.sub(r"//.*", "", line).strip()
                 if code:
                     h.update(code.encode() + b"\n")
     return h.hexdigest()

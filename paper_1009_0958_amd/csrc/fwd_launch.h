@@ -65,7 +65,7 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         default:
             if constexpr (strip_form<W, KIND, U8>())
                 if (is_strip_config(cfg))
-                return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
+                    return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
             return hipErrorInvalidValue;
         }
     } else {
@@ -75,9 +75,9 @@ static hipError_t launch_t(int cfg, const FwdParams& prm, hipStream_t stream) {
         case 2: return launch_shape<W, KIND, DIST, U8, AGG, 32, 16>(prm, stream);
         case 3: return launch_shape<W, KIND, DIST, U8, AGG, 64, 8>(prm, stream);
         default:
-            if constexpr (strip_form<W, KIND, U8>())  // 32-wide strips of 8 bands of 16 rows
+            if constexpr (strip_form<W, KIND, U8>())  // 32-wide strips of 8 or 3 bands of 16 rows
                 if (is_strip_config(cfg))
-                return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
+                    return launch_strip_extern<W>(KIND, DIST, U8, prm, strip_bands(cfg), stream);
             return hipErrorInvalidValue;
         }
     }

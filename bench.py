@@ -109,7 +109,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "399f07da71c587dc671162d1b2247271752c39e9317b65c00814f39ef5911604"
+TRAFFIC_SRC_SHA256 = "2051ccae2184a933f7db4fbb33cd2011e2e2bd521b80c83b1eb78f43704acd1d"
 
 
 def forward_sources_sha256():

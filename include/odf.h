@@ -135,7 +135,7 @@ int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, 
  *          paper's setting is lambda = 2, T = 10.8 (angles in radians, L2 in
  *          the units of the image values).
  *   T      any value but NaN (+inf keeps every centre; below 0 gives the DDF).
- * Windows 3 and 5 (ODF_EUNSUPPORTED for 7 and 9).
+ * Windows 3, 5 and 7 (ODF_EUNSUPPORTED for 9).
  * Errors: as odf_filter_u8, plus ODF_EINVAL for lambda out of range or T NaN.
  */
 int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
@@ -160,9 +160,9 @@ int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, 
  *   level  k in [1, (n+1)/2].
  *   img, out, idx as for odf_filter_u8; ties go to the lowest index.
  * Runs on the ACWDDF sweep, with tile table entries of its own (kind
- * ODF_CWVMF or ODF_CWDDF in the tuning calls); windows 3 and 5.
+ * ODF_CWVMF or ODF_CWDDF in the tuning calls); windows 3, 5 and 7.
  * Errors: as odf_filter_u8, plus ODF_EINVAL for kind or level out of range,
- * ODF_EUNSUPPORTED for windows 7 and 9.
+ * ODF_EUNSUPPORTED for window 9.
  */
 int odf_cw_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, int dist, int q,
                      int level, uint8_t* out, uint8_t* idx, void* stream);
@@ -206,7 +206,7 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
  * y(c) = sum_u pi_u x_u.  tau -> 0 tends to the hard selection where the
  * minimum is unique.
  *   x  B x M x N x 3 float32 (read only); y  B x M x N x 3 float32 output.
- * Windows 3 and 5 (ODF_EUNSUPPORTED for 7 and 9).
+ * Windows 3, 5 and 7 (ODF_EUNSUPPORTED for 9).
  * Errors: as odf_filter_f32, plus ODF_EINVAL for tau <= 0 or not finite.
  */
 int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,
@@ -262,7 +262,7 @@ int odf_softmin_bwd_f32_noalloc(const float* x, const float* dy, int B, int M, i
  * every window to the workspace (n x 3 binary64 per pixel, 8-byte aligned,
  * owned by the caller, contents on entry ignored), then sums, for every pixel,
  * those of the members that are that pixel (windows in raster order, members
- * in index order): deterministic.  Windows 3 and 5.
+ * in index order): deterministic.  Windows 3, 5 and 7.
  */
 int odf_softmin_fwd_f64(const double* x, int B, int M, int N, int window, int kind, double p,
                         double tau, double* y, void* stream);
@@ -381,8 +381,9 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * The forward kernels run one thread per pixel of an extended tile
  * (output tile plus halo).  Configs 0..3 are tile shapes (one workgroup per
  * output tile); configs ODF_STRIP_CONFIG (4) and ODF_SHORT_STRIP_CONFIG (5) are
- * the strip form, offered for ODF_BVDF and ODF_DDF at 3x3, 5x5 and 7x7 and for
- * ODF_BVDF at 9x9 on uint8 (the batch offers them for all its groups): one
+ * the strip form, offered for ODF_BVDF and ODF_DDF at 3x3, 5x5 and 7x7, for
+ * ODF_BVDF at 9x9 on uint8 and for the centre-weighted kinds at 3x3 and 5x5
+ * (the batch offers them for all its groups): one
  * workgroup per strip of 32 - 2h output columns and 8 * 16 - 2h (config 4) or
  * 3 * 16 - 2h (config 5, for images too small to fill the GPU with long
  * strips) output rows, walking down it in bands of 32 x 16 member pixels and
@@ -391,11 +392,12 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * bitwise equal to the tile shapes).  odf_tile_config
  * gives the extended width and height of a tile shape, or of one band of the
  * strip form.  The process-wide table picks a config per (window, kind,
- * dist, input type), kind any odf_kind (windows 3 and 5 for ODF_ACWDDF,
+ * dist, input type), kind any odf_kind (windows 3, 5 and 7 for ODF_ACWDDF,
  * ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular term and keeps one entry
  * for every dist); the default is shape 2 (32 x 16) for every class (the 5x5
- * centre-weighted kinds and 7x7 offer only the 512-thread shapes 2 and 3, 9x9
- * only shape 2).  The table is initialised once per process and each entry is
+ * centre-weighted kinds and 7x7 offer only the 512-thread shapes 2 and 3 and,
+ * where the strip form covers them, configs 4 and 5; 9x9 only shape 2 and the
+ * strips).  The table is initialised once per process and each entry is
  * read and written atomically. */
 #define ODF_NUM_TILE_CONFIGS 6
 #define ODF_STRIP_CONFIG 4

@@ -128,7 +128,7 @@ int acwddf_any(const void* img, bool u8, int B, int M, int N, int window, int di
                int lambda, float T, void* out, uint8_t* idx, void* stream) {
     int rc = check_common(img, B, M, N, window, ODF_DDF, 0.5f, dist, q);
     if (rc) return rc;
-    if (window >= 7) return fail(ODF_EUNSUPPORTED, "ACWDDF supports windows 3 and 5");
+    if (window >= 9) return fail(ODF_EUNSUPPORTED, "ACWDDF supports windows 3, 5 and 7");
     if (!out) return fail(ODF_EINVAL, "out is NULL");
     const int dmax = (window * window + 1) / 2 - 2;
     if (lambda < 1 || lambda > dmax)
@@ -157,8 +157,8 @@ int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, 
     if (rc) return rc;
     if (kind != ODF_CWVMF && kind != ODF_CWDDF)
         return fail(ODF_EINVAL, "kind %d is not ODF_CWVMF or ODF_CWDDF", kind);
-    if (window >= 7)
-        return fail(ODF_EUNSUPPORTED, "centre-weighted filters support windows 3 and 5");
+    if (window >= 9)
+        return fail(ODF_EUNSUPPORTED, "centre-weighted filters support windows 3, 5 and 7");
     if (!out) return fail(ODF_EINVAL, "out is NULL");
     const int n = window * window, dmax = (n + 1) / 2;
     if (level < 1 || level > dmax) return fail(ODF_EINVAL, "level %d out of range [1, %d]", level, dmax);
@@ -260,8 +260,8 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
 static int check_soft(const float* x, int B, int M, int N, int window, int kind, float p, float tau) {
     int rc = check_common(x, B, M, N, window, kind, p, ODF_EXACT, 4);
     if (rc) return rc;
-    if (window >= 7)
-        return fail(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3 and 5");
+    if (window >= 9)
+        return fail(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3, 5 and 7");
     if (!(tau > 0.0f) || !(tau < 3.0e38f)) return fail(ODF_EINVAL, "tau must be positive and finite");
     return ODF_OK;
 }
@@ -283,7 +283,7 @@ int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kin
 }
 
 size_t odf_softmin_bwd_workspace(int B, int M, int N, int window, int kind) {
-    if (B < 1 || M < 1 || N < 1 || (window != 3 && window != 5) ||
+    if (B < 1 || M < 1 || N < 1 || (window != 3 && window != 5 && window != 7) ||
         (kind != ODF_BVDF && kind != ODF_DDF))
         return 0;
     return odf::softmin_workspace_bytes(window, kind, B, M, N);

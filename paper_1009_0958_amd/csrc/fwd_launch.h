@@ -113,7 +113,7 @@ static hipError_t launch_w(int kind, int dist, bool u8, bool agg, int cfg, const
                            hipStream_t s) {
     if (kind == kBVDF) return launch_wk<W, kBVDF>(dist, u8, agg, cfg, prm, s);
     if (kind == kDDF) return launch_wk<W, kDDF>(dist, u8, agg, cfg, prm, s);
-    if constexpr (W >= 7) return hipErrorInvalidValue;  // no 7x7 or 9x9 centre-weighted filters
+    if constexpr (W >= 9) return hipErrorInvalidValue;  // no 9x9 centre-weighted filters
     else if (kind == kACW) return launch_wk<W, kACW>(dist, u8, agg, cfg, prm, s);
     else if (kind == kCW) return launch_wk<W, kCW>(dist, u8, agg, cfg, prm, s);
     else return launch_wk<W, kCWV>(dist, u8, agg, cfg, prm, s);

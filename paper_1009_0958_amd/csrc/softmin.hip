@@ -31,13 +31,21 @@ namespace odf {
 // sweeps, which frees the registers for 1024-thread tiles.  The backward uses
 // 512-thread tiles; it parks the angle sums A during the L2 sweep as well and
 // recomputes Omega from A and D where it needs it, so that (with 128 VGPRs) two
-// workgroups share a compute unit.
+// workgroups share a compute unit.  7x7 keeps 512-thread tiles both ways (26 x 10
+// windows): its 49 weights per window fill ~95 KB of LDS, one workgroup per
+// compute unit, so the backward may take 256 VGPRs for its 2 x 49 aggregates.
 template <int W, int KIND, bool BWD>
 struct SoftTile {
     static constexpr int EXT_W = 32;
     static constexpr int EXT_H = (W == 5 && !BWD) ? 32 : 16;
     static constexpr int NT = EXT_W * EXT_H;
 };
+
+template <int W, bool BWD>
+constexpr int soft_waves_per_eu() {
+    if (!BWD) return 1;
+    return W == 7 ? 2 : 4;
+}
 
 __device__ __forceinline__ float key_value(uint32_t k) {
     uint32_t bits = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
@@ -229,7 +237,7 @@ __device__ __forceinline__ void propagate_pairs(const float (&gr)[W * W],
 
 template <int W, int KIND, bool BWD>
 __global__ void __launch_bounds__((SoftTile<W, KIND, BWD>::NT))
-    __attribute__((amdgpu_waves_per_eu(BWD ? 4 : 1))) softmin_kernel(SoftParams prm) {
+    __attribute__((amdgpu_waves_per_eu(soft_waves_per_eu<W, BWD>()))) softmin_kernel(SoftParams prm) {
     constexpr int EXT_W = SoftTile<W, KIND, BWD>::EXT_W, EXT_H = SoftTile<W, KIND, BWD>::EXT_H;
     using Gm = FwdGeom<W, EXT_W, EXT_H>;
     constexpr int H = Gm::H, NW = Gm::NW, G = Gm::G, TW = Gm::TW, TH = Gm::TH, NT = Gm::NT;
@@ -572,9 +580,12 @@ size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
     if (window == 3) {
         if (kind == kBVDF) soft_grid<3, kBVDF, true>(prm, tx, ty, nt);
         else soft_grid<3, kDDF, true>(prm, tx, ty, nt);
-    } else {
+    } else if (window == 5) {
         if (kind == kBVDF) soft_grid<5, kBVDF, true>(prm, tx, ty, nt);
         else soft_grid<5, kDDF, true>(prm, tx, ty, nt);
+    } else {
+        if (kind == kBVDF) soft_grid<7, kBVDF, true>(prm, tx, ty, nt);
+        else soft_grid<7, kDDF, true>(prm, tx, ty, nt);
     }
     return (size_t)B * tx * ty * nt * 3 * sizeof(float);
 }
@@ -582,7 +593,9 @@ size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
 hipError_t launch_softmin(int window, int kind, bool bwd, const SoftParams& prm, hipStream_t s) {
     if (window == 3)
         return kind == kBVDF ? launch_soft_t<3, kBVDF>(bwd, prm, s) : launch_soft_t<3, kDDF>(bwd, prm, s);
-    return kind == kBVDF ? launch_soft_t<5, kBVDF>(bwd, prm, s) : launch_soft_t<5, kDDF>(bwd, prm, s);
+    if (window == 5)
+        return kind == kBVDF ? launch_soft_t<5, kBVDF>(bwd, prm, s) : launch_soft_t<5, kDDF>(bwd, prm, s);
+    return kind == kBVDF ? launch_soft_t<7, kBVDF>(bwd, prm, s) : launch_soft_t<7, kDDF>(bwd, prm, s);
 }
 
 }  // namespace odf

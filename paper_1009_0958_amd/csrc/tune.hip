@@ -134,7 +134,7 @@ namespace {
 bool valid_class(int window, int kind, int dist) {
     if (window != 3 && window != 5 && window != 7 && window != 9) return false;
     if (kind < ODF_BVDF || kind > ODF_CWDDF) return false;
-    if (window >= 7 && kind != ODF_BVDF && kind != ODF_DDF) return false;
+    if (window == 9 && kind != ODF_BVDF && kind != ODF_DDF) return false;
     return dist >= 0 && dist <= 2;
 }
 

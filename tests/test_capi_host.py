@@ -158,13 +158,13 @@ def test_batch_and_tune_argument_errors():
 @pytest.mark.parametrize("args,code,text", [
     ((None, 1, 8, 8, 3, 0, 4, 2, 10.8, FAKE2), odf.EINVAL, "img"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 2, 10.8, None), odf.EINVAL, "out"),
-    ((FAKE, 1, 8, 8, 7, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 9, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 3, 3, 4, 2, 10.8, FAKE2), odf.EINVAL, "dist"),
     ((FAKE, 1, 8, 8, 3, 1, 7, 2, 10.8, FAKE2), odf.EINVAL, "q"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 0, 10.8, FAKE2), odf.EINVAL, "lambda"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 4, 10.8, FAKE2), odf.EINVAL, "lambda"),
     ((FAKE, 1, 8, 8, 5, 0, 4, 12, 10.8, FAKE2), odf.EINVAL, "lambda"),
+    ((FAKE, 1, 8, 8, 7, 0, 4, 24, 10.8, FAKE2), odf.EINVAL, "lambda"),  # 7x7: lambda <= 23
     ((FAKE, 1, 8, 8, 3, 0, 4, 2, float("nan"), FAKE2), odf.EINVAL, "NaN"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 2, 10.8, FAKE), odf.EINVAL, "overlaps"),
 ])
@@ -183,7 +183,10 @@ def test_acwddf_tuning_table():
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 3) == odf.OK
     assert L.odf_tune_set(5, odf.ACWDDF, 0, 1, 2) == odf.OK
     assert L.odf_tune_get(3, 5, 0, 1) == odf.EINVAL  # kinds end at ODF_CWDDF
-    assert L.odf_tune_get(7, odf.ACWDDF, 0, 1) == odf.EINVAL  # no 7x7 ACWDDF
+    assert L.odf_tune_get(7, odf.ACWDDF, 0, 1) == 2
+    assert L.odf_tune_set(7, odf.ACWDDF, 0, 1, 1) == odf.EINVAL  # 512-thread shapes only
+    assert L.odf_tune_set(7, odf.ACWDDF, 0, 1, 4) == odf.EINVAL  # no strip form
+    assert L.odf_tune_get(9, odf.ACWDDF, 0, 1) == odf.EINVAL  # no 9x9 ACWDDF
     assert L.odf_tune_get(7, odf.DDF, 0, 1) == 2
     assert L.odf_tune_set(7, odf.DDF, 0, 1, 1) == odf.EINVAL  # 512-thread shapes only
 
@@ -210,11 +213,15 @@ def test_noise_and_quality_reject():
     assert L.odf_quality_u8(None, FAKE2, 1, 4, 4, W, W, W, 64, None) == odf.EINVAL
 
 
-def test_window7_limits():
+def test_softmin_window_limits():
+    """The softmin takes windows 3, 5 and 7; its 7x7 backward workspace holds
+    one 32 x 16 extended tile (26 x 10 windows) of float32 triples per tile."""
     L = odf.lib()
-    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 7, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 9, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert "softmin" in odf.last_error()
-    assert L.odf_softmin_bwd_workspace(1, 8, 8, 7, 1) == 0
+    assert L.odf_softmin_bwd_workspace(1, 8, 8, 9, 1) == 0
+    tiles = 2 * -(-100 // 26) * -(-45 // 10)
+    assert L.odf_softmin_bwd_workspace(2, 45, 100, 7, 1) == tiles * 512 * 3 * 4
 
 
 def test_softmin_f64_rejects():
@@ -223,7 +230,7 @@ def test_softmin_f64_rejects():
     fwd = lambda *a: L.odf_softmin_fwd_f64(*a[:6], D(a[6]), D(a[7]), a[8], None)  # noqa: E731
     assert fwd(None, 1, 4, 4, 3, 1, 0.25, 0.1, FAKE2) == odf.EINVAL and "x" in odf.last_error()
     assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.1, None) == odf.EINVAL and "y" in odf.last_error()
-    assert fwd(FAKE, 1, 4, 4, 7, 1, 0.25, 0.1, FAKE2) == odf.EUNSUPPORTED
+    assert fwd(FAKE, 1, 4, 4, 9, 1, 0.25, 0.1, FAKE2) == odf.EUNSUPPORTED
     assert fwd(FAKE, 1, 4, 4, 3, 1, 1.5, 0.1, FAKE2) == odf.EINVAL and "p" in odf.last_error()
     assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.0, FAKE2) == odf.EINVAL and "tau" in odf.last_error()
     assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, float("inf"), FAKE2) == odf.EINVAL
@@ -232,7 +239,8 @@ def test_softmin_f64_rejects():
     assert "overlaps" in odf.last_error()
     need = L.odf_softmin_bwd_f64_workspace(1, 4, 4, 5)
     assert need == 4 * 4 * 25 * 3 * 8
-    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 7) == 0
+    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 7) == 4 * 4 * 49 * 3 * 8
+    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 9) == 0
     F3 = ctypes.c_void_p(0x7F0000200000)
     WS = ctypes.c_void_p(0x7F0000300000)
     bwd = lambda ws, nbytes, w=5: L.odf_softmin_bwd_f64(  # noqa: E731
@@ -254,7 +262,8 @@ def test_cw_filter_rejects():
     assert f(5, odf.CWDDF, 14) == odf.EINVAL
     assert f(3, odf.DDF, 1) == odf.EINVAL and "kind" in odf.last_error()
     assert f(3, odf.ACWDDF, 1) == odf.EINVAL
-    assert f(7, odf.CWVMF, 1) == odf.EUNSUPPORTED
+    assert f(9, odf.CWVMF, 1) == odf.EUNSUPPORTED
+    assert f(7, odf.CWDDF, 26) == odf.EINVAL and "level" in odf.last_error()  # 7x7: k <= 25
     assert f(3, odf.CWDDF, 1, dist=3) == odf.EINVAL and "dist" in odf.last_error()
     assert f(3, odf.CWVMF, 1, out=None) == odf.EINVAL and "out" in odf.last_error()
     assert f(3, odf.CWVMF, 1, out=FAKE) == odf.EINVAL and "overlaps" in odf.last_error()
@@ -324,12 +333,14 @@ def test_allocation_failure_reports_enomem(monkeypatch):
 
 def test_tuning_table_has_centre_weighted_entries():
     """CWVMF^k and CWDDF^k have tile table entries of their own (5x5: the
-    512-thread shapes only; no 7x7); CWVMF, which has no angular term, keeps
-    one entry for every dist."""
+    512-thread shapes only, as at 7x7; no 9x9); CWVMF, which has no angular
+    term, keeps one entry for every dist."""
     L = odf._batch_lib()
     for kind in (odf.CWVMF, odf.CWDDF):
         assert odf.tune_get(3, kind, odf.EXACT) == 2
-        assert L.odf_tune_get(7, kind, odf.EXACT, 1) == odf.EINVAL
+        assert L.odf_tune_get(7, kind, odf.EXACT, 1) == 2
+        assert L.odf_tune_set(7, kind, odf.EXACT, 1, 0) == odf.EINVAL
+        assert L.odf_tune_get(9, kind, odf.EXACT, 1) == odf.EINVAL
         assert L.odf_tune_set(5, kind, odf.EXACT, 1, 0) == odf.EINVAL  # 1024 threads
     odf.tune_set(3, odf.CWDDF, odf.RGB, True, 1)
     assert odf.tune_get(3, odf.CWDDF, odf.RGB) == 1
@@ -349,7 +360,7 @@ def test_noalloc_softmin_rejects_before_launch():
     assert "static scratch" in odf.last_error()
     assert f(FAKE, None, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EINVAL
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.0, FAKE2, None) == odf.EINVAL  # tau
-    assert f(FAKE, FAKE2, 1, 8, 8, 7, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert f(FAKE, FAKE2, 1, 8, 8, 9, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE, None) == odf.EINVAL  # dx = x
     assert "overlaps" in odf.last_error()
 

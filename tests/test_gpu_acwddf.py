@@ -38,7 +38,8 @@ def run_and_check(img, window, dist, q=4, lam=2, T=10.8, max_ambiguous=0.01):
 
 
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
-@pytest.mark.parametrize("window,lam", [(3, 1), (3, 2), (3, 3), (5, 2), (5, 11)])
+@pytest.mark.parametrize("window,lam", [(3, 1), (3, 2), (3, 3), (5, 2), (5, 11), (7, 2),
+                                        (7, 23)])
 def test_ragged_tiles(window, lam, dist):
     img = synth.image_corr(70, 97, 0.20, key=window * 10 + lam)
     n_mis, n_amb, n = run_and_check(img, window, dist, lam=lam)
@@ -46,7 +47,7 @@ def test_ragged_tiles(window, lam, dist):
 
 
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 def test_sparse_zero_pixels(window, dist):
     # zero pixels among nonzero ones, also on tile boundaries: their direction is
     # (1,1,1) and their L2 terms come from the other pixel's norm
@@ -73,7 +74,7 @@ def test_thresholds(T):
     run_and_check(img, 3, EXACT, T=T)
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
 def test_negative_threshold_is_ddf_product_bitwise(window, dist):
     """T < 0: every window switches to the eq. (3) selection, which the
@@ -86,20 +87,20 @@ def test_negative_threshold_is_ddf_product_bitwise(window, dist):
     assert bool((i_inf == (window * window - 1) // 2).all())
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 def test_float_inputs(window):
     img = synth.float_batch(2, 45, 70, 0.1, key=window) * 255.0
     run_and_check(img.astype(np.float32), window, EXACT)
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 40), (37, 1), (2, 2), (5, 5)])
 def test_degenerate_sizes(window, shape):
     img = synth.image_corr(shape[0], shape[1], 0.3, key=11)
     run_and_check(img, window, EXACT)
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 def test_tile_shapes_identical(window):
     x = _gpu(synth.image_corr(150, 170, 0.2, key=13))
     saved = odf.tune_get(window, odf.ACWDDF, EXACT, True)
@@ -109,7 +110,7 @@ def test_tile_shapes_identical(window):
             try:
                 odf.tune_set(window, odf.ACWDDF, EXACT, True, cfg)
             except odf.ODFError:
-                assert window == 5 and cfg in (0, 1)
+                assert window in (5, 7) and cfg in (0, 1)
                 continue
             out, idx = odf.acwddf(x, window, EXACT)
             if ref is None:

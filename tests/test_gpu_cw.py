@@ -29,18 +29,21 @@ def _run(img, window, kind, level, dist, q=4):
     return n_mis, n
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("kind,dists", [(odf.CWVMF, (EXACT,)), (odf.CWDDF, (EXACT, MINIMAX, RGB))])
 def test_all_levels_ragged(window, kind, dists):
+    """Every level at 3x3 and 5x5; at 7x7 (25 levels) the two ends, the middle
+    and two between."""
     img = synth.image_corr(61, 83, 0.2, key=30 + window)
     d = (window * window + 1) // 2
-    for level in range(1, d + 1):
+    levels = range(1, d + 1) if window < 7 else (1, 2, 7, 13, d)
+    for level in levels:
         for dist in dists:
             n_mis, n = _run(img, window, kind, level, dist)
             print("  mismatch %d of %d" % (n_mis, n), flush=True)
 
 
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 def test_float_and_edges(window):
     d = (window * window + 1) // 2
     for shape in ((1, 1), (1, 9), (7, 1), (29, 33)):
@@ -52,7 +55,7 @@ def test_float_and_edges(window):
 
 
 @pytest.mark.parametrize("dist", [EXACT, MINIMAX, RGB])
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 def test_batch_with_zero_pixels(window, dist):
     """Three images in one call, several tiles each with ragged edges, 5 % zero
     pixels; uint8 and float32 (whose layout keeps the raw values beside the
@@ -72,7 +75,7 @@ def test_level_1_keeps_every_pixel():
     inequality), so the output equals the input."""
     img = synth.image_uncorr(40, 50, 0.3, key=8)
     x = torch.from_numpy(img).to(DEV)
-    for window in (3, 5):
+    for window in (3, 5, 7):
         for kind in (odf.CWVMF, odf.CWDDF):
             out, _ = odf.cw_filter(x, window, kind, 1, RGB)
             assert torch.equal(out, x)
@@ -83,7 +86,7 @@ def test_level_d_matches_the_plain_filters():
     as DDF p = 1/2 (the product of eq. 3), up to near-ties."""
     img = synth.image_corr(50, 70, 0.2, key=12)
     x = torch.from_numpy(img).to(DEV)
-    for window in (3, 5):
+    for window in (3, 5, 7):
         d = (window * window + 1) // 2
         _, iv = odf.cw_filter(x, window, odf.CWVMF, d, EXACT)
         _, i1 = odf.filter(x, window, odf.DDF, 1.0, EXACT)

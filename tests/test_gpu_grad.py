@@ -81,7 +81,8 @@ def _objectives(x, window, kind, p):
 
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
-                                           (5, BVDF, 0.0), (5, DDF, 0.5)])
+                                           (5, BVDF, 0.0), (5, DDF, 0.5), (7, DDF, 0.25),
+                                           (7, BVDF, 0.0)])
 @pytest.mark.parametrize("tau", [0.1, 0.01])
 def test_softmin_forward_matches_oracle(window, kind, p, tau):
     print("case: softmin fwd w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
@@ -94,7 +95,8 @@ def test_softmin_forward_matches_oracle(window, kind, p, tau):
 
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
-                                           (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0)])
+                                           (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0),
+                                           (7, DDF, 0.25), (7, BVDF, 0.0), (7, DDF, 1.0)])
 @pytest.mark.parametrize("tau", [0.1, 0.01])
 def test_softmin_backward_matches_oracle(window, kind, p, tau):
     print("case: softmin bwd w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
@@ -123,6 +125,22 @@ def test_softmin_autograd_and_edge_shapes():
         yr = oracle.softmin_fwd(x, 5, DDF, 0.25, 0.1)
         bnd = soft_bounds(x, _objectives(x, 5, DDF, 0.25), 5, 0.1, max(np.abs(ref).max(), 1e-6))
         check_soft(y.detach().cpu().numpy(), yr, xt.grad.cpu().numpy(), ref, bnd, str(shape))
+
+
+def test_softmin_7x7_edge_shapes_and_tiles():
+    """7x7 on shapes smaller than one window, thin ones, and several 26 x 10
+    tiles with ragged edges both ways (the combine pass sums up to four tiles
+    per pixel), float32 against the oracle's budget."""
+    for shape in ((1, 1, 1), (1, 3, 11), (1, 23, 2), (2, 31, 57)):
+        print("case: softmin 7x7 shape=%s" % (shape,), flush=True)
+        x = synth.float_batch(*shape, 0.2, key=17)
+        dy = np.random.default_rng(17).standard_normal(x.shape).astype(np.float32)
+        y = odf.softmin_forward(_gpu(x), 7, DDF, 0.25, 0.1).cpu().numpy()
+        dx = odf.softmin_backward(_gpu(x), _gpu(dy), 7, DDF, 0.25, 0.1).cpu().numpy()
+        yr = oracle.softmin_fwd(x, 7, DDF, 0.25, 0.1)
+        ref = oracle.softmin_bwd(x, dy.astype(np.float64), 7, DDF, 0.25, 0.1)
+        bnd = soft_bounds(x, _objectives(x, 7, DDF, 0.25), 7, 0.1, max(np.abs(ref).max(), 1e-6))
+        check_soft(y, yr, dx, ref, bnd, "7x7 %s" % (shape,))
 
 
 def test_softmin_small_tau_is_hard_selection():
@@ -165,7 +183,8 @@ def test_full_size_batch_crops():
 # ------------------------------------------------------------------ binary64 twins
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
-                                           (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0)])
+                                           (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0),
+                                           (7, DDF, 0.25), (7, BVDF, 0.0)])
 @pytest.mark.parametrize("tau", [0.1, 0.01])
 def test_softmin_f64_matches_oracle(window, kind, p, tau):
     """The binary64 twins against the binary64 oracle: both evaluate the same
@@ -192,7 +211,7 @@ def test_softmin_f64_edge_shapes_and_zero_pixels():
         x = synth.float_batch(*shape, 0.2, key=5).astype(np.float64)
         x[..., ::3, ::2, :] = 0.0
         dy = np.random.default_rng(1).standard_normal(x.shape)
-        for window in (3, 5):
+        for window in (3, 5, 7):
             y = odf.softmin_forward(_gpu(x), window, DDF, 0.25, 0.1).cpu().numpy()
             assert np.abs(y - oracle.softmin_fwd(x, window, DDF, 0.25, 0.1)).max() <= 1e-12
             dx = odf.softmin_backward(_gpu(x), _gpu(dy), window, DDF, 0.25, 0.1).cpu().numpy()
@@ -208,7 +227,8 @@ def test_softmin_f64_gradcheck_on_gpu():
     zero pixel are skipped: there the direction jumps to the constant (1, 1, 1),
     so the filter is not differentiable."""
     small = _gpu(synth.float_batch(1, 6, 7, 0.1, key=9).astype(np.float64)).requires_grad_(True)
-    for window, kind, p in ((3, DDF, 0.25), (5, DDF, 0.25), (5, BVDF, 0.0)):
+    for window, kind, p in ((3, DDF, 0.25), (5, DDF, 0.25), (5, BVDF, 0.0), (7, DDF, 0.25)):
+        print("case: gradcheck 6 x 7 w=%d kind=%d" % (window, kind), flush=True)
         fn = lambda t: odf.softmin_filter(t, window, kind, p, 0.1)  # noqa: E731
         assert torch.autograd.gradcheck(fn, (small,), eps=1e-6, atol=1e-7, rtol=1e-5)
     x = synth.float_batch(16, 512, 512, 0.1)

@@ -57,7 +57,10 @@
 #endif
 
 enum { OK_BVDF = 0, OK_DDF = 1 };
-enum { NMAX = 81 }; /* members of the largest window (9 x 9) */
+/* members of the largest window: 15 x 15 for the filter and its hard backward
+ * (the member index is stored in a byte), 9 x 9 for the softmin relaxation,
+ * ACWDDF and the centre-weighted filters */
+enum { NMAX = 225, NMAX9 = 81 };
 enum { OD_EXACT = 0, OD_MINIMAX = 1, OD_RGB = 2 };
 
 /* Table 1: minimax polynomial coefficients a_0..a_4 as printed, rows q = 2,3,4. */
@@ -241,7 +244,7 @@ static void filter_one(const double *img, int M, int N, int w, int kind, double 
 
 static int check_args(int B, int M, int N, int w, int kind, double p, int dist, int q) {
     if (B < 1 || M < 1 || N < 1) return -1;
-    if (w != 3 && w != 5 && w != 7 && w != 9) return -1;
+    if (w < 3 || w > 15 || w % 2 == 0) return -1; /* odd sqrt(n) x sqrt(n) windows */
     if (kind != OK_BVDF && kind != OK_DDF) return -1;
     if (dist < OD_EXACT || dist > OD_RGB) return -1;
     if (dist == OD_MINIMAX && (q < 2 || q > 4)) return -1;
@@ -321,7 +324,7 @@ int oracle_filter_at(const double *img, int B, int M, int N, int w, int kind, do
  * Output pixels are visited in raster order. */
 int oracle_backward_hard(const uint8_t *idx, const double *dy, int B, int M, int N, int w,
                          double *dx) {
-    if (B < 1 || M < 1 || N < 1 || (w != 3 && w != 5 && w != 7 && w != 9) || !idx || !dy || !dx)
+    if (B < 1 || M < 1 || N < 1 || w < 3 || w > 15 || w % 2 == 0 || !idx || !dy || !dx)
         return -1;
     int h = (w - 1) / 2, n = w * w;
     int64_t mn = (int64_t)M * N;
@@ -382,14 +385,15 @@ static void softmin_window(const double *base, int M, int N, int w, int kind, do
 
 int oracle_softmin_fwd(const double *img, int B, int M, int N, int w, int kind, double p,
                        double tau, double *y, double *pi_out, int nthreads) {
-    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || !(tau > 0.0) || !img || !y) return -1;
+    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || w > 9 || !(tau > 0.0) || !img || !y)
+        return -1;
     set_threads(nthreads);
     int64_t mn = (int64_t)M * N, total = mn * B;
     int n = w * w;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t pix = 0; pix < total; ++pix) {
-        int64_t src[NMAX];
-        double A[NMAX], D[NMAX], Om[NMAX], pi[NMAX];
+        int64_t src[NMAX9];
+        double A[NMAX9], D[NMAX9], Om[NMAX9], pi[NMAX9];
         int64_t b = pix / mn, rc = pix % mn;
         softmin_window(img + b * mn * 3, M, N, w, kind, p, tau, (int)(rc / N), (int)(rc % N), src,
                        A, D, Om, pi, y + 3 * pix);
@@ -444,7 +448,8 @@ static void objective_grad(double A, double D, double Om, int kind, double p, do
  * processed in parallel; inside an image, output pixels in raster order. */
 int oracle_softmin_bwd(const double *img, const double *dy, int B, int M, int N, int w, int kind,
                        double p, double tau, double *dx, int nthreads) {
-    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || !(tau > 0.0) || !img || !dy || !dx)
+    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || w > 9 || !(tau > 0.0) || !img || !dy ||
+        !dx)
         return -1;
     set_threads(nthreads);
     int64_t mn = (int64_t)M * N;
@@ -455,8 +460,8 @@ int oracle_softmin_bwd(const double *img, const double *dy, int B, int M, int N,
         const double *base = img + (int64_t)b * mn * 3;
         double *gx = dx + (int64_t)b * mn * 3;
         for (int64_t rc = 0; rc < mn; ++rc) {
-            int64_t src[NMAX];
-            double A[NMAX], D[NMAX], Om[NMAX], pi[NMAX], y[3];
+            int64_t src[NMAX9];
+            double A[NMAX9], D[NMAX9], Om[NMAX9], pi[NMAX9], y[3];
             softmin_window(base, M, N, w, kind, p, tau, (int)(rc / N), (int)(rc % N), src, A, D,
                            Om, pi, y);
             const double *g = dy + 3 * ((int64_t)b * mn + rc);
@@ -522,8 +527,8 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
     int64_t b = pix / mn, rc = pix % mn;
     int r = (int)(rc / N), c = (int)(rc % N);
     int n = w * w, d = (n - 1) / 2;
-    int64_t src[NMAX];
-    double th[NMAX][NMAX], l2[NMAX][NMAX], Om[4][NMAX];
+    int64_t src[NMAX9];
+    double th[NMAX9][NMAX9], l2[NMAX9][NMAX9], Om[4][NMAX9];
     const double *base = img + b * mn * 3;
     window_members(M, N, w, r, c, src);
     for (int u = 0; u < n; ++u)
@@ -565,7 +570,7 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
 }
 
 static int check_acw(int B, int M, int N, int w, int dist, int q, int lambda, double T) {
-    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q)) return -1;
+    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || w > 9) return -1;
     int dd = (w * w + 1) / 2;
     if (lambda < 1 || lambda > dd - 2 || T != T) return -1;
     return 0;
@@ -616,8 +621,8 @@ static void cw_one(const double *img, int M, int N, int w, int vmf, int dist, in
     int64_t b = pix / mn, rc = pix % mn;
     int r = (int)(rc / N), c = (int)(rc % N);
     int n = w * w, d = (n - 1) / 2;
-    int64_t src[NMAX];
-    double Om[NMAX];
+    int64_t src[NMAX9];
+    double Om[NMAX9];
     const double *base = img + b * mn * 3;
     window_members(M, N, w, r, c, src);
     for (int u = 0; u < n; ++u) {
@@ -643,7 +648,7 @@ static void cw_one(const double *img, int M, int N, int w, int vmf, int dist, in
 /* CWVMF^k (vmf = 1) or CWDDF^k (vmf = 0) over B images; out, idx, obj nullable. */
 int oracle_cwfilter(const double *img, int B, int M, int N, int w, int vmf, int dist, int q,
                     int level, double *out, uint8_t *idx, double *obj, int nthreads) {
-    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || !img) return -1;
+    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || w > 9 || !img) return -1;
     if (level < 1 || level > (w * w + 1) / 2 || (vmf != 0 && vmf != 1)) return -1;
     set_threads(nthreads);
     int64_t total = (int64_t)B * M * N;

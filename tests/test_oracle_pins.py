@@ -206,11 +206,27 @@ def _mp_chroma(a, b):
 
 
 def _mp_filter(img, w, kind, p, dist):
-    """50-digit brute force of eqs. 1-3 over every window (replicated border)."""
+    """50-digit brute force of eqs. 1-3 over every window (replicated border).
+    The two pair terms of a pair of colours are evaluated once and reused
+    (windows larger than the image repeat its few colours many times)."""
     M, N, _ = img.shape
     h = w // 2
     A = np.empty((M, N, w * w))
     D = np.empty((M, N, w * w))
+    memo = {}
+
+    def terms(xu, xv):
+        key = (tuple(int(v) for v in xu), tuple(int(v) for v in xv))
+        if key not in memo:
+            if dist == EXACT:
+                a = _mp_angle(xu, xv)
+            else:
+                bb = _mp_chroma(xu, xv)
+                a = (mpmath.mpf("1.436437") * bb + mpmath.mpf("0.027664")) if kind == DDF else bb
+            d = mpmath.sqrt(sum((mpmath.mpf(int(x)) - int(y)) ** 2 for x, y in zip(xu, xv)))
+            memo[key] = (a, d)
+        return memo[key]
+
     for r in range(M):
         for c in range(N):
             mem = [img[min(max(r + dy, 0), M - 1), min(max(c + dx, 0), N - 1)]
@@ -219,14 +235,9 @@ def _mp_filter(img, w, kind, p, dist):
                 sa = mpmath.mpf(0)
                 sd = mpmath.mpf(0)
                 for xv in mem:
-                    if dist == EXACT:
-                        sa += _mp_angle(xu, xv)
-                    else:
-                        bb = _mp_chroma(xu, xv)
-                        sa += (mpmath.mpf("1.436437") * bb + mpmath.mpf("0.027664")) \
-                            if kind == DDF else bb
-                    sd += mpmath.sqrt(sum((mpmath.mpf(int(x)) - int(y)) ** 2
-                                          for x, y in zip(xu, xv)))
+                    a, d = terms(xu, xv)
+                    sa += a
+                    sd += d
                 A[r, c, u] = float(sa)
                 D[r, c, u] = float(sd)
     return A, D
@@ -235,9 +246,15 @@ def _mp_filter(img, w, kind, p, dist):
 @pytest.mark.parametrize("w,kind,p,dist", [
     (w, kind, p, dist) for w in (3, 5) for kind, p in ((BVDF, 0.0), (DDF, 0.25), (DDF, 0.5))
     for dist in (EXACT, RGB)] + [(7, BVDF, 0.0, EXACT), (7, DDF, 0.25, EXACT),
-                                 (9, BVDF, 0.0, EXACT), (9, DDF, 0.25, RGB)])
+                                 (9, BVDF, 0.0, EXACT), (9, DDF, 0.25, RGB),
+                                 (11, BVDF, 0.0, EXACT), (11, DDF, 0.25, EXACT),
+                                 (13, DDF, 0.5, RGB), (15, BVDF, 0.0, RGB),
+                                 (15, DDF, 0.25, EXACT)])
 def test_filter_vs_50_digit_bruteforce(w, kind, p, dist):
-    img = _tiny_image(w * 10 + kind, {3: 6, 5: 5, 7: 4, 9: 4}[w], 5)
+    """Every window size the filter takes, 3 x 3 to 15 x 15: at 11 x 11 and
+    above on images smaller than the window, so that most members are
+    replicated border pixels and many aggregates tie exactly."""
+    img = _tiny_image(w * 10 + kind, {3: 6, 5: 5, 7: 4, 9: 4}.get(w, 4), 5)
     out, idx, A, D, O = oracle.filter(img, w, kind, p, dist, aggregates=True)
     mA, mD = _mp_filter(img, w, kind, p, dist)
     assert np.allclose(A, mA, rtol=1e-13, atol=1e-13)
@@ -261,7 +278,7 @@ def test_filter_vs_50_digit_bruteforce(w, kind, p, dist):
 
 
 @pytest.mark.parametrize("q", [2, 3, 4])
-@pytest.mark.parametrize("w", [3, 5, 7, 9])
+@pytest.mark.parametrize("w", [3, 5, 7, 9, 11, 15])
 def test_minimax_aggregates_within_table1_bound(q, w):
     img = _tiny_image(70 + q, 8, 8)
     _, _, Ae, _, _ = oracle.filter(img, w, BVDF, 0, EXACT, aggregates=True)
@@ -461,7 +478,8 @@ def test_canonical_direction_keeps_scaled_images():
 # ------------------------------------------------------------ hard backward
 
 @pytest.mark.parametrize("w,kind,p,dist", [(3, DDF, 0.25, EXACT), (5, BVDF, 0.0, MINIMAX),
-                                           (7, DDF, 0.5, RGB), (5, DDF, 0.3, EXACT)])
+                                           (7, DDF, 0.5, RGB), (5, DDF, 0.3, EXACT),
+                                           (13, DDF, 0.25, MINIMAX)])
 def test_filter_at_matches_full_filter(w, kind, p, dist):
     """filter_at (the sampled form the full-size parity tests and the benchmark's
     mismatch counts use) returns, at each listed flat position (b*M + r)*N + c,
@@ -489,7 +507,7 @@ def test_filter_at_matches_full_filter(w, kind, p, dist):
 def test_backward_hard_routes_and_conserves():
     rng = np.random.default_rng(2)
     img = _tiny_image(13, 12, 10)
-    for w in (3, 5, 7, 9):
+    for w in (3, 5, 7, 9, 11, 15):
         _, idx = oracle.filter(img, w, DDF, 0.25, EXACT)
         dy = rng.standard_normal(img.shape)
         dx = oracle.backward_hard(idx, dy, w)
@@ -550,3 +568,24 @@ def test_softmin_limits():
     # tau -> infinity: the plain mean of the (replicated) window
     y = oracle.softmin_fwd(x, 3, DDF, 0.25, 1e9)
     assert np.allclose(y, _window_stack(x, 3).mean(2), rtol=0, atol=1e-8)
+
+
+def test_window_range():
+    """The filter and its hard backward take every odd window from 3 x 3 to
+    15 x 15 (the member index is a byte); the softmin relaxation stops at 9 x 9.
+    Even and larger windows are rejected."""
+    img = _tiny_image(3, 4, 5)
+    for w in (1, 2, 4, 10, 17):
+        with pytest.raises(ValueError):
+            oracle.filter(img, w, BVDF, 0.0, EXACT)
+        with pytest.raises(ValueError):
+            oracle.backward_hard(np.zeros((4, 5), np.uint8), np.zeros((4, 5, 3)), w)
+    x = img.astype(np.float64)
+    with pytest.raises(ValueError):
+        oracle.softmin_fwd(x, 11, DDF, 0.25, 0.1)
+    with pytest.raises(ValueError):
+        oracle.cwfilter(img, 11, True, EXACT, 4, 1)
+    # a constant image: every member ties, the lowest index wins
+    for w in (11, 13, 15):
+        out, idx = oracle.filter(np.full((5, 6, 3), 77, np.uint8), w, DDF, 0.25, EXACT)
+        assert np.all(idx == 0) and np.all(out == 77.0)

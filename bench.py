@@ -566,7 +566,8 @@ def mismatch_sample(B, M, N, k, seed):
 def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
     """7680 x 4320 frame (3x3 BVDF, 5x5, 7x7 and 9x9) and 64 x 1920 x 1080
     frames (5x5), correlated noise 0.15 (tile configs autotuned per class on a
-    frame of this size first, untimed).  With ``samples`` (a dict), the windows of 1 M seeded pixels
+    frame of this size first, untimed); 11x11 and 15x15 (the direct form) on
+    one 1920 x 1080 frame.  With ``samples`` (a dict), the windows of 1 M seeded pixels
     (5x5; 100 000 for 3x3 and 7x7, 20 000 for 9x9) and the GPU's index there are
     kept for the oracle check of the cpu_baseline leg."""
     forms = {}
@@ -608,17 +609,36 @@ def large_frame_forms(torch, odf, synth, dev, DIST, samples=None):
                     gidx = bi.reshape(-1)[torch.from_numpy(pix).to(dev)].cpu().numpy()
                     samples.setdefault("cases", []).append((name, key, w, kind, p, d, gidx))
         del big, bo, bi
+    # windows past 9x9 run the direct form (no configs; every pair term of a
+    # window evaluated, n^2 per pixel): one 1920 x 1080 frame, exact angle
+    img = torch.from_numpy(synth.image_corr(1080, 1920, 0.15, key=611)).to(dev)
+    o = torch.empty_like(img)
+    i = torch.empty((1080, 1920), dtype=torch.uint8, device=dev)
+    for w in (11, 15):
+        for kind, p in (("bvdf", 0.0), ("ddf", 0.25)):
+            kk = odf.BVDF if kind == "bvdf" else odf.DDF
+            ms = time_launches(torch, lambda: odf.filter(img, w, kk, p, odf.EXACT, 4, out=o, idx=i),
+                               3, warm=1)
+            # the cost model counts each unique pair once per pixel (what the
+            # tile kernels evaluate); the direct form evaluates w^4 per pixel
+            forms["%s%d_exact_1920x1080_direct" % (kind, w)] = {
+                "mpix_s": round(1920 * 1080 / (ms * 1e3), 1), "ms": round(ms, 3),
+                "pair_terms_per_px": w ** 4,
+                "pair_terms_per_s": float("%.4g" % (1920 * 1080 * w ** 4 / (ms * 1e-3))),
+                "unique_pair_model_frac": round(slots_per_pixel(w, kind, p, "exact") * 1920 * 1080
+                                                / (ms * 1e-3) / PEAK_SLOTS, 4)}
+    del img, o, i
     return forms
 
 
 def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
     """ACWDDF (lambda = 2, T = 10.8) on the 1024 x 1024 image and on a
-    7680 x 4320 frame (3x3 and 5x5), each pair term, configs tuned per size;
+    7680 x 4320 frame (3x3, 5x5 and 7x7), each pair term, configs tuned per size;
     the 1024 x 1024 3x3 index maps are kept for the oracle's mismatch count.
     Also CWVMF^2 and CWDDF^2 (exact) on the 1024 x 1024 image, tuned."""
     forms = {}
     big = torch.from_numpy(synth.image_corr(4320, 7680, 0.15, key=500)).to(dev)
-    for w in (3, 5):
+    for w in (3, 5, 7):
         for d in ("exact", "minimax", "rgb"):
             for tag, img in (("1024x1024", x1k), ("7680x4320", big)):
                 M, N = img.shape[:2]
@@ -640,7 +660,7 @@ def acwddf_forms(torch, odf, synth, dev, DIST, x1k, acw_idx):
     M, N = x1k.shape[:2]
     o = torch.empty_like(x1k)
     i = torch.empty((M, N), dtype=torch.uint8, device=dev)
-    for w in (3, 5):
+    for w in (3, 5, 7):
         for name, kind, d in (("cwvmf", odf.CWVMF, "rgb"), ("cwddf", odf.CWDDF, "exact")):
             best, _ = autotune(odf, w, kind, DIST[d], True, M, N, 5)
             ms = time_launches(torch, lambda: odf.cw_filter(x1k, w, kind, 2, DIST[d], 4, out=o,
@@ -792,8 +812,8 @@ def plain_softmin(torch, x, w, p, tau):
 
 def differentiable_forms(torch, odf, synth, dev):
     """16 x 512 x 512 float32, DDF 5x5 p = 0.25: hard fwd + one-hot bwd, and
-    softmin fwd + bwd at tau 0.01 and 0.1; a plain PyTorch softmin on 2 of the
-    images for comparison."""
+    softmin fwd + bwd at tau 0.01 and 0.1 (and 7x7 at tau 0.1); a plain PyTorch
+    softmin on 2 of the images for comparison."""
     forms = {}
     x = torch.from_numpy(synth.float_batch(16, 512, 512, 0.1)).to(dev)
     dy = torch.randn_like(x)
@@ -826,6 +846,19 @@ def differentiable_forms(torch, odf, synth, dev):
                                    / PEAK_SLOTS, 4),
             "bwd_valu_frac": round(softmin_slots_per_pixel(5, True) * npx / (ms_sb * 1e-3)
                                    / PEAK_SLOTS, 4)}
+    ws7 = torch.empty(odf.lib().odf_softmin_bwd_workspace(16, 512, 512, 7, odf.DDF),
+                      dtype=torch.uint8, device=dev)
+    ms_sf = time_launches(torch, lambda: odf.softmin_forward(x, 7, odf.DDF, 0.25, 0.1), 3)
+    ms_sb = time_launches(torch, lambda: odf.softmin_backward(x, dy, 7, odf.DDF, 0.25, 0.1,
+                                                              workspace=ws7), 3)
+    del ws7
+    forms["ddf7_f32_16x512x512_softmin_tau0.1"] = {
+        "fwd_ms": round(ms_sf, 3), "bwd_ms": round(ms_sb, 3),
+        "fwd_bwd_mpix_s": round(npx / ((ms_sf + ms_sb) * 1e3), 1),
+        "fwd_valu_frac": round(softmin_slots_per_pixel(7, False) * npx / (ms_sf * 1e-3)
+                               / PEAK_SLOTS, 4),
+        "bwd_valu_frac": round(softmin_slots_per_pixel(7, True) * npx / (ms_sb * 1e-3)
+                               / PEAK_SLOTS, 4)}
     # plain PyTorch on 2 images (its n^2 intermediates take several GB per image)
     xs = x[:2].clone().requires_grad_(True)
     g = dy[:2].contiguous()

@@ -86,16 +86,19 @@ const char* odf_last_error(void);
  *         window member.
  *   idx   B x M x N uint8 or NULL: the selected member index u in 0..n-1.
  *         Ties go to the lowest index.
- *   window 3, 5, 7 or 9; kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only, ignored by
- *         BVDF); dist ODF_EXACT / ODF_MINIMAX / ODF_RGB; q in {2, 3, 4} for
- *         ODF_MINIMAX (ignored otherwise).
+ *   window any odd size from 3 to 15 (n = window^2 <= 225, so that the index
+ *         fits a byte); kind ODF_BVDF / ODF_DDF; p in [0, 1] (DDF only,
+ *         ignored by BVDF); dist ODF_EXACT / ODF_MINIMAX / ODF_RGB; q in
+ *         {2, 3, 4} for ODF_MINIMAX (ignored otherwise).
+ * Windows 3 to 9 run the tile and strip kernels (configs of the tuning
+ * table); 11, 13 and 15 run a direct form with no configs: one workgroup per
+ * 8 x 8 block of windows, every pair term of a window evaluated by the member
+ * that needs it (the tile kernels' n aggregates per thread stop fitting the
+ * registers past 9 x 9, 81 members).
  * Zero pixels take the direction (1,1,1) in the angle and chromaticity terms.
  * Errors: ODF_EINVAL for null img/out, sizes < 1, out overlapping img, or a
- * parameter out of range; ODF_EUNSUPPORTED for window not in {3, 5, 7, 9}
- * (9 x 9 keeps 81 aggregates per thread: one tile shape and, for ODF_BVDF on
- * uint8, the strip form, about 250 VGPRs; 11 x 11 would need 121 and is not
- * offered);
- * ODF_EHIP if the launch fails.
+ * parameter out of range; ODF_EUNSUPPORTED for an even window or one outside
+ * 3 to 15; ODF_EHIP if the launch fails.
  */
 int odf_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, float p,
                   int dist, int q, uint8_t* out, uint8_t* idx, void* stream);
@@ -178,7 +181,7 @@ int odf_cw_filter_f32(const float* img, int B, int M, int N, int window, int kin
  *          written as 0 for BVDF).
  *   Omega  B x M x N x n float32 or NULL: the objective the argmin uses
  *          (A for BVDF; A^(1-p) D^p for DDF).
- * Errors as for odf_filter_u8.
+ * Errors as for odf_filter_u8; windows 3 to 9 only (ODF_EUNSUPPORTED above).
  */
 int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int window, int kind,
                        float p, int dist, int q, float* A, float* D, float* Omega, void* stream);
@@ -194,8 +197,8 @@ int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int wind
  *        An index entry >= window^2 (not produced by the filter) routes
  *        nothing: its dy(c) reaches no pixel.
  * The forward selection is not touched.  Errors: ODF_EINVAL for null
- * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for a window
- * other than 3, 5, 7 or 9.
+ * pointers, sizes, or dx overlapping dy/idx; ODF_EUNSUPPORTED for an even
+ * window or one outside 3 to 15.
  */
 int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int N, int window,
                           float* dx, void* stream);

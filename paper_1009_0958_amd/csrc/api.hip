@@ -62,8 +62,8 @@ int check_common(const void* img, int B, int M, int N, int window, int kind, flo
     if (B < 1 || M < 1 || N < 1) return fail(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
     if ((long long)B * M * N >= (1ll << 31))
         return fail(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
-    if (window != 3 && window != 5 && window != 7 && window != 9)
-        return fail(ODF_EUNSUPPORTED, "window %d not supported (3, 5, 7 or 9)", window);
+    if (window < 3 || window > 15 || window % 2 == 0)
+        return fail(ODF_EUNSUPPORTED, "window %d not supported (odd, 3 to 15)", window);
     if (kind != ODF_BVDF && kind != ODF_DDF) return fail(ODF_EINVAL, "kind %d out of range", kind);
     if (dist < ODF_EXACT || dist > ODF_RGB) return fail(ODF_EINVAL, "dist %d out of range", dist);
     if (dist == ODF_MINIMAX && (q < 2 || q > 4))
@@ -117,7 +117,8 @@ int filter_any(const void* img, bool u8, int B, int M, int N, int window, int ki
     odf::FwdParams prm = make_params(img, B, M, N, kind == ODF_DDF ? p : 0.0f, dist, q);
     prm.out = out;
     prm.idx = idx;
-    const int cfg = odf::tuned_config(window, kind, dist, u8);
+    // windows past 9x9 run the direct form, which has no tile configs
+    const int cfg = window <= 9 ? odf::tuned_config(window, kind, dist, u8) : 0;
     hipError_t e = odf::launch_forward(window, kind, dist, u8, false, cfg, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -223,6 +224,7 @@ int odf_aggregates_f32(const void* img, int is_u8, int B, int M, int N, int wind
                        float p, int dist, int q, float* A, float* D, float* Omega, void* stream) {
     int rc = check_common(img, B, M, N, window, kind, p, dist, q);
     if (rc) return rc;
+    if (window > 9) return fail(ODF_EUNSUPPORTED, "aggregates are exported for windows 3 to 9");
     if (!A) return fail(ODF_EINVAL, "A is NULL");
     const size_t npix = (size_t)B * M * N;
     const size_t nagg = npix * window * window * sizeof(float);
@@ -246,8 +248,8 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
     if (!idx || !dy || !dx) return fail(ODF_EINVAL, "idx, dy and dx must be non-NULL");
     if (B < 1 || M < 1 || N < 1) return fail(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
     if ((long long)B * M * N >= (1ll << 31)) return fail(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
-    if (window != 3 && window != 5 && window != 7 && window != 9)
-        return fail(ODF_EUNSUPPORTED, "window %d not supported (3, 5, 7 or 9)", window);
+    if (window < 3 || window > 15 || window % 2 == 0)
+        return fail(ODF_EUNSUPPORTED, "window %d not supported (odd, 3 to 15)", window);
     const size_t npix = (size_t)B * M * N;
     if (overlaps(dx, npix * 12, dy, npix * 12) || overlaps(dx, npix * 12, idx, npix))
         return fail(ODF_EINVAL, "dx overlaps dy or idx");

@@ -123,8 +123,10 @@ hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy,
         hipLaunchKernelGGL(bwd_hard_kernel<5>, grid, block, 0, stream, idx, dy, dx, M, N, tg);
     else if (window == 7)
         hipLaunchKernelGGL(bwd_hard_kernel<7>, grid, block, 0, stream, idx, dy, dx, M, N, tg);
-    else
+    else if (window == 9)
         hipLaunchKernelGGL(bwd_hard_kernel<9>, grid, block, 0, stream, idx, dy, dx, M, N, tg);
+    else
+        return launch_backward_hard_general(window, idx, dy, dx, B, M, N, stream);
     return hipGetLastError();
 }
 

@@ -163,6 +163,12 @@ struct SoftParams {
     TileGrid cgrid;        // the combine pass's 64 x 4 pixel blocks
 };
 
+// BVDF / DDF at the odd windows 11 to 15 (general.hip: a direct form, no tile
+// configs), and the hard backward at any odd window up to 15.
+hipError_t launch_forward_general(int window, int kind, int dist, bool u8, const FwdParams& prm,
+                                  hipStream_t stream);
+hipError_t launch_backward_hard_general(int window, const uint8_t* idx, const float* dy, float* dx,
+                                        int B, int M, int N, hipStream_t stream);
 hipError_t launch_backward_hard(int window, const uint8_t* idx, const float* dy, float* dx, int B,
                                 int M, int N, hipStream_t stream);
 size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N);

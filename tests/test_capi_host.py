@@ -31,8 +31,11 @@ def _u8(img, B, M, N, w, kind, p, dist, q, out, idx=None):
     ((FAKE, 1, -1, 8, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
     ((FAKE, 1, 8, 0, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "sizes"),
     ((FAKE, 4096, 4096, 4096, 3, 0, 0.0, 0, 4, FAKE2), odf.EINVAL, "2^31"),
-    ((FAKE, 1, 8, 8, 11, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 17, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 4, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 12, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 1, 0, 0.0, 0, 4, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 13, 2, 0.0, 0, 4, FAKE2), odf.EINVAL, "kind"),  # 13x13: checked as 3x3
     ((FAKE, 1, 8, 8, 3, 2, 0.0, 0, 4, FAKE2), odf.EINVAL, "kind"),
     ((FAKE, 1, 8, 8, 3, 0, 0.0, 3, 4, FAKE2), odf.EINVAL, "dist"),
     ((FAKE, 1, 8, 8, 3, 0, 0.0, 1, 5, FAKE2), odf.EINVAL, "q"),
@@ -62,6 +65,30 @@ def test_f32_and_aggregates_reject():
     assert "A" in odf.last_error()
     assert L.odf_aggregates_f32(FAKE, 1, 1, 4, 4, 3, 0, 0.0, 0, 4, FAKE2, FAKE2, None, None) == odf.EINVAL
     assert "overlap" in odf.last_error()
+    # windows past 9x9 run the direct form, which exports no aggregates
+    assert L.odf_aggregates_f32(FAKE, 1, 1, 4, 4, 11, 0, 0.0, 0, 4, FAKE2, None, None,
+                                None) == odf.EUNSUPPORTED
+    assert "aggregates" in odf.last_error()
+
+
+def test_general_windows_validated_like_the_others():
+    """11x11 to 15x15: the hard backward, ACWDDF, the centre-weighted filters,
+    the softmin and the tuning table reject what they do not offer."""
+    L = odf.lib()
+    B = odf._batch_lib()
+    bwd = lambda w, dx=FAKE2: L.odf_backward_hard_f32(  # noqa: E731
+        FAKE, ctypes.c_void_p(0x7F0000200000), 1, 8, 8, w, dx, None)
+    for w in (2, 16, 17):
+        assert bwd(w) == odf.EUNSUPPORTED and "window" in odf.last_error()
+    assert bwd(15, dx=ctypes.c_void_p(0x7F0000200000 + 12)) == odf.EINVAL  # dx overlaps dy
+    for w in (11, 13, 15):
+        assert L.odf_acwddf_u8(FAKE, 1, 8, 8, w, 0, 4, 2, 10.8, FAKE2, None, None) \
+            == odf.EUNSUPPORTED
+        assert L.odf_cw_filter_u8(FAKE, 1, 8, 8, w, odf.CWVMF, 0, 4, 1, FAKE2, None, None) \
+            == odf.EUNSUPPORTED
+        assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, w, 1, 0.25, 0.1, FAKE2, None) \
+            == odf.EUNSUPPORTED
+        assert B.odf_tune_get(w, odf.DDF, 0, 1) == odf.EINVAL
 
 
 def test_declared_names_match_binding():

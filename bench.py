@@ -109,7 +109,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "2051ccae2184a933f7db4fbb33cd2011e2e2bd521b80c83b1eb78f43704acd1d"
+TRAFFIC_SRC_SHA256 = "95d220b155b744e70984afe928e5cb481385127ad85552d06d8949d3b073a789"
 
 
 def forward_sources_sha256():

@@ -109,7 +109,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "95d220b155b744e70984afe928e5cb481385127ad85552d06d8949d3b073a789"
+TRAFFIC_SRC_SHA256 = "287884b6929f2dd37a98e3de70331f183629356f49cffd10e80f7c7eeeb60bc3"
 
 
 def forward_sources_sha256():
@@ -776,7 +776,8 @@ def batched_form(torch, odf, synth, dev, DIST, samples=None):
     return {"batched_256_mixed": {
         "mpix": round(npx / 1e6, 2), "loop_configs": tuned,
         "batch_tile_shapes": batch_tuned, "plan_ext_tiles": info["ext_tiles"],
-        "plan_configs": dict(zip(("w3_bvdf", "w3_ddf", "w5_bvdf", "w5_ddf"), info["configs"])),
+        "plan_configs": dict(zip(("w3_bvdf", "w3_ddf", "w5_bvdf", "w5_ddf", "w7_bvdf", "w7_ddf"),
+                                 info["configs"])),
         "direct_graph_ms": round(ms_direct, 3),
         "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),
         "loop_ms": round(ms_loop, 3), "loop_mpix_s": round(npx / (ms_loop * 1e3), 1),

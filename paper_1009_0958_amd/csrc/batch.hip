@@ -62,7 +62,7 @@ struct BatchShape {
     static constexpr int THREADS = EXT_W * EXT_H;
 };
 
-constexpr int kNumClasses = 12;  // (window 3/5) x (BVDF/DDF) x (exact/minimax/rgb)
+constexpr int kNumClasses = 3 * kNumBatchGroups;  // (window 3/5/7) x (BVDF/DDF) x (exact/minimax/rgb)
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float uni(float v) {
@@ -189,9 +189,9 @@ __global__ void __launch_bounds__(512)
         batch_strip<W, KIND, kRgb>(*reinterpret_cast<StripSh<W, KIND, kRgb>*>(smem), bc, tile);
 }
 
-// class = ((window == 5) * 2 + kind) * 3 + dist; group = class / 3
-constexpr int kNumGroups = kNumClasses / 3;
-static int group_window(int grp) { return grp / 2 ? 5 : 3; }
+// class = batch_group(window, kind) * 3 + dist; group = class / 3
+constexpr int kNumGroups = kNumBatchGroups;
+static int group_window(int grp) { return batch_group_window(grp); }
 
 static void group_geometry(int grp, int cfg, int& tw, int& th, int& threads) {
     const int h = group_window(grp) / 2;
@@ -206,12 +206,20 @@ static void group_geometry(int grp, int cfg, int& tw, int& th, int& threads) {
     threads = kTileW[cfg] * kTileH[cfg];
 }
 
+// (7x7 groups offer the 512-thread shapes 2 and 3 and the strips, as the
+// per-image kernels do; make_plan rejects the others)
 template <int W, int KIND>
 static void launch_group_wk(int cfg, int threads, const BatchClass& bc, hipStream_t s) {
     const dim3 grid = flat_grid(bc.ntiles);
     switch (cfg) {
-    case 0: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), grid, dim3(threads), 0, s, bc); break;
-    case 1: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), grid, dim3(threads), 0, s, bc); break;
+    case 0:
+        if constexpr (W < 7)
+            hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 0>), grid, dim3(threads), 0, s, bc);
+        break;
+    case 1:
+        if constexpr (W < 7)
+            hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), grid, dim3(threads), 0, s, bc);
+        break;
     case 2: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 2>), grid, dim3(threads), 0, s, bc); break;
     case 3: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 3>), grid, dim3(threads), 0, s, bc); break;
     default: hipLaunchKernelGGL((batch_strip_kernel<W, KIND>), grid, dim3(threads), 0, s, bc); break;
@@ -223,7 +231,9 @@ static void launch_group(int grp, int cfg, int threads, const BatchClass& bc, hi
     case 0: launch_group_wk<3, kBVDF>(cfg, threads, bc, s); break;
     case 1: launch_group_wk<3, kDDF>(cfg, threads, bc, s); break;
     case 2: launch_group_wk<5, kBVDF>(cfg, threads, bc, s); break;
-    default: launch_group_wk<5, kDDF>(cfg, threads, bc, s); break;
+    case 3: launch_group_wk<5, kDDF>(cfg, threads, bc, s); break;
+    case 4: launch_group_wk<7, kBVDF>(cfg, threads, bc, s); break;
+    default: launch_group_wk<7, kDDF>(cfg, threads, bc, s); break;
     }
 }
 
@@ -276,7 +286,8 @@ int make_plan(const odf_job* jobs, int njobs, const int* cfg, odf_plan** plan) {
         if (!j.img || !j.out) return bfail(ODF_EINVAL, "job img/out is NULL");
         if (j.M < 1 || j.N < 1 || (long long)j.M * j.N >= (1ll << 31))
             return bfail(ODF_EINVAL, "job size out of range");
-        if (j.window != 3 && j.window != 5) return bfail(ODF_EUNSUPPORTED, "job window not 3 or 5");
+        if (j.window != 3 && j.window != 5 && j.window != 7)
+            return bfail(ODF_EUNSUPPORTED, "job window not 3, 5 or 7");
         if (j.kind != ODF_BVDF && j.kind != ODF_DDF) return bfail(ODF_EINVAL, "job kind out of range");
         if (j.dist < ODF_EXACT || j.dist > ODF_RGB) return bfail(ODF_EINVAL, "job dist out of range");
         if (j.dist == ODF_MINIMAX && (j.q < 2 || j.q > 4)) return bfail(ODF_EINVAL, "job q out of range");
@@ -303,7 +314,9 @@ int make_plan(const odf_job* jobs, int njobs, const int* cfg, odf_plan** plan) {
         b.p = j.kind == ODF_DDF ? j.p : 0.0f;
         b.coef = odf::MinimaxCoef{};
         if (j.dist == ODF_MINIMAX) b.coef = odf::minimax_coef(j.q);
-        const int grp = (j.window == 5) * 2 + (j.kind == ODF_DDF);
+        const int grp = odf::batch_group(j.window, j.kind);
+        if (!odf::tile_config_valid(j.window, j.kind, cfg[grp], true))
+            return bfail(ODF_EINVAL, "config not offered for a job's window and kind");
         int tw, th, thr;
         odf::group_geometry(grp, cfg[grp], tw, th, thr);
         for (int ty = 0; ty < j.M; ty += th)
@@ -370,7 +383,7 @@ int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* 
                       hipStream_t s) {
     std::vector<odf_job> sub;
     for (int i = 0; i < njobs; ++i)
-        if ((jobs[i].window == 5) * 2 + (jobs[i].kind == ODF_DDF) == grp) sub.push_back(jobs[i]);
+        if (odf::batch_group(jobs[i].window, jobs[i].kind) == grp) sub.push_back(jobs[i]);
     for (int c = 0; c < odf::kNumTileConfigs; ++c) ms[c] = -1.0f;
     if (sub.empty()) return ODF_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -380,6 +393,7 @@ int time_group_shapes(const odf_job* jobs, int njobs, int grp, int reps, float* 
     }
     int rc = ODF_OK;
     for (int c = 0; c < odf::kNumTileConfigs && rc == ODF_OK; ++c) {
+        if (!odf::tile_config_valid(odf::group_window(grp), grp % 2, c, true)) continue;  // -1
         int cfg[odf::kNumGroups];
         for (int g = 0; g < odf::kNumGroups; ++g) cfg[g] = odf::batch_tuned_config(g);
         cfg[grp] = c;
@@ -490,9 +504,10 @@ int odf_plan_configs(const odf_plan* plan, int* configs) {
 
 int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, float* times_ms,
                        void* stream) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || reps < 1)
+    if ((window != 3 && window != 5 && window != 7) || (kind != ODF_BVDF && kind != ODF_DDF) ||
+        reps < 1)
         return odf::set_error(ODF_EINVAL, "autotune_batch: arguments out of range");
-    const int grp = (window == 5) * 2 + (kind == ODF_DDF);
+    const int grp = odf::batch_group(window, kind);
     // a mixed work list: frames and small images of several aspect ratios,
     // each with every pair term
     static const int kSizes[][2] = {{1080, 1920}, {720, 1280}, {512, 512}, {300, 400},

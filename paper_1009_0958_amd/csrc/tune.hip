@@ -38,7 +38,7 @@ int dist_slot(int kind, int dist) { return kind == ODF_CWVMF ? (int)kRgb : dist;
 
 // Batch groups: 32 x 32 for 3x3 DDF and 32 x 16 otherwise until tuned (the
 // steady-state best measured on MI355X on 3840 x 2160 frames).
-std::atomic<int> g_batch[4];
+std::atomic<int> g_batch[kNumBatchGroups];
 
 void ensure_init() {
     std::call_once(g_table_once, [] {
@@ -47,7 +47,7 @@ void ensure_init() {
                 for (int d = 0; d < 3; ++d)
                     for (int u = 0; u < 2; ++u)
                         g_table[w][k][d][u].store(tile_config_default(3 + 2 * w, k));
-        for (int g = 0; g < 4; ++g) g_batch[g].store(g == 1 ? 0 : 2);
+        for (int g = 0; g < kNumBatchGroups; ++g) g_batch[g].store(g == 1 ? 0 : 2);
     });
 }
 
@@ -266,15 +266,16 @@ done:
 }
 
 int odf_batch_tune_get(int window, int kind) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF)) return ODF_EINVAL;
-    return odf::batch_tuned_config((window == 5) * 2 + kind);
+    if ((window != 3 && window != 5 && window != 7) || (kind != ODF_BVDF && kind != ODF_DDF))
+        return ODF_EINVAL;
+    return odf::batch_tuned_config(odf::batch_group(window, kind));
 }
 
 int odf_batch_tune_set(int window, int kind, int config) {
-    if ((window != 3 && window != 5) || (kind != ODF_BVDF && kind != ODF_DDF) || config < 0 ||
-        config >= odf::kNumTileConfigs)
+    if ((window != 3 && window != 5 && window != 7) || (kind != ODF_BVDF && kind != ODF_DDF) ||
+        !odf::tile_config_valid(window, kind, config, true))
         return ODF_EINVAL;
-    odf::set_batch_tuned_config((window == 5) * 2 + kind, config);
+    odf::set_batch_tuned_config(odf::batch_group(window, kind), config);
     return ODF_OK;
 }
 

@@ -447,7 +447,8 @@ def _batch_lib():
     return L
 
 
-NUM_CLASSES = 12  # ((window == 5) * 2 + kind) * 3 + dist
+NUM_BATCH_GROUPS = 6  # ((window - 3) / 2) * 2 + kind, windows 3, 5, 7
+NUM_CLASSES = 3 * NUM_BATCH_GROUPS  # group * 3 + dist
 
 
 def _job_array(jobs):
@@ -510,12 +511,12 @@ class BatchPlan:
         _check(_batch_lib().odf_plan_info(self._plan, ctypes.byref(nj), ctypes.byref(npix),
                                           ctypes.cast(tiles, ctypes.c_void_p),
                                           ctypes.cast(grids, ctypes.c_void_p)))
-        cfg = (ctypes.c_int * 4)()
+        cfg = (ctypes.c_int * NUM_BATCH_GROUPS)()
         _check(_batch_lib().odf_plan_configs(self._plan, ctypes.cast(cfg, ctypes.c_void_p)))
         return {"jobs": nj.value, "pixels": npix.value, "tiles": list(tiles), "grids": list(grids),
                 "configs": list(cfg),
                 "ext_tiles": {"w%d_%s" % (3 + 2 * (g // 2), ("bvdf", "ddf")[g % 2]):
-                              tile_config(cfg[g]) for g in range(4)}}
+                              tile_config(cfg[g]) for g in range(NUM_BATCH_GROUPS)}}
 
     def close(self):
         if self._plan:
@@ -585,15 +586,15 @@ def autotune_batch_jobs(jobs, reps=2, cache_path=None):
     [ms per config])} for the groups that hold jobs."""
     arr, keep = _job_array(jobs)
     C = NUM_TILE_CONFIGS
-    times = (ctypes.c_float * (4 * C))()
+    times = (ctypes.c_float * (NUM_BATCH_GROUPS * C))()
     path = None if cache_path is None else cache_path.encode()
     _check(_batch_lib().odf_autotune_batch_jobs(ctypes.cast(arr, ctypes.c_void_p), len(jobs), reps,
                                                 path, ctypes.cast(times, ctypes.c_void_p),
                                                 _stream(torch.cuda.current_device())))
     res = {}
-    for g in range(4):
+    for g in range(NUM_BATCH_GROUPS):
         ms = list(times[C * g:C * g + C])
-        if ms[0] >= 0:
+        if any(m >= 0 for m in ms):
             w, k = 3 + 2 * (g // 2), g % 2
             res["w%d_%s" % (w, ("bvdf", "ddf")[k])] = (batch_tune_get(w, k), ms)
     del keep

@@ -107,7 +107,7 @@ class _Job(ctypes.Structure):
 @pytest.mark.parametrize("fields,code,text", [
     (dict(img=None), odf.EINVAL, "img"),
     (dict(M=0), odf.EINVAL, "size"),
-    (dict(window=7), odf.EUNSUPPORTED, "window"),
+    (dict(window=9), odf.EUNSUPPORTED, "window"),
     (dict(kind=3), odf.EINVAL, "kind"),
     (dict(dist=5), odf.EINVAL, "dist"),
     (dict(dist=1, q=9), odf.EINVAL, "q"),
@@ -159,7 +159,13 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
     # batch tuning table: defaults, range checks, and the retired persistent form
     assert L.odf_batch_tune_get(3, odf.DDF) == 0 and L.odf_batch_tune_get(5, odf.BVDF) == 2
-    assert L.odf_batch_tune_get(7, odf.DDF) == odf.EINVAL
+    assert L.odf_batch_tune_get(7, odf.DDF) == 2 and L.odf_batch_tune_get(9, odf.DDF) == odf.EINVAL
+    # 7x7 groups: the 512-thread shapes and the strips, as the per-image table
+    assert L.odf_batch_tune_set(7, odf.DDF, 0) == odf.EINVAL
+    assert L.odf_batch_tune_set(7, odf.BVDF, 1) == odf.EINVAL
+    assert L.odf_batch_tune_set(7, odf.DDF, odf.STRIP) == odf.OK
+    assert L.odf_batch_tune_get(7, odf.DDF) == odf.STRIP
+    assert L.odf_batch_tune_set(7, odf.DDF, 2) == odf.OK
     assert L.odf_batch_tune_get(3, odf.ACWDDF) == odf.EINVAL
     assert L.odf_batch_tune_set(3, odf.BVDF, odf.NUM_TILE_CONFIGS) == odf.EINVAL
     assert L.odf_batch_tune_set(3, odf.BVDF, odf.STRIP) == odf.OK  # the strip form
@@ -168,7 +174,7 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_batch_tune_set(5, odf.DDF, -1) == odf.EINVAL
     assert L.odf_batch_tune_set(5, odf.DDF, 1) == odf.OK and L.odf_batch_tune_get(5, odf.DDF) == 1
     assert L.odf_batch_tune_set(5, odf.DDF, 2) == odf.OK
-    assert L.odf_autotune_batch(7, 0, 1, None, None, None) == odf.EINVAL
+    assert L.odf_autotune_batch(9, 0, 1, None, None, None) == odf.EINVAL
     assert L.odf_autotune_batch(3, 0, 0, None, None, None) == odf.EINVAL
     jobs = (odf._Job * 1)()
     assert L.odf_autotune_batch_jobs(None, 1, 2, None, None, None) == odf.EINVAL

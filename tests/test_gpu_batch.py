@@ -28,7 +28,7 @@ def _mixed_jobs(count, seed, max_side=160):
         job = dict(img=torch.from_numpy(img).to(DEV),
                    out=torch.empty((M, N, 3), dtype=torch.uint8, device=DEV),
                    idx=torch.empty((M, N), dtype=torch.uint8, device=DEV),
-                   window=int(rng.choice([3, 5])), kind=int(rng.integers(0, 2)),
+                   window=int(rng.choice([3, 5, 7])), kind=int(rng.integers(0, 2)),
                    dist=int(rng.integers(0, 3)), q=int(rng.integers(2, 5)),
                    p=float(rng.choice([0.0, 0.25, 0.5, 1.0])))
         jobs.append(job)
@@ -42,19 +42,22 @@ def _per_image(job):
 
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 def test_batch_equals_per_image_and_oracle(cfg):
-    """Every group on config cfg (the batch tuning table set for all four): a
-    tile shape, or the strip form (4: 8 bands per strip, 5: 3 bands)."""
+    """Every group on config cfg (the batch tuning table set for all six): a
+    tile shape, or the strip form (4: 8 bands per strip, 5: 3 bands); the 7x7
+    groups, which do not offer the 1024-thread shapes 0 and 1, stay on 2 there."""
     jobs, imgs = _mixed_jobs(40, 1)
-    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
+    assert {j["window"] for j in jobs} == {3, 5, 7}
+    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5, 7) for k in (0, 1)}
+    c7 = cfg if cfg >= 2 else 2
     try:
         for (w, k) in keep:
-            odf.batch_tune_set(w, k, cfg)
+            odf.batch_tune_set(w, k, c7 if w == 7 else cfg)
         plan = odf.BatchPlan(jobs)
     finally:
         for (w, k), c in keep.items():
             odf.batch_tune_set(w, k, c)
     info = plan.info()
-    assert info["configs"] == [cfg] * 4
+    assert info["configs"] == [cfg] * 4 + [c7] * 2
     print("plan:", info, flush=True)
     assert info["jobs"] == 40 and sum(info["tiles"]) > 0
     plan.launch()
@@ -95,7 +98,7 @@ def test_batch_without_idx_and_single_job():
     assert torch.equal(out, ref)
 
 
-@pytest.mark.parametrize("window,kind", [(3, 0), (3, 1), (5, 0), (5, 1)])
+@pytest.mark.parametrize("window,kind", [(3, 0), (3, 1), (5, 0), (5, 1), (7, 0), (7, 1)])
 def test_tile_shapes_give_identical_results(window, kind):
     img = torch.from_numpy(synth.image_corr(150, 170, 0.2, key=window + kind)).to(DEV)
     default = odf.tune_get(window, kind, odf.EXACT, True)
@@ -131,7 +134,7 @@ def test_autotune_batch_drives_the_plan(tmp_path):
     list, sets the fastest in the batch table, which the next plan uses; the
     cache line restores it."""
     cache = str(tmp_path / "tune.jsonl")
-    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
+    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5, 7) for k in (0, 1)}
     try:
         best, times = odf.autotune_batch(5, odf.BVDF, 2, cache)
         print("autotune_batch 5x5 BVDF:", best, times, flush=True)
@@ -160,7 +163,7 @@ def test_autotune_batch_on_the_callers_jobs():
     """odf_autotune_batch_jobs times each group's shapes on the given jobs and
     sets the table for the groups present; the plan made next uses them and
     still gives the per-image results."""
-    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5) for k in (0, 1)}
+    keep = {(w, k): odf.batch_tune_get(w, k) for w in (3, 5, 7) for k in (0, 1)}
     try:
         jobs, _ = _mixed_jobs(30, 5)
         res = odf.autotune_batch_jobs(jobs, 2)
@@ -170,7 +173,10 @@ def test_autotune_batch_on_the_callers_jobs():
         plan = odf.BatchPlan(jobs)
         info = plan.info()
         for g, (best, ms) in res.items():
-            assert len(ms) == odf.NUM_TILE_CONFIGS and ms[best] == min(ms)
+            # -1: a config the group does not offer (7x7: the 1024-thread shapes)
+            timed = [m for m in ms if m >= 0]
+            assert len(ms) == odf.NUM_TILE_CONFIGS and ms[best] == min(timed)
+            assert (ms[0] < 0 and ms[1] < 0) == g.startswith("w7")
             assert info["ext_tiles"][g] == odf.tile_config(best)
         plan.launch()
         torch.cuda.synchronize()
@@ -182,3 +188,29 @@ def test_autotune_batch_on_the_callers_jobs():
         for (w, k), c in keep.items():
             odf.batch_tune_set(w, k, c)
 
+
+
+def test_autotune_batch_7x7_group():
+    """The 7x7 groups: the batch autotuner times the shapes they offer (2, 3 and
+    the strips; -1 for the 1024-thread shapes) and the plan runs on the fastest,
+    bitwise equal to the per-image filter."""
+    keep = {(7, k): odf.batch_tune_get(7, k) for k in (0, 1)}
+    try:
+        best, times = odf.autotune_batch(7, odf.DDF, 1)
+        print("autotune_batch 7x7 DDF:", best, times, flush=True)
+        assert times[0] < 0 and times[1] < 0 and all(t > 0 for t in times[2:])
+        assert best >= 2 and times[best] == min(times[2:])
+        jobs, _ = _mixed_jobs(8, 7)
+        for j in jobs:
+            j["window"], j["kind"] = 7, odf.DDF
+        plan = odf.BatchPlan(jobs)
+        assert plan.info()["configs"][5] == best
+        plan.launch()
+        torch.cuda.synchronize()
+        for j in jobs:
+            out, idx = _per_image(j)
+            assert torch.equal(j["out"], out) and torch.equal(j["idx"], idx)
+        plan.close()
+    finally:
+        for (w, k), c in keep.items():
+            odf.batch_tune_set(w, k, c)

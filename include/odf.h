@@ -209,7 +209,7 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
  * y(c) = sum_u pi_u x_u.  tau -> 0 tends to the hard selection where the
  * minimum is unique.
  *   x  B x M x N x 3 float32 (read only); y  B x M x N x 3 float32 output.
- * Windows 3, 5 and 7 (ODF_EUNSUPPORTED for 9).
+ * Windows 3, 5, 7 and 9 (ODF_EUNSUPPORTED above).
  * Errors: as odf_filter_f32, plus ODF_EINVAL for tau <= 0 or not finite.
  */
 int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,
@@ -265,7 +265,7 @@ int odf_softmin_bwd_f32_noalloc(const float* x, const float* dy, int B, int M, i
  * every window to the workspace (n x 3 binary64 per pixel, 8-byte aligned,
  * owned by the caller, contents on entry ignored), then sums, for every pixel,
  * those of the members that are that pixel (windows in raster order, members
- * in index order): deterministic.  Windows 3, 5 and 7.
+ * in index order): deterministic.  Windows 3, 5, 7 and 9.
  */
 int odf_softmin_fwd_f64(const double* x, int B, int M, int N, int window, int kind, double p,
                         double tau, double* y, void* stream);

@@ -31,9 +31,10 @@ namespace odf {
 // sweeps, which frees the registers for 1024-thread tiles.  The backward uses
 // 512-thread tiles; it parks the angle sums A during the L2 sweep as well and
 // recomputes Omega from A and D where it needs it, so that (with 128 VGPRs) two
-// workgroups share a compute unit.  7x7 keeps 512-thread tiles both ways (26 x 10
-// windows): its 49 weights per window fill ~95 KB of LDS, one workgroup per
-// compute unit, so the backward may take 256 VGPRs for its 2 x 49 aggregates.
+// workgroups share a compute unit.  7x7 and 9x9 keep 512-thread tiles both ways
+// (26 x 10 and 24 x 8 windows): their 49 or 81 weights per window fill 77-114 KB
+// of LDS, one workgroup per compute unit, so the backward may take 256 VGPRs
+// for its two sets of member aggregates (9x9 spills part of them).
 template <int W, int KIND, bool BWD>
 struct SoftTile {
     static constexpr int EXT_W = 32;
@@ -44,7 +45,7 @@ struct SoftTile {
 template <int W, bool BWD>
 constexpr int soft_waves_per_eu() {
     if (!BWD) return 1;
-    return W == 7 ? 2 : 4;
+    return W >= 7 ? 2 : 4;
 }
 
 __device__ __forceinline__ float key_value(uint32_t k) {
@@ -583,9 +584,12 @@ size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
     } else if (window == 5) {
         if (kind == kBVDF) soft_grid<5, kBVDF, true>(prm, tx, ty, nt);
         else soft_grid<5, kDDF, true>(prm, tx, ty, nt);
-    } else {
+    } else if (window == 7) {
         if (kind == kBVDF) soft_grid<7, kBVDF, true>(prm, tx, ty, nt);
         else soft_grid<7, kDDF, true>(prm, tx, ty, nt);
+    } else {
+        if (kind == kBVDF) soft_grid<9, kBVDF, true>(prm, tx, ty, nt);
+        else soft_grid<9, kDDF, true>(prm, tx, ty, nt);
     }
     return (size_t)B * tx * ty * nt * 3 * sizeof(float);
 }
@@ -595,7 +599,9 @@ hipError_t launch_softmin(int window, int kind, bool bwd, const SoftParams& prm,
         return kind == kBVDF ? launch_soft_t<3, kBVDF>(bwd, prm, s) : launch_soft_t<3, kDDF>(bwd, prm, s);
     if (window == 5)
         return kind == kBVDF ? launch_soft_t<5, kBVDF>(bwd, prm, s) : launch_soft_t<5, kDDF>(bwd, prm, s);
-    return kind == kBVDF ? launch_soft_t<7, kBVDF>(bwd, prm, s) : launch_soft_t<7, kDDF>(bwd, prm, s);
+    if (window == 7)
+        return kind == kBVDF ? launch_soft_t<7, kBVDF>(bwd, prm, s) : launch_soft_t<7, kDDF>(bwd, prm, s);
+    return kind == kBVDF ? launch_soft_t<9, kBVDF>(bwd, prm, s) : launch_soft_t<9, kDDF>(bwd, prm, s);
 }
 
 }  // namespace odf

@@ -246,8 +246,8 @@ int check_soft64(const double* x, int B, int M, int N, int window, int kind, dou
     if (B < 1 || M < 1 || N < 1)
         return set_error(ODF_EINVAL, "sizes must be >= 1 (B=%d M=%d N=%d)", B, M, N);
     if ((long long)B * M * N >= (1ll << 31)) return set_error(ODF_EINVAL, "B*M*N must be < 2^31 pixels");
-    if (window != 3 && window != 5 && window != 7)
-        return set_error(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3, 5 and 7");
+    if (window != 3 && window != 5 && window != 7 && window != 9)
+        return set_error(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3 to 9");
     if (kind != ODF_BVDF && kind != ODF_DDF) return set_error(ODF_EINVAL, "kind %d out of range", kind);
     if (kind == ODF_DDF && !(p >= 0.0 && p <= 1.0)) return set_error(ODF_EINVAL, "p must be in [0, 1]");
     if (!(tau > 0.0) || !(tau < 1.0e300)) return set_error(ODF_EINVAL, "tau must be positive and finite");
@@ -274,7 +274,8 @@ int odf_softmin_fwd_f64(const double* x, int B, int M, int N, int window, int ki
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const hipError_t e = window == 3   ? odf::launch_soft64_w<3>(false, prm, s)
                          : window == 5 ? odf::launch_soft64_w<5>(false, prm, s)
-                                       : odf::launch_soft64_w<7>(false, prm, s);
+                         : window == 7 ? odf::launch_soft64_w<7>(false, prm, s)
+                                       : odf::launch_soft64_w<9>(false, prm, s);
     if (e != hipSuccess)
         return odf::set_error(ODF_EHIP, "binary64 softmin forward launch: %s", hipGetErrorString(e));
     return ODF_OK;
@@ -282,7 +283,7 @@ int odf_softmin_fwd_f64(const double* x, int B, int M, int N, int window, int ki
 
 size_t odf_softmin_bwd_f64_workspace(int B, int M, int N, int window) {
     if (B < 1 || M < 1 || N < 1 || (long long)B * M * N >= (1ll << 31) ||
-        (window != 3 && window != 5 && window != 7))
+        (window != 3 && window != 5 && window != 7 && window != 9))
         return 0;
     return (size_t)B * M * N * window * window * 3 * sizeof(double);
 }
@@ -314,7 +315,8 @@ int odf_softmin_bwd_f64(const double* x, const double* dy, int B, int M, int N, 
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const hipError_t e = window == 3   ? odf::launch_soft64_w<3>(true, prm, s)
                          : window == 5 ? odf::launch_soft64_w<5>(true, prm, s)
-                                       : odf::launch_soft64_w<7>(true, prm, s);
+                         : window == 7 ? odf::launch_soft64_w<7>(true, prm, s)
+                                       : odf::launch_soft64_w<9>(true, prm, s);
     if (e != hipSuccess)
         return odf::set_error(ODF_EHIP, "binary64 softmin backward launch: %s", hipGetErrorString(e));
     return ODF_OK;

@@ -247,12 +247,13 @@ def test_noise_and_quality_reject():
 
 
 def test_softmin_window_limits():
-    """The softmin takes windows 3, 5 and 7; its 7x7 backward workspace holds
+    """The softmin takes windows 3 to 9; its 7x7 backward workspace holds
     one 32 x 16 extended tile (26 x 10 windows) of float32 triples per tile."""
     L = odf.lib()
-    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 9, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 11, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert "softmin" in odf.last_error()
-    assert L.odf_softmin_bwd_workspace(1, 8, 8, 9, 1) == 0
+    assert L.odf_softmin_bwd_workspace(1, 8, 8, 11, 1) == 0
+    assert L.odf_softmin_bwd_workspace(1, 8, 8, 9, 1) == 1 * 1 * 512 * 3 * 4  # 24 x 8 windows
     tiles = 2 * -(-100 // 26) * -(-45 // 10)
     assert L.odf_softmin_bwd_workspace(2, 45, 100, 7, 1) == tiles * 512 * 3 * 4
 
@@ -263,7 +264,7 @@ def test_softmin_f64_rejects():
     fwd = lambda *a: L.odf_softmin_fwd_f64(*a[:6], D(a[6]), D(a[7]), a[8], None)  # noqa: E731
     assert fwd(None, 1, 4, 4, 3, 1, 0.25, 0.1, FAKE2) == odf.EINVAL and "x" in odf.last_error()
     assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.1, None) == odf.EINVAL and "y" in odf.last_error()
-    assert fwd(FAKE, 1, 4, 4, 9, 1, 0.25, 0.1, FAKE2) == odf.EUNSUPPORTED
+    assert fwd(FAKE, 1, 4, 4, 11, 1, 0.25, 0.1, FAKE2) == odf.EUNSUPPORTED
     assert fwd(FAKE, 1, 4, 4, 3, 1, 1.5, 0.1, FAKE2) == odf.EINVAL and "p" in odf.last_error()
     assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, 0.0, FAKE2) == odf.EINVAL and "tau" in odf.last_error()
     assert fwd(FAKE, 1, 4, 4, 3, 1, 0.25, float("inf"), FAKE2) == odf.EINVAL
@@ -273,7 +274,8 @@ def test_softmin_f64_rejects():
     need = L.odf_softmin_bwd_f64_workspace(1, 4, 4, 5)
     assert need == 4 * 4 * 25 * 3 * 8
     assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 7) == 4 * 4 * 49 * 3 * 8
-    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 9) == 0
+    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 9) == 4 * 4 * 81 * 3 * 8
+    assert L.odf_softmin_bwd_f64_workspace(1, 4, 4, 11) == 0
     F3 = ctypes.c_void_p(0x7F0000200000)
     WS = ctypes.c_void_p(0x7F0000300000)
     bwd = lambda ws, nbytes, w=5: L.odf_softmin_bwd_f64(  # noqa: E731
@@ -393,7 +395,7 @@ def test_noalloc_softmin_rejects_before_launch():
     assert "static scratch" in odf.last_error()
     assert f(FAKE, None, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EINVAL
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.0, FAKE2, None) == odf.EINVAL  # tau
-    assert f(FAKE, FAKE2, 1, 8, 8, 9, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert f(FAKE, FAKE2, 1, 8, 8, 11, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE, None) == odf.EINVAL  # dx = x
     assert "overlaps" in odf.last_error()
 

@@ -82,7 +82,7 @@ def _objectives(x, window, kind, p):
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
                                            (5, BVDF, 0.0), (5, DDF, 0.5), (7, DDF, 0.25),
-                                           (7, BVDF, 0.0)])
+                                           (7, BVDF, 0.0), (9, DDF, 0.25), (9, BVDF, 0.0)])
 @pytest.mark.parametrize("tau", [0.1, 0.01])
 def test_softmin_forward_matches_oracle(window, kind, p, tau):
     print("case: softmin fwd w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
@@ -96,7 +96,8 @@ def test_softmin_forward_matches_oracle(window, kind, p, tau):
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
                                            (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0),
-                                           (7, DDF, 0.25), (7, BVDF, 0.0), (7, DDF, 1.0)])
+                                           (7, DDF, 0.25), (7, BVDF, 0.0), (7, DDF, 1.0),
+                                           (9, DDF, 0.25), (9, BVDF, 0.0)])
 @pytest.mark.parametrize("tau", [0.1, 0.01])
 def test_softmin_backward_matches_oracle(window, kind, p, tau):
     print("case: softmin bwd w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
@@ -127,20 +128,21 @@ def test_softmin_autograd_and_edge_shapes():
         check_soft(y.detach().cpu().numpy(), yr, xt.grad.cpu().numpy(), ref, bnd, str(shape))
 
 
-def test_softmin_7x7_edge_shapes_and_tiles():
-    """7x7 on shapes smaller than one window, thin ones, and several 26 x 10
-    tiles with ragged edges both ways (the combine pass sums up to four tiles
-    per pixel), float32 against the oracle's budget."""
+@pytest.mark.parametrize("w", [7, 9])
+def test_softmin_large_window_edge_shapes_and_tiles(w):
+    """7x7 and 9x9 on shapes smaller than one window, thin ones, and several
+    tiles (26 x 10 or 24 x 8 windows) with ragged edges both ways (the combine
+    pass sums up to four tiles per pixel), float32 against the oracle's budget."""
     for shape in ((1, 1, 1), (1, 3, 11), (1, 23, 2), (2, 31, 57)):
-        print("case: softmin 7x7 shape=%s" % (shape,), flush=True)
+        print("case: softmin %dx%d shape=%s" % (w, w, shape), flush=True)
         x = synth.float_batch(*shape, 0.2, key=17)
         dy = np.random.default_rng(17).standard_normal(x.shape).astype(np.float32)
-        y = odf.softmin_forward(_gpu(x), 7, DDF, 0.25, 0.1).cpu().numpy()
-        dx = odf.softmin_backward(_gpu(x), _gpu(dy), 7, DDF, 0.25, 0.1).cpu().numpy()
-        yr = oracle.softmin_fwd(x, 7, DDF, 0.25, 0.1)
-        ref = oracle.softmin_bwd(x, dy.astype(np.float64), 7, DDF, 0.25, 0.1)
-        bnd = soft_bounds(x, _objectives(x, 7, DDF, 0.25), 7, 0.1, max(np.abs(ref).max(), 1e-6))
-        check_soft(y, yr, dx, ref, bnd, "7x7 %s" % (shape,))
+        y = odf.softmin_forward(_gpu(x), w, DDF, 0.25, 0.1).cpu().numpy()
+        dx = odf.softmin_backward(_gpu(x), _gpu(dy), w, DDF, 0.25, 0.1).cpu().numpy()
+        yr = oracle.softmin_fwd(x, w, DDF, 0.25, 0.1)
+        ref = oracle.softmin_bwd(x, dy.astype(np.float64), w, DDF, 0.25, 0.1)
+        bnd = soft_bounds(x, _objectives(x, w, DDF, 0.25), w, 0.1, max(np.abs(ref).max(), 1e-6))
+        check_soft(y, yr, dx, ref, bnd, "%dx%d %s" % (w, w, shape))
 
 
 def test_softmin_small_tau_is_hard_selection():
@@ -184,7 +186,7 @@ def test_full_size_batch_crops():
 
 @pytest.mark.parametrize("window,kind,p", [(3, BVDF, 0.0), (3, DDF, 0.25), (5, DDF, 0.25),
                                            (5, BVDF, 0.0), (5, DDF, 0.5), (3, DDF, 1.0),
-                                           (7, DDF, 0.25), (7, BVDF, 0.0)])
+                                           (7, DDF, 0.25), (7, BVDF, 0.0), (9, DDF, 0.25)])
 @pytest.mark.parametrize("tau", [0.1, 0.01])
 def test_softmin_f64_matches_oracle(window, kind, p, tau):
     """The binary64 twins against the binary64 oracle: both evaluate the same

@@ -57,9 +57,8 @@
 #endif
 
 enum { OK_BVDF = 0, OK_DDF = 1 };
-/* members of the largest window: 15 x 15 for the filter and its hard backward
- * (the member index is stored in a byte), 9 x 9 for the softmin relaxation,
- * ACWDDF and the centre-weighted filters */
+/* members of the largest window: 15 x 15 for the filters (the member index is
+ * stored in a byte), 9 x 9 for the softmin relaxation */
 enum { NMAX = 225, NMAX9 = 81 };
 enum { OD_EXACT = 0, OD_MINIMAX = 1, OD_RGB = 2 };
 
@@ -527,14 +526,18 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
     int64_t b = pix / mn, rc = pix % mn;
     int r = (int)(rc / N), c = (int)(rc % N);
     int n = w * w, d = (n - 1) / 2;
-    int64_t src[NMAX9];
-    double th[NMAX9][NMAX9], l2[NMAX9][NMAX9], Om[4][NMAX9];
+    int64_t src[NMAX];
+    double Om[4][NMAX];
+    /* the n x n pair terms of the window, th[u n + v] and l2[u n + v] (on the
+     * heap: 810 KB at 15 x 15) */
+    double *th = malloc(sizeof(double) * n * n), *l2 = malloc(sizeof(double) * n * n);
+    if (!th || !l2) abort();
     const double *base = img + b * mn * 3;
     window_members(M, N, w, r, c, src);
     for (int u = 0; u < n; ++u)
         for (int v = 0; v < n; ++v) {
-            th[u][v] = pair_term(base + src[u] * 3, base + src[v] * 3, OK_DDF, dist, q);
-            l2[u][v] = minkowski_l2(base + src[u] * 3, base + src[v] * 3);
+            th[u * n + v] = pair_term(base + src[u] * 3, base + src[v] * 3, OK_DDF, dist, q);
+            l2[u * n + v] = minkowski_l2(base + src[u] * 3, base + src[v] * 3);
         }
     /* eq. (3) and the three centre-weighted objectives */
     for (int j = 0; j < 4; ++j) {
@@ -543,8 +546,8 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
             double a = 0.0, e = 0.0;
             for (int v = 0; v < n; ++v) {
                 double wv = (j > 0 && v == d) ? (double)(n - 2 * k + 2) : 1.0;
-                a += wv * th[u][v];
-                e += wv * l2[u][v];
+                a += wv * th[u * n + v];
+                e += wv * l2[u * n + v];
             }
             Om[j][u] = a * e;
         }
@@ -556,7 +559,7 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
             if (Om[j][u] < Om[j][sel[j]]) sel[j] = u;
     }
     double S = 0.0;
-    for (int j = 1; j < 4; ++j) S += th[sel[j]][d] * l2[sel[j]][d];
+    for (int j = 1; j < 4; ++j) S += th[sel[j] * n + d] * l2[sel[j] * n + d];
     int chosen = S > T ? sel[0] : d;
     const double *x = base + src[chosen] * 3;
     if (out) { out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; }
@@ -565,12 +568,14 @@ static void acwddf_one(const double *img, int M, int N, int w, int dist, int q, 
     if (diag) {
         for (int j = 0; j < 4; ++j)
             for (int u = 0; u < n; ++u) diag[j * n + u] = Om[j][u];
-        for (int u = 0; u < n; ++u) diag[4 * n + u] = th[u][d] * l2[u][d];
+        for (int u = 0; u < n; ++u) diag[4 * n + u] = th[u * n + d] * l2[u * n + d];
     }
+    free(th);
+    free(l2);
 }
 
 static int check_acw(int B, int M, int N, int w, int dist, int q, int lambda, double T) {
-    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || w > 9) return -1;
+    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q)) return -1;
     int dd = (w * w + 1) / 2;
     if (lambda < 1 || lambda > dd - 2 || T != T) return -1;
     return 0;
@@ -621,8 +626,8 @@ static void cw_one(const double *img, int M, int N, int w, int vmf, int dist, in
     int64_t b = pix / mn, rc = pix % mn;
     int r = (int)(rc / N), c = (int)(rc % N);
     int n = w * w, d = (n - 1) / 2;
-    int64_t src[NMAX9];
-    double Om[NMAX9];
+    int64_t src[NMAX];
+    double Om[NMAX];
     const double *base = img + b * mn * 3;
     window_members(M, N, w, r, c, src);
     for (int u = 0; u < n; ++u) {
@@ -648,7 +653,7 @@ static void cw_one(const double *img, int M, int N, int w, int vmf, int dist, in
 /* CWVMF^k (vmf = 1) or CWDDF^k (vmf = 0) over B images; out, idx, obj nullable. */
 int oracle_cwfilter(const double *img, int B, int M, int N, int w, int vmf, int dist, int q,
                     int level, double *out, uint8_t *idx, double *obj, int nthreads) {
-    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || w > 9 || !img) return -1;
+    if (check_args(B, M, N, w, OK_DDF, 0.5, dist, q) || !img) return -1;
     if (level < 1 || level > (w * w + 1) / 2 || (vmf != 0 && vmf != 1)) return -1;
     set_threads(nthreads);
     int64_t total = (int64_t)B * M * N;

@@ -148,14 +148,14 @@ def test_at_matches_full_and_rejects():
     o2, i2, S2, d2 = oracle.acwddf_at(x, pix, window=5, dist=RGB, lam=3, T=5.0)
     assert np.array_equal(o2, out.reshape(-1, 3)[pix]) and np.array_equal(i2, idx.ravel()[pix])
     assert np.array_equal(S2, S.ravel()[pix]) and np.array_equal(d2, dg.reshape(-1, 125)[pix])
-    for bad in (dict(lam=0), dict(lam=4), dict(T=math.nan), dict(window=11)):
+    for bad in (dict(lam=0), dict(lam=4), dict(T=math.nan), dict(window=17), dict(window=10)):
         kw = dict(window=3, lam=2, T=1.0)
         kw.update(bad)
         with pytest.raises(ValueError):
             oracle.acwddf(x, **kw)
 
 
-@pytest.mark.parametrize("w,lam", [(3, 1), (3, 2), (5, 4)])
+@pytest.mark.parametrize("w,lam", [(3, 1), (3, 2), (5, 4), (11, 2), (15, 100)])
 def test_statistic_sums_the_three_levels(w, lam):
     """S is the sum, over the levels lambda .. lambda + 2 only (their columns
     are pinned by the closed forms above), of A(y_k, x_d) L2(y_k, x_d) at each
@@ -174,3 +174,18 @@ def test_statistic_sums_the_three_levels(w, lam):
                                            -1)[..., 0] + np.take_along_axis(cen, sel0[..., None],
                                                                              -1)[..., 0]
     assert not np.allclose(S, with_ddf, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("w", [11, 15])
+def test_large_windows_reduce_to_the_plain_filters(w):
+    """Past 9 x 9 as below: T < 0 switches every window to the eq. (3)
+    selection, which is DDF with p = 1/2 (its objective the square root of the
+    product); T = +inf keeps every centre."""
+    x = np.random.default_rng(w).integers(0, 256, (9, 11, 3))
+    n = w * w
+    _, i_neg, _, dg = oracle.acwddf(x, window=w, dist=EXACT, lam=2, T=-1.0, diag=True)
+    _, i_ddf, A, D, _ = oracle.filter(x, w, DDF, 0.5, EXACT, 4, aggregates=True)
+    assert np.allclose(dg[..., :n], A * D, rtol=1e-12)
+    assert np.array_equal(i_neg, i_ddf)
+    _, i_inf, _ = oracle.acwddf(x, window=w, dist=EXACT, lam=2, T=math.inf)
+    assert np.all(i_inf == (n - 1) // 2)

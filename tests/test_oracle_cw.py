@@ -23,11 +23,12 @@ def _angle(a, b):
     return math.acos(float(a @ b) / math.sqrt(float(a @ a) * float(b @ b)))
 
 
-@pytest.mark.parametrize("w", [3, 5])
+@pytest.mark.parametrize("w", [3, 5, 11])
 @pytest.mark.parametrize("vmf", [True, False])
 def test_lone_impulse_closed_form(w, vmf):
     """A w x w image of colour a with colour b at one pixel: the objectives of
-    the window centred on the image centre in closed form, for every level."""
+    the window centred on the image centre in closed form, for every level
+    (11 x 11: the first two, a middle one and the last)."""
     n = w * w
     d = (n - 1) // 2
     a, b = (30, 200, 90), (220, 10, 40)
@@ -36,7 +37,8 @@ def test_lone_impulse_closed_form(w, vmf):
         x = np.empty((w, w, 3))
         x[:] = a
         x[where // w, where % w] = b
-        for k in range(1, (n + 1) // 2 + 1):
+        levels = range(1, (n + 1) // 2 + 1) if w <= 5 else (1, 2, 30, (n + 1) // 2)
+        for k in levels:
             wd = n - 2 * k + 2
             _, idx, obj = oracle.cwfilter(x, w, vmf, EXACT, 4, k)
             o = obj[w // 2, w // 2]
@@ -56,7 +58,7 @@ def test_lone_impulse_closed_form(w, vmf):
                 assert idx[w // 2, w // 2] == (1 if where == 0 else 0)
 
 
-@pytest.mark.parametrize("w", [3, 5])
+@pytest.mark.parametrize("w", [3, 5, 11, 15])
 def test_level_d_is_the_unweighted_filter(w):
     """At k = d every weight is 1: CWVMF^d is the vector median (DDF p = 1) and
     CWDDF^d the product of eq. (3) (DDF p = 1/2, whose objective is its square
@@ -74,7 +76,7 @@ def test_level_d_is_the_unweighted_filter(w):
         assert np.allclose(np.sqrt(o_p), Oh, rtol=1e-12)
 
 
-@pytest.mark.parametrize("w", [3, 5])
+@pytest.mark.parametrize("w", [3, 5, 13])
 @pytest.mark.parametrize("vmf", [True, False])
 def test_level_1_keeps_the_centre_colour(w, vmf):
     """k = 1 weighs the centre by n: by the triangle inequality of L2 (and of

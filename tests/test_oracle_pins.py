@@ -571,7 +571,7 @@ def test_softmin_limits():
 
 
 def test_window_range():
-    """The filter and its hard backward take every odd window from 3 x 3 to
+    """The filters and the hard backward take every odd window from 3 x 3 to
     15 x 15 (the member index is a byte); the softmin relaxation stops at 9 x 9.
     Even and larger windows are rejected."""
     img = _tiny_image(3, 4, 5)
@@ -583,8 +583,9 @@ def test_window_range():
     x = img.astype(np.float64)
     with pytest.raises(ValueError):
         oracle.softmin_fwd(x, 11, DDF, 0.25, 0.1)
-    with pytest.raises(ValueError):
-        oracle.cwfilter(img, 11, True, EXACT, 4, 1)
+    for w in (10, 17):
+        with pytest.raises(ValueError):
+            oracle.cwfilter(img, w, True, EXACT, 4, 1)
     # a constant image: every member ties, the lowest index wins
     for w in (11, 13, 15):
         out, idx = oracle.filter(np.full((5, 6, 3), 77, np.uint8), w, DDF, 0.25, EXACT)

@@ -138,7 +138,9 @@ int odf_filter_f32(const float* img, int B, int M, int N, int window, int kind, 
  *          paper's setting is lambda = 2, T = 10.8 (angles in radians, L2 in
  *          the units of the image values).
  *   T      any value but NaN (+inf keeps every centre; below 0 gives the DDF).
- * Windows 3, 5 and 7 (ODF_EUNSUPPORTED for 9).
+ * Any odd window from 3 to 15: 3 to 7 on the tile (and, to 5, strip)
+ * kernels, 9 to 15 on the direct form of odf_filter_u8's large windows (no
+ * configs).
  * Errors: as odf_filter_u8, plus ODF_EINVAL for lambda out of range or T NaN.
  */
 int odf_acwddf_u8(const uint8_t* img, int B, int M, int N, int window, int dist, int q,
@@ -163,9 +165,9 @@ int odf_acwddf_f32(const float* img, int B, int M, int N, int window, int dist, 
  *   level  k in [1, (n+1)/2].
  *   img, out, idx as for odf_filter_u8; ties go to the lowest index.
  * Runs on the ACWDDF sweep, with tile table entries of its own (kind
- * ODF_CWVMF or ODF_CWDDF in the tuning calls); windows 3, 5 and 7.
- * Errors: as odf_filter_u8, plus ODF_EINVAL for kind or level out of range,
- * ODF_EUNSUPPORTED for window 9.
+ * ODF_CWVMF or ODF_CWDDF in the tuning calls) for windows 3 to 7; windows 9 to
+ * 15 (odd) run the direct form, which has no configs.
+ * Errors: as odf_filter_u8, plus ODF_EINVAL for kind or level out of range.
  */
 int odf_cw_filter_u8(const uint8_t* img, int B, int M, int N, int window, int kind, int dist, int q,
                      int level, uint8_t* out, uint8_t* idx, void* stream);
@@ -395,8 +397,8 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * bitwise equal to the tile shapes).  odf_tile_config
  * gives the extended width and height of a tile shape, or of one band of the
  * strip form.  The process-wide table picks a config per (window, kind,
- * dist, input type), kind any odf_kind (windows 3, 5 and 7 for ODF_ACWDDF,
- * ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular term and keeps one entry
+ * dist, input type), kind any odf_kind (windows 3 to 9; 3, 5 and 7 for
+ * ODF_ACWDDF, ODF_CWVMF and ODF_CWDDF; ODF_CWVMF has no angular term and keeps one entry
  * for every dist); the default is shape 2 (32 x 16) for every class (the 5x5
  * centre-weighted kinds and 7x7 offer only the 512-thread shapes 2 and 3 and,
  * where the strip form covers them, configs 4 and 5; 9x9 only shape 2 and the

@@ -129,7 +129,6 @@ int acwddf_any(const void* img, bool u8, int B, int M, int N, int window, int di
                int lambda, float T, void* out, uint8_t* idx, void* stream) {
     int rc = check_common(img, B, M, N, window, ODF_DDF, 0.5f, dist, q);
     if (rc) return rc;
-    if (window >= 9) return fail(ODF_EUNSUPPORTED, "ACWDDF supports windows 3, 5 and 7");
     if (!out) return fail(ODF_EINVAL, "out is NULL");
     const int dmax = (window * window + 1) / 2 - 2;
     if (lambda < 1 || lambda > dmax)
@@ -145,7 +144,8 @@ int acwddf_any(const void* img, bool u8, int B, int M, int N, int window, int di
     prm.out = out;
     prm.idx = idx;
     odf::set_acw_params(window, lambda, T, prm);
-    const int cfg = odf::tuned_config(window, ODF_ACWDDF, dist, u8);
+    // from 9x9 the centre-weighted kinds run the direct form, which has no configs
+    const int cfg = window <= 7 ? odf::tuned_config(window, ODF_ACWDDF, dist, u8) : 0;
     hipError_t e = odf::launch_forward(window, ODF_ACWDDF, dist, u8, false, cfg, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "ACWDDF launch");
@@ -158,8 +158,6 @@ int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, 
     if (rc) return rc;
     if (kind != ODF_CWVMF && kind != ODF_CWDDF)
         return fail(ODF_EINVAL, "kind %d is not ODF_CWVMF or ODF_CWDDF", kind);
-    if (window >= 9)
-        return fail(ODF_EUNSUPPORTED, "centre-weighted filters support windows 3, 5 and 7");
     if (!out) return fail(ODF_EINVAL, "out is NULL");
     const int n = window * window, dmax = (n + 1) / 2;
     if (level < 1 || level > dmax) return fail(ODF_EINVAL, "level %d out of range [1, %d]", level, dmax);
@@ -175,7 +173,7 @@ int cw_any(const void* img, bool u8, int B, int M, int N, int window, int kind, 
     prm.out = out;
     prm.idx = idx;
     for (int j = 0; j < 3; ++j) prm.acw_wm1[j] = (float)(n - 2 * level + 1);  // w_d(k) - 1
-    const int cfg = odf::tuned_config(window, kind, d, u8);
+    const int cfg = window <= 7 ? odf::tuned_config(window, kind, d, u8) : 0;
     hipError_t e = odf::launch_forward(window, odf::kernel_kind(kind), d, u8, false, cfg, prm,
                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "centre-weighted filter launch");

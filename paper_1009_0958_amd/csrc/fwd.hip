@@ -42,8 +42,10 @@ hipError_t launch_forward(int window, int kind, int dist, bool u8, bool aggregat
     if (window == 3) return launch_w<3>(kind, dist, u8, aggregates, cfg, prm, stream);
     if (window == 5) return launch_forward5(kind, dist, u8, aggregates, cfg, prm, stream);
     if (window == 7) return launch_forward7(kind, dist, u8, aggregates, cfg, prm, stream);
-    if (window == 9) return launch_forward9(kind, dist, u8, aggregates, cfg, prm, stream);
-    if (aggregates) return hipErrorInvalidValue;  // no aggregate-inspection form past 9x9
+    if (window == 9 && !centre_weighted(kind))
+        return launch_forward9(kind, dist, u8, aggregates, cfg, prm, stream);
+    // the direct form: BVDF / DDF past 9x9, the centre-weighted kinds from 9x9
+    if (aggregates) return hipErrorInvalidValue;  // no aggregate-inspection form there
     return launch_forward_general(window, kind, dist, u8, prm, stream);
 }
 

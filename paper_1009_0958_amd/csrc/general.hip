@@ -1,6 +1,7 @@
 // general.hip -- BVDF and DDF (eqs. 1-3) at the odd windows 11x11, 13x13 and
-// 15x15 (Section II: a sqrt(n) x sqrt(n) window of any odd size), and the hard
-// backward of their selections.
+// 15x15 (Section II: a sqrt(n) x sqrt(n) window of any odd size), ACWDDF and
+// the centre-weighted filters of Section III (eq. 9) at 9x9 to 15x15, and the
+// hard backward of the selections.
 //
 // The tile kernels keep a window's n aggregates in registers per thread and
 // share pair terms between windows through LDS planes; past 9x9 (81
@@ -16,6 +17,10 @@
 // share their canonical direction) then sum identical terms in the same order
 // and tie exactly, and the lowest index wins the 64-bit (objective bits,
 // index) LDS minimum.  The member index is a byte, which bounds n at 225.
+// The centre-weighted kinds keep, beside A and D, the member's terms with the
+// window centre (cA, cD), from which the weights of eq. (9) form the levels'
+// objectives as in the tile kernels; ACWDDF's switching statistic is then
+// taken from the three levels' selections.
 #include "aggregates.h"
 #include "canon.h"
 #include "odf_internal.h"
@@ -42,10 +47,14 @@ __device__ __forceinline__ uint32_t general_key_bits(int mode, float p, float A,
 template <int KIND, int DIST, bool U8>
 __global__ void __launch_bounds__(kGenThreads) fwd_general_kernel(FwdParams prm, int w) {
     constexpr bool CANON = U8 && KIND == kBVDF;  // as in the tile form
+    constexpr bool ANG = KIND != kCWV;           // CWVMF^k has no angular term
+    constexpr bool L2 = KIND != kBVDF;
+    constexpr int NKEY = KIND == kACW ? 4 : 1;    // ACWDDF: eq. (3) and three levels
+    constexpr int NWIN = kGenTile * kGenTile;
     __shared__ float4 s_dir[kGenExt * kGenExt];
     __shared__ float4 s_raw[U8 ? 1 : kGenExt * kGenExt];
     __shared__ float s_inv[U8 ? kGenExt * kGenExt : 1];
-    __shared__ unsigned long long s_key[kGenTile * kGenTile];
+    __shared__ unsigned long long s_key[NKEY * NWIN];
 
     const int t = flat_block(prm.grid.n);
     if (t < 0) return;
@@ -80,7 +89,7 @@ __global__ void __launch_bounds__(kGenThreads) fwd_general_kernel(FwdParams prm,
         }
         s_dir[i] = d;
     }
-    for (int i = tid; i < kGenTile * kGenTile; i += kGenThreads) s_key[i] = ~0ull;
+    for (int i = tid; i < NKEY * NWIN; i += kGenThreads) s_key[i] = ~0ull;
     __syncthreads();
 
     // a2-a4: lane = window (cy, cx) of the block, wave = members u = wave, wave + 4, ...
@@ -98,40 +107,91 @@ __global__ void __launch_bounds__(kGenThreads) fwd_general_kernel(FwdParams prm,
         const float4 ra = s_raw[U8 ? 0 : m];  // float images only
         const bool a_zero = U8 && a.w < 0.0f;
         const uint64_t a_zero_wave = U8 ? __builtin_amdgcn_ballot_w64(a_zero) : 0;
-        float A = 0.0f, D = 0.0f, cA = 0.0f, cD = 0.0f;  // sums and their compensations
+        float A = 0.0f, D = 0.0f, kA = 0.0f, kD = 0.0f;  // sums and their compensations
+        float tcen = 0.0f, lcen = 0.0f;                   // the terms with the centre
         for (int vy = 0; vy < w; ++vy) {
             const int row = (cy + vy) * E + cx;
             for (int vx = 0; vx < w; ++vx) {
 #pragma clang fp contract(off)
                 const int v = row + vx;
-                float th, l2 = 0.0f;
+                float th = 0.0f, l2 = 0.0f;
                 if constexpr (U8) {
-                    pair_u8<KIND, DIST, true, KIND == kDDF>(a, ia, a_zero, a_zero_wave, s_dir[v],
-                                                           s_inv[v], prm.coef, ac, th, l2);
+                    pair_u8<KIND, DIST, ANG, L2>(a, ia, a_zero, a_zero_wave, s_dir[v], s_inv[v],
+                                                 prm.coef, ac, th, l2);
                 } else {
                     const float4 rb = s_raw[v];
-                    th = pair_term<KIND, DIST, false>(a, ra, s_dir[v], rb, prm.coef, ac);
-                    if (KIND == kDDF) l2 = l2_term(ra, rb);
+                    if (ANG) th = pair_term<KIND, DIST, false>(a, ra, s_dir[v], rb, prm.coef, ac);
+                    if (L2) l2 = l2_term(ra, rb);
                 }
-                const float yA = th - cA, tA = A + yA;
-                cA = (tA - A) - yA;
-                A = tA;
-                if (KIND == kDDF) {
-                    const float yD = l2 - cD, tD = D + yD;
-                    cD = (tD - D) - yD;
+                if (ANG) {
+                    const float yA = th - kA, tA = A + yA;
+                    kA = (tA - A) - yA;
+                    A = tA;
+                }
+                if (L2) {
+                    const float yD = l2 - kD, tD = D + yD;
+                    kD = (tD - D) - yD;
                     D = tD;
+                }
+                if (centre_weighted(KIND) && vy == h && vx == h) {
+                    tcen = th;
+                    lcen = l2;
                 }
             }
         }
-        const uint32_t bits = general_key_bits(mode, p, A, D);
-        if (in_image) atomicMin(&s_key[lane], ((unsigned long long)bits << 32) | (unsigned)u);
+        const unsigned long long uu = (unsigned)u;
+        if (!in_image) continue;
+        if constexpr (KIND == kACW) {
+            // eq. (3) and the three levels of eq. (9): the centre's weight
+            // w_d(k) adds w_d(k) - 1 times the centre term to both sums
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float o = j == 0 ? A * D
+                                       : fmaf(prm.acw_wm1[j - 1], tcen, A) *
+                                             fmaf(prm.acw_wm1[j - 1], lcen, D);
+                atomicMin(&s_key[j * NWIN + lane], ((unsigned long long)__float_as_uint(o) << 32) | uu);
+            }
+        } else if constexpr (KIND == kCW || KIND == kCWV) {
+            const float w1 = prm.acw_wm1[0];
+            const float dw = fmaf(w1, lcen, D);
+            const float o = KIND == kCWV ? dw : fmaf(w1, tcen, A) * dw;
+            atomicMin(&s_key[lane], ((unsigned long long)__float_as_uint(o) << 32) | uu);
+        } else {
+            const uint32_t bits = general_key_bits(mode, p, A, D);
+            atomicMin(&s_key[lane], ((unsigned long long)bits << 32) | uu);
+        }
     }
     __syncthreads();
 
     // the selected member of every in-image window, copied from the image
-    if (tid >= kGenTile * kGenTile || !in_image) return;
+    if (tid >= NWIN || !in_image) return;
     const int gy = ty0 + cy, gx = tx0 + cx;
-    const int u = min((int)(s_key[tid] & 0xffu), n - 1);
+    int u = min((int)(s_key[tid] & 0xffu), n - 1);
+    if constexpr (KIND == kACW) {
+        // switch: S = sum over the three levels of A(y_k, x_d) L2(y_k, x_d); the
+        // eq. (3) selection if S > T, else the centre
+        const int c = (cy + h) * E + cx + h;
+        const float4 cd = s_dir[c];
+        float S = 0.0f;
+#pragma unroll
+        for (int j = 1; j <= 3; ++j) {
+            const int uj = min((int)(s_key[j * NWIN + tid] & 0xffu), n - 1);
+            const int m = (cy + uj / w) * E + cx + uj % w;
+            float th, l2;
+            if constexpr (U8) {
+                const float4 md = s_dir[m];
+                const bool mz = md.w < 0.0f;
+                pair_u8<KIND, DIST, true, true>(md, s_inv[m], mz, __builtin_amdgcn_ballot_w64(mz),
+                                                cd, s_inv[c], prm.coef, ac, th, l2);
+            } else {
+                const float4 cr = s_raw[c];
+                th = pair_term<KIND, DIST, false>(s_dir[m], s_raw[m], cd, cr, prm.coef, ac);
+                l2 = l2_term(s_raw[m], cr);
+            }
+            S += th * l2;
+        }
+        if (!(S > prm.acw_T)) u = (n - 1) / 2;
+    }
     const int sy = min(max(gy + u / w - h, 0), M - 1);
     const int sx = min(max(gx + u % w - h, 0), N - 1);
     const size_t pix = ((size_t)b * M + gy) * N + gx;
@@ -154,16 +214,23 @@ hipError_t launch_general_k(int window, int dist, const FwdParams& prm, hipStrea
     q.grid = tile_grid(prm.B, (prm.N + kGenTile - 1) / kGenTile,
                        (prm.M + kGenTile - 1) / kGenTile);
     const dim3 grid = flat_grid(q.grid.n), block(kGenThreads);
-    switch (dist) {
-    case kExact:
-        hipLaunchKernelGGL((fwd_general_kernel<KIND, kExact, U8>), grid, block, 0, s, q, window);
-        break;
-    case kMinimax:
-        hipLaunchKernelGGL((fwd_general_kernel<KIND, kMinimax, U8>), grid, block, 0, s, q, window);
-        break;
-    default:
+    if constexpr (KIND == kCWV) {  // no angular term
+        (void)dist;
         hipLaunchKernelGGL((fwd_general_kernel<KIND, kRgb, U8>), grid, block, 0, s, q, window);
-        break;
+    } else {
+        switch (dist) {
+        case kExact:
+            hipLaunchKernelGGL((fwd_general_kernel<KIND, kExact, U8>), grid, block, 0, s, q,
+                               window);
+            break;
+        case kMinimax:
+            hipLaunchKernelGGL((fwd_general_kernel<KIND, kMinimax, U8>), grid, block, 0, s, q,
+                               window);
+            break;
+        default:
+            hipLaunchKernelGGL((fwd_general_kernel<KIND, kRgb, U8>), grid, block, 0, s, q, window);
+            break;
+        }
     }
     return hipGetLastError();
 }
@@ -208,14 +275,29 @@ __global__ void __launch_bounds__(256) bwd_general_kernel(const uint8_t* __restr
 
 hipError_t launch_forward_general(int window, int kind, int dist, bool u8, const FwdParams& prm,
                                   hipStream_t s) {
-    if (window < 11 || window > 2 * kGenMaxH + 1 || window % 2 == 0) return hipErrorInvalidValue;
-    if (kind == kBVDF)
+    // BVDF / DDF from 11x11 (9x9 and below run the tiles), the centre-weighted
+    // kinds from 9x9
+    const int lo = centre_weighted(kind) ? 9 : 11;
+    if (window < lo || window > 2 * kGenMaxH + 1 || window % 2 == 0) return hipErrorInvalidValue;
+    switch (kind) {
+    case kBVDF:
         return u8 ? launch_general_k<kBVDF, true>(window, dist, prm, s)
                   : launch_general_k<kBVDF, false>(window, dist, prm, s);
-    if (kind == kDDF)
+    case kDDF:
         return u8 ? launch_general_k<kDDF, true>(window, dist, prm, s)
                   : launch_general_k<kDDF, false>(window, dist, prm, s);
-    return hipErrorInvalidValue;
+    case kACW:
+        return u8 ? launch_general_k<kACW, true>(window, dist, prm, s)
+                  : launch_general_k<kACW, false>(window, dist, prm, s);
+    case kCW:
+        return u8 ? launch_general_k<kCW, true>(window, dist, prm, s)
+                  : launch_general_k<kCW, false>(window, dist, prm, s);
+    case kCWV:  // no angular term: one form for every dist
+        return u8 ? launch_general_k<kCWV, true>(window, dist, prm, s)
+                  : launch_general_k<kCWV, false>(window, dist, prm, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_backward_hard_general(int window, const uint8_t* idx, const float* dy, float* dx,

@@ -72,8 +72,9 @@ def test_f32_and_aggregates_reject():
 
 
 def test_general_windows_validated_like_the_others():
-    """11x11 to 15x15: the hard backward, ACWDDF, the centre-weighted filters,
-    the softmin and the tuning table reject what they do not offer."""
+    """11x11 to 15x15: the hard backward, the softmin and the tuning table
+    reject what they do not offer; ACWDDF and the centre-weighted filters
+    validate their own arguments at these sizes (nothing is launched here)."""
     L = odf.lib()
     B = odf._batch_lib()
     bwd = lambda w, dx=FAKE2: L.odf_backward_hard_f32(  # noqa: E731
@@ -82,11 +83,19 @@ def test_general_windows_validated_like_the_others():
         assert bwd(w) == odf.EUNSUPPORTED and "window" in odf.last_error()
     assert bwd(15, dx=ctypes.c_void_p(0x7F0000200000 + 12)) == odf.EINVAL  # dx overlaps dy
     for w in (11, 13, 15):
+        n = w * w
+        # lambda <= (n + 1) / 2 - 2 and level <= (n + 1) / 2 at every size
+        assert L.odf_acwddf_u8(FAKE, 1, 8, 8, w, 0, 4, (n + 1) // 2 - 1, 10.8, FAKE2, None,
+                               None) == odf.EINVAL and "lambda" in odf.last_error()
+        assert L.odf_cw_filter_u8(FAKE, 1, 8, 8, w, odf.CWVMF, 0, 4, (n + 1) // 2 + 1, FAKE2,
+                                  None, None) == odf.EINVAL and "level" in odf.last_error()
+        assert L.odf_acwddf_u8(FAKE, 1, 8, 8, w, 0, 4, 2, 10.8, FAKE, None, None) == odf.EINVAL
+        assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, w, 1, 0.25, 0.1, FAKE2, None) \
+            == odf.EUNSUPPORTED
+    for w in (10, 17):
         assert L.odf_acwddf_u8(FAKE, 1, 8, 8, w, 0, 4, 2, 10.8, FAKE2, None, None) \
             == odf.EUNSUPPORTED
         assert L.odf_cw_filter_u8(FAKE, 1, 8, 8, w, odf.CWVMF, 0, 4, 1, FAKE2, None, None) \
-            == odf.EUNSUPPORTED
-        assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, w, 1, 0.25, 0.1, FAKE2, None) \
             == odf.EUNSUPPORTED
         assert B.odf_tune_get(w, odf.DDF, 0, 1) == odf.EINVAL
 
@@ -191,7 +200,7 @@ def test_batch_and_tune_argument_errors():
 @pytest.mark.parametrize("args,code,text", [
     ((None, 1, 8, 8, 3, 0, 4, 2, 10.8, FAKE2), odf.EINVAL, "img"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 2, 10.8, None), odf.EINVAL, "out"),
-    ((FAKE, 1, 8, 8, 9, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
+    ((FAKE, 1, 8, 8, 17, 0, 4, 2, 10.8, FAKE2), odf.EUNSUPPORTED, "window"),
     ((FAKE, 1, 8, 8, 3, 3, 4, 2, 10.8, FAKE2), odf.EINVAL, "dist"),
     ((FAKE, 1, 8, 8, 3, 1, 7, 2, 10.8, FAKE2), odf.EINVAL, "q"),
     ((FAKE, 1, 8, 8, 3, 0, 4, 0, 10.8, FAKE2), odf.EINVAL, "lambda"),
@@ -297,7 +306,7 @@ def test_cw_filter_rejects():
     assert f(5, odf.CWDDF, 14) == odf.EINVAL
     assert f(3, odf.DDF, 1) == odf.EINVAL and "kind" in odf.last_error()
     assert f(3, odf.ACWDDF, 1) == odf.EINVAL
-    assert f(9, odf.CWVMF, 1) == odf.EUNSUPPORTED
+    assert f(17, odf.CWVMF, 1) == odf.EUNSUPPORTED
     assert f(7, odf.CWDDF, 26) == odf.EINVAL and "level" in odf.last_error()  # 7x7: k <= 25
     assert f(3, odf.CWDDF, 1, dist=3) == odf.EINVAL and "dist" in odf.last_error()
     assert f(3, odf.CWVMF, 1, out=None) == odf.EINVAL and "out" in odf.last_error()

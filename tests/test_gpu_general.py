@@ -120,3 +120,58 @@ def test_sampled_1080p():
     print("1080p 11x11: mismatch %d of %d" % (n_mis, n), flush=True)
     src = source_pixels(img, idx, 11).reshape(-1, 3)
     assert np.array_equal(out.reshape(-1, 3), src)
+
+
+@pytest.mark.parametrize("window", [9, 11, 15])
+@pytest.mark.parametrize("u8", [True, False])
+def test_acwddf_direct_form(window, u8):
+    """ACWDDF (lambda = 2, T = 10.8) at 9x9 to 15x15 on the direct form, every
+    pair term, against the oracle's selections and switching statistic (the
+    selection may differ only where binary32 can change a level's argmin or
+    the side of T)."""
+    from parity import check_acwddf, window_colours
+    img = synth.image_corr(2 * 19, 26, 0.2, key=window).reshape(2, 19, 26, 3)
+    x = img if u8 else img.astype(np.float32)
+    n = window * window
+    for dist in (EXACT, MINIMAX, RGB):
+        print("case: general acwddf %s w=%d dist=%d" % (x.dtype, window, dist), flush=True)
+        out, idx = odf.acwddf(_gpu(x), window, dist, 4, 2, 10.8)
+        out, idx = out.cpu().numpy(), idx.cpu().numpy()
+        _, o_idx, S, dg = oracle.acwddf(x, window, dist, 4, 2, 10.8, diag=True)
+        n_mis, n_amb, n_tot = check_acwddf(idx, o_idx, window_colours(x, window), S, dg, n,
+                                           10.8, 0.05)
+        print("  mismatch %d ambiguous %d of %d" % (n_mis, n_amb, n_tot), flush=True)
+        assert np.array_equal(out.reshape(-1, 3), source_pixels(x, idx, window).reshape(-1, 3))
+
+
+@pytest.mark.parametrize("window", [9, 13])
+@pytest.mark.parametrize("u8", [True, False])
+def test_centre_weighted_direct_form(window, u8):
+    """CWVMF^k and CWDDF^k at 9x9 and 13x13 on the direct form: levels 1, 2,
+    a middle one and d, against the oracle's objectives."""
+    img = synth.image_corr(2 * 17, 23, 0.2, key=30 + window).reshape(2, 17, 23, 3)
+    x = img if u8 else img.astype(np.float32) / 255
+    d = (window * window + 1) // 2
+    for kind, dists in ((odf.CWVMF, (EXACT,)), (odf.CWDDF, (EXACT, MINIMAX, RGB))):
+        for level in (1, 2, d // 2, d):
+            for dist in dists:
+                print("case: general cw %s w=%d kind=%d level=%d dist=%d"
+                      % (x.dtype, window, kind, level, dist), flush=True)
+                out, idx = odf.cw_filter(_gpu(x), window, kind, level, dist, 4)
+                out, idx = out.cpu().numpy(), idx.cpu().numpy()
+                _, _, obj = oracle.cwfilter(x, window, kind == odf.CWVMF, dist, 4, level)
+                check_selection(idx, obj)
+                assert np.array_equal(out.reshape(-1, 3),
+                                      source_pixels(x, idx, window).reshape(-1, 3))
+
+
+def test_centre_weighted_extremes_direct_form():
+    """Level 1 keeps every pixel (the centre weighed n wins by the triangle
+    inequality) and ACWDDF with T = +inf keeps every centre, at 11x11."""
+    img = synth.image_uncorr(20, 27, 0.3, key=8)
+    x = _gpu(img)
+    for kind in (odf.CWVMF, odf.CWDDF):
+        out, _ = odf.cw_filter(x, 11, kind, 1, RGB)
+        assert torch.equal(out, x)
+    _, idx = odf.acwddf(x, 11, EXACT, 4, 2, float("inf"))
+    assert bool((idx == 60).all())

@@ -109,7 +109,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "287884b6929f2dd37a98e3de70331f183629356f49cffd10e80f7c7eeeb60bc3"
+TRAFFIC_SRC_SHA256 = "628e0de6aad0ee0875fb263f18fddc7a6a224460760a4c4ca9ab4e571a24761b"
 
 
 def forward_sources_sha256():

@@ -109,7 +109,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "628e0de6aad0ee0875fb263f18fddc7a6a224460760a4c4ca9ab4e571a24761b"
+TRAFFIC_SRC_SHA256 = "85093c2be13af8cd2b9b931ea925ba2edf760d06054cb00c8c4eb6bb2b266f43"
 
 
 def forward_sources_sha256():
@@ -776,7 +776,8 @@ def batched_form(torch, odf, synth, dev, DIST, samples=None):
     return {"batched_256_mixed": {
         "mpix": round(npx / 1e6, 2), "loop_configs": tuned,
         "batch_tile_shapes": batch_tuned, "plan_ext_tiles": info["ext_tiles"],
-        "plan_configs": dict(zip(("w3_bvdf", "w3_ddf", "w5_bvdf", "w5_ddf", "w7_bvdf", "w7_ddf"),
+        "plan_configs": dict(zip(("w3_bvdf", "w3_ddf", "w5_bvdf", "w5_ddf", "w7_bvdf", "w7_ddf",
+                                  "w9_bvdf", "w9_ddf"),
                                  info["configs"])),
         "direct_graph_ms": round(ms_direct, 3),
         "direct_graph_mpix_s": round(npx / (ms_direct * 1e3), 1),

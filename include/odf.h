@@ -282,7 +282,7 @@ int odf_softmin_bwd_f64(const double* x, const double* dy, int B, int M, int N, 
 /* ---------------------------------------------------------------- batches
  * Many uint8 images of different sizes, windows and variants in one launch.
  * A job is one image with its own parameters (same meaning as the arguments
- * of odf_filter_u8; idx may be NULL; windows 3, 5 and 7, kinds ODF_BVDF and
+ * of odf_filter_u8; idx may be NULL; windows 3, 5, 7 and 9, kinds ODF_BVDF and
  * ODF_DDF).  Results are bitwise equal to those of odf_filter_u8 on each
  * image. */
 typedef struct {
@@ -327,12 +327,12 @@ int odf_batch_plan_ex(const odf_job* jobs, int njobs, int flags, odf_plan** plan
 int odf_batch_launch(const odf_plan* plan, void* stream);
 
 /* Plan summary: job count, total pixels, and per class of window, kind and
- * pair term, class = (((window - 3) / 2) * 2 + kind) * 3 + dist (arrays of 18, each
+ * pair term, class = (((window - 3) / 2) * 2 + kind) * 3 + dist (arrays of 24, each
  * nullable): its tiles, and the workgroups launched for them (one per tile). */
 int odf_plan_info(const odf_plan* plan, int* njobs, long long* npix, int* ntiles, int* grids);
 
 /* The config each group of the plan runs on (a tile shape, odf_tile_config
- * number, or a strip config), group = ((window - 3) / 2) * 2 + kind, configs[6].
+ * number, or a strip config), group = ((window - 3) / 2) * 2 + kind, configs[8].
  * ODF_EINVAL for NULL. */
 int odf_plan_configs(const odf_plan* plan, int* configs);
 
@@ -424,10 +424,11 @@ int odf_autotune(int window, int kind, int dist, int is_u8, int M, int N, int re
 
 /* The batch tuning table: the config (0..3 a tile shape, ODF_STRIP_CONFIG or
  * ODF_SHORT_STRIP_CONFIG the strip form) of the batch group of
- * `window` (3, 5, 7) and `kind` (ODF_BVDF, ODF_DDF); 32 x 32 for 3x3 DDF and
+ * `window` (3, 5, 7, 9) and `kind` (ODF_BVDF, ODF_DDF); 32 x 32 for 3x3 DDF and
  * 32 x 16 otherwise until tuned.  get returns the config or ODF_EINVAL; set
  * returns ODF_OK, or ODF_EINVAL for a config the group does not offer (7x7:
- * the 512-thread shapes 2 and 3 and the strips, as odf_tune_set).  Plans read
+ * the 512-thread shapes 2 and 3 and the strips; 9x9: shape 2 and, for
+ * ODF_BVDF, the strips; as odf_tune_set for uint8).  Plans read
  * the table when they are made. */
 int odf_batch_tune_get(int window, int kind);
 int odf_batch_tune_set(int window, int kind, int config);
@@ -447,7 +448,7 @@ int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, f
  * batch group that holds jobs, its configs are timed on the group's jobs (reps
  * launches each; the jobs' outputs are written) and the fastest is set in the
  * batch table and appended to cache_path (nullable);
- * times_ms[ODF_NUM_TILE_CONFIGS * group + config] (nullable, 6 *
+ * times_ms[ODF_NUM_TILE_CONFIGS * group + config] (nullable, 8 *
  * ODF_NUM_TILE_CONFIGS floats) receives the milliseconds, -1 for groups
  * without jobs and for configs a group does not offer.  A plan made afterwards for the same jobs runs
  * on the shapes tuned for them.  Errors: as odf_batch_plan. */

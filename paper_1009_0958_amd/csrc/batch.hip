@@ -62,7 +62,7 @@ struct BatchShape {
     static constexpr int THREADS = EXT_W * EXT_H;
 };
 
-constexpr int kNumClasses = 3 * kNumBatchGroups;  // (window 3/5/7) x (BVDF/DDF) x (exact/minimax/rgb)
+constexpr int kNumClasses = 3 * kNumBatchGroups;  // (window 3/5/7/9) x (BVDF/DDF) x (exact/minimax/rgb)
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float uni(float v) {
@@ -206,8 +206,9 @@ static void group_geometry(int grp, int cfg, int& tw, int& th, int& threads) {
     threads = kTileW[cfg] * kTileH[cfg];
 }
 
-// (7x7 groups offer the 512-thread shapes 2 and 3 and the strips, as the
-// per-image kernels do; make_plan rejects the others)
+// (7x7 groups offer the 512-thread shapes 2 and 3 and the strips, 9x9 groups
+// shape 2 and, for BVDF, the strips, as the per-image kernels do; make_plan
+// rejects the others)
 template <int W, int KIND>
 static void launch_group_wk(int cfg, int threads, const BatchClass& bc, hipStream_t s) {
     const dim3 grid = flat_grid(bc.ntiles);
@@ -221,8 +222,14 @@ static void launch_group_wk(int cfg, int threads, const BatchClass& bc, hipStrea
             hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 1>), grid, dim3(threads), 0, s, bc);
         break;
     case 2: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 2>), grid, dim3(threads), 0, s, bc); break;
-    case 3: hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 3>), grid, dim3(threads), 0, s, bc); break;
-    default: hipLaunchKernelGGL((batch_strip_kernel<W, KIND>), grid, dim3(threads), 0, s, bc); break;
+    case 3:
+        if constexpr (W < 9)
+            hipLaunchKernelGGL((batch_direct_kernel<W, KIND, 3>), grid, dim3(threads), 0, s, bc);
+        break;
+    default:
+        if constexpr (strip_form<W, KIND, true>())
+            hipLaunchKernelGGL((batch_strip_kernel<W, KIND>), grid, dim3(threads), 0, s, bc);
+        break;
     }
 }
 
@@ -233,7 +240,9 @@ static void launch_group(int grp, int cfg, int threads, const BatchClass& bc, hi
     case 2: launch_group_wk<5, kBVDF>(cfg, threads, bc, s); break;
     case 3: launch_group_wk<5, kDDF>(cfg, threads, bc, s); break;
     case 4: launch_group_wk<7, kBVDF>(cfg, threads, bc, s); break;
-    default: launch_group_wk<7, kDDF>(cfg, threads, bc, s); break;
+    case 5: launch_group_wk<7, kDDF>(cfg, threads, bc, s); break;
+    case 6: launch_group_wk<9, kBVDF>(cfg, threads, bc, s); break;
+    default: launch_group_wk<9, kDDF>(cfg, threads, bc, s); break;
     }
 }
 
@@ -286,8 +295,8 @@ int make_plan(const odf_job* jobs, int njobs, const int* cfg, odf_plan** plan) {
         if (!j.img || !j.out) return bfail(ODF_EINVAL, "job img/out is NULL");
         if (j.M < 1 || j.N < 1 || (long long)j.M * j.N >= (1ll << 31))
             return bfail(ODF_EINVAL, "job size out of range");
-        if (j.window != 3 && j.window != 5 && j.window != 7)
-            return bfail(ODF_EUNSUPPORTED, "job window not 3, 5 or 7");
+        if (!odf::batch_window(j.window))
+            return bfail(ODF_EUNSUPPORTED, "job window not 3, 5, 7 or 9");
         if (j.kind != ODF_BVDF && j.kind != ODF_DDF) return bfail(ODF_EINVAL, "job kind out of range");
         if (j.dist < ODF_EXACT || j.dist > ODF_RGB) return bfail(ODF_EINVAL, "job dist out of range");
         if (j.dist == ODF_MINIMAX && (j.q < 2 || j.q > 4)) return bfail(ODF_EINVAL, "job q out of range");
@@ -504,7 +513,7 @@ int odf_plan_configs(const odf_plan* plan, int* configs) {
 
 int odf_autotune_batch(int window, int kind, int reps, const char* cache_path, float* times_ms,
                        void* stream) {
-    if ((window != 3 && window != 5 && window != 7) || (kind != ODF_BVDF && kind != ODF_DDF) ||
+    if (!odf::batch_window(window) || (kind != ODF_BVDF && kind != ODF_DDF) ||
         reps < 1)
         return odf::set_error(ODF_EINVAL, "autotune_batch: arguments out of range");
     const int grp = odf::batch_group(window, kind);

@@ -121,9 +121,12 @@ constexpr int kTileW[kNumTileShapes] = {32, 64, 32, 64};
 constexpr int kTileH[kNumTileShapes] = {32, 16, 16, 8};
 // The batch kernels' shape per group (window 3 / 5 x BVDF / DDF, group =
 // (window == 5) * 2 + kind): the process-wide batch tuning table.
-// Batch groups: one per (window 3, 5 or 7, kind BVDF or DDF), numbered
+// Batch groups: one per (window 3, 5, 7 or 9, kind BVDF or DDF), numbered
 // ((window - 3) / 2) * 2 + kind; classes add the pair term: group * 3 + dist.
-constexpr int kNumBatchGroups = 6;
+constexpr int kNumBatchGroups = 8;
+inline bool batch_window(int window) {
+    return window == 3 || window == 5 || window == 7 || window == 9;
+}
 inline int batch_group(int window, int kind) { return (window - 3) / 2 * 2 + (kind == kDDF); }
 inline int batch_group_window(int group) { return 3 + 2 * (group / 2); }
 int batch_tuned_config(int group);

@@ -266,13 +266,12 @@ done:
 }
 
 int odf_batch_tune_get(int window, int kind) {
-    if ((window != 3 && window != 5 && window != 7) || (kind != ODF_BVDF && kind != ODF_DDF))
-        return ODF_EINVAL;
+    if (!odf::batch_window(window) || (kind != ODF_BVDF && kind != ODF_DDF)) return ODF_EINVAL;
     return odf::batch_tuned_config(odf::batch_group(window, kind));
 }
 
 int odf_batch_tune_set(int window, int kind, int config) {
-    if ((window != 3 && window != 5 && window != 7) || (kind != ODF_BVDF && kind != ODF_DDF) ||
+    if (!odf::batch_window(window) || (kind != ODF_BVDF && kind != ODF_DDF) ||
         !odf::tile_config_valid(window, kind, config, true))
         return ODF_EINVAL;
     odf::set_batch_tuned_config(odf::batch_group(window, kind), config);

@@ -447,7 +447,7 @@ def _batch_lib():
     return L
 
 
-NUM_BATCH_GROUPS = 6  # ((window - 3) / 2) * 2 + kind, windows 3, 5, 7
+NUM_BATCH_GROUPS = 8  # ((window - 3) / 2) * 2 + kind, windows 3, 5, 7, 9
 NUM_CLASSES = 3 * NUM_BATCH_GROUPS  # group * 3 + dist
 
 

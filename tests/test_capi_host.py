@@ -116,7 +116,7 @@ class _Job(ctypes.Structure):
 @pytest.mark.parametrize("fields,code,text", [
     (dict(img=None), odf.EINVAL, "img"),
     (dict(M=0), odf.EINVAL, "size"),
-    (dict(window=9), odf.EUNSUPPORTED, "window"),
+    (dict(window=11), odf.EUNSUPPORTED, "window"),
     (dict(kind=3), odf.EINVAL, "kind"),
     (dict(dist=5), odf.EINVAL, "dist"),
     (dict(dist=1, q=9), odf.EINVAL, "q"),
@@ -168,7 +168,13 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_autotune(3, 0, 0, 1, 0, 10, 1, None, None, None) == odf.EINVAL
     # batch tuning table: defaults, range checks, and the retired persistent form
     assert L.odf_batch_tune_get(3, odf.DDF) == 0 and L.odf_batch_tune_get(5, odf.BVDF) == 2
-    assert L.odf_batch_tune_get(7, odf.DDF) == 2 and L.odf_batch_tune_get(9, odf.DDF) == odf.EINVAL
+    assert L.odf_batch_tune_get(7, odf.DDF) == 2 and L.odf_batch_tune_get(9, odf.DDF) == 2
+    assert L.odf_batch_tune_get(11, odf.DDF) == odf.EINVAL
+    # 9x9 groups: shape 2, and the strips for BVDF (uint8)
+    assert L.odf_batch_tune_set(9, odf.DDF, odf.STRIP) == odf.EINVAL
+    assert L.odf_batch_tune_set(9, odf.DDF, 3) == odf.EINVAL
+    assert L.odf_batch_tune_set(9, odf.BVDF, odf.SHORT_STRIP) == odf.OK
+    assert L.odf_batch_tune_set(9, odf.BVDF, 2) == odf.OK
     # 7x7 groups: the 512-thread shapes and the strips, as the per-image table
     assert L.odf_batch_tune_set(7, odf.DDF, 0) == odf.EINVAL
     assert L.odf_batch_tune_set(7, odf.BVDF, 1) == odf.EINVAL
@@ -183,7 +189,7 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_batch_tune_set(5, odf.DDF, -1) == odf.EINVAL
     assert L.odf_batch_tune_set(5, odf.DDF, 1) == odf.OK and L.odf_batch_tune_get(5, odf.DDF) == 1
     assert L.odf_batch_tune_set(5, odf.DDF, 2) == odf.OK
-    assert L.odf_autotune_batch(9, 0, 1, None, None, None) == odf.EINVAL
+    assert L.odf_autotune_batch(11, 0, 1, None, None, None) == odf.EINVAL
     assert L.odf_autotune_batch(3, 0, 0, None, None, None) == odf.EINVAL
     jobs = (odf._Job * 1)()
     assert L.odf_autotune_batch_jobs(None, 1, 2, None, None, None) == odf.EINVAL
@@ -368,7 +374,7 @@ def test_allocation_failure_reports_enomem(monkeypatch):
     # validation still comes first
     rc = L.odf_autotune(11, odf.DDF, odf.EXACT, 1, 64, 64, 2, None, None, None)
     assert rc == odf.EINVAL
-    assert L.odf_autotune_batch(9, odf.DDF, 2, None, None, None) == odf.EINVAL
+    assert L.odf_autotune_batch(11, odf.DDF, 2, None, None, None) == odf.EINVAL
     monkeypatch.setenv("ODF_TEST_FAIL_ALLOC", "0")
     bad = (_Job * 1)()
     bad[0] = _Job(0, 0x7F0000100000, 0, 40, 50, 3, 1, 0, 4, 0.25)

@@ -144,3 +144,47 @@ def test_hard_backward_of_acwddf_selection():
     dx = odf.backward_hard(idx, _gpu(dy), 3).cpu().numpy()
     ref = oracle.backward_hard(idx.cpu().numpy(), dy.astype(np.float64), 3)
     assert np.array_equal(dx, ref.astype(np.float32))
+
+
+def _sampled_window_colours(img, pix, window):
+    """Member colours of the windows at flat positions pix of an (M, N, 3)
+    image, (len(pix), n, 3) (replicated border), without the whole image's."""
+    M, N, _ = img.shape
+    h = window // 2
+    r, c = np.divmod(np.asarray(pix), N)
+    dy, dx = np.divmod(np.arange(window * window), window)
+    rr = np.clip(r[:, None] + dy[None] - h, 0, M - 1)
+    cc = np.clip(c[:, None] + dx[None] - h, 0, N - 1)
+    return img[rr, cc]
+
+
+@pytest.mark.parametrize("window,cfg", [(5, 2), (5, 4), (7, 2)])
+def test_largest_frame_sampled(window, cfg):
+    """The 7680 x 4320 frame of the benchmark's ACWDDF forms, on the tile shape
+    and (5x5) the strip form that the forms' autotuner picks there: 5000 seeded
+    pixels and the four corners, each pair term, against the oracle."""
+    M, N = 4320, 7680
+    img = synth.image_corr(M, N, 0.15, key=500)
+    x = _gpu(img)
+    rng = np.random.default_rng(window * 10 + cfg)
+    pix = np.concatenate([rng.choice(M * N, 5000, replace=False), [0, N - 1, (M - 1) * N, M * N - 1]])
+    cols = _sampled_window_colours(img, pix, window)
+    for dist in (EXACT, MINIMAX, RGB):
+        print("case: acwddf 7680x4320 w=%d cfg=%d dist=%d" % (window, cfg, dist), flush=True)
+        saved = odf.tune_get(window, odf.ACWDDF, dist, True)
+        odf.tune_set(window, odf.ACWDDF, dist, True, cfg)
+        try:
+            out, idx = odf.acwddf(x, window, dist)
+            torch.cuda.synchronize()
+        finally:
+            odf.tune_set(window, odf.ACWDDF, dist, True, saved)
+        gi = idx.cpu().numpy().reshape(-1)[pix]
+        _, o_idx, S, dg = oracle.acwddf_at(img, pix, window, dist)
+        n_mis, n_amb, n = check_acwddf(gi, o_idx, cols, S, dg, window * window, 10.8, 0.02)
+        print("  mismatch %d ambiguous %d of %d" % (n_mis, n_amb, n), flush=True)
+        h = window // 2
+        r, c = np.divmod(pix, N)
+        sr = np.clip(r + gi // window - h, 0, M - 1)
+        sc = np.clip(c + gi % window - h, 0, N - 1)
+        assert np.array_equal(out.cpu().numpy().reshape(-1, 3)[pix], img[sr, sc])
+        del out, idx

@@ -109,7 +109,7 @@ TRAFFIC_KIB = {  # (form, ext_w, ext_h): (FETCH_SIZE KiB, WRITE_SIZE KiB)
 TRAFFIC_SOURCES = ("fwd.hip", "fwd5.hip", "fwd5s.hip", "fwd_launch.h", "fwd_strip.h", "batch.hip",
                    "fwd_tile.h", "aggregates.h", "pair_terms.h", "canon.h", "atan_poly.h",
                    "odf_internal.h")
-TRAFFIC_SRC_SHA256 = "85093c2be13af8cd2b9b931ea925ba2edf760d06054cb00c8c4eb6bb2b266f43"
+TRAFFIC_SRC_SHA256 = "321fb4117fa9493761d1644d027873b17247d3c30bd0b81522068f963120b72f"
 
 
 def forward_sources_sha256():

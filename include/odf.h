@@ -387,7 +387,7 @@ int odf_quality_u8(const uint8_t* y, const uint8_t* ref, int B, int M, int N, do
  * (output tile plus halo).  Configs 0..3 are tile shapes (one workgroup per
  * output tile); configs ODF_STRIP_CONFIG (4) and ODF_SHORT_STRIP_CONFIG (5) are
  * the strip form, offered for ODF_BVDF and ODF_DDF at 3x3, 5x5 and 7x7, for
- * ODF_BVDF at 9x9 on uint8 and for the centre-weighted kinds at 3x3 and 5x5
+ * ODF_BVDF at 9x9 on uint8 and for the centre-weighted kinds at 3x3 to 7x7
  * (the batch offers them for all its groups): one
  * workgroup per strip of 32 - 2h output columns and 8 * 16 - 2h (config 4) or
  * 3 * 16 - 2h (config 5, for images too small to fill the GPU with long

@@ -11,7 +11,7 @@ namespace odf {
 // for a float32 tile's pixel arrays).
 bool tile_config_valid(int window, int kind, int cfg, bool u8) {
     if (is_strip_config(cfg)) {  // as strip_form (fwd_strip.h)
-        if (centre_weighted(kind)) return window == 3 || window == 5;
+        if (centre_weighted(kind)) return window == 3 || window == 5 || window == 7;
         return (kind == kBVDF || kind == kDDF) &&
                (window == 3 || window == 5 || window == 7 || (window == 9 && kind == kBVDF && u8));
     }

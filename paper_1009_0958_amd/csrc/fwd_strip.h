@@ -100,10 +100,11 @@ struct StripCarry {
 // The classes with a strip form: BVDF and DDF at 3x3, 5x5 and 7x7, BVDF at
 // 9x9 on uint8 (the float32 9x9 strip and the 9x9 DDF strip, with its second
 // set of carried planes, would not fit the 160 KiB of LDS of a CU), and the
-// centre-weighted kinds (ACWDDF, CWDDF^k, CWVMF^k) at 3x3 and 5x5.
+// centre-weighted kinds (ACWDDF, CWDDF^k, CWVMF^k) at 3x3 to 7x7 (7x7 ACWDDF: 152 KB of
+// LDS for float32, within a CU).
 template <int W, int KIND, bool U8>
 constexpr bool strip_form() {
-    if (centre_weighted(KIND)) return W == 3 || W == 5;
+    if (centre_weighted(KIND)) return W == 3 || W == 5 || W == 7;
     if (KIND != kBVDF && KIND != kDDF) return false;
     return W == 3 || W == 5 || W == 7 || (W == 9 && KIND == kBVDF && U8);
 }

@@ -146,7 +146,7 @@ def test_batch_and_tune_argument_errors():
     assert L.odf_tune_get(4, 0, 0, 1) == odf.EINVAL
     assert odf.tile_config(0) == (32, 32) and odf.tile_config(3) == (64, 8)
     # configs 4, 5: the strip form (32 x 16 bands): BVDF and DDF at 3x3 to 7x7, BVDF 9x9 on
-    # uint8, the centre-weighted kinds at 3x3 and 5x5
+    # uint8, the centre-weighted kinds at 3x3 to 7x7
     assert odf.tile_config(odf.STRIP) == (32, 16) and odf.tile_config(odf.SHORT_STRIP) == (32, 16)
     assert L.odf_tile_config(odf.NUM_TILE_CONFIGS, ctypes.byref(ctypes.c_int()),
                              ctypes.byref(ctypes.c_int())) == odf.EINVAL
@@ -233,7 +233,8 @@ def test_acwddf_tuning_table():
     assert L.odf_tune_get(3, 5, 0, 1) == odf.EINVAL  # kinds end at ODF_CWDDF
     assert L.odf_tune_get(7, odf.ACWDDF, 0, 1) == 2
     assert L.odf_tune_set(7, odf.ACWDDF, 0, 1, 1) == odf.EINVAL  # 512-thread shapes only
-    assert L.odf_tune_set(7, odf.ACWDDF, 0, 1, 4) == odf.EINVAL  # no strip form
+    assert L.odf_tune_set(7, odf.ACWDDF, 0, 1, 4) == odf.OK  # the strip form
+    assert L.odf_tune_set(7, odf.ACWDDF, 0, 1, 2) == odf.OK
     assert L.odf_tune_get(9, odf.ACWDDF, 0, 1) == odf.EINVAL  # no 9x9 ACWDDF
     assert L.odf_tune_get(7, odf.DDF, 0, 1) == 2
     assert L.odf_tune_set(7, odf.DDF, 0, 1, 1) == odf.EINVAL  # 512-thread shapes only

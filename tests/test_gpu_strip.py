@@ -100,7 +100,7 @@ def test_strip_oracle(window, kind, p, dist):
 
 def test_strip_not_offered():
     """The strip form covers BVDF and DDF at 3x3 to 7x7, BVDF at 9x9 on uint8 and
-    the centre-weighted kinds at 3x3 and 5x5."""
+    the centre-weighted kinds at 3x3 to 7x7."""
     for window, kind, u8 in [(9, DDF, True), (9, BVDF, False)]:
         for cfg in STRIPS:
             with pytest.raises(odf.ODFError):
@@ -125,7 +125,7 @@ def _run_cw(x, window, kind, dist, cfg, level):
 
 @pytest.mark.parametrize("cfg", STRIPS)
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 5, 7), (1, 130, 61), (2, 257, 45), (1, 40, 300)])
-@pytest.mark.parametrize("window", [3, 5])
+@pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("u8", [True, False])
 def test_strip_equals_tile_centre_weighted(shape, window, u8, cfg):
     """ACWDDF (its four keys per window and the switching statistic) and the

@@ -57,9 +57,8 @@
 #endif
 
 enum { OK_BVDF = 0, OK_DDF = 1 };
-/* members of the largest window: 15 x 15 for the filters (the member index is
- * stored in a byte), 9 x 9 for the softmin relaxation */
-enum { NMAX = 225, NMAX9 = 81 };
+/* members of the largest window, 15 x 15 (the member index is stored in a byte) */
+enum { NMAX = 225 };
 enum { OD_EXACT = 0, OD_MINIMAX = 1, OD_RGB = 2 };
 
 /* Table 1: minimax polynomial coefficients a_0..a_4 as printed, rows q = 2,3,4. */
@@ -384,15 +383,14 @@ static void softmin_window(const double *base, int M, int N, int w, int kind, do
 
 int oracle_softmin_fwd(const double *img, int B, int M, int N, int w, int kind, double p,
                        double tau, double *y, double *pi_out, int nthreads) {
-    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || w > 9 || !(tau > 0.0) || !img || !y)
-        return -1;
+    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || !(tau > 0.0) || !img || !y) return -1;
     set_threads(nthreads);
     int64_t mn = (int64_t)M * N, total = mn * B;
     int n = w * w;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t pix = 0; pix < total; ++pix) {
-        int64_t src[NMAX9];
-        double A[NMAX9], D[NMAX9], Om[NMAX9], pi[NMAX9];
+        int64_t src[NMAX];
+        double A[NMAX], D[NMAX], Om[NMAX], pi[NMAX];
         int64_t b = pix / mn, rc = pix % mn;
         softmin_window(img + b * mn * 3, M, N, w, kind, p, tau, (int)(rc / N), (int)(rc % N), src,
                        A, D, Om, pi, y + 3 * pix);
@@ -447,8 +445,7 @@ static void objective_grad(double A, double D, double Om, int kind, double p, do
  * processed in parallel; inside an image, output pixels in raster order. */
 int oracle_softmin_bwd(const double *img, const double *dy, int B, int M, int N, int w, int kind,
                        double p, double tau, double *dx, int nthreads) {
-    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || w > 9 || !(tau > 0.0) || !img || !dy ||
-        !dx)
+    if (check_args(B, M, N, w, kind, p, OD_EXACT, 4) || !(tau > 0.0) || !img || !dy || !dx)
         return -1;
     set_threads(nthreads);
     int64_t mn = (int64_t)M * N;
@@ -459,8 +456,8 @@ int oracle_softmin_bwd(const double *img, const double *dy, int B, int M, int N,
         const double *base = img + (int64_t)b * mn * 3;
         double *gx = dx + (int64_t)b * mn * 3;
         for (int64_t rc = 0; rc < mn; ++rc) {
-            int64_t src[NMAX9];
-            double A[NMAX9], D[NMAX9], Om[NMAX9], pi[NMAX9], y[3];
+            int64_t src[NMAX];
+            double A[NMAX], D[NMAX], Om[NMAX], pi[NMAX], y[3];
             softmin_window(base, M, N, w, kind, p, tau, (int)(rc / N), (int)(rc % N), src, A, D,
                            Om, pi, y);
             const double *g = dy + 3 * ((int64_t)b * mn + rc);

@@ -537,7 +537,8 @@ def _float_tiny(seed, M, N):
 
 @pytest.mark.parametrize("w,kind,p,tau", [(3, BVDF, 0.0, 0.1), (3, DDF, 0.25, 0.1),
                                           (5, DDF, 0.25, 0.1), (5, DDF, 0.25, 0.01),
-                                          (3, DDF, 0.5, 0.01), (5, BVDF, 0.0, 0.01)])
+                                          (3, DDF, 0.5, 0.01), (5, BVDF, 0.0, 0.01),
+                                          (11, DDF, 0.25, 0.1)])
 def test_softmin_gradient_vs_central_differences(w, kind, p, tau):
     x = _float_tiny(21 + w, 5, 6)
     rng = np.random.default_rng(3)
@@ -571,9 +572,9 @@ def test_softmin_limits():
 
 
 def test_window_range():
-    """The filters and the hard backward take every odd window from 3 x 3 to
-    15 x 15 (the member index is a byte); the softmin relaxation stops at 9 x 9.
-    Even and larger windows are rejected."""
+    """The filters, the hard backward and the softmin relaxation take every odd
+    window from 3 x 3 to 15 x 15 (the member index is a byte).  Even and larger
+    windows are rejected."""
     img = _tiny_image(3, 4, 5)
     for w in (1, 2, 4, 10, 17):
         with pytest.raises(ValueError):
@@ -581,8 +582,9 @@ def test_window_range():
         with pytest.raises(ValueError):
             oracle.backward_hard(np.zeros((4, 5), np.uint8), np.zeros((4, 5, 3)), w)
     x = img.astype(np.float64)
-    with pytest.raises(ValueError):
-        oracle.softmin_fwd(x, 11, DDF, 0.25, 0.1)
+    for w in (10, 17):
+        with pytest.raises(ValueError):
+            oracle.softmin_fwd(x, w, DDF, 0.25, 0.1)
     for w in (10, 17):
         with pytest.raises(ValueError):
             oracle.cwfilter(img, w, True, EXACT, 4, 1)

@@ -211,7 +211,8 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
  * y(c) = sum_u pi_u x_u.  tau -> 0 tends to the hard selection where the
  * minimum is unique.
  *   x  B x M x N x 3 float32 (read only); y  B x M x N x 3 float32 output.
- * Windows 3, 5, 7 and 9 (ODF_EUNSUPPORTED above).
+ * Any odd window from 3 to 15: 3 to 9 on LDS tiles, 11 to 15 on a direct form
+ * (one thread per window, every pair term evaluated; far slower).
  * Errors: as odf_filter_f32, plus ODF_EINVAL for tau <= 0 or not finite.
  */
 int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kind, float p,

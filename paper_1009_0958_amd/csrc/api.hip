@@ -260,8 +260,6 @@ int odf_backward_hard_f32(const uint8_t* idx, const float* dy, int B, int M, int
 static int check_soft(const float* x, int B, int M, int N, int window, int kind, float p, float tau) {
     int rc = check_common(x, B, M, N, window, kind, p, ODF_EXACT, 4);
     if (rc) return rc;
-    if (window >= 11)
-        return fail(ODF_EUNSUPPORTED, "the softmin relaxation supports windows 3 to 9");
     if (!(tau > 0.0f) || !(tau < 3.0e38f)) return fail(ODF_EINVAL, "tau must be positive and finite");
     return ODF_OK;
 }
@@ -283,7 +281,7 @@ int odf_softmin_fwd_f32(const float* x, int B, int M, int N, int window, int kin
 }
 
 size_t odf_softmin_bwd_workspace(int B, int M, int N, int window, int kind) {
-    if (B < 1 || M < 1 || N < 1 || window < 3 || window > 9 || window % 2 == 0 ||
+    if (B < 1 || M < 1 || N < 1 || window < 3 || window > 15 || window % 2 == 0 ||
         (kind != ODF_BVDF && kind != ODF_DDF))
         return 0;
     return odf::softmin_workspace_bytes(window, kind, B, M, N);

@@ -545,6 +545,163 @@ __global__ void __launch_bounds__(256) softmin_combine(SoftParams prm) {
     o[2] = a2;
 }
 
+// Direct form for the odd windows 11 to 15 (the tiles' (member, window) weight
+// arrays outgrow the LDS there): one thread per window, every pair term of the
+// window evaluated from its definition (n^2 per window, no reuse).  The forward
+// forms A, D, Omega and the weights as above; the backward then forms, for
+// every member u of its window, pi_u dy + sum_v (G^A_u + G^A_v) grad_1 theta(u, v)
+// + (G^D_u + G^D_v) grad_1 |u - v| (the dependence of A_u and of every A_v on
+// x_u), written to the workspace (n x 3 floats per pixel), and a gather pass
+// sums, for every pixel q, the member gradients read from q over the windows
+// within h of q in raster order and their members in index order:
+// deterministic.  Per-window arrays live in scratch (n <= 225).
+constexpr int kSoftDirMaxN = 225;
+constexpr int kSoftDirThreads = 128;
+
+__device__ __forceinline__ void soft_dir_member(const SoftParams& prm, int b, int r, int c, int u,
+                                                int w, float4& d, float4& raw) {
+    const int h = w / 2;
+    const int gy = min(max(r + u / w - h, 0), prm.M - 1);
+    const int gx = min(max(c + u % w - h, 0), prm.N - 1);
+    const float* s = prm.x + (((size_t)b * prm.M + gy) * prm.N + gx) * 3;
+    prepare_pixel<kExact, false>(s[0], s[1], s[2], d, raw);
+}
+
+template <int KIND, bool BWD>
+__global__ void __launch_bounds__(kSoftDirThreads) softmin_direct_kernel(SoftParams prm, int w) {
+    const int blk = flat_block(prm.grid.n);
+    if (blk < 0) return;
+    const long long mn = (long long)prm.M * prm.N, npix = mn * prm.B;
+    const long long pix = (long long)blk * kSoftDirThreads + threadIdx.x;
+    if (pix >= npix) return;
+    const int b = (int)(pix / mn);
+    const int rc = (int)(pix - (long long)b * mn);
+    const int r = rc / prm.N, c = rc - r * prm.N;
+    const int n = w * w;
+    const float p = prm.p, inv_tau = prm.inv_tau;
+    const MinimaxCoef no_coef{};
+    const AtanCoef ac = atan_coef();
+    float A[kSoftDirMaxN], D[kSoftDirMaxN], E[kSoftDirMaxN];
+    float omin = __builtin_huge_valf();
+    for (int u = 0; u < n; ++u) {
+        float4 du, ru;
+        soft_dir_member(prm, b, r, c, u, w, du, ru);
+        float a = 0.0f, d = 0.0f;
+        for (int v = 0; v < n; ++v) {
+            float4 dv, rv;
+            soft_dir_member(prm, b, r, c, v, w, dv, rv);
+            a += pair_term<KIND, kExact, false>(du, ru, dv, rv, no_coef, ac);
+            if (KIND == kDDF) d += l2_term(ru, rv);
+        }
+        A[u] = a;
+        D[u] = d;
+        E[u] = soft_objective<KIND>(a, d, p);
+        omin = fminf(omin, E[u]);
+    }
+    float z = 0.0f;
+    for (int u = 0; u < n; ++u) {
+        E[u] = __expf((omin - E[u]) * inv_tau);
+        z += E[u];
+    }
+    const float iz = 1.0f / z;
+    float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
+    for (int u = 0; u < n; ++u) {
+        float4 du, ru;
+        soft_dir_member(prm, b, r, c, u, w, du, ru);
+        const float pu = E[u] * iz;
+        y0 = fmaf(pu, ru.x, y0);
+        y1 = fmaf(pu, ru.y, y1);
+        y2 = fmaf(pu, ru.z, y2);
+    }
+    if (!BWD) {
+        prm.y[pix * 3 + 0] = y0;
+        prm.y[pix * 3 + 1] = y1;
+        prm.y[pix * 3 + 2] = y2;
+        return;
+    }
+    const float g0 = prm.dy[pix * 3 + 0], g1 = prm.dy[pix * 3 + 1], g2 = prm.dy[pix * 3 + 2];
+    // A[], D[] <- G^A, G^D of every member
+    for (int u = 0; u < n; ++u) {
+        float4 du, ru;
+        soft_dir_member(prm, b, r, c, u, w, du, ru);
+        const float pu = E[u] * iz;
+        const float t = fmaf(ru.x - y0, g0, fmaf(ru.y - y1, g1, (ru.z - y2) * g2));
+        const float gom = -pu * t * inv_tau;
+        float dA, dD;
+        objective_grad<KIND>(A[u], D[u], soft_objective<KIND>(A[u], D[u], p), p, dA, dD);
+        A[u] = gom * dA;
+        D[u] = gom * dD;
+    }
+    for (int u = 0; u < n; ++u) {
+        float4 du, ru;
+        soft_dir_member(prm, b, r, c, u, w, du, ru);
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f;
+        for (int v = 0; v < n; ++v) {
+            float4 dv, rv;
+            soft_dir_member(prm, b, r, c, v, w, dv, rv);
+            add_cross_dir(du, dv, A[u] + A[v], v0, v1, v2);
+            if (KIND == kDDF) add_l2_dir(ru, rv, D[u] + D[v], l0, l1, l2);
+        }
+        // a x (sum S c / |c|), times da/dx / |a|^2 (0 for the zero pixel)
+        const float scale = ru.w / fmaf(du.x, du.x, fmaf(du.y, du.y, du.z * du.z));
+        const float pu = E[u] * iz;
+        float* o = prm.ws + ((size_t)pix * n + u) * 3;
+        o[0] = fmaf(pu, g0, fmaf(fmaf(du.y, v2, -du.z * v1), scale, l0));
+        o[1] = fmaf(pu, g1, fmaf(fmaf(du.z, v0, -du.x * v2), scale, l1));
+        o[2] = fmaf(pu, g2, fmaf(fmaf(du.x, v1, -du.y * v0), scale, l2));
+    }
+}
+
+// dx(q): the member gradients of the windows within h of q (raster order)
+// whose member u is read from q (replicated border), members in index order.
+__global__ void __launch_bounds__(kSoftDirThreads) softmin_direct_gather(SoftParams prm, int w) {
+    const int blk = flat_block(prm.grid.n);
+    if (blk < 0) return;
+    const long long mn = (long long)prm.M * prm.N, npix = mn * prm.B;
+    const long long pix = (long long)blk * kSoftDirThreads + threadIdx.x;
+    if (pix >= npix) return;
+    const int b = (int)(pix / mn);
+    const int rc = (int)(pix - (long long)b * mn);
+    const int qy = rc / prm.N, qx = rc - qy * prm.N;
+    const int h = w / 2, n = w * w;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    for (int cy = max(qy - h, 0); cy <= min(qy + h, prm.M - 1); ++cy) {
+        for (int cx = max(qx - h, 0); cx <= min(qx + h, prm.N - 1); ++cx) {
+            const size_t cpix = ((size_t)b * prm.M + cy) * prm.N + cx;
+            for (int u = 0; u < n; ++u) {
+                const int sy = min(max(cy + u / w - h, 0), prm.M - 1);
+                const int sx = min(max(cx + u % w - h, 0), prm.N - 1);
+                if (sy != qy || sx != qx) continue;
+                const float* g = prm.ws + (cpix * n + u) * 3;
+                a0 += g[0];
+                a1 += g[1];
+                a2 += g[2];
+            }
+        }
+    }
+    prm.dx[pix * 3 + 0] = a0;
+    prm.dx[pix * 3 + 1] = a1;
+    prm.dx[pix * 3 + 2] = a2;
+}
+
+template <int KIND>
+static hipError_t launch_soft_direct(int w, bool bwd, const SoftParams& prm, hipStream_t s) {
+    SoftParams q = prm;
+    const long long npix = (long long)prm.B * prm.M * prm.N;
+    const long long nblk = (npix + kSoftDirThreads - 1) / kSoftDirThreads;
+    q.grid = tile_grid(1, (int)nblk, 1);
+    const dim3 grid = flat_grid(nblk), block(kSoftDirThreads);
+    if (!bwd) {
+        hipLaunchKernelGGL((softmin_direct_kernel<KIND, false>), grid, block, 0, s, q, w);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((softmin_direct_kernel<KIND, true>), grid, block, 0, s, q, w);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(softmin_direct_gather, grid, block, 0, s, q, w);
+    return hipGetLastError();
+}
+
 template <int W, int KIND, bool BWD>
 static void soft_grid(const SoftParams& prm, int& tx, int& ty, int& nt) {
     using Gm = FwdGeom<W, SoftTile<W, KIND, BWD>::EXT_W, SoftTile<W, KIND, BWD>::EXT_H>;
@@ -575,6 +732,8 @@ static hipError_t launch_soft_t(bool bwd, const SoftParams& prm, hipStream_t s) 
 }
 
 size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
+    if (window >= 11)  // the direct form: n x 3 floats per pixel
+        return (size_t)B * M * N * window * window * 3 * sizeof(float);
     SoftParams prm{};
     prm.B = B; prm.M = M; prm.N = N;
     int tx, ty, nt;
@@ -595,6 +754,9 @@ size_t softmin_workspace_bytes(int window, int kind, int B, int M, int N) {
 }
 
 hipError_t launch_softmin(int window, int kind, bool bwd, const SoftParams& prm, hipStream_t s) {
+    if (window >= 11)
+        return kind == kBVDF ? launch_soft_direct<kBVDF>(window, bwd, prm, s)
+                             : launch_soft_direct<kDDF>(window, bwd, prm, s);
     if (window == 3)
         return kind == kBVDF ? launch_soft_t<3, kBVDF>(bwd, prm, s) : launch_soft_t<3, kDDF>(bwd, prm, s);
     if (window == 5)

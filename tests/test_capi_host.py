@@ -72,9 +72,9 @@ def test_f32_and_aggregates_reject():
 
 
 def test_general_windows_validated_like_the_others():
-    """11x11 to 15x15: the hard backward, the softmin and the tuning table
-    reject what they do not offer; ACWDDF and the centre-weighted filters
-    validate their own arguments at these sizes (nothing is launched here)."""
+    """11x11 to 15x15: the hard backward and the tuning table reject what they
+    do not offer; ACWDDF, the centre-weighted filters and the softmin validate
+    their own arguments at these sizes (nothing is launched here)."""
     L = odf.lib()
     B = odf._batch_lib()
     bwd = lambda w, dx=FAKE2: L.odf_backward_hard_f32(  # noqa: E731
@@ -90,8 +90,8 @@ def test_general_windows_validated_like_the_others():
         assert L.odf_cw_filter_u8(FAKE, 1, 8, 8, w, odf.CWVMF, 0, 4, (n + 1) // 2 + 1, FAKE2,
                                   None, None) == odf.EINVAL and "level" in odf.last_error()
         assert L.odf_acwddf_u8(FAKE, 1, 8, 8, w, 0, 4, 2, 10.8, FAKE, None, None) == odf.EINVAL
-        assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, w, 1, 0.25, 0.1, FAKE2, None) \
-            == odf.EUNSUPPORTED
+        assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, w, 1, 0.25, 0.0, FAKE2, None) \
+            == odf.EINVAL and "tau" in odf.last_error()
     for w in (10, 17):
         assert L.odf_acwddf_u8(FAKE, 1, 8, 8, w, 0, 4, 2, 10.8, FAKE2, None, None) \
             == odf.EUNSUPPORTED
@@ -263,12 +263,15 @@ def test_noise_and_quality_reject():
 
 
 def test_softmin_window_limits():
-    """The softmin takes windows 3 to 9; its 7x7 backward workspace holds
-    one 32 x 16 extended tile (26 x 10 windows) of float32 triples per tile."""
+    """The softmin takes every odd window from 3 to 15; its 7x7 backward
+    workspace holds one 32 x 16 extended tile (26 x 10 windows) of float32
+    triples per tile, from 11x11 (the direct form) n triples per pixel."""
     L = odf.lib()
-    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 11, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
-    assert "softmin" in odf.last_error()
-    assert L.odf_softmin_bwd_workspace(1, 8, 8, 11, 1) == 0
+    assert L.odf_softmin_fwd_f32(FAKE, 1, 8, 8, 17, 1, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert "window" in odf.last_error()
+    assert L.odf_softmin_bwd_workspace(1, 8, 8, 17, 1) == 0
+    assert L.odf_softmin_bwd_workspace(1, 8, 8, 12, 1) == 0
+    assert L.odf_softmin_bwd_workspace(2, 8, 9, 13, 1) == 2 * 8 * 9 * 169 * 3 * 4
     assert L.odf_softmin_bwd_workspace(1, 8, 8, 9, 1) == 1 * 1 * 512 * 3 * 4  # 24 x 8 windows
     tiles = 2 * -(-100 // 26) * -(-45 // 10)
     assert L.odf_softmin_bwd_workspace(2, 45, 100, 7, 1) == tiles * 512 * 3 * 4
@@ -411,7 +414,7 @@ def test_noalloc_softmin_rejects_before_launch():
     assert "static scratch" in odf.last_error()
     assert f(FAKE, None, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EINVAL
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.0, FAKE2, None) == odf.EINVAL  # tau
-    assert f(FAKE, FAKE2, 1, 8, 8, 11, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
+    assert f(FAKE, FAKE2, 1, 8, 8, 17, odf.DDF, 0.25, 0.1, FAKE2, None) == odf.EUNSUPPORTED
     assert f(FAKE, FAKE2, 1, 8, 8, 5, odf.DDF, 0.25, 0.1, FAKE, None) == odf.EINVAL  # dx = x
     assert "overlaps" in odf.last_error()
 

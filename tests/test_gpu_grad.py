@@ -249,3 +249,24 @@ def test_softmin_f64_gradcheck_on_gpu():
             fn = lambda t: odf.softmin_filter(t, 5, kind, p, tau)  # noqa: E731
             assert torch.autograd.gradcheck(fn, (crop,), eps=1e-6, atol=1e-7, rtol=1e-5,
                                             fast_mode=True)
+
+
+@pytest.mark.parametrize("window,kind,p", [(11, DDF, 0.25), (11, BVDF, 0.0), (13, DDF, 0.5),
+                                           (15, DDF, 0.25)])
+@pytest.mark.parametrize("tau", [0.1, 0.01])
+def test_softmin_direct_form_matches_oracle(window, kind, p, tau):
+    """11x11 to 15x15 (the direct form: one thread per window, member gradients
+    gathered per pixel in a fixed order), forward and backward against the
+    oracle's budget, and deterministic."""
+    print("case: softmin direct w=%d kind=%d p=%s tau=%s" % (window, kind, p, tau), flush=True)
+    x = synth.float_batch(2, 15, 19, 0.1, key=60 + window + kind)
+    dy = np.random.default_rng(window).standard_normal(x.shape).astype(np.float32)
+    y = odf.softmin_forward(_gpu(x), window, kind, p, tau).cpu().numpy()
+    dx = odf.softmin_backward(_gpu(x), _gpu(dy), window, kind, p, tau).cpu().numpy()
+    yr = oracle.softmin_fwd(x, window, kind, p, tau)
+    ref = oracle.softmin_bwd(x, dy.astype(np.float64), window, kind, p, tau)
+    bnd = soft_bounds(x, _objectives(x, window, kind, p), window, tau, np.abs(ref).max())
+    ry, rd = check_soft(y, yr, dx, ref, bnd, "direct %d" % window)
+    print("worst error / bound: y %.3f, dx %.3f" % (ry, rd), flush=True)
+    dx2 = odf.softmin_backward(_gpu(x), _gpu(dy), window, kind, p, tau).cpu().numpy()
+    assert np.array_equal(dx, dx2)
